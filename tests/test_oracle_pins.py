@@ -1,0 +1,506 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's formulas: each checks a property that the
+defining equations imply (exactness classes, closed forms, printed values,
+invariants, convergence order), chosen so that a dropped term, a wrong sign,
+a shifted stencil index or a transposed axis fails at least one of them.
+"""
+import math
+import os
+from fractions import Fraction
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.special
+
+import oracle
+from paper_2607_17836_amd import synth
+
+L = 2 * np.pi
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def grid_sample(n, fn):
+    h = L / n
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")   # [j, i]
+    return fn(X, Y)
+
+
+def interior_points(n, rng, count, lo_cell, hi_cell):
+    """Random points whose cell index lies in [lo_cell, hi_cell] on both axes."""
+    h = L / n
+    ci = rng.integers(lo_cell, hi_cell + 1, count)
+    cj = rng.integers(lo_cell, hi_cell + 1, count)
+    return (ci + rng.uniform(0, 1, count)) * h, (cj + rng.uniform(0, 1, count)) * h
+
+
+# --------------------------------------------------------------------------
+# Spatial interpolation (Sec. 3.4)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme", ["bilinear", "catmull_rom", "bspline"])
+def test_partition_of_unity(scheme):
+    """The weights of every scheme sum to one, so a constant field comes back
+    unchanged everywhere, across the periodic seam included."""
+    n = 16
+    rng = np.random.default_rng(0)
+    f = np.full((n, n), 3.25)
+    x = np.concatenate([rng.uniform(0, L, 500), [0.0, L - 1e-15, -1e-3, L + 1e-3]])
+    y = np.concatenate([rng.uniform(0, L, 500), [L - 1e-15, 0.0, 7.0, -0.5]])
+    out = oracle.interp(f, x, y, scheme)
+    # 16 rounded products and sums, weights of either sign with sum |w| <= 1.6
+    assert np.max(np.abs(out - 3.25)) <= 16 * np.spacing(3.25)
+
+
+def test_bilinear_exact_on_bilinear_functions():
+    """Bilinear interpolation reproduces span{1, x, y, xy} inside the domain
+    and returns node values at nodes (eq. bilinear_interp)."""
+    n = 16
+    fn = lambda X, Y: 0.7 - 1.3 * X + 0.4 * Y + 0.9 * X * Y
+    f = grid_sample(n, fn)
+    rng = np.random.default_rng(1)
+    x, y = interior_points(n, rng, 2000, 0, n - 2)
+    assert np.max(np.abs(oracle.interp(f, x, y, "bilinear") - fn(x, y))) < 1e-12
+    h = L / n
+    i, j = rng.integers(0, n, 50), rng.integers(0, n, 50)
+    np.testing.assert_allclose(oracle.interp(f, i * h, j * h, "bilinear"), f[j, i], rtol=0, atol=1e-13)
+
+
+def test_catmull_rom_exact_on_biquadratics():
+    """Catmull-Rom (cubic Hermite with central-difference slopes) reproduces
+    quadratics exactly in each axis, so biquadratics are exact away from the
+    seam; W(0) = (0, 1, 0, 0) makes it interpolate node values (eq. cr_kernel)."""
+    n = 16
+    fn = lambda X, Y: (0.3 + 0.5 * X - 0.2 * X * X) * (1.1 - 0.7 * Y + 0.15 * Y * Y) + 0.05 * X * X
+    f = grid_sample(n, fn)
+    rng = np.random.default_rng(2)
+    x, y = interior_points(n, rng, 2000, 1, n - 3)
+    assert np.max(np.abs(oracle.interp(f, x, y, "catmull_rom") - fn(x, y))) < 1e-11
+    h = L / n
+    i, j = rng.integers(0, n, 50), rng.integers(0, n, 50)
+    g = rng.standard_normal((n, n))
+    np.testing.assert_allclose(oracle.interp(g, i * h, j * h, "catmull_rom"), g[j, i], rtol=0, atol=1e-14)
+    # a cubic is NOT reproduced (the scheme is third-order, not fourth)
+    fc = grid_sample(n, lambda X, Y: X ** 3)
+    assert np.max(np.abs(oracle.interp(fc, x, y, "catmull_rom") - x ** 3)) > 1e-4
+
+
+def _one_sided(g, scheme, xe, yv, side, e):
+    """Value, slope and curvature just to one side of x = xe (second-order
+    one-sided differences along x)."""
+    xs = xe + side * e * np.arange(4)
+    f = oracle.interp(g, xs, np.full(4, yv), scheme)
+    d1 = side * (-3 * f[0] + 4 * f[1] - f[2]) / (2 * e)
+    d2 = (2 * f[0] - 5 * f[1] + 4 * f[2] - f[3]) / (e * e)
+    return f[0], d1, d2
+
+
+def test_interpolant_smoothness_across_cell_edges():
+    """Across cell edges the interpolant of a random periodic field is C0 for
+    bilinear, C1 (not C2) for Catmull-Rom and C2 for the cubic B-spline."""
+    n = 12
+    h = L / n
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal((n, n))
+    jumps = {s: [0.0, 0.0] for s in ("bilinear", "catmull_rom", "bspline")}
+    for k in range(n):
+        xe, yv = k * h, rng.uniform(0, L)
+        for scheme in jumps:
+            _, l1, l2 = _one_sided(g, scheme, xe, yv, -1, 1e-4)
+            _, r1, r2 = _one_sided(g, scheme, xe, yv, +1, 1e-4)
+            jumps[scheme][0] = max(jumps[scheme][0], abs(l1 - r1))
+            jumps[scheme][1] = max(jumps[scheme][1], abs(l2 - r2))
+    assert jumps["bilinear"][0] > 0.1
+    assert jumps["catmull_rom"][0] < 1e-5 and jumps["catmull_rom"][1] > 0.1
+    assert jumps["bspline"][0] < 1e-5 and jumps["bspline"][1] < 1e-2
+
+
+def test_bspline_smoothing_operator_on_biquadratics():
+    """Without prefilter the cubic B-spline acts on a quadratic q as
+    q + (h^2/6) q'' per axis, so on a biquadratic it returns
+    (I + h^2/6 d_xx)(I + h^2/6 d_yy) q; linears are exact."""
+    n = 16
+    h = L / n
+    a0, a1, a2 = 0.3, 0.5, -0.2
+    b0, b1, b2 = 1.1, -0.7, 0.15
+    fx = lambda X: a0 + a1 * X + a2 * X * X
+    fy = lambda Y: b0 + b1 * Y + b2 * Y * Y
+    f = grid_sample(n, lambda X, Y: fx(X) * fy(Y))
+    rng = np.random.default_rng(4)
+    x, y = interior_points(n, rng, 2000, 1, n - 3)
+    expect = (fx(x) + h * h / 6 * 2 * a2) * (fy(y) + h * h / 6 * 2 * b2)
+    assert np.max(np.abs(oracle.interp(f, x, y, "bspline") - expect)) < 1e-11
+    lin = grid_sample(n, lambda X, Y: 0.2 + 0.9 * X - 0.4 * Y)
+    assert np.max(np.abs(oracle.interp(lin, x, y, "bspline") - (0.2 + 0.9 * x - 0.4 * y))) < 1e-12
+
+
+@pytest.mark.parametrize("kx,ky", [(1, 0), (0, 3), (2, 5)])
+def test_bspline_node_multiplier_on_fourier_modes(kx, ky):
+    """At the nodes the un-prefiltered B-spline maps f_i to
+    (f_{i-1} + 4 f_i + f_{i+1})/6 per axis, i.e. multiplies the mode
+    sin(kx x + ky y)... by (2 + cos(k h))/3 per axis; periodic wrap included."""
+    n = 16
+    h = L / n
+    f = grid_sample(n, lambda X, Y: np.cos(kx * X) * np.cos(ky * Y))
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    out = oracle.interp(f, (i * h).ravel(), (j * h).ravel(), "bspline")
+    factor = (2 + np.cos(kx * h)) / 3 * (2 + np.cos(ky * h)) / 3
+    np.testing.assert_allclose(out, factor * f.ravel(), rtol=0, atol=1e-13)
+
+
+def test_axes_not_transposed():
+    """A field that varies only in x interpolates to a value independent of y
+    (f[j, i] layout, x fastest)."""
+    n = 16
+    f = grid_sample(n, lambda X, Y: np.sin(X) + 0 * Y)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, L, 20)
+    for scheme in ("bilinear", "catmull_rom", "bspline"):
+        a = oracle.interp(f, x, np.full(20, 0.3), scheme)
+        b = oracle.interp(f, x, np.full(20, 4.1), scheme)
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-15)
+        assert np.max(np.abs(a - np.sin(x))) < 0.05
+
+
+@pytest.mark.parametrize("scheme", ["catmull_rom", "bspline"])
+def test_compat_edge_fallback_cells(scheme):
+    """With the compatibility flag, bicubic cells whose 4x4 stencil leaves the
+    grid (i in {0, n-2, n-1} on either axis) return the bilinear value; other
+    cells are unchanged."""
+    n = 16
+    h = L / n
+    rng = np.random.default_rng(6)
+    g = rng.standard_normal((n, n))
+    for ci in range(n):
+        x = np.array([(ci + 0.37) * h])
+        y = np.array([(7 + 0.61) * h])
+        c = oracle.interp(g, x, y, scheme, compat_edge=1)
+        p = oracle.interp(g, x, y, scheme, compat_edge=0)
+        b = oracle.interp(g, x, y, "bilinear")
+        if ci in (0, n - 2, n - 1):
+            assert c[0] == b[0]
+        else:
+            assert c[0] == p[0]
+
+
+# --------------------------------------------------------------------------
+# Temporal interpolation and RK4 stage times (Sec. 3.2, 3.4)
+# --------------------------------------------------------------------------
+def test_temporal_endpoints_and_pingpong_roles():
+    n = 8
+    rng = np.random.default_rng(7)
+    ua, va, ub, vb = (rng.standard_normal((n, n)) for _ in range(4))
+    x, y = rng.uniform(0, L, 30), rng.uniform(0, L, 30)
+    fl = oracle.grid_flow(ua, va, ub, vb, scheme="catmull_rom", t_slot=(2.0, 3.0))
+    u0, v0 = oracle.velocity(fl, x, y, 2.0)
+    u1, v1 = oracle.velocity(fl, x, y, 3.0)
+    np.testing.assert_array_equal(u0, oracle.interp(ua, x, y, "catmull_rom"))
+    np.testing.assert_array_equal(v1, oracle.interp(vb, x, y, "catmull_rom"))
+    um, _ = oracle.velocity(fl, x, y, 2.25)
+    np.testing.assert_allclose(um, 0.75 * u0 + 0.25 * u1, atol=1e-14)
+    # ping-pong: step n uses slot n % 2 as the earlier level
+    fp = oracle.grid_flow(ua, va, ub, vb, time_mode=oracle.PINGPONG)
+    ue, _ = oracle.velocity(fp, x, y, 5.0, step=4, t_n=5.0, dt=0.1)
+    uo, _ = oracle.velocity(fp, x, y, 5.0, step=5, t_n=5.0, dt=0.1)
+    np.testing.assert_array_equal(ue, oracle.interp(ua, x, y))
+    np.testing.assert_array_equal(uo, oracle.interp(ub, x, y))
+
+
+def test_time_linear_uniform_flow_is_integrated_exactly():
+    """For u(t) linear in time and uniform in space, RK4 with stages at
+    t_n, t_n + dt/2, t_n + dt/2, t_n + dt integrates exactly:
+    x_{n+1} = x_n + dt (u(t_n) + u(t_n + dt))/2."""
+    n = 8
+    ua, va = np.full((n, n), 1.0), np.full((n, n), 0.5)
+    ub, vb = np.full((n, n), 3.0), np.full((n, n), -1.0)
+    fl = oracle.grid_flow(ua, va, ub, vb, t_slot=(0.0, 1.0))
+    sp = oracle.Species([1.0], [2.0])
+    dt = 0.125
+    oracle.run(fl, sp, 1, dt, t_start=0.25)
+    u = lambda t: 1.0 + 2.0 * t
+    v = lambda t: 0.5 - 1.5 * t
+    assert abs(sp.dx[0] - dt * (u(0.25) + u(0.375)) / 2) < 1e-15
+    assert abs(sp.dy[0] - dt * (v(0.25) + v(0.375)) / 2) < 1e-15
+
+
+def test_uniform_flow_tracer_and_its_statistics():
+    """Steady uniform flow: x_n = x0 + n dt U (wrapped), every particle has
+    the same displacement, so MSD = |U|^2 t^2, D_x = U_x^2 t/2 and SEM = 0."""
+    fl = oracle.uniform_flow(0.7, -0.3)
+    sp = oracle.Species([6.0], [0.1])
+    rec = oracle.run(fl, sp, 100, 0.05, stats_every=10)
+    assert abs(sp.dx[0] - 0.7 * 5.0) < 1e-13 and abs(sp.dy[0] + 0.3 * 5.0) < 1e-13
+    assert abs(sp.xw[0] - oracle.wrap(6.0 + 3.5)) < 1e-12
+    assert abs(sp.yw[0] - oracle.wrap(0.1 - 1.5)) < 1e-12
+    t = rec[:, 0]
+    np.testing.assert_allclose(rec[:, 3], (0.58) * t * t, rtol=1e-12)
+    np.testing.assert_allclose(rec[:, 4], 0.49 * t / 2, rtol=1e-12)
+    np.testing.assert_allclose(rec[:, 6], 0.0, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Inertial particles (Sec. 3.3, 5.3)
+# --------------------------------------------------------------------------
+def _rk4_linear_closed_form(st, dt, nsteps, x0, v0, U):
+    """RK4 applied to y' = A y + b is y_{n+1} = P4(dt A) y_n + dt Q3(dt A) b with
+    P4(Z) = sum_{k<=4} Z^k/k! and Q3(Z) = sum_{k<=3} Z^k/(k+1)!; evaluated in
+    40-digit arithmetic for y = (x, v), A = [[0, 1], [0, -1/St]], b = (0, U/St)."""
+    mpmath.mp.dps = 40
+    st, dt = mpmath.mpf(st), mpmath.mpf(dt)
+    A = mpmath.matrix([[0, 1], [0, -1 / st]])
+    b = mpmath.matrix([0, mpmath.mpf(U) / st])
+    Z = dt * A
+    I = mpmath.eye(2)
+    P, Q, Zk = I * 0, I * 0, I
+    for k in range(5):
+        P += Zk / mpmath.factorial(k)
+        if k <= 3:
+            Q += Zk / mpmath.factorial(k + 1)
+        Zk = Zk * Z
+    c = dt * (Q * b)
+    y = mpmath.matrix([mpmath.mpf(x0), mpmath.mpf(v0)])
+    for _ in range(nsteps):
+        y = P * y + c
+    return float(y[0]), float(y[1])
+
+
+@pytest.mark.parametrize("st", [0.1, 0.5, 2.0])
+def test_inertial_uniform_flow_discrete_closed_form(st):
+    dt, nsteps = 1e-2, 300
+    fl = oracle.uniform_flow(1.0, 0.0, length=1e6)
+    sp = oracle.Species([0.25], [0.25], kind=oracle.INERTIAL, st=st, vx0=[0.0], vy0=[0.0], length=1e6)
+    oracle.run(fl, sp, nsteps, dt)
+    xe, ve = _rk4_linear_closed_form(st, dt, nsteps, 0.0, 0.0, 1.0)
+    assert abs(sp.dx[0] - xe) < 1e-13 * max(1, abs(xe))
+    assert abs(sp.vx[0] - ve) < 1e-14
+    assert sp.dy[0] == 0.0 and sp.vy[0] == 0.0
+
+
+@pytest.mark.parametrize("st", [0.1, 1.0])
+def test_inertial_uniform_flow_continuous_solution(st):
+    """eq. uniform_solution: v = 1 - exp(-t/St), x = x0 + t - St (1 - exp(-t/St)),
+    reached to O(dt^4)."""
+    dt, T = 1e-3, 0.5
+    n = 16
+    fl = oracle.grid_flow(np.ones((n, n)), np.zeros((n, n)), t_slot=(0.0, 10.0))
+    sp = oracle.Species([0.25], [0.25], kind=oracle.INERTIAL, st=st, vx0=[0.0], vy0=[0.0])
+    oracle.run(fl, sp, int(round(T / dt)), dt)
+    e = math.exp(-T / st)
+    assert abs(sp.vx[0] - (1 - e)) < 1e-11
+    assert abs(0.25 + sp.dx[0] - (0.25 + T - st * (1 - e))) < 1e-11
+
+
+def _transit_time(st, dt=1e-3):
+    n = 16
+    fl = oracle.grid_flow(np.ones((n, n)), np.zeros((n, n)), t_slot=(0.0, 100.0))
+    kind = oracle.INERTIAL if st > 0 else oracle.TRACER
+    sp = oracle.Species([0.25], [0.25], kind=kind, st=st, vx0=[0.0], vy0=[0.0])
+    t, xprev = 0.0, 0.25
+    for k in range(100000):
+        oracle.run(fl, sp, 1, dt, t_start=k * dt, step0=k)
+        x = 0.25 + sp.dx[0]
+        if x >= 0.5:
+            return k * dt + dt * (0.5 - xprev) / (x - xprev)
+        xprev = x
+    raise AssertionError("no crossing")
+
+
+def test_table1_transit_times():
+    """Sec. 5.3, Table uniform_validation: transit time 0.25 -> 0.5 in the
+    uniform flow u = (1, 0), to the printed three decimals."""
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "table1_transit.txt"))
+            if l.strip() and not l.startswith("#")]
+    for st_s, t_s in rows:
+        t = _transit_time(float(st_s))
+        assert abs(t - float(t_s)) <= 0.0005 + 1e-9, (st_s, t, t_s)
+
+
+def test_st_zero_is_tracer_and_small_st_converges_linearly():
+    """Sec. 3.3: St -> 0 recovers the tracer equations.  St = 0 integrates the
+    tracer equations bit for bit; for small St with v0 = u(x0) the deviation
+    from the tracer path scales like St."""
+    fl = oracle.tg_flow()
+    x0, y0 = [0.3, 2.0, 4.4], [1.1, 0.2, 5.5]
+    tr = oracle.Species(x0, y0)
+    oracle.run(fl, tr, 2000, 1e-4)
+    z = oracle.Species(x0, y0, kind=oracle.INERTIAL, st=0.0)
+    oracle.run(fl, z, 2000, 1e-4)
+    np.testing.assert_array_equal(tr.xw, z.xw)
+    np.testing.assert_array_equal(tr.dy, z.dy)
+    devs = []
+    sts = [1e-2, 5e-3, 2.5e-3]
+    for st in sts:
+        u0, v0 = oracle.velocity(fl, x0, y0, 0.0)
+        sp = oracle.Species(x0, y0, kind=oracle.INERTIAL, st=st, vx0=u0, vy0=v0)
+        oracle.run(fl, sp, 2000, 1e-4)
+        devs.append(np.max(np.hypot(sp.dx - tr.dx, sp.dy - tr.dy)))
+    slope = np.polyfit(np.log(sts), np.log(devs), 1)[0]
+    assert 0.9 < slope < 1.1, (slope, devs)
+
+
+# --------------------------------------------------------------------------
+# Tracers in Taylor-Green flow (Sec. 5.2 flow with eps = 0)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("c", [0.985, 0.841, 0.479])
+def test_steady_tg_orbit_period_and_invariant(c):
+    """psi = sin x sin y is constant along tracer paths of the steady cellular
+    flow; the closed orbit psi = c has period 4 K(m = 1 - c^2)."""
+    fl = oracle.tg_flow()
+    sp = oracle.Species([np.pi / 2], [np.arcsin(c)])
+    dt = 2e-3
+    crossings = []
+    xo = sp.xw[0] - np.pi / 2
+    psi_dev = 0.0
+    for k in range(10000):
+        oracle.run(fl, sp, 1, dt, t_start=k * dt, step0=k)
+        xn = sp.xw[0] - np.pi / 2
+        psi_dev = max(psi_dev, abs(np.sin(sp.xw[0]) * np.sin(sp.yw[0]) - c))
+        if k > 5 and (xo < 0 <= xn or xo > 0 >= xn):
+            crossings.append((k + (-xo) / (xn - xo)) * dt)
+            if len(crossings) == 2:
+                break
+        xo = xn
+    period = crossings[1]
+    assert abs(period - 4 * scipy.special.ellipk(1 - c * c)) < 1e-5
+    assert psi_dev < 1e-9
+
+
+def test_rk4_fourth_order_in_analytic_flow():
+    """Position error at T = 1 in the oscillating Taylor-Green flow falls by
+    ~2^4 per halving of dt."""
+    fl = oracle.tg_flow(alpha=1.0, k=1.0, eps=0.3, omega=1.8, phi=0.0)
+    x0, y0 = [0.4, 2.5, 5.0], [1.3, 0.7, 3.9]
+    ref = oracle.Species(x0, y0)
+    oracle.run(fl, ref, 6400, 1.0 / 6400)
+    errs = []
+    for m in (25, 50, 100):
+        sp = oracle.Species(x0, y0)
+        oracle.run(fl, sp, m, 1.0 / m)
+        errs.append(np.max(np.hypot(sp.dx - ref.dx, sp.dy - ref.dy)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 14.0 < r1 < 18.5 and 14.0 < r2 < 18.5, errs
+
+
+def test_grid_tg_interpolation_error_is_second_order():
+    """Bilinear interpolation of the gridded Taylor-Green field has O(h^2)
+    error: doubling n divides the path error by ~4."""
+    x0, y0 = [0.4, 2.5, 5.0], [1.3, 0.7, 3.9]
+    ref = oracle.Species(x0, y0)
+    oracle.run(oracle.tg_flow(), ref, 200, 0.01)
+    errs = []
+    for n in (32, 64, 128):
+        u, v, _ = synth.taylor_green(n)
+        sp = oracle.Species(x0, y0)
+        oracle.run(oracle.grid_flow(u, v, t_slot=(0.0, 10.0)), sp, 200, 0.01)
+        errs.append(np.max(np.hypot(sp.dx - ref.dx, sp.dy - ref.dy)))
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
+
+
+# --------------------------------------------------------------------------
+# Statistics (MSD, D, SEM on unwrapped trajectories)
+# --------------------------------------------------------------------------
+def test_stats_against_exact_sums():
+    rng = np.random.default_rng(8)
+    dx = rng.standard_normal(10001) * 3 + 1e-3
+    dy = rng.standard_normal(10001) * 0.5
+    rec = oracle.stats(dx, dy, t=2.5, elapsed=2.0)
+    mx = math.fsum(dx * dx) / dx.size
+    my = math.fsum(dy * dy) / dy.size
+    assert rec[0] == 2.5 and rec[7] == dx.size
+    assert abs(rec[1] - mx) <= 1e-15 * mx and abs(rec[2] - my) <= 1e-15 * my
+    assert abs(rec[3] - (mx + my)) <= 2e-15 * (mx + my)
+    assert abs(rec[4] - mx / 4.0) <= 1e-15 * mx and abs(rec[5] - my / 4.0) <= 1e-15 * my
+    r2 = dx * dx + dy * dy
+    sem = math.sqrt(np.var(r2, ddof=1) / r2.size)
+    assert abs(rec[6] - sem) <= 1e-12 * sem
+
+
+def test_unwrapped_displacement_survives_many_wraps():
+    """Uniform flow crossing the periodic boundary many times: the wrapped
+    coordinate stays in [0, L) and the unwrapped one grows linearly."""
+    fl = oracle.uniform_flow(25.0, -13.0)
+    sp = oracle.Species([1.0, 6.2], [0.1, 3.0])
+    oracle.run(fl, sp, 400, 0.01)
+    assert np.all((sp.xw >= 0) & (sp.xw < L) & (sp.yw >= 0) & (sp.yw < L))
+    np.testing.assert_allclose(sp.dx, 100.0, rtol=1e-13)
+    np.testing.assert_allclose(sp.dy, -52.0, rtol=1e-13)
+    np.testing.assert_allclose(np.mod(sp.x0 + sp.dx, L), sp.xw, atol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# Exact-rational brute force of one step (rounding check)
+# --------------------------------------------------------------------------
+def _frac_bilinear(f, n, h, x, y):
+    i = int(x // h) % n
+    j = int(y // h) % n
+    xi = (x - (x // h) * h) / h
+    eta = (y - (y // h) * h) / h
+    g = lambda a, b: f[b % n][a % n]
+    return ((1 - xi) * (1 - eta) * g(i, j) + xi * (1 - eta) * g(i + 1, j)
+            + (1 - xi) * eta * g(i, j + 1) + xi * eta * g(i + 1, j + 1))
+
+
+def test_exact_rational_step_on_4x4_grid():
+    """One tracer step on a 4x4 grid with domain length 4 (h = 1) and dyadic
+    data, evaluated in exact rationals, agrees with the FP64 oracle to a few
+    ulp.  Uses the definition of bilinear interpolation and classical RK4."""
+    n, Lr = 4, Fraction(4)
+    rng = np.random.default_rng(9)
+    U = [[Fraction(int(rng.integers(-8, 9)), 8) for _ in range(n)] for _ in range(n)]
+    V = [[Fraction(int(rng.integers(-8, 9)), 8) for _ in range(n)] for _ in range(n)]
+    x0, y0, dt = Fraction(13, 16), Fraction(37, 16), Fraction(1, 4)
+
+    def vel(x, y):
+        x, y = x % Lr, y % Lr
+        return _frac_bilinear(U, n, 1, x, y), _frac_bilinear(V, n, 1, x, y)
+
+    k1 = vel(x0, y0)
+    k2 = vel(x0 + dt / 2 * k1[0], y0 + dt / 2 * k1[1])
+    k3 = vel(x0 + dt / 2 * k2[0], y0 + dt / 2 * k2[1])
+    k4 = vel(x0 + dt * k3[0], y0 + dt * k3[1])
+    ex = dt / 6 * (k1[0] + 2 * k2[0] + 2 * k3[0] + k4[0])
+    ey = dt / 6 * (k1[1] + 2 * k2[1] + 2 * k3[1] + k4[1])
+    fu = np.array([[float(a) for a in row] for row in U])
+    fv = np.array([[float(a) for a in row] for row in V])
+    fl = oracle.grid_flow(fu, fv, t_slot=(0.0, 1.0), length=4.0)
+    sp = oracle.Species([float(x0)], [float(y0)], length=4.0)
+    oracle.run(fl, sp, 1, float(dt))
+    assert abs(sp.dx[0] - float(ex)) < 1e-15 and abs(sp.dy[0] - float(ey)) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# Initial positions and cell keys
+# --------------------------------------------------------------------------
+def test_splitmix64_reference_outputs():
+    """SplitMix64 seeded with 0 produces the published reference stream
+    0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4, 0x06c45d188009454f."""
+    assert oracle.splitmix64(0, 0) == 0xE220A8397B1DCDAF
+    assert oracle.splitmix64(0, 1) == 0x6E789E6AA1B965F4
+    assert oracle.splitmix64(0, 2) == 0x06C45D188009454F
+
+
+def test_uniform_init_is_uniform_and_in_domain():
+    x, y = oracle.init_uniform(21, 100000)
+    assert np.all((x >= 0) & (x < L) & (y >= 0) & (y < L))
+    hx = np.histogram(x, bins=16, range=(0, L))[0]
+    assert np.all(np.abs(hx - 100000 / 16) < 5 * np.sqrt(100000 / 16))
+    assert abs(np.corrcoef(x, y)[0, 1]) < 0.01
+
+
+@pytest.mark.parametrize("tile", [1, 4, 16])
+def test_cell_keys_tile_major_bijection(tile):
+    n = 32
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    i, j = i.ravel(), j.ravel()
+    k = oracle.cell_keys(n, tile, i, j).astype(np.int64)
+    assert np.array_equal(np.sort(k), np.arange(n * n))
+    # decode: key -> tile (row-major over tiles) -> cell (row-major in tile)
+    t, r = k // (tile * tile), k % (tile * tile)
+    ti, tj = t % (n // tile), t // (n // tile)
+    np.testing.assert_array_equal(ti * tile + r % tile, i)
+    np.testing.assert_array_equal(tj * tile + r // tile, j)
+    kc = oracle.cell_keys(n, tile, i, j, coarse=True).astype(np.int64)
+    np.testing.assert_array_equal(kc, t)
+    if tile == 1:
+        np.testing.assert_array_equal(k, j * n + i)
