@@ -1,0 +1,147 @@
+// Internal interface between the host runtime (runtime.cpp) and the gfx950
+// kernels (step.hip, sort.hip, misc.hip) of liblpt.so.  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lpt {
+
+constexpr int kMaxSpecies = 16;
+constexpr int kStatTerms = 3;   // sum dx^2, sum dy^2, sum (dx^2 + dy^2)^2
+
+enum Scheme : int32_t { kBilinear = 0, kCatmullRom = 1, kBSpline = 2 };
+
+// One species as the step kernel sees it.  A species owns the contiguous
+// particle range [offset, offset + count) of the state arrays and the logical
+// blocks [block_begin, block_end) of the step grid.
+struct SpeciesDev {
+    int32_t inertial;      // 1: Stokes drag with inv_st; 0: tracer (St == 0 too)
+    int32_t scheme;        // Scheme
+    double inv_st;         // 1/St (inertial only)
+    int64_t offset;
+    int64_t count;
+    int32_t block_begin;
+    int32_t block_end;
+};
+
+struct StepParams {
+    int32_t n;             // grid points per side
+    int32_t nspecies;
+    int32_t total_blocks;  // logical blocks over all species
+    int32_t compat_edge;   // bicubic reverts to bilinear near the grid edge
+    double L, h, invh;     // domain side, spacing, n/L
+    double dt;
+    double wa[4], wb[4];   // temporal weights of slot 0 / slot 1 per RK4 stage
+    SpeciesDev sp[kMaxSpecies];
+};
+
+// Device-resident clock so that captured step chunks can be replayed.
+struct DevClock {
+    double t;          // time after the last enqueued step
+    int64_t step;      // steps taken
+    int64_t nrec;      // statistics records written per species
+    int64_t pad_;
+};
+
+// FP64 state, structure of arrays, pairs interleaved (x, y).
+struct State64 {
+    double2 *pos;      // wrapped position in [0, L)
+    double2 *disp;     // unwrapped displacement since initialisation
+    double2 *vel;      // particle velocity (inertial species)
+    uint32_t *id;      // global particle index (species offset + local index)
+};
+
+// FP32 split state: integer periodic cell packed as (cy << 16) | cx, binary32
+// offset in [0, 1) cell units, binary64 displacement (physical units),
+// binary32 velocity in cells per unit time.
+struct State32 {
+    uint32_t *cell;
+    float2 *off;
+    double2 *disp;
+    float2 *vel;
+    uint32_t *id;
+};
+
+// Snapshot records: both time levels of one node side by side.
+// FP64: {u0, v0, u1, v1} in physical units.  FP32: {u0, v0, u1, v1} in
+// cells per unit time (u * n / L).
+struct alignas(32) Rec64 { double u0, v0, u1, v1; };
+
+// ---- launch wrappers (return hipGetLastError of the launch) -------------
+hipError_t launch_pack64(Rec64 *rec, int slot, const double *u, const double *v, int64_t nn,
+                         hipStream_t st);
+hipError_t launch_pack32(float4 *rec, int slot, const double *u, const double *v, int64_t nn,
+                         double scale, hipStream_t st);
+hipError_t launch_psi_to_velocity(const double *psi, double *u, double *v, int n, double h,
+                                  hipStream_t st);
+
+hipError_t launch_step64(const StepParams &P, const State64 &S, const Rec64 *rec,
+                         double *partials, DevClock *clock, bool stats, bool cubic,
+                         bool inertial, int block, int grid, hipStream_t st);
+hipError_t launch_step32(const StepParams &P, const State32 &S, const float4 *rec,
+                         double *partials, DevClock *clock, bool stats, bool cubic,
+                         bool inertial, int block, int grid, hipStream_t st);
+
+hipError_t launch_finalize(const StepParams &P, const double *partials, DevClock *clock,
+                           double *records, int64_t rec_cap, double t0, hipStream_t st);
+
+// Initial state of particles [begin, begin + count) from x0 and v0 (both in
+// original order, indexed by global particle index).  An inertial species
+// takes its velocity from the field (vel_from_field) or from v0.
+hipError_t launch_init64(const StepParams &P, const State64 &S, const double2 *x0,
+                         const double2 *v0, const Rec64 *rec, int species, int64_t begin,
+                         int64_t count, double wa, double wb, int vel_from_field,
+                         hipStream_t st);
+hipError_t launch_init32(const StepParams &P, const State32 &S, const double2 *x0,
+                         const double2 *v0, const float4 *rec, int species, int64_t begin,
+                         int64_t count, double wa, double wb, int vel_from_field,
+                         hipStream_t st);
+hipError_t launch_interleave(double2 *dst, const double *a, const double *b, int64_t n,
+                             hipStream_t st);
+hipError_t launch_splitmix(double2 *x0, int64_t count, uint64_t seed, double L, hipStream_t st);
+
+hipError_t launch_interp64(const StepParams &P, const Rec64 *rec, int scheme, int64_t npts,
+                           const double *x, const double *y, double wa, double wb, double *u,
+                           double *v, hipStream_t st);
+hipError_t launch_interp32(const StepParams &P, const float4 *rec, int scheme, int64_t npts,
+                           const double *x, const double *y, double wa, double wb, double *u,
+                           double *v, hipStream_t st);
+
+// Readout in original particle order (id - offset).
+hipError_t launch_readout64(const State64 &S, const double2 *x0, int64_t offset, int64_t count,
+                            double L, double *xw, double *yw, double *xu, double *yu,
+                            double *vx, double *vy, hipStream_t st);
+hipError_t launch_readout32(const State32 &S, const double2 *x0, int64_t offset, int64_t count,
+                            double h, double *xw, double *yw, double *xu, double *yu,
+                            double *vx, double *vy, hipStream_t st);
+
+hipError_t launch_order(const uint32_t *id, int64_t offset, int64_t count, int32_t *out,
+                        hipStream_t st);
+
+// ---- cell-order sort -------------------------------------------------------
+struct SortWork {
+    uint32_t *keys[2];
+    uint32_t *vals[2];
+    uint32_t *hist;        // 256 * max_tiles counters
+    uint32_t *scan_tmp;    // block sums of the histogram scan
+    int64_t capacity;      // keys
+};
+int64_t sort_hist_entries(int64_t n);
+int64_t sort_scan_blocks(int64_t n);
+
+// keys = (species << tile_bits) | tile index of the stored cell; vals = iota.
+hipError_t launch_keys64(const StepParams &P, const State64 &S, int tile, int tile_bits,
+                         uint32_t *keys, uint32_t *vals, hipStream_t st);
+hipError_t launch_keys32(const StepParams &P, const State32 &S, int tile, int tile_bits,
+                         uint32_t *keys, uint32_t *vals, hipStream_t st);
+// Stable LSD radix sort of (keys[0], vals[0]) over the low key_bits bits;
+// *result receives the buffer index (0 or 1) holding the sorted output.
+hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, int *result, hipStream_t st);
+hipError_t launch_permute64(const State64 &src, const State64 &dst, const uint32_t *perm,
+                            int64_t n, bool with_vel, hipStream_t st);
+hipError_t launch_permute32(const State32 &src, const State32 &dst, const uint32_t *perm,
+                            int64_t n, bool with_vel, hipStream_t st);
+hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t st);
+
+}  // namespace lpt

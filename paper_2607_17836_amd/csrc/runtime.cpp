@@ -1,0 +1,923 @@
+// Host runtime of liblpt.so: the C ABI of include/lpt.h on top of the gfx950
+// kernels.  Validation happens before anything is enqueued so that a failed
+// call leaves the context unchanged; every HIP failure is reported as
+// LPT_E_HIP with the runtime's message.
+#include "lpt.h"
+#include "lpt_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace lpt;
+
+namespace {
+
+struct SpeciesHost {
+    int32_t kind;
+    double st;
+    int32_t scheme;
+    int64_t count;
+    int64_t offset;
+    bool vel_from_field;
+};
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+}  // namespace
+
+struct lpt_ctx {
+    lpt_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int32_t n = 0;
+    double L = 0, h = 0, invh = 0;
+    int32_t precision = LPT_FP64;
+    int32_t block = 256;
+    int32_t sort_interval = 0;
+    int32_t sort_tile = 16;
+    bool compat_edge = false;
+    std::string err;
+
+    // snapshots
+    void *rec = nullptr;   // Rec64[n*n] or float4[n*n]
+    bool slot_set[2] = {false, false};
+    double t_slot[2] = {0, 0};
+    int32_t time_mode = LPT_TIME_BRACKET;
+
+    // particles
+    std::vector<SpeciesHost> sp;
+    int64_t np = 0;
+    State64 s64[2]{};
+    State32 s32[2]{};
+    int cur = 0;
+    double2 *x0 = nullptr;   // initial positions, original order
+    double2 *v0 = nullptr;   // given initial velocities, original order
+    bool has_inertial = false, has_cubic = false;
+
+    // statistics
+    double *partials = nullptr;
+    int64_t partial_blocks = 0;
+    double *records = nullptr;
+    int64_t rec_cap = 0;
+    int64_t nrec = 0;
+    DevClock *clock = nullptr;
+
+    // sort workspace
+    SortWork sw{};
+
+    int64_t steps = 0;
+    double t = 0;
+
+    // optional event timing of step kernels and re-sorts
+    bool time_kernels = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_step, ev_sort;
+};
+
+namespace {
+
+lpt_status fail(lpt_ctx *c, lpt_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+    do {                                                                                    \
+        const hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), LPT_E_HIP,                                                   \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T *&p, size_t count)
+{
+    void *q = nullptr;
+    const hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    p = static_cast<T *>(q);
+    return e;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2i(int64_t v)
+{
+    int s = 0;
+    while ((int64_t(1) << s) < v) ++s;
+    return s;
+}
+
+void free_state(lpt_ctx *c)
+{
+    for (int k = 0; k < 2; ++k) {
+        dfree(c->s64[k].pos);
+        dfree(c->s64[k].disp);
+        dfree(c->s64[k].vel);
+        dfree(c->s64[k].id);
+        dfree(c->s32[k].cell);
+        dfree(c->s32[k].off);
+        dfree(c->s32[k].disp);
+        dfree(c->s32[k].vel);
+        dfree(c->s32[k].id);
+    }
+}
+
+void free_sort(lpt_ctx *c)
+{
+    dfree(c->sw.keys[0]);
+    dfree(c->sw.keys[1]);
+    dfree(c->sw.vals[0]);
+    dfree(c->sw.vals[1]);
+    dfree(c->sw.hist);
+    dfree(c->sw.scan_tmp);
+    c->sw.capacity = 0;
+}
+
+StepParams make_params(const lpt_ctx *c)
+{
+    StepParams P{};
+    P.n = c->n;
+    P.nspecies = (int32_t)c->sp.size();
+    P.compat_edge = c->compat_edge ? 1 : 0;
+    P.L = c->L;
+    P.h = c->h;
+    P.invh = c->invh;
+    int32_t blk = 0;
+    for (size_t s = 0; s < c->sp.size(); ++s) {
+        const SpeciesHost &h = c->sp[s];
+        SpeciesDev &d = P.sp[s];
+        d.inertial = (h.kind == LPT_INERTIAL && h.st > 0.0) ? 1 : 0;
+        d.scheme = h.scheme;
+        d.inv_st = d.inertial ? 1.0 / h.st : 0.0;
+        d.offset = h.offset;
+        d.count = h.count;
+        d.block_begin = blk;
+        blk += (int32_t)((h.count + c->block - 1) / c->block);
+        d.block_end = blk;
+    }
+    P.total_blocks = blk;
+    return P;
+}
+
+// Temporal weights of slot 0 / slot 1 at time t for the step with 0-based
+// number `step` starting at t_n.
+void weights_at(const lpt_ctx *c, int64_t step, double t_n, double t, double dt, double &wa,
+                double &wb)
+{
+    if (c->time_mode == LPT_TIME_PINGPONG) {
+        const double theta = (t - t_n) / dt;
+        const bool slot0_first = (step & 1) == 0;
+        wa = slot0_first ? 1.0 - theta : theta;
+        wb = slot0_first ? theta : 1.0 - theta;
+    } else {
+        const double ta = c->t_slot[0], tb = c->t_slot[1];
+        double theta = (t - ta) / (tb - ta);
+        theta = std::min(1.0, std::max(0.0, theta));
+        wa = 1.0 - theta;
+        wb = theta;
+    }
+}
+
+int species_bits(const lpt_ctx *c) { return c->sp.size() > 1 ? ilog2i((int64_t)c->sp.size()) : 0; }
+int tile_bits(const lpt_ctx *c) { return 2 * ilog2i(c->n / c->sort_tile); }
+
+lpt_status ensure_sort_work(lpt_ctx *c)
+{
+    if (c->sw.capacity >= c->np) return LPT_OK;
+    free_sort(c);
+    HIP_TRY(c, dalloc(c->sw.keys[0], c->np));
+    HIP_TRY(c, dalloc(c->sw.keys[1], c->np));
+    HIP_TRY(c, dalloc(c->sw.vals[0], c->np));
+    HIP_TRY(c, dalloc(c->sw.vals[1], c->np));
+    HIP_TRY(c, dalloc(c->sw.hist, (size_t)sort_hist_entries(c->np)));
+    HIP_TRY(c, dalloc(c->sw.scan_tmp, (size_t)sort_scan_blocks(c->np)));
+    c->sw.capacity = c->np;
+    return LPT_OK;
+}
+
+// Next timing event of the pool (created on first use).
+hipError_t next_event(lpt_ctx *c, hipEvent_t &ev)
+{
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        const hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        c->ev_pool.push_back(e);
+    }
+    ev = c->ev_pool[c->ev_used++];
+    return hipSuccess;
+}
+
+hipError_t mark(lpt_ctx *c, hipEvent_t &ev)
+{
+    const hipError_t r = next_event(c, ev);
+    return r != hipSuccess ? r : hipEventRecord(ev, c->stream);
+}
+
+lpt_status do_sort(lpt_ctx *c)
+{
+    if (c->np <= 1) return LPT_OK;
+    lpt_status s = ensure_sort_work(c);
+    if (s != LPT_OK) return s;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->time_kernels) HIP_TRY(c, mark(c, e0));
+    const StepParams P = make_params(c);
+    const int tb = tile_bits(c);
+    const int kb = std::max(1, tb + species_bits(c));
+    if (c->precision == LPT_FP64)
+        HIP_TRY(c, launch_keys64(P, c->s64[c->cur], c->sort_tile, tb, c->sw.keys[0], c->sw.vals[0],
+                                 c->stream));
+    else
+        HIP_TRY(c, launch_keys32(P, c->s32[c->cur], c->sort_tile, tb, c->sw.keys[0], c->sw.vals[0],
+                                 c->stream));
+    int res = 0;
+    HIP_TRY(c, radix_sort(c->sw, c->np, kb, &res, c->stream));
+    const uint32_t *perm = c->sw.vals[res];
+    if (c->precision == LPT_FP64)
+        HIP_TRY(c, launch_permute64(c->s64[c->cur], c->s64[1 - c->cur], perm, c->np,
+                                    c->has_inertial, c->stream));
+    else
+        HIP_TRY(c, launch_permute32(c->s32[c->cur], c->s32[1 - c->cur], perm, c->np,
+                                    c->has_inertial, c->stream));
+    c->cur = 1 - c->cur;
+    if (c->time_kernels) {
+        HIP_TRY(c, mark(c, e1));
+        c->ev_sort.emplace_back(e0, e1);
+    }
+    return LPT_OK;
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+extern "C" {
+
+const char *lpt_status_string(lpt_status s)
+{
+    switch (s) {
+    case LPT_OK: return "LPT_OK";
+    case LPT_E_ARG: return "LPT_E_ARG";
+    case LPT_E_STATE: return "LPT_E_STATE";
+    case LPT_E_RANGE: return "LPT_E_RANGE";
+    case LPT_E_NOMEM: return "LPT_E_NOMEM";
+    case LPT_E_HIP: return "LPT_E_HIP";
+    }
+    return "LPT_E_UNKNOWN";
+}
+
+const char *lpt_last_error(const lpt_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+static thread_local std::string g_create_error;
+
+lpt_status lpt_create(const lpt_config *cfg, lpt_ctx **out)
+{
+    if (!cfg || !out) return LPT_E_ARG;
+    *out = nullptr;
+    const int32_t n = cfg->n;
+    if (n < 4 || n > 32768) return LPT_E_ARG;
+    if (cfg->precision != LPT_FP64 && cfg->precision != LPT_FP32_SPLIT) return LPT_E_ARG;
+    const double L = cfg->length == 0.0 ? 2.0 * M_PI : cfg->length;
+    if (!(L > 0.0) || !std::isfinite(L) || !std::isfinite(cfg->t0)) return LPT_E_ARG;
+    if (cfg->sort_interval < 0) return LPT_E_ARG;
+    int32_t tile = cfg->sort_tile;
+    if (tile == 0) {
+        tile = 16;
+        while (tile > 1 && n % tile) tile >>= 1;
+    }
+    if (!is_pow2(tile) || n % tile) return LPT_E_ARG;
+    const int32_t block = cfg->block_size == 0 ? 256 : cfg->block_size;
+    if (block != 64 && block != 128 && block != 256 && block != 512) return LPT_E_ARG;
+    if (cfg->flags & ~(LPT_FLAG_COMPAT_EDGE | LPT_FLAG_TIME_KERNELS)) return LPT_E_ARG;
+
+    lpt_ctx *c = new (std::nothrow) lpt_ctx();
+    if (!c) return LPT_E_NOMEM;
+    c->cfg = *cfg;
+    c->stream = static_cast<hipStream_t>(cfg->hip_stream);
+    c->n = n;
+    c->L = L;
+    c->h = L / n;
+    c->invh = n / L;
+    c->precision = cfg->precision;
+    c->block = block;
+    c->sort_interval = cfg->sort_interval;
+    c->sort_tile = tile;
+    c->compat_edge = (cfg->flags & LPT_FLAG_COMPAT_EDGE) != 0;
+    c->time_kernels = (cfg->flags & LPT_FLAG_TIME_KERNELS) != 0;
+    c->t = cfg->t0;
+
+    auto bail = [&](hipError_t e) {
+        g_create_error = hipGetErrorString(e);
+        lpt_destroy(c);
+        return LPT_E_HIP;
+    };
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) return bail(e);
+    const size_t nn = (size_t)n * n;
+    const size_t rec_bytes = nn * (c->precision == LPT_FP64 ? sizeof(Rec64) : sizeof(float4));
+    e = hipMalloc(&c->rec, rec_bytes);
+    if (e != hipSuccess) return bail(e);
+    e = hipMemsetAsync(c->rec, 0, rec_bytes, c->stream);
+    if (e != hipSuccess) return bail(e);
+    e = dalloc(c->clock, 1);
+    if (e != hipSuccess) return bail(e);
+    DevClock ck{cfg->t0, 0, 0, 0};
+    e = hipMemcpyAsync(c->clock, &ck, sizeof ck, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return bail(e);
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return bail(e);
+    *out = c;
+    return LPT_OK;
+}
+
+void lpt_destroy(lpt_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    free_state(c);
+    free_sort(c);
+    dfree(c->x0);
+    dfree(c->v0);
+    dfree(c->partials);
+    dfree(c->records);
+    dfree(c->clock);
+    if (c->rec) (void)hipFree(c->rec);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+lpt_status lpt_synchronize(lpt_ctx *c)
+{
+    if (!c) return LPT_E_ARG;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LPT_OK;
+}
+
+// Device copies of caller arrays: `count` doubles per pointer.
+namespace {
+struct Staged {
+    std::vector<double *> bufs;
+    ~Staged()
+    {
+        for (double *p : bufs) (void)hipFree(p);
+    }
+};
+
+lpt_status stage_in(lpt_ctx *c, Staged &st, const double *src, int64_t count, int32_t on_device,
+                    const double *&dst)
+{
+    if (!src) {
+        dst = nullptr;
+        return LPT_OK;
+    }
+    if (on_device) {
+        dst = src;
+        return LPT_OK;
+    }
+    double *d = nullptr;
+    HIP_TRY(c, dalloc(d, (size_t)count));
+    st.bufs.push_back(d);
+    HIP_TRY(c, hipMemcpyAsync(d, src, (size_t)count * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
+    dst = d;
+    return LPT_OK;
+}
+}  // namespace
+
+lpt_status lpt_set_snapshot(lpt_ctx *c, int32_t slot, double t, const double *u, const double *v,
+                            int32_t on_device)
+{
+    if (!c) return LPT_E_ARG;
+    if (slot != 0 && slot != 1) return fail(c, LPT_E_ARG, "slot must be 0 or 1");
+    if (!is_finite(t)) return fail(c, LPT_E_ARG, "snapshot time must be finite");
+    if (!u || !v) return fail(c, LPT_E_ARG, "u and v must not be NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t nn = (int64_t)c->n * c->n;
+    Staged st;
+    const double *du = nullptr, *dv = nullptr;
+    lpt_status s = stage_in(c, st, u, nn, on_device, du);
+    if (s == LPT_OK) s = stage_in(c, st, v, nn, on_device, dv);
+    if (s != LPT_OK) return s;
+    if (c->precision == LPT_FP64)
+        HIP_TRY(c, launch_pack64(static_cast<Rec64 *>(c->rec), slot, du, dv, nn, c->stream));
+    else
+        HIP_TRY(c, launch_pack32(static_cast<float4 *>(c->rec), slot, du, dv, nn, c->invh,
+                                 c->stream));
+    if (!st.bufs.empty()) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->slot_set[slot] = true;
+    c->t_slot[slot] = t;
+    return LPT_OK;
+}
+
+lpt_status lpt_set_snapshot_psi(lpt_ctx *c, int32_t slot, double t, const double *psi,
+                                int32_t on_device)
+{
+    if (!c) return LPT_E_ARG;
+    if (slot != 0 && slot != 1) return fail(c, LPT_E_ARG, "slot must be 0 or 1");
+    if (!is_finite(t)) return fail(c, LPT_E_ARG, "snapshot time must be finite");
+    if (!psi) return fail(c, LPT_E_ARG, "psi must not be NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t nn = (int64_t)c->n * c->n;
+    Staged st;
+    const double *dp = nullptr;
+    lpt_status s = stage_in(c, st, psi, nn, on_device, dp);
+    if (s != LPT_OK) return s;
+    double *uv = nullptr;
+    HIP_TRY(c, dalloc(uv, (size_t)(2 * nn)));
+    st.bufs.push_back(uv);
+    HIP_TRY(c, launch_psi_to_velocity(dp, uv, uv + nn, c->n, c->h, c->stream));
+    if (c->precision == LPT_FP64)
+        HIP_TRY(c, launch_pack64(static_cast<Rec64 *>(c->rec), slot, uv, uv + nn, nn, c->stream));
+    else
+        HIP_TRY(c, launch_pack32(static_cast<float4 *>(c->rec), slot, uv, uv + nn, nn, c->invh,
+                                 c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->slot_set[slot] = true;
+    c->t_slot[slot] = t;
+    return LPT_OK;
+}
+
+lpt_status lpt_set_time_mode(lpt_ctx *c, lpt_time_mode mode)
+{
+    if (!c) return LPT_E_ARG;
+    if (mode != LPT_TIME_BRACKET && mode != LPT_TIME_PINGPONG)
+        return fail(c, LPT_E_ARG, "unknown time mode");
+    c->time_mode = mode;
+    return LPT_OK;
+}
+
+namespace {
+
+lpt_status init_species_state(lpt_ctx *c, int sid)
+{
+    const StepParams P = make_params(c);
+    const SpeciesHost &s = c->sp[sid];
+    double wa = 1.0, wb = 0.0;
+    if (c->slot_set[0] && c->slot_set[1]) weights_at(c, c->steps, c->t, c->t, 1.0, wa, wb);
+    const int field = s.vel_from_field ? 1 : 0;
+    if (c->precision == LPT_FP64)
+        HIP_TRY(c, launch_init64(P, c->s64[c->cur], c->x0, c->v0, static_cast<Rec64 *>(c->rec),
+                                 sid, s.offset, s.count, wa, wb, field, c->stream));
+    else
+        HIP_TRY(c, launch_init32(P, c->s32[c->cur], c->x0, c->v0, static_cast<float4 *>(c->rec),
+                                 sid, s.offset, s.count, wa, wb, field, c->stream));
+    return LPT_OK;
+}
+
+// Grow every state array to `np` particles, keeping the first `old` ones.
+lpt_status grow_state(lpt_ctx *c, int64_t np, int64_t old, bool inertial)
+{
+    const bool fp64 = c->precision == LPT_FP64;
+    State64 n64[2]{};
+    State32 n32[2]{};
+    double2 *nx0 = nullptr, *nv0 = nullptr;
+    auto cleanup = [&]() {
+        for (int k = 0; k < 2; ++k) {
+            dfree(n64[k].pos); dfree(n64[k].disp); dfree(n64[k].vel); dfree(n64[k].id);
+            dfree(n32[k].cell); dfree(n32[k].off); dfree(n32[k].disp); dfree(n32[k].vel);
+            dfree(n32[k].id);
+        }
+        dfree(nx0);
+        dfree(nv0);
+    };
+    bool ok = true;
+    const bool vel = inertial || c->has_inertial;
+    for (int k = 0; k < 2 && ok; ++k) {
+        if (fp64) {
+            ok = dalloc(n64[k].pos, np) == hipSuccess && dalloc(n64[k].disp, np) == hipSuccess &&
+                 dalloc(n64[k].id, np) == hipSuccess &&
+                 (!vel || dalloc(n64[k].vel, np) == hipSuccess);
+        } else {
+            ok = dalloc(n32[k].cell, np) == hipSuccess && dalloc(n32[k].off, np) == hipSuccess &&
+                 dalloc(n32[k].disp, np) == hipSuccess && dalloc(n32[k].id, np) == hipSuccess &&
+                 (!vel || dalloc(n32[k].vel, np) == hipSuccess);
+        }
+    }
+    ok = ok && dalloc(nx0, np) == hipSuccess && (!vel || dalloc(nv0, np) == hipSuccess);
+    if (!ok) {
+        cleanup();
+        (void)hipGetLastError();
+        return fail(c, LPT_E_NOMEM, "device allocation of the particle state failed");
+    }
+    if (old > 0) {
+        const int k = c->cur;
+        hipError_t e = hipSuccess;
+        auto cp = [&](void *d, const void *s, size_t bytes) {
+            if (e == hipSuccess && s && d)
+                e = hipMemcpyAsync(d, s, bytes, hipMemcpyDeviceToDevice, c->stream);
+        };
+        if (fp64) {
+            cp(n64[k].pos, c->s64[k].pos, old * sizeof(double2));
+            cp(n64[k].disp, c->s64[k].disp, old * sizeof(double2));
+            cp(n64[k].vel, c->s64[k].vel, old * sizeof(double2));
+            cp(n64[k].id, c->s64[k].id, old * sizeof(uint32_t));
+        } else {
+            cp(n32[k].cell, c->s32[k].cell, old * sizeof(uint32_t));
+            cp(n32[k].off, c->s32[k].off, old * sizeof(float2));
+            cp(n32[k].disp, c->s32[k].disp, old * sizeof(double2));
+            cp(n32[k].vel, c->s32[k].vel, old * sizeof(float2));
+            cp(n32[k].id, c->s32[k].id, old * sizeof(uint32_t));
+        }
+        cp(nx0, c->x0, old * sizeof(double2));
+        cp(nv0, c->v0, old * sizeof(double2));
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            cleanup();
+            return fail(c, LPT_E_HIP, std::string("state copy: ") + hipGetErrorString(e));
+        }
+    }
+    free_state(c);
+    dfree(c->x0);
+    dfree(c->v0);
+    for (int k = 0; k < 2; ++k) {
+        c->s64[k] = n64[k];
+        c->s32[k] = n32[k];
+    }
+    c->x0 = nx0;
+    c->v0 = nv0;
+    return LPT_OK;
+}
+
+}  // namespace
+
+lpt_status lpt_add_species(lpt_ctx *c, lpt_kind kind, double st, lpt_scheme scheme, int64_t count,
+                           const double *x0, const double *y0, const double *vx0,
+                           const double *vy0, int32_t on_device, int32_t *species_id)
+{
+    if (!c) return LPT_E_ARG;
+    if (kind != LPT_TRACER && kind != LPT_INERTIAL) return fail(c, LPT_E_ARG, "unknown kind");
+    if (!(st >= 0.0) || !is_finite(st)) return fail(c, LPT_E_ARG, "St must be finite and >= 0");
+    if (scheme < LPT_BILINEAR || scheme > LPT_BSPLINE) return fail(c, LPT_E_ARG, "unknown scheme");
+    if (count < 1) return fail(c, LPT_E_ARG, "count must be >= 1");
+    if (!x0 || !y0) return fail(c, LPT_E_ARG, "x0 and y0 must not be NULL");
+    if ((vx0 == nullptr) != (vy0 == nullptr))
+        return fail(c, LPT_E_ARG, "give both vx0 and vy0 or neither");
+    if (c->steps > 0) return fail(c, LPT_E_STATE, "species must be added before the first step");
+    if ((int)c->sp.size() >= kMaxSpecies) return fail(c, LPT_E_ARG, "too many species");
+    if (c->np + count > (int64_t)0x7FFFFFFF) return fail(c, LPT_E_ARG, "too many particles");
+    const bool inertial = kind == LPT_INERTIAL && st > 0.0;
+    if (inertial && !vx0 && !(c->slot_set[0] && c->slot_set[1]))
+        return fail(c, LPT_E_STATE, "v0 from the field needs both snapshots set");
+    int32_t nsp = (int32_t)c->sp.size() + 1;
+    if (2 * ilog2i(c->n / c->sort_tile) + (nsp > 1 ? ilog2i(nsp) : 0) > 32)
+        return fail(c, LPT_E_ARG, "sort key wider than 32 bits; raise sort_tile");
+    HIP_TRY(c, hipSetDevice(c->device));
+
+    Staged stg;
+    const double *dx = nullptr, *dy = nullptr, *dvx = nullptr, *dvy = nullptr;
+    lpt_status s = stage_in(c, stg, x0, count, on_device, dx);
+    if (s == LPT_OK) s = stage_in(c, stg, y0, count, on_device, dy);
+    if (s == LPT_OK && inertial) s = stage_in(c, stg, vx0, count, on_device, dvx);
+    if (s == LPT_OK && inertial) s = stage_in(c, stg, vy0, count, on_device, dvy);
+    if (s != LPT_OK) return s;
+
+    const int64_t old = c->np;
+    s = grow_state(c, old + count, old, inertial);
+    if (s != LPT_OK) return s;
+    // partial sums: one slot per logical block of every species
+    SpeciesHost h{(int32_t)kind, st, (int32_t)scheme, count, old, inertial && !vx0};
+    c->sp.push_back(h);
+    c->np = old + count;
+    c->has_inertial = c->has_inertial || inertial;
+    c->has_cubic = c->has_cubic || scheme != LPT_BILINEAR;
+    const StepParams P = make_params(c);
+    if (P.total_blocks > c->partial_blocks) {
+        dfree(c->partials);
+        HIP_TRY(c, dalloc(c->partials, (size_t)kStatTerms * P.total_blocks));
+        c->partial_blocks = P.total_blocks;
+    }
+    HIP_TRY(c, launch_interleave(c->x0 + old, dx, dy, count, c->stream));
+    if (inertial && dvx) HIP_TRY(c, launch_interleave(c->v0 + old, dvx, dvy, count, c->stream));
+    s = init_species_state(c, (int)c->sp.size() - 1);
+    if (s != LPT_OK) return s;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (species_id) *species_id = (int32_t)c->sp.size() - 1;
+    return LPT_OK;
+}
+
+lpt_status lpt_init_uniform(lpt_ctx *c, int32_t sid, uint64_t seed)
+{
+    if (!c) return LPT_E_ARG;
+    if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, LPT_E_ARG, "unknown species");
+    if (c->steps > 0) return fail(c, LPT_E_STATE, "initialisation only before the first step");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const SpeciesHost &s = c->sp[sid];
+    HIP_TRY(c, launch_splitmix(c->x0 + s.offset, s.count, seed, c->L, c->stream));
+    // a previous sort may have moved particles of this species around inside
+    // its range: re-initialising writes the state in original order again
+    return init_species_state(c, sid);
+}
+
+lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
+{
+    if (!c) return LPT_E_ARG;
+    if (nsteps < 0) return fail(c, LPT_E_ARG, "nsteps must be >= 0");
+    if (!(dt > 0.0) || !is_finite(dt)) return fail(c, LPT_E_ARG, "dt must be finite and > 0");
+    if (stats_every < 0) return fail(c, LPT_E_ARG, "stats_every must be >= 0");
+    if (c->sp.empty()) return fail(c, LPT_E_STATE, "no species");
+    if (!c->slot_set[0] || !c->slot_set[1])
+        return fail(c, LPT_E_STATE, "both snapshot slots must be set");
+    if (nsteps == 0) return LPT_OK;
+    if (c->time_mode == LPT_TIME_PINGPONG) {
+        const double gap = std::fabs(c->t_slot[1] - c->t_slot[0]);
+        if (std::fabs(gap - dt) > 1e-9 * dt)
+            return fail(c, LPT_E_ARG, "ping-pong mode needs dt equal to the snapshot spacing");
+    } else {
+        const double ta = c->t_slot[0], tb = c->t_slot[1];
+        if (!(tb > ta)) return fail(c, LPT_E_STATE, "bracket mode needs t(slot 1) > t(slot 0)");
+        const double tol = 1e-9 * (tb - ta);
+        double tt = c->t;
+        for (int64_t k = 0; k < nsteps; ++k) {
+            if (tt < ta - tol || tt + dt > tb + tol) {
+                char buf[160];
+                std::snprintf(buf, sizeof buf,
+                              "step %lld spans [%.17g, %.17g], outside the bracket [%.17g, %.17g]",
+                              (long long)(c->steps + k), tt, tt + dt, ta, tb);
+                return fail(c, LPT_E_RANGE, buf);
+            }
+            tt += dt;
+        }
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    // statistics capacity
+    int64_t new_rec = 0;
+    if (stats_every > 0) new_rec = (c->steps + nsteps) / stats_every - c->steps / stats_every;
+    if (c->nrec + new_rec > c->rec_cap) {
+        const int64_t cap = std::max<int64_t>(2 * c->rec_cap, c->nrec + new_rec + 64);
+        const int64_t ns = (int64_t)c->sp.size();
+        double *nr = nullptr;
+        HIP_TRY(c, dalloc(nr, (size_t)(ns * cap * 8)));
+        for (int64_t s = 0; s < ns && c->nrec > 0; ++s)
+            HIP_TRY(c, hipMemcpyAsync(nr + s * cap * 8, c->records + s * c->rec_cap * 8,
+                                      (size_t)c->nrec * 8 * sizeof(double),
+                                      hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        dfree(c->records);
+        c->records = nr;
+        c->rec_cap = cap;
+    }
+    StepParams P = make_params(c);
+    P.dt = dt;
+    const double stage_c[4] = {0.0, 0.5, 0.5, 1.0};
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (c->sort_interval > 0 && c->steps % c->sort_interval == 0) {
+            const lpt_status s = do_sort(c);
+            if (s != LPT_OK) return s;
+        }
+        for (int q = 0; q < 4; ++q)
+            weights_at(c, c->steps, c->t, c->t + stage_c[q] * dt, dt, P.wa[q], P.wb[q]);
+        const bool rec = stats_every > 0 && (c->steps + 1) % stats_every == 0;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->time_kernels) HIP_TRY(c, mark(c, e0));
+        if (c->precision == LPT_FP64)
+            HIP_TRY(c, launch_step64(P, c->s64[c->cur], static_cast<const Rec64 *>(c->rec),
+                                     c->partials, c->clock, rec, c->has_cubic, c->has_inertial,
+                                     c->block, P.total_blocks, c->stream));
+        else
+            HIP_TRY(c, launch_step32(P, c->s32[c->cur], static_cast<const float4 *>(c->rec),
+                                     c->partials, c->clock, rec, c->has_cubic, c->has_inertial,
+                                     c->block, P.total_blocks, c->stream));
+        if (c->time_kernels) {
+            HIP_TRY(c, mark(c, e1));
+            c->ev_step.emplace_back(e0, e1);
+        }
+        if (rec) {
+            HIP_TRY(c, launch_finalize(P, c->partials, c->clock, c->records, c->rec_cap,
+                                       c->cfg.t0, c->stream));
+            c->nrec += 1;
+        }
+        c->t += dt;
+        c->steps += 1;
+    }
+    return LPT_OK;
+}
+
+lpt_status lpt_sort(lpt_ctx *c)
+{
+    if (!c) return LPT_E_ARG;
+    if (c->sp.empty()) return fail(c, LPT_E_STATE, "no species");
+    HIP_TRY(c, hipSetDevice(c->device));
+    return do_sort(c);
+}
+
+namespace {
+lpt_status readout(lpt_ctx *c, int32_t sid, double *xw, double *yw, double *xu, double *yu,
+                   double *vx, double *vy, int32_t on_device)
+{
+    const SpeciesHost &s = c->sp[sid];
+    HIP_TRY(c, hipSetDevice(c->device));
+    double *outs[6] = {xw, yw, xu, yu, vx, vy};
+    double *dev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    Staged st;
+    for (int k = 0; k < 6; ++k) {
+        if (!outs[k]) continue;
+        if (on_device) {
+            dev[k] = outs[k];
+        } else {
+            HIP_TRY(c, dalloc(dev[k], (size_t)s.count));
+            st.bufs.push_back(dev[k]);
+        }
+    }
+    if (c->precision == LPT_FP64)
+        HIP_TRY(c, launch_readout64(c->s64[c->cur], c->x0, s.offset, s.count, c->L, dev[0], dev[1],
+                                    dev[2], dev[3], dev[4], dev[5], c->stream));
+    else
+        HIP_TRY(c, launch_readout32(c->s32[c->cur], c->x0, s.offset, s.count, c->h, dev[0],
+                                    dev[1], dev[2], dev[3], dev[4], dev[5], c->stream));
+    if (!on_device) {
+        for (int k = 0; k < 6; ++k)
+            if (outs[k])
+                HIP_TRY(c, hipMemcpyAsync(outs[k], dev[k], (size_t)s.count * sizeof(double),
+                                          hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return LPT_OK;
+}
+}  // namespace
+
+lpt_status lpt_get_positions(lpt_ctx *c, int32_t sid, double *xw, double *yw, double *xu,
+                             double *yu, int32_t on_device)
+{
+    if (!c) return LPT_E_ARG;
+    if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, LPT_E_ARG, "unknown species");
+    return readout(c, sid, xw, yw, xu, yu, nullptr, nullptr, on_device);
+}
+
+lpt_status lpt_get_velocities(lpt_ctx *c, int32_t sid, double *vx, double *vy, int32_t on_device)
+{
+    if (!c) return LPT_E_ARG;
+    if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, LPT_E_ARG, "unknown species");
+    const SpeciesHost &s = c->sp[sid];
+    if (!(s.kind == LPT_INERTIAL && s.st > 0.0))
+        return fail(c, LPT_E_STATE, "species carries no particle velocity (tracer or St = 0)");
+    return readout(c, sid, nullptr, nullptr, nullptr, nullptr, vx, vy, on_device);
+}
+
+lpt_status lpt_get_stats(lpt_ctx *c, int32_t sid, lpt_stat *out, int64_t cap, int64_t *n_written)
+{
+    if (!c) return LPT_E_ARG;
+    if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, LPT_E_ARG, "unknown species");
+    if (cap < 0 || (cap > 0 && !out)) return fail(c, LPT_E_ARG, "bad output buffer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t m = std::min(cap, c->nrec);
+    if (m > 0) {
+        HIP_TRY(c, hipMemcpyAsync(out, c->records + (int64_t)sid * c->rec_cap * 8,
+                                  (size_t)m * sizeof(lpt_stat), hipMemcpyDeviceToHost,
+                                  c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (n_written) *n_written = m;
+    return LPT_OK;
+}
+
+lpt_status lpt_get_order(lpt_ctx *c, int32_t sid, int32_t *ids, int32_t on_device)
+{
+    if (!c) return LPT_E_ARG;
+    if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, LPT_E_ARG, "unknown species");
+    if (!ids) return fail(c, LPT_E_ARG, "ids must not be NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const SpeciesHost &s = c->sp[sid];
+    const uint32_t *id = c->precision == LPT_FP64 ? c->s64[c->cur].id : c->s32[c->cur].id;
+    int32_t *d = ids;
+    if (!on_device) HIP_TRY(c, dalloc(d, (size_t)s.count));
+    hipError_t e = launch_order(id, s.offset, s.count, d, c->stream);
+    if (e == hipSuccess && !on_device)
+        e = hipMemcpyAsync(ids, d, (size_t)s.count * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (!on_device) (void)hipFree(d);
+    HIP_TRY(c, e);
+    return LPT_OK;
+}
+
+lpt_status lpt_get_timing(lpt_ctx *c, lpt_timing *out, int32_t reset)
+{
+    if (!c) return LPT_E_ARG;
+    if (!out) return fail(c, LPT_E_ARG, "out must not be NULL");
+    if (!c->time_kernels) return fail(c, LPT_E_STATE, "context created without LPT_FLAG_TIME_KERNELS");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    lpt_timing t{};
+    for (const auto &p : c->ev_step) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, p.first, p.second));
+        t.step_kernel_ms += ms;
+        t.step_launches += 1;
+    }
+    for (const auto &p : c->ev_sort) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, p.first, p.second));
+        t.sort_ms += ms;
+        t.sorts += 1;
+    }
+    *out = t;
+    if (reset) {
+        c->ev_step.clear();
+        c->ev_sort.clear();
+        c->ev_used = 0;
+    }
+    return LPT_OK;
+}
+
+lpt_status lpt_get_time(lpt_ctx *c, int64_t *steps, double *t)
+{
+    if (!c) return LPT_E_ARG;
+    if (steps) *steps = c->steps;
+    if (t) *t = c->t;
+    return LPT_OK;
+}
+
+lpt_status lpt_interp(lpt_ctx *c, lpt_scheme scheme, int64_t npts, const double *x, const double *y,
+                      double w_a, double w_b, double *u, double *v, int32_t on_device)
+{
+    if (!c) return LPT_E_ARG;
+    if (scheme < LPT_BILINEAR || scheme > LPT_BSPLINE) return fail(c, LPT_E_ARG, "unknown scheme");
+    if (npts < 0) return fail(c, LPT_E_ARG, "npts must be >= 0");
+    if (npts > 0 && (!x || !y || !u || !v)) return fail(c, LPT_E_ARG, "NULL array");
+    if (!is_finite(w_a) || !is_finite(w_b)) return fail(c, LPT_E_ARG, "weights must be finite");
+    if (npts == 0) return LPT_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    Staged st;
+    const double *dx = nullptr, *dy = nullptr;
+    lpt_status s = stage_in(c, st, x, npts, on_device, dx);
+    if (s == LPT_OK) s = stage_in(c, st, y, npts, on_device, dy);
+    if (s != LPT_OK) return s;
+    double *du = u, *dv = v;
+    if (!on_device) {
+        HIP_TRY(c, dalloc(du, (size_t)npts));
+        st.bufs.push_back(du);
+        HIP_TRY(c, dalloc(dv, (size_t)npts));
+        st.bufs.push_back(dv);
+    }
+    const StepParams P = make_params(c);
+    if (c->precision == LPT_FP64)
+        HIP_TRY(c, launch_interp64(P, static_cast<const Rec64 *>(c->rec), scheme, npts, dx, dy,
+                                   w_a, w_b, du, dv, c->stream));
+    else
+        HIP_TRY(c, launch_interp32(P, static_cast<const float4 *>(c->rec), scheme, npts, dx, dy,
+                                   w_a, w_b, du, dv, c->stream));
+    if (!on_device) {
+        HIP_TRY(c, hipMemcpyAsync(u, du, (size_t)npts * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+        HIP_TRY(c, hipMemcpyAsync(v, dv, (size_t)npts * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return LPT_OK;
+}
+
+lpt_status lpt_radix_sort(lpt_ctx *c, int64_t npts, int32_t key_bits, const uint32_t *keys_in,
+                          uint32_t *keys_out, uint32_t *perm)
+{
+    if (!c) return LPT_E_ARG;
+    if (npts < 0 || npts > (int64_t)0x7FFFFFFF) return fail(c, LPT_E_ARG, "bad npts");
+    if (key_bits < 1 || key_bits > 32) return fail(c, LPT_E_ARG, "key_bits must be in [1, 32]");
+    if (npts > 0 && !keys_in) return fail(c, LPT_E_ARG, "keys_in must not be NULL");
+    if (npts == 0) return LPT_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    SortWork w{};
+    lpt_status s = LPT_OK;
+    auto release = [&]() {
+        (void)hipStreamSynchronize(c->stream);
+        dfree(w.keys[0]); dfree(w.keys[1]); dfree(w.vals[0]); dfree(w.vals[1]);
+        dfree(w.hist); dfree(w.scan_tmp);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = dalloc(w.keys[0], npts);
+    if (e == hipSuccess) e = dalloc(w.keys[1], npts);
+    if (e == hipSuccess) e = dalloc(w.vals[0], npts);
+    if (e == hipSuccess) e = dalloc(w.vals[1], npts);
+    if (e == hipSuccess) e = dalloc(w.hist, (size_t)sort_hist_entries(npts));
+    if (e == hipSuccess) e = dalloc(w.scan_tmp, (size_t)sort_scan_blocks(npts));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(w.keys[0], keys_in, (size_t)npts * 4, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = launch_iota(w.vals[0], npts, c->stream);
+    int res = 0;
+    if (e == hipSuccess) e = radix_sort(w, npts, key_bits, &res, c->stream);
+    if (e == hipSuccess && keys_out)
+        e = hipMemcpyAsync(keys_out, w.keys[res], (size_t)npts * 4, hipMemcpyDeviceToDevice,
+                           c->stream);
+    if (e == hipSuccess && perm)
+        e = hipMemcpyAsync(perm, w.vals[res], (size_t)npts * 4, hipMemcpyDeviceToDevice, c->stream);
+    release();
+    if (e != hipSuccess) s = fail(c, LPT_E_HIP, std::string("radix sort: ") + hipGetErrorString(e));
+    return s;
+}
+
+}  // extern "C"

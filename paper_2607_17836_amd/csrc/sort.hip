@@ -1,0 +1,382 @@
+// Cell-order re-sorting of the particle state: key generation, a stable LSD
+// radix sort with 8-bit digits, and the structure-of-arrays permutation.
+//
+// Radix pass = histogram (per 4096-key tile) -> exclusive scan of the
+// digit-major histogram table -> stable scatter.  Inside a tile, each wave
+// owns a contiguous run of 1024 keys and ranks them with 8 ballots per
+// 64 keys (lanes with an equal digit form a match mask); per-wave running
+// counts live in LDS and are turned into scatter bases by one scan over the
+// waves.  Equal digits therefore keep input order: tile order, then wave,
+// then iteration, then lane -- which is the input order.
+#include "lpt_kernels.h"
+
+namespace lpt {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kItems = 16;                             // keys per thread
+constexpr int kTile = kSortThreads * kItems;           // 4096 keys
+constexpr int kWaveRun = kTile / kSortWaves;           // 1024 keys per wave
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kScanThreads * kScanItems;  // 2048 counters
+constexpr int kTopThreads = 1024;
+constexpr int kTopItems = 8;
+
+int64_t sort_hist_entries(int64_t n) { return 256 * ((n + kTile - 1) / kTile); }
+int64_t sort_scan_blocks(int64_t n)
+{
+    return (sort_hist_entries(n) + kScanChunk - 1) / kScanChunk;
+}
+
+// ---------------------------------------------------------------------------
+// keys
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int cell_of_pos(double x, double invh, int n)
+{
+    double c = floor(x * invh);
+    if (!(c >= 0.0)) c = 0.0;            // NaN / tiny negative
+    int ci = (int)fmin(c, (double)(n - 1));
+    return ci;
+}
+
+__device__ __forceinline__ int species_of_particle(const StepParams &P, int64_t p)
+{
+    int s = 0;
+    for (int k = 1; k < P.nspecies; ++k)
+        if (p >= P.sp[k].offset) s = k;
+    return s;
+}
+
+__device__ __forceinline__ uint32_t tile_key(int ci, int cj, int n, int tile_shift, int tile_bits,
+                                             int species)
+{
+    const uint32_t tx = (uint32_t)ci >> tile_shift, ty = (uint32_t)cj >> tile_shift;
+    const uint32_t tiles_x = (uint32_t)n >> tile_shift;
+    return ((uint32_t)species << tile_bits) | (ty * tiles_x + tx);
+}
+
+__global__ void keys64_kernel(StepParams P, State64 S, int tile_shift, int tile_bits,
+                              uint32_t *keys, uint32_t *vals, int64_t total)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= total) return;
+    const double2 x = S.pos[p];
+    const int ci = cell_of_pos(x.x, P.invh, P.n), cj = cell_of_pos(x.y, P.invh, P.n);
+    keys[p] = tile_key(ci, cj, P.n, tile_shift, tile_bits, species_of_particle(P, p));
+    vals[p] = (uint32_t)p;
+}
+
+__global__ void keys32_kernel(StepParams P, State32 S, int tile_shift, int tile_bits,
+                              uint32_t *keys, uint32_t *vals, int64_t total)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= total) return;
+    const uint32_t c = S.cell[p];
+    keys[p] = tile_key((int)(c & 0xFFFFu), (int)(c >> 16), P.n, tile_shift, tile_bits,
+                       species_of_particle(P, p));
+    vals[p] = (uint32_t)p;
+}
+
+static int64_t total_particles(const StepParams &P)
+{
+    const SpeciesDev &s = P.sp[P.nspecies - 1];
+    return s.offset + s.count;
+}
+
+static int ilog2(int t)
+{
+    int s = 0;
+    while ((1 << s) < t) ++s;
+    return s;
+}
+
+hipError_t launch_keys64(const StepParams &P, const State64 &S, int tile, int tile_bits,
+                         uint32_t *keys, uint32_t *vals, hipStream_t st)
+{
+    const int64_t total = total_particles(P);
+    const int b = 256;
+    hipLaunchKernelGGL(keys64_kernel, dim3((unsigned)((total + b - 1) / b)), dim3(b), 0, st, P, S,
+                       ilog2(tile), tile_bits, keys, vals, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys32(const StepParams &P, const State32 &S, int tile, int tile_bits,
+                         uint32_t *keys, uint32_t *vals, hipStream_t st)
+{
+    const int64_t total = total_particles(P);
+    const int b = 256;
+    hipLaunchKernelGGL(keys32_kernel, dim3((unsigned)((total + b - 1) / b)), dim3(b), 0, st, P, S,
+                       ilog2(tile), tile_bits, keys, vals, total);
+    return hipGetLastError();
+}
+
+__global__ void iota_kernel(uint32_t *v, int64_t n)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) v[p] = (uint32_t)p;
+}
+
+hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, v, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// radix pass kernels
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kSortThreads) void hist_kernel(const uint32_t *__restrict__ keys,
+                                                            int64_t n, int shift, uint32_t mask,
+                                                            uint32_t *hist, int ntiles)
+{
+    __shared__ uint32_t h[256];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t i = base + (int64_t)k * kSortThreads + tid;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
+}
+
+// Inclusive block scan of one value per thread (256 threads, 4 waves).
+__device__ __forceinline__ uint32_t block_scan_incl(uint32_t x, uint32_t *wsum, uint32_t &total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    const int nw = blockDim.x >> 6;
+    for (int k = 0; k < nw; ++k) {
+        if (k < w) before += wsum[k];
+        tot += wsum[k];
+    }
+    total = tot;
+    __syncthreads();
+    return x + before;
+}
+
+// Sum of each scan chunk.
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t *__restrict__ a,
+                                                                   int64_t m, uint32_t *sums)
+{
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < m) s += a[base + k];
+    uint32_t total;
+    block_scan_incl(s, wsum, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of the chunk sums in one block.
+__global__ __launch_bounds__(kTopThreads) void scan_top_kernel(uint32_t *sums, int64_t nb)
+{
+    __shared__ uint32_t wsum[kTopThreads / 64];
+    const int64_t base = (int64_t)threadIdx.x * kTopItems;
+    uint32_t v[kTopItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kTopItems; ++k) {
+        v[k] = base + k < nb ? sums[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t total;
+    const uint32_t incl = block_scan_incl(s, wsum, total);
+    uint32_t run = incl - s;
+#pragma unroll
+    for (int k = 0; k < kTopItems; ++k) {
+        if (base + k < nb) sums[base + k] = run;
+        run += v[k];
+    }
+}
+
+// Exclusive scan of each chunk, offset by its chunk base.
+__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t *a, int64_t m,
+                                                                 const uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < m ? a[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t total;
+    const uint32_t incl = block_scan_incl(s, wsum, total);
+    uint32_t run = sums[blockIdx.x] + incl - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < m) a[base + k] = run;
+        run += v[k];
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void scatter_kernel(
+    const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
+    uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, int64_t n, int shift,
+    uint32_t mask, const uint32_t *__restrict__ offsets, int ntiles)
+{
+    __shared__ uint32_t wcount[kSortWaves][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < kSortWaves; ++k) wcount[k][tid] = 0;
+    __syncthreads();
+
+    const int64_t run0 = (int64_t)blockIdx.x * kTile + (int64_t)w * kWaveRun;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    uint32_t key[kItems], val[kItems], rank[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int64_t i = run0 + (int64_t)it * 64 + lane;
+        const bool valid = i < n;
+        key[it] = valid ? keys_in[i] : 0u;
+        val[it] = valid ? vals_in[i] : 0u;
+        const uint32_t d = (key[it] >> shift) & mask;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
+        }
+        const uint32_t before = wcount[w][d];
+        rank[it] = before + (uint32_t)__popcll(m & lt);
+        if (valid && lane == __ffsll((unsigned long long)m) - 1)
+            wcount[w][d] = before + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    {
+        uint32_t runv = offsets[(int64_t)tid * ntiles + blockIdx.x];
+#pragma unroll
+        for (int k = 0; k < kSortWaves; ++k) {
+            const uint32_t c = wcount[k][tid];
+            wcount[k][tid] = runv;
+            runv += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int64_t i = run0 + (int64_t)it * 64 + lane;
+        if (i < n) {
+            const uint32_t d = (key[it] >> shift) & mask;
+            const uint32_t pos = wcount[w][d] + rank[it];
+            keys_out[pos] = key[it];
+            vals_out[pos] = val[it];
+        }
+    }
+}
+
+hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, int *result, hipStream_t st)
+{
+    *result = 0;
+    if (n <= 1) return hipSuccess;
+    const int ntiles = (int)((n + kTile - 1) / kTile);
+    const int64_t m = 256LL * ntiles;
+    const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
+    if (nb > (int64_t)kTopThreads * kTopItems) return hipErrorInvalidValue;
+    int cur = 0;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        const int bits = key_bits - shift < 8 ? key_bits - shift : 8;
+        const uint32_t mask = (1u << bits) - 1u;
+        hipLaunchKernelGGL(hist_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, W.keys[cur], n,
+                           shift, mask, W.hist, ntiles);
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st,
+                           W.hist, m, W.scan_tmp);
+        hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kTopThreads), 0, st, W.scan_tmp, nb);
+        hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st, W.hist,
+                           m, W.scan_tmp);
+        hipLaunchKernelGGL(scatter_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, W.keys[cur],
+                           W.vals[cur], W.keys[1 - cur], W.vals[1 - cur], n, shift, mask, W.hist,
+                           ntiles);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        cur = 1 - cur;
+    }
+    *result = cur;
+    return hipSuccess;
+}
+
+__global__ void order_kernel(const uint32_t *__restrict__ id, int64_t offset, int64_t count,
+                             int32_t *out)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) out[k] = (int32_t)((int64_t)id[offset + k] - offset);
+}
+
+hipError_t launch_order(const uint32_t *id, int64_t offset, int64_t count, int32_t *out,
+                        hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(order_kernel, dim3((unsigned)((count + b - 1) / b)), dim3(b), 0, st, id,
+                       offset, count, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// permutation of the state: dst[p] = src[perm[p]]
+// ---------------------------------------------------------------------------
+__global__ void permute64_kernel(State64 src, State64 dst, const uint32_t *__restrict__ perm,
+                                 int64_t n, int with_vel)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t q = perm[p];
+    dst.pos[p] = src.pos[q];
+    dst.disp[p] = src.disp[q];
+    dst.id[p] = src.id[q];
+    if (with_vel) dst.vel[p] = src.vel[q];
+}
+
+__global__ void permute32_kernel(State32 src, State32 dst, const uint32_t *__restrict__ perm,
+                                 int64_t n, int with_vel)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t q = perm[p];
+    dst.cell[p] = src.cell[q];
+    dst.off[p] = src.off[q];
+    dst.disp[p] = src.disp[q];
+    dst.id[p] = src.id[q];
+    if (with_vel) dst.vel[p] = src.vel[q];
+}
+
+hipError_t launch_permute64(const State64 &src, const State64 &dst, const uint32_t *perm,
+                            int64_t n, bool with_vel, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(permute64_kernel, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, src,
+                       dst, perm, n, (int)with_vel);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute32(const State32 &src, const State32 &dst, const uint32_t *perm,
+                            int64_t n, bool with_vel, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(permute32_kernel, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, src,
+                       dst, perm, n, (int)with_vel);
+    return hipGetLastError();
+}
+
+}  // namespace lpt

@@ -1,0 +1,905 @@
+// gfx950 kernels of the particle step: snapshot packing, RK4 + interpolation
+// (FP64 and FP32-split), initial state, velocity probe, readout and the
+// statistics finalisation.
+//
+// One thread advances one particle by one RK4 step (Alg. coupled_EL, particle
+// loop; eqs. rk4_update / rk4_inertial).  Each of the four stages gathers the
+// 4 (bilinear) or 16 (bicubic) node records around the stage position; a node
+// record carries both retained time levels, so one gather serves the temporal
+// interpolation (eq. temporal_interp) as well.  State is structure-of-arrays
+// with interleaved (x, y) pairs, so the per-step state stream is fully
+// coalesced; the gathers rely on cell-ordered particles (sort.hip) and an
+// XCD-aware block order for L2 locality.
+#include "lpt_kernels.h"
+
+#include <math.h>
+
+namespace lpt {
+
+constexpr int kMaxBlock = 512;
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Block order.  The hardware deals consecutive workgroups round-robin over the
+// 8 XCDs of the chip; remap so that XCD x processes one contiguous run of
+// logical blocks (neighbouring cells after the cell sort) and its private L2
+// sees their shared stencil rows.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_logical_block(int b, int G)
+{
+    constexpr int X = 8;
+    const int x = b % X, k = b / X;
+    const int q = G / X, r = G % X;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+__device__ __forceinline__ int species_of(const StepParams &P, int lb)
+{
+    int s = 0;
+    for (int k = 1; k < P.nspecies; ++k)
+        if (lb >= P.sp[k].block_begin) s = k;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Periodic cell index of a (possibly unwrapped) cell coordinate.  The common
+// case is within one period; anything else (including NaN) takes the slow
+// path, which always returns an index in [0, n) so that no gather can leave
+// the field.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int periodic_index(long long c, int n)
+{
+    if (c >= -(long long)n && c < 2LL * n) {
+        int ci = (int)c;
+        if (ci >= n) ci -= n;
+        else if (ci < 0) ci += n;
+        return ci;
+    }
+    long long m = c % n;
+    if (m < 0) m += n;
+    return (int)m;
+}
+
+__device__ __forceinline__ int index_of_floor(double c, int n)
+{
+    if (!(fabs(c) < 4.0e18)) return 0;   // NaN / inf: any valid cell
+    return periodic_index((long long)c, n);
+}
+
+__device__ __forceinline__ int next_i(int i, int n) { return i + 1 == n ? 0 : i + 1; }
+__device__ __forceinline__ int prev_i(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+
+// Catmull-Rom kernel (eq. cr_kernel) and cubic B-spline kernel
+// (eq. bspline_kernel), evaluated in Horner form.
+template <typename T>
+__device__ __forceinline__ void weights_cr(T s, T w[4])
+{
+    w[0] = s * (T(-0.5) + s * (T(1.0) + s * T(-0.5)));
+    w[1] = T(1.0) + s * s * (T(-2.5) + s * T(1.5));
+    w[2] = s * (T(0.5) + s * (T(2.0) + s * T(-1.5)));
+    w[3] = s * s * (T(-0.5) + s * T(0.5));
+}
+
+template <typename T>
+__device__ __forceinline__ void weights_bs(T s, T w[4])
+{
+    const T r = T(1.0) - s;
+    const T sixth = T(1.0) / T(6.0);
+    w[0] = r * r * r * sixth;
+    w[1] = (T(4.0) + s * s * (T(-6.0) + s * T(3.0))) * sixth;
+    w[2] = (T(1.0) + s * (T(3.0) + s * (T(3.0) + s * T(-3.0)))) * sixth;
+    w[3] = s * s * s * sixth;
+}
+
+// ===========================================================================
+// FP64 path
+// ===========================================================================
+__device__ __forceinline__ void node64(const Rec64 *__restrict__ rec, int idx, double wa,
+                                       double wb, double &u, double &v)
+{
+    const double2 *q = reinterpret_cast<const double2 *>(rec + idx);
+    const double2 a = q[0];
+    const double2 b = q[1];
+    u = wa * a.x + wb * b.x;
+    v = wa * a.y + wb * b.y;
+}
+
+// Velocity at (x, y) (physical units, any real value) with temporal weights
+// (wa, wb) on the two snapshot slots.
+template <bool CUBIC>
+__device__ __forceinline__ void vel64(const Rec64 *__restrict__ rec, int n, double invh,
+                                      int scheme, int compat, double x, double y, double wa,
+                                      double wb, double &u, double &v)
+{
+    const double sx = x * invh, sy = y * invh;
+    const double fx = floor(sx), fy = floor(sy);
+    const double xi = sx - fx, eta = sy - fy;
+    const int i = index_of_floor(fx, n), j = index_of_floor(fy, n);
+    const int i1 = next_i(i, n), j1 = next_i(j, n);
+    const bool edge = compat && (i == 0 || i >= n - 2 || j == 0 || j >= n - 2);
+    if (!CUBIC || scheme == kBilinear || edge) {
+        double u00, v00, u10, v10, u01, v01, u11, v11;
+        const int r0 = j * n, r1 = j1 * n;
+        node64(rec, r0 + i, wa, wb, u00, v00);
+        node64(rec, r0 + i1, wa, wb, u10, v10);
+        node64(rec, r1 + i, wa, wb, u01, v01);
+        node64(rec, r1 + i1, wa, wb, u11, v11);
+        const double w00 = (1.0 - xi) * (1.0 - eta), w10 = xi * (1.0 - eta);
+        const double w01 = (1.0 - xi) * eta, w11 = xi * eta;
+        u = w00 * u00 + w10 * u10 + w01 * u01 + w11 * u11;
+        v = w00 * v00 + w10 * v10 + w01 * v01 + w11 * v11;
+        return;
+    }
+    if constexpr (CUBIC) {
+        double wx[4], wy[4];
+        if (scheme == kCatmullRom) {
+            weights_cr(xi, wx);
+            weights_cr(eta, wy);
+        } else {
+            weights_bs(xi, wx);
+            weights_bs(eta, wy);
+        }
+        const int ix[4] = {prev_i(i, n), i, i1, next_i(i1, n)};
+        const int jy[4] = {prev_i(j, n), j, j1, next_i(j1, n)};
+        double au = 0.0, av = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int row = jy[b] * n;
+            double ru = 0.0, rv = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                double nu, nv;
+                node64(rec, row + ix[a], wa, wb, nu, nv);
+                ru += wx[a] * nu;
+                rv += wx[a] * nv;
+            }
+            au += wy[b] * ru;
+            av += wy[b] * rv;
+        }
+        u = au;
+        v = av;
+    }
+}
+
+__device__ __forceinline__ double wrap_pos(double z, double L)
+{
+    if (z >= L) z -= L;
+    else if (z < 0.0) z += L;
+    if (!(z >= 0.0 && z < L)) {
+        if (z == z) {   // finite but far away, or +L after rounding
+            z = z - L * floor(z / L);
+            if (z < 0.0) z += L;
+            if (z >= L) z -= L;
+        }
+    }
+    return z;
+}
+
+template <int NT>
+__device__ __forceinline__ void block_sum3(double a, double b, double c, double *out)
+{
+    __shared__ double red[3][NT / kWave];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, kWave);
+        b += __shfl_down(b, off, kWave);
+        c += __shfl_down(c, off, kWave);
+    }
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    if (lane == 0) {
+        red[0][w] = a;
+        red[1][w] = b;
+        red[2][w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        const int nw = blockDim.x / kWave;
+        for (int k = 0; k < nw; ++k) {
+            s0 += red[0][k];
+            s1 += red[1][k];
+            s2 += red[2][k];
+        }
+        out[0] = s0;
+        out[1] = s1;
+        out[2] = s2;
+    }
+}
+
+template <bool CUBIC, bool INERTIAL, bool STATS>
+__global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64 S,
+                                                           const Rec64 *__restrict__ rec,
+                                                           double *__restrict__ partials,
+                                                           DevClock *clock)
+{
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const SpeciesDev &sp = P.sp[species_of(P, lb)];
+    const int64_t local = (int64_t)(lb - sp.block_begin) * blockDim.x + threadIdx.x;
+    const bool active = local < sp.count;
+    const int64_t p = sp.offset + local;
+    const int n = P.n;
+    const double invh = P.invh, dt = P.dt, hdt = 0.5 * P.dt, dt6 = P.dt / 6.0;
+    double r2x = 0.0, r2y = 0.0;
+
+    if (active) {
+        const double2 x = S.pos[p];
+        double2 d = S.disp[p];
+        double ddx, ddy;
+        if (INERTIAL && sp.inertial) {
+            // eqs. inertial_particle, drag_rk4, rk4_inertial
+            const double2 vn = S.vel[p];
+            const double is = sp.inv_st;
+            double u, v;
+            const double V1x = vn.x, V1y = vn.y;
+            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x, x.y, P.wa[0], P.wb[0], u, v);
+            const double A1x = (u - V1x) * is, A1y = (v - V1y) * is;
+            const double V2x = vn.x + hdt * A1x, V2y = vn.y + hdt * A1y;
+            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x + hdt * V1x, x.y + hdt * V1y,
+                         P.wa[1], P.wb[1], u, v);
+            const double A2x = (u - V2x) * is, A2y = (v - V2y) * is;
+            const double V3x = vn.x + hdt * A2x, V3y = vn.y + hdt * A2y;
+            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x + hdt * V2x, x.y + hdt * V2y,
+                         P.wa[2], P.wb[2], u, v);
+            const double A3x = (u - V3x) * is, A3y = (v - V3y) * is;
+            const double V4x = vn.x + dt * A3x, V4y = vn.y + dt * A3y;
+            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x + dt * V3x, x.y + dt * V3y,
+                         P.wa[3], P.wb[3], u, v);
+            const double A4x = (u - V4x) * is, A4y = (v - V4y) * is;
+            ddx = dt6 * (V1x + 2.0 * V2x + 2.0 * V3x + V4x);
+            ddy = dt6 * (V1y + 2.0 * V2y + 2.0 * V3y + V4y);
+            S.vel[p] = make_double2(vn.x + dt6 * (A1x + 2.0 * A2x + 2.0 * A3x + A4x),
+                                    vn.y + dt6 * (A1y + 2.0 * A2y + 2.0 * A3y + A4y));
+        } else {
+            // eq. rk4_update, stages at t_n, t_n + dt/2, t_n + dt/2, t_n + dt
+            double k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
+            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x, x.y, P.wa[0], P.wb[0], k1x, k1y);
+            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x + hdt * k1x, x.y + hdt * k1y,
+                         P.wa[1], P.wb[1], k2x, k2y);
+            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x + hdt * k2x, x.y + hdt * k2y,
+                         P.wa[2], P.wb[2], k3x, k3y);
+            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x + dt * k3x, x.y + dt * k3y,
+                         P.wa[3], P.wb[3], k4x, k4y);
+            ddx = dt6 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
+            ddy = dt6 * (k1y + 2.0 * k2y + 2.0 * k3y + k4y);
+        }
+        // wrapped coordinates for evaluation/output, unwrapped displacement
+        // for statistics
+        S.pos[p] = make_double2(wrap_pos(x.x + ddx, P.L), wrap_pos(x.y + ddy, P.L));
+        d.x += ddx;
+        d.y += ddy;
+        S.disp[p] = d;
+        r2x = d.x * d.x;
+        r2y = d.y * d.y;
+    }
+    if (STATS) {
+        const double r2 = r2x + r2y;
+        block_sum3<kMaxBlock>(r2x, r2y, r2 * r2, partials + (int64_t)kStatTerms * lb);
+    }
+    if (lb == 0 && threadIdx.x == 0) {
+        clock->t += P.dt;
+        clock->step += 1;
+    }
+}
+
+// ===========================================================================
+// FP32 split path.  Positions are (cell, offset) with the offset in cell
+// units; the packed field is in cells per unit time, so every stage works in
+// cell units: q = offset + c*dt*k.
+// ===========================================================================
+__device__ __forceinline__ int cell_plus(int c, float f, int n)
+{
+    if (fabsf(f) < 1.0e9f) return periodic_index((long long)c + (long long)f, n);
+    return 0;   // NaN / absurd displacement: any valid cell
+}
+
+__device__ __forceinline__ float4 ldrec(const float4 *__restrict__ rec, int idx)
+{
+    return rec[idx];
+}
+
+template <bool CUBIC>
+__device__ __forceinline__ void vel32(const float4 *__restrict__ rec, int n, int scheme,
+                                      int compat, int cx, int cy, float qx, float qy, float wa,
+                                      float wb, float &u, float &v)
+{
+    const float fx = floorf(qx), fy = floorf(qy);
+    const float xi = qx - fx, eta = qy - fy;
+    const int i = cell_plus(cx, fx, n), j = cell_plus(cy, fy, n);
+    const int i1 = next_i(i, n), j1 = next_i(j, n);
+    const bool edge = compat && (i == 0 || i >= n - 2 || j == 0 || j >= n - 2);
+    if (!CUBIC || scheme == kBilinear || edge) {
+        const int r0 = j * n, r1 = j1 * n;
+        const float4 a = ldrec(rec, r0 + i), b = ldrec(rec, r0 + i1);
+        const float4 c = ldrec(rec, r1 + i), d = ldrec(rec, r1 + i1);
+        const float w00 = (1.0f - xi) * (1.0f - eta), w10 = xi * (1.0f - eta);
+        const float w01 = (1.0f - xi) * eta, w11 = xi * eta;
+        const float ua = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
+        const float va = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
+        const float ub = w00 * a.z + w10 * b.z + w01 * c.z + w11 * d.z;
+        const float vb = w00 * a.w + w10 * b.w + w01 * c.w + w11 * d.w;
+        u = wa * ua + wb * ub;
+        v = wa * va + wb * vb;
+        return;
+    }
+    if constexpr (CUBIC) {
+        float wx[4], wy[4];
+        if (scheme == kCatmullRom) {
+            weights_cr(xi, wx);
+            weights_cr(eta, wy);
+        } else {
+            weights_bs(xi, wx);
+            weights_bs(eta, wy);
+        }
+        const int ix[4] = {prev_i(i, n), i, i1, next_i(i1, n)};
+        const int jy[4] = {prev_i(j, n), j, j1, next_i(j1, n)};
+        float au = 0.f, av = 0.f, bu = 0.f, bv = 0.f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int row = jy[b] * n;
+            float ru = 0.f, rv = 0.f, su = 0.f, sv = 0.f;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const float4 r = ldrec(rec, row + ix[a]);
+                ru += wx[a] * r.x;
+                rv += wx[a] * r.y;
+                su += wx[a] * r.z;
+                sv += wx[a] * r.w;
+            }
+            au += wy[b] * ru;
+            av += wy[b] * rv;
+            bu += wy[b] * su;
+            bv += wy[b] * sv;
+        }
+        u = wa * au + wb * bu;
+        v = wa * av + wb * bv;
+    }
+}
+
+// New (cell, offset) after a displacement of dq cells from offset o.
+__device__ __forceinline__ void advance_split(int &c, float &o, float dq, int n)
+{
+    const float q = o + dq;
+    const float f = floorf(q);
+    float r = q - f;   // exact for |q| < 2^23
+    int nc = cell_plus(c, f, n);
+    if (r >= 1.0f) {   // q a hair below an integer rounds the fraction up to 1
+        r -= 1.0f;
+        nc = next_i(nc, n);
+    }
+    if (!(r >= 0.0f)) r = 0.0f;   // NaN guard keeps the state in range
+    c = nc;
+    o = r;
+}
+
+template <bool CUBIC, bool INERTIAL, bool STATS>
+__global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32 S,
+                                                           const float4 *__restrict__ rec,
+                                                           double *__restrict__ partials,
+                                                           DevClock *clock)
+{
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const SpeciesDev &sp = P.sp[species_of(P, lb)];
+    const int64_t local = (int64_t)(lb - sp.block_begin) * blockDim.x + threadIdx.x;
+    const bool active = local < sp.count;
+    const int64_t p = sp.offset + local;
+    const int n = P.n;
+    const float dt = (float)P.dt, hdt = 0.5f * dt, dt6 = dt / 6.0f;
+    const float wa0 = (float)P.wa[0], wa1 = (float)P.wa[1], wa2 = (float)P.wa[2], wa3 = (float)P.wa[3];
+    const float wb0 = (float)P.wb[0], wb1 = (float)P.wb[1], wb2 = (float)P.wb[2], wb3 = (float)P.wb[3];
+    double r2x = 0.0, r2y = 0.0;
+
+    if (active) {
+        const uint32_t cell = S.cell[p];
+        const float2 o = S.off[p];
+        double2 d = S.disp[p];
+        int cx = (int)(cell & 0xFFFFu), cy = (int)(cell >> 16);
+        float dqx, dqy;
+        if (INERTIAL && sp.inertial) {
+            const float2 vn = S.vel[p];
+            const float is = (float)sp.inv_st;
+            float u, v;
+            const float V1x = vn.x, V1y = vn.y;
+            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x, o.y, wa0, wb0, u, v);
+            const float A1x = (u - V1x) * is, A1y = (v - V1y) * is;
+            const float V2x = vn.x + hdt * A1x, V2y = vn.y + hdt * A1y;
+            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x + hdt * V1x, o.y + hdt * V1y,
+                         wa1, wb1, u, v);
+            const float A2x = (u - V2x) * is, A2y = (v - V2y) * is;
+            const float V3x = vn.x + hdt * A2x, V3y = vn.y + hdt * A2y;
+            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x + hdt * V2x, o.y + hdt * V2y,
+                         wa2, wb2, u, v);
+            const float A3x = (u - V3x) * is, A3y = (v - V3y) * is;
+            const float V4x = vn.x + dt * A3x, V4y = vn.y + dt * A3y;
+            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x + dt * V3x, o.y + dt * V3y,
+                         wa3, wb3, u, v);
+            const float A4x = (u - V4x) * is, A4y = (v - V4y) * is;
+            dqx = dt6 * (V1x + 2.0f * V2x + 2.0f * V3x + V4x);
+            dqy = dt6 * (V1y + 2.0f * V2y + 2.0f * V3y + V4y);
+            S.vel[p] = make_float2(vn.x + dt6 * (A1x + 2.0f * A2x + 2.0f * A3x + A4x),
+                                   vn.y + dt6 * (A1y + 2.0f * A2y + 2.0f * A3y + A4y));
+        } else {
+            float k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
+            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x, o.y, wa0, wb0, k1x, k1y);
+            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x + hdt * k1x, o.y + hdt * k1y,
+                         wa1, wb1, k2x, k2y);
+            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x + hdt * k2x, o.y + hdt * k2y,
+                         wa2, wb2, k3x, k3y);
+            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x + dt * k3x, o.y + dt * k3y,
+                         wa3, wb3, k4x, k4y);
+            dqx = dt6 * (k1x + 2.0f * k2x + 2.0f * k3x + k4x);
+            dqy = dt6 * (k1y + 2.0f * k2y + 2.0f * k3y + k4y);
+        }
+        float ox = o.x, oy = o.y;
+        advance_split(cx, ox, dqx, n);
+        advance_split(cy, oy, dqy, n);
+        S.cell[p] = (uint32_t)cx | ((uint32_t)cy << 16);
+        S.off[p] = make_float2(ox, oy);
+        d.x += (double)dqx * P.h;
+        d.y += (double)dqy * P.h;
+        S.disp[p] = d;
+        r2x = d.x * d.x;
+        r2y = d.y * d.y;
+    }
+    if (STATS) {
+        const double r2 = r2x + r2y;
+        block_sum3<kMaxBlock>(r2x, r2y, r2 * r2, partials + (int64_t)kStatTerms * lb);
+    }
+    if (lb == 0 && threadIdx.x == 0) {
+        clock->t += P.dt;
+        clock->step += 1;
+    }
+}
+
+template <bool C, bool I, bool S>
+static hipError_t launch64_t(const StepParams &P, const State64 &St, const Rec64 *rec,
+                             double *partials, DevClock *clock, int block, int grid,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL((step64_kernel<C, I, S>), dim3(grid), dim3(block), 0, st, P, St, rec,
+                       partials, clock);
+    return hipGetLastError();
+}
+
+template <bool C, bool I, bool S>
+static hipError_t launch32_t(const StepParams &P, const State32 &St, const float4 *rec,
+                             double *partials, DevClock *clock, int block, int grid,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL((step32_kernel<C, I, S>), dim3(grid), dim3(block), 0, st, P, St, rec,
+                       partials, clock);
+    return hipGetLastError();
+}
+
+#define LPT_DISPATCH(fn, ...)                                                        \
+    do {                                                                             \
+        const int sel = (cubic ? 4 : 0) | (inertial ? 2 : 0) | (stats ? 1 : 0);      \
+        switch (sel) {                                                               \
+        case 0: return fn<false, false, false>(__VA_ARGS__);                          \
+        case 1: return fn<false, false, true>(__VA_ARGS__);                           \
+        case 2: return fn<false, true, false>(__VA_ARGS__);                           \
+        case 3: return fn<false, true, true>(__VA_ARGS__);                            \
+        case 4: return fn<true, false, false>(__VA_ARGS__);                           \
+        case 5: return fn<true, false, true>(__VA_ARGS__);                            \
+        case 6: return fn<true, true, false>(__VA_ARGS__);                            \
+        default: return fn<true, true, true>(__VA_ARGS__);                            \
+        }                                                                            \
+    } while (0)
+
+hipError_t launch_step64(const StepParams &P, const State64 &S, const Rec64 *rec,
+                         double *partials, DevClock *clock, bool stats, bool cubic,
+                         bool inertial, int block, int grid, hipStream_t st)
+{
+    LPT_DISPATCH(launch64_t, P, S, rec, partials, clock, block, grid, st);
+}
+
+hipError_t launch_step32(const StepParams &P, const State32 &S, const float4 *rec,
+                         double *partials, DevClock *clock, bool stats, bool cubic,
+                         bool inertial, int block, int grid, hipStream_t st)
+{
+    LPT_DISPATCH(launch32_t, P, S, rec, partials, clock, block, grid, st);
+}
+
+// ===========================================================================
+// Statistics: fixed-order reduction of the per-block partial sums into one
+// record per species (Sec. 3.2 and 5.5 quantities).
+// ===========================================================================
+constexpr int kFinThreads = 256;
+
+__global__ __launch_bounds__(kFinThreads) void finalize_kernel(StepParams P,
+                                                               const double *__restrict__ partials,
+                                                               DevClock *clock, double *records,
+                                                               int64_t cap, double t0)
+{
+    __shared__ double sm[kStatTerms][kFinThreads];
+    const double t = clock->t;
+    const int64_t idx = clock->nrec;
+    const int tid = threadIdx.x;
+    for (int s = 0; s < P.nspecies; ++s) {
+        const SpeciesDev &sp = P.sp[s];
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int k = sp.block_begin + tid; k < sp.block_end; k += kFinThreads) {
+            a += partials[(int64_t)kStatTerms * k + 0];
+            b += partials[(int64_t)kStatTerms * k + 1];
+            c += partials[(int64_t)kStatTerms * k + 2];
+        }
+        sm[0][tid] = a;
+        sm[1][tid] = b;
+        sm[2][tid] = c;
+        __syncthreads();
+        for (int w = kFinThreads / 2; w > 0; w >>= 1) {
+            if (tid < w) {
+                sm[0][tid] += sm[0][tid + w];
+                sm[1][tid] += sm[1][tid + w];
+                sm[2][tid] += sm[2][tid + w];
+            }
+            __syncthreads();
+        }
+        if (tid == 0 && idx < cap) {
+            const double nn = (double)sp.count;
+            const double mx = sm[0][0] / nn, my = sm[1][0] / nn, m = mx + my;
+            double var = sp.count > 1 ? (sm[2][0] - nn * m * m) / (nn - 1.0) : 0.0;
+            if (var < 0.0) var = 0.0;
+            const double el = t - t0;
+            double *r = records + ((int64_t)s * cap + idx) * 8;
+            r[0] = t;
+            r[1] = mx;
+            r[2] = my;
+            r[3] = m;
+            r[4] = el > 0.0 ? mx / (2.0 * el) : 0.0;
+            r[5] = el > 0.0 ? my / (2.0 * el) : 0.0;
+            r[6] = sqrt(var / nn);
+            reinterpret_cast<int64_t *>(r)[7] = sp.count;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) clock->nrec = idx + 1;
+}
+
+hipError_t launch_finalize(const StepParams &P, const double *partials, DevClock *clock,
+                           double *records, int64_t rec_cap, double t0, hipStream_t st)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, st, P, partials, clock,
+                       records, rec_cap, t0);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Snapshot ingest: planar u, v of one time level into its half of the node
+// records.
+// ===========================================================================
+__global__ void pack64_kernel(Rec64 *rec, int slot, const double *__restrict__ u,
+                              const double *__restrict__ v, int64_t nn)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn) return;
+    double2 *q = reinterpret_cast<double2 *>(rec + k) + slot;
+    *q = make_double2(u[k], v[k]);
+}
+
+__global__ void pack32_kernel(float4 *rec, int slot, const double *__restrict__ u,
+                              const double *__restrict__ v, int64_t nn, double scale)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn) return;
+    float2 *q = reinterpret_cast<float2 *>(rec + k) + slot;
+    *q = make_float2((float)(u[k] * scale), (float)(v[k] * scale));
+}
+
+hipError_t launch_pack64(Rec64 *rec, int slot, const double *u, const double *v, int64_t nn,
+                         hipStream_t st)
+{
+    const int b = 256;
+    hipLaunchKernelGGL(pack64_kernel, dim3((unsigned)((nn + b - 1) / b)), dim3(b), 0, st, rec,
+                       slot, u, v, nn);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack32(float4 *rec, int slot, const double *u, const double *v, int64_t nn,
+                         double scale, hipStream_t st)
+{
+    const int b = 256;
+    hipLaunchKernelGGL(pack32_kernel, dim3((unsigned)((nn + b - 1) / b)), dim3(b), 0, st, rec,
+                       slot, u, v, nn, scale);
+    return hipGetLastError();
+}
+
+// Grid centred differences of psi (eq. particle_velocity_reconstruction with
+// the interpolation moved onto the grid).
+__global__ void psi_vel_kernel(const double *__restrict__ psi, double *u, double *v, int n,
+                               double h)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)n * n) return;
+    const int i = (int)(k % n), j = (int)(k / n);
+    const double inv2h = 1.0 / (2.0 * h);
+    u[k] = (psi[(int64_t)next_i(j, n) * n + i] - psi[(int64_t)prev_i(j, n) * n + i]) * inv2h;
+    v[k] = -(psi[(int64_t)j * n + next_i(i, n)] - psi[(int64_t)j * n + prev_i(i, n)]) * inv2h;
+}
+
+hipError_t launch_psi_to_velocity(const double *psi, double *u, double *v, int n, double h,
+                                  hipStream_t st)
+{
+    const int64_t nn = (int64_t)n * n;
+    const int b = 256;
+    hipLaunchKernelGGL(psi_vel_kernel, dim3((unsigned)((nn + b - 1) / b)), dim3(b), 0, st, psi,
+                       u, v, n, h);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Initial state.  Positions come from x0 (original order); the velocity of an
+// inertial species is v0 if given, else the interpolated fluid velocity.
+// ===========================================================================
+__global__ void init64_kernel(StepParams P, State64 S, const double2 *__restrict__ x0,
+                              const double2 *__restrict__ v0, const Rec64 *__restrict__ rec,
+                              int species, int64_t begin, int64_t count, double wa, double wb,
+                              int vel_from_field)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const int64_t p = begin + k;
+    const SpeciesDev &sp = P.sp[species];
+    const double2 x = x0[p];
+    S.pos[p] = make_double2(wrap_pos(x.x, P.L), wrap_pos(x.y, P.L));
+    S.disp[p] = make_double2(0.0, 0.0);
+    S.id[p] = (uint32_t)p;
+    if (sp.inertial) {
+        if (vel_from_field) {
+            double u, v;
+            vel64<true>(rec, P.n, P.invh, sp.scheme, P.compat_edge, x.x, x.y, wa, wb, u, v);
+            S.vel[p] = make_double2(u, v);
+        } else {
+            S.vel[p] = v0[p];
+        }
+    }
+}
+
+__device__ __forceinline__ void split_of(double x, double invh, int n, int &c, float &o)
+{
+    const double s = x * invh;
+    const double f = floor(s);
+    float r = (float)(s - f);
+    int ci = index_of_floor(f, n);
+    if (r >= 1.0f) {
+        r = 0.0f;
+        ci = next_i(ci, n);
+    }
+    if (!(r >= 0.0f)) r = 0.0f;
+    c = ci;
+    o = r;
+}
+
+__global__ void init32_kernel(StepParams P, State32 S, const double2 *__restrict__ x0,
+                              const double2 *__restrict__ v0, const float4 *__restrict__ rec,
+                              int species, int64_t begin, int64_t count, double wa, double wb,
+                              int vel_from_field)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const int64_t p = begin + k;
+    const SpeciesDev &sp = P.sp[species];
+    const double2 x = x0[p];
+    int cx, cy;
+    float ox, oy;
+    split_of(x.x, P.invh, P.n, cx, ox);
+    split_of(x.y, P.invh, P.n, cy, oy);
+    S.cell[p] = (uint32_t)cx | ((uint32_t)cy << 16);
+    S.off[p] = make_float2(ox, oy);
+    S.disp[p] = make_double2(0.0, 0.0);
+    S.id[p] = (uint32_t)p;
+    if (sp.inertial) {
+        if (vel_from_field) {
+            float u, v;
+            vel32<true>(rec, P.n, sp.scheme, P.compat_edge, cx, cy, ox, oy, (float)wa, (float)wb,
+                        u, v);
+            S.vel[p] = make_float2(u, v);
+        } else {
+            S.vel[p] = make_float2((float)(v0[p].x * P.invh), (float)(v0[p].y * P.invh));
+        }
+    }
+}
+
+hipError_t launch_init64(const StepParams &P, const State64 &S, const double2 *x0,
+                         const double2 *v0, const Rec64 *rec, int species, int64_t begin,
+                         int64_t count, double wa, double wb, int vel_from_field,
+                         hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(init64_kernel, dim3((unsigned)((count + b - 1) / b)), dim3(b), 0, st, P,
+                       S, x0, v0, rec, species, begin, count, wa, wb, vel_from_field);
+    return hipGetLastError();
+}
+
+hipError_t launch_init32(const StepParams &P, const State32 &S, const double2 *x0,
+                         const double2 *v0, const float4 *rec, int species, int64_t begin,
+                         int64_t count, double wa, double wb, int vel_from_field,
+                         hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(init32_kernel, dim3((unsigned)((count + b - 1) / b)), dim3(b), 0, st, P,
+                       S, x0, v0, rec, species, begin, count, wa, wb, vel_from_field);
+    return hipGetLastError();
+}
+
+__global__ void interleave_kernel(double2 *dst, const double *__restrict__ a,
+                                  const double *__restrict__ b, int64_t n)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = make_double2(a[k], b[k]);
+}
+
+hipError_t launch_interleave(double2 *dst, const double *a, const double *b, int64_t n,
+                             hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int bs = 256;
+    hipLaunchKernelGGL(interleave_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st,
+                       dst, a, b, n);
+    return hipGetLastError();
+}
+
+// Counter-indexed SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output k of
+// the stream seeded with s is mix(s + (k + 1) * golden gamma).
+__device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__global__ void splitmix_kernel(double2 *x0, int64_t count, uint64_t seed, double L)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const double ux = (double)(splitmix_at(seed, 2 * (uint64_t)k) >> 11) * 0x1p-53;
+    const double uy = (double)(splitmix_at(seed, 2 * (uint64_t)k + 1) >> 11) * 0x1p-53;
+    x0[k] = make_double2(wrap_pos(L * ux, L), wrap_pos(L * uy, L));
+}
+
+hipError_t launch_splitmix(double2 *x0, int64_t count, uint64_t seed, double L, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(splitmix_kernel, dim3((unsigned)((count + b - 1) / b)), dim3(b), 0, st,
+                       x0, count, seed, L);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Velocity probe at arbitrary points (verification entry point).
+// ===========================================================================
+__global__ void interp64_kernel(StepParams P, const Rec64 *__restrict__ rec, int scheme,
+                                int64_t npts, const double *__restrict__ x,
+                                const double *__restrict__ y, double wa, double wb, double *u,
+                                double *v)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= npts) return;
+    double uu, vv;
+    vel64<true>(rec, P.n, P.invh, scheme, P.compat_edge, x[k], y[k], wa, wb, uu, vv);
+    u[k] = uu;
+    v[k] = vv;
+}
+
+__global__ void interp32_kernel(StepParams P, const float4 *__restrict__ rec, int scheme,
+                                int64_t npts, const double *__restrict__ x,
+                                const double *__restrict__ y, double wa, double wb, double *u,
+                                double *v)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= npts) return;
+    int cx, cy;
+    float ox, oy;
+    split_of(x[k], P.invh, P.n, cx, ox);
+    split_of(y[k], P.invh, P.n, cy, oy);
+    float uu, vv;
+    vel32<true>(rec, P.n, scheme, P.compat_edge, cx, cy, ox, oy, (float)wa, (float)wb, uu, vv);
+    u[k] = (double)uu * P.h;
+    v[k] = (double)vv * P.h;
+}
+
+hipError_t launch_interp64(const StepParams &P, const Rec64 *rec, int scheme, int64_t npts,
+                           const double *x, const double *y, double wa, double wb, double *u,
+                           double *v, hipStream_t st)
+{
+    if (npts <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(interp64_kernel, dim3((unsigned)((npts + b - 1) / b)), dim3(b), 0, st, P,
+                       rec, scheme, npts, x, y, wa, wb, u, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp32(const StepParams &P, const float4 *rec, int scheme, int64_t npts,
+                           const double *x, const double *y, double wa, double wb, double *u,
+                           double *v, hipStream_t st)
+{
+    if (npts <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(interp32_kernel, dim3((unsigned)((npts + b - 1) / b)), dim3(b), 0, st, P,
+                       rec, scheme, npts, x, y, wa, wb, u, v);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Readout in original particle order.
+// ===========================================================================
+__global__ void readout64_kernel(State64 S, const double2 *__restrict__ x0, int64_t offset,
+                                 int64_t count, double *xw, double *yw, double *xu, double *yu,
+                                 double *vx, double *vy)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const int64_t p = offset + k;
+    const uint32_t g = S.id[p];
+    const int64_t q = (int64_t)g - offset;
+    if (q < 0 || q >= count) return;
+    const double2 x = S.pos[p];
+    if (xw) xw[q] = x.x;
+    if (yw) yw[q] = x.y;
+    if (xu || yu) {
+        const double2 d = S.disp[p];
+        const double2 a = x0[g];
+        if (xu) xu[q] = a.x + d.x;
+        if (yu) yu[q] = a.y + d.y;
+    }
+    if (vx || vy) {
+        const double2 w = S.vel[p];
+        if (vx) vx[q] = w.x;
+        if (vy) vy[q] = w.y;
+    }
+}
+
+__global__ void readout32_kernel(State32 S, const double2 *__restrict__ x0, int64_t offset,
+                                 int64_t count, double h, double *xw, double *yw, double *xu,
+                                 double *yu, double *vx, double *vy)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const int64_t p = offset + k;
+    const uint32_t g = S.id[p];
+    const int64_t q = (int64_t)g - offset;
+    if (q < 0 || q >= count) return;
+    const uint32_t c = S.cell[p];
+    const float2 o = S.off[p];
+    if (xw) xw[q] = ((double)(c & 0xFFFFu) + (double)o.x) * h;
+    if (yw) yw[q] = ((double)(c >> 16) + (double)o.y) * h;
+    if (xu || yu) {
+        const double2 d = S.disp[p];
+        const double2 a = x0[g];
+        if (xu) xu[q] = a.x + d.x;
+        if (yu) yu[q] = a.y + d.y;
+    }
+    if (vx || vy) {
+        const float2 w = S.vel[p];
+        if (vx) vx[q] = (double)w.x * h;
+        if (vy) vy[q] = (double)w.y * h;
+    }
+}
+
+hipError_t launch_readout64(const State64 &S, const double2 *x0, int64_t offset, int64_t count,
+                            double L, double *xw, double *yw, double *xu, double *yu,
+                            double *vx, double *vy, hipStream_t st)
+{
+    (void)L;
+    if (count <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(readout64_kernel, dim3((unsigned)((count + b - 1) / b)), dim3(b), 0, st,
+                       S, x0, offset, count, xw, yw, xu, yu, vx, vy);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout32(const State32 &S, const double2 *x0, int64_t offset, int64_t count,
+                            double h, double *xw, double *yw, double *xu, double *yu,
+                            double *vx, double *vy, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(readout32_kernel, dim3((unsigned)((count + b - 1) / b)), dim3(b), 0, st,
+                       S, x0, offset, count, h, xw, yw, xu, yu, vx, vy);
+    return hipGetLastError();
+}
+
+}  // namespace lpt

@@ -1,0 +1,293 @@
+"""Thin ctypes binding of liblpt.so (include/lpt.h).
+
+Argument marshalling only: every step of the particle path runs in the HIP
+kernels of liblpt.so.  Arrays may be numpy (host) or torch CUDA tensors
+(device); torch is used for device memory and streams only.  Loading fails
+loudly when the native library is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+try:  # load torch's HIP runtime first so the process holds exactly one
+    import torch
+except Exception:  # pragma: no cover - torch is part of the image
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblpt.so")
+
+OK, E_ARG, E_STATE, E_RANGE, E_NOMEM, E_HIP = range(6)
+BILINEAR, CATMULL_ROM, BSPLINE = 0, 1, 2
+FP64, FP32_SPLIT = 0, 1
+TRACER, INERTIAL = 0, 1
+TIME_BRACKET, TIME_PINGPONG = 0, 1
+FLAG_COMPAT_EDGE = 0x1
+FLAG_TIME_KERNELS = 0x2
+
+SCHEMES = {"bilinear": BILINEAR, "catmull_rom": CATMULL_ROM, "bspline": BSPLINE}
+PRECISIONS = {"fp64": FP64, "fp32_split": FP32_SPLIT}
+KINDS = {"tracer": TRACER, "inertial": INERTIAL}
+TIME_MODES = {"bracket": TIME_BRACKET, "pingpong": TIME_PINGPONG}
+
+
+class LptConfig(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("precision", C.c_int32), ("length", C.c_double), ("t0", C.c_double),
+        ("hip_stream", C.c_void_p), ("sort_interval", C.c_int32), ("sort_tile", C.c_int32),
+        ("block_size", C.c_int32), ("flags", C.c_uint32),
+    ]
+
+
+class LptTiming(C.Structure):
+    _fields_ = [("step_kernel_ms", C.c_double), ("step_launches", C.c_int64),
+                ("sort_ms", C.c_double), ("sorts", C.c_int64)]
+
+
+STAT_DTYPE = np.dtype([("t", "<f8"), ("msd_x", "<f8"), ("msd_y", "<f8"), ("msd", "<f8"),
+                       ("d_x", "<f8"), ("d_y", "<f8"), ("sem", "<f8"), ("n", "<i8")])
+
+# (name, restype, argtypes) of every exported entry point
+_P = C.c_void_p
+_SIGS = [
+    ("lpt_create", C.c_int, [C.POINTER(LptConfig), C.POINTER(C.c_void_p)]),
+    ("lpt_destroy", None, [_P]),
+    ("lpt_last_error", C.c_char_p, [_P]),
+    ("lpt_status_string", C.c_char_p, [C.c_int]),
+    ("lpt_synchronize", C.c_int, [_P]),
+    ("lpt_set_snapshot", C.c_int, [_P, C.c_int32, C.c_double, _P, _P, C.c_int32]),
+    ("lpt_set_snapshot_psi", C.c_int, [_P, C.c_int32, C.c_double, _P, C.c_int32]),
+    ("lpt_set_time_mode", C.c_int, [_P, C.c_int]),
+    ("lpt_add_species", C.c_int, [_P, C.c_int, C.c_double, C.c_int, C.c_int64, _P, _P, _P, _P,
+                                  C.c_int32, C.POINTER(C.c_int32)]),
+    ("lpt_init_uniform", C.c_int, [_P, C.c_int32, C.c_uint64]),
+    ("lpt_step", C.c_int, [_P, C.c_int64, C.c_double, C.c_int32]),
+    ("lpt_sort", C.c_int, [_P]),
+    ("lpt_get_positions", C.c_int, [_P, C.c_int32, _P, _P, _P, _P, C.c_int32]),
+    ("lpt_get_velocities", C.c_int, [_P, C.c_int32, _P, _P, C.c_int32]),
+    ("lpt_get_stats", C.c_int, [_P, C.c_int32, _P, C.c_int64, C.POINTER(C.c_int64)]),
+    ("lpt_get_order", C.c_int, [_P, C.c_int32, _P, C.c_int32]),
+    ("lpt_get_timing", C.c_int, [_P, C.POINTER(LptTiming), C.c_int32]),
+    ("lpt_get_time", C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    ("lpt_interp", C.c_int, [_P, C.c_int, C.c_int64, _P, _P, C.c_double, C.c_double, _P, _P,
+                             C.c_int32]),
+    ("lpt_radix_sort", C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, _P]),
+]
+
+_lib = None
+
+
+def load():
+    """Load liblpt.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"liblpt.so is not built ({LIB_PATH}); run "
+                               "`python -m paper_2607_17836_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class LptError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{load().lpt_status_string(status).decode()}: {msg}")
+        self.status = status
+
+
+def _is_dev(a):
+    return torch is not None and isinstance(a, torch.Tensor) and a.is_cuda
+
+
+def _arr(a, count=None, dtype=np.float64):
+    """(pointer, on_device, keepalive) of a float64 input array."""
+    if a is None:
+        return None, 0, None
+    if _is_dev(a):
+        assert a.dtype == torch.float64 and a.is_contiguous(), "device arrays: contiguous float64"
+        assert count is None or a.numel() == count
+        return a.data_ptr(), 1, a
+    h = np.ascontiguousarray(a, dtype=dtype)
+    assert count is None or h.size == count, (h.size, count)
+    return h.ctypes.data, 0, h
+
+
+class Tracker:
+    """One liblpt context (see include/lpt.h for the meaning of every call)."""
+
+    def __init__(self, n, precision="fp64", length=0.0, t0=0.0, stream=None, sort_interval=0,
+                 sort_tile=0, block_size=0, compat_edge=False, time_kernels=False):
+        lib = load()
+        cfg = LptConfig()
+        cfg.n = n
+        cfg.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
+        cfg.length = length
+        cfg.t0 = t0
+        cfg.hip_stream = stream
+        cfg.sort_interval = sort_interval
+        cfg.sort_tile = sort_tile
+        cfg.block_size = block_size
+        cfg.flags = (FLAG_COMPAT_EDGE if compat_edge else 0) | (FLAG_TIME_KERNELS if time_kernels else 0)
+        h = C.c_void_p()
+        st = lib.lpt_create(C.byref(cfg), C.byref(h))
+        if st != OK:
+            raise LptError(st, "lpt_create failed")
+        self._h = h
+        self.n = n
+        self.length = length if length else 2 * np.pi
+        self.precision = cfg.precision
+        self.counts = []
+
+    # -- plumbing ---------------------------------------------------------
+    def _check(self, st):
+        if st != OK:
+            raise LptError(st, load().lpt_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lpt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- API --------------------------------------------------------------
+    def synchronize(self):
+        self._check(load().lpt_synchronize(self._h))
+
+    def set_snapshot(self, slot, t, u, v):
+        nn = self.n * self.n
+        pu, du, ku = _arr(u, nn)
+        pv, dv, kv = _arr(v, nn)
+        assert du == dv
+        self._check(load().lpt_set_snapshot(self._h, slot, t, pu, pv, du))
+
+    def set_snapshot_psi(self, slot, t, psi):
+        p, d, k = _arr(psi, self.n * self.n)
+        self._check(load().lpt_set_snapshot_psi(self._h, slot, t, p, d))
+
+    def set_time_mode(self, mode):
+        self._check(load().lpt_set_time_mode(self._h, TIME_MODES[mode] if isinstance(mode, str) else mode))
+
+    def add_species(self, kind, st, scheme, x0, y0, vx0=None, vy0=None):
+        kind = KINDS[kind] if isinstance(kind, str) else kind
+        scheme = SCHEMES[scheme] if isinstance(scheme, str) else scheme
+        count = int(x0.numel() if _is_dev(x0) else np.size(x0))
+        px, d1, k1 = _arr(x0, count)
+        py, d2, k2 = _arr(y0, count)
+        pvx, d3, k3 = _arr(vx0, count)
+        pvy, d4, k4 = _arr(vy0, count)
+        sid = C.c_int32()
+        self._check(load().lpt_add_species(self._h, kind, float(st), scheme, count, px, py, pvx,
+                                           pvy, d1, C.byref(sid)))
+        self.counts.append(count)
+        return sid.value
+
+    def init_uniform(self, sid, seed):
+        self._check(load().lpt_init_uniform(self._h, sid, C.c_uint64(seed)))
+
+    def step(self, nsteps, dt, stats_every=0):
+        self._check(load().lpt_step(self._h, int(nsteps), float(dt), int(stats_every)))
+
+    def sort(self):
+        self._check(load().lpt_sort(self._h))
+
+    def get_positions(self, sid, out=None):
+        """Returns (xw, yw, xu, yu) numpy arrays, or fills the given device tensors."""
+        count = self.counts[sid]
+        if out is not None:
+            ptrs = [t.data_ptr() if t is not None else None for t in out]
+            self._check(load().lpt_get_positions(self._h, sid, *ptrs, 1))
+            return out
+        arrs = [np.empty(count) for _ in range(4)]
+        self._check(load().lpt_get_positions(self._h, sid, *[a.ctypes.data for a in arrs], 0))
+        return tuple(arrs)
+
+    def get_velocities(self, sid):
+        count = self.counts[sid]
+        vx, vy = np.empty(count), np.empty(count)
+        self._check(load().lpt_get_velocities(self._h, sid, vx.ctypes.data, vy.ctypes.data, 0))
+        return vx, vy
+
+    def get_stats(self, sid, cap=1 << 20):
+        steps, _ = self.get_time()
+        cap = min(cap, max(steps, 1))
+        out = np.zeros(cap, dtype=STAT_DTYPE)
+        nw = C.c_int64()
+        self._check(load().lpt_get_stats(self._h, sid, out.ctypes.data, cap, C.byref(nw)))
+        return out[: nw.value]
+
+    def get_order(self, sid):
+        ids = np.empty(self.counts[sid], dtype=np.int32)
+        self._check(load().lpt_get_order(self._h, sid, ids.ctypes.data, 0))
+        return ids
+
+    def get_timing(self, reset=True):
+        t = LptTiming()
+        self._check(load().lpt_get_timing(self._h, C.byref(t), int(reset)))
+        return dict(step_kernel_ms=t.step_kernel_ms, step_launches=t.step_launches,
+                    sort_ms=t.sort_ms, sorts=t.sorts)
+
+    def get_time(self):
+        s, t = C.c_int64(), C.c_double()
+        self._check(load().lpt_get_time(self._h, C.byref(s), C.byref(t)))
+        return s.value, t.value
+
+    def interp(self, scheme, x, y, wa=1.0, wb=0.0):
+        scheme = SCHEMES[scheme] if isinstance(scheme, str) else scheme
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        u, v = np.empty_like(x), np.empty_like(x)
+        self._check(load().lpt_interp(self._h, scheme, x.size, x.ctypes.data, y.ctypes.data,
+                                      float(wa), float(wb), u.ctypes.data, v.ctypes.data, 0))
+        return u, v
+
+    def radix_sort(self, keys, key_bits):
+        """Stable sort of a device uint32 tensor (as torch.int32 storage);
+        returns (sorted keys, permutation) as device tensors."""
+        assert _is_dev(keys) and keys.dtype == torch.int32 and keys.is_contiguous()
+        out = torch.empty_like(keys)
+        perm = torch.empty_like(keys)
+        self._check(load().lpt_radix_sort(self._h, keys.numel(), key_bits, keys.data_ptr(),
+                                          out.data_ptr(), perm.data_ptr()))
+        return out, perm
+
+
+def create_error_status(n, **kw):
+    """Status of lpt_create for a configuration (no context is kept)."""
+    lib = load()
+    cfg = LptConfig()
+    cfg.n = n
+    cfg.precision = kw.get("precision", FP64)
+    cfg.length = kw.get("length", 0.0)
+    cfg.t0 = kw.get("t0", 0.0)
+    cfg.hip_stream = None
+    cfg.sort_interval = kw.get("sort_interval", 0)
+    cfg.sort_tile = kw.get("sort_tile", 0)
+    cfg.block_size = kw.get("block_size", 0)
+    cfg.flags = kw.get("flags", 0)
+    h = C.c_void_p()
+    st = lib.lpt_create(C.byref(cfg), C.byref(h))
+    if st == OK:
+        lib.lpt_destroy(h)
+    return st

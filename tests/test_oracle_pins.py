@@ -242,27 +242,7 @@ def test_uniform_flow_tracer_and_its_statistics():
 # --------------------------------------------------------------------------
 # Inertial particles (Sec. 3.3, 5.3)
 # --------------------------------------------------------------------------
-def _rk4_linear_closed_form(st, dt, nsteps, x0, v0, U):
-    """RK4 applied to y' = A y + b is y_{n+1} = P4(dt A) y_n + dt Q3(dt A) b with
-    P4(Z) = sum_{k<=4} Z^k/k! and Q3(Z) = sum_{k<=3} Z^k/(k+1)!; evaluated in
-    40-digit arithmetic for y = (x, v), A = [[0, 1], [0, -1/St]], b = (0, U/St)."""
-    mpmath.mp.dps = 40
-    st, dt = mpmath.mpf(st), mpmath.mpf(dt)
-    A = mpmath.matrix([[0, 1], [0, -1 / st]])
-    b = mpmath.matrix([0, mpmath.mpf(U) / st])
-    Z = dt * A
-    I = mpmath.eye(2)
-    P, Q, Zk = I * 0, I * 0, I
-    for k in range(5):
-        P += Zk / mpmath.factorial(k)
-        if k <= 3:
-            Q += Zk / mpmath.factorial(k + 1)
-        Zk = Zk * Z
-    c = dt * (Q * b)
-    y = mpmath.matrix([mpmath.mpf(x0), mpmath.mpf(v0)])
-    for _ in range(nsteps):
-        y = P * y + c
-    return float(y[0]), float(y[1])
+from closed_forms import rk4_linear_closed_form as _rk4_linear_closed_form
 
 
 @pytest.mark.parametrize("st", [0.1, 0.5, 2.0])
