@@ -86,13 +86,13 @@ def cpu_baseline(w, budget_s=15.0):
     import oracle
     a, b, _ = w.snapshots()
     fl = oracle.grid_flow(a[0], a[1], b[0], b[1], scheme="bilinear", time_mode=oracle.PINGPONG)
-    x0, y0 = oracle.init_uniform(w.species[0][4], 1 << 16)
+    x0, y0 = oracle.init_uniform(w.species[0][4], 1 << 20)
     # calibrate on a small batch, then size the sample to ~budget_s
-    sp = oracle.Species(x0[:2048], y0[:2048])
+    sp = oracle.Species(x0[:4096], y0[:4096])
     t0 = time.perf_counter()
     oracle.run(fl, sp, 5, w.dt)
-    per = (time.perf_counter() - t0) / (2048 * 5)
-    count = int(min(1 << 16, max(4096, budget_s / per / 20)))
+    per = (time.perf_counter() - t0) / (4096 * 5)
+    count = int(min(1 << 20, max(4096, budget_s / per / 20)))
     nsteps = 20
     sp = oracle.Species(x0[:count], y0[:count])
     t0 = time.perf_counter()
@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--bw-probe", action="store_true",
+                    help="only run the copy/triad bandwidth probe and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
@@ -119,6 +121,14 @@ def main():
 
     from paper_2607_17836_amd import lpt, workloads
     lpt.load()
+    probe = lpt.Tracker(16, "fp64")
+    copy_gbs, triad_gbs = probe.bw_probe(1 << 30, 10)
+    probe.close()
+    log(f"[bench] achievable bandwidth: copy {copy_gbs:.0f} GB/s, triad {triad_gbs:.0f} GB/s")
+    if args.bw_probe:
+        print(json.dumps({"copy_gbps": copy_gbs, "triad_gbps": triad_gbs,
+                          "bytes_per_buffer": 1 << 30, "iters": 10}), flush=True)
+        return
     w = workloads.C3_SPLIT
     npart = w.particles
     elapsed, timing, nstats = run_gpu(w, args.steps, args.warmup, lpt)
@@ -162,7 +172,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "step32_kernel<bilinear, tracer>",
                      "kernel_avg_us": kern_ms * 1e3, "alg_bytes_per_particle_step": b_alg,
-                     "alg_bytes_per_launch": bytes_per_launch},
+                     "alg_bytes_per_launch": bytes_per_launch,
+                     "achievable_copy_gbps": copy_gbs, "achievable_triad_gbps": triad_gbs,
+                     "frac_of_copy": achieved / copy_gbs},
     }
     out.update(extra)
     if not args.no_cpu_baseline:

@@ -224,6 +224,14 @@ lpt_status lpt_interp(lpt_ctx *ctx, lpt_scheme scheme, int64_t npts, const doubl
 lpt_status lpt_radix_sort(lpt_ctx *ctx, int64_t npts, int32_t key_bits,
                           const uint32_t *keys_in, uint32_t *keys_out, uint32_t *perm);
 
+/* Achievable device-memory bandwidth: a plain copy of `bytes` (rounded down
+ * to a multiple of 16) between two device buffers, and a STREAM triad
+ * a = b + s*c over three such buffers, each repeated `iters` times on the
+ * context stream.  GB/s counts bytes read plus bytes written (copy: 2*bytes
+ * per pass, triad: 3*bytes).  The buffers are allocated and freed inside. */
+lpt_status lpt_bw_probe(lpt_ctx *ctx, int64_t bytes, int32_t iters, double *copy_gbps,
+                        double *triad_gbps);
+
 #ifdef __cplusplus
 }
 #endif

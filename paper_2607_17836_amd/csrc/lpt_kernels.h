@@ -25,14 +25,29 @@ struct SpeciesDev {
     int32_t block_end;
 };
 
+// Node records are stored with a periodic ghost border: one node before and
+// two after the grid on each axis, so that every stencil (bilinear: i..i+1,
+// bicubic: i-1..i+2) of a cell i in [0, n) is contiguous and never wraps.
+// Node (i, j), -1 <= i, j <= n + 1, lives at index (j + 1) * pitch + (i + 1)
+// with pitch = n + 3.
+constexpr int kGhostLo = 1;
+constexpr int kGhostHi = 2;
+inline int64_t padded_pitch(int n) { return (int64_t)n + kGhostLo + kGhostHi; }
+
+// Which time levels a stage needs: weights (1, 0), (0, 1), or a blend.
+enum SlotMode : int32_t { kSlot0 = 0, kSlot1 = 1, kBlend = 2 };
+
 struct StepParams {
     int32_t n;             // grid points per side
+    int32_t pitch;         // n + 3 (padded row length)
+    int32_t mask;          // n - 1 if n is a power of two, else -1
     int32_t nspecies;
     int32_t total_blocks;  // logical blocks over all species
     int32_t compat_edge;   // bicubic reverts to bilinear near the grid edge
     double L, h, invh;     // domain side, spacing, n/L
     double dt;
     double wa[4], wb[4];   // temporal weights of slot 0 / slot 1 per RK4 stage
+    int32_t smode[4];      // SlotMode per RK4 stage
     SpeciesDev sp[kMaxSpecies];
 };
 
@@ -69,9 +84,10 @@ struct State32 {
 struct alignas(32) Rec64 { double u0, v0, u1, v1; };
 
 // ---- launch wrappers (return hipGetLastError of the launch) -------------
-hipError_t launch_pack64(Rec64 *rec, int slot, const double *u, const double *v, int64_t nn,
+// rec: the padded record array ((n + 3)^2 records).
+hipError_t launch_pack64(Rec64 *rec, int slot, const double *u, const double *v, int n,
                          hipStream_t st);
-hipError_t launch_pack32(float4 *rec, int slot, const double *u, const double *v, int64_t nn,
+hipError_t launch_pack32(float4 *rec, int slot, const double *u, const double *v, int n,
                          double scale, hipStream_t st);
 hipError_t launch_psi_to_velocity(const double *psi, double *u, double *v, int n, double h,
                                   hipStream_t st);
@@ -118,6 +134,10 @@ hipError_t launch_readout32(const State32 &S, const double2 *x0, int64_t offset,
 
 hipError_t launch_order(const uint32_t *id, int64_t offset, int64_t count, int32_t *out,
                         hipStream_t st);
+
+// bandwidth probe (bytes: per buffer, multiple of 16)
+hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t st);
+hipError_t launch_triad(const void *b, const void *c, void *a, int64_t bytes, hipStream_t st);
 
 // ---- cell-order sort -------------------------------------------------------
 struct SortWork {

@@ -51,7 +51,7 @@ struct lpt_ctx {
     std::string err;
 
     // snapshots
-    void *rec = nullptr;   // Rec64[n*n] or float4[n*n]
+    void *rec = nullptr;   // padded Rec64 or float4 records, (n + 3)^2
     bool slot_set[2] = {false, false};
     double t_slot[2] = {0, 0};
     int32_t time_mode = LPT_TIME_BRACKET;
@@ -151,6 +151,13 @@ StepParams make_params(const lpt_ctx *c)
 {
     StepParams P{};
     P.n = c->n;
+    P.pitch = (int32_t)padded_pitch(c->n);
+    P.mask = is_pow2(c->n) ? c->n - 1 : -1;
+    for (int q = 0; q < 4; ++q) {
+        P.wa[q] = 1.0;
+        P.wb[q] = 0.0;
+        P.smode[q] = kSlot0;
+    }
     P.nspecies = (int32_t)c->sp.size();
     P.compat_edge = c->compat_edge ? 1 : 0;
     P.L = c->L;
@@ -190,6 +197,13 @@ void weights_at(const lpt_ctx *c, int64_t step, double t_n, double t, double dt,
         wa = 1.0 - theta;
         wb = theta;
     }
+}
+
+int32_t slot_mode(double wa, double wb)
+{
+    if (wa == 1.0 && wb == 0.0) return kSlot0;
+    if (wa == 0.0 && wb == 1.0) return kSlot1;
+    return kBlend;
 }
 
 int species_bits(const lpt_ctx *c) { return c->sp.size() > 1 ? ilog2i((int64_t)c->sp.size()) : 0; }
@@ -327,8 +341,8 @@ lpt_status lpt_create(const lpt_config *cfg, lpt_ctx **out)
     };
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) return bail(e);
-    const size_t nn = (size_t)n * n;
-    const size_t rec_bytes = nn * (c->precision == LPT_FP64 ? sizeof(Rec64) : sizeof(float4));
+    const size_t np2 = (size_t)padded_pitch(n) * (size_t)padded_pitch(n);
+    const size_t rec_bytes = np2 * (c->precision == LPT_FP64 ? sizeof(Rec64) : sizeof(float4));
     e = hipMalloc(&c->rec, rec_bytes);
     if (e != hipSuccess) return bail(e);
     e = hipMemsetAsync(c->rec, 0, rec_bytes, c->stream);
@@ -415,9 +429,9 @@ lpt_status lpt_set_snapshot(lpt_ctx *c, int32_t slot, double t, const double *u,
     if (s == LPT_OK) s = stage_in(c, st, v, nn, on_device, dv);
     if (s != LPT_OK) return s;
     if (c->precision == LPT_FP64)
-        HIP_TRY(c, launch_pack64(static_cast<Rec64 *>(c->rec), slot, du, dv, nn, c->stream));
+        HIP_TRY(c, launch_pack64(static_cast<Rec64 *>(c->rec), slot, du, dv, c->n, c->stream));
     else
-        HIP_TRY(c, launch_pack32(static_cast<float4 *>(c->rec), slot, du, dv, nn, c->invh,
+        HIP_TRY(c, launch_pack32(static_cast<float4 *>(c->rec), slot, du, dv, c->n, c->invh,
                                  c->stream));
     if (!st.bufs.empty()) HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->slot_set[slot] = true;
@@ -443,9 +457,10 @@ lpt_status lpt_set_snapshot_psi(lpt_ctx *c, int32_t slot, double t, const double
     st.bufs.push_back(uv);
     HIP_TRY(c, launch_psi_to_velocity(dp, uv, uv + nn, c->n, c->h, c->stream));
     if (c->precision == LPT_FP64)
-        HIP_TRY(c, launch_pack64(static_cast<Rec64 *>(c->rec), slot, uv, uv + nn, nn, c->stream));
+        HIP_TRY(c, launch_pack64(static_cast<Rec64 *>(c->rec), slot, uv, uv + nn, c->n,
+                                 c->stream));
     else
-        HIP_TRY(c, launch_pack32(static_cast<float4 *>(c->rec), slot, uv, uv + nn, nn, c->invh,
+        HIP_TRY(c, launch_pack32(static_cast<float4 *>(c->rec), slot, uv, uv + nn, c->n, c->invh,
                                  c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->slot_set[slot] = true;
@@ -680,8 +695,10 @@ lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
             const lpt_status s = do_sort(c);
             if (s != LPT_OK) return s;
         }
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 4; ++q) {
             weights_at(c, c->steps, c->t, c->t + stage_c[q] * dt, dt, P.wa[q], P.wb[q]);
+            P.smode[q] = slot_mode(P.wa[q], P.wb[q]);
+        }
         const bool rec = stats_every > 0 && (c->steps + 1) % stats_every == 0;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->time_kernels) HIP_TRY(c, mark(c, e0));
@@ -918,6 +935,49 @@ lpt_status lpt_radix_sort(lpt_ctx *c, int64_t npts, int32_t key_bits, const uint
     release();
     if (e != hipSuccess) s = fail(c, LPT_E_HIP, std::string("radix sort: ") + hipGetErrorString(e));
     return s;
+}
+
+lpt_status lpt_bw_probe(lpt_ctx *c, int64_t bytes, int32_t iters, double *copy_gbps,
+                        double *triad_gbps)
+{
+    if (!c) return LPT_E_ARG;
+    bytes &= ~(int64_t)15;
+    if (bytes <= 0 || iters < 1) return fail(c, LPT_E_ARG, "bytes and iters must be positive");
+    HIP_TRY(c, hipSetDevice(c->device));
+    void *a = nullptr, *b = nullptr, *d = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&a, bytes);
+    if (e == hipSuccess) e = hipMalloc(&b, bytes);
+    if (e == hipSuccess) e = hipMalloc(&d, bytes);
+    if (e == hipSuccess) e = hipMemsetAsync(a, 0, bytes, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b, 0, bytes, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d, 0, bytes, c->stream);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float ms = 0.f;
+    // copy: one warm-up pass, then iters timed passes
+    if (e == hipSuccess) e = launch_copy(a, b, bytes, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    for (int32_t k = 0; k < iters && e == hipSuccess; ++k) e = launch_copy(a, b, bytes, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && copy_gbps) *copy_gbps = 2.0 * bytes * iters / (ms * 1e-3) / 1e9;
+    if (e == hipSuccess) e = launch_triad(a, b, d, bytes, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    for (int32_t k = 0; k < iters && e == hipSuccess; ++k) e = launch_triad(a, b, d, bytes, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && triad_gbps) *triad_gbps = 3.0 * bytes * iters / (ms * 1e-3) / 1e9;
+    (void)hipStreamSynchronize(c->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (d) (void)hipFree(d);
+    HIP_TRY(c, e);
+    return LPT_OK;
 }
 
 }  // extern "C"

@@ -6,10 +6,12 @@
 // loop; eqs. rk4_update / rk4_inertial).  Each of the four stages gathers the
 // 4 (bilinear) or 16 (bicubic) node records around the stage position; a node
 // record carries both retained time levels, so one gather serves the temporal
-// interpolation (eq. temporal_interp) as well.  State is structure-of-arrays
-// with interleaved (x, y) pairs, so the per-step state stream is fully
-// coalesced; the gathers rely on cell-ordered particles (sort.hip) and an
-// XCD-aware block order for L2 locality.
+// interpolation (eq. temporal_interp) too, and a stage whose temporal weight
+// is (1, 0) or (0, 1) loads only the half it needs.  Records carry a periodic
+// ghost border, so a stencil never wraps: its nodes are fixed offsets from one
+// base address.  State is structure-of-arrays with interleaved (x, y) pairs,
+// so the per-step state stream is fully coalesced; the gathers rely on
+// cell-ordered particles (sort.hip) and an XCD-aware block order for L2 reuse.
 #include "lpt_kernels.h"
 
 #include <math.h>
@@ -18,6 +20,8 @@ namespace lpt {
 
 constexpr int kMaxBlock = 512;
 constexpr int kWave = 64;
+constexpr float kCellClampF = 1073741824.0f;   // 2^30 cells
+constexpr double kCellClampD = 1073741824.0;
 
 // ---------------------------------------------------------------------------
 // Block order.  The hardware deals consecutive workgroups round-robin over the
@@ -42,32 +46,35 @@ __device__ __forceinline__ int species_of(const StepParams &P, int lb)
 }
 
 // ---------------------------------------------------------------------------
-// Periodic cell index of a (possibly unwrapped) cell coordinate.  The common
-// case is within one period; anything else (including NaN) takes the slow
-// path, which always returns an index in [0, n) so that no gather can leave
-// the field.
+// Periodic cell index.  Cell coordinates are clamped to +-2^30 before the
+// integer conversion (one v_med3), so that any input -- NaN and absurd
+// displacements included -- yields an index inside [0, n) and no gather can
+// leave the field; within +-2^30 cells the mapping is the exact periodic one.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int periodic_index(long long c, int n)
+__device__ __forceinline__ int wrap_cell(int c, int n, int mask)
 {
-    if (c >= -(long long)n && c < 2LL * n) {
-        int ci = (int)c;
-        if (ci >= n) ci -= n;
-        else if (ci < 0) ci += n;
-        return ci;
+    if (mask >= 0) return c & mask;
+    if (c < 0) c += n;
+    if (c >= n) c -= n;
+    if ((unsigned)c >= (unsigned)n) {
+        c %= n;
+        if (c < 0) c += n;
     }
-    long long m = c % n;
-    if (m < 0) m += n;
-    return (int)m;
+    return c;
 }
 
-__device__ __forceinline__ int index_of_floor(double c, int n)
+__device__ __forceinline__ int cell_plus(int c, float fl, int n, int mask)
 {
-    if (!(fabs(c) < 4.0e18)) return 0;   // NaN / inf: any valid cell
-    return periodic_index((long long)c, n);
+    const float f = __builtin_amdgcn_fmed3f(fl, -kCellClampF, kCellClampF);
+    return wrap_cell(c + (int)f, n, mask);
 }
 
-__device__ __forceinline__ int next_i(int i, int n) { return i + 1 == n ? 0 : i + 1; }
-__device__ __forceinline__ int prev_i(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+__device__ __forceinline__ int cell_of_floor(double fl, int n, int mask)
+{
+    double f = fmin(fmax(fl, -kCellClampD), kCellClampD);
+    if (!(f == f)) f = 0.0;
+    return wrap_cell((int)f, n, mask);
+}
 
 // Catmull-Rom kernel (eq. cr_kernel) and cubic B-spline kernel
 // (eq. bspline_kernel), evaluated in Horner form.
@@ -91,41 +98,64 @@ __device__ __forceinline__ void weights_bs(T s, T w[4])
     w[3] = s * s * s * sixth;
 }
 
+template <typename T>
+__device__ __forceinline__ void bilinear_weights(T xi, T eta, T &w00, T &w10, T &w01, T &w11)
+{
+    w11 = xi * eta;
+    w10 = xi - w11;            // xi (1 - eta)
+    w01 = eta - w11;           // (1 - xi) eta
+    w00 = (T(1.0) - xi) - w01; // (1 - xi)(1 - eta)
+}
+
+__device__ __forceinline__ bool edge_cell(int compat, int i, int j, int n)
+{
+    return compat && (i == 0 || i >= n - 2 || j == 0 || j >= n - 2);
+}
+
 // ===========================================================================
-// FP64 path
+// FP64 path (physical units)
 // ===========================================================================
-__device__ __forceinline__ void node64(const Rec64 *__restrict__ rec, int idx, double wa,
+// Time-blended (u, v) of one node record.
+__device__ __forceinline__ void node64(const Rec64 *__restrict__ r, int smode, double wa,
                                        double wb, double &u, double &v)
 {
-    const double2 *q = reinterpret_cast<const double2 *>(rec + idx);
-    const double2 a = q[0];
-    const double2 b = q[1];
-    u = wa * a.x + wb * b.x;
-    v = wa * a.y + wb * b.y;
+    const double2 *q = reinterpret_cast<const double2 *>(r);
+    if (smode == kSlot0) {
+        const double2 a = q[0];
+        u = a.x;
+        v = a.y;
+    } else if (smode == kSlot1) {
+        const double2 b = q[1];
+        u = b.x;
+        v = b.y;
+    } else {
+        const double2 a = q[0], b = q[1];
+        u = wa * a.x + wb * b.x;
+        v = wa * a.y + wb * b.y;
+    }
 }
 
 // Velocity at (x, y) (physical units, any real value) with temporal weights
-// (wa, wb) on the two snapshot slots.
+// (wa, wb) on the two snapshot slots.  rec0 points at node (0, 0).
 template <bool CUBIC>
-__device__ __forceinline__ void vel64(const Rec64 *__restrict__ rec, int n, double invh,
-                                      int scheme, int compat, double x, double y, double wa,
-                                      double wb, double &u, double &v)
+__device__ __forceinline__ void vel64(const Rec64 *__restrict__ rec0, const StepParams &P,
+                                      int scheme, double x, double y, double wa, double wb,
+                                      int smode, double &u, double &v)
 {
-    const double sx = x * invh, sy = y * invh;
+    const double sx = x * P.invh, sy = y * P.invh;
     const double fx = floor(sx), fy = floor(sy);
     const double xi = sx - fx, eta = sy - fy;
-    const int i = index_of_floor(fx, n), j = index_of_floor(fy, n);
-    const int i1 = next_i(i, n), j1 = next_i(j, n);
-    const bool edge = compat && (i == 0 || i >= n - 2 || j == 0 || j >= n - 2);
-    if (!CUBIC || scheme == kBilinear || edge) {
+    const int n = P.n, pitch = P.pitch;
+    const int i = cell_of_floor(fx, n, P.mask), j = cell_of_floor(fy, n, P.mask);
+    if (!CUBIC || scheme == kBilinear || edge_cell(P.compat_edge, i, j, n)) {
+        const Rec64 *p = rec0 + (__mul24(j, pitch) + i);
         double u00, v00, u10, v10, u01, v01, u11, v11;
-        const int r0 = j * n, r1 = j1 * n;
-        node64(rec, r0 + i, wa, wb, u00, v00);
-        node64(rec, r0 + i1, wa, wb, u10, v10);
-        node64(rec, r1 + i, wa, wb, u01, v01);
-        node64(rec, r1 + i1, wa, wb, u11, v11);
-        const double w00 = (1.0 - xi) * (1.0 - eta), w10 = xi * (1.0 - eta);
-        const double w01 = (1.0 - xi) * eta, w11 = xi * eta;
+        node64(p, smode, wa, wb, u00, v00);
+        node64(p + 1, smode, wa, wb, u10, v10);
+        node64(p + pitch, smode, wa, wb, u01, v01);
+        node64(p + pitch + 1, smode, wa, wb, u11, v11);
+        double w00, w10, w01, w11;
+        bilinear_weights(xi, eta, w00, w10, w01, w11);
         u = w00 * u00 + w10 * u10 + w01 * u01 + w11 * u11;
         v = w00 * v00 + w10 * v10 + w01 * v01 + w11 * v11;
         return;
@@ -139,22 +169,21 @@ __device__ __forceinline__ void vel64(const Rec64 *__restrict__ rec, int n, doub
             weights_bs(xi, wx);
             weights_bs(eta, wy);
         }
-        const int ix[4] = {prev_i(i, n), i, i1, next_i(i1, n)};
-        const int jy[4] = {prev_i(j, n), j, j1, next_i(j1, n)};
+        const Rec64 *p = rec0 + (__mul24(j - 1, pitch) + (i - 1));
         double au = 0.0, av = 0.0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int row = jy[b] * n;
             double ru = 0.0, rv = 0.0;
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 double nu, nv;
-                node64(rec, row + ix[a], wa, wb, nu, nv);
+                node64(p + a, smode, wa, wb, nu, nv);
                 ru += wx[a] * nu;
                 rv += wx[a] * nv;
             }
             au += wy[b] * ru;
             av += wy[b] * rv;
+            p += pitch;
         }
         u = au;
         v = av;
@@ -217,8 +246,8 @@ __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64
     const int64_t local = (int64_t)(lb - sp.block_begin) * blockDim.x + threadIdx.x;
     const bool active = local < sp.count;
     const int64_t p = sp.offset + local;
-    const int n = P.n;
-    const double invh = P.invh, dt = P.dt, hdt = 0.5 * P.dt, dt6 = P.dt / 6.0;
+    const Rec64 *rec0 = rec + P.pitch + 1;
+    const double dt = P.dt, hdt = 0.5 * P.dt, dt6 = P.dt / 6.0;
     double r2x = 0.0, r2y = 0.0;
 
     if (active) {
@@ -231,19 +260,19 @@ __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64
             const double is = sp.inv_st;
             double u, v;
             const double V1x = vn.x, V1y = vn.y;
-            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x, x.y, P.wa[0], P.wb[0], u, v);
+            vel64<CUBIC>(rec0, P, sp.scheme, x.x, x.y, P.wa[0], P.wb[0], P.smode[0], u, v);
             const double A1x = (u - V1x) * is, A1y = (v - V1y) * is;
             const double V2x = vn.x + hdt * A1x, V2y = vn.y + hdt * A1y;
-            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x + hdt * V1x, x.y + hdt * V1y,
-                         P.wa[1], P.wb[1], u, v);
+            vel64<CUBIC>(rec0, P, sp.scheme, x.x + hdt * V1x, x.y + hdt * V1y, P.wa[1], P.wb[1],
+                         P.smode[1], u, v);
             const double A2x = (u - V2x) * is, A2y = (v - V2y) * is;
             const double V3x = vn.x + hdt * A2x, V3y = vn.y + hdt * A2y;
-            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x + hdt * V2x, x.y + hdt * V2y,
-                         P.wa[2], P.wb[2], u, v);
+            vel64<CUBIC>(rec0, P, sp.scheme, x.x + hdt * V2x, x.y + hdt * V2y, P.wa[2], P.wb[2],
+                         P.smode[2], u, v);
             const double A3x = (u - V3x) * is, A3y = (v - V3y) * is;
             const double V4x = vn.x + dt * A3x, V4y = vn.y + dt * A3y;
-            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x + dt * V3x, x.y + dt * V3y,
-                         P.wa[3], P.wb[3], u, v);
+            vel64<CUBIC>(rec0, P, sp.scheme, x.x + dt * V3x, x.y + dt * V3y, P.wa[3], P.wb[3],
+                         P.smode[3], u, v);
             const double A4x = (u - V4x) * is, A4y = (v - V4y) * is;
             ddx = dt6 * (V1x + 2.0 * V2x + 2.0 * V3x + V4x);
             ddy = dt6 * (V1y + 2.0 * V2y + 2.0 * V3y + V4y);
@@ -252,13 +281,13 @@ __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64
         } else {
             // eq. rk4_update, stages at t_n, t_n + dt/2, t_n + dt/2, t_n + dt
             double k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
-            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x, x.y, P.wa[0], P.wb[0], k1x, k1y);
-            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x + hdt * k1x, x.y + hdt * k1y,
-                         P.wa[1], P.wb[1], k2x, k2y);
-            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x + hdt * k2x, x.y + hdt * k2y,
-                         P.wa[2], P.wb[2], k3x, k3y);
-            vel64<CUBIC>(rec, n, invh, sp.scheme, P.compat_edge, x.x + dt * k3x, x.y + dt * k3y,
-                         P.wa[3], P.wb[3], k4x, k4y);
+            vel64<CUBIC>(rec0, P, sp.scheme, x.x, x.y, P.wa[0], P.wb[0], P.smode[0], k1x, k1y);
+            vel64<CUBIC>(rec0, P, sp.scheme, x.x + hdt * k1x, x.y + hdt * k1y, P.wa[1], P.wb[1],
+                         P.smode[1], k2x, k2y);
+            vel64<CUBIC>(rec0, P, sp.scheme, x.x + hdt * k2x, x.y + hdt * k2y, P.wa[2], P.wb[2],
+                         P.smode[2], k3x, k3y);
+            vel64<CUBIC>(rec0, P, sp.scheme, x.x + dt * k3x, x.y + dt * k3y, P.wa[3], P.wb[3],
+                         P.smode[3], k4x, k4y);
             ddx = dt6 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
             ddy = dt6 * (k1y + 2.0 * k2y + 2.0 * k3y + k4y);
         }
@@ -284,41 +313,47 @@ __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64
 // ===========================================================================
 // FP32 split path.  Positions are (cell, offset) with the offset in cell
 // units; the packed field is in cells per unit time, so every stage works in
-// cell units: q = offset + c*dt*k.
+// cell units: q = offset + c*dt*k, cell = stored cell + floor(q), in-cell
+// coordinate = fract(q).
 // ===========================================================================
-__device__ __forceinline__ int cell_plus(int c, float f, int n)
+template <int SM>
+__device__ __forceinline__ float2 half32(const float4 *__restrict__ r)
 {
-    if (fabsf(f) < 1.0e9f) return periodic_index((long long)c + (long long)f, n);
-    return 0;   // NaN / absurd displacement: any valid cell
-}
-
-__device__ __forceinline__ float4 ldrec(const float4 *__restrict__ rec, int idx)
-{
-    return rec[idx];
+    return reinterpret_cast<const float2 *>(r)[SM];
 }
 
 template <bool CUBIC>
-__device__ __forceinline__ void vel32(const float4 *__restrict__ rec, int n, int scheme,
-                                      int compat, int cx, int cy, float qx, float qy, float wa,
-                                      float wb, float &u, float &v)
+__device__ __forceinline__ void vel32(const float4 *__restrict__ rec0, const StepParams &P,
+                                      int scheme, int cx, int cy, float qx, float qy, float wa,
+                                      float wb, int smode, float &u, float &v)
 {
     const float fx = floorf(qx), fy = floorf(qy);
-    const float xi = qx - fx, eta = qy - fy;
-    const int i = cell_plus(cx, fx, n), j = cell_plus(cy, fy, n);
-    const int i1 = next_i(i, n), j1 = next_i(j, n);
-    const bool edge = compat && (i == 0 || i >= n - 2 || j == 0 || j >= n - 2);
-    if (!CUBIC || scheme == kBilinear || edge) {
-        const int r0 = j * n, r1 = j1 * n;
-        const float4 a = ldrec(rec, r0 + i), b = ldrec(rec, r0 + i1);
-        const float4 c = ldrec(rec, r1 + i), d = ldrec(rec, r1 + i1);
-        const float w00 = (1.0f - xi) * (1.0f - eta), w10 = xi * (1.0f - eta);
-        const float w01 = (1.0f - xi) * eta, w11 = xi * eta;
-        const float ua = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
-        const float va = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
-        const float ub = w00 * a.z + w10 * b.z + w01 * c.z + w11 * d.z;
-        const float vb = w00 * a.w + w10 * b.w + w01 * c.w + w11 * d.w;
-        u = wa * ua + wb * ub;
-        v = wa * va + wb * vb;
+    const float xi = __builtin_amdgcn_fractf(qx), eta = __builtin_amdgcn_fractf(qy);
+    const int n = P.n, pitch = P.pitch;
+    const int i = cell_plus(cx, fx, n, P.mask), j = cell_plus(cy, fy, n, P.mask);
+    if (!CUBIC || scheme == kBilinear || edge_cell(P.compat_edge, i, j, n)) {
+        const float4 *p = rec0 + (__mul24(j, pitch) + i);
+        float w00, w10, w01, w11;
+        bilinear_weights(xi, eta, w00, w10, w01, w11);
+        if (smode == kSlot0) {
+            const float2 a = half32<0>(p), b = half32<0>(p + 1);
+            const float2 c = half32<0>(p + pitch), d = half32<0>(p + pitch + 1);
+            u = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
+            v = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
+        } else if (smode == kSlot1) {
+            const float2 a = half32<1>(p), b = half32<1>(p + 1);
+            const float2 c = half32<1>(p + pitch), d = half32<1>(p + pitch + 1);
+            u = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
+            v = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
+        } else {
+            const float4 a = p[0], b = p[1], c = p[pitch], d = p[pitch + 1];
+            const float ua = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
+            const float va = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
+            const float ub = w00 * a.z + w10 * b.z + w01 * c.z + w11 * d.z;
+            const float vb = w00 * a.w + w10 * b.w + w01 * c.w + w11 * d.w;
+            u = wa * ua + wb * ub;
+            v = wa * va + wb * vb;
+        }
         return;
     }
     if constexpr (CUBIC) {
@@ -330,44 +365,60 @@ __device__ __forceinline__ void vel32(const float4 *__restrict__ rec, int n, int
             weights_bs(xi, wx);
             weights_bs(eta, wy);
         }
-        const int ix[4] = {prev_i(i, n), i, i1, next_i(i1, n)};
-        const int jy[4] = {prev_i(j, n), j, j1, next_i(j1, n)};
-        float au = 0.f, av = 0.f, bu = 0.f, bv = 0.f;
+        const float4 *p = rec0 + (__mul24(j - 1, pitch) + (i - 1));
+        if (smode != kBlend) {
+            const int h = smode;   // which half of the record
+            float au = 0.f, av = 0.f;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int row = jy[b] * n;
-            float ru = 0.f, rv = 0.f, su = 0.f, sv = 0.f;
+            for (int b = 0; b < 4; ++b) {
+                const float2 *q = reinterpret_cast<const float2 *>(p) + h;
+                float ru = 0.f, rv = 0.f;
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const float4 r = ldrec(rec, row + ix[a]);
-                ru += wx[a] * r.x;
-                rv += wx[a] * r.y;
-                su += wx[a] * r.z;
-                sv += wx[a] * r.w;
+                for (int a = 0; a < 4; ++a) {
+                    const float2 r = q[2 * a];
+                    ru += wx[a] * r.x;
+                    rv += wx[a] * r.y;
+                }
+                au += wy[b] * ru;
+                av += wy[b] * rv;
+                p += pitch;
             }
-            au += wy[b] * ru;
-            av += wy[b] * rv;
-            bu += wy[b] * su;
-            bv += wy[b] * sv;
+            u = au;
+            v = av;
+        } else {
+            float au = 0.f, av = 0.f, bu = 0.f, bv = 0.f;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                float ru = 0.f, rv = 0.f, su = 0.f, sv = 0.f;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const float4 r = p[a];
+                    ru += wx[a] * r.x;
+                    rv += wx[a] * r.y;
+                    su += wx[a] * r.z;
+                    sv += wx[a] * r.w;
+                }
+                au += wy[b] * ru;
+                av += wy[b] * rv;
+                bu += wy[b] * su;
+                bv += wy[b] * sv;
+                p += pitch;
+            }
+            u = wa * au + wb * bu;
+            v = wa * av + wb * bv;
         }
-        u = wa * au + wb * bu;
-        v = wa * av + wb * bv;
     }
 }
 
-// New (cell, offset) after a displacement of dq cells from offset o.
-__device__ __forceinline__ void advance_split(int &c, float &o, float dq, int n)
+// New (cell, offset) after a displacement of dq cells from offset o; the
+// offset stays in [0, 1) (fract never returns 1).
+__device__ __forceinline__ void advance_split(int &c, float &o, float dq, const StepParams &P)
 {
     const float q = o + dq;
     const float f = floorf(q);
-    float r = q - f;   // exact for |q| < 2^23
-    int nc = cell_plus(c, f, n);
-    if (r >= 1.0f) {   // q a hair below an integer rounds the fraction up to 1
-        r -= 1.0f;
-        nc = next_i(nc, n);
-    }
+    float r = __builtin_amdgcn_fractf(q);
     if (!(r >= 0.0f)) r = 0.0f;   // NaN guard keeps the state in range
-    c = nc;
+    c = cell_plus(c, f, P.n, P.mask);
     o = r;
 }
 
@@ -382,16 +433,16 @@ __global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32
     const int64_t local = (int64_t)(lb - sp.block_begin) * blockDim.x + threadIdx.x;
     const bool active = local < sp.count;
     const int64_t p = sp.offset + local;
-    const int n = P.n;
-    const float dt = (float)P.dt, hdt = 0.5f * dt, dt6 = dt / 6.0f;
+    const float4 *rec0 = rec + P.pitch + 1;
+    const float dt = (float)P.dt, hdt = (float)(0.5 * P.dt), dt6 = (float)(P.dt / 6.0);
     const float wa0 = (float)P.wa[0], wa1 = (float)P.wa[1], wa2 = (float)P.wa[2], wa3 = (float)P.wa[3];
     const float wb0 = (float)P.wb[0], wb1 = (float)P.wb[1], wb2 = (float)P.wb[2], wb3 = (float)P.wb[3];
+    const int m0 = P.smode[0], m1 = P.smode[1], m2 = P.smode[2], m3 = P.smode[3];
     double r2x = 0.0, r2y = 0.0;
 
     if (active) {
         const uint32_t cell = S.cell[p];
         const float2 o = S.off[p];
-        double2 d = S.disp[p];
         int cx = (int)(cell & 0xFFFFu), cy = (int)(cell >> 16);
         float dqx, dqy;
         if (INERTIAL && sp.inertial) {
@@ -399,19 +450,19 @@ __global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32
             const float is = (float)sp.inv_st;
             float u, v;
             const float V1x = vn.x, V1y = vn.y;
-            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x, o.y, wa0, wb0, u, v);
+            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x, o.y, wa0, wb0, m0, u, v);
             const float A1x = (u - V1x) * is, A1y = (v - V1y) * is;
             const float V2x = vn.x + hdt * A1x, V2y = vn.y + hdt * A1y;
-            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x + hdt * V1x, o.y + hdt * V1y,
-                         wa1, wb1, u, v);
+            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x + hdt * V1x, o.y + hdt * V1y, wa1, wb1, m1,
+                         u, v);
             const float A2x = (u - V2x) * is, A2y = (v - V2y) * is;
             const float V3x = vn.x + hdt * A2x, V3y = vn.y + hdt * A2y;
-            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x + hdt * V2x, o.y + hdt * V2y,
-                         wa2, wb2, u, v);
+            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x + hdt * V2x, o.y + hdt * V2y, wa2, wb2, m2,
+                         u, v);
             const float A3x = (u - V3x) * is, A3y = (v - V3y) * is;
             const float V4x = vn.x + dt * A3x, V4y = vn.y + dt * A3y;
-            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x + dt * V3x, o.y + dt * V3y,
-                         wa3, wb3, u, v);
+            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x + dt * V3x, o.y + dt * V3y, wa3, wb3, m3,
+                         u, v);
             const float A4x = (u - V4x) * is, A4y = (v - V4y) * is;
             dqx = dt6 * (V1x + 2.0f * V2x + 2.0f * V3x + V4x);
             dqy = dt6 * (V1y + 2.0f * V2y + 2.0f * V3y + V4y);
@@ -419,19 +470,20 @@ __global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32
                                    vn.y + dt6 * (A1y + 2.0f * A2y + 2.0f * A3y + A4y));
         } else {
             float k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
-            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x, o.y, wa0, wb0, k1x, k1y);
-            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x + hdt * k1x, o.y + hdt * k1y,
-                         wa1, wb1, k2x, k2y);
-            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x + hdt * k2x, o.y + hdt * k2y,
-                         wa2, wb2, k3x, k3y);
-            vel32<CUBIC>(rec, n, sp.scheme, P.compat_edge, cx, cy, o.x + dt * k3x, o.y + dt * k3y,
-                         wa3, wb3, k4x, k4y);
+            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x, o.y, wa0, wb0, m0, k1x, k1y);
+            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x + hdt * k1x, o.y + hdt * k1y, wa1, wb1, m1,
+                         k2x, k2y);
+            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x + hdt * k2x, o.y + hdt * k2y, wa2, wb2, m2,
+                         k3x, k3y);
+            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x + dt * k3x, o.y + dt * k3y, wa3, wb3, m3,
+                         k4x, k4y);
             dqx = dt6 * (k1x + 2.0f * k2x + 2.0f * k3x + k4x);
             dqy = dt6 * (k1y + 2.0f * k2y + 2.0f * k3y + k4y);
         }
         float ox = o.x, oy = o.y;
-        advance_split(cx, ox, dqx, n);
-        advance_split(cy, oy, dqy, n);
+        advance_split(cx, ox, dqx, P);
+        advance_split(cy, oy, dqy, P);
+        double2 d = S.disp[p];
         S.cell[p] = (uint32_t)cx | ((uint32_t)cy << 16);
         S.off[p] = make_float2(ox, oy);
         d.x += (double)dqx * P.h;
@@ -564,47 +616,62 @@ hipError_t launch_finalize(const StepParams &P, const double *partials, DevClock
 }
 
 // ===========================================================================
-// Snapshot ingest: planar u, v of one time level into its half of the node
-// records.
+// Snapshot ingest: planar u, v of one time level into its half of the padded
+// node records (ghost nodes are periodic images).
 // ===========================================================================
-__global__ void pack64_kernel(Rec64 *rec, int slot, const double *__restrict__ u,
-                              const double *__restrict__ v, int64_t nn)
+__device__ __forceinline__ int ghost_source(int a, int n)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nn) return;
-    double2 *q = reinterpret_cast<double2 *>(rec + k) + slot;
-    *q = make_double2(u[k], v[k]);
+    int i = a - kGhostLo;
+    if (i < 0) i += n;
+    if (i >= n) i -= n;
+    return i;
+}
+
+__global__ void pack64_kernel(Rec64 *rec, int slot, const double *__restrict__ u,
+                              const double *__restrict__ v, int n)
+{
+    const int pitch = n + kGhostLo + kGhostHi;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
+    if (a >= pitch) return;
+    const int64_t src = (int64_t)ghost_source(b, n) * n + ghost_source(a, n);
+    double2 *q = reinterpret_cast<double2 *>(rec + (int64_t)b * pitch + a) + slot;
+    *q = make_double2(u[src], v[src]);
 }
 
 __global__ void pack32_kernel(float4 *rec, int slot, const double *__restrict__ u,
-                              const double *__restrict__ v, int64_t nn, double scale)
+                              const double *__restrict__ v, int n, double scale)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nn) return;
-    float2 *q = reinterpret_cast<float2 *>(rec + k) + slot;
-    *q = make_float2((float)(u[k] * scale), (float)(v[k] * scale));
+    const int pitch = n + kGhostLo + kGhostHi;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
+    if (a >= pitch) return;
+    const int64_t src = (int64_t)ghost_source(b, n) * n + ghost_source(a, n);
+    float2 *q = reinterpret_cast<float2 *>(rec + (int64_t)b * pitch + a) + slot;
+    *q = make_float2((float)(u[src] * scale), (float)(v[src] * scale));
 }
 
-hipError_t launch_pack64(Rec64 *rec, int slot, const double *u, const double *v, int64_t nn,
+hipError_t launch_pack64(Rec64 *rec, int slot, const double *u, const double *v, int n,
                          hipStream_t st)
 {
-    const int b = 256;
-    hipLaunchKernelGGL(pack64_kernel, dim3((unsigned)((nn + b - 1) / b)), dim3(b), 0, st, rec,
-                       slot, u, v, nn);
+    const int pitch = n + kGhostLo + kGhostHi, b = 256;
+    hipLaunchKernelGGL(pack64_kernel, dim3((pitch + b - 1) / b, pitch), dim3(b), 0, st, rec, slot,
+                       u, v, n);
     return hipGetLastError();
 }
 
-hipError_t launch_pack32(float4 *rec, int slot, const double *u, const double *v, int64_t nn,
+hipError_t launch_pack32(float4 *rec, int slot, const double *u, const double *v, int n,
                          double scale, hipStream_t st)
 {
-    const int b = 256;
-    hipLaunchKernelGGL(pack32_kernel, dim3((unsigned)((nn + b - 1) / b)), dim3(b), 0, st, rec,
-                       slot, u, v, nn, scale);
+    const int pitch = n + kGhostLo + kGhostHi, b = 256;
+    hipLaunchKernelGGL(pack32_kernel, dim3((pitch + b - 1) / b, pitch), dim3(b), 0, st, rec, slot,
+                       u, v, n, scale);
     return hipGetLastError();
 }
 
 // Grid centred differences of psi (eq. particle_velocity_reconstruction with
 // the interpolation moved onto the grid).
+__device__ __forceinline__ int nxt(int i, int n) { return i + 1 == n ? 0 : i + 1; }
+__device__ __forceinline__ int prv(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+
 __global__ void psi_vel_kernel(const double *__restrict__ psi, double *u, double *v, int n,
                                double h)
 {
@@ -612,8 +679,8 @@ __global__ void psi_vel_kernel(const double *__restrict__ psi, double *u, double
     if (k >= (int64_t)n * n) return;
     const int i = (int)(k % n), j = (int)(k / n);
     const double inv2h = 1.0 / (2.0 * h);
-    u[k] = (psi[(int64_t)next_i(j, n) * n + i] - psi[(int64_t)prev_i(j, n) * n + i]) * inv2h;
-    v[k] = -(psi[(int64_t)j * n + next_i(i, n)] - psi[(int64_t)j * n + prev_i(i, n)]) * inv2h;
+    u[k] = (psi[(int64_t)nxt(j, n) * n + i] - psi[(int64_t)prv(j, n) * n + i]) * inv2h;
+    v[k] = -(psi[(int64_t)j * n + nxt(i, n)] - psi[(int64_t)j * n + prv(i, n)]) * inv2h;
 }
 
 hipError_t launch_psi_to_velocity(const double *psi, double *u, double *v, int n, double h,
@@ -628,8 +695,13 @@ hipError_t launch_psi_to_velocity(const double *psi, double *u, double *v, int n
 
 // ===========================================================================
 // Initial state.  Positions come from x0 (original order); the velocity of an
-// inertial species is v0 if given, else the interpolated fluid velocity.
+// inertial species is taken from the field or from v0.
 // ===========================================================================
+__device__ __forceinline__ int smode_of(double wa, double wb)
+{
+    return wb == 0.0 && wa == 1.0 ? kSlot0 : (wa == 0.0 && wb == 1.0 ? kSlot1 : kBlend);
+}
+
 __global__ void init64_kernel(StepParams P, State64 S, const double2 *__restrict__ x0,
                               const double2 *__restrict__ v0, const Rec64 *__restrict__ rec,
                               int species, int64_t begin, int64_t count, double wa, double wb,
@@ -646,7 +718,7 @@ __global__ void init64_kernel(StepParams P, State64 S, const double2 *__restrict
     if (sp.inertial) {
         if (vel_from_field) {
             double u, v;
-            vel64<true>(rec, P.n, P.invh, sp.scheme, P.compat_edge, x.x, x.y, wa, wb, u, v);
+            vel64<true>(rec + P.pitch + 1, P, sp.scheme, x.x, x.y, wa, wb, smode_of(wa, wb), u, v);
             S.vel[p] = make_double2(u, v);
         } else {
             S.vel[p] = v0[p];
@@ -654,15 +726,15 @@ __global__ void init64_kernel(StepParams P, State64 S, const double2 *__restrict
     }
 }
 
-__device__ __forceinline__ void split_of(double x, double invh, int n, int &c, float &o)
+__device__ __forceinline__ void split_of(double x, const StepParams &P, int &c, float &o)
 {
-    const double s = x * invh;
+    const double s = x * P.invh;
     const double f = floor(s);
     float r = (float)(s - f);
-    int ci = index_of_floor(f, n);
+    int ci = cell_of_floor(f, P.n, P.mask);
     if (r >= 1.0f) {
         r = 0.0f;
-        ci = next_i(ci, n);
+        ci = wrap_cell(ci + 1, P.n, P.mask);
     }
     if (!(r >= 0.0f)) r = 0.0f;
     c = ci;
@@ -681,8 +753,8 @@ __global__ void init32_kernel(StepParams P, State32 S, const double2 *__restrict
     const double2 x = x0[p];
     int cx, cy;
     float ox, oy;
-    split_of(x.x, P.invh, P.n, cx, ox);
-    split_of(x.y, P.invh, P.n, cy, oy);
+    split_of(x.x, P, cx, ox);
+    split_of(x.y, P, cy, oy);
     S.cell[p] = (uint32_t)cx | ((uint32_t)cy << 16);
     S.off[p] = make_float2(ox, oy);
     S.disp[p] = make_double2(0.0, 0.0);
@@ -690,8 +762,8 @@ __global__ void init32_kernel(StepParams P, State32 S, const double2 *__restrict
     if (sp.inertial) {
         if (vel_from_field) {
             float u, v;
-            vel32<true>(rec, P.n, sp.scheme, P.compat_edge, cx, cy, ox, oy, (float)wa, (float)wb,
-                        u, v);
+            vel32<true>(rec + P.pitch + 1, P, sp.scheme, cx, cy, ox, oy, (float)wa, (float)wb,
+                        smode_of(wa, wb), u, v);
             S.vel[p] = make_float2(u, v);
         } else {
             S.vel[p] = make_float2((float)(v0[p].x * P.invh), (float)(v0[p].y * P.invh));
@@ -779,7 +851,7 @@ __global__ void interp64_kernel(StepParams P, const Rec64 *__restrict__ rec, int
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= npts) return;
     double uu, vv;
-    vel64<true>(rec, P.n, P.invh, scheme, P.compat_edge, x[k], y[k], wa, wb, uu, vv);
+    vel64<true>(rec + P.pitch + 1, P, scheme, x[k], y[k], wa, wb, smode_of(wa, wb), uu, vv);
     u[k] = uu;
     v[k] = vv;
 }
@@ -793,10 +865,11 @@ __global__ void interp32_kernel(StepParams P, const float4 *__restrict__ rec, in
     if (k >= npts) return;
     int cx, cy;
     float ox, oy;
-    split_of(x[k], P.invh, P.n, cx, ox);
-    split_of(y[k], P.invh, P.n, cy, oy);
+    split_of(x[k], P, cx, ox);
+    split_of(y[k], P, cy, oy);
     float uu, vv;
-    vel32<true>(rec, P.n, scheme, P.compat_edge, cx, cy, ox, oy, (float)wa, (float)wb, uu, vv);
+    vel32<true>(rec + P.pitch + 1, P, scheme, cx, cy, ox, oy, (float)wa, (float)wb,
+                smode_of(wa, wb), uu, vv);
     u[k] = (double)uu * P.h;
     v[k] = (double)vv * P.h;
 }

@@ -75,6 +75,8 @@ _SIGS = [
     ("lpt_interp", C.c_int, [_P, C.c_int, C.c_int64, _P, _P, C.c_double, C.c_double, _P, _P,
                              C.c_int32]),
     ("lpt_radix_sort", C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, _P]),
+    ("lpt_bw_probe", C.c_int, [_P, C.c_int64, C.c_int32, C.POINTER(C.c_double),
+                               C.POINTER(C.c_double)]),
 ]
 
 _lib = None
@@ -261,6 +263,12 @@ class Tracker:
         self._check(load().lpt_interp(self._h, scheme, x.size, x.ctypes.data, y.ctypes.data,
                                       float(wa), float(wb), u.ctypes.data, v.ctypes.data, 0))
         return u, v
+
+    def bw_probe(self, nbytes, iters=20):
+        """(copy GB/s, triad GB/s) of plain streaming kernels on this device."""
+        cp, tr = C.c_double(), C.c_double()
+        self._check(load().lpt_bw_probe(self._h, int(nbytes), int(iters), C.byref(cp), C.byref(tr)))
+        return cp.value, tr.value
 
     def radix_sort(self, keys, key_bits):
         """Stable sort of a device uint32 tensor (as torch.int32 storage);
