@@ -95,6 +95,12 @@ typedef struct {
     int32_t block_size;     /* threads per block of the step kernel, multiple
                                of 64 in [64, 1024]; 0 selects 256             */
     uint32_t flags;         /* LPT_FLAG_*                                     */
+    int32_t tile_records;   /* capacity, in node records, of the per-block
+                               LDS field tile of the step kernel: 0 selects
+                               the default (19200 bytes: 1200 FP32-split or
+                               600 FP64 records), -1 disables tiles (every
+                               stencil gathers from global memory), else
+                               at least 16 records and at most 61440 bytes  */
 } lpt_config;
 
 /* One statistics record of one species (Sec. 3.2, 5.5):

@@ -34,6 +34,10 @@ constexpr int kGhostLo = 1;
 constexpr int kGhostHi = 2;
 inline int64_t padded_pitch(int n) { return (int64_t)n + kGhostLo + kGhostHi; }
 
+// A block stages an LDS tile only if it holds at most this many node records
+// per particle of the block (sparse species gather from global memory).
+constexpr int kTileWaste = 8;
+
 // Which time levels a stage needs: weights (1, 0), (0, 1), or a blend.
 enum SlotMode : int32_t { kSlot0 = 0, kSlot1 = 1, kBlend = 2 };
 
@@ -48,6 +52,8 @@ struct StepParams {
     double dt;
     double wa[4], wb[4];   // temporal weights of slot 0 / slot 1 per RK4 stage
     int32_t smode[4];      // SlotMode per RK4 stage
+    int32_t tile_cap;      // LDS tile capacity in node records (0: no tile)
+    const float *umax;     // device: largest node speed of slot 0 / 1, cells per unit time
     SpeciesDev sp[kMaxSpecies];
 };
 
@@ -89,6 +95,8 @@ hipError_t launch_pack64(Rec64 *rec, int slot, const double *u, const double *v,
                          hipStream_t st);
 hipError_t launch_pack32(float4 *rec, int slot, const double *u, const double *v, int n,
                          double scale, hipStream_t st);
+hipError_t launch_speed_max(const double *u, const double *v, int64_t nn, double scale,
+                            float *out, hipStream_t st);
 hipError_t launch_psi_to_velocity(const double *psi, double *u, double *v, int n, double h,
                                   hipStream_t st);
 

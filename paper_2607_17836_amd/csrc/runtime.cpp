@@ -19,6 +19,11 @@ using namespace lpt;
 
 namespace {
 
+// LDS budget of the step kernel's field tile: the default keeps eight
+// 256-thread blocks (32 waves) resident per CU within the 160 KiB of LDS.
+constexpr size_t kTileBytesDefault = 19200;
+constexpr size_t kTileBytesMax = 61440;
+
 struct SpeciesHost {
     int32_t kind;
     double st;
@@ -47,11 +52,13 @@ struct lpt_ctx {
     int32_t block = 256;
     int32_t sort_interval = 0;
     int32_t sort_tile = 16;
+    int32_t tile_cap = 0;    // LDS tile capacity of the step kernel, node records
     bool compat_edge = false;
     std::string err;
 
     // snapshots
     void *rec = nullptr;   // padded Rec64 or float4 records, (n + 3)^2
+    float *umax = nullptr; // largest node speed per slot, cells per unit time
     bool slot_set[2] = {false, false};
     double t_slot[2] = {0, 0};
     int32_t time_mode = LPT_TIME_BRACKET;
@@ -159,6 +166,8 @@ StepParams make_params(const lpt_ctx *c)
         P.smode[q] = kSlot0;
     }
     P.nspecies = (int32_t)c->sp.size();
+    P.tile_cap = c->tile_cap;
+    P.umax = c->umax;
     P.compat_edge = c->compat_edge ? 1 : 0;
     P.L = c->L;
     P.h = c->h;
@@ -317,6 +326,12 @@ lpt_status lpt_create(const lpt_config *cfg, lpt_ctx **out)
     const int32_t block = cfg->block_size == 0 ? 256 : cfg->block_size;
     if (block != 64 && block != 128 && block != 256 && block != 512) return LPT_E_ARG;
     if (cfg->flags & ~(LPT_FLAG_COMPAT_EDGE | LPT_FLAG_TIME_KERNELS)) return LPT_E_ARG;
+    const size_t rec_size = cfg->precision == LPT_FP64 ? sizeof(Rec64) : sizeof(float4);
+    const int32_t tile_max = (int32_t)(kTileBytesMax / rec_size);
+    int32_t tile_cap = cfg->tile_records;
+    if (tile_cap == 0) tile_cap = (int32_t)(kTileBytesDefault / rec_size);
+    else if (tile_cap == -1) tile_cap = 0;
+    else if (tile_cap < 16 || tile_cap > tile_max) return LPT_E_ARG;
 
     lpt_ctx *c = new (std::nothrow) lpt_ctx();
     if (!c) return LPT_E_NOMEM;
@@ -330,6 +345,7 @@ lpt_status lpt_create(const lpt_config *cfg, lpt_ctx **out)
     c->block = block;
     c->sort_interval = cfg->sort_interval;
     c->sort_tile = tile;
+    c->tile_cap = tile_cap;
     c->compat_edge = (cfg->flags & LPT_FLAG_COMPAT_EDGE) != 0;
     c->time_kernels = (cfg->flags & LPT_FLAG_TIME_KERNELS) != 0;
     c->t = cfg->t0;
@@ -346,6 +362,9 @@ lpt_status lpt_create(const lpt_config *cfg, lpt_ctx **out)
     e = hipMalloc(&c->rec, rec_bytes);
     if (e != hipSuccess) return bail(e);
     e = hipMemsetAsync(c->rec, 0, rec_bytes, c->stream);
+    if (e != hipSuccess) return bail(e);
+    e = dalloc(c->umax, 2);
+    if (e == hipSuccess) e = hipMemsetAsync(c->umax, 0, 2 * sizeof(float), c->stream);
     if (e != hipSuccess) return bail(e);
     e = dalloc(c->clock, 1);
     if (e != hipSuccess) return bail(e);
@@ -370,6 +389,7 @@ void lpt_destroy(lpt_ctx *c)
     dfree(c->partials);
     dfree(c->records);
     dfree(c->clock);
+    dfree(c->umax);
     if (c->rec) (void)hipFree(c->rec);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -428,6 +448,8 @@ lpt_status lpt_set_snapshot(lpt_ctx *c, int32_t slot, double t, const double *u,
     lpt_status s = stage_in(c, st, u, nn, on_device, du);
     if (s == LPT_OK) s = stage_in(c, st, v, nn, on_device, dv);
     if (s != LPT_OK) return s;
+    HIP_TRY(c, hipMemsetAsync(c->umax + slot, 0, sizeof(float), c->stream));
+    HIP_TRY(c, launch_speed_max(du, dv, nn, c->invh, c->umax + slot, c->stream));
     if (c->precision == LPT_FP64)
         HIP_TRY(c, launch_pack64(static_cast<Rec64 *>(c->rec), slot, du, dv, c->n, c->stream));
     else
@@ -456,6 +478,8 @@ lpt_status lpt_set_snapshot_psi(lpt_ctx *c, int32_t slot, double t, const double
     HIP_TRY(c, dalloc(uv, (size_t)(2 * nn)));
     st.bufs.push_back(uv);
     HIP_TRY(c, launch_psi_to_velocity(dp, uv, uv + nn, c->n, c->h, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->umax + slot, 0, sizeof(float), c->stream));
+    HIP_TRY(c, launch_speed_max(uv, uv + nn, nn, c->invh, c->umax + slot, c->stream));
     if (c->precision == LPT_FP64)
         HIP_TRY(c, launch_pack64(static_cast<Rec64 *>(c->rec), slot, uv, uv + nn, c->n,
                                  c->stream));

@@ -113,11 +113,116 @@ __device__ __forceinline__ bool edge_cell(int compat, int i, int j, int n)
 }
 
 // ===========================================================================
+// LDS field tiles.  After the cell-order sort, the particles of one block sit
+// in a compact patch of cells.  The block finds the bounding box of its
+// particles' stored cells, widens it by a halo that covers every RK4 stage
+// position (the largest displacement a step can make, from the largest node
+// speed of the two time levels) plus the interpolation stencil, and copies
+// the node records of that box into LDS with coalesced row loads.  The four
+// stages then gather from LDS.  Every gather checks that its whole stencil
+// lies inside the tile and otherwise reads global memory, so the halo is a
+// performance estimate, never a correctness assumption.
+// ===========================================================================
+struct Tile {
+    int x0, y0;   // global node index of tile entry (0, 0)
+    int w, h;     // tile extent in nodes
+    int on;       // block-uniform: the tile is staged
+};
+
+__device__ __forceinline__ Tile no_tile() { return Tile{0, 0, 0, 0, 0}; }
+
+// Tile index of stencil origin node (i0, j0) if the span x span stencil that
+// starts there lies inside the tile.
+__device__ __forceinline__ bool tile_index(const Tile &T, int i0, int j0, int span, int n,
+                                           int mask, int &idx)
+{
+    const int rx = wrap_cell(i0 - T.x0, n, mask), ry = wrap_cell(j0 - T.y0, n, mask);
+    idx = ry * T.w + rx;
+    return T.on && rx <= T.w - span && ry <= T.h - span;
+}
+
+extern __shared__ __align__(32) unsigned char lpt_dyn_lds[];
+
+// Halo in cells for one step of size dt: the largest stage displacement
+// (velocity bound times dt, rounded up) -- Catmull-Rom can overshoot the node
+// values by up to (1 + 1/4)^2 because its weights have |W| summing to
+// 1 + s(1 - s) per axis; bilinear and B-spline weights are convex.
+__device__ __forceinline__ int step_halo(const StepParams &P, int scheme, float dt)
+{
+    const float um = fmaxf(P.umax[0], P.umax[1]);   // cells per unit time
+    const float cs = scheme == kCatmullRom ? 1.5625f : 1.0f;
+    const float d = fminf(cs * um * dt, 16.0f);
+    return d > 0.0f ? (int)ceilf(d) : 0;
+}
+
+// Cooperative tile set-up of one block (all threads must call it).
+// (cx, cy): the thread's stored cell (ignored when !active); (ax, ay): the
+// stored cell of the block's first particle, which is always active.
+template <typename Rec>
+__device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec0,
+                                          const StepParams &P, bool active, int cx, int cy,
+                                          int ax, int ay, int lo, int hi, int nactive)
+{
+    __shared__ int red[4][kMaxBlock / kWave];
+    const int n = P.n, mask = P.mask, half = n >> 1;
+    int rx = 0, ry = 0;
+    if (active) {
+        rx = wrap_cell(cx - ax, n, mask);
+        ry = wrap_cell(cy - ay, n, mask);
+        if (rx > half) rx -= n;
+        if (ry > half) ry -= n;
+    }
+    int mnx = rx, mxx = rx, mny = ry, mxy = ry;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        mnx = min(mnx, __shfl_xor(mnx, off, kWave));
+        mxx = max(mxx, __shfl_xor(mxx, off, kWave));
+        mny = min(mny, __shfl_xor(mny, off, kWave));
+        mxy = max(mxy, __shfl_xor(mxy, off, kWave));
+    }
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    if (lane == 0) {
+        red[0][wv] = mnx;
+        red[1][wv] = mxx;
+        red[2][wv] = mny;
+        red[3][wv] = mxy;
+    }
+    __syncthreads();
+    mnx = red[0][0];
+    mxx = red[1][0];
+    mny = red[2][0];
+    mxy = red[3][0];
+    for (int k = 1; k < nw; ++k) {
+        mnx = min(mnx, red[0][k]);
+        mxx = max(mxx, red[1][k]);
+        mny = min(mny, red[2][k]);
+        mxy = max(mxy, red[3][k]);
+    }
+    Tile T;
+    T.w = mxx - mnx + 1 + lo + hi;
+    T.h = mxy - mny + 1 + lo + hi;
+    T.x0 = wrap_cell(ax + mnx - lo, n, mask);
+    T.y0 = wrap_cell(ay + mny - lo, n, mask);
+    const int area = T.w * T.h;
+    T.on = P.tile_cap > 0 && area <= P.tile_cap && T.w < n && T.h < n &&
+           area <= kTileWaste * nactive;
+    if (T.on) {
+        for (int r = wv; r < T.h; r += nw) {
+            const Rec *row = rec0 + (int64_t)wrap_cell(T.y0 + r, n, mask) * P.pitch;
+            Rec *dst = lds + r * T.w;
+            for (int c = lane; c < T.w; c += kWave) dst[c] = row[wrap_cell(T.x0 + c, n, mask)];
+        }
+    }
+    __syncthreads();
+    return T;
+}
+
+// ===========================================================================
 // FP64 path (physical units)
 // ===========================================================================
 // Time-blended (u, v) of one node record.
-__device__ __forceinline__ void node64(const Rec64 *__restrict__ r, int smode, double wa,
-                                       double wb, double &u, double &v)
+__device__ __forceinline__ void node64(const Rec64 *r, int smode, double wa, double wb, double &u,
+                                       double &v)
 {
     const double2 *q = reinterpret_cast<const double2 *>(r);
     if (smode == kSlot0) {
@@ -135,29 +240,67 @@ __device__ __forceinline__ void node64(const Rec64 *__restrict__ r, int smode, d
     }
 }
 
+// eq. bilinear_interp on the records at p (node (i, j)), p + 1, p + pitch,
+// p + pitch + 1.
+__device__ __forceinline__ void bil64(const Rec64 *p, int pitch, double xi, double eta, int smode,
+                                      double wa, double wb, double &u, double &v)
+{
+    double u00, v00, u10, v10, u01, v01, u11, v11;
+    node64(p, smode, wa, wb, u00, v00);
+    node64(p + 1, smode, wa, wb, u10, v10);
+    node64(p + pitch, smode, wa, wb, u01, v01);
+    node64(p + pitch + 1, smode, wa, wb, u11, v11);
+    double w00, w10, w01, w11;
+    bilinear_weights(xi, eta, w00, w10, w01, w11);
+    u = w00 * u00 + w10 * u10 + w01 * u01 + w11 * u11;
+    v = w00 * v00 + w10 * v10 + w01 * v01 + w11 * v11;
+}
+
+// eqs. cr_interp / bspline_interp on the 4x4 records whose first is p
+// (node (i - 1, j - 1)).
+__device__ __forceinline__ void cub64(const Rec64 *p, int pitch, const double wx[4],
+                                      const double wy[4], int smode, double wa, double wb,
+                                      double &u, double &v)
+{
+    double au = 0.0, av = 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        double ru = 0.0, rv = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            double nu, nv;
+            node64(p + a, smode, wa, wb, nu, nv);
+            ru += wx[a] * nu;
+            rv += wx[a] * nv;
+        }
+        au += wy[b] * ru;
+        av += wy[b] * rv;
+        p += pitch;
+    }
+    u = au;
+    v = av;
+}
+
 // Velocity at (x, y) (physical units, any real value) with temporal weights
-// (wa, wb) on the two snapshot slots.  rec0 points at node (0, 0).
+// (wa, wb) on the two snapshot slots.  rec0 points at global node (0, 0);
+// tile/T is the block's LDS tile (T.on == 0: global only).
 template <bool CUBIC>
-__device__ __forceinline__ void vel64(const Rec64 *__restrict__ rec0, const StepParams &P,
-                                      int scheme, double x, double y, double wa, double wb,
-                                      int smode, double &u, double &v)
+__device__ __forceinline__ void vel64(const Rec64 *__restrict__ rec0, const Rec64 *tile,
+                                      const Tile &T, const StepParams &P, int scheme, double x,
+                                      double y, double wa, double wb, int smode, double &u,
+                                      double &v)
 {
     const double sx = x * P.invh, sy = y * P.invh;
     const double fx = floor(sx), fy = floor(sy);
     const double xi = sx - fx, eta = sy - fy;
-    const int n = P.n, pitch = P.pitch;
-    const int i = cell_of_floor(fx, n, P.mask), j = cell_of_floor(fy, n, P.mask);
+    const int n = P.n, mask = P.mask;
+    const int i = cell_of_floor(fx, n, mask), j = cell_of_floor(fy, n, mask);
+    int t;
     if (!CUBIC || scheme == kBilinear || edge_cell(P.compat_edge, i, j, n)) {
-        const Rec64 *p = rec0 + (__mul24(j, pitch) + i);
-        double u00, v00, u10, v10, u01, v01, u11, v11;
-        node64(p, smode, wa, wb, u00, v00);
-        node64(p + 1, smode, wa, wb, u10, v10);
-        node64(p + pitch, smode, wa, wb, u01, v01);
-        node64(p + pitch + 1, smode, wa, wb, u11, v11);
-        double w00, w10, w01, w11;
-        bilinear_weights(xi, eta, w00, w10, w01, w11);
-        u = w00 * u00 + w10 * u10 + w01 * u01 + w11 * u11;
-        v = w00 * v00 + w10 * v10 + w01 * v01 + w11 * v11;
+        if (tile_index(T, i, j, 2, n, mask, t))
+            bil64(tile + t, T.w, xi, eta, smode, wa, wb, u, v);
+        else
+            bil64(rec0 + (__mul24(j, P.pitch) + i), P.pitch, xi, eta, smode, wa, wb, u, v);
         return;
     }
     if constexpr (CUBIC) {
@@ -169,24 +312,10 @@ __device__ __forceinline__ void vel64(const Rec64 *__restrict__ rec0, const Step
             weights_bs(xi, wx);
             weights_bs(eta, wy);
         }
-        const Rec64 *p = rec0 + (__mul24(j - 1, pitch) + (i - 1));
-        double au = 0.0, av = 0.0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            double ru = 0.0, rv = 0.0;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                double nu, nv;
-                node64(p + a, smode, wa, wb, nu, nv);
-                ru += wx[a] * nu;
-                rv += wx[a] * nv;
-            }
-            au += wy[b] * ru;
-            av += wy[b] * rv;
-            p += pitch;
-        }
-        u = au;
-        v = av;
+        if (tile_index(T, i - 1, j - 1, 4, n, mask, t))
+            cub64(tile + t, T.w, wx, wy, smode, wa, wb, u, v);
+        else
+            cub64(rec0 + (__mul24(j - 1, P.pitch) + (i - 1)), P.pitch, wx, wy, smode, wa, wb, u, v);
     }
 }
 
@@ -235,23 +364,50 @@ __device__ __forceinline__ void block_sum3(double a, double b, double c, double 
     }
 }
 
+// Halo extents of a scheme: a bilinear stencil spans nodes i..i+1, a bicubic
+// one i-1..i+2 (the compatibility fallback to bilinear stays inside both).
+__device__ __forceinline__ void stencil_reach(int scheme, int &lo, int &hi)
+{
+    lo = scheme == kBilinear ? 0 : 1;
+    hi = scheme == kBilinear ? 1 : 2;
+}
+
 template <bool CUBIC, bool INERTIAL, bool STATS>
 __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64 S,
                                                            const Rec64 *__restrict__ rec,
                                                            double *__restrict__ partials,
                                                            DevClock *clock)
 {
+    Rec64 *lds = reinterpret_cast<Rec64 *>(lpt_dyn_lds);
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const SpeciesDev &sp = P.sp[species_of(P, lb)];
-    const int64_t local = (int64_t)(lb - sp.block_begin) * blockDim.x + threadIdx.x;
+    const int64_t base = (int64_t)(lb - sp.block_begin) * blockDim.x;
+    const int64_t local = base + threadIdx.x;
     const bool active = local < sp.count;
     const int64_t p = sp.offset + local;
     const Rec64 *rec0 = rec + P.pitch + 1;
     const double dt = P.dt, hdt = 0.5 * P.dt, dt6 = P.dt / 6.0;
     double r2x = 0.0, r2y = 0.0;
 
+    double2 x = make_double2(0.0, 0.0);
+    if (active) x = S.pos[p];
+    Tile T = no_tile();
+    if (P.tile_cap > 0) {
+        const double2 a = S.pos[sp.offset + base];
+        const int n = P.n, mask = P.mask;
+        const int ax = cell_of_floor(floor(a.x * P.invh), n, mask);
+        const int ay = cell_of_floor(floor(a.y * P.invh), n, mask);
+        const int cx = cell_of_floor(floor(x.x * P.invh), n, mask);
+        const int cy = cell_of_floor(floor(x.y * P.invh), n, mask);
+        int lo, hi;
+        stencil_reach(sp.scheme, lo, hi);
+        const int H = step_halo(P, sp.scheme, (float)dt);
+        const int64_t left = sp.count - base;
+        T = stage_tile<Rec64>(lds, rec0, P, active, cx, cy, ax, ay, lo + H, hi + H,
+                              (int)(left < (int64_t)blockDim.x ? left : blockDim.x));
+    }
+
     if (active) {
-        const double2 x = S.pos[p];
         double2 d = S.disp[p];
         double ddx, ddy;
         if (INERTIAL && sp.inertial) {
@@ -260,19 +416,19 @@ __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64
             const double is = sp.inv_st;
             double u, v;
             const double V1x = vn.x, V1y = vn.y;
-            vel64<CUBIC>(rec0, P, sp.scheme, x.x, x.y, P.wa[0], P.wb[0], P.smode[0], u, v);
+            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x, x.y, P.wa[0], P.wb[0], P.smode[0], u, v);
             const double A1x = (u - V1x) * is, A1y = (v - V1y) * is;
             const double V2x = vn.x + hdt * A1x, V2y = vn.y + hdt * A1y;
-            vel64<CUBIC>(rec0, P, sp.scheme, x.x + hdt * V1x, x.y + hdt * V1y, P.wa[1], P.wb[1],
-                         P.smode[1], u, v);
+            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x + hdt * V1x, x.y + hdt * V1y, P.wa[1],
+                         P.wb[1], P.smode[1], u, v);
             const double A2x = (u - V2x) * is, A2y = (v - V2y) * is;
             const double V3x = vn.x + hdt * A2x, V3y = vn.y + hdt * A2y;
-            vel64<CUBIC>(rec0, P, sp.scheme, x.x + hdt * V2x, x.y + hdt * V2y, P.wa[2], P.wb[2],
-                         P.smode[2], u, v);
+            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x + hdt * V2x, x.y + hdt * V2y, P.wa[2],
+                         P.wb[2], P.smode[2], u, v);
             const double A3x = (u - V3x) * is, A3y = (v - V3y) * is;
             const double V4x = vn.x + dt * A3x, V4y = vn.y + dt * A3y;
-            vel64<CUBIC>(rec0, P, sp.scheme, x.x + dt * V3x, x.y + dt * V3y, P.wa[3], P.wb[3],
-                         P.smode[3], u, v);
+            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x + dt * V3x, x.y + dt * V3y, P.wa[3],
+                         P.wb[3], P.smode[3], u, v);
             const double A4x = (u - V4x) * is, A4y = (v - V4y) * is;
             ddx = dt6 * (V1x + 2.0 * V2x + 2.0 * V3x + V4x);
             ddy = dt6 * (V1y + 2.0 * V2y + 2.0 * V3y + V4y);
@@ -281,13 +437,14 @@ __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64
         } else {
             // eq. rk4_update, stages at t_n, t_n + dt/2, t_n + dt/2, t_n + dt
             double k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
-            vel64<CUBIC>(rec0, P, sp.scheme, x.x, x.y, P.wa[0], P.wb[0], P.smode[0], k1x, k1y);
-            vel64<CUBIC>(rec0, P, sp.scheme, x.x + hdt * k1x, x.y + hdt * k1y, P.wa[1], P.wb[1],
-                         P.smode[1], k2x, k2y);
-            vel64<CUBIC>(rec0, P, sp.scheme, x.x + hdt * k2x, x.y + hdt * k2y, P.wa[2], P.wb[2],
-                         P.smode[2], k3x, k3y);
-            vel64<CUBIC>(rec0, P, sp.scheme, x.x + dt * k3x, x.y + dt * k3y, P.wa[3], P.wb[3],
-                         P.smode[3], k4x, k4y);
+            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x, x.y, P.wa[0], P.wb[0], P.smode[0], k1x,
+                         k1y);
+            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x + hdt * k1x, x.y + hdt * k1y, P.wa[1],
+                         P.wb[1], P.smode[1], k2x, k2y);
+            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x + hdt * k2x, x.y + hdt * k2y, P.wa[2],
+                         P.wb[2], P.smode[2], k3x, k3y);
+            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x + dt * k3x, x.y + dt * k3y, P.wa[3],
+                         P.wb[3], P.smode[3], k4x, k4y);
             ddx = dt6 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
             ddy = dt6 * (k1y + 2.0 * k2y + 2.0 * k3y + k4y);
         }
@@ -317,43 +474,100 @@ __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64
 // coordinate = fract(q).
 // ===========================================================================
 template <int SM>
-__device__ __forceinline__ float2 half32(const float4 *__restrict__ r)
+__device__ __forceinline__ float2 half32(const float4 *r)
 {
     return reinterpret_cast<const float2 *>(r)[SM];
 }
 
+__device__ __forceinline__ void bil32(const float4 *p, int pitch, float xi, float eta, int smode,
+                                      float wa, float wb, float &u, float &v)
+{
+    float w00, w10, w01, w11;
+    bilinear_weights(xi, eta, w00, w10, w01, w11);
+    if (smode == kSlot0) {
+        const float2 a = half32<0>(p), b = half32<0>(p + 1);
+        const float2 c = half32<0>(p + pitch), d = half32<0>(p + pitch + 1);
+        u = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
+        v = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
+    } else if (smode == kSlot1) {
+        const float2 a = half32<1>(p), b = half32<1>(p + 1);
+        const float2 c = half32<1>(p + pitch), d = half32<1>(p + pitch + 1);
+        u = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
+        v = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
+    } else {
+        const float4 a = p[0], b = p[1], c = p[pitch], d = p[pitch + 1];
+        const float ua = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
+        const float va = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
+        const float ub = w00 * a.z + w10 * b.z + w01 * c.z + w11 * d.z;
+        const float vb = w00 * a.w + w10 * b.w + w01 * c.w + w11 * d.w;
+        u = wa * ua + wb * ub;
+        v = wa * va + wb * vb;
+    }
+}
+
+__device__ __forceinline__ void cub32(const float4 *p, int pitch, const float wx[4],
+                                      const float wy[4], int smode, float wa, float wb, float &u,
+                                      float &v)
+{
+    if (smode != kBlend) {
+        const int h = smode;   // which half of the record
+        float au = 0.f, av = 0.f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const float2 *q = reinterpret_cast<const float2 *>(p) + h;
+            float ru = 0.f, rv = 0.f;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const float2 r = q[2 * a];
+                ru += wx[a] * r.x;
+                rv += wx[a] * r.y;
+            }
+            au += wy[b] * ru;
+            av += wy[b] * rv;
+            p += pitch;
+        }
+        u = au;
+        v = av;
+    } else {
+        float au = 0.f, av = 0.f, bu = 0.f, bv = 0.f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            float ru = 0.f, rv = 0.f, su = 0.f, sv = 0.f;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const float4 r = p[a];
+                ru += wx[a] * r.x;
+                rv += wx[a] * r.y;
+                su += wx[a] * r.z;
+                sv += wx[a] * r.w;
+            }
+            au += wy[b] * ru;
+            av += wy[b] * rv;
+            bu += wy[b] * su;
+            bv += wy[b] * sv;
+            p += pitch;
+        }
+        u = wa * au + wb * bu;
+        v = wa * av + wb * bv;
+    }
+}
+
 template <bool CUBIC>
-__device__ __forceinline__ void vel32(const float4 *__restrict__ rec0, const StepParams &P,
-                                      int scheme, int cx, int cy, float qx, float qy, float wa,
-                                      float wb, int smode, float &u, float &v)
+__device__ __forceinline__ void vel32(const float4 *__restrict__ rec0, const float4 *tile,
+                                      const Tile &T, const StepParams &P, int scheme, int cx,
+                                      int cy, float qx, float qy, float wa, float wb, int smode,
+                                      float &u, float &v)
 {
     const float fx = floorf(qx), fy = floorf(qy);
     const float xi = __builtin_amdgcn_fractf(qx), eta = __builtin_amdgcn_fractf(qy);
-    const int n = P.n, pitch = P.pitch;
-    const int i = cell_plus(cx, fx, n, P.mask), j = cell_plus(cy, fy, n, P.mask);
+    const int n = P.n, mask = P.mask;
+    const int i = cell_plus(cx, fx, n, mask), j = cell_plus(cy, fy, n, mask);
+    int t;
     if (!CUBIC || scheme == kBilinear || edge_cell(P.compat_edge, i, j, n)) {
-        const float4 *p = rec0 + (__mul24(j, pitch) + i);
-        float w00, w10, w01, w11;
-        bilinear_weights(xi, eta, w00, w10, w01, w11);
-        if (smode == kSlot0) {
-            const float2 a = half32<0>(p), b = half32<0>(p + 1);
-            const float2 c = half32<0>(p + pitch), d = half32<0>(p + pitch + 1);
-            u = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
-            v = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
-        } else if (smode == kSlot1) {
-            const float2 a = half32<1>(p), b = half32<1>(p + 1);
-            const float2 c = half32<1>(p + pitch), d = half32<1>(p + pitch + 1);
-            u = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
-            v = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
-        } else {
-            const float4 a = p[0], b = p[1], c = p[pitch], d = p[pitch + 1];
-            const float ua = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
-            const float va = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
-            const float ub = w00 * a.z + w10 * b.z + w01 * c.z + w11 * d.z;
-            const float vb = w00 * a.w + w10 * b.w + w01 * c.w + w11 * d.w;
-            u = wa * ua + wb * ub;
-            v = wa * va + wb * vb;
-        }
+        if (tile_index(T, i, j, 2, n, mask, t))
+            bil32(tile + t, T.w, xi, eta, smode, wa, wb, u, v);
+        else
+            bil32(rec0 + (__mul24(j, P.pitch) + i), P.pitch, xi, eta, smode, wa, wb, u, v);
         return;
     }
     if constexpr (CUBIC) {
@@ -365,48 +579,10 @@ __device__ __forceinline__ void vel32(const float4 *__restrict__ rec0, const Ste
             weights_bs(xi, wx);
             weights_bs(eta, wy);
         }
-        const float4 *p = rec0 + (__mul24(j - 1, pitch) + (i - 1));
-        if (smode != kBlend) {
-            const int h = smode;   // which half of the record
-            float au = 0.f, av = 0.f;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const float2 *q = reinterpret_cast<const float2 *>(p) + h;
-                float ru = 0.f, rv = 0.f;
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const float2 r = q[2 * a];
-                    ru += wx[a] * r.x;
-                    rv += wx[a] * r.y;
-                }
-                au += wy[b] * ru;
-                av += wy[b] * rv;
-                p += pitch;
-            }
-            u = au;
-            v = av;
-        } else {
-            float au = 0.f, av = 0.f, bu = 0.f, bv = 0.f;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                float ru = 0.f, rv = 0.f, su = 0.f, sv = 0.f;
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const float4 r = p[a];
-                    ru += wx[a] * r.x;
-                    rv += wx[a] * r.y;
-                    su += wx[a] * r.z;
-                    sv += wx[a] * r.w;
-                }
-                au += wy[b] * ru;
-                av += wy[b] * rv;
-                bu += wy[b] * su;
-                bv += wy[b] * sv;
-                p += pitch;
-            }
-            u = wa * au + wb * bu;
-            v = wa * av + wb * bv;
-        }
+        if (tile_index(T, i - 1, j - 1, 4, n, mask, t))
+            cub32(tile + t, T.w, wx, wy, smode, wa, wb, u, v);
+        else
+            cub32(rec0 + (__mul24(j - 1, P.pitch) + (i - 1)), P.pitch, wx, wy, smode, wa, wb, u, v);
     }
 }
 
@@ -428,9 +604,11 @@ __global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32
                                                            double *__restrict__ partials,
                                                            DevClock *clock)
 {
+    float4 *lds = reinterpret_cast<float4 *>(lpt_dyn_lds);
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const SpeciesDev &sp = P.sp[species_of(P, lb)];
-    const int64_t local = (int64_t)(lb - sp.block_begin) * blockDim.x + threadIdx.x;
+    const int64_t base = (int64_t)(lb - sp.block_begin) * blockDim.x;
+    const int64_t local = base + threadIdx.x;
     const bool active = local < sp.count;
     const int64_t p = sp.offset + local;
     const float4 *rec0 = rec + P.pitch + 1;
@@ -440,29 +618,44 @@ __global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32
     const int m0 = P.smode[0], m1 = P.smode[1], m2 = P.smode[2], m3 = P.smode[3];
     double r2x = 0.0, r2y = 0.0;
 
+    uint32_t cell = 0;
+    float2 o = make_float2(0.f, 0.f);
     if (active) {
-        const uint32_t cell = S.cell[p];
-        const float2 o = S.off[p];
-        int cx = (int)(cell & 0xFFFFu), cy = (int)(cell >> 16);
+        cell = S.cell[p];
+        o = S.off[p];
+    }
+    int cx = (int)(cell & 0xFFFFu), cy = (int)(cell >> 16);
+    Tile T = no_tile();
+    if (P.tile_cap > 0) {
+        const uint32_t a = S.cell[sp.offset + base];
+        int lo, hi;
+        stencil_reach(sp.scheme, lo, hi);
+        const int H = step_halo(P, sp.scheme, dt);
+        const int64_t left = sp.count - base;
+        T = stage_tile<float4>(lds, rec0, P, active, cx, cy, (int)(a & 0xFFFFu), (int)(a >> 16),
+                               lo + H, hi + H, (int)(left < (int64_t)blockDim.x ? left : blockDim.x));
+    }
+
+    if (active) {
         float dqx, dqy;
         if (INERTIAL && sp.inertial) {
             const float2 vn = S.vel[p];
             const float is = (float)sp.inv_st;
             float u, v;
             const float V1x = vn.x, V1y = vn.y;
-            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x, o.y, wa0, wb0, m0, u, v);
+            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x, o.y, wa0, wb0, m0, u, v);
             const float A1x = (u - V1x) * is, A1y = (v - V1y) * is;
             const float V2x = vn.x + hdt * A1x, V2y = vn.y + hdt * A1y;
-            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x + hdt * V1x, o.y + hdt * V1y, wa1, wb1, m1,
-                         u, v);
+            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x + hdt * V1x, o.y + hdt * V1y, wa1,
+                         wb1, m1, u, v);
             const float A2x = (u - V2x) * is, A2y = (v - V2y) * is;
             const float V3x = vn.x + hdt * A2x, V3y = vn.y + hdt * A2y;
-            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x + hdt * V2x, o.y + hdt * V2y, wa2, wb2, m2,
-                         u, v);
+            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x + hdt * V2x, o.y + hdt * V2y, wa2,
+                         wb2, m2, u, v);
             const float A3x = (u - V3x) * is, A3y = (v - V3y) * is;
             const float V4x = vn.x + dt * A3x, V4y = vn.y + dt * A3y;
-            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x + dt * V3x, o.y + dt * V3y, wa3, wb3, m3,
-                         u, v);
+            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x + dt * V3x, o.y + dt * V3y, wa3,
+                         wb3, m3, u, v);
             const float A4x = (u - V4x) * is, A4y = (v - V4y) * is;
             dqx = dt6 * (V1x + 2.0f * V2x + 2.0f * V3x + V4x);
             dqy = dt6 * (V1y + 2.0f * V2y + 2.0f * V3y + V4y);
@@ -470,13 +663,13 @@ __global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32
                                    vn.y + dt6 * (A1y + 2.0f * A2y + 2.0f * A3y + A4y));
         } else {
             float k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
-            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x, o.y, wa0, wb0, m0, k1x, k1y);
-            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x + hdt * k1x, o.y + hdt * k1y, wa1, wb1, m1,
-                         k2x, k2y);
-            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x + hdt * k2x, o.y + hdt * k2y, wa2, wb2, m2,
-                         k3x, k3y);
-            vel32<CUBIC>(rec0, P, sp.scheme, cx, cy, o.x + dt * k3x, o.y + dt * k3y, wa3, wb3, m3,
-                         k4x, k4y);
+            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x, o.y, wa0, wb0, m0, k1x, k1y);
+            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x + hdt * k1x, o.y + hdt * k1y, wa1,
+                         wb1, m1, k2x, k2y);
+            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x + hdt * k2x, o.y + hdt * k2y, wa2,
+                         wb2, m2, k3x, k3y);
+            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x + dt * k3x, o.y + dt * k3y, wa3,
+                         wb3, m3, k4x, k4y);
             dqx = dt6 * (k1x + 2.0f * k2x + 2.0f * k3x + k4x);
             dqy = dt6 * (k1y + 2.0f * k2y + 2.0f * k3y + k4y);
         }
@@ -507,7 +700,8 @@ static hipError_t launch64_t(const StepParams &P, const State64 &St, const Rec64
                              double *partials, DevClock *clock, int block, int grid,
                              hipStream_t st)
 {
-    hipLaunchKernelGGL((step64_kernel<C, I, S>), dim3(grid), dim3(block), 0, st, P, St, rec,
+    const size_t lds = P.tile_cap > 0 ? (size_t)P.tile_cap * sizeof(Rec64) : 0;
+    hipLaunchKernelGGL((step64_kernel<C, I, S>), dim3(grid), dim3(block), lds, st, P, St, rec,
                        partials, clock);
     return hipGetLastError();
 }
@@ -517,7 +711,8 @@ static hipError_t launch32_t(const StepParams &P, const State32 &St, const float
                              double *partials, DevClock *clock, int block, int grid,
                              hipStream_t st)
 {
-    hipLaunchKernelGGL((step32_kernel<C, I, S>), dim3(grid), dim3(block), 0, st, P, St, rec,
+    const size_t lds = P.tile_cap > 0 ? (size_t)P.tile_cap * sizeof(float4) : 0;
+    hipLaunchKernelGGL((step32_kernel<C, I, S>), dim3(grid), dim3(block), lds, st, P, St, rec,
                        partials, clock);
     return hipGetLastError();
 }
@@ -550,7 +745,6 @@ hipError_t launch_step32(const StepParams &P, const State32 &S, const float4 *re
 {
     LPT_DISPATCH(launch32_t, P, S, rec, partials, clock, block, grid, st);
 }
-
 // ===========================================================================
 // Statistics: fixed-order reduction of the per-block partial sums into one
 // record per species (Sec. 3.2 and 5.5 quantities).
@@ -667,6 +861,42 @@ hipError_t launch_pack32(float4 *rec, int slot, const double *u, const double *v
     return hipGetLastError();
 }
 
+// Largest |u| or |v| of one time level, times `scale` (to cells per unit
+// time), folded into *out with an unsigned max on the binary32 bit pattern
+// (monotonic for non-negative values).  *out must be zeroed first.  Only the
+// LDS tile halo of the step kernel uses it.
+constexpr int kMaxThreads = 256;
+
+__global__ __launch_bounds__(kMaxThreads) void speed_max_kernel(const double *__restrict__ u,
+                                                                const double *__restrict__ v,
+                                                                int64_t nn, double scale,
+                                                                unsigned *out)
+{
+    __shared__ float red[kMaxThreads / kWave];
+    float m = 0.0f;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nn;
+         k += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, (float)(fmax(fabs(u[k]), fabs(v[k])) * scale));
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x / kWave); ++k) m = fmaxf(m, red[k]);
+        atomicMax(out, __float_as_uint(m));
+    }
+}
+
+hipError_t launch_speed_max(const double *u, const double *v, int64_t nn, double scale,
+                            float *out, hipStream_t st)
+{
+    const int64_t want = (nn + kMaxThreads - 1) / kMaxThreads;
+    const unsigned grid = (unsigned)(want < 1024 ? (want > 0 ? want : 1) : 1024);
+    hipLaunchKernelGGL(speed_max_kernel, dim3(grid), dim3(kMaxThreads), 0, st, u, v, nn, scale,
+                       reinterpret_cast<unsigned *>(out));
+    return hipGetLastError();
+}
+
 // Grid centred differences of psi (eq. particle_velocity_reconstruction with
 // the interpolation moved onto the grid).
 __device__ __forceinline__ int nxt(int i, int n) { return i + 1 == n ? 0 : i + 1; }
@@ -718,7 +948,7 @@ __global__ void init64_kernel(StepParams P, State64 S, const double2 *__restrict
     if (sp.inertial) {
         if (vel_from_field) {
             double u, v;
-            vel64<true>(rec + P.pitch + 1, P, sp.scheme, x.x, x.y, wa, wb, smode_of(wa, wb), u, v);
+            vel64<true>(rec + P.pitch + 1, nullptr, no_tile(), P, sp.scheme, x.x, x.y, wa, wb, smode_of(wa, wb), u, v);
             S.vel[p] = make_double2(u, v);
         } else {
             S.vel[p] = v0[p];
@@ -762,7 +992,7 @@ __global__ void init32_kernel(StepParams P, State32 S, const double2 *__restrict
     if (sp.inertial) {
         if (vel_from_field) {
             float u, v;
-            vel32<true>(rec + P.pitch + 1, P, sp.scheme, cx, cy, ox, oy, (float)wa, (float)wb,
+            vel32<true>(rec + P.pitch + 1, nullptr, no_tile(), P, sp.scheme, cx, cy, ox, oy, (float)wa, (float)wb,
                         smode_of(wa, wb), u, v);
             S.vel[p] = make_float2(u, v);
         } else {
@@ -851,7 +1081,7 @@ __global__ void interp64_kernel(StepParams P, const Rec64 *__restrict__ rec, int
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= npts) return;
     double uu, vv;
-    vel64<true>(rec + P.pitch + 1, P, scheme, x[k], y[k], wa, wb, smode_of(wa, wb), uu, vv);
+    vel64<true>(rec + P.pitch + 1, nullptr, no_tile(), P, scheme, x[k], y[k], wa, wb, smode_of(wa, wb), uu, vv);
     u[k] = uu;
     v[k] = vv;
 }
@@ -868,7 +1098,7 @@ __global__ void interp32_kernel(StepParams P, const float4 *__restrict__ rec, in
     split_of(x[k], P, cx, ox);
     split_of(y[k], P, cy, oy);
     float uu, vv;
-    vel32<true>(rec + P.pitch + 1, P, scheme, cx, cy, ox, oy, (float)wa, (float)wb,
+    vel32<true>(rec + P.pitch + 1, nullptr, no_tile(), P, scheme, cx, cy, ox, oy, (float)wa, (float)wb,
                 smode_of(wa, wb), uu, vv);
     u[k] = (double)uu * P.h;
     v[k] = (double)vv * P.h;

@@ -38,7 +38,7 @@ class LptConfig(C.Structure):
     _fields_ = [
         ("n", C.c_int32), ("precision", C.c_int32), ("length", C.c_double), ("t0", C.c_double),
         ("hip_stream", C.c_void_p), ("sort_interval", C.c_int32), ("sort_tile", C.c_int32),
-        ("block_size", C.c_int32), ("flags", C.c_uint32),
+        ("block_size", C.c_int32), ("flags", C.c_uint32), ("tile_records", C.c_int32),
     ]
 
 
@@ -125,7 +125,8 @@ class Tracker:
     """One liblpt context (see include/lpt.h for the meaning of every call)."""
 
     def __init__(self, n, precision="fp64", length=0.0, t0=0.0, stream=None, sort_interval=0,
-                 sort_tile=0, block_size=0, compat_edge=False, time_kernels=False):
+                 sort_tile=0, block_size=0, compat_edge=False, time_kernels=False,
+                 tile_records=0):
         lib = load()
         cfg = LptConfig()
         cfg.n = n
@@ -136,6 +137,7 @@ class Tracker:
         cfg.sort_interval = sort_interval
         cfg.sort_tile = sort_tile
         cfg.block_size = block_size
+        cfg.tile_records = tile_records
         cfg.flags = (FLAG_COMPAT_EDGE if compat_edge else 0) | (FLAG_TIME_KERNELS if time_kernels else 0)
         h = C.c_void_p()
         st = lib.lpt_create(C.byref(cfg), C.byref(h))

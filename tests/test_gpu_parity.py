@@ -320,6 +320,72 @@ def test_sorting_never_changes_results(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
+def test_lds_tiles_never_change_results(precision):
+    """The step kernel's LDS field tiles are copies of the node records, so
+    per-particle results are bit-identical with tiles off, with the default
+    tile and with a tile too small to hold most blocks' boxes.  One inertial
+    species starts ten times faster than any node, so its stage positions
+    leave the tile halo and exercise the per-lane fallback to global
+    gathers; an even-sized grid and an odd one cover both index wraps."""
+    for n in (256, 200):
+        say(f"lds tiles {precision} n={n}")
+        (ua, va), (ub, vb) = synth.spectrum_snapshots(n, 10, 8, 0.002)
+        outs = []
+        for tile in (-1, 0, 64):
+            tr = lpt.Tracker(n, precision, sort_interval=4, sort_tile=8 if n == 256 else 0,
+                             tile_records=tile)
+            tr.set_time_mode("pingpong")
+            tr.set_snapshot(0, 0.0, ua, va)
+            tr.set_snapshot(1, 0.002, ub, vb)
+            z = np.zeros(30000)
+            fast = np.full(5000, 40.0)
+            sids = [tr.add_species("tracer", 0.0, sch, z, z) for sch in SCHEMES]
+            sids.append(tr.add_species("inertial", 0.3, "catmull_rom", z[:9000], z[:9000]))
+            sids.append(tr.add_species("inertial", 0.05, "bilinear", z[:5000], z[:5000],
+                                       fast, -fast))
+            for k, sid in enumerate(sids):
+                tr.init_uniform(sid, 100 + k)
+            tr.step(13, 0.002, stats_every=13)
+            outs.append([tr.get_positions(s) for s in sids] +
+                        [tr.get_velocities(s) for s in sids[3:]] +
+                        [tr.get_stats(s)["msd"] for s in sids])
+            tr.close()
+        for other in outs[1:]:
+            for a, b in zip(outs[0], other):
+                for qa, qb in zip(a, b):
+                    np.testing.assert_array_equal(qa, qb)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_tile_escapees_match_oracle(scheme):
+    """FP64 inertial particles launched far faster than the flow leave the
+    LDS tile during their stages; their trajectories still match the oracle
+    within 1e-10 after 10 steps."""
+    say(f"tile escapees {scheme}")
+    n, dt, count = 128, 0.002, 6000
+    (ua, va), (ub, vb) = synth.spectrum_snapshots(n, 6, 9, dt)
+    x0, y0 = oracle.init_uniform(77, count)
+    rng = np.random.default_rng(5)
+    vx0 = rng.normal(0.0, 30.0, count)
+    vy0 = rng.normal(0.0, 30.0, count)
+    tr = lpt.Tracker(n, "fp64", sort_interval=2, sort_tile=8)
+    tr.set_time_mode("pingpong")
+    tr.set_snapshot(0, 0.0, ua, va)
+    tr.set_snapshot(1, dt, ub, vb)
+    sid = tr.add_species("inertial", 0.02, scheme, x0, y0, vx0, vy0)
+    tr.step(10, dt)
+    xw, yw, xu, yu = tr.get_positions(sid)
+    vx, vy = tr.get_velocities(sid)
+    tr.close()
+    fl = oracle.grid_flow(ua, va, ub, vb, scheme=scheme, time_mode=oracle.PINGPONG)
+    sp = oracle.Species(x0, y0, kind=oracle.INERTIAL, st=0.02, vx0=vx0, vy0=vy0)
+    oracle.run(fl, sp, 10, dt)
+    assert np.max(pdist(xw, sp.xw)) < 1e-10 and np.max(pdist(yw, sp.yw)) < 1e-10
+    assert np.max(np.abs(xu - (x0 + sp.dx))) < 1e-10
+    assert np.max(np.abs(vx - sp.vx)) < 1e-8 and np.max(np.abs(vy - sp.vy)) < 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
 def test_sort_produces_stable_tile_order(precision):
     """Right after initialisation (slots in original order), lpt_sort leaves
     the slots in the stable argsort order of the cell-tile keys of the
