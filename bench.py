@@ -18,6 +18,7 @@ events on the stream it runs on, against the 8 TB/s HBM peak.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -54,13 +55,13 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def run_gpu(w, steps, warmup, lpt):
+def run_gpu(w, steps, warmup, lpt, **over):
     import torch
     tr = None
     try:
         from paper_2607_17836_amd import workloads
         t0 = time.perf_counter()
-        tr = workloads.build_tracker(w, lpt, time_kernels=True)
+        tr = workloads.build_tracker(w, lpt, time_kernels=True, **over)
         tr.synchronize()
         log(f"[bench] setup of {w.name}: {time.perf_counter() - t0:.1f} s")
         tr.step(warmup, w.dt, w.stats_every)
@@ -111,6 +112,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--tile-records", type=int, default=0,
+                    help="LDS tile capacity of the step kernel (0 default, -1 off)")
+    ap.add_argument("--block-size", type=int, default=0, help="step-kernel block size (0 default)")
+    ap.add_argument("--sort-interval", type=int, default=None,
+                    help="steps between cell-order re-sorts (default: the workload's)")
     ap.add_argument("--bw-probe", action="store_true",
                     help="only run the copy/triad bandwidth probe and print its JSON")
     args = ap.parse_args()
@@ -130,8 +136,11 @@ def main():
                           "bytes_per_buffer": 1 << 30, "iters": 10}), flush=True)
         return
     w = workloads.C3_SPLIT
+    if args.sort_interval is not None:
+        w = dataclasses.replace(w, sort_interval=args.sort_interval)
+    over = dict(tile_records=args.tile_records, block_size=args.block_size)
     npart = w.particles
-    elapsed, timing, nstats = run_gpu(w, args.steps, args.warmup, lpt)
+    elapsed, timing, nstats = run_gpu(w, args.steps, args.warmup, lpt, **over)
     value = npart * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
     kern_ms = timing["step_kernel_ms"] / max(1, timing["step_launches"])
@@ -153,7 +162,7 @@ def main():
                                  w.field_seed, w.dt, w.time_mode, w.steps, w.stats_every,
                                  w.sort_interval, w.sort_tile, w.species)
         k64 = max(100, args.steps // 4)
-        e64, t64, _ = run_gpu(w64, k64, min(args.warmup, 20), lpt)
+        e64, t64, _ = run_gpu(w64, k64, min(args.warmup, 20), lpt, **over)
         extra["fp64_same_workload"] = {
             "value": npart * k64 / e64, "unit": "particle-steps/s", "steps": k64,
             "step_kernel_us": 1e3 * t64["step_kernel_ms"] / max(1, t64["step_launches"])}
@@ -167,7 +176,8 @@ def main():
         "config": {"workload": w.name, "grid": w.n, "particles": npart, "precision": w.precision,
                    "scheme": "bilinear", "dt": w.dt, "time_mode": w.time_mode,
                    "sort_interval": w.sort_interval, "sort_tile": w.sort_tile,
-                   "stats_every": w.stats_every, "parallelism": "1 GPU"},
+                   "stats_every": w.stats_every, "tile_records": args.tile_records,
+                   "block_size": args.block_size, "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "step32_kernel<bilinear, tracer>",

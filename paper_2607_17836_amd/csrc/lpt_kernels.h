@@ -52,6 +52,11 @@ struct StepParams {
     double dt;
     double wa[4], wb[4];   // temporal weights of slot 0 / slot 1 per RK4 stage
     int32_t smode[4];      // SlotMode per RK4 stage
+    // binary32 copies for the FP32-split kernel, rounded once on the host
+    float dtf, hdtf, dt6f; // dt, dt/2, dt/6
+    float waf[4], wbf[4];
+    int32_t ends_one;      // stages 1 and 4 read one level each: h0 and h3
+    int32_t h0, h3;
     int32_t tile_cap;      // LDS tile capacity in node records (0: no tile)
     const float *umax;     // device: largest node speed of slot 0 / 1, cells per unit time
     SpeciesDev sp[kMaxSpecies];
@@ -103,8 +108,9 @@ hipError_t launch_psi_to_velocity(const double *psi, double *u, double *v, int n
 hipError_t launch_step64(const StepParams &P, const State64 &S, const Rec64 *rec,
                          double *partials, DevClock *clock, bool stats, bool cubic,
                          bool inertial, int block, int grid, hipStream_t st);
+// schemes: the scheme shared by every species, or 3 if they differ.
 hipError_t launch_step32(const StepParams &P, const State32 &S, const float4 *rec,
-                         double *partials, DevClock *clock, bool stats, bool cubic,
+                         double *partials, DevClock *clock, bool stats, int schemes,
                          bool inertial, int block, int grid, hipStream_t st);
 
 hipError_t launch_finalize(const StepParams &P, const double *partials, DevClock *clock,

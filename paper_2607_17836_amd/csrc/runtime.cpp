@@ -215,6 +215,15 @@ int32_t slot_mode(double wa, double wb)
     return kBlend;
 }
 
+// The scheme every species uses, or 3 if they differ.
+int common_scheme(const lpt_ctx *c)
+{
+    int s = c->sp.empty() ? 0 : c->sp[0].scheme;
+    for (const SpeciesHost &h : c->sp)
+        if (h.scheme != s) return 3;
+    return s;
+}
+
 int species_bits(const lpt_ctx *c) { return c->sp.size() > 1 ? ilog2i((int64_t)c->sp.size()) : 0; }
 int tile_bits(const lpt_ctx *c) { return 2 * ilog2i(c->n / c->sort_tile); }
 
@@ -713,6 +722,9 @@ lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
     }
     StepParams P = make_params(c);
     P.dt = dt;
+    P.dtf = (float)dt;
+    P.hdtf = (float)(0.5 * dt);
+    P.dt6f = (float)(dt / 6.0);
     const double stage_c[4] = {0.0, 0.5, 0.5, 1.0};
     for (int64_t k = 0; k < nsteps; ++k) {
         if (c->sort_interval > 0 && c->steps % c->sort_interval == 0) {
@@ -722,7 +734,12 @@ lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
         for (int q = 0; q < 4; ++q) {
             weights_at(c, c->steps, c->t, c->t + stage_c[q] * dt, dt, P.wa[q], P.wb[q]);
             P.smode[q] = slot_mode(P.wa[q], P.wb[q]);
+            P.waf[q] = (float)P.wa[q];
+            P.wbf[q] = (float)P.wb[q];
         }
+        P.ends_one = P.smode[0] != kBlend && P.smode[3] != kBlend;
+        P.h0 = P.smode[0] == kSlot1 ? 1 : 0;
+        P.h3 = P.smode[3] == kSlot1 ? 1 : 0;
         const bool rec = stats_every > 0 && (c->steps + 1) % stats_every == 0;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->time_kernels) HIP_TRY(c, mark(c, e0));
@@ -732,8 +749,8 @@ lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
                                      c->block, P.total_blocks, c->stream));
         else
             HIP_TRY(c, launch_step32(P, c->s32[c->cur], static_cast<const float4 *>(c->rec),
-                                     c->partials, c->clock, rec, c->has_cubic, c->has_inertial,
-                                     c->block, P.total_blocks, c->stream));
+                                     c->partials, c->clock, rec, common_scheme(c),
+                                     c->has_inertial, c->block, P.total_blocks, c->stream));
         if (c->time_kernels) {
             HIP_TRY(c, mark(c, e1));
             c->ev_step.emplace_back(e0, e1);

@@ -155,49 +155,80 @@ __device__ __forceinline__ int step_halo(const StepParams &P, int scheme, float 
     return d > 0.0f ? (int)ceilf(d) : 0;
 }
 
+// Wave-wide maximum of two packed unsigned 16-bit lanes by DPP: four row
+// shifts reduce each 16-lane row, two row broadcasts combine the rows, and
+// lane 63 ends with the result.  Lanes outside a shift read 0, the identity.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pmax16(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                  __builtin_bit_cast(u16x2, b)));
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_pmax(uint32_t x)
+{
+    return pmax16(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, true));
+}
+
+__device__ __forceinline__ uint32_t wave_pmax16(uint32_t x)
+{
+    x = dpp_pmax<0x111, 0xF>(x);   // row_shr:1
+    x = dpp_pmax<0x112, 0xF>(x);   // row_shr:2
+    x = dpp_pmax<0x114, 0xF>(x);   // row_shr:4
+    x = dpp_pmax<0x118, 0xF>(x);   // row_shr:8
+    x = dpp_pmax<0x142, 0xA>(x);   // row_bcast:15
+    x = dpp_pmax<0x143, 0xC>(x);   // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Rows of the tile one wave loads before it writes any of them to LDS, so
+// that their global-memory latencies overlap.
+template <typename Rec>
+constexpr int fill_rows()
+{
+    return sizeof(Rec) <= 16 ? 8 : 4;
+}
+
 // Cooperative tile set-up of one block (all threads must call it).
 // (cx, cy): the thread's stored cell (ignored when !active); (ax, ay): the
-// stored cell of the block's first particle, which is always active.
+// stored cell of the block's first particle, which is always active.  The
+// box is reduced on cell offsets from (ax, ay), biased by 2^15 and packed
+// two per word, as maxima of (r + 2^15) and (2^15 - r).
 template <typename Rec>
 __device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec0,
                                           const StepParams &P, bool active, int cx, int cy,
                                           int ax, int ay, int lo, int hi, int nactive)
 {
-    __shared__ int red[4][kMaxBlock / kWave];
+    __shared__ uint32_t red[2][kMaxBlock / kWave];
+    constexpr int kBias = 1 << 15;
     const int n = P.n, mask = P.mask, half = n >> 1;
     int rx = 0, ry = 0;
-    if (active) {
-        rx = wrap_cell(cx - ax, n, mask);
-        ry = wrap_cell(cy - ay, n, mask);
-        if (rx > half) rx -= n;
-        if (ry > half) ry -= n;
+    if (active) {   // cx - ax lies in (-n, n): map it to (-n/2, n/2]
+        rx = cx - ax;
+        ry = cy - ay;
+        rx += rx < -half ? n : (rx > half ? -n : 0);
+        ry += ry < -half ? n : (ry > half ? -n : 0);
     }
-    int mnx = rx, mxx = rx, mny = ry, mxy = ry;
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        mnx = min(mnx, __shfl_xor(mnx, off, kWave));
-        mxx = max(mxx, __shfl_xor(mxx, off, kWave));
-        mny = min(mny, __shfl_xor(mny, off, kWave));
-        mxy = max(mxy, __shfl_xor(mxy, off, kWave));
-    }
+    uint32_t up = (uint32_t)(rx + kBias) | ((uint32_t)(ry + kBias) << 16);
+    uint32_t dn = (uint32_t)(kBias - rx) | ((uint32_t)(kBias - ry) << 16);
+    up = wave_pmax16(up);
+    dn = wave_pmax16(dn);
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     if (lane == 0) {
-        red[0][wv] = mnx;
-        red[1][wv] = mxx;
-        red[2][wv] = mny;
-        red[3][wv] = mxy;
+        red[0][wv] = up;
+        red[1][wv] = dn;
     }
     __syncthreads();
-    mnx = red[0][0];
-    mxx = red[1][0];
-    mny = red[2][0];
-    mxy = red[3][0];
+    up = red[0][0];
+    dn = red[1][0];
     for (int k = 1; k < nw; ++k) {
-        mnx = min(mnx, red[0][k]);
-        mxx = max(mxx, red[1][k]);
-        mny = min(mny, red[2][k]);
-        mxy = max(mxy, red[3][k]);
+        up = pmax16(up, red[0][k]);
+        dn = pmax16(dn, red[1][k]);
     }
+    const int mxx = (int)(up & 0xFFFFu) - kBias, mxy = (int)(up >> 16) - kBias;
+    const int mnx = kBias - (int)(dn & 0xFFFFu), mny = kBias - (int)(dn >> 16);
     Tile T;
     T.w = mxx - mnx + 1 + lo + hi;
     T.h = mxy - mny + 1 + lo + hi;
@@ -207,10 +238,28 @@ __device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec
     T.on = P.tile_cap > 0 && area <= P.tile_cap && T.w < n && T.h < n &&
            area <= kTileWaste * nactive;
     if (T.on) {
-        for (int r = wv; r < T.h; r += nw) {
-            const Rec *row = rec0 + (int64_t)wrap_cell(T.y0 + r, n, mask) * P.pitch;
-            Rec *dst = lds + r * T.w;
-            for (int c = lane; c < T.w; c += kWave) dst[c] = row[wrap_cell(T.x0 + c, n, mask)];
+        // Every load of a group is issued before any LDS write, so their
+        // latencies overlap.  Rows past the tile are clamped to its last
+        // row: they re-read it and rewrite the same values.  T.x0 + c and
+        // T.y0 + r lie in [0, 2n): one conditional subtraction wraps them.
+        constexpr int R = fill_rows<Rec>();
+        const int w0 = __builtin_amdgcn_readfirstlane(wv);   // wave-uniform row start
+        for (int c = lane; c < T.w; c += kWave) {
+            int gx = T.x0 + c;
+            gx -= gx >= n ? n : 0;
+            const Rec *src = rec0 + gx;
+            Rec *dst = lds + c;
+            for (int r0 = w0; r0 < T.h; r0 += R * nw) {
+                Rec buf[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    int gy = T.y0 + min(r0 + k * nw, T.h - 1);
+                    gy -= gy >= n ? n : 0;
+                    buf[k] = src[__mul24(gy, P.pitch)];
+                }
+#pragma unroll
+                for (int k = 0; k < R; ++k) dst[__mul24(min(r0 + k * nw, T.h - 1), T.w)] = buf[k];
+            }
         }
     }
     __syncthreads();
@@ -598,7 +647,172 @@ __device__ __forceinline__ void advance_split(int &c, float &o, float dq, const 
     o = r;
 }
 
-template <bool CUBIC, bool INERTIAL, bool STATS>
+// ---------------------------------------------------------------------------
+// The FP32-split step, specialised per block on (scheme, particle kind).
+// Stage positions are kept relative to the particle's stored cell: the stage
+// cell is (cx + floor(qx), cy + floor(qy)) and, inside the LDS tile, its tile
+// coordinate is (rx + floor(qx), ry + floor(qy)) with (rx, ry) the stored
+// cell's tile coordinate, computed once per particle.  Only a stencil that
+// leaves the tile needs the periodic wrap and a global gather.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrapn(int c, const StepParams &P)
+{
+    return wrap_cell(c, P.n, P.mask);
+}
+
+// Node records of one stencil row / column combination, evaluated from the
+// records starting at p with row pitch `pitch`.  ONE: read the half `h` of
+// each record (temporal weight (1, 0) or (0, 1)); else blend both halves
+// with (wa, wb).
+template <int SCH>
+__device__ __forceinline__ void eval32(const float4 *p, int pitch, float xi, float eta, bool one,
+                                       int h, float wa, float wb, float &u, float &v)
+{
+    if constexpr (SCH == kBilinear) {
+        float w00, w10, w01, w11;
+        bilinear_weights(xi, eta, w00, w10, w01, w11);
+        if (one) {
+            const float2 *q = reinterpret_cast<const float2 *>(p) + h;
+            const float2 a = q[0], b = q[2], c = q[2 * pitch], d = q[2 * pitch + 2];
+            u = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
+            v = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
+        } else {
+            const float4 a = p[0], b = p[1], c = p[pitch], d = p[pitch + 1];
+            const float ua = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
+            const float va = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
+            const float ub = w00 * a.z + w10 * b.z + w01 * c.z + w11 * d.z;
+            const float vb = w00 * a.w + w10 * b.w + w01 * c.w + w11 * d.w;
+            u = wa * ua + wb * ub;
+            v = wa * va + wb * vb;
+        }
+    } else {
+        float wx[4], wy[4];
+        if constexpr (SCH == kCatmullRom) {
+            weights_cr(xi, wx);
+            weights_cr(eta, wy);
+        } else {
+            weights_bs(xi, wx);
+            weights_bs(eta, wy);
+        }
+        cub32(p, pitch, wx, wy, one ? h : kBlend, wa, wb, u, v);
+    }
+}
+
+// Fluid velocity (cells per unit time) of one RK4 stage at stored cell
+// (cx, cy) + q.  (rx, ry): tile coordinate of the stored cell.
+template <int SCH>
+__device__ __forceinline__ void stage32(const float4 *__restrict__ rec0, const float4 *lds,
+                                        const Tile &T, const StepParams &P, int cx, int cy,
+                                        int rx, int ry, float qx, float qy, bool one, int h,
+                                        float wa, float wb, float &u, float &v)
+{
+    constexpr int c1 = SCH == kBilinear ? 0 : 1;
+    constexpr int span = SCH == kBilinear ? 2 : 4;
+    qx = __builtin_amdgcn_fmed3f(qx, -kCellClampF, kCellClampF);
+    qy = __builtin_amdgcn_fmed3f(qy, -kCellClampF, kCellClampF);
+    const float flx = floorf(qx), fly = floorf(qy);
+    const int fx = (int)flx, fy = (int)fly;
+    const float xi = qx - flx, eta = qy - fly;
+    if constexpr (SCH != kBilinear) {
+        if (P.compat_edge) {   // the paper's bilinear fallback near the grid edge
+            const int i = wrapn(cx + fx, P), j = wrapn(cy + fy, P);
+            if (edge_cell(1, i, j, P.n)) {
+                eval32<kBilinear>(rec0 + (__mul24(j, P.pitch) + i), P.pitch, xi, eta, one, h, wa,
+                                  wb, u, v);
+                return;
+            }
+        }
+    }
+    const int tx = rx + fx - c1, ty = ry + fy - c1;
+    if (T.on && (unsigned)tx <= (unsigned)(T.w - span) && (unsigned)ty <= (unsigned)(T.h - span)) {
+        eval32<SCH>(lds + (__mul24(ty, T.w) + tx), T.w, xi, eta, one, h, wa, wb, u, v);
+    } else {
+        const int i = wrapn(cx + fx, P) - c1, j = wrapn(cy + fy, P) - c1;
+        eval32<SCH>(rec0 + (__mul24(j, P.pitch) + i), P.pitch, xi, eta, one, h, wa, wb, u, v);
+    }
+}
+
+// One RK4 step of one particle (eqs. rk4_update / rk4_inertial, Stokes drag
+// of eq. drag_rk4), then the split-position update and the FP64
+// displacement.  Returns the new displacement squared per axis.
+template <int SCH, bool INERT>
+__device__ __forceinline__ void particle32(const StepParams &P, const State32 &S,
+                                           const float4 *__restrict__ rec0, const float4 *lds,
+                                           const Tile &T, const SpeciesDev &sp, int64_t p,
+                                           uint32_t cell, float2 o, double &r2x, double &r2y)
+{
+    int cx = (int)(cell & 0xFFFFu), cy = (int)(cell >> 16);
+    int rx = 0, ry = 0;
+    if (T.on) {   // cx - T.x0 lies in (-n, n)
+        rx = cx - T.x0;
+        ry = cy - T.y0;
+        rx += rx < 0 ? P.n : 0;
+        ry += ry < 0 ? P.n : 0;
+    }
+    const float dt = P.dtf, hdt = P.hdtf, dt6 = P.dt6f;
+    const bool one = P.ends_one != 0;   // first / last stage read a single time level
+    float dqx, dqy;
+    if constexpr (INERT) {
+        const float2 vn = S.vel[p];
+        const float is = (float)sp.inv_st;
+        float u, v;
+        const float V1x = vn.x, V1y = vn.y;
+        stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x, o.y, one, P.h0, P.waf[0], P.wbf[0], u, v);
+        const float A1x = (u - V1x) * is, A1y = (v - V1y) * is;
+        const float V2x = vn.x + hdt * A1x, V2y = vn.y + hdt * A1y;
+        stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x + hdt * V1x, o.y + hdt * V1y, false, 0,
+                     P.waf[1], P.wbf[1], u, v);
+        const float A2x = (u - V2x) * is, A2y = (v - V2y) * is;
+        const float V3x = vn.x + hdt * A2x, V3y = vn.y + hdt * A2y;
+        stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x + hdt * V2x, o.y + hdt * V2y, false, 0,
+                     P.waf[2], P.wbf[2], u, v);
+        const float A3x = (u - V3x) * is, A3y = (v - V3y) * is;
+        const float V4x = vn.x + dt * A3x, V4y = vn.y + dt * A3y;
+        stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x + dt * V3x, o.y + dt * V3y, one, P.h3,
+                     P.waf[3], P.wbf[3], u, v);
+        const float A4x = (u - V4x) * is, A4y = (v - V4y) * is;
+        dqx = dt6 * (V1x + 2.0f * V2x + 2.0f * V3x + V4x);
+        dqy = dt6 * (V1y + 2.0f * V2y + 2.0f * V3y + V4y);
+        S.vel[p] = make_float2(vn.x + dt6 * (A1x + 2.0f * A2x + 2.0f * A3x + A4x),
+                               vn.y + dt6 * (A1y + 2.0f * A2y + 2.0f * A3y + A4y));
+    } else {
+        float k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
+        stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x, o.y, one, P.h0, P.waf[0], P.wbf[0],
+                     k1x, k1y);
+        stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x + hdt * k1x, o.y + hdt * k1y, false, 0,
+                     P.waf[1], P.wbf[1], k2x, k2y);
+        stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x + hdt * k2x, o.y + hdt * k2y, false, 0,
+                     P.waf[2], P.wbf[2], k3x, k3y);
+        stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x + dt * k3x, o.y + dt * k3y, one, P.h3,
+                     P.waf[3], P.wbf[3], k4x, k4y);
+        dqx = dt6 * (k1x + 2.0f * k2x + 2.0f * k3x + k4x);
+        dqy = dt6 * (k1y + 2.0f * k2y + 2.0f * k3y + k4y);
+    }
+    float ox = o.x, oy = o.y;
+    advance_split(cx, ox, dqx, P);
+    advance_split(cy, oy, dqy, P);
+    double2 d = S.disp[p];
+    S.cell[p] = (uint32_t)cx | ((uint32_t)cy << 16);
+    S.off[p] = make_float2(ox, oy);
+    d.x += (double)dqx * P.h;
+    d.y += (double)dqy * P.h;
+    S.disp[p] = d;
+    r2x = d.x * d.x;
+    r2y = d.y * d.y;
+}
+
+// SCHS: kBilinear / kCatmullRom / kBSpline when every species of the launch
+// uses that scheme, kAnyScheme otherwise.  KINDS: 0 tracers only (St == 0
+// included), 1 tracers and/or inertial species.
+constexpr int kAnyScheme = 3;
+
+template <int SCH, int SCHS>
+constexpr bool scheme_compiled()
+{
+    return SCHS == kAnyScheme || SCHS == SCH;
+}
+
+template <int SCHS, int KINDS, bool STATS>
 __global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32 S,
                                                            const float4 *__restrict__ rec,
                                                            double *__restrict__ partials,
@@ -606,16 +820,12 @@ __global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32
 {
     float4 *lds = reinterpret_cast<float4 *>(lpt_dyn_lds);
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const SpeciesDev &sp = P.sp[species_of(P, lb)];
+    const SpeciesDev &sp = P.sp[P.nspecies > 1 ? species_of(P, lb) : 0];
     const int64_t base = (int64_t)(lb - sp.block_begin) * blockDim.x;
     const int64_t local = base + threadIdx.x;
     const bool active = local < sp.count;
     const int64_t p = sp.offset + local;
     const float4 *rec0 = rec + P.pitch + 1;
-    const float dt = (float)P.dt, hdt = (float)(0.5 * P.dt), dt6 = (float)(P.dt / 6.0);
-    const float wa0 = (float)P.wa[0], wa1 = (float)P.wa[1], wa2 = (float)P.wa[2], wa3 = (float)P.wa[3];
-    const float wb0 = (float)P.wb[0], wb1 = (float)P.wb[1], wb2 = (float)P.wb[2], wb3 = (float)P.wb[3];
-    const int m0 = P.smode[0], m1 = P.smode[1], m2 = P.smode[2], m3 = P.smode[3];
     double r2x = 0.0, r2y = 0.0;
 
     uint32_t cell = 0;
@@ -624,66 +834,36 @@ __global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32
         cell = S.cell[p];
         o = S.off[p];
     }
-    int cx = (int)(cell & 0xFFFFu), cy = (int)(cell >> 16);
     Tile T = no_tile();
     if (P.tile_cap > 0) {
         const uint32_t a = S.cell[sp.offset + base];
         int lo, hi;
         stencil_reach(sp.scheme, lo, hi);
-        const int H = step_halo(P, sp.scheme, dt);
+        const int H = step_halo(P, sp.scheme, P.dtf);
         const int64_t left = sp.count - base;
-        T = stage_tile<float4>(lds, rec0, P, active, cx, cy, (int)(a & 0xFFFFu), (int)(a >> 16),
-                               lo + H, hi + H, (int)(left < (int64_t)blockDim.x ? left : blockDim.x));
+        T = stage_tile<float4>(lds, rec0, P, active, (int)(cell & 0xFFFFu), (int)(cell >> 16),
+                               (int)(a & 0xFFFFu), (int)(a >> 16), lo + H, hi + H,
+                               (int)(left < (int64_t)blockDim.x ? left : blockDim.x));
     }
-
     if (active) {
-        float dqx, dqy;
-        if (INERTIAL && sp.inertial) {
-            const float2 vn = S.vel[p];
-            const float is = (float)sp.inv_st;
-            float u, v;
-            const float V1x = vn.x, V1y = vn.y;
-            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x, o.y, wa0, wb0, m0, u, v);
-            const float A1x = (u - V1x) * is, A1y = (v - V1y) * is;
-            const float V2x = vn.x + hdt * A1x, V2y = vn.y + hdt * A1y;
-            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x + hdt * V1x, o.y + hdt * V1y, wa1,
-                         wb1, m1, u, v);
-            const float A2x = (u - V2x) * is, A2y = (v - V2y) * is;
-            const float V3x = vn.x + hdt * A2x, V3y = vn.y + hdt * A2y;
-            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x + hdt * V2x, o.y + hdt * V2y, wa2,
-                         wb2, m2, u, v);
-            const float A3x = (u - V3x) * is, A3y = (v - V3y) * is;
-            const float V4x = vn.x + dt * A3x, V4y = vn.y + dt * A3y;
-            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x + dt * V3x, o.y + dt * V3y, wa3,
-                         wb3, m3, u, v);
-            const float A4x = (u - V4x) * is, A4y = (v - V4y) * is;
-            dqx = dt6 * (V1x + 2.0f * V2x + 2.0f * V3x + V4x);
-            dqy = dt6 * (V1y + 2.0f * V2y + 2.0f * V3y + V4y);
-            S.vel[p] = make_float2(vn.x + dt6 * (A1x + 2.0f * A2x + 2.0f * A3x + A4x),
-                                   vn.y + dt6 * (A1y + 2.0f * A2y + 2.0f * A3y + A4y));
-        } else {
-            float k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
-            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x, o.y, wa0, wb0, m0, k1x, k1y);
-            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x + hdt * k1x, o.y + hdt * k1y, wa1,
-                         wb1, m1, k2x, k2y);
-            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x + hdt * k2x, o.y + hdt * k2y, wa2,
-                         wb2, m2, k3x, k3y);
-            vel32<CUBIC>(rec0, lds, T, P, sp.scheme, cx, cy, o.x + dt * k3x, o.y + dt * k3y, wa3,
-                         wb3, m3, k4x, k4y);
-            dqx = dt6 * (k1x + 2.0f * k2x + 2.0f * k3x + k4x);
-            dqy = dt6 * (k1y + 2.0f * k2y + 2.0f * k3y + k4y);
+        const bool inert = KINDS != 0 && sp.inertial;
+        if (scheme_compiled<kBilinear, SCHS>() && (SCHS != kAnyScheme || sp.scheme == kBilinear)) {
+            if (KINDS != 0 && inert)
+                particle32<kBilinear, KINDS != 0>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+            else
+                particle32<kBilinear, false>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+        } else if (scheme_compiled<kCatmullRom, SCHS>() &&
+                   (SCHS != kAnyScheme || sp.scheme == kCatmullRom)) {
+            if (KINDS != 0 && inert)
+                particle32<kCatmullRom, KINDS != 0>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+            else
+                particle32<kCatmullRom, false>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+        } else if (scheme_compiled<kBSpline, SCHS>()) {
+            if (KINDS != 0 && inert)
+                particle32<kBSpline, KINDS != 0>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+            else
+                particle32<kBSpline, false>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
         }
-        float ox = o.x, oy = o.y;
-        advance_split(cx, ox, dqx, P);
-        advance_split(cy, oy, dqy, P);
-        double2 d = S.disp[p];
-        S.cell[p] = (uint32_t)cx | ((uint32_t)cy << 16);
-        S.off[p] = make_float2(ox, oy);
-        d.x += (double)dqx * P.h;
-        d.y += (double)dqy * P.h;
-        S.disp[p] = d;
-        r2x = d.x * d.x;
-        r2y = d.y * d.y;
     }
     if (STATS) {
         const double r2 = r2x + r2y;
@@ -706,15 +886,27 @@ static hipError_t launch64_t(const StepParams &P, const State64 &St, const Rec64
     return hipGetLastError();
 }
 
-template <bool C, bool I, bool S>
+template <int SCHS, int KINDS, bool ST>
 static hipError_t launch32_t(const StepParams &P, const State32 &St, const float4 *rec,
                              double *partials, DevClock *clock, int block, int grid,
                              hipStream_t st)
 {
     const size_t lds = P.tile_cap > 0 ? (size_t)P.tile_cap * sizeof(float4) : 0;
-    hipLaunchKernelGGL((step32_kernel<C, I, S>), dim3(grid), dim3(block), lds, st, P, St, rec,
-                       partials, clock);
+    hipLaunchKernelGGL((step32_kernel<SCHS, KINDS, ST>), dim3(grid), dim3(block), lds, st, P, St,
+                       rec, partials, clock);
     return hipGetLastError();
+}
+
+template <int SCHS>
+static hipError_t launch32_s(const StepParams &P, const State32 &S, const float4 *rec,
+                             double *partials, DevClock *clock, bool stats, bool inertial,
+                             int block, int grid, hipStream_t st)
+{
+    if (inertial)
+        return stats ? launch32_t<SCHS, 1, true>(P, S, rec, partials, clock, block, grid, st)
+                     : launch32_t<SCHS, 1, false>(P, S, rec, partials, clock, block, grid, st);
+    return stats ? launch32_t<SCHS, 0, true>(P, S, rec, partials, clock, block, grid, st)
+                 : launch32_t<SCHS, 0, false>(P, S, rec, partials, clock, block, grid, st);
 }
 
 #define LPT_DISPATCH(fn, ...)                                                        \
@@ -740,10 +932,19 @@ hipError_t launch_step64(const StepParams &P, const State64 &S, const Rec64 *rec
 }
 
 hipError_t launch_step32(const StepParams &P, const State32 &S, const float4 *rec,
-                         double *partials, DevClock *clock, bool stats, bool cubic,
+                         double *partials, DevClock *clock, bool stats, int schemes,
                          bool inertial, int block, int grid, hipStream_t st)
 {
-    LPT_DISPATCH(launch32_t, P, S, rec, partials, clock, block, grid, st);
+    switch (schemes) {
+    case kBilinear:
+        return launch32_s<kBilinear>(P, S, rec, partials, clock, stats, inertial, block, grid, st);
+    case kCatmullRom:
+        return launch32_s<kCatmullRom>(P, S, rec, partials, clock, stats, inertial, block, grid, st);
+    case kBSpline:
+        return launch32_s<kBSpline>(P, S, rec, partials, clock, stats, inertial, block, grid, st);
+    default:
+        return launch32_s<kAnyScheme>(P, S, rec, partials, clock, stats, inertial, block, grid, st);
+    }
 }
 // ===========================================================================
 // Statistics: fixed-order reduction of the per-block partial sums into one
