@@ -81,6 +81,15 @@ def lib():
         L.orc_init_uniform.argtypes = [C.c_uint64, C.c_int64, C.c_double, dp, dp]
         L.orc_cell_keys.restype = None
         L.orc_cell_keys.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int64, ip, ip, ip]
+        L.orc_interp_grad.restype = None
+        L.orc_interp_grad.argtypes = [dp, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_double,
+                                      C.c_double, dp, dp, dp]
+        L.orc_tangent_run.restype = None
+        L.orc_tangent_run.argtypes = [C.POINTER(Flow), C.c_int64, dp, dp, dp, dp, dp, C.c_int64,
+                                      C.c_double, C.c_double, C.c_int64]
+        L.orc_adjoint_run.restype = None
+        L.orc_adjoint_run.argtypes = [C.POINTER(Flow), C.c_int64, dp, dp, dp, dp, C.c_int64,
+                                      C.c_double, C.c_double, C.c_int64, dp, dp, dp, dp]
         L.orc_cells_of.restype = None
         L.orc_cells_of.argtypes = [C.c_int32, C.c_double, C.c_int64, dp, ip]
         _lib = L
@@ -259,3 +268,50 @@ def cells_of(n, x, length=2 * np.pi):
 def sort_permutation(keys):
     """Stable ascending order of the keys (library primitive)."""
     return np.argsort(np.asarray(keys), kind="stable")
+
+
+# -- derivatives of the discrete map (tracers) -------------------------------
+
+def interp_grad(f, x, y, scheme=BILINEAR, length=2 * np.pi, compat_edge=0):
+    """(value, d/dx, d/dy) of one interpolated grid field at one point."""
+    if isinstance(scheme, str):
+        scheme = SCHEMES[scheme]
+    f = _f64(f)
+    out = np.zeros(3)
+    o = out.ctypes.data
+    lib().orc_interp_grad(_ptr(f), f.shape[-1], length, scheme, compat_edge, float(x), float(y),
+                          C.c_void_p(o), C.c_void_p(o + 8), C.c_void_p(o + 16))
+    return out[0], out[1], out[2]
+
+
+def tangent(flow: FlowSpec, sp: Species, nsteps, dt, t_start=0.0, step0=0):
+    """Advance a tracer species in place and return F = dx_T/dx_0 [np, 2, 2]
+    by forward tangent propagation."""
+    F = np.zeros((sp.n, 2, 2))
+    F[:, 0, 0] = F[:, 1, 1] = 1.0
+    lib().orc_tangent_run(C.byref(flow.struct), sp.n, _ptr(sp.xw), _ptr(sp.yw), _ptr(sp.dx),
+                          _ptr(sp.dy), _ptr(F), int(nsteps), float(dt), float(t_start), int(step0))
+    return F
+
+
+def adjoint(flow: FlowSpec, x0, y0, a, b, nsteps, dt, t_start=0.0, step0=0, grid=True):
+    """Reverse sweep for L = sum(a x_T + b y_T): returns (dL/dx0, dL/dy0, gU)
+    with gU [2 slots, 2 components (u, v), n, n] (None without a grid)."""
+    x0, y0, a, b = _f64(x0), _f64(y0), _f64(a), _f64(b)
+    np_ = x0.size
+    gx, gy = np.empty(np_), np.empty(np_)
+    n = flow.struct.n
+    gU = np.zeros((2, 2, n, n)) if (grid and flow.struct.source == SRC_GRID) else None
+    tape = np.empty(2 * np_ * max(1, int(nsteps)))
+    lib().orc_adjoint_run(C.byref(flow.struct), np_, _ptr(x0), _ptr(y0), _ptr(a), _ptr(b),
+                          int(nsteps), float(dt), float(t_start), int(step0), _ptr(gx), _ptr(gy),
+                          _ptr(gU), _ptr(tape))
+    return gx, gy, gU
+
+
+def ftle(F, T):
+    """Finite-time Lyapunov exponent (1/T) ln sqrt(lambda_max(F^T F)) per
+    particle (F [np, 2, 2])."""
+    C_ = np.einsum("pki,pkj->pij", F, F)
+    lam = np.linalg.eigvalsh(C_)[:, -1]
+    return np.log(np.sqrt(lam)) / T

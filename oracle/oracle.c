@@ -485,3 +485,311 @@ void orc_cells_of(int32_t n, double L, int64_t np, const double *x, int32_t *ci)
         ci[p] = i;
     }
 }
+
+/* ======================================================================== */
+/* Derivatives of the discrete particle map (tracers).  The paper has no     */
+/* adjoint; these are the plain derivatives of the steps above, for          */
+/* finite-time Lyapunov exponents and for gradients with respect to the      */
+/* gridded velocity.  The floor of the cell location is piecewise constant,  */
+/* so d(cell)/dx = 0 and d(xi)/dx = 1/h inside a cell.                        */
+/* ======================================================================== */
+
+/* Derivatives of the Catmull-Rom and B-spline kernels (eqs. cr_kernel and
+ * bspline_kernel differentiated in s). */
+static void cr_dweights(double s, double w[4])
+{
+    w[0] = -0.5 + 2.0 * s - 1.5 * s * s;
+    w[1] = -5.0 * s + 4.5 * s * s;
+    w[2] = 0.5 + 4.0 * s - 4.5 * s * s;
+    w[3] = -s + 1.5 * s * s;
+}
+
+static void bspline_dweights(double s, double w[4])
+{
+    w[0] = -0.5 * (1.0 - s) * (1.0 - s);
+    w[1] = 1.5 * s * s - 2.0 * s;
+    w[2] = -1.5 * s * s + s + 0.5;
+    w[3] = 0.5 * s * s;
+}
+
+/* Stencil of one interpolation: up to 16 nodes (periodic indices into the
+ * [n*n] field), their weights, and the weights' x- and y-derivatives. */
+typedef struct {
+    int32_t count;
+    int64_t idx[16];
+    double w[16], wx[16], wy[16];
+} stencil;
+
+static void make_stencil(int32_t n, double L, int32_t scheme, int32_t compat_edge, double x,
+                         double y, stencil *st)
+{
+    double h = L / (double)n;
+    double xm = orc_wrap(x, L), ym = orc_wrap(y, L);
+    int32_t i, j;
+    double xi, eta;
+    locate(xm, n, h, &i, &xi);
+    locate(ym, n, h, &j, &eta);
+    int bil = scheme == ORC_BILINEAR ||
+              (compat_edge && (i - 1 < 0 || i + 2 > n - 1 || j - 1 < 0 || j + 2 > n - 1));
+    st->count = 0;
+    if (bil) {
+        /* eq. bilinear_interp: weights (1-xi)(1-eta), xi(1-eta), (1-xi)eta, xi eta */
+        double wxs[2] = {1.0 - xi, xi}, wys[2] = {1.0 - eta, eta};
+        double dxs[2] = {-1.0 / h, 1.0 / h}, dys[2] = {-1.0 / h, 1.0 / h};
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+                int k = st->count++;
+                st->idx[k] = (int64_t)imod((int64_t)j + b, n) * n + imod((int64_t)i + a, n);
+                st->w[k] = wxs[a] * wys[b];
+                st->wx[k] = dxs[a] * wys[b];
+                st->wy[k] = wxs[a] * dys[b];
+            }
+        return;
+    }
+    double wx4[4], wy4[4], dx4[4], dy4[4];
+    if (scheme == ORC_CATMULL_ROM) {
+        cr_weights(xi, wx4);
+        cr_weights(eta, wy4);
+        cr_dweights(xi, dx4);
+        cr_dweights(eta, dy4);
+    } else {
+        bspline_weights(xi, wx4);
+        bspline_weights(eta, wy4);
+        bspline_dweights(xi, dx4);
+        bspline_dweights(eta, dy4);
+    }
+    /* eqs. cr_interp / bspline_interp: node (i+m-2, j+q-2) has weight
+     * W_m(xi) W_q(eta) */
+    for (int q = 1; q <= 4; ++q)
+        for (int m = 1; m <= 4; ++m) {
+            int k = st->count++;
+            st->idx[k] = (int64_t)imod((int64_t)j + q - 2, n) * n + imod((int64_t)i + m - 2, n);
+            st->w[k] = wx4[m - 1] * wy4[q - 1];
+            st->wx[k] = dx4[m - 1] / h * wy4[q - 1];
+            st->wy[k] = wx4[m - 1] * dy4[q - 1] / h;
+        }
+}
+
+/* Value and gradient of one interpolated grid field at (x, y). */
+void orc_interp_grad(const double *f, int32_t n, double L, int32_t scheme, int32_t compat_edge,
+                     double x, double y, double *val, double *dfdx, double *dfdy)
+{
+    stencil st;
+    make_stencil(n, L, scheme, compat_edge, x, y, &st);
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k = 0; k < st.count; ++k) {
+        a += st.w[k] * f[st.idx[k]];
+        b += st.wx[k] * f[st.idx[k]];
+        c += st.wy[k] * f[st.idx[k]];
+    }
+    *val = a;
+    *dfdx = b;
+    *dfdy = c;
+}
+
+/* Fluid velocity U and its spatial Jacobian J = [[du/dx, du/dy], [dv/dx,
+ * dv/dy]] at (x, y, t) within bracket b (grid, uniform and Taylor-Green
+ * sources). */
+static void velocity_jac(const orc_flow *fl, const bracket *b, double x, double y, double t,
+                         double U[2], double J[4])
+{
+    if (fl->source == ORC_SRC_GRID) {
+        double theta = (t - b->t_lo) / (b->t_hi - b->t_lo);
+        double wt[2] = {1.0 - theta, theta};
+        int32_t sl[2] = {b->lo, b->hi};
+        U[0] = U[1] = 0.0;
+        for (int q = 0; q < 4; ++q) J[q] = 0.0;
+        for (int s = 0; s < 2; ++s) {
+            double val, dx, dy;
+            orc_interp_grad(fl->u[sl[s]], fl->n, fl->length, fl->scheme, fl->compat_edge, x, y,
+                            &val, &dx, &dy);
+            U[0] += wt[s] * val;
+            J[0] += wt[s] * dx;
+            J[1] += wt[s] * dy;
+            orc_interp_grad(fl->v[sl[s]], fl->n, fl->length, fl->scheme, fl->compat_edge, x, y,
+                            &val, &dx, &dy);
+            U[1] += wt[s] * val;
+            J[2] += wt[s] * dx;
+            J[3] += wt[s] * dy;
+        }
+        return;
+    }
+    if (fl->source == ORC_SRC_UNIFORM) {
+        U[0] = fl->U0;
+        U[1] = fl->V0;
+        J[0] = J[1] = J[2] = J[3] = 0.0;
+        return;
+    }
+    if (fl->source == ORC_SRC_TG) {
+        /* eq. kinematic_flow differentiated in x and y */
+        double ax = fl->k * (x - fl->eps * sin(fl->omega * t));
+        double ay = fl->k * (y - fl->eps * sin(fl->omega * t + fl->phi));
+        double A = fl->alpha, k = fl->k;
+        U[0] = A * sin(ax) * cos(ay);
+        U[1] = -A * cos(ax) * sin(ay);
+        J[0] = A * k * cos(ax) * cos(ay);
+        J[1] = -A * k * sin(ax) * sin(ay);
+        J[2] = A * k * sin(ax) * sin(ay);
+        J[3] = -A * k * cos(ax) * cos(ay);
+        return;
+    }
+    U[0] = U[1] = NAN;
+    J[0] = J[1] = J[2] = J[3] = NAN;
+}
+
+/* 2x2 product C = A B (row-major). */
+static void mat2(const double A[4], const double B[4], double C[4])
+{
+    double c0 = A[0] * B[0] + A[1] * B[2];
+    double c1 = A[0] * B[1] + A[1] * B[3];
+    double c2 = A[2] * B[0] + A[3] * B[2];
+    double c3 = A[2] * B[1] + A[3] * B[3];
+    C[0] = c0;
+    C[1] = c1;
+    C[2] = c2;
+    C[3] = c3;
+}
+
+/* Forward tangent propagation of F = d x_n / d x_0 (row-major 2x2 per
+ * particle, in/out) alongside the tracer RK4 step of eq. rk4_update: every
+ * stage state carries its own tangent, X_s = F + c_s dt K_{s-1}, and
+ * K_s = J(x_s) X_s.  Advances xw, yw, dxs, dys as orc_run does. */
+void orc_tangent_run(const orc_flow *fl, int64_t np, double *xw, double *yw, double *dxs,
+                     double *dys, double *F, int64_t nsteps, double dt, double t_start,
+                     int64_t step0)
+{
+    for (int64_t k = 0; k < nsteps; ++k) {
+        double t_n = t_start + (double)k * dt;
+        bracket b = bracket_for_step(fl, step0 + k, t_n, dt);
+        for (int64_t p = 0; p < np; ++p) {
+            double *Fp = F + 4 * p;
+            double x = xw[p], y = yw[p];
+            double U1[2], U2[2], U3[2], U4[2], J[4], K1[4], K2[4], K3[4], K4[4], X[4];
+            velocity_jac(fl, &b, x, y, t_n, U1, J);
+            mat2(J, Fp, K1);
+            for (int q = 0; q < 4; ++q) X[q] = Fp[q] + dt / 2.0 * K1[q];
+            velocity_jac(fl, &b, x + dt / 2.0 * U1[0], y + dt / 2.0 * U1[1], t_n + dt / 2.0, U2, J);
+            mat2(J, X, K2);
+            for (int q = 0; q < 4; ++q) X[q] = Fp[q] + dt / 2.0 * K2[q];
+            velocity_jac(fl, &b, x + dt / 2.0 * U2[0], y + dt / 2.0 * U2[1], t_n + dt / 2.0, U3, J);
+            mat2(J, X, K3);
+            for (int q = 0; q < 4; ++q) X[q] = Fp[q] + dt * K3[q];
+            velocity_jac(fl, &b, x + dt * U3[0], y + dt * U3[1], t_n + dt, U4, J);
+            mat2(J, X, K4);
+            for (int q = 0; q < 4; ++q)
+                Fp[q] += dt / 6.0 * (K1[q] + 2.0 * K2[q] + 2.0 * K3[q] + K4[q]);
+            double ddx = dt / 6.0 * (U1[0] + 2.0 * U2[0] + 2.0 * U3[0] + U4[0]);
+            double ddy = dt / 6.0 * (U1[1] + 2.0 * U2[1] + 2.0 * U3[1] + U4[1]);
+            xw[p] = orc_wrap(x + ddx, fl->length);
+            yw[p] = orc_wrap(y + ddy, fl->length);
+            dxs[p] += ddx;
+            dys[p] += ddy;
+        }
+    }
+}
+
+/* Scatter lam (dL/dU at one stage point) into the grid gradient: the stage
+ * velocity is sum over time levels s and stencil nodes k of
+ * wt_s w_k (u_s[k], v_s[k]). */
+static void scatter_stage(const orc_flow *fl, const bracket *b, double x, double y, double t,
+                          const double lam[2], double *gU)
+{
+    int64_t nn = (int64_t)fl->n * fl->n;
+    double theta = (t - b->t_lo) / (b->t_hi - b->t_lo);
+    double wt[2] = {1.0 - theta, theta};
+    int32_t sl[2] = {b->lo, b->hi};
+    stencil st;
+    make_stencil(fl->n, fl->length, fl->scheme, fl->compat_edge, x, y, &st);
+    for (int s = 0; s < 2; ++s) {
+        double *gu = gU + (int64_t)(2 * sl[s]) * nn;      /* [slot][u] */
+        double *gv = gU + (int64_t)(2 * sl[s] + 1) * nn;  /* [slot][v] */
+        for (int k = 0; k < st.count; ++k) {
+            gu[st.idx[k]] += wt[s] * st.w[k] * lam[0];
+            gv[st.idx[k]] += wt[s] * st.w[k] * lam[1];
+        }
+    }
+}
+
+/* Reverse sweep for L = sum_p (a_p x_T,p + b_p y_T,p) over nsteps tracer RK4
+ * steps from (x0, y0): the forward pass keeps every step's start position
+ * (a full tape), the reverse pass recomputes each step's stages and applies
+ * the chain rule through the combine, the stage states and the spatial and
+ * temporal interpolation.  Outputs dL/dx0, dL/dy0 and, for a grid source,
+ * adds dL/d(grid value) into gU laid out [slot][component u, v][n*n]
+ * (caller zeroes it).  tape: caller buffer of 2*np*nsteps doubles. */
+void orc_adjoint_run(const orc_flow *fl, int64_t np, const double *x0, const double *y0,
+                     const double *a, const double *bb, int64_t nsteps, double dt,
+                     double t_start, int64_t step0, double *gx0, double *gy0, double *gU,
+                     double *tape)
+{
+    for (int64_t p = 0; p < np; ++p) {
+        double x = orc_wrap(x0[p], fl->length), y = orc_wrap(y0[p], fl->length);
+        for (int64_t k = 0; k < nsteps; ++k) {
+            double t_n = t_start + (double)k * dt;
+            bracket b = bracket_for_step(fl, step0 + k, t_n, dt);
+            tape[2 * (k * np + p)] = x;
+            tape[2 * (k * np + p) + 1] = y;
+            double ddx, ddy;
+            tracer_step(fl, &b, x, y, t_n, dt, &ddx, &ddy);
+            x = orc_wrap(x + ddx, fl->length);
+            y = orc_wrap(y + ddy, fl->length);
+        }
+    }
+    for (int64_t p = 0; p < np; ++p) {
+        double lam[2] = {a[p], bb[p]};
+        for (int64_t k = nsteps - 1; k >= 0; --k) {
+            double t_n = t_start + (double)k * dt;
+            bracket b = bracket_for_step(fl, step0 + k, t_n, dt);
+            double x = tape[2 * (k * np + p)], y = tape[2 * (k * np + p) + 1];
+            /* recompute the stages */
+            double U1[2], U2[2], U3[2], U4[2], J1[4], J2[4], J3[4], J4[4];
+            double t2 = t_n + dt / 2.0, t4 = t_n + dt;
+            velocity_jac(fl, &b, x, y, t_n, U1, J1);
+            double x2 = x + dt / 2.0 * U1[0], y2 = y + dt / 2.0 * U1[1];
+            velocity_jac(fl, &b, x2, y2, t2, U2, J2);
+            double x3 = x + dt / 2.0 * U2[0], y3 = y + dt / 2.0 * U2[1];
+            velocity_jac(fl, &b, x3, y3, t2, U3, J3);
+            double x4 = x + dt * U3[0], y4 = y + dt * U3[1];
+            velocity_jac(fl, &b, x4, y4, t4, U4, J4);
+            /* x' = x + dt/6 (k1 + 2 k2 + 2 k3 + k4) */
+            double lx[2] = {lam[0], lam[1]};
+            double l1[2] = {dt / 6.0 * lam[0], dt / 6.0 * lam[1]};
+            double l2[2] = {dt / 3.0 * lam[0], dt / 3.0 * lam[1]};
+            double l3[2] = {dt / 3.0 * lam[0], dt / 3.0 * lam[1]};
+            double l4[2] = {dt / 6.0 * lam[0], dt / 6.0 * lam[1]};
+            double ls[2];
+            /* k4 = U(x4, t4), x4 = x + dt k3 */
+            if (gU && fl->source == ORC_SRC_GRID) scatter_stage(fl, &b, x4, y4, t4, l4, gU);
+            ls[0] = J4[0] * l4[0] + J4[2] * l4[1];
+            ls[1] = J4[1] * l4[0] + J4[3] * l4[1];
+            lx[0] += ls[0];
+            lx[1] += ls[1];
+            l3[0] += dt * ls[0];
+            l3[1] += dt * ls[1];
+            /* k3 = U(x3, t2), x3 = x + dt/2 k2 */
+            if (gU && fl->source == ORC_SRC_GRID) scatter_stage(fl, &b, x3, y3, t2, l3, gU);
+            ls[0] = J3[0] * l3[0] + J3[2] * l3[1];
+            ls[1] = J3[1] * l3[0] + J3[3] * l3[1];
+            lx[0] += ls[0];
+            lx[1] += ls[1];
+            l2[0] += dt / 2.0 * ls[0];
+            l2[1] += dt / 2.0 * ls[1];
+            /* k2 = U(x2, t2), x2 = x + dt/2 k1 */
+            if (gU && fl->source == ORC_SRC_GRID) scatter_stage(fl, &b, x2, y2, t2, l2, gU);
+            ls[0] = J2[0] * l2[0] + J2[2] * l2[1];
+            ls[1] = J2[1] * l2[0] + J2[3] * l2[1];
+            lx[0] += ls[0];
+            lx[1] += ls[1];
+            l1[0] += dt / 2.0 * ls[0];
+            l1[1] += dt / 2.0 * ls[1];
+            /* k1 = U(x, t_n) */
+            if (gU && fl->source == ORC_SRC_GRID) scatter_stage(fl, &b, x, y, t_n, l1, gU);
+            lx[0] += J1[0] * l1[0] + J1[2] * l1[1];
+            lx[1] += J1[1] * l1[0] + J1[3] * l1[1];
+            lam[0] = lx[0];
+            lam[1] = lx[1];
+        }
+        gx0[p] = lam[0];
+        gy0[p] = lam[1];
+    }
+}
