@@ -213,6 +213,40 @@ lpt_status lpt_get_timing(lpt_ctx *ctx, lpt_timing *out, int32_t reset);
 /* Number of steps taken and current time. */
 lpt_status lpt_get_time(lpt_ctx *ctx, int64_t *steps, double *t);
 
+/* ---- derivatives of the discrete tracer map (FP64) ---------------------- */
+/* The paper has no adjoint.  These entry points differentiate exactly the
+ * discrete map that lpt_step computes for tracers (eq. rk4_update with the
+ * interpolation of Sec. 3.4 and eq. temporal_interp): inside a cell the cell
+ * index is constant, so d(xi)/dx = n/L.  LPT_FP64 contexts whose species are
+ * all tracers (or St = 0) only; otherwise LPT_E_STATE. */
+
+/* Advance every species by nsteps steps like lpt_step (no statistics, no
+ * re-sort), keeping the positions at every ckpt_every-th step and each
+ * step's temporal weights, so that lpt_adjoint / lpt_jacobian can recompute
+ * the trajectory segment by segment.  Device memory: ceil(nsteps /
+ * ckpt_every) * 16 bytes per particle for the checkpoints, plus
+ * min(ckpt_every, nsteps) * 16 bytes per particle during a reverse sweep. */
+lpt_status lpt_forward_checkpointed(lpt_ctx *ctx, int64_t nsteps, double dt, int32_t ckpt_every);
+
+/* Reverse sweep of the last lpt_forward_checkpointed run (no step may follow
+ * it) for L = sum_p (gx_T[p] x_T,p + gy_T[p] y_T,p), x_T the final
+ * unwrapped position, p the global particle index (species concatenated in
+ * the order they were added).  Outputs (any may be NULL):
+ *   gx_0, gy_0: dL/dx_0, dL/dy_0 per particle (np doubles each);
+ *   gU: dL/d(grid value), [slot 0, 1][u, v][n][n] doubles (4 n^2),
+ *       x fastest; summed with FP64 atomics, so the last bits depend on
+ *       scheduling.
+ * All arrays are host or device memory per on_device. */
+lpt_status lpt_adjoint(lpt_ctx *ctx, const double *gx_T, const double *gy_T, double *gx_0,
+                       double *gy_0, double *gU, int32_t on_device);
+
+/* Jacobian F = d x_T / d x_0 of every particle of the last
+ * lpt_forward_checkpointed run, by a reverse sweep with two adjoint vectors:
+ * F[4p + 0..3] = dx_T/dx_0, dx_T/dy_0, dy_T/dx_0, dy_T/dy_0 (row-major
+ * 2x2; finite-time Lyapunov exponent (1/T) ln sqrt(lambda_max(F^T F))).
+ * np * 4 doubles, host or device memory per on_device. */
+lpt_status lpt_jacobian(lpt_ctx *ctx, double *F, int32_t on_device);
+
 /* ---- primitives exposed for verification -------------------------------- */
 
 /* Evaluate the interpolated fluid velocity at npts points with the given

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblpt.so")
-SOURCES = ["runtime.cpp", "step.hip", "sort.hip", "probe.hip"]
+SOURCES = ["runtime.cpp", "step.hip", "sort.hip", "probe.hip", "adjoint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,0 +1,343 @@
+// gfx950 kernels of the reverse-mode derivatives of the FP64 tracer step.
+//
+// The paper has no adjoint; these are the derivatives of the discrete map the
+// step kernel computes (eq. rk4_update with the spatial interpolation of
+// Sec. 3.4 and the temporal interpolation of eq. temporal_interp), for
+// finite-time Lyapunov exponents (dx_T/dx_0) and for gradients of a scalar
+// loss with respect to the gridded velocity.  Inside a cell the cell index
+// is constant, so d(xi)/dx = n/L; across a cell edge bilinear interpolation
+// is only continuous, and its derivative is the one-sided one of the cell
+// that holds the point.
+//
+// One thread carries one particle's adjoint vector(s) backwards through one
+// step: it recomputes the four stage points from the step's start position
+// (read from the segment tape), then applies the chain rule through the RK4
+// combine, the stage states and the interpolation.  Grid gradients are
+// scatter-added with FP64 atomics (summation order, hence rounding, depends
+// on scheduling).
+#include "field_dev.h"
+
+namespace lpt {
+
+struct Loc64 {
+    int i, j;          // periodic cell
+    double xi, eta;    // in-cell coordinates
+};
+
+__device__ __forceinline__ Loc64 locate64(const StepParams &P, double x, double y)
+{
+    const double sx = x * P.invh, sy = y * P.invh;
+    const double fx = floor(sx), fy = floor(sy);
+    Loc64 l;
+    l.xi = sx - fx;
+    l.eta = sy - fy;
+    l.i = cell_of_floor(fx, P.n, P.mask);
+    l.j = cell_of_floor(fy, P.n, P.mask);
+    return l;
+}
+
+// Derivatives of the Catmull-Rom and B-spline kernels in s.
+__device__ __forceinline__ void dweights_cr(double s, double w[4])
+{
+    w[0] = -0.5 + s * (2.0 - 1.5 * s);
+    w[1] = s * (-5.0 + 4.5 * s);
+    w[2] = 0.5 + s * (4.0 - 4.5 * s);
+    w[3] = s * (-1.0 + 1.5 * s);
+}
+
+__device__ __forceinline__ void dweights_bs(double s, double w[4])
+{
+    const double r = 1.0 - s;
+    w[0] = -0.5 * r * r;
+    w[1] = s * (1.5 * s - 2.0);
+    w[2] = 0.5 + s * (1.0 - 1.5 * s);
+    w[3] = 0.5 * s * s;
+}
+
+// Stencil of the point: `cnt` nodes starting at (i0, j0), cnt x cnt, with
+// 1D weights and their derivatives per axis.
+struct Sten64 {
+    int cnt, i0, j0;
+    double wx[4], wy[4], dx[4], dy[4];
+};
+
+__device__ __forceinline__ Sten64 stencil64(const StepParams &P, int scheme, const Loc64 &l)
+{
+    Sten64 s;
+    const bool bil = scheme == kBilinear || edge_cell(P.compat_edge, l.i, l.j, P.n);
+    if (bil) {
+        s.cnt = 2;
+        s.i0 = l.i;
+        s.j0 = l.j;
+        s.wx[0] = 1.0 - l.xi;
+        s.wx[1] = l.xi;
+        s.wy[0] = 1.0 - l.eta;
+        s.wy[1] = l.eta;
+        s.dx[0] = -1.0;
+        s.dx[1] = 1.0;
+        s.dy[0] = -1.0;
+        s.dy[1] = 1.0;
+        return s;
+    }
+    s.cnt = 4;
+    s.i0 = l.i - 1;
+    s.j0 = l.j - 1;
+    if (scheme == kCatmullRom) {
+        weights_cr(l.xi, s.wx);
+        weights_cr(l.eta, s.wy);
+        dweights_cr(l.xi, s.dx);
+        dweights_cr(l.eta, s.dy);
+    } else {
+        weights_bs(l.xi, s.wx);
+        weights_bs(l.eta, s.wy);
+        dweights_bs(l.xi, s.dx);
+        dweights_bs(l.eta, s.dy);
+    }
+    return s;
+}
+
+// Spatial Jacobian J = [du/dx, du/dy, dv/dx, dv/dy] of the time-blended
+// interpolated velocity at a stencil (records read through the ghost
+// border, so the stencil never wraps).
+__device__ __forceinline__ void jacobian64(const Rec64 *__restrict__ rec0, const StepParams &P,
+                                           const Sten64 &s, double wa, double wb, int smode,
+                                           double J[4])
+{
+    double ux = 0.0, uy = 0.0, vx = 0.0, vy = 0.0;
+    for (int b = 0; b < s.cnt; ++b) {
+        const Rec64 *row = rec0 + (__mul24(s.j0 + b, P.pitch) + s.i0);
+        double rux = 0.0, rvx = 0.0, ru = 0.0, rv = 0.0;
+        for (int a = 0; a < s.cnt; ++a) {
+            double u, v;
+            node64(row + a, smode, wa, wb, u, v);
+            rux += s.dx[a] * u;
+            rvx += s.dx[a] * v;
+            ru += s.wx[a] * u;
+            rv += s.wx[a] * v;
+        }
+        ux += s.wy[b] * rux;
+        vx += s.wy[b] * rvx;
+        uy += s.dy[b] * ru;
+        vy += s.dy[b] * rv;
+    }
+    J[0] = ux * P.invh;
+    J[1] = uy * P.invh;
+    J[2] = vx * P.invh;
+    J[3] = vy * P.invh;
+}
+
+// dL/d(grid) += lam (x) (temporal weight) (x) (node weight), into gU laid
+// out [slot][u, v][n * n].
+__device__ __forceinline__ void scatter64(double *gU, const StepParams &P, const Sten64 &s,
+                                          double wa, double wb, double lx, double ly)
+{
+    const int n = P.n;
+    const int64_t nn = (int64_t)n * n;
+    const double wt[2] = {wa, wb};
+    for (int b = 0; b < s.cnt; ++b) {
+        const int j = wrap_cell(s.j0 + b, n, P.mask);
+        for (int a = 0; a < s.cnt; ++a) {
+            const int i = wrap_cell(s.i0 + a, n, P.mask);
+            const double w = s.wx[a] * s.wy[b];
+            const int64_t k = (int64_t)j * n + i;
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl) {
+                const double c = wt[sl] * w;
+                if (c != 0.0) {
+                    atomicAdd(gU + (2 * sl) * nn + k, c * lx);
+                    atomicAdd(gU + (2 * sl + 1) * nn + k, c * ly);
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void add_jt(const double J[4], const double l[2], double out[2])
+{
+    out[0] = J[0] * l[0] + J[2] * l[1];
+    out[1] = J[1] * l[0] + J[3] * l[1];
+}
+
+// Recompute one step of every particle's position: out = wrap(in + step).
+__global__ __launch_bounds__(kMaxBlock) void recompute64_kernel(StepParams P, const Rec64 *__restrict__ rec,
+                                                          const double2 *__restrict__ in,
+                                                          double2 *__restrict__ out)
+{
+    const int lb = blockIdx.x;
+    const SpeciesDev &sp = P.sp[species_of(P, lb)];
+    const int64_t local = (int64_t)(lb - sp.block_begin) * blockDim.x + threadIdx.x;
+    if (local >= sp.count) return;
+    const int64_t p = sp.offset + local;
+    const Rec64 *rec0 = rec + P.pitch + 1;
+    const double2 x = in[p];
+    double ddx, ddy;
+    if (sp.scheme == kBilinear)
+        rk4_tracer64<false>(rec0, nullptr, no_tile(), P, sp.scheme, x, ddx, ddy);
+    else
+        rk4_tracer64<true>(rec0, nullptr, no_tile(), P, sp.scheme, x, ddx, ddy);
+    out[p] = make_double2(wrap_pos(x.x + ddx, P.L), wrap_pos(x.y + ddy, P.L));
+}
+
+// One reverse step.  lam holds NL adjoint vectors per particle
+// (lam[p * NL + r]); gU (may be null) receives the grid gradient of the
+// first one.
+template <int NL>
+__global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P, const Rec64 *__restrict__ rec,
+                                                        const double2 *__restrict__ tape,
+                                                        double2 *__restrict__ lam, double *gU)
+{
+    const int lb = blockIdx.x;
+    const SpeciesDev &sp = P.sp[species_of(P, lb)];
+    const int64_t local = (int64_t)(lb - sp.block_begin) * blockDim.x + threadIdx.x;
+    if (local >= sp.count) return;
+    const int64_t p = sp.offset + local;
+    const Rec64 *rec0 = rec + P.pitch + 1;
+    const int scheme = sp.scheme;
+    const double dt = P.dt, hdt = 0.5 * P.dt, dt6 = P.dt / 6.0, dt3 = P.dt / 3.0;
+    const double2 x = tape[p];
+
+    // forward recomputation of the stage points, exactly as the step kernel
+    double px[4], py[4];
+    double k1x, k1y, k2x, k2y, k3x, k3y;
+    px[0] = x.x;
+    py[0] = x.y;
+    vel64<true>(rec0, nullptr, no_tile(), P, scheme, px[0], py[0], P.wa[0], P.wb[0], P.smode[0],
+                k1x, k1y);
+    px[1] = x.x + hdt * k1x;
+    py[1] = x.y + hdt * k1y;
+    vel64<true>(rec0, nullptr, no_tile(), P, scheme, px[1], py[1], P.wa[1], P.wb[1], P.smode[1],
+                k2x, k2y);
+    px[2] = x.x + hdt * k2x;
+    py[2] = x.y + hdt * k2y;
+    vel64<true>(rec0, nullptr, no_tile(), P, scheme, px[2], py[2], P.wa[2], P.wb[2], P.smode[2],
+                k3x, k3y);
+    px[3] = x.x + dt * k3x;
+    py[3] = x.y + dt * k3y;
+
+    Sten64 st[4];
+    double J[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        st[q] = stencil64(P, scheme, locate64(P, px[q], py[q]));
+        jacobian64(rec0, P, st[q], P.wa[q], P.wb[q], P.smode[q], J[q]);
+    }
+
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const double2 l = lam[p * NL + r];
+        // x' = x + dt/6 (k1 + 2 k2 + 2 k3 + k4)
+        double lx[2] = {l.x, l.y};
+        double l1[2] = {dt6 * l.x, dt6 * l.y};
+        double l2[2] = {dt3 * l.x, dt3 * l.y};
+        double l3[2] = {dt3 * l.x, dt3 * l.y};
+        const double l4[2] = {dt6 * l.x, dt6 * l.y};
+        double ls[2];
+        const bool grid = gU != nullptr && r == 0;
+        // k4 = U(x4), x4 = x + dt k3
+        if (grid) scatter64(gU, P, st[3], P.wa[3], P.wb[3], l4[0], l4[1]);
+        add_jt(J[3], l4, ls);
+        lx[0] += ls[0];
+        lx[1] += ls[1];
+        l3[0] += dt * ls[0];
+        l3[1] += dt * ls[1];
+        // k3 = U(x3), x3 = x + dt/2 k2
+        if (grid) scatter64(gU, P, st[2], P.wa[2], P.wb[2], l3[0], l3[1]);
+        add_jt(J[2], l3, ls);
+        lx[0] += ls[0];
+        lx[1] += ls[1];
+        l2[0] += hdt * ls[0];
+        l2[1] += hdt * ls[1];
+        // k2 = U(x2), x2 = x + dt/2 k1
+        if (grid) scatter64(gU, P, st[1], P.wa[1], P.wb[1], l2[0], l2[1]);
+        add_jt(J[1], l2, ls);
+        lx[0] += ls[0];
+        lx[1] += ls[1];
+        l1[0] += hdt * ls[0];
+        l1[1] += hdt * ls[1];
+        // k1 = U(x)
+        if (grid) scatter64(gU, P, st[0], P.wa[0], P.wb[0], l1[0], l1[1]);
+        add_jt(J[0], l1, ls);
+        lx[0] += ls[0];
+        lx[1] += ls[1];
+        lam[p * NL + r] = make_double2(lx[0], lx[1]);
+    }
+}
+
+// lam[p * NL + r] from the caller's per-id seeds: NL == 1: (gx[id], gy[id]);
+// NL == 2: the unit vectors (d x_T, d y_T).
+__global__ void seed_adjoint_kernel(const uint32_t *__restrict__ id, int64_t np, int nl,
+                                    const double *__restrict__ gx, const double *__restrict__ gy,
+                                    double2 *lam)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    if (nl == 1) {
+        const uint32_t g = id[p];
+        lam[p] = make_double2(gx[g], gy[g]);
+    } else {
+        lam[2 * p] = make_double2(1.0, 0.0);
+        lam[2 * p + 1] = make_double2(0.0, 1.0);
+    }
+}
+
+// Results back in original (id) order: NL == 1: gx0, gy0; NL == 2: the
+// Jacobian F[id] = [[dx/dx0, dx/dy0], [dy/dx0, dy/dy0]].
+__global__ void gather_adjoint_kernel(const uint32_t *__restrict__ id, int64_t np, int nl,
+                                      const double2 *__restrict__ lam, double *gx, double *gy,
+                                      double *F)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const uint32_t g = id[p];
+    if (nl == 1) {
+        const double2 l = lam[p];
+        if (gx) gx[g] = l.x;
+        if (gy) gy[g] = l.y;
+    } else {
+        const double2 r0 = lam[2 * p], r1 = lam[2 * p + 1];
+        F[4 * (int64_t)g + 0] = r0.x;
+        F[4 * (int64_t)g + 1] = r0.y;
+        F[4 * (int64_t)g + 2] = r1.x;
+        F[4 * (int64_t)g + 3] = r1.y;
+    }
+}
+
+hipError_t launch_recompute64(const StepParams &P, const Rec64 *rec, const double2 *in,
+                              double2 *out, int block, hipStream_t st)
+{
+    hipLaunchKernelGGL(recompute64_kernel, dim3(P.total_blocks), dim3(block), 0, st, P, rec, in,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint64(const StepParams &P, const Rec64 *rec, const double2 *tape,
+                            double2 *lam, int nl, double *gU, int block, hipStream_t st)
+{
+    if (nl == 1)
+        hipLaunchKernelGGL(adjoint64_kernel<1>, dim3(P.total_blocks), dim3(block), 0, st, P, rec,
+                           tape, lam, gU);
+    else
+        hipLaunchKernelGGL(adjoint64_kernel<2>, dim3(P.total_blocks), dim3(block), 0, st, P, rec,
+                           tape, lam, (double *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_adjoint(const uint32_t *id, int64_t np, int nl, const double *gx,
+                               const double *gy, double2 *lam, hipStream_t st)
+{
+    const int b = 256;
+    hipLaunchKernelGGL(seed_adjoint_kernel, dim3((unsigned)((np + b - 1) / b)), dim3(b), 0, st, id,
+                       np, nl, gx, gy, lam);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_adjoint(const uint32_t *id, int64_t np, int nl, const double2 *lam,
+                                 double *gx, double *gy, double *F, hipStream_t st)
+{
+    const int b = 256;
+    hipLaunchKernelGGL(gather_adjoint_kernel, dim3((unsigned)((np + b - 1) / b)), dim3(b), 0, st,
+                       id, np, nl, lam, gx, gy, F);
+    return hipGetLastError();
+}
+
+}  // namespace lpt

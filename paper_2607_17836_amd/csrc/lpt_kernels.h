@@ -149,6 +149,17 @@ hipError_t launch_readout32(const State32 &S, const double2 *x0, int64_t offset,
 hipError_t launch_order(const uint32_t *id, int64_t offset, int64_t count, int32_t *out,
                         hipStream_t st);
 
+// reverse-mode derivatives of the FP64 tracer step (adjoint.hip); block is
+// the step kernel's block size (P's species block layout)
+hipError_t launch_recompute64(const StepParams &P, const Rec64 *rec, const double2 *in,
+                              double2 *out, int block, hipStream_t st);
+hipError_t launch_adjoint64(const StepParams &P, const Rec64 *rec, const double2 *tape,
+                            double2 *lam, int nl, double *gU, int block, hipStream_t st);
+hipError_t launch_seed_adjoint(const uint32_t *id, int64_t np, int nl, const double *gx,
+                               const double *gy, double2 *lam, hipStream_t st);
+hipError_t launch_gather_adjoint(const uint32_t *id, int64_t np, int nl, const double2 *lam,
+                                 double *gx, double *gy, double *F, hipStream_t st);
+
 // bandwidth probe (bytes: per buffer, multiple of 16)
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t st);
 hipError_t launch_triad(const void *b, const void *c, void *a, int64_t bytes, hipStream_t st);

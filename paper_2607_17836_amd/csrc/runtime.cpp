@@ -24,6 +24,10 @@ namespace {
 constexpr size_t kTileBytesDefault = 19200;
 constexpr size_t kTileBytesMax = 61440;
 
+struct StepWeights {
+    double wa[4], wb[4];
+};
+
 struct SpeciesHost {
     int32_t kind;
     double st;
@@ -86,6 +90,15 @@ struct lpt_ctx {
 
     int64_t steps = 0;
     double t = 0;
+
+    // checkpointed forward run for the derivatives
+    double2 *ck = nullptr;       // positions at segment starts, [segment][np]
+    size_t ck_bytes = 0;
+    int32_t ck_every = 0;
+    int64_t ck_nsteps = 0, ck_step0 = 0;
+    double ck_dt = 0, ck_t0 = 0;
+    std::vector<StepWeights> ck_w;   // temporal weights of every recorded step
+    bool ck_valid = false;
 
     // optional event timing of step kernels and re-sorts
     bool time_kernels = false;
@@ -399,6 +412,7 @@ void lpt_destroy(lpt_ctx *c)
     dfree(c->records);
     dfree(c->clock);
     dfree(c->umax);
+    dfree(c->ck);
     if (c->rec) (void)hipFree(c->rec);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -672,9 +686,11 @@ lpt_status lpt_init_uniform(lpt_ctx *c, int32_t sid, uint64_t seed)
     return init_species_state(c, sid);
 }
 
-lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
+namespace {
+
+// Argument and state checks shared by lpt_step and lpt_forward_checkpointed.
+lpt_status check_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
 {
-    if (!c) return LPT_E_ARG;
     if (nsteps < 0) return fail(c, LPT_E_ARG, "nsteps must be >= 0");
     if (!(dt > 0.0) || !is_finite(dt)) return fail(c, LPT_E_ARG, "dt must be finite and > 0");
     if (stats_every < 0) return fail(c, LPT_E_ARG, "stats_every must be >= 0");
@@ -702,44 +718,78 @@ lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
             tt += dt;
         }
     }
-    HIP_TRY(c, hipSetDevice(c->device));
-    // statistics capacity
+    return LPT_OK;
+}
+
+lpt_status grow_records(lpt_ctx *c, int64_t nsteps, int32_t stats_every)
+{
     int64_t new_rec = 0;
     if (stats_every > 0) new_rec = (c->steps + nsteps) / stats_every - c->steps / stats_every;
-    if (c->nrec + new_rec > c->rec_cap) {
-        const int64_t cap = std::max<int64_t>(2 * c->rec_cap, c->nrec + new_rec + 64);
-        const int64_t ns = (int64_t)c->sp.size();
-        double *nr = nullptr;
-        HIP_TRY(c, dalloc(nr, (size_t)(ns * cap * 8)));
-        for (int64_t s = 0; s < ns && c->nrec > 0; ++s)
-            HIP_TRY(c, hipMemcpyAsync(nr + s * cap * 8, c->records + s * c->rec_cap * 8,
-                                      (size_t)c->nrec * 8 * sizeof(double),
-                                      hipMemcpyDeviceToDevice, c->stream));
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        dfree(c->records);
-        c->records = nr;
-        c->rec_cap = cap;
+    if (c->nrec + new_rec <= c->rec_cap) return LPT_OK;
+    const int64_t cap = std::max<int64_t>(2 * c->rec_cap, c->nrec + new_rec + 64);
+    const int64_t ns = (int64_t)c->sp.size();
+    double *nr = nullptr;
+    HIP_TRY(c, dalloc(nr, (size_t)(ns * cap * 8)));
+    for (int64_t s = 0; s < ns && c->nrec > 0; ++s)
+        HIP_TRY(c, hipMemcpyAsync(nr + s * cap * 8, c->records + s * c->rec_cap * 8,
+                                  (size_t)c->nrec * 8 * sizeof(double), hipMemcpyDeviceToDevice,
+                                  c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c->records);
+    c->records = nr;
+    c->rec_cap = cap;
+    return LPT_OK;
+}
+
+// Temporal weights of the step about to be taken (global number c->steps,
+// starting at c->t).
+void step_weights(const lpt_ctx *c, double dt, StepParams &P)
+{
+    const double stage_c[4] = {0.0, 0.5, 0.5, 1.0};
+    for (int q = 0; q < 4; ++q) {
+        weights_at(c, c->steps, c->t, c->t + stage_c[q] * dt, dt, P.wa[q], P.wb[q]);
+        P.smode[q] = slot_mode(P.wa[q], P.wb[q]);
+        P.waf[q] = (float)P.wa[q];
+        P.wbf[q] = (float)P.wb[q];
     }
-    StepParams P = make_params(c);
+    P.ends_one = P.smode[0] != kBlend && P.smode[3] != kBlend;
+    P.h0 = P.smode[0] == kSlot1 ? 1 : 0;
+    P.h3 = P.smode[3] == kSlot1 ? 1 : 0;
+}
+
+void set_dt(StepParams &P, double dt)
+{
     P.dt = dt;
     P.dtf = (float)dt;
     P.hdtf = (float)(0.5 * dt);
     P.dt6f = (float)(dt / 6.0);
-    const double stage_c[4] = {0.0, 0.5, 0.5, 1.0};
+}
+
+// Enqueue nsteps steps.  With `ckpt`, no re-sort happens, the position of
+// every particle is saved before each step whose index in the run is a
+// multiple of c->ck_every, and every step's temporal weights are kept.
+lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every, bool ckpt)
+{
+    StepParams P = make_params(c);
+    set_dt(P, dt);
     for (int64_t k = 0; k < nsteps; ++k) {
-        if (c->sort_interval > 0 && c->steps % c->sort_interval == 0) {
+        if (!ckpt && c->sort_interval > 0 && c->steps % c->sort_interval == 0) {
             const lpt_status s = do_sort(c);
             if (s != LPT_OK) return s;
         }
-        for (int q = 0; q < 4; ++q) {
-            weights_at(c, c->steps, c->t, c->t + stage_c[q] * dt, dt, P.wa[q], P.wb[q]);
-            P.smode[q] = slot_mode(P.wa[q], P.wb[q]);
-            P.waf[q] = (float)P.wa[q];
-            P.wbf[q] = (float)P.wb[q];
+        step_weights(c, dt, P);
+        if (ckpt) {
+            if (k % c->ck_every == 0)
+                HIP_TRY(c, hipMemcpyAsync(c->ck + (k / c->ck_every) * c->np, c->s64[c->cur].pos,
+                                          (size_t)c->np * sizeof(double2),
+                                          hipMemcpyDeviceToDevice, c->stream));
+            StepWeights w;
+            for (int q = 0; q < 4; ++q) {
+                w.wa[q] = P.wa[q];
+                w.wb[q] = P.wb[q];
+            }
+            c->ck_w.push_back(w);
         }
-        P.ends_one = P.smode[0] != kBlend && P.smode[3] != kBlend;
-        P.h0 = P.smode[0] == kSlot1 ? 1 : 0;
-        P.h3 = P.smode[3] == kSlot1 ? 1 : 0;
         const bool rec = stats_every > 0 && (c->steps + 1) % stats_every == 0;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->time_kernels) HIP_TRY(c, mark(c, e0));
@@ -763,6 +813,202 @@ lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
         c->t += dt;
         c->steps += 1;
     }
+    return LPT_OK;
+}
+
+}  // namespace
+
+lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
+{
+    if (!c) return LPT_E_ARG;
+    lpt_status s = check_steps(c, nsteps, dt, stats_every);
+    if (s != LPT_OK || nsteps == 0) return s;
+    HIP_TRY(c, hipSetDevice(c->device));
+    s = grow_records(c, nsteps, stats_every);
+    if (s != LPT_OK) return s;
+    c->ck_valid = false;
+    return run_steps(c, nsteps, dt, stats_every, false);
+}
+
+lpt_status lpt_forward_checkpointed(lpt_ctx *c, int64_t nsteps, double dt, int32_t ckpt_every)
+{
+    if (!c) return LPT_E_ARG;
+    if (c->precision != LPT_FP64)
+        return fail(c, LPT_E_STATE, "derivatives need an LPT_FP64 context");
+    for (const SpeciesHost &h : c->sp)
+        if (h.kind == LPT_INERTIAL && h.st > 0.0)
+            return fail(c, LPT_E_STATE, "derivatives are implemented for tracers only");
+    if (nsteps < 1) return fail(c, LPT_E_ARG, "nsteps must be >= 1");
+    if (ckpt_every < 1) return fail(c, LPT_E_ARG, "ckpt_every must be >= 1");
+    lpt_status s = check_steps(c, nsteps, dt, 0);
+    if (s != LPT_OK) return s;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+    const size_t need = (size_t)nseg * (size_t)c->np * sizeof(double2);
+    if (need > c->ck_bytes) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        dfree(c->ck);
+        c->ck_bytes = 0;
+        void *q = nullptr;
+        if (hipMalloc(&q, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, LPT_E_NOMEM, "checkpoint buffer allocation failed");
+        }
+        c->ck = static_cast<double2 *>(q);
+        c->ck_bytes = need;
+    }
+    c->ck_every = ckpt_every;
+    c->ck_nsteps = nsteps;
+    c->ck_w.clear();
+    c->ck_dt = dt;
+    c->ck_step0 = c->steps;
+    c->ck_t0 = c->t;
+    c->ck_valid = false;
+    s = run_steps(c, nsteps, dt, 0, true);
+    if (s != LPT_OK) return s;
+    c->ck_valid = true;
+    return LPT_OK;
+}
+
+namespace {
+
+// Reverse sweep over the last checkpointed run: per segment, newest first,
+// rebuild the segment's per-step positions from its checkpoint, then take
+// the adjoint kernel back through them.
+lpt_status reverse_sweep(lpt_ctx *c, int nl, double2 *lam, double *gU)
+{
+    const int64_t E = c->ck_every, N = c->ck_nsteps, np = c->np;
+    const int64_t tape_len = std::min(E, N);
+    double2 *tape = nullptr;
+    HIP_TRY(c, dalloc(tape, (size_t)(tape_len * np)));
+    StepParams P = make_params(c);
+    set_dt(P, c->ck_dt);
+    const Rec64 *rec = static_cast<const Rec64 *>(c->rec);
+    hipError_t e = hipSuccess;
+    for (int64_t seg = (N - 1) / E; seg >= 0 && e == hipSuccess; --seg) {
+        const int64_t k0 = seg * E, len = std::min(E, N - k0);
+        e = hipMemcpyAsync(tape, c->ck + seg * np, (size_t)np * sizeof(double2),
+                           hipMemcpyDeviceToDevice, c->stream);
+        for (int64_t s = 1; s < len && e == hipSuccess; ++s) {
+            const StepWeights &w = c->ck_w[(size_t)(k0 + s - 1)];
+            for (int q = 0; q < 4; ++q) {
+                P.wa[q] = w.wa[q];
+                P.wb[q] = w.wb[q];
+                P.smode[q] = slot_mode(w.wa[q], w.wb[q]);
+            }
+            e = launch_recompute64(P, rec, tape + (s - 1) * np, tape + s * np, c->block,
+                                   c->stream);
+        }
+        for (int64_t s = len - 1; s >= 0 && e == hipSuccess; --s) {
+            const StepWeights &w = c->ck_w[(size_t)(k0 + s)];
+            for (int q = 0; q < 4; ++q) {
+                P.wa[q] = w.wa[q];
+                P.wb[q] = w.wb[q];
+                P.smode[q] = slot_mode(w.wa[q], w.wb[q]);
+            }
+            e = launch_adjoint64(P, rec, tape + s * np, lam, nl, gU, c->block, c->stream);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(tape);
+    HIP_TRY(c, e);
+    return LPT_OK;
+}
+
+lpt_status check_adjoint(lpt_ctx *c)
+{
+    if (!c->ck_valid || c->steps != c->ck_step0 + c->ck_nsteps)
+        return fail(c, LPT_E_STATE,
+                    "call lpt_forward_checkpointed first (and take no other step after it)");
+    return LPT_OK;
+}
+
+}  // namespace
+
+lpt_status lpt_adjoint(lpt_ctx *c, const double *gx_T, const double *gy_T, double *gx_0,
+                       double *gy_0, double *gU, int32_t on_device)
+{
+    if (!c) return LPT_E_ARG;
+    if (!gx_T || !gy_T) return fail(c, LPT_E_ARG, "gx_T and gy_T must not be NULL");
+    lpt_status s = check_adjoint(c);
+    if (s != LPT_OK) return s;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t np = c->np, nn4 = 4 * (int64_t)c->n * c->n;
+    Staged st;
+    const double *dgx = nullptr, *dgy = nullptr;
+    s = stage_in(c, st, gx_T, np, on_device, dgx);
+    if (s == LPT_OK) s = stage_in(c, st, gy_T, np, on_device, dgy);
+    if (s != LPT_OK) return s;
+    double2 *lam = nullptr;
+    HIP_TRY(c, dalloc(lam, (size_t)np));
+    st.bufs.push_back(reinterpret_cast<double *>(lam));
+    double *dU = nullptr;
+    if (gU) {
+        if (on_device) {
+            dU = gU;
+        } else {
+            HIP_TRY(c, dalloc(dU, (size_t)nn4));
+            st.bufs.push_back(dU);
+        }
+        HIP_TRY(c, hipMemsetAsync(dU, 0, (size_t)nn4 * sizeof(double), c->stream));
+    }
+    const uint32_t *id = c->s64[c->cur].id;
+    HIP_TRY(c, launch_seed_adjoint(id, np, 1, dgx, dgy, lam, c->stream));
+    s = reverse_sweep(c, 1, lam, dU);
+    if (s != LPT_OK) return s;
+    double *ox = gx_0, *oy = gy_0;
+    if (!on_device) {
+        if (gx_0) {
+            HIP_TRY(c, dalloc(ox, (size_t)np));
+            st.bufs.push_back(ox);
+        }
+        if (gy_0) {
+            HIP_TRY(c, dalloc(oy, (size_t)np));
+            st.bufs.push_back(oy);
+        }
+    }
+    HIP_TRY(c, launch_gather_adjoint(id, np, 1, lam, ox, oy, nullptr, c->stream));
+    if (!on_device) {
+        if (gx_0)
+            HIP_TRY(c, hipMemcpyAsync(gx_0, ox, (size_t)np * sizeof(double),
+                                      hipMemcpyDeviceToHost, c->stream));
+        if (gy_0)
+            HIP_TRY(c, hipMemcpyAsync(gy_0, oy, (size_t)np * sizeof(double),
+                                      hipMemcpyDeviceToHost, c->stream));
+        if (gU)
+            HIP_TRY(c, hipMemcpyAsync(gU, dU, (size_t)nn4 * sizeof(double),
+                                      hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LPT_OK;
+}
+
+lpt_status lpt_jacobian(lpt_ctx *c, double *F, int32_t on_device)
+{
+    if (!c) return LPT_E_ARG;
+    if (!F) return fail(c, LPT_E_ARG, "F must not be NULL");
+    lpt_status s = check_adjoint(c);
+    if (s != LPT_OK) return s;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t np = c->np;
+    Staged st;
+    double2 *lam = nullptr;
+    HIP_TRY(c, dalloc(lam, (size_t)(2 * np)));
+    st.bufs.push_back(reinterpret_cast<double *>(lam));
+    const uint32_t *id = c->s64[c->cur].id;
+    HIP_TRY(c, launch_seed_adjoint(id, np, 2, nullptr, nullptr, lam, c->stream));
+    s = reverse_sweep(c, 2, lam, nullptr);
+    if (s != LPT_OK) return s;
+    double *dF = F;
+    if (!on_device) {
+        HIP_TRY(c, dalloc(dF, (size_t)(4 * np)));
+        st.bufs.push_back(dF);
+    }
+    HIP_TRY(c, launch_gather_adjoint(id, np, 2, lam, nullptr, nullptr, dF, c->stream));
+    if (!on_device)
+        HIP_TRY(c, hipMemcpyAsync(F, dF, (size_t)(4 * np) * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return LPT_OK;
 }
 

@@ -12,376 +12,9 @@
 // base address.  State is structure-of-arrays with interleaved (x, y) pairs,
 // so the per-step state stream is fully coalesced; the gathers rely on
 // cell-ordered particles (sort.hip) and an XCD-aware block order for L2 reuse.
-#include "lpt_kernels.h"
-
-#include <math.h>
+#include "field_dev.h"
 
 namespace lpt {
-
-constexpr int kMaxBlock = 512;
-constexpr int kWave = 64;
-constexpr float kCellClampF = 1073741824.0f;   // 2^30 cells
-constexpr double kCellClampD = 1073741824.0;
-
-// ---------------------------------------------------------------------------
-// Block order.  The hardware deals consecutive workgroups round-robin over the
-// 8 XCDs of the chip; remap so that XCD x processes one contiguous run of
-// logical blocks (neighbouring cells after the cell sort) and its private L2
-// sees their shared stencil rows.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int xcd_logical_block(int b, int G)
-{
-    constexpr int X = 8;
-    const int x = b % X, k = b / X;
-    const int q = G / X, r = G % X;
-    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-}
-
-__device__ __forceinline__ int species_of(const StepParams &P, int lb)
-{
-    int s = 0;
-    for (int k = 1; k < P.nspecies; ++k)
-        if (lb >= P.sp[k].block_begin) s = k;
-    return s;
-}
-
-// ---------------------------------------------------------------------------
-// Periodic cell index.  Cell coordinates are clamped to +-2^30 before the
-// integer conversion (one v_med3), so that any input -- NaN and absurd
-// displacements included -- yields an index inside [0, n) and no gather can
-// leave the field; within +-2^30 cells the mapping is the exact periodic one.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int wrap_cell(int c, int n, int mask)
-{
-    if (mask >= 0) return c & mask;
-    if (c < 0) c += n;
-    if (c >= n) c -= n;
-    if ((unsigned)c >= (unsigned)n) {
-        c %= n;
-        if (c < 0) c += n;
-    }
-    return c;
-}
-
-__device__ __forceinline__ int cell_plus(int c, float fl, int n, int mask)
-{
-    const float f = __builtin_amdgcn_fmed3f(fl, -kCellClampF, kCellClampF);
-    return wrap_cell(c + (int)f, n, mask);
-}
-
-__device__ __forceinline__ int cell_of_floor(double fl, int n, int mask)
-{
-    double f = fmin(fmax(fl, -kCellClampD), kCellClampD);
-    if (!(f == f)) f = 0.0;
-    return wrap_cell((int)f, n, mask);
-}
-
-// Catmull-Rom kernel (eq. cr_kernel) and cubic B-spline kernel
-// (eq. bspline_kernel), evaluated in Horner form.
-template <typename T>
-__device__ __forceinline__ void weights_cr(T s, T w[4])
-{
-    w[0] = s * (T(-0.5) + s * (T(1.0) + s * T(-0.5)));
-    w[1] = T(1.0) + s * s * (T(-2.5) + s * T(1.5));
-    w[2] = s * (T(0.5) + s * (T(2.0) + s * T(-1.5)));
-    w[3] = s * s * (T(-0.5) + s * T(0.5));
-}
-
-template <typename T>
-__device__ __forceinline__ void weights_bs(T s, T w[4])
-{
-    const T r = T(1.0) - s;
-    const T sixth = T(1.0) / T(6.0);
-    w[0] = r * r * r * sixth;
-    w[1] = (T(4.0) + s * s * (T(-6.0) + s * T(3.0))) * sixth;
-    w[2] = (T(1.0) + s * (T(3.0) + s * (T(3.0) + s * T(-3.0)))) * sixth;
-    w[3] = s * s * s * sixth;
-}
-
-template <typename T>
-__device__ __forceinline__ void bilinear_weights(T xi, T eta, T &w00, T &w10, T &w01, T &w11)
-{
-    w11 = xi * eta;
-    w10 = xi - w11;            // xi (1 - eta)
-    w01 = eta - w11;           // (1 - xi) eta
-    w00 = (T(1.0) - xi) - w01; // (1 - xi)(1 - eta)
-}
-
-__device__ __forceinline__ bool edge_cell(int compat, int i, int j, int n)
-{
-    return compat && (i == 0 || i >= n - 2 || j == 0 || j >= n - 2);
-}
-
-// ===========================================================================
-// LDS field tiles.  After the cell-order sort, the particles of one block sit
-// in a compact patch of cells.  The block finds the bounding box of its
-// particles' stored cells, widens it by a halo that covers every RK4 stage
-// position (the largest displacement a step can make, from the largest node
-// speed of the two time levels) plus the interpolation stencil, and copies
-// the node records of that box into LDS with coalesced row loads.  The four
-// stages then gather from LDS.  Every gather checks that its whole stencil
-// lies inside the tile and otherwise reads global memory, so the halo is a
-// performance estimate, never a correctness assumption.
-// ===========================================================================
-struct Tile {
-    int x0, y0;   // global node index of tile entry (0, 0)
-    int w, h;     // tile extent in nodes
-    int on;       // block-uniform: the tile is staged
-};
-
-__device__ __forceinline__ Tile no_tile() { return Tile{0, 0, 0, 0, 0}; }
-
-// Tile index of stencil origin node (i0, j0) if the span x span stencil that
-// starts there lies inside the tile.
-__device__ __forceinline__ bool tile_index(const Tile &T, int i0, int j0, int span, int n,
-                                           int mask, int &idx)
-{
-    const int rx = wrap_cell(i0 - T.x0, n, mask), ry = wrap_cell(j0 - T.y0, n, mask);
-    idx = ry * T.w + rx;
-    return T.on && rx <= T.w - span && ry <= T.h - span;
-}
-
-extern __shared__ __align__(32) unsigned char lpt_dyn_lds[];
-
-// Halo in cells for one step of size dt: the largest stage displacement
-// (velocity bound times dt, rounded up) -- Catmull-Rom can overshoot the node
-// values by up to (1 + 1/4)^2 because its weights have |W| summing to
-// 1 + s(1 - s) per axis; bilinear and B-spline weights are convex.
-__device__ __forceinline__ int step_halo(const StepParams &P, int scheme, float dt)
-{
-    const float um = fmaxf(P.umax[0], P.umax[1]);   // cells per unit time
-    const float cs = scheme == kCatmullRom ? 1.5625f : 1.0f;
-    const float d = fminf(cs * um * dt, 16.0f);
-    return d > 0.0f ? (int)ceilf(d) : 0;
-}
-
-// Wave-wide maximum of two packed unsigned 16-bit lanes by DPP: four row
-// shifts reduce each 16-lane row, two row broadcasts combine the rows, and
-// lane 63 ends with the result.  Lanes outside a shift read 0, the identity.
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ uint32_t pmax16(uint32_t a, uint32_t b)
-{
-    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
-                                                                  __builtin_bit_cast(u16x2, b)));
-}
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ uint32_t dpp_pmax(uint32_t x)
-{
-    return pmax16(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, true));
-}
-
-__device__ __forceinline__ uint32_t wave_pmax16(uint32_t x)
-{
-    x = dpp_pmax<0x111, 0xF>(x);   // row_shr:1
-    x = dpp_pmax<0x112, 0xF>(x);   // row_shr:2
-    x = dpp_pmax<0x114, 0xF>(x);   // row_shr:4
-    x = dpp_pmax<0x118, 0xF>(x);   // row_shr:8
-    x = dpp_pmax<0x142, 0xA>(x);   // row_bcast:15
-    x = dpp_pmax<0x143, 0xC>(x);   // row_bcast:31
-    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-}
-
-// Rows of the tile one wave loads before it writes any of them to LDS, so
-// that their global-memory latencies overlap.
-template <typename Rec>
-constexpr int fill_rows()
-{
-    return sizeof(Rec) <= 16 ? 8 : 4;
-}
-
-// Cooperative tile set-up of one block (all threads must call it).
-// (cx, cy): the thread's stored cell (ignored when !active); (ax, ay): the
-// stored cell of the block's first particle, which is always active.  The
-// box is reduced on cell offsets from (ax, ay), biased by 2^15 and packed
-// two per word, as maxima of (r + 2^15) and (2^15 - r).
-template <typename Rec>
-__device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec0,
-                                          const StepParams &P, bool active, int cx, int cy,
-                                          int ax, int ay, int lo, int hi, int nactive)
-{
-    __shared__ uint32_t red[2][kMaxBlock / kWave];
-    constexpr int kBias = 1 << 15;
-    const int n = P.n, mask = P.mask, half = n >> 1;
-    int rx = 0, ry = 0;
-    if (active) {   // cx - ax lies in (-n, n): map it to (-n/2, n/2]
-        rx = cx - ax;
-        ry = cy - ay;
-        rx += rx < -half ? n : (rx > half ? -n : 0);
-        ry += ry < -half ? n : (ry > half ? -n : 0);
-    }
-    uint32_t up = (uint32_t)(rx + kBias) | ((uint32_t)(ry + kBias) << 16);
-    uint32_t dn = (uint32_t)(kBias - rx) | ((uint32_t)(kBias - ry) << 16);
-    up = wave_pmax16(up);
-    dn = wave_pmax16(dn);
-    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    if (lane == 0) {
-        red[0][wv] = up;
-        red[1][wv] = dn;
-    }
-    __syncthreads();
-    up = red[0][0];
-    dn = red[1][0];
-    for (int k = 1; k < nw; ++k) {
-        up = pmax16(up, red[0][k]);
-        dn = pmax16(dn, red[1][k]);
-    }
-    const int mxx = (int)(up & 0xFFFFu) - kBias, mxy = (int)(up >> 16) - kBias;
-    const int mnx = kBias - (int)(dn & 0xFFFFu), mny = kBias - (int)(dn >> 16);
-    Tile T;
-    T.w = mxx - mnx + 1 + lo + hi;
-    T.h = mxy - mny + 1 + lo + hi;
-    T.x0 = wrap_cell(ax + mnx - lo, n, mask);
-    T.y0 = wrap_cell(ay + mny - lo, n, mask);
-    const int area = T.w * T.h;
-    T.on = P.tile_cap > 0 && area <= P.tile_cap && T.w < n && T.h < n &&
-           area <= kTileWaste * nactive;
-    if (T.on) {
-        // Every load of a group is issued before any LDS write, so their
-        // latencies overlap.  Rows past the tile are clamped to its last
-        // row: they re-read it and rewrite the same values.  T.x0 + c and
-        // T.y0 + r lie in [0, 2n): one conditional subtraction wraps them.
-        constexpr int R = fill_rows<Rec>();
-        const int w0 = __builtin_amdgcn_readfirstlane(wv);   // wave-uniform row start
-        for (int c = lane; c < T.w; c += kWave) {
-            int gx = T.x0 + c;
-            gx -= gx >= n ? n : 0;
-            const Rec *src = rec0 + gx;
-            Rec *dst = lds + c;
-            for (int r0 = w0; r0 < T.h; r0 += R * nw) {
-                Rec buf[R];
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    int gy = T.y0 + min(r0 + k * nw, T.h - 1);
-                    gy -= gy >= n ? n : 0;
-                    buf[k] = src[__mul24(gy, P.pitch)];
-                }
-#pragma unroll
-                for (int k = 0; k < R; ++k) dst[__mul24(min(r0 + k * nw, T.h - 1), T.w)] = buf[k];
-            }
-        }
-    }
-    __syncthreads();
-    return T;
-}
-
-// ===========================================================================
-// FP64 path (physical units)
-// ===========================================================================
-// Time-blended (u, v) of one node record.
-__device__ __forceinline__ void node64(const Rec64 *r, int smode, double wa, double wb, double &u,
-                                       double &v)
-{
-    const double2 *q = reinterpret_cast<const double2 *>(r);
-    if (smode == kSlot0) {
-        const double2 a = q[0];
-        u = a.x;
-        v = a.y;
-    } else if (smode == kSlot1) {
-        const double2 b = q[1];
-        u = b.x;
-        v = b.y;
-    } else {
-        const double2 a = q[0], b = q[1];
-        u = wa * a.x + wb * b.x;
-        v = wa * a.y + wb * b.y;
-    }
-}
-
-// eq. bilinear_interp on the records at p (node (i, j)), p + 1, p + pitch,
-// p + pitch + 1.
-__device__ __forceinline__ void bil64(const Rec64 *p, int pitch, double xi, double eta, int smode,
-                                      double wa, double wb, double &u, double &v)
-{
-    double u00, v00, u10, v10, u01, v01, u11, v11;
-    node64(p, smode, wa, wb, u00, v00);
-    node64(p + 1, smode, wa, wb, u10, v10);
-    node64(p + pitch, smode, wa, wb, u01, v01);
-    node64(p + pitch + 1, smode, wa, wb, u11, v11);
-    double w00, w10, w01, w11;
-    bilinear_weights(xi, eta, w00, w10, w01, w11);
-    u = w00 * u00 + w10 * u10 + w01 * u01 + w11 * u11;
-    v = w00 * v00 + w10 * v10 + w01 * v01 + w11 * v11;
-}
-
-// eqs. cr_interp / bspline_interp on the 4x4 records whose first is p
-// (node (i - 1, j - 1)).
-__device__ __forceinline__ void cub64(const Rec64 *p, int pitch, const double wx[4],
-                                      const double wy[4], int smode, double wa, double wb,
-                                      double &u, double &v)
-{
-    double au = 0.0, av = 0.0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        double ru = 0.0, rv = 0.0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            double nu, nv;
-            node64(p + a, smode, wa, wb, nu, nv);
-            ru += wx[a] * nu;
-            rv += wx[a] * nv;
-        }
-        au += wy[b] * ru;
-        av += wy[b] * rv;
-        p += pitch;
-    }
-    u = au;
-    v = av;
-}
-
-// Velocity at (x, y) (physical units, any real value) with temporal weights
-// (wa, wb) on the two snapshot slots.  rec0 points at global node (0, 0);
-// tile/T is the block's LDS tile (T.on == 0: global only).
-template <bool CUBIC>
-__device__ __forceinline__ void vel64(const Rec64 *__restrict__ rec0, const Rec64 *tile,
-                                      const Tile &T, const StepParams &P, int scheme, double x,
-                                      double y, double wa, double wb, int smode, double &u,
-                                      double &v)
-{
-    const double sx = x * P.invh, sy = y * P.invh;
-    const double fx = floor(sx), fy = floor(sy);
-    const double xi = sx - fx, eta = sy - fy;
-    const int n = P.n, mask = P.mask;
-    const int i = cell_of_floor(fx, n, mask), j = cell_of_floor(fy, n, mask);
-    int t;
-    if (!CUBIC || scheme == kBilinear || edge_cell(P.compat_edge, i, j, n)) {
-        if (tile_index(T, i, j, 2, n, mask, t))
-            bil64(tile + t, T.w, xi, eta, smode, wa, wb, u, v);
-        else
-            bil64(rec0 + (__mul24(j, P.pitch) + i), P.pitch, xi, eta, smode, wa, wb, u, v);
-        return;
-    }
-    if constexpr (CUBIC) {
-        double wx[4], wy[4];
-        if (scheme == kCatmullRom) {
-            weights_cr(xi, wx);
-            weights_cr(eta, wy);
-        } else {
-            weights_bs(xi, wx);
-            weights_bs(eta, wy);
-        }
-        if (tile_index(T, i - 1, j - 1, 4, n, mask, t))
-            cub64(tile + t, T.w, wx, wy, smode, wa, wb, u, v);
-        else
-            cub64(rec0 + (__mul24(j - 1, P.pitch) + (i - 1)), P.pitch, wx, wy, smode, wa, wb, u, v);
-    }
-}
-
-__device__ __forceinline__ double wrap_pos(double z, double L)
-{
-    if (z >= L) z -= L;
-    else if (z < 0.0) z += L;
-    if (!(z >= 0.0 && z < L)) {
-        if (z == z) {   // finite but far away, or +L after rounding
-            z = z - L * floor(z / L);
-            if (z < 0.0) z += L;
-            if (z >= L) z -= L;
-        }
-    }
-    return z;
-}
-
 template <int NT>
 __device__ __forceinline__ void block_sum3(double a, double b, double c, double *out)
 {
@@ -484,18 +117,7 @@ __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64
             S.vel[p] = make_double2(vn.x + dt6 * (A1x + 2.0 * A2x + 2.0 * A3x + A4x),
                                     vn.y + dt6 * (A1y + 2.0 * A2y + 2.0 * A3y + A4y));
         } else {
-            // eq. rk4_update, stages at t_n, t_n + dt/2, t_n + dt/2, t_n + dt
-            double k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
-            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x, x.y, P.wa[0], P.wb[0], P.smode[0], k1x,
-                         k1y);
-            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x + hdt * k1x, x.y + hdt * k1y, P.wa[1],
-                         P.wb[1], P.smode[1], k2x, k2y);
-            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x + hdt * k2x, x.y + hdt * k2y, P.wa[2],
-                         P.wb[2], P.smode[2], k3x, k3y);
-            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x + dt * k3x, x.y + dt * k3y, P.wa[3],
-                         P.wb[3], P.smode[3], k4x, k4y);
-            ddx = dt6 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
-            ddy = dt6 * (k1y + 2.0 * k2y + 2.0 * k3y + k4y);
+            rk4_tracer64<CUBIC>(rec0, lds, T, P, sp.scheme, x, ddx, ddy);
         }
         // wrapped coordinates for evaluation/output, unwrapped displacement
         // for statistics

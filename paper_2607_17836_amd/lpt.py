@@ -75,6 +75,9 @@ _SIGS = [
     ("lpt_interp", C.c_int, [_P, C.c_int, C.c_int64, _P, _P, C.c_double, C.c_double, _P, _P,
                              C.c_int32]),
     ("lpt_radix_sort", C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, _P]),
+    ("lpt_forward_checkpointed", C.c_int, [_P, C.c_int64, C.c_double, C.c_int32]),
+    ("lpt_adjoint", C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int32]),
+    ("lpt_jacobian", C.c_int, [_P, _P, C.c_int32]),
     ("lpt_bw_probe", C.c_int, [_P, C.c_int64, C.c_int32, C.POINTER(C.c_double),
                                C.POINTER(C.c_double)]),
 ]
@@ -272,6 +275,41 @@ class Tracker:
         self._check(load().lpt_bw_probe(self._h, int(nbytes), int(iters), C.byref(cp), C.byref(tr)))
         return cp.value, tr.value
 
+    # -- derivatives (FP64 tracers) ---------------------------------------
+    def forward_checkpointed(self, nsteps, dt, ckpt_every):
+        self._check(load().lpt_forward_checkpointed(self._h, int(nsteps), float(dt),
+                                                    int(ckpt_every)))
+
+    def adjoint(self, gx_T, gy_T, want_grid=True):
+        """Reverse sweep for L = sum(gx_T x_T + gy_T y_T) over all particles
+        (global index order).  Host arrays in -> numpy out; device tensors in
+        -> device tensors out.  Returns (gx0, gy0, gU [2, 2, n, n] or None)."""
+        np_ = sum(self.counts)
+        if _is_dev(gx_T):
+            gx0 = torch.empty(np_, dtype=torch.float64, device=gx_T.device)
+            gy0 = torch.empty_like(gx0)
+            gU = torch.empty((2, 2, self.n, self.n), dtype=torch.float64,
+                             device=gx_T.device) if want_grid else None
+            self._check(load().lpt_adjoint(self._h, gx_T.data_ptr(), gy_T.data_ptr(),
+                                           gx0.data_ptr(), gy0.data_ptr(),
+                                           gU.data_ptr() if gU is not None else None, 1))
+            return gx0, gy0, gU
+        a = np.ascontiguousarray(gx_T, dtype=np.float64)
+        b = np.ascontiguousarray(gy_T, dtype=np.float64)
+        assert a.size == np_ and b.size == np_
+        gx0, gy0 = np.empty(np_), np.empty(np_)
+        gU = np.empty((2, 2, self.n, self.n)) if want_grid else None
+        self._check(load().lpt_adjoint(self._h, a.ctypes.data, b.ctypes.data, gx0.ctypes.data,
+                                       gy0.ctypes.data,
+                                       gU.ctypes.data if gU is not None else None, 0))
+        return gx0, gy0, gU
+
+    def jacobian(self):
+        """F = dx_T/dx_0 [np, 2, 2] (numpy) of the last checkpointed run."""
+        F = np.empty((sum(self.counts), 2, 2))
+        self._check(load().lpt_jacobian(self._h, F.ctypes.data, 0))
+        return F
+
     def radix_sort(self, keys, key_bits):
         """Stable sort of a device uint32 tensor (as torch.int32 storage);
         returns (sorted keys, permutation) as device tensors."""
@@ -301,3 +339,58 @@ def create_error_status(n, **kw):
     if st == OK:
         lib.lpt_destroy(h)
     return st
+
+
+# ---------------------------------------------------------------------------
+# Autograd: tracer trajectories as a differentiable function of the initial
+# positions and of both velocity snapshots.
+# ---------------------------------------------------------------------------
+if torch is not None:
+
+    class LptTrajectory(torch.autograd.Function):
+        """x_T = Phi(x0, Ua, Ub): nsteps FP64 tracer RK4 steps (see
+        include/lpt.h) through the snapshots Ua = (u, v) at t_a (slot 0) and
+        Ub at t_b (slot 1).  Inputs are CUDA float64 tensors: x0, y0 [np],
+        Ua, Ub [2, n, n].  Returns the unwrapped final positions (xT, yT).
+        The backward pass is the library's reverse sweep over checkpoints
+        every `ckpt_every` steps; it returns gradients for x0, y0, Ua, Ub."""
+
+        @staticmethod
+        def forward(ctx, x0, y0, Ua, Ub, nsteps, dt, scheme="bilinear", ckpt_every=20,
+                    time_mode="bracket", t_slot=(0.0, 1.0)):
+            n = Ua.shape[-1]
+            tr = Tracker(n, "fp64")
+            tr.set_time_mode(time_mode)
+            tr.set_snapshot(0, t_slot[0], Ua[0].contiguous(), Ua[1].contiguous())
+            tr.set_snapshot(1, t_slot[1], Ub[0].contiguous(), Ub[1].contiguous())
+            tr.add_species("tracer", 0.0, scheme, x0.contiguous(), y0.contiguous())
+            tr.forward_checkpointed(nsteps, dt, ckpt_every)
+            xT = torch.empty_like(x0)
+            yT = torch.empty_like(y0)
+            tr.get_positions(0, out=(None, None, xT, yT))
+            ctx.tr = tr
+            return xT, yT
+
+        @staticmethod
+        def backward(ctx, gx, gy):
+            tr = ctx.tr
+            gx = gx.contiguous() if gx is not None else torch.zeros(tr.counts[0], dtype=torch.float64, device="cuda")
+            gy = gy.contiguous() if gy is not None else torch.zeros_like(gx)
+            gx0, gy0, gU = tr.adjoint(gx, gy, want_grid=any(ctx.needs_input_grad[2:4]))
+            tr.close()
+            ctx.tr = None
+            gUa = gU[0] if gU is not None else None
+            gUb = gU[1] if gU is not None else None
+            return gx0, gy0, gUa, gUb, None, None, None, None, None, None
+
+
+def ftle(F, T):
+    """Finite-time Lyapunov exponent (1/T) ln sqrt(lambda_max(F^T F)) of
+    Jacobians F [np, 2, 2] (closed-form largest eigenvalue of the symmetric
+    2x2 Cauchy-Green tensor)."""
+    F = np.asarray(F)
+    a = F[:, 0, 0] ** 2 + F[:, 1, 0] ** 2
+    d = F[:, 0, 1] ** 2 + F[:, 1, 1] ** 2
+    b = F[:, 0, 0] * F[:, 0, 1] + F[:, 1, 0] * F[:, 1, 1]
+    lam = 0.5 * (a + d) + np.sqrt(0.25 * (a - d) ** 2 + b * b)
+    return np.log(np.sqrt(lam)) / T
