@@ -213,6 +213,31 @@ lpt_status lpt_get_timing(lpt_ctx *ctx, lpt_timing *out, int32_t reset);
 /* Number of steps taken and current time. */
 lpt_status lpt_get_time(lpt_ctx *ctx, int64_t *steps, double *t);
 
+/* ---- launch tuning -------------------------------------------------------- */
+/* Launch-shape choices of the step path.  None of them changes a
+ * per-particle result (positions, displacements and velocities are the same
+ * bits with any choice), so an autotuner may pick them for speed.  The
+ * statistics sum per block, so a different block size changes their last
+ * bits; they are run-to-run reproducible for a fixed block size. */
+typedef struct {
+    int32_t block_size;     /* threads per block of the step kernel: 64, 128,
+                               256 or 512 (0 selects 256)                    */
+    int32_t tile_records;   /* as lpt_config.tile_records (0 default, -1 off) */
+    int32_t sort_interval;  /* steps between cell-order re-sorts; 0 = never   */
+    int32_t persistent;     /* 1: launch only as many workgroups as stay
+                               resident; each loops over a contiguous range of
+                               blocks of its own XCD                           */
+    int32_t graph_chunk;    /* > 0: in PINGPONG mode without
+                               LPT_FLAG_TIME_KERNELS, lpt_step captures runs of
+                               this many steps (sorts and statistics included)
+                               into a hipGraph once and replays it             */
+} lpt_tuning;
+
+lpt_status lpt_get_tuning(lpt_ctx *ctx, lpt_tuning *out);
+/* Validated as a whole; on error nothing changes.  Takes effect at the next
+ * step.  Changing the block size reallocates the statistics partials. */
+lpt_status lpt_set_tuning(lpt_ctx *ctx, const lpt_tuning *tuning);
+
 /* ---- derivatives of the discrete tracer map (FP64) ---------------------- */
 /* The paper has no adjoint.  These entry points differentiate exactly the
  * discrete map that lpt_step computes for tracers (eq. rk4_update with the

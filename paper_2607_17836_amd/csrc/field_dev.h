@@ -29,6 +29,22 @@ __device__ __forceinline__ int xcd_logical_block(int b, int G)
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// Persistent launches: XCD x (= blockIdx.x mod X, X = min(8, grid)) owns the
+// contiguous logical blocks [x T / X, (x + 1) T / X) and its workgroups
+// stride through them.  Every workgroup's range ends, so the grid always
+// drains, and every logical block has exactly one owner.
+__device__ __forceinline__ void persistent_range(int T, int &first, int &stride, int &end)
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    const int X = G < 8 ? G : 8;
+    const int x = b % X, k = b / X;
+    const int gx = (G - x + X - 1) / X;   // workgroups on XCD x
+    const int lo = (int)((int64_t)T * x / X), hi = (int)((int64_t)T * (x + 1) / X);
+    first = lo + k;
+    stride = gx;
+    end = hi;
+}
+
 __device__ __forceinline__ int species_of(const StepParams &P, int lb)
 {
     int s = 0;

@@ -57,6 +57,7 @@ struct StepParams {
     float waf[4], wbf[4];
     int32_t ends_one;      // stages 1 and 4 read one level each: h0 and h3
     int32_t h0, h3;
+    int32_t persistent;    // grid sized to residency; workgroups loop over blocks
     int32_t tile_cap;      // LDS tile capacity in node records (0: no tile)
     const float *umax;     // device: largest node speed of slot 0 / 1, cells per unit time
     SpeciesDev sp[kMaxSpecies];

@@ -8,6 +8,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -57,6 +60,13 @@ struct lpt_ctx {
     int32_t sort_interval = 0;
     int32_t sort_tile = 16;
     int32_t tile_cap = 0;    // LDS tile capacity of the step kernel, node records
+    int32_t persistent = 0;  // persistent step launches
+    int32_t graph_chunk = 0; // steps per captured hipGraph (0: eager launches)
+    // executable graphs of step chunks, keyed by (step phase, state buffer,
+    // chunk length, dt bits, stats_every, buffer epoch)
+    std::map<std::tuple<int64_t, int, int64_t, uint64_t, int32_t, uint64_t>, hipGraphExec_t> graphs;
+    uint64_t epoch = 0;      // bumped whenever a buffer a graph may hold changes
+    hipStream_t own_stream = nullptr;   // capture stream when the context uses the null stream
     bool compat_edge = false;
     std::string err;
 
@@ -180,6 +190,7 @@ StepParams make_params(const lpt_ctx *c)
     }
     P.nspecies = (int32_t)c->sp.size();
     P.tile_cap = c->tile_cap;
+    P.persistent = c->persistent;
     P.umax = c->umax;
     P.compat_edge = c->compat_edge ? 1 : 0;
     P.L = c->L;
@@ -208,7 +219,8 @@ void weights_at(const lpt_ctx *c, int64_t step, double t_n, double t, double dt,
                 double &wb)
 {
     if (c->time_mode == LPT_TIME_PINGPONG) {
-        const double theta = (t - t_n) / dt;
+        // t is t_n + c dt with c in {0, 1/2, 1}; take the fraction exactly
+        const double theta = (t - t_n) / dt < 0.25 ? 0.0 : ((t - t_n) / dt < 0.75 ? 0.5 : 1.0);
         const bool slot0_first = (step & 1) == 0;
         wa = slot0_first ? 1.0 - theta : theta;
         wb = slot0_first ? theta : 1.0 - theta;
@@ -413,6 +425,9 @@ void lpt_destroy(lpt_ctx *c)
     dfree(c->clock);
     dfree(c->umax);
     dfree(c->ck);
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     if (c->rec) (void)hipFree(c->rec);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -688,6 +703,13 @@ lpt_status lpt_init_uniform(lpt_ctx *c, int32_t sid, uint64_t seed)
 
 namespace {
 
+void invalidate_graphs(lpt_ctx *c)
+{
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+    c->epoch += 1;
+}
+
 // Argument and state checks shared by lpt_step and lpt_forward_checkpointed.
 lpt_status check_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
 {
@@ -738,6 +760,7 @@ lpt_status grow_records(lpt_ctx *c, int64_t nsteps, int32_t stats_every)
     dfree(c->records);
     c->records = nr;
     c->rec_cap = cap;
+    invalidate_graphs(c);
     return LPT_OK;
 }
 
@@ -768,14 +791,19 @@ void set_dt(StepParams &P, double dt)
 // Enqueue nsteps steps.  With `ckpt`, no re-sort happens, the position of
 // every particle is saved before each step whose index in the run is a
 // multiple of c->ck_every, and every step's temporal weights are kept.
-lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every, bool ckpt)
+lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every, bool ckpt,
+                     bool launch = true)
 {
     StepParams P = make_params(c);
     set_dt(P, dt);
     for (int64_t k = 0; k < nsteps; ++k) {
         if (!ckpt && c->sort_interval > 0 && c->steps % c->sort_interval == 0) {
-            const lpt_status s = do_sort(c);
-            if (s != LPT_OK) return s;
+            if (launch) {
+                const lpt_status s = do_sort(c);
+                if (s != LPT_OK) return s;
+            } else if (c->np > 1) {
+                c->cur = 1 - c->cur;   // what do_sort does to the host state
+            }
         }
         step_weights(c, dt, P);
         if (ckpt) {
@@ -791,6 +819,12 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
             c->ck_w.push_back(w);
         }
         const bool rec = stats_every > 0 && (c->steps + 1) % stats_every == 0;
+        if (!launch) {
+            c->nrec += rec ? 1 : 0;
+            c->t += dt;
+            c->steps += 1;
+            continue;
+        }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->time_kernels) HIP_TRY(c, mark(c, e0));
         if (c->precision == LPT_FP64)
@@ -816,6 +850,78 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
     return LPT_OK;
 }
 
+// Steps in chunks of c->graph_chunk, each captured once into a hipGraph and
+// replayed.  A chunk's kernel parameters depend only on the step number
+// modulo the ping-pong/statistics/sort period, the current state buffer, the
+// chunk length, dt and stats_every, which together key the cache; any
+// reallocation of a buffer a graph holds clears it.  The host bookkeeping
+// (time, step count, records, state buffer) advances exactly as for eager
+// launches.  The step and sort paths hold no memset and no allocation, so
+// they capture cleanly; the sort workspace is allocated before capture.
+lpt_status run_graph_chunks_on(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
+{
+    if (c->sort_interval > 0) {
+        const lpt_status s = ensure_sort_work(c);
+        if (s != LPT_OK) return s;
+    }
+    auto lcm = [](int64_t a, int64_t b) {
+        int64_t x = a, y = b;
+        while (y) {
+            const int64_t t = x % y;
+            x = y;
+            y = t;
+        }
+        return a / x * b;
+    };
+    int64_t period = 2;
+    if (c->sort_interval > 0) period = lcm(period, c->sort_interval);
+    if (stats_every > 0) period = lcm(period, stats_every);
+    uint64_t dt_bits;
+    std::memcpy(&dt_bits, &dt, sizeof dt_bits);
+    while (nsteps > 0) {
+        const int64_t len = std::min<int64_t>(c->graph_chunk, nsteps);
+        const auto key = std::make_tuple(c->steps % period, c->cur, len, dt_bits, stats_every,
+                                         c->epoch);
+        auto it = c->graphs.find(key);
+        hipGraphExec_t exec = nullptr;
+        if (it == c->graphs.end()) {
+            HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            const lpt_status s = run_steps(c, len, dt, stats_every, false, true);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(c->stream, &g);
+            if (s != LPT_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return s;
+            }
+            HIP_TRY(c, e);
+            const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIP_TRY(c, ei);
+            c->graphs.emplace(key, exec);
+        } else {
+            exec = it->second;
+            const lpt_status s = run_steps(c, len, dt, stats_every, false, false);
+            if (s != LPT_OK) return s;
+        }
+        HIP_TRY(c, hipGraphLaunch(exec, c->stream));
+        nsteps -= len;
+    }
+    return LPT_OK;
+}
+
+// Graph chunks need a capturable stream: a context on the null stream
+// captures and replays on a blocking stream of its own, which stays ordered
+// with the null stream.
+lpt_status run_graph_chunks(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
+{
+    if (c->stream) return run_graph_chunks_on(c, nsteps, dt, stats_every);
+    if (!c->own_stream) HIP_TRY(c, hipStreamCreate(&c->own_stream));
+    c->stream = c->own_stream;
+    const lpt_status s = run_graph_chunks_on(c, nsteps, dt, stats_every);
+    c->stream = nullptr;
+    return s;
+}
+
 }  // namespace
 
 lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
@@ -827,7 +933,9 @@ lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
     s = grow_records(c, nsteps, stats_every);
     if (s != LPT_OK) return s;
     c->ck_valid = false;
-    return run_steps(c, nsteps, dt, stats_every, false);
+    if (c->graph_chunk <= 0 || c->time_mode != LPT_TIME_PINGPONG || c->time_kernels)
+        return run_steps(c, nsteps, dt, stats_every, false);
+    return run_graph_chunks(c, nsteps, dt, stats_every);
 }
 
 lpt_status lpt_forward_checkpointed(lpt_ctx *c, int64_t nsteps, double dt, int32_t ckpt_every)
@@ -1222,6 +1330,61 @@ lpt_status lpt_radix_sort(lpt_ctx *c, int64_t npts, int32_t key_bits, const uint
     release();
     if (e != hipSuccess) s = fail(c, LPT_E_HIP, std::string("radix sort: ") + hipGetErrorString(e));
     return s;
+}
+
+lpt_status lpt_get_tuning(lpt_ctx *c, lpt_tuning *out)
+{
+    if (!c) return LPT_E_ARG;
+    if (!out) return fail(c, LPT_E_ARG, "out must not be NULL");
+    out->block_size = c->block;
+    out->tile_records = c->tile_cap > 0 ? c->tile_cap : -1;
+    out->sort_interval = c->sort_interval;
+    out->persistent = c->persistent;
+    out->graph_chunk = c->graph_chunk;
+    return LPT_OK;
+}
+
+lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
+{
+    if (!c) return LPT_E_ARG;
+    if (!t) return fail(c, LPT_E_ARG, "tuning must not be NULL");
+    const int32_t block = t->block_size == 0 ? 256 : t->block_size;
+    if (block != 64 && block != 128 && block != 256 && block != 512)
+        return fail(c, LPT_E_ARG, "block_size must be 64, 128, 256 or 512");
+    const size_t rec_size = c->precision == LPT_FP64 ? sizeof(Rec64) : sizeof(float4);
+    int32_t tile = t->tile_records;
+    if (tile == 0) tile = (int32_t)(kTileBytesDefault / rec_size);
+    else if (tile == -1) tile = 0;
+    else if (tile < 16 || (size_t)tile > kTileBytesMax / rec_size)
+        return fail(c, LPT_E_ARG, "tile_records out of range");
+    if (t->sort_interval < 0) return fail(c, LPT_E_ARG, "sort_interval must be >= 0");
+    if (t->persistent != 0 && t->persistent != 1) return fail(c, LPT_E_ARG, "persistent is 0 or 1");
+    if (t->graph_chunk < 0) return fail(c, LPT_E_ARG, "graph_chunk must be >= 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (block != c->block) {
+        // the statistics partials hold one slot per logical block
+        const int32_t old = c->block;
+        c->block = block;
+        const StepParams P = make_params(c);
+        if (P.total_blocks > c->partial_blocks) {
+            double *np = nullptr;
+            if (dalloc(np, (size_t)kStatTerms * P.total_blocks) != hipSuccess) {
+                c->block = old;
+                (void)hipGetLastError();
+                return fail(c, LPT_E_NOMEM, "statistics partials allocation failed");
+            }
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            dfree(c->partials);
+            c->partials = np;
+            c->partial_blocks = P.total_blocks;
+        }
+    }
+    c->tile_cap = tile;
+    c->sort_interval = t->sort_interval;
+    c->persistent = t->persistent;
+    c->graph_chunk = t->graph_chunk;
+    invalidate_graphs(c);
+    return LPT_OK;
 }
 
 lpt_status lpt_bw_probe(lpt_ctx *c, int64_t bytes, int32_t iters, double *copy_gbps,

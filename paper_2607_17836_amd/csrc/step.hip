@@ -55,13 +55,12 @@ __device__ __forceinline__ void stencil_reach(int scheme, int &lo, int &hi)
 }
 
 template <bool CUBIC, bool INERTIAL, bool STATS>
-__global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64 S,
-                                                           const Rec64 *__restrict__ rec,
-                                                           double *__restrict__ partials,
-                                                           DevClock *clock)
+__device__ __forceinline__ void step64_block(const StepParams &P, const State64 &S,
+                                             const Rec64 *__restrict__ rec,
+                                             double *__restrict__ partials, DevClock *clock,
+                                             int lb)
 {
     Rec64 *lds = reinterpret_cast<Rec64 *>(lpt_dyn_lds);
-    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const SpeciesDev &sp = P.sp[species_of(P, lb)];
     const int64_t base = (int64_t)(lb - sp.block_begin) * blockDim.x;
     const int64_t local = base + threadIdx.x;
@@ -136,6 +135,23 @@ __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64
         clock->t += P.dt;
         clock->step += 1;
     }
+}
+
+template <bool CUBIC, bool INERTIAL, bool STATS>
+__global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64 S,
+                                                           const Rec64 *__restrict__ rec,
+                                                           double *__restrict__ partials,
+                                                           DevClock *clock)
+{
+    if (!P.persistent) {
+        step64_block<CUBIC, INERTIAL, STATS>(P, S, rec, partials, clock,
+                                             xcd_logical_block(blockIdx.x, gridDim.x));
+        return;
+    }
+    int first, stride, end;
+    persistent_range(P.total_blocks, first, stride, end);
+    for (int lb = first; lb < end; lb += stride)
+        step64_block<CUBIC, INERTIAL, STATS>(P, S, rec, partials, clock, lb);
 }
 
 // ===========================================================================
@@ -435,13 +451,12 @@ constexpr bool scheme_compiled()
 }
 
 template <int SCHS, int KINDS, bool STATS>
-__global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32 S,
-                                                           const float4 *__restrict__ rec,
-                                                           double *__restrict__ partials,
-                                                           DevClock *clock)
+__device__ __forceinline__ void step32_block(const StepParams &P, const State32 &S,
+                                             const float4 *__restrict__ rec,
+                                             double *__restrict__ partials, DevClock *clock,
+                                             int lb)
 {
     float4 *lds = reinterpret_cast<float4 *>(lpt_dyn_lds);
-    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const SpeciesDev &sp = P.sp[P.nspecies > 1 ? species_of(P, lb) : 0];
     const int64_t base = (int64_t)(lb - sp.block_begin) * blockDim.x;
     const int64_t local = base + threadIdx.x;
@@ -497,13 +512,61 @@ __global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32
     }
 }
 
+// One launch advances every particle by one step.  Normal launches map one
+// workgroup to one logical block (XCD-aware order); with P.persistent set the
+// grid is sized to the resident capacity and each workgroup walks a
+// contiguous range of logical blocks of its own XCD.
+template <int SCHS, int KINDS, bool STATS>
+__global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32 S,
+                                                           const float4 *__restrict__ rec,
+                                                           double *__restrict__ partials,
+                                                           DevClock *clock)
+{
+    if (!P.persistent) {
+        step32_block<SCHS, KINDS, STATS>(P, S, rec, partials, clock,
+                                         xcd_logical_block(blockIdx.x, gridDim.x));
+        return;
+    }
+    int first, stride, end;
+    persistent_range(P.total_blocks, first, stride, end);
+    for (int lb = first; lb < end; lb += stride)
+        step32_block<SCHS, KINDS, STATS>(P, S, rec, partials, clock, lb);
+}
+
+// Grid of a launch: one workgroup per logical block, or -- when the step
+// parameters ask for a persistent launch -- as many workgroups as the device
+// keeps resident (occupancy of this kernel at this block size and LDS size,
+// times the CU count), if that is fewer.
+template <typename K>
+static int launch_grid(K kernel, const StepParams &P, int block, size_t lds, int grid,
+                       StepParams &Q)
+{
+    Q = P;
+    Q.persistent = 0;
+    if (!P.persistent) return grid;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess ||
+        per_cu < 1) {
+        (void)hipGetLastError();
+        return grid;
+    }
+    const int64_t resident = (int64_t)per_cu * cus;
+    if (resident >= grid) return grid;
+    Q.persistent = 1;
+    return (int)resident;
+}
+
 template <bool C, bool I, bool S>
 static hipError_t launch64_t(const StepParams &P, const State64 &St, const Rec64 *rec,
                              double *partials, DevClock *clock, int block, int grid,
                              hipStream_t st)
 {
     const size_t lds = P.tile_cap > 0 ? (size_t)P.tile_cap * sizeof(Rec64) : 0;
-    hipLaunchKernelGGL((step64_kernel<C, I, S>), dim3(grid), dim3(block), lds, st, P, St, rec,
+    StepParams Q;
+    const int g = launch_grid(step64_kernel<C, I, S>, P, block, lds, grid, Q);
+    hipLaunchKernelGGL((step64_kernel<C, I, S>), dim3(g), dim3(block), lds, st, Q, St, rec,
                        partials, clock);
     return hipGetLastError();
 }
@@ -514,7 +577,9 @@ static hipError_t launch32_t(const StepParams &P, const State32 &St, const float
                              hipStream_t st)
 {
     const size_t lds = P.tile_cap > 0 ? (size_t)P.tile_cap * sizeof(float4) : 0;
-    hipLaunchKernelGGL((step32_kernel<SCHS, KINDS, ST>), dim3(grid), dim3(block), lds, st, P, St,
+    StepParams Q;
+    const int g = launch_grid(step32_kernel<SCHS, KINDS, ST>, P, block, lds, grid, Q);
+    hipLaunchKernelGGL((step32_kernel<SCHS, KINDS, ST>), dim3(g), dim3(block), lds, st, Q, St,
                        rec, partials, clock);
     return hipGetLastError();
 }

@@ -42,6 +42,12 @@ class LptConfig(C.Structure):
     ]
 
 
+class LptTuning(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("tile_records", C.c_int32),
+                ("sort_interval", C.c_int32), ("persistent", C.c_int32),
+                ("graph_chunk", C.c_int32)]
+
+
 class LptTiming(C.Structure):
     _fields_ = [("step_kernel_ms", C.c_double), ("step_launches", C.c_int64),
                 ("sort_ms", C.c_double), ("sorts", C.c_int64)]
@@ -75,6 +81,8 @@ _SIGS = [
     ("lpt_interp", C.c_int, [_P, C.c_int, C.c_int64, _P, _P, C.c_double, C.c_double, _P, _P,
                              C.c_int32]),
     ("lpt_radix_sort", C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, _P]),
+    ("lpt_get_tuning", C.c_int, [_P, C.POINTER(LptTuning)]),
+    ("lpt_set_tuning", C.c_int, [_P, C.POINTER(LptTuning)]),
     ("lpt_forward_checkpointed", C.c_int, [_P, C.c_int64, C.c_double, C.c_int32]),
     ("lpt_adjoint", C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int32]),
     ("lpt_jacobian", C.c_int, [_P, _P, C.c_int32]),
@@ -274,6 +282,18 @@ class Tracker:
         cp, tr = C.c_double(), C.c_double()
         self._check(load().lpt_bw_probe(self._h, int(nbytes), int(iters), C.byref(cp), C.byref(tr)))
         return cp.value, tr.value
+
+    # -- tuning -----------------------------------------------------------
+    def get_tuning(self):
+        t = LptTuning()
+        self._check(load().lpt_get_tuning(self._h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in LptTuning._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = LptTuning(**cur)
+        self._check(load().lpt_set_tuning(self._h, C.byref(t)))
 
     # -- derivatives (FP64 tracers) ---------------------------------------
     def forward_checkpointed(self, nsteps, dt, ckpt_every):

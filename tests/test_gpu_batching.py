@@ -1,0 +1,156 @@
+"""Launch-shape choices never change results: persistent launches, hipGraph
+step chunks and tuning changes are checked bit for bit against plain eager
+launches, and the batched multi-species launch against one context per
+species (through the C ABI)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_17836_amd import lpt, synth, workloads
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = ["bilinear", "catmull_rom", "bspline"]
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def _mixed(precision, n=128, dt=0.002, **tr_kw):
+    (ua, va), (ub, vb) = synth.spectrum_snapshots(n, 8, 12, dt)
+    tr = lpt.Tracker(n, precision, **tr_kw)
+    tr.set_time_mode("pingpong")
+    tr.set_snapshot(0, 0.0, ua, va)
+    tr.set_snapshot(1, dt, ub, vb)
+    sids = []
+    for k, (kind, st, sch, cnt) in enumerate([("tracer", 0.0, "bilinear", 5000),
+                                             ("inertial", 0.05, "catmull_rom", 3001),
+                                             ("inertial", 1.0, "bspline", 777),
+                                             ("tracer", 0.0, "bspline", 64)]):
+        z = np.zeros(cnt)
+        sids.append(tr.add_species(kind, st, sch, z, z))
+        tr.init_uniform(sids[-1], 300 + k)
+    return tr, sids
+
+
+def _snap(tr, sids):
+    out = []
+    for s in sids:
+        out += list(tr.get_positions(s))
+        if s in (1, 2):
+            out += list(tr.get_velocities(s))
+        out.append(tr.get_stats(s)["msd"])
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
+def test_persistent_launches_match_normal_launches(precision):
+    say(f"persistent {precision}")
+    outs = []
+    for persistent in (0, 1):
+        tr, sids = _mixed(precision, sort_interval=5)
+        tr.set_tuning(persistent=persistent)
+        tr.step(23, 0.002, stats_every=4)
+        outs.append(_snap(tr, sids))
+        tr.close()
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
+def test_graph_chunks_replay_exactly_like_eager_steps(precision):
+    """Chunks of 6 steps captured once and replayed several times, with eager
+    readouts and synchronisations in between, against eager stepping in
+    lockstep; both sort every 4 steps and take statistics every 3."""
+    say(f"graphs {precision}")
+    eager, sids = _mixed(precision, sort_interval=4)
+    graph, _ = _mixed(precision, sort_interval=4)
+    graph.set_tuning(graph_chunk=6, persistent=1)
+    for rnd, nsteps in enumerate((6, 6, 12, 5, 6, 13)):
+        eager.step(nsteps, 0.002, stats_every=3)
+        graph.step(nsteps, 0.002, stats_every=3)
+        graph.synchronize()
+        for a, b in zip(_snap(eager, sids), _snap(graph, sids)):
+            np.testing.assert_array_equal(a, b, err_msg=f"round {rnd}")
+    assert graph.get_time() == eager.get_time()
+    eager.close()
+    graph.close()
+
+
+def test_tuning_is_validated_and_changes_nothing_on_error():
+    tr, _ = _mixed("fp32_split")
+    before = tr.get_tuning()
+    for bad in (dict(block_size=96), dict(tile_records=3), dict(sort_interval=-1),
+                dict(persistent=2), dict(graph_chunk=-5), dict(tile_records=100000)):
+        with pytest.raises(lpt.LptError) as e:
+            tr.set_tuning(**bad)
+        assert e.value.status == lpt.E_ARG
+        assert tr.get_tuning() == before
+    tr.set_tuning(block_size=512, tile_records=2400, sort_interval=7, persistent=1,
+                  graph_chunk=10)
+    assert tr.get_tuning() == dict(block_size=512, tile_records=2400, sort_interval=7,
+                                   persistent=1, graph_chunk=10)
+    tr.close()
+
+
+def test_block_size_change_mid_run_keeps_results():
+    """Per-particle state is bit-identical across block sizes; statistics sum
+    per block, so they agree to rounding."""
+    say("block size change")
+    outs = []
+    for blocks in ((256, 256), (128, 512)):
+        tr, sids = _mixed("fp32_split", sort_interval=3)
+        tr.set_tuning(block_size=blocks[0])
+        tr.step(9, 0.002, stats_every=3)
+        tr.set_tuning(block_size=blocks[1])
+        tr.step(9, 0.002, stats_every=3)
+        outs.append(_snap(tr, sids))
+        tr.close()
+    for a, b in zip(*outs):
+        if a.size == 6:   # statistics: the block-level reduction tree follows the block size
+            np.testing.assert_allclose(a, b, rtol=1e-14)
+        else:
+            np.testing.assert_array_equal(a, b)
+
+
+def test_batched_species_match_one_context_per_species():
+    """The batching workload's species mix (8 Stokes numbers, uneven counts,
+    scheme k mod 3; reduced counts and grid) in one launch per step gives
+    every particle exactly the state it gets when its species runs alone."""
+    n, dt = 256, 1e-3
+    (ua, va), (ub, vb) = synth.spectrum_snapshots(n, 10, 4, dt)
+    mix = [(("inertial" if st > 0 else "tracer"), st, SCHEMES[k % 3], 1000 + 613 * k, 40 + k)
+           for k, st in enumerate(workloads.C4_STS)]
+
+    def build(species):
+        tr = lpt.Tracker(n, "fp32_split", sort_interval=10)
+        tr.set_time_mode("pingpong")
+        tr.set_snapshot(0, 0.0, ua, va)
+        tr.set_snapshot(1, dt, ub, vb)
+        ids = []
+        for kind, st, sch, cnt, seed in species:
+            z = np.zeros(cnt)
+            ids.append(tr.add_species(kind, st, sch, z, z))
+            tr.init_uniform(ids[-1], seed)
+        return tr, ids
+
+    say("batched")
+    tr, ids = build(mix)
+    tr.set_tuning(graph_chunk=10, persistent=1)
+    tr.step(40, dt, stats_every=20)
+    batched = [(tr.get_positions(s), tr.get_velocities(s) if mix[k][0] == "inertial" else None,
+                tr.get_stats(s)) for k, s in enumerate(ids)]
+    tr.close()
+    for k, spec in enumerate(mix):
+        say(f"alone {k}")
+        one, (sid,) = build([spec])
+        one.step(40, dt, stats_every=20)
+        for a, b in zip(batched[k][0], one.get_positions(sid)):
+            np.testing.assert_array_equal(a, b)
+        if spec[0] == "inertial":
+            for a, b in zip(batched[k][1], one.get_velocities(sid)):
+                np.testing.assert_array_equal(a, b)
+        st = one.get_stats(sid)
+        np.testing.assert_allclose(batched[k][2]["msd"], st["msd"], rtol=1e-13)
+        one.close()
