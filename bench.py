@@ -1,19 +1,25 @@
 """Benchmark of the particle hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 
-Workload (the headline configuration): a 4096^2 doubly periodic grid with two
-FP32 velocity snapshots from the k0 = 20 random-phase spectrum (ping-pong time
-levels, dt = 1e-3), 2^24 passive tracers in split form (int cell + FP32
-offset, FP64 displacement), bilinear interpolation.  One step = one RK4 step
-of every particle (cell location, 4 stages of spatial + temporal
+Default workload (the headline configuration): a 4096^2 doubly periodic grid
+with two FP32 velocity snapshots from the k0 = 20 random-phase spectrum
+(ping-pong time levels, dt = 1e-3), 2^24 passive tracers in split form (int
+cell + FP32 offset, FP64 displacement), bilinear interpolation.  One step =
+one RK4 step of every particle (cell location, 4 stages of spatial + temporal
 interpolation, combine, wrap, FP64 displacement), plus the cell-order re-sort
 every 20 steps and the FP64 MSD/dispersion reduction every 100 steps, all
 inside the timed region.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  The roofline object reports the step kernel's
+Other workloads (--workload): batch2048 (8 Stokes-number species, all three
+schemes, autotuned launch shape), spec1024_fp64 (FP64 tracers + inertial
+particles, --scheme), tg64 (FP64 Taylor-Green, 4096 tracers) and adjoint2048
+(FP64 checkpointed forward run plus reverse sweep with grid gradients).
+
+Prints one JSON line.  The roofline object reports the dominant kernel's
 algorithmic bytes per launch over its average duration, measured with HIP
-events on the stream it runs on, against the 8 TB/s HBM peak.
+events recorded by the library on the stream the kernel runs on, against the
+8 TB/s HBM peak.
 """
 from __future__ import annotations
 
@@ -32,36 +38,63 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s (RK4+interp) at 2^24 particles, 4096² grid; HBM GB/s fraction"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step32_spec4096_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2607_17836_amd", "csrc", "step.hip")
+CSRC = os.path.join(ROOT, "paper_2607_17836_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def state_bytes(precision: str, kind: str) -> int:
+def state_bytes(precision: str, kind: str, st: float) -> int:
     """Bytes of one particle's state read (and again written) per step."""
+    inertial = kind == "inertial" and st > 0
     if precision == "fp32_split":   # packed cell u32 + float2 offset + double2 displacement
-        return 4 + 8 + 16 + (8 if kind == "inertial" else 0)
-    return 16 + 16 + (16 if kind == "inertial" else 0)   # double2 pos + double2 disp
+        return 4 + 8 + 16 + (8 if inertial else 0)
+    return 16 + 16 + (16 if inertial else 0)   # double2 pos + double2 disp (+ double2 vel)
 
 
 def field_pair_bytes(n: int, precision: str) -> int:
+    """Both time levels of every grid node (u, v each), read once per step."""
     return n * n * (16 if precision == "fp32_split" else 32)
 
 
+def alg_bytes_per_step(w) -> float:
+    state = sum(cnt * 2 * state_bytes(w.precision, kind, st) for kind, st, _, cnt, _ in w.species)
+    return state + field_pair_bytes(w.n, w.precision)
+
+
 def kernel_source_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
 
 
-def run_gpu(w, steps, warmup, lpt, **over):
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary, if it was taken with the current kernel sources."""
+    path = os.path.join(PROFILES, f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    tf = json.load(open(path))
+    if tf.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return tf.get("hbm_bytes_per_launch")
+
+
+def run_gpu(w, steps, warmup, lpt, tuning=None, **over):
+    """Time `steps` steps after `warmup` untimed ones.  Returns (elapsed s,
+    library timing dict, stats records of species 0).  Per-kernel HIP events
+    are on (graph chunks are then replaced by eager launches)."""
     import torch
+    from paper_2607_17836_amd import workloads
     tr = None
     try:
-        from paper_2607_17836_amd import workloads
         t0 = time.perf_counter()
         tr = workloads.build_tracker(w, lpt, time_kernels=True, **over)
+        if tuning:
+            tr.set_tuning(**tuning)
         tr.synchronize()
         log(f"[bench] setup of {w.name}: {time.perf_counter() - t0:.1f} s")
         tr.step(warmup, w.dt, w.stats_every)
@@ -83,26 +116,150 @@ def run_gpu(w, steps, warmup, lpt, **over):
 
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle (single thread, as written) on a bounded sample of the
-    same workload: the same fields in FP64, a prefix of the same particles."""
+    same workload: the same fields in FP64, a prefix of each species'
+    particles, 20 steps."""
     import oracle
-    a, b, _ = w.snapshots()
-    fl = oracle.grid_flow(a[0], a[1], b[0], b[1], scheme="bilinear", time_mode=oracle.PINGPONG)
-    x0, y0 = oracle.init_uniform(w.species[0][4], 1 << 20)
-    # calibrate on a small batch, then size the sample to ~budget_s
-    sp = oracle.Species(x0[:4096], y0[:4096])
+    a, b, (ta, tb) = w.snapshots()
+    tm = oracle.PINGPONG if w.time_mode == "pingpong" else oracle.BRACKET
+    flows = {}
+    sps = []
+    frac = None
+    for kind, st, scheme, count, seed in w.species:
+        if scheme not in flows:
+            flows[scheme] = oracle.grid_flow(a[0], a[1], b[0], b[1], scheme=scheme, time_mode=tm,
+                                             t_slot=(ta, tb))
+        sps.append((flows[scheme], kind, st, count, seed))
+    # calibrate on a small batch of the first species, then size the sample
+    fl, kind, st, count, seed = sps[0]
+    x0, y0 = oracle.init_uniform(seed, 2048)
     t0 = time.perf_counter()
-    oracle.run(fl, sp, 5, w.dt)
-    per = (time.perf_counter() - t0) / (4096 * 5)
-    count = int(min(1 << 20, max(4096, budget_s / per / 20)))
+    oracle.run(fl, oracle.Species(x0, y0), 3, w.dt)
+    per = (time.perf_counter() - t0) / (2048 * 3)
     nsteps = 20
-    sp = oracle.Species(x0[:count], y0[:count])
-    t0 = time.perf_counter()
-    oracle.run(fl, sp, nsteps, w.dt, stats_every=10)
-    el = time.perf_counter() - t0
-    return {"value": count * nsteps / el, "unit": "particle-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{count} of the 2^24 tracers x {nsteps} steps on the same 4096^2 fields "
-                      f"(FP64), {el:.1f} s, single-threaded C oracle"}
+    total = sum(s[3] for s in sps)
+    frac = min(1.0, budget_s / per / nsteps / total)
+    done, el = 0, 0.0
+    for fl, kind, st, count, seed in sps:
+        m = max(64, int(count * frac))
+        x0, y0 = oracle.init_uniform(seed, m)
+        if kind == "inertial" and st > 0:
+            u0, v0 = oracle.velocity(fl, x0, y0, ta, step=0, t_n=ta, dt=w.dt)
+            sp = oracle.Species(x0, y0, kind=oracle.INERTIAL, st=st, vx0=u0, vy0=v0)
+        else:
+            sp = oracle.Species(x0, y0)
+        t0 = time.perf_counter()
+        oracle.run(fl, sp, nsteps, w.dt, stats_every=10)
+        el += time.perf_counter() - t0
+        done += m * nsteps
+    return {"value": done / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done // nsteps} particles (the first {frac:.3%} of each species of "
+                      f"{w.name}) x {nsteps} steps on the same {w.n}^2 fields in FP64, "
+                      f"{el:.1f} s, single-threaded C oracle"}
+
+
+def step_kernel_name(w):
+    schemes = {s[2] for s in w.species}
+    inertial = any(k == "inertial" and st > 0 for k, st, _, _, _ in w.species)
+    sch = schemes.pop() if len(schemes) == 1 else "mixed schemes"
+    kind = "tracers + inertial" if inertial else "tracers"
+    return f"step{'32' if w.precision == 'fp32_split' else '64'}_kernel<{sch}, {kind}>"
+
+
+def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False):
+    over = {}
+    if args.tile_records:
+        over["tile_records"] = args.tile_records
+    if args.block_size:
+        over["block_size"] = args.block_size
+    npart = w.particles
+    elapsed, timing, nstats = run_gpu(w, args.steps, args.warmup, lpt, tuning, **over)
+    value = npart * args.steps / elapsed
+    kern_ms = timing["step_kernel_ms"] / max(1, timing["step_launches"])
+    bytes_per_launch = alg_bytes_per_step(w)
+    achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
+    log(f"[bench] {args.steps} steps in {elapsed:.3f} s; step kernel {kern_ms * 1e3:.1f} us avg "
+        f"over {timing['step_launches']} launches; sort {timing['sort_ms']:.2f} ms over "
+        f"{timing['sorts']} sorts; {nstats} stats records")
+    extra = {}
+    if fp64_twin and not args.no_fp64:
+        w64 = dataclasses.replace(w, name=w.name.replace("fp32split", "fp64"), precision="fp64")
+        k64 = max(100, args.steps // 4)
+        e64, t64, _ = run_gpu(w64, k64, min(args.warmup, 20), lpt, tuning, **over)
+        k64us = 1e3 * t64["step_kernel_ms"] / max(1, t64["step_launches"])
+        extra["fp64_same_workload"] = {
+            "value": npart * k64 / e64, "unit": "particle-steps/s", "steps": k64,
+            "step_kernel_us": k64us,
+            "achieved_gbps": alg_bytes_per_step(w64) / (k64us * 1e-6) / 1e9}
+        log(f"[bench] FP64 path on the same workload: {npart * k64 / e64:.3e} particle-steps/s")
+    tun = dict(tuning or {})
+    cfg = {"workload": w.name, "grid": w.n, "particles": npart, "precision": w.precision,
+           "species": [{"kind": k, "St": st, "scheme": sch, "count": cnt}
+                       for k, st, sch, cnt, _ in w.species],
+           "dt": w.dt, "time_mode": w.time_mode,
+           "sort_interval": tun.get("sort_interval", w.sort_interval),
+           "sort_tile": w.sort_tile, "stats_every": w.stats_every,
+           "tile_records": tun.get("tile_records", args.tile_records),
+           "block_size": tun.get("block_size", args.block_size or 256),
+           "persistent": tun.get("persistent", 0), "parallelism": "1 GPU"}
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
+            "kernel": step_kernel_name(w), "kernel_avg_us": kern_ms * 1e3,
+            "alg_bytes_per_particle_step": bytes_per_launch / npart,
+            "alg_bytes_per_launch": bytes_per_launch}
+    return value, 1e3 * elapsed / args.steps, cfg, roof, extra
+
+
+def bench_adjoint(args, lpt):
+    """2048^2 FP64 steady Taylor-Green + 0.1 x (k0 = 10 spectrum), 2^22
+    tracers on the cell-centre lattice, bilinear, 200 steps of dt = 0.01 with
+    checkpoints every 20: the checkpointed forward run, the reverse sweep with
+    grid gradients of L = sum(a x_T + b y_T), and the Jacobian sweep."""
+    import torch
+    from paper_2607_17836_amd import synth
+    n, nsteps, dt, every = 2048, 200, 0.01, 20
+    u, v, _ = synth.taylor_green(n)
+    (pu, pv), _ = synth.spectrum_snapshots(n, 10, 5, dt)
+    u, v = u + 0.1 * pu, v + 0.1 * pv
+    x0, y0 = synth.lattice_points(n, 2048)
+    npart = x0.size
+    rng = np.random.default_rng(51)
+    dev = "cuda"
+    a = torch.tensor(rng.normal(size=npart), device=dev)
+    b = torch.tensor(rng.normal(size=npart), device=dev)
+    tr = lpt.Tracker(n, "fp64")
+    tr.set_snapshot(0, 0.0, u, v)
+    tr.set_snapshot(1, nsteps * dt, u, v)
+    tr.add_species("tracer", 0.0, "bilinear", x0, y0)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    t_fwd, _ = timed(lambda: tr.forward_checkpointed(nsteps, dt, every))
+    t_adj, (gx, gy, gU) = timed(lambda: tr.adjoint(a, b))
+    t_jac, F = timed(lambda: tr.jacobian())
+    sig = lpt.ftle(F, nsteps * dt)
+    tr.close()
+    log(f"[bench] adjoint2048: forward {t_fwd:.3f} s, reverse+grid {t_adj:.3f} s, "
+        f"jacobian {t_jac:.3f} s; FTLE mean {np.mean(sig):.4f}, max {np.max(sig):.4f}")
+    value = npart * nsteps / (t_fwd + t_adj)
+    # reverse sweep per particle-step: tape read + recompute write + read
+    # (3 x 16 B), adjoint vector read + write (32 B), and one field pass
+    bpps = 3 * 16 + 32 + field_pair_bytes(n, "fp64") / npart
+    cfg = {"workload": "adjoint2048_fp64_tg_lattice_2p22", "grid": n, "particles": npart,
+           "precision": "fp64", "scheme": "bilinear", "dt": dt, "steps": nsteps,
+           "ckpt_every": every, "parallelism": "1 GPU"}
+    roof = {"bound": "hbm", "achieved": bpps * npart * nsteps / t_adj / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": bpps * npart * nsteps / t_adj / 1e9 / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "reverse sweep (recompute64 + adjoint64<1> with FP64 atomic scatter)",
+            "alg_bytes_per_particle_step": bpps,
+            "seconds": {"forward": t_fwd, "reverse_with_grid": t_adj, "jacobian": t_jac}}
+    return value, 1e3 * (t_fwd + t_adj) / nsteps, cfg, roof
 
 
 def main():
@@ -110,6 +267,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="spec4096_split",
+                    choices=["spec4096_split", "batch2048", "spec1024_fp64", "tg64",
+                             "adjoint2048"])
+    ap.add_argument("--scheme", default="bilinear", choices=["bilinear", "catmull_rom", "bspline"],
+                    help="scheme of the spec1024_fp64 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--tile-records", type=int, default=0,
@@ -121,8 +283,8 @@ def main():
                     help="only run the copy/triad bandwidth probe and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
-              f"multi-GPU path", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build runs the "
+              f"particle path on a single GPU and has no multi-GPU mode", file=sys.stderr)
         sys.exit(2)
 
     from paper_2607_17836_amd import lpt, workloads
@@ -135,59 +297,58 @@ def main():
         print(json.dumps({"copy_gbps": copy_gbs, "triad_gbps": triad_gbs,
                           "bytes_per_buffer": 1 << 30, "iters": 10}), flush=True)
         return
-    w = workloads.C3_SPLIT
-    if args.sort_interval is not None:
-        w = dataclasses.replace(w, sort_interval=args.sort_interval)
-    over = dict(tile_records=args.tile_records, block_size=args.block_size)
-    npart = w.particles
-    elapsed, timing, nstats = run_gpu(w, args.steps, args.warmup, lpt, **over)
-    value = npart * args.steps / elapsed
-    ms_per_step = 1e3 * elapsed / args.steps
-    kern_ms = timing["step_kernel_ms"] / max(1, timing["step_launches"])
-    b_alg = 2 * state_bytes(w.precision, "tracer") + field_pair_bytes(w.n, w.precision) / npart
-    bytes_per_launch = b_alg * npart
-    achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tf = json.load(open(TRAFFIC_FILE))
-        if tf.get("kernel_source_sha256_16") == kernel_source_hash():
-            traffic = tf.get("hbm_bytes_per_launch")
-    log(f"[bench] {args.steps} steps in {elapsed:.3f} s; step kernel {kern_ms * 1e3:.1f} us avg "
-        f"over {timing['step_launches']} launches; sort {timing['sort_ms']:.2f} ms over "
-        f"{timing['sorts']} sorts; {nstats} stats records")
 
     extra = {}
-    if not args.no_fp64:
-        w64 = workloads.Workload(w.name.replace("fp32split", "fp64"), w.n, "fp64", w.field, w.k0,
-                                 w.field_seed, w.dt, w.time_mode, w.steps, w.stats_every,
-                                 w.sort_interval, w.sort_tile, w.species)
-        k64 = max(100, args.steps // 4)
-        e64, t64, _ = run_gpu(w64, k64, min(args.warmup, 20), lpt, **over)
-        extra["fp64_same_workload"] = {
-            "value": npart * k64 / e64, "unit": "particle-steps/s", "steps": k64,
-            "step_kernel_us": 1e3 * t64["step_kernel_ms"] / max(1, t64["step_launches"])}
-        log(f"[bench] FP64 path on the same workload: {npart * k64 / e64:.3e} particle-steps/s")
-
+    dtype = "f32"
+    metric = METRIC
+    w = None
+    if args.workload == "adjoint2048":
+        value, ms_per_step, cfg, roof = bench_adjoint(args, lpt)
+        dtype = "f64"
+        metric = "particle-steps/s (checkpointed forward + reverse sweep with grid gradient)"
+        args.steps, args.warmup = 200, 0
+    else:
+        tuning = None
+        fp64_twin = False
+        if args.workload == "spec4096_split":
+            w = workloads.C3_SPLIT
+            fp64_twin = True
+        elif args.workload == "batch2048":
+            import torch
+            from paper_2607_17836_amd import autotune
+            w = workloads.C4_BATCH
+            tuning, ms, hit = autotune.cached_or_tune(
+                w, lpt, workloads, torch.cuda.get_device_name(0),
+                log=lambda m: None)
+            tuning = dict(tuning, graph_chunk=0)   # per-kernel events need eager launches
+            log(f"[bench] autotuned launch shape ({'cached' if hit else 'tuned now'}): {tuning}")
+        elif args.workload == "spec1024_fp64":
+            w = workloads.c2_spectrum(args.scheme)
+            dtype = "f64"
+        else:
+            w = workloads.C1_TG
+            dtype = "f64"
+            # steady field: the bracket just has to cover warm-up + timed steps
+            w = dataclasses.replace(w, steps=max(w.steps, args.steps + args.warmup))
+        if args.sort_interval is not None:
+            w = dataclasses.replace(w, sort_interval=args.sort_interval)
+        value, ms_per_step, cfg, roof, extra = bench_steps(args, lpt, workloads, w, tuning,
+                                                           fp64_twin)
+        if w.precision == "fp64":
+            dtype = "f64"
+        if w is not workloads.C3_SPLIT:
+            metric = f"particle-steps/s (RK4+interp), {w.name}"
+    roof["achievable_copy_gbps"] = copy_gbs
+    roof["achievable_triad_gbps"] = triad_gbs
+    roof["frac_of_copy"] = roof["achieved"] / copy_gbs
     out = {
-        "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+        "metric": metric, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": w.name, "grid": w.n, "particles": npart, "precision": w.precision,
-                   "scheme": "bilinear", "dt": w.dt, "time_mode": w.time_mode,
-                   "sort_interval": w.sort_interval, "sort_tile": w.sort_tile,
-                   "stats_every": w.stats_every, "tile_records": args.tile_records,
-                   "block_size": args.block_size, "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "step32_kernel<bilinear, tracer>",
-                     "kernel_avg_us": kern_ms * 1e3, "alg_bytes_per_particle_step": b_alg,
-                     "alg_bytes_per_launch": bytes_per_launch,
-                     "achievable_copy_gbps": copy_gbs, "achievable_triad_gbps": triad_gbs,
-                     "frac_of_copy": achieved / copy_gbs},
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic", "config": cfg, "roofline": roof,
     }
     out.update(extra)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and w is not None:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 

@@ -238,6 +238,12 @@ lpt_status lpt_get_tuning(lpt_ctx *ctx, lpt_tuning *out);
  * step.  Changing the block size reallocates the statistics partials. */
 lpt_status lpt_set_tuning(lpt_ctx *ctx, const lpt_tuning *tuning);
 
+/* lpt_step with HIP events recorded on the context stream before and after
+ * it; *ms receives the elapsed device time (synchronises).  The autotuner's
+ * clock: it covers every launch of the steps, graph replays included. */
+lpt_status lpt_time_steps(lpt_ctx *ctx, int64_t nsteps, double dt, int32_t stats_every,
+                          double *ms);
+
 /* ---- derivatives of the discrete tracer map (FP64) ---------------------- */
 /* The paper has no adjoint.  These entry points differentiate exactly the
  * discrete map that lpt_step computes for tracers (eq. rk4_update with the

@@ -1,0 +1,103 @@
+"""Launch-shape autotuner of the step path.
+
+Picks block size, LDS tile capacity, re-sort interval, persistent launches
+and hipGraph chunk length for one workload by timing candidates with HIP
+events on a throwaway context of that workload (``lpt_time_steps``), by
+coordinate descent from the library defaults.  None of these choices changes
+a per-particle result (see ``lpt_set_tuning``), only the time per step.
+Results are cached in a JSON file keyed by the device, the grid, the
+precision and the species mix.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lpt_tuning.json")
+
+SPACE = {
+    "block_size": (256, 128, 512),
+    "tile_records": (0, -1, 800, 1600, 2400),
+    "sort_interval": (20, 10, 40, 5),
+    "persistent": (0, 1),
+    "graph_chunk": (0, 100),
+}
+
+
+def workload_key(w, device_name: str) -> str:
+    mix = ";".join(f"{k}:{st}:{sch}:{cnt}" for k, st, sch, cnt, _ in w.species)
+    return f"{device_name}|n={w.n}|{w.precision}|{w.time_mode}|dt={w.dt}|K={w.stats_every}|{mix}"
+
+
+def _valid(t, precision):
+    rec = 32 if precision == "fp64" else 16
+    if t["tile_records"] > 0 and t["tile_records"] * rec > 61440:
+        return False
+    if t["graph_chunk"] and t["graph_chunk"] % max(1, t["sort_interval"]):
+        return False
+    return True
+
+
+def tune(w, lpt_mod, workloads_mod, trial_steps=80, rounds=2, log=None):
+    """Coordinate descent over SPACE; returns (best tuning dict, ms per step)."""
+    tr = workloads_mod.build_tracker(w, lpt_mod)
+    try:
+        best = tr.get_tuning()
+        best.update(sort_interval=w.sort_interval or 20, graph_chunk=0, persistent=0,
+                    tile_records=0, block_size=256)
+
+        def measure(t):
+            tr.set_tuning(**t)
+            tr.time_steps(max(10, trial_steps // 4), w.dt, w.stats_every)   # warm (captures graphs)
+            return tr.time_steps(trial_steps, w.dt, w.stats_every) / trial_steps
+
+        best_ms = measure(best)
+        for _ in range(rounds):
+            improved = False
+            for name, values in SPACE.items():
+                for v in values:
+                    if v == best[name]:
+                        continue
+                    cand = dict(best, **{name: v})
+                    if not _valid(cand, w.precision):
+                        continue
+                    ms = measure(cand)
+                    if log:
+                        log(f"[autotune] {cand} -> {ms * 1e3:.1f} us/step")
+                    if ms < best_ms * 0.99:
+                        best, best_ms, improved = cand, ms, True
+            if not improved:
+                break
+        return best, best_ms
+    finally:
+        tr.close()
+
+
+def load_cache(path=None):
+    path = path or os.environ.get("LPT_TUNE_CACHE", DEFAULT_CACHE)
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def cached_or_tune(w, lpt_mod, workloads_mod, device_name, path=None, log=None, **kw):
+    """The cached tuning of a workload on this device, tuning it first if the
+    cache has no entry."""
+    path = path or os.environ.get("LPT_TUNE_CACHE", DEFAULT_CACHE)
+    cache = load_cache(path)
+    key = workload_key(w, device_name)
+    if key in cache:
+        return cache[key]["tuning"], cache[key]["ms_per_step"], True
+    best, ms = tune(w, lpt_mod, workloads_mod, log=log, **kw)
+    cache[key] = {"tuning": best, "ms_per_step": ms}
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + f".tmp{os.getpid()}"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return best, ms, False

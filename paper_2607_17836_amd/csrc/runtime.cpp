@@ -938,6 +938,45 @@ lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
     return run_graph_chunks(c, nsteps, dt, stats_every);
 }
 
+lpt_status lpt_time_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
+                          double *ms)
+{
+    if (!c) return LPT_E_ARG;
+    if (!ms) return fail(c, LPT_E_ARG, "ms must not be NULL");
+    lpt_status s = check_steps(c, nsteps, dt, stats_every);
+    if (s != LPT_OK) return s;
+    HIP_TRY(c, hipSetDevice(c->device));
+    s = grow_records(c, nsteps, stats_every);   // outside the timed interval
+    if (s != LPT_OK) return s;
+    if (c->sort_interval > 0) {
+        s = ensure_sort_work(c);
+        if (s != LPT_OK) return s;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(c, hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        HIP_TRY(c, e);
+    }
+    // a null-stream context replays graphs on its own blocking stream, which
+    // the null stream waits for, so the events bracket the work either way
+    e = hipEventRecord(e0, c->stream);
+    if (e == hipSuccess) {
+        s = lpt_step(c, nsteps, dt, stats_every);
+        if (s == LPT_OK) e = hipEventRecord(e1, c->stream);
+    }
+    float t = 0.f;
+    if (e == hipSuccess && s == LPT_OK) e = hipEventSynchronize(e1);
+    if (e == hipSuccess && s == LPT_OK) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != LPT_OK) return s;
+    HIP_TRY(c, e);
+    *ms = t;
+    return LPT_OK;
+}
+
 lpt_status lpt_forward_checkpointed(lpt_ctx *c, int64_t nsteps, double dt, int32_t ckpt_every)
 {
     if (!c) return LPT_E_ARG;

@@ -82,6 +82,7 @@ _SIGS = [
                              C.c_int32]),
     ("lpt_radix_sort", C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, _P]),
     ("lpt_get_tuning", C.c_int, [_P, C.POINTER(LptTuning)]),
+    ("lpt_time_steps", C.c_int, [_P, C.c_int64, C.c_double, C.c_int32, C.POINTER(C.c_double)]),
     ("lpt_set_tuning", C.c_int, [_P, C.POINTER(LptTuning)]),
     ("lpt_forward_checkpointed", C.c_int, [_P, C.c_int64, C.c_double, C.c_int32]),
     ("lpt_adjoint", C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int32]),
@@ -288,6 +289,13 @@ class Tracker:
         t = LptTuning()
         self._check(load().lpt_get_tuning(self._h, C.byref(t)))
         return {k: getattr(t, k) for k, _ in LptTuning._fields_}
+
+    def time_steps(self, nsteps, dt, stats_every=0):
+        """Device milliseconds of lpt_step(nsteps) between HIP events."""
+        ms = C.c_double()
+        self._check(load().lpt_time_steps(self._h, int(nsteps), float(dt), int(stats_every),
+                                          C.byref(ms)))
+        return ms.value
 
     def set_tuning(self, **kw):
         cur = self.get_tuning()
