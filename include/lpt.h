@@ -213,6 +213,23 @@ lpt_status lpt_get_timing(lpt_ctx *ctx, lpt_timing *out, int32_t reset);
 /* Number of steps taken and current time. */
 lpt_status lpt_get_time(lpt_ctx *ctx, int64_t *steps, double *t);
 
+/* ---- checkpoint / resume --------------------------------------------------- */
+/* Serialise everything lpt_step evolves: the particle state of every species
+ * in the context's current slot order together with the slot -> particle
+ * map (so the cell-order sort and the statistics' summation order carry
+ * over), the initial positions and velocities, the time and step count, the
+ * statistics records and the device clock.
+ * Velocity snapshots are inputs, not state: set them again after a resume.
+ * With blob == NULL only *size (the bytes needed) is returned; otherwise
+ * cap must be at least that.  Host memory. */
+lpt_status lpt_get_state(lpt_ctx *ctx, void *blob, size_t cap, size_t *size);
+/* Restore a blob from lpt_get_state into a context created with the same n
+ * and precision and given the same species (kind, St, scheme, count) in the
+ * same order; anything else is LPT_E_ARG and leaves the context unchanged.
+ * Stepping on from the restored context gives the same bits as stepping on
+ * from the saved one. */
+lpt_status lpt_set_state(lpt_ctx *ctx, const void *blob, size_t size);
+
 /* ---- launch tuning -------------------------------------------------------- */
 /* Launch-shape choices of the step path.  None of them changes a
  * per-particle result (positions, displacements and velocities are the same

@@ -1371,6 +1371,196 @@ lpt_status lpt_radix_sort(lpt_ctx *c, int64_t npts, int32_t key_bits, const uint
     return s;
 }
 
+// ---- checkpoint / resume ---------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+struct StateHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t n, precision, nspecies;
+    int64_t np, steps, nrec;
+    double t;
+    int32_t time_mode, has_vel;
+    DevClock clock;
+};
+
+struct StateSpecies {
+    int32_t kind, scheme;
+    double st;
+    int64_t count;
+    int32_t vel_from_field, pad_;
+};
+
+const char kStateMagic[8] = {'L', 'P', 'T', 'S', 'T', 'A', 'T', 'E'};
+
+// Byte sizes of the per-particle arrays, in blob order.
+std::vector<size_t> state_arrays(const lpt_ctx *c)
+{
+    const size_t np = (size_t)c->np;
+    std::vector<size_t> a;
+    if (c->precision == LPT_FP64) {
+        a = {np * sizeof(double2), np * sizeof(double2)};
+        if (c->has_inertial) a.push_back(np * sizeof(double2));
+    } else {
+        a = {np * sizeof(uint32_t), np * sizeof(float2), np * sizeof(double2)};
+        if (c->has_inertial) a.push_back(np * sizeof(float2));
+    }
+    a.push_back(np * sizeof(uint32_t));                    // id (slot -> particle)
+    a.push_back(np * sizeof(double2));                     // x0 (by particle)
+    if (c->has_inertial) a.push_back(np * sizeof(double2));  // v0 (by particle)
+    return a;
+}
+
+std::vector<void *> state_ptrs(lpt_ctx *c, int k)
+{
+    std::vector<void *> p;
+    if (c->precision == LPT_FP64) {
+        p = {c->s64[k].pos, c->s64[k].disp};
+        if (c->has_inertial) p.push_back(c->s64[k].vel);
+        p.push_back(c->s64[k].id);
+    } else {
+        p = {c->s32[k].cell, c->s32[k].off, c->s32[k].disp};
+        if (c->has_inertial) p.push_back(c->s32[k].vel);
+        p.push_back(c->s32[k].id);
+    }
+    p.push_back(c->x0);
+    if (c->has_inertial) p.push_back(c->v0);
+    return p;
+}
+
+size_t state_size(const lpt_ctx *c)
+{
+    size_t s = sizeof(StateHeader) + c->sp.size() * sizeof(StateSpecies);
+    for (size_t b : state_arrays(c)) s += b;
+    return s + c->sp.size() * (size_t)c->nrec * 8 * sizeof(double);
+}
+
+}  // namespace
+
+extern "C" {
+
+lpt_status lpt_get_state(lpt_ctx *c, void *blob, size_t cap, size_t *size)
+{
+    if (!c) return LPT_E_ARG;
+    const size_t need = state_size(c);
+    if (size) *size = need;
+    if (!blob) return LPT_OK;
+    if (cap < need) return fail(c, LPT_E_ARG, "state buffer too small");
+    if (c->sp.empty()) return fail(c, LPT_E_STATE, "no species");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int o = c->cur;
+    char *out = static_cast<char *>(blob);
+    StateHeader h{};
+    std::memcpy(h.magic, kStateMagic, 8);
+    h.version = 1;
+    h.n = c->n;
+    h.precision = c->precision;
+    h.nspecies = (int32_t)c->sp.size();
+    h.np = c->np;
+    h.steps = c->steps;
+    h.nrec = c->nrec;
+    h.t = c->t;
+    h.time_mode = c->time_mode;
+    h.has_vel = c->has_inertial ? 1 : 0;
+    HIP_TRY(c, hipMemcpyAsync(&h.clock, c->clock, sizeof(DevClock), hipMemcpyDeviceToHost,
+                              c->stream));
+    size_t off = sizeof(StateHeader);
+    for (const SpeciesHost &sh : c->sp) {
+        StateSpecies ss{sh.kind, sh.scheme, sh.st, sh.count, sh.vel_from_field ? 1 : 0, 0};
+        std::memcpy(out + off, &ss, sizeof ss);
+        off += sizeof ss;
+    }
+    const std::vector<size_t> sizes = state_arrays(c);
+    const std::vector<void *> src = state_ptrs(c, o);
+    for (size_t a = 0; a < sizes.size(); ++a) {
+        HIP_TRY(c, hipMemcpyAsync(out + off, src[a], sizes[a], hipMemcpyDeviceToHost, c->stream));
+        off += sizes[a];
+    }
+    const size_t rb = (size_t)c->nrec * 8 * sizeof(double);
+    for (size_t sidx = 0; sidx < c->sp.size(); ++sidx) {
+        if (rb)
+            HIP_TRY(c, hipMemcpyAsync(out + off, c->records + sidx * c->rec_cap * 8, rb,
+                                      hipMemcpyDeviceToHost, c->stream));
+        off += rb;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::memcpy(out, &h, sizeof h);
+    return LPT_OK;
+}
+
+lpt_status lpt_set_state(lpt_ctx *c, const void *blob, size_t size)
+{
+    if (!c) return LPT_E_ARG;
+    if (!blob || size < sizeof(StateHeader)) return fail(c, LPT_E_ARG, "state blob too small");
+    const char *in = static_cast<const char *>(blob);
+    StateHeader h;
+    std::memcpy(&h, in, sizeof h);
+    if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1)
+        return fail(c, LPT_E_ARG, "not an lpt state blob");
+    if (h.n != c->n || h.precision != c->precision || h.nspecies != (int32_t)c->sp.size() ||
+        h.np != c->np || h.has_vel != (c->has_inertial ? 1 : 0))
+        return fail(c, LPT_E_ARG, "state blob does not match this context (grid, precision or "
+                                  "species)");
+    size_t off = sizeof(StateHeader);
+    if (size < off + c->sp.size() * sizeof(StateSpecies))
+        return fail(c, LPT_E_ARG, "state blob truncated");
+    for (const SpeciesHost &sh : c->sp) {
+        StateSpecies ss;
+        std::memcpy(&ss, in + off, sizeof ss);
+        off += sizeof ss;
+        if (ss.kind != sh.kind || ss.scheme != sh.scheme || ss.st != sh.st || ss.count != sh.count)
+            return fail(c, LPT_E_ARG, "state blob species differ from this context's");
+    }
+    if (h.nrec < 0 || h.steps < 0) return fail(c, LPT_E_ARG, "corrupt state blob");
+    const size_t need = sizeof(StateHeader) + c->sp.size() * sizeof(StateSpecies) +
+                        [&] {
+                            size_t b = 0;
+                            for (size_t x : state_arrays(c)) b += x;
+                            return b;
+                        }() +
+                        c->sp.size() * (size_t)h.nrec * 8 * sizeof(double);
+    if (size < need) return fail(c, LPT_E_ARG, "state blob truncated");
+    HIP_TRY(c, hipSetDevice(c->device));
+    // statistics capacity first (the only step that may fail for lack of memory)
+    if (h.nrec > c->rec_cap) {
+        const int64_t ns = (int64_t)c->sp.size();
+        double *nr = nullptr;
+        if (dalloc(nr, (size_t)(ns * (h.nrec + 64) * 8)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, LPT_E_NOMEM, "statistics records allocation failed");
+        }
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        dfree(c->records);
+        c->records = nr;
+        c->rec_cap = h.nrec + 64;
+    }
+    const std::vector<size_t> sizes = state_arrays(c);
+    const std::vector<void *> dst = state_ptrs(c, c->cur);
+    for (size_t a = 0; a < sizes.size(); ++a) {
+        HIP_TRY(c, hipMemcpyAsync(dst[a], in + off, sizes[a], hipMemcpyHostToDevice, c->stream));
+        off += sizes[a];
+    }
+    const size_t rb = (size_t)h.nrec * 8 * sizeof(double);
+    for (size_t sidx = 0; sidx < c->sp.size(); ++sidx) {
+        if (rb)
+            HIP_TRY(c, hipMemcpyAsync(c->records + sidx * c->rec_cap * 8, in + off, rb,
+                                      hipMemcpyHostToDevice, c->stream));
+        off += rb;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->clock, &h.clock, sizeof(DevClock), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->steps = h.steps;
+    c->t = h.t;
+    c->nrec = h.nrec;
+    c->time_mode = h.time_mode;
+    c->ck_valid = false;
+    invalidate_graphs(c);
+    return LPT_OK;
+}
+
 lpt_status lpt_get_tuning(lpt_ctx *c, lpt_tuning *out)
 {
     if (!c) return LPT_E_ARG;

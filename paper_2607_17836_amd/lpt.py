@@ -81,6 +81,8 @@ _SIGS = [
     ("lpt_interp", C.c_int, [_P, C.c_int, C.c_int64, _P, _P, C.c_double, C.c_double, _P, _P,
                              C.c_int32]),
     ("lpt_radix_sort", C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, _P]),
+    ("lpt_get_state", C.c_int, [_P, _P, C.c_size_t, C.POINTER(C.c_size_t)]),
+    ("lpt_set_state", C.c_int, [_P, _P, C.c_size_t]),
     ("lpt_get_tuning", C.c_int, [_P, C.POINTER(LptTuning)]),
     ("lpt_time_steps", C.c_int, [_P, C.c_int64, C.c_double, C.c_int32, C.POINTER(C.c_double)]),
     ("lpt_set_tuning", C.c_int, [_P, C.POINTER(LptTuning)]),
@@ -283,6 +285,18 @@ class Tracker:
         cp, tr = C.c_double(), C.c_double()
         self._check(load().lpt_bw_probe(self._h, int(nbytes), int(iters), C.byref(cp), C.byref(tr)))
         return cp.value, tr.value
+
+    # -- checkpoint / resume ---------------------------------------------
+    def get_state(self) -> bytes:
+        size = C.c_size_t()
+        self._check(load().lpt_get_state(self._h, None, 0, C.byref(size)))
+        buf = C.create_string_buffer(size.value)
+        self._check(load().lpt_get_state(self._h, buf, size.value, C.byref(size)))
+        return buf.raw[: size.value]
+
+    def set_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._check(load().lpt_set_state(self._h, buf, len(blob)))
 
     # -- tuning -----------------------------------------------------------
     def get_tuning(self):

@@ -154,3 +154,30 @@ def test_batched_species_match_one_context_per_species():
         st = one.get_stats(sid)
         np.testing.assert_allclose(batched[k][2]["msd"], st["msd"], rtol=1e-13)
         one.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
+def test_state_resume_continues_bit_for_bit(precision):
+    """Save after 7 steps, restore into a fresh context with the same
+    species, step 11 more: identical bits to stepping 18 without a break
+    (re-sorts every 4 steps and statistics every 3 included); a mismatched
+    context refuses the blob."""
+    say(f"resume {precision}")
+    a, sids = _mixed(precision, sort_interval=4)
+    a.step(7, 0.002, stats_every=3)
+    blob = a.get_state()
+    a.step(11, 0.002, stats_every=3)
+    b, _ = _mixed(precision, sort_interval=4)
+    b.set_state(blob)
+    assert b.get_time()[0] == 7
+    b.step(11, 0.002, stats_every=3)
+    for x, y in zip(_snap(a, sids), _snap(b, sids)):
+        np.testing.assert_array_equal(x, y)
+    assert a.get_time() == b.get_time()
+    a.close()
+    b.close()
+    other = lpt.Tracker(128, "fp64" if precision == "fp32_split" else "fp32_split")
+    with pytest.raises(lpt.LptError) as e:
+        other.set_state(blob)
+    assert e.value.status == lpt.E_ARG
+    other.close()
