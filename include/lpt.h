@@ -248,6 +248,10 @@ typedef struct {
                                LPT_FLAG_TIME_KERNELS, lpt_step captures runs of
                                this many steps (sorts and statistics included)
                                into a hipGraph once and replays it             */
+    float halo_scale;       /* LDS tile halo as a multiple of the largest
+                               displacement a step can make at the largest node
+                               speed, in (0, 4]; 0 selects 1.  Below 1 the
+                               fastest particles gather from global memory    */
 } lpt_tuning;
 
 lpt_status lpt_get_tuning(lpt_ctx *ctx, lpt_tuning *out);

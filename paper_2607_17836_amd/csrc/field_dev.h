@@ -45,6 +45,38 @@ __device__ __forceinline__ void persistent_range(int T, int &first, int &stride,
     end = hi;
 }
 
+// Streaming (non-temporal) loads and stores of the particle state: each
+// value is touched once per step, so it should not displace the field's node
+// records from the caches.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t ld_stream(const uint32_t *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+__device__ __forceinline__ float2 ld_stream(const float2 *p)
+{
+    const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2 *>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ld_stream(const double2 *p)
+{
+    const f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st_stream(uint32_t *p, uint32_t v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_stream(float2 *p, float2 v)
+{
+    f32x2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<f32x2 *>(p));
+}
+__device__ __forceinline__ void st_stream(double2 *p, double2 v)
+{
+    f64x2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<f64x2 *>(p));
+}
+
 __device__ __forceinline__ int species_of(const StepParams &P, int lb)
 {
     int s = 0;
@@ -159,7 +191,7 @@ __device__ __forceinline__ int step_halo(const StepParams &P, int scheme, float 
 {
     const float um = fmaxf(P.umax[0], P.umax[1]);   // cells per unit time
     const float cs = scheme == kCatmullRom ? 1.5625f : 1.0f;
-    const float d = fminf(cs * um * dt, 16.0f);
+    const float d = fminf(P.halo_scale * cs * um * dt, 16.0f);
     return d > 0.0f ? (int)ceilf(d) : 0;
 }
 

@@ -59,6 +59,7 @@ struct StepParams {
     int32_t h0, h3;
     int32_t persistent;    // grid sized to residency; workgroups loop over blocks
     int32_t tile_cap;      // LDS tile capacity in node records (0: no tile)
+    float halo_scale;      // tile halo = halo_scale x the largest-speed displacement
     const float *umax;     // device: largest node speed of slot 0 / 1, cells per unit time
     SpeciesDev sp[kMaxSpecies];
 };

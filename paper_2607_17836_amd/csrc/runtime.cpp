@@ -61,6 +61,7 @@ struct lpt_ctx {
     int32_t sort_tile = 16;
     int32_t tile_cap = 0;    // LDS tile capacity of the step kernel, node records
     int32_t persistent = 0;  // persistent step launches
+    float halo_scale = 1.0f; // LDS tile halo relative to the largest-speed bound
     int32_t graph_chunk = 0; // steps per captured hipGraph (0: eager launches)
     // executable graphs of step chunks, keyed by (step phase, state buffer,
     // chunk length, dt bits, stats_every, buffer epoch)
@@ -191,6 +192,7 @@ StepParams make_params(const lpt_ctx *c)
     P.nspecies = (int32_t)c->sp.size();
     P.tile_cap = c->tile_cap;
     P.persistent = c->persistent;
+    P.halo_scale = c->halo_scale;
     P.umax = c->umax;
     P.compat_edge = c->compat_edge ? 1 : 0;
     P.L = c->L;
@@ -1570,6 +1572,7 @@ lpt_status lpt_get_tuning(lpt_ctx *c, lpt_tuning *out)
     out->sort_interval = c->sort_interval;
     out->persistent = c->persistent;
     out->graph_chunk = c->graph_chunk;
+    out->halo_scale = c->halo_scale;
     return LPT_OK;
 }
 
@@ -1589,6 +1592,8 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
     if (t->sort_interval < 0) return fail(c, LPT_E_ARG, "sort_interval must be >= 0");
     if (t->persistent != 0 && t->persistent != 1) return fail(c, LPT_E_ARG, "persistent is 0 or 1");
     if (t->graph_chunk < 0) return fail(c, LPT_E_ARG, "graph_chunk must be >= 0");
+    const float halo = t->halo_scale == 0.0f ? 1.0f : t->halo_scale;
+    if (!(halo > 0.0f && halo <= 4.0f)) return fail(c, LPT_E_ARG, "halo_scale must be in (0, 4]");
     HIP_TRY(c, hipSetDevice(c->device));
     if (block != c->block) {
         // the statistics partials hold one slot per logical block
@@ -1612,6 +1617,7 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
     c->sort_interval = t->sort_interval;
     c->persistent = t->persistent;
     c->graph_chunk = t->graph_chunk;
+    c->halo_scale = halo;
     invalidate_graphs(c);
     return LPT_OK;
 }

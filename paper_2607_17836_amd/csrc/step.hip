@@ -373,7 +373,7 @@ __device__ __forceinline__ void stage32(const float4 *__restrict__ rec0, const f
 // One RK4 step of one particle (eqs. rk4_update / rk4_inertial, Stokes drag
 // of eq. drag_rk4), then the split-position update and the FP64
 // displacement.  Returns the new displacement squared per axis.
-template <int SCH, bool INERT>
+template <int SCH, bool INERT, bool ONE>
 __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S,
                                            const float4 *__restrict__ rec0, const float4 *lds,
                                            const Tile &T, const SpeciesDev &sp, int64_t p,
@@ -388,10 +388,10 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
         ry += ry < 0 ? P.n : 0;
     }
     const float dt = P.dtf, hdt = P.hdtf, dt6 = P.dt6f;
-    const bool one = P.ends_one != 0;   // first / last stage read a single time level
+    constexpr bool one = ONE;   // first / last stage read a single time level
     float dqx, dqy;
     if constexpr (INERT) {
-        const float2 vn = S.vel[p];
+        const float2 vn = ld_stream(S.vel + p);
         const float is = (float)sp.inv_st;
         float u, v;
         const float V1x = vn.x, V1y = vn.y;
@@ -411,8 +411,8 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
         const float A4x = (u - V4x) * is, A4y = (v - V4y) * is;
         dqx = dt6 * (V1x + 2.0f * V2x + 2.0f * V3x + V4x);
         dqy = dt6 * (V1y + 2.0f * V2y + 2.0f * V3y + V4y);
-        S.vel[p] = make_float2(vn.x + dt6 * (A1x + 2.0f * A2x + 2.0f * A3x + A4x),
-                               vn.y + dt6 * (A1y + 2.0f * A2y + 2.0f * A3y + A4y));
+        st_stream(S.vel + p, make_float2(vn.x + dt6 * (A1x + 2.0f * A2x + 2.0f * A3x + A4x),
+                                         vn.y + dt6 * (A1y + 2.0f * A2y + 2.0f * A3y + A4y)));
     } else {
         float k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
         stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x, o.y, one, P.h0, P.waf[0], P.wbf[0],
@@ -429,12 +429,12 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
     float ox = o.x, oy = o.y;
     advance_split(cx, ox, dqx, P);
     advance_split(cy, oy, dqy, P);
-    double2 d = S.disp[p];
-    S.cell[p] = (uint32_t)cx | ((uint32_t)cy << 16);
-    S.off[p] = make_float2(ox, oy);
+    double2 d = ld_stream(S.disp + p);
+    st_stream(S.cell + p, (uint32_t)cx | ((uint32_t)cy << 16));
+    st_stream(S.off + p, make_float2(ox, oy));
     d.x += (double)dqx * P.h;
     d.y += (double)dqy * P.h;
-    S.disp[p] = d;
+    st_stream(S.disp + p, d);
     r2x = d.x * d.x;
     r2y = d.y * d.y;
 }
@@ -448,6 +448,35 @@ template <int SCH, int SCHS>
 constexpr bool scheme_compiled()
 {
     return SCHS == kAnyScheme || SCHS == SCH;
+}
+
+// The particle body for the block's (scheme, kind), compiled for the schemes
+// and kinds the launch may meet.
+template <int SCHS, int KINDS, bool ONE>
+__device__ __forceinline__ void particle_dispatch(const StepParams &P, const State32 &S,
+                                                  const float4 *__restrict__ rec0,
+                                                  const float4 *lds, const Tile &T,
+                                                  const SpeciesDev &sp, int64_t p, uint32_t cell,
+                                                  float2 o, double &r2x, double &r2y)
+{
+    const bool inert = KINDS != 0 && sp.inertial;
+    if (scheme_compiled<kBilinear, SCHS>() && (SCHS != kAnyScheme || sp.scheme == kBilinear)) {
+        if (KINDS != 0 && inert)
+            particle32<kBilinear, KINDS != 0, ONE>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+        else
+            particle32<kBilinear, false, ONE>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+    } else if (scheme_compiled<kCatmullRom, SCHS>() &&
+               (SCHS != kAnyScheme || sp.scheme == kCatmullRom)) {
+        if (KINDS != 0 && inert)
+            particle32<kCatmullRom, KINDS != 0, ONE>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+        else
+            particle32<kCatmullRom, false, ONE>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+    } else if (scheme_compiled<kBSpline, SCHS>()) {
+        if (KINDS != 0 && inert)
+            particle32<kBSpline, KINDS != 0, ONE>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+        else
+            particle32<kBSpline, false, ONE>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+    }
 }
 
 template <int SCHS, int KINDS, bool STATS>
@@ -468,8 +497,8 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
     uint32_t cell = 0;
     float2 o = make_float2(0.f, 0.f);
     if (active) {
-        cell = S.cell[p];
-        o = S.off[p];
+        cell = ld_stream(S.cell + p);
+        o = ld_stream(S.off + p);
     }
     Tile T = no_tile();
     if (P.tile_cap > 0) {
@@ -483,24 +512,10 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
                                (int)(left < (int64_t)blockDim.x ? left : blockDim.x));
     }
     if (active) {
-        const bool inert = KINDS != 0 && sp.inertial;
-        if (scheme_compiled<kBilinear, SCHS>() && (SCHS != kAnyScheme || sp.scheme == kBilinear)) {
-            if (KINDS != 0 && inert)
-                particle32<kBilinear, KINDS != 0>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
-            else
-                particle32<kBilinear, false>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
-        } else if (scheme_compiled<kCatmullRom, SCHS>() &&
-                   (SCHS != kAnyScheme || sp.scheme == kCatmullRom)) {
-            if (KINDS != 0 && inert)
-                particle32<kCatmullRom, KINDS != 0>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
-            else
-                particle32<kCatmullRom, false>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
-        } else if (scheme_compiled<kBSpline, SCHS>()) {
-            if (KINDS != 0 && inert)
-                particle32<kBSpline, KINDS != 0>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
-            else
-                particle32<kBSpline, false>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
-        }
+        if (P.ends_one)
+            particle_dispatch<SCHS, KINDS, true>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+        else
+            particle_dispatch<SCHS, KINDS, false>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
     }
     if (STATS) {
         const double r2 = r2x + r2y;

@@ -45,7 +45,7 @@ class LptConfig(C.Structure):
 class LptTuning(C.Structure):
     _fields_ = [("block_size", C.c_int32), ("tile_records", C.c_int32),
                 ("sort_interval", C.c_int32), ("persistent", C.c_int32),
-                ("graph_chunk", C.c_int32)]
+                ("graph_chunk", C.c_int32), ("halo_scale", C.c_float)]
 
 
 class LptTiming(C.Structure):

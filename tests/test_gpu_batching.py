@@ -82,15 +82,16 @@ def test_tuning_is_validated_and_changes_nothing_on_error():
     tr, _ = _mixed("fp32_split")
     before = tr.get_tuning()
     for bad in (dict(block_size=96), dict(tile_records=3), dict(sort_interval=-1),
-                dict(persistent=2), dict(graph_chunk=-5), dict(tile_records=100000)):
+                dict(persistent=2), dict(graph_chunk=-5), dict(tile_records=100000),
+                dict(halo_scale=-1.0), dict(halo_scale=9.0)):
         with pytest.raises(lpt.LptError) as e:
             tr.set_tuning(**bad)
         assert e.value.status == lpt.E_ARG
         assert tr.get_tuning() == before
     tr.set_tuning(block_size=512, tile_records=2400, sort_interval=7, persistent=1,
-                  graph_chunk=10)
+                  graph_chunk=10, halo_scale=0.5)
     assert tr.get_tuning() == dict(block_size=512, tile_records=2400, sort_interval=7,
-                                   persistent=1, graph_chunk=10)
+                                   persistent=1, graph_chunk=10, halo_scale=0.5)
     tr.close()
 
 

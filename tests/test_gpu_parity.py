@@ -331,9 +331,10 @@ def test_lds_tiles_never_change_results(precision):
         say(f"lds tiles {precision} n={n}")
         (ua, va), (ub, vb) = synth.spectrum_snapshots(n, 10, 8, 0.002)
         outs = []
-        for tile in (-1, 0, 64):
+        for tile, halo in ((-1, 1.0), (0, 1.0), (64, 1.0), (0, 0.3)):
             tr = lpt.Tracker(n, precision, sort_interval=4, sort_tile=8 if n == 256 else 0,
                              tile_records=tile)
+            tr.set_tuning(halo_scale=halo)
             tr.set_time_mode("pingpong")
             tr.set_snapshot(0, 0.0, ua, va)
             tr.set_snapshot(1, 0.002, ub, vb)
