@@ -158,7 +158,7 @@ __device__ __forceinline__ bool edge_cell(int compat, int i, int j, int n)
 // particles' stored cells, widens it by a halo that covers every RK4 stage
 // position (the largest displacement a step can make, from the largest node
 // speed of the two time levels) plus the interpolation stencil, and copies
-// the node records of that box into LDS with coalesced row loads.  The four
+// the node records of that box into LDS with coalesced loads.  The four
 // stages then gather from LDS.  Every gather checks that its whole stencil
 // lies inside the tile and otherwise reads global memory, so the halo is a
 // performance estimate, never a correctness assumption.
@@ -228,7 +228,52 @@ __device__ __forceinline__ uint32_t wave_pmax16(uint32_t x)
 template <typename Rec>
 constexpr int fill_rows()
 {
-    return sizeof(Rec) <= 16 ? 8 : 4;
+    return sizeof(Rec) <= 16 ? 4 : 2;
+}
+
+// Copy the tile's node records into LDS (all threads of the block).  The
+// tile is walked as one flat row-major index space, so every index is lane
+// arithmetic (no per-row scalar work) and all lanes load: entry k = ty * w +
+// tx, with ty from a binary32 reciprocal of w corrected by one step (exact
+// for k < 2^22).  A thread issues the loads of a whole group before any LDS
+// write so that their latencies overlap; the last group's indices are
+// clamped to the last entry, which is then re-read and rewritten with the
+// same value.  T.x0 + tx and T.y0 + ty lie in [0, 2n): one conditional
+// subtraction wraps them.
+template <typename Rec>
+__device__ __forceinline__ void fill_tile(Rec *lds, const Rec *__restrict__ rec0,
+                                          const StepParams &P, const Tile &T)
+{
+    if (!T.on) return;
+    constexpr int R = fill_rows<Rec>();
+    const int n = P.n, w = T.w, area = T.w * T.h, nt = blockDim.x;
+    const float inv_w = 1.0f / (float)w;
+    const int groups = (area + R * nt - 1) / (R * nt);
+    for (int g = 0; g < groups; ++g) {
+        Rec buf[R];
+        int dst[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = min((int)threadIdx.x + (g * R + r) * nt, area - 1);
+            int ty = (int)((float)k * inv_w);
+            int tx = k - ty * w;
+            if (tx < 0) {
+                ty -= 1;
+                tx += w;
+            } else if (tx >= w) {
+                ty += 1;
+                tx -= w;
+            }
+            int gx = T.x0 + tx, gy = T.y0 + ty;
+            gx -= gx >= n ? n : 0;
+            gy -= gy >= n ? n : 0;
+            buf[r] = rec0[__mul24(gy, P.pitch) + gx];
+            dst[r] = k;
+        }
+        __builtin_amdgcn_sched_barrier(0);   // the group's loads ahead of its writes
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[dst[r]] = buf[r];
+    }
 }
 
 // Cooperative tile set-up of one block (all threads must call it).
@@ -277,31 +322,7 @@ __device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec
     const int area = T.w * T.h;
     T.on = P.tile_cap > 0 && area <= P.tile_cap && T.w < n && T.h < n &&
            area <= kTileWaste * nactive;
-    if (T.on) {
-        // Every load of a group is issued before any LDS write, so their
-        // latencies overlap.  Rows past the tile are clamped to its last
-        // row: they re-read it and rewrite the same values.  T.x0 + c and
-        // T.y0 + r lie in [0, 2n): one conditional subtraction wraps them.
-        constexpr int R = fill_rows<Rec>();
-        const int w0 = __builtin_amdgcn_readfirstlane(wv);   // wave-uniform row start
-        for (int c = lane; c < T.w; c += kWave) {
-            int gx = T.x0 + c;
-            gx -= gx >= n ? n : 0;
-            const Rec *src = rec0 + gx;
-            Rec *dst = lds + c;
-            for (int r0 = w0; r0 < T.h; r0 += R * nw) {
-                Rec buf[R];
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    int gy = T.y0 + min(r0 + k * nw, T.h - 1);
-                    gy -= gy >= n ? n : 0;
-                    buf[k] = src[__mul24(gy, P.pitch)];
-                }
-#pragma unroll
-                for (int k = 0; k < R; ++k) dst[__mul24(min(r0 + k * nw, T.h - 1), T.w)] = buf[k];
-            }
-        }
-    }
+    fill_tile<Rec>(lds, rec0, P, T);
     __syncthreads();
     return T;
 }

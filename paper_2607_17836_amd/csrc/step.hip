@@ -370,6 +370,29 @@ __device__ __forceinline__ void stage32(const float4 *__restrict__ rec0, const f
     }
 }
 
+// The first stage sits at the stored position itself: stored cell, in-cell
+// coordinates = the stored offset in [0, 1) (so floor(q) = 0 and the general
+// stage computes the same values).  The stored cell lies inside the block's
+// box, and the tile adds the stencil reach around it, so with a tile the
+// stencil is always inside and no check or fallback is needed.
+template <int SCH, bool ONE>
+__device__ __forceinline__ void stage32_first(const float4 *__restrict__ rec0, const float4 *lds,
+                                              const Tile &T, const StepParams &P, int cx, int cy,
+                                              int rx, int ry, float2 o, int h, float wa, float wb,
+                                              float &u, float &v)
+{
+    constexpr int c1 = SCH == kBilinear ? 0 : 1;
+    if (SCH != kBilinear && P.compat_edge) {
+        stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x, o.y, ONE, h, wa, wb, u, v);
+        return;
+    }
+    if (T.on)
+        eval32<SCH>(lds + (__mul24(ry - c1, T.w) + (rx - c1)), T.w, o.x, o.y, ONE, h, wa, wb, u, v);
+    else
+        eval32<SCH>(rec0 + (__mul24(cy - c1, P.pitch) + (cx - c1)), P.pitch, o.x, o.y, ONE, h, wa,
+                    wb, u, v);
+}
+
 // One RK4 step of one particle (eqs. rk4_update / rk4_inertial, Stokes drag
 // of eq. drag_rk4), then the split-position update and the FP64
 // displacement.  Returns the new displacement squared per axis.
@@ -377,7 +400,7 @@ template <int SCH, bool INERT, bool ONE>
 __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S,
                                            const float4 *__restrict__ rec0, const float4 *lds,
                                            const Tile &T, const SpeciesDev &sp, int64_t p,
-                                           uint32_t cell, float2 o, double &r2x, double &r2y)
+                                           uint32_t &cell, float2 o, double &r2x, double &r2y)
 {
     int cx = (int)(cell & 0xFFFFu), cy = (int)(cell >> 16);
     int rx = 0, ry = 0;
@@ -395,7 +418,7 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
         const float is = (float)sp.inv_st;
         float u, v;
         const float V1x = vn.x, V1y = vn.y;
-        stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x, o.y, one, P.h0, P.waf[0], P.wbf[0], u, v);
+        stage32_first<SCH, ONE>(rec0, lds, T, P, cx, cy, rx, ry, o, P.h0, P.waf[0], P.wbf[0], u, v);
         const float A1x = (u - V1x) * is, A1y = (v - V1y) * is;
         const float V2x = vn.x + hdt * A1x, V2y = vn.y + hdt * A1y;
         stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x + hdt * V1x, o.y + hdt * V1y, false, 0,
@@ -415,8 +438,8 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
                                          vn.y + dt6 * (A1y + 2.0f * A2y + 2.0f * A3y + A4y)));
     } else {
         float k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
-        stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x, o.y, one, P.h0, P.waf[0], P.wbf[0],
-                     k1x, k1y);
+        stage32_first<SCH, ONE>(rec0, lds, T, P, cx, cy, rx, ry, o, P.h0, P.waf[0], P.wbf[0], k1x,
+                                k1y);
         stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x + hdt * k1x, o.y + hdt * k1y, false, 0,
                      P.waf[1], P.wbf[1], k2x, k2y);
         stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x + hdt * k2x, o.y + hdt * k2y, false, 0,
@@ -430,7 +453,8 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
     advance_split(cx, ox, dqx, P);
     advance_split(cy, oy, dqy, P);
     double2 d = ld_stream(S.disp + p);
-    st_stream(S.cell + p, (uint32_t)cx | ((uint32_t)cy << 16));
+    cell = (uint32_t)cx | ((uint32_t)cy << 16);
+    st_stream(S.cell + p, cell);
     st_stream(S.off + p, make_float2(ox, oy));
     d.x += (double)dqx * P.h;
     d.y += (double)dqy * P.h;
@@ -456,7 +480,7 @@ template <int SCHS, int KINDS, bool ONE>
 __device__ __forceinline__ void particle_dispatch(const StepParams &P, const State32 &S,
                                                   const float4 *__restrict__ rec0,
                                                   const float4 *lds, const Tile &T,
-                                                  const SpeciesDev &sp, int64_t p, uint32_t cell,
+                                                  const SpeciesDev &sp, int64_t p, uint32_t &cell,
                                                   float2 o, double &r2x, double &r2y)
 {
     const bool inert = KINDS != 0 && sp.inertial;
@@ -502,14 +526,14 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
     }
     Tile T = no_tile();
     if (P.tile_cap > 0) {
-        const uint32_t a = S.cell[sp.offset + base];
         int lo, hi;
         stencil_reach(sp.scheme, lo, hi);
         const int H = step_halo(P, sp.scheme, P.dtf);
         const int64_t left = sp.count - base;
+        const int nact = (int)(left < (int64_t)blockDim.x ? left : blockDim.x);
+        const uint32_t a = S.cell[sp.offset + base];
         T = stage_tile<float4>(lds, rec0, P, active, (int)(cell & 0xFFFFu), (int)(cell >> 16),
-                               (int)(a & 0xFFFFu), (int)(a >> 16), lo + H, hi + H,
-                               (int)(left < (int64_t)blockDim.x ? left : blockDim.x));
+                               (int)(a & 0xFFFFu), (int)(a >> 16), lo + H, hi + H, nact);
     }
     if (active) {
         if (P.ends_one)
