@@ -555,8 +555,13 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
 // workgroup to one logical block (XCD-aware order); with P.persistent set the
 // grid is sized to the resident capacity and each workgroup walks a
 // contiguous range of logical blocks of its own XCD.
+// Bilinear blocks hold eight 256-thread blocks per CU (the LDS tile's
+// budget), i.e. eight waves per SIMD, so their registers are bounded to fit
+// that; the bicubic bodies need more registers and keep the default bound.
 template <int SCHS, int KINDS, bool STATS>
-__global__ __launch_bounds__(kMaxBlock) void step32_kernel(StepParams P, State32 S,
+__global__ __launch_bounds__(kMaxBlock)
+__attribute__((amdgpu_waves_per_eu(SCHS == kBilinear ? 8 : 1)))
+void step32_kernel(StepParams P, State32 S,
                                                            const float4 *__restrict__ rec,
                                                            double *__restrict__ partials,
                                                            DevClock *clock)
