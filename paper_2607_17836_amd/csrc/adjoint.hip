@@ -126,26 +126,46 @@ __device__ __forceinline__ void jacobian64(const Rec64 *__restrict__ rec0, const
     J[3] = vy * P.invh;
 }
 
-// dL/d(grid) += lam (x) (temporal weight) (x) (node weight), into gU laid
-// out [slot][u, v][n * n].
-__device__ __forceinline__ void scatter64(double *gU, const StepParams &P, const Sten64 &s,
-                                          double wa, double wb, double lx, double ly)
+// Accumulator of dL/d(grid) for one block: gU in global memory, laid out
+// [slot][u, v][n * n], and optionally the block's box B of nodes in LDS as
+// four planes (slot 0 u, slot 0 v, slot 1 u, slot 1 v) of B.w * B.h doubles.
+struct GridGrad {
+    double *gU;
+    double *acc;   // LDS planes, used when B.on
+    Tile B;
+};
+
+// dL/d(grid) += lam (x) (temporal weight) (x) (node weight).
+__device__ __forceinline__ void scatter64(const GridGrad &G, const StepParams &P,
+                                          const Sten64 &s, double wa, double wb, double lx,
+                                          double ly)
 {
     const int n = P.n;
     const int64_t nn = (int64_t)n * n;
+    const int area = G.B.w * G.B.h;
     const double wt[2] = {wa, wb};
     for (int b = 0; b < s.cnt; ++b) {
         const int j = wrap_cell(s.j0 + b, n, P.mask);
+        int ry = j - G.B.y0;
+        ry += ry < 0 ? n : 0;
         for (int a = 0; a < s.cnt; ++a) {
             const int i = wrap_cell(s.i0 + a, n, P.mask);
+            int rx = i - G.B.x0;
+            rx += rx < 0 ? n : 0;
             const double w = s.wx[a] * s.wy[b];
-            const int64_t k = (int64_t)j * n + i;
+            const bool local = G.B.on && rx < G.B.w && ry < G.B.h;
 #pragma unroll
             for (int sl = 0; sl < 2; ++sl) {
                 const double c = wt[sl] * w;
-                if (c != 0.0) {
-                    atomicAdd(gU + (2 * sl) * nn + k, c * lx);
-                    atomicAdd(gU + (2 * sl + 1) * nn + k, c * ly);
+                if (c == 0.0) continue;
+                if (local) {
+                    const int k = ry * G.B.w + rx;
+                    atomicAdd(G.acc + (2 * sl) * area + k, c * lx);
+                    atomicAdd(G.acc + (2 * sl + 1) * area + k, c * ly);
+                } else {
+                    const int64_t k = (int64_t)j * n + i;
+                    atomicAdd(G.gU + (2 * sl) * nn + k, c * lx);
+                    atomicAdd(G.gU + (2 * sl + 1) * nn + k, c * ly);
                 }
             }
         }
@@ -180,86 +200,133 @@ __global__ __launch_bounds__(kMaxBlock) void recompute64_kernel(StepParams P, co
 
 // One reverse step.  lam holds NL adjoint vectors per particle
 // (lam[p * NL + r]); gU (may be null) receives the grid gradient of the
-// first one.
-template <int NL>
-__global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P, const Rec64 *__restrict__ rec,
-                                                        const double2 *__restrict__ tape,
-                                                        double2 *__restrict__ lam, double *gU)
+// first one.  With AGG, the block first sums its contributions in an LDS box
+// of the grid (its particles' cells widened by the step's displacement
+// bound and the stencil reach; acc_cap nodes of LDS) and then adds the box
+// to gU with one atomic per nonzero entry; contributions outside the box
+// (particles faster than the bound) go to gU directly.
+extern __shared__ __align__(32) unsigned char adj_dyn_lds[];
+
+template <int NL, bool AGG>
+__global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
+                                                              const Rec64 *__restrict__ rec,
+                                                              const double2 *__restrict__ tape,
+                                                              double2 *__restrict__ lam,
+                                                              double *gU, int acc_cap)
 {
     const int lb = blockIdx.x;
     const SpeciesDev &sp = P.sp[species_of(P, lb)];
-    const int64_t local = (int64_t)(lb - sp.block_begin) * blockDim.x + threadIdx.x;
-    if (local >= sp.count) return;
+    const int64_t base = (int64_t)(lb - sp.block_begin) * blockDim.x;
+    const int64_t local = base + threadIdx.x;
+    const bool active = local < sp.count;
     const int64_t p = sp.offset + local;
     const Rec64 *rec0 = rec + P.pitch + 1;
     const int scheme = sp.scheme;
     const double dt = P.dt, hdt = 0.5 * P.dt, dt6 = P.dt / 6.0, dt3 = P.dt / 3.0;
-    const double2 x = tape[p];
+    const double2 x = active ? tape[p] : make_double2(0.0, 0.0);
 
-    // forward recomputation of the stage points, exactly as the step kernel
-    double px[4], py[4];
-    double k1x, k1y, k2x, k2y, k3x, k3y;
-    px[0] = x.x;
-    py[0] = x.y;
-    vel64<true>(rec0, nullptr, no_tile(), P, scheme, px[0], py[0], P.wa[0], P.wb[0], P.smode[0],
-                k1x, k1y);
-    px[1] = x.x + hdt * k1x;
-    py[1] = x.y + hdt * k1y;
-    vel64<true>(rec0, nullptr, no_tile(), P, scheme, px[1], py[1], P.wa[1], P.wb[1], P.smode[1],
-                k2x, k2y);
-    px[2] = x.x + hdt * k2x;
-    py[2] = x.y + hdt * k2y;
-    vel64<true>(rec0, nullptr, no_tile(), P, scheme, px[2], py[2], P.wa[2], P.wb[2], P.smode[2],
-                k3x, k3y);
-    px[3] = x.x + dt * k3x;
-    py[3] = x.y + dt * k3y;
-
-    Sten64 st[4];
-    double J[4][4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        st[q] = stencil64(P, scheme, locate64(P, px[q], py[q]));
-        jacobian64(rec0, P, st[q], P.wa[q], P.wb[q], P.smode[q], J[q]);
+    GridGrad G{gU, reinterpret_cast<double *>(adj_dyn_lds), no_tile()};
+    if constexpr (AGG) {
+        const Loc64 me = locate64(P, x.x, x.y);
+        const double2 a0 = tape[sp.offset + base];
+        const Loc64 an = locate64(P, a0.x, a0.y);
+        int lo, hi;
+        stencil_reach(scheme, lo, hi);
+        const int H = step_halo(P, scheme, (float)dt);
+        G.B = block_box(active, me.i, me.j, an.i, an.j, P.n, P.mask, lo + H, hi + H);
+        const int area = G.B.w * G.B.h;
+        G.B.on = area <= acc_cap && G.B.w < P.n && G.B.h < P.n;
+        if (G.B.on)
+            for (int k = threadIdx.x; k < 4 * area; k += blockDim.x) G.acc[k] = 0.0;
+        __syncthreads();
     }
 
+    if (active) {
+        // forward recomputation of the stage points, exactly as the step kernel
+        double px[4], py[4];
+        double k1x, k1y, k2x, k2y, k3x, k3y;
+        px[0] = x.x;
+        py[0] = x.y;
+        vel64<true>(rec0, nullptr, no_tile(), P, scheme, px[0], py[0], P.wa[0], P.wb[0],
+                    P.smode[0], k1x, k1y);
+        px[1] = x.x + hdt * k1x;
+        py[1] = x.y + hdt * k1y;
+        vel64<true>(rec0, nullptr, no_tile(), P, scheme, px[1], py[1], P.wa[1], P.wb[1],
+                    P.smode[1], k2x, k2y);
+        px[2] = x.x + hdt * k2x;
+        py[2] = x.y + hdt * k2y;
+        vel64<true>(rec0, nullptr, no_tile(), P, scheme, px[2], py[2], P.wa[2], P.wb[2],
+                    P.smode[2], k3x, k3y);
+        px[3] = x.x + dt * k3x;
+        py[3] = x.y + dt * k3y;
+
+        Sten64 st[4];
+        double J[4][4];
 #pragma unroll
-    for (int r = 0; r < NL; ++r) {
-        const double2 l = lam[p * NL + r];
-        // x' = x + dt/6 (k1 + 2 k2 + 2 k3 + k4)
-        double lx[2] = {l.x, l.y};
-        double l1[2] = {dt6 * l.x, dt6 * l.y};
-        double l2[2] = {dt3 * l.x, dt3 * l.y};
-        double l3[2] = {dt3 * l.x, dt3 * l.y};
-        const double l4[2] = {dt6 * l.x, dt6 * l.y};
-        double ls[2];
-        const bool grid = gU != nullptr && r == 0;
-        // k4 = U(x4), x4 = x + dt k3
-        if (grid) scatter64(gU, P, st[3], P.wa[3], P.wb[3], l4[0], l4[1]);
-        add_jt(J[3], l4, ls);
-        lx[0] += ls[0];
-        lx[1] += ls[1];
-        l3[0] += dt * ls[0];
-        l3[1] += dt * ls[1];
-        // k3 = U(x3), x3 = x + dt/2 k2
-        if (grid) scatter64(gU, P, st[2], P.wa[2], P.wb[2], l3[0], l3[1]);
-        add_jt(J[2], l3, ls);
-        lx[0] += ls[0];
-        lx[1] += ls[1];
-        l2[0] += hdt * ls[0];
-        l2[1] += hdt * ls[1];
-        // k2 = U(x2), x2 = x + dt/2 k1
-        if (grid) scatter64(gU, P, st[1], P.wa[1], P.wb[1], l2[0], l2[1]);
-        add_jt(J[1], l2, ls);
-        lx[0] += ls[0];
-        lx[1] += ls[1];
-        l1[0] += hdt * ls[0];
-        l1[1] += hdt * ls[1];
-        // k1 = U(x)
-        if (grid) scatter64(gU, P, st[0], P.wa[0], P.wb[0], l1[0], l1[1]);
-        add_jt(J[0], l1, ls);
-        lx[0] += ls[0];
-        lx[1] += ls[1];
-        lam[p * NL + r] = make_double2(lx[0], lx[1]);
+        for (int q = 0; q < 4; ++q) {
+            st[q] = stencil64(P, scheme, locate64(P, px[q], py[q]));
+            jacobian64(rec0, P, st[q], P.wa[q], P.wb[q], P.smode[q], J[q]);
+        }
+
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const double2 l = lam[p * NL + r];
+            // x' = x + dt/6 (k1 + 2 k2 + 2 k3 + k4)
+            double lx[2] = {l.x, l.y};
+            double l1[2] = {dt6 * l.x, dt6 * l.y};
+            double l2[2] = {dt3 * l.x, dt3 * l.y};
+            double l3[2] = {dt3 * l.x, dt3 * l.y};
+            const double l4[2] = {dt6 * l.x, dt6 * l.y};
+            double ls[2];
+            const bool grid = gU != nullptr && r == 0;
+            // k4 = U(x4), x4 = x + dt k3
+            if (grid) scatter64(G, P, st[3], P.wa[3], P.wb[3], l4[0], l4[1]);
+            add_jt(J[3], l4, ls);
+            lx[0] += ls[0];
+            lx[1] += ls[1];
+            l3[0] += dt * ls[0];
+            l3[1] += dt * ls[1];
+            // k3 = U(x3), x3 = x + dt/2 k2
+            if (grid) scatter64(G, P, st[2], P.wa[2], P.wb[2], l3[0], l3[1]);
+            add_jt(J[2], l3, ls);
+            lx[0] += ls[0];
+            lx[1] += ls[1];
+            l2[0] += hdt * ls[0];
+            l2[1] += hdt * ls[1];
+            // k2 = U(x2), x2 = x + dt/2 k1
+            if (grid) scatter64(G, P, st[1], P.wa[1], P.wb[1], l2[0], l2[1]);
+            add_jt(J[1], l2, ls);
+            lx[0] += ls[0];
+            lx[1] += ls[1];
+            l1[0] += hdt * ls[0];
+            l1[1] += hdt * ls[1];
+            // k1 = U(x)
+            if (grid) scatter64(G, P, st[0], P.wa[0], P.wb[0], l1[0], l1[1]);
+            add_jt(J[0], l1, ls);
+            lx[0] += ls[0];
+            lx[1] += ls[1];
+            lam[p * NL + r] = make_double2(lx[0], lx[1]);
+        }
+    }
+
+    if constexpr (AGG) {
+        __syncthreads();
+        if (G.B.on) {
+            const int n = P.n, area = G.B.w * G.B.h;
+            const int64_t nn = (int64_t)n * n;
+            for (int k = threadIdx.x; k < area; k += blockDim.x) {
+                const int ty = k / G.B.w, tx = k - ty * G.B.w;
+                int gx = G.B.x0 + tx, gy = G.B.y0 + ty;
+                gx -= gx >= n ? n : 0;
+                gy -= gy >= n ? n : 0;
+                const int64_t g = (int64_t)gy * n + gx;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double v = G.acc[q * area + k];
+                    if (v != 0.0) atomicAdd(gU + q * nn + g, v);
+                }
+            }
+        }
     }
 }
 
@@ -310,15 +377,22 @@ hipError_t launch_recompute64(const StepParams &P, const Rec64 *rec, const doubl
     return hipGetLastError();
 }
 
+// LDS of the aggregating adjoint: four planes of doubles per box node.
+constexpr int kAdjAccNodes = 1024;
+
 hipError_t launch_adjoint64(const StepParams &P, const Rec64 *rec, const double2 *tape,
                             double2 *lam, int nl, double *gU, int block, hipStream_t st)
 {
-    if (nl == 1)
-        hipLaunchKernelGGL(adjoint64_kernel<1>, dim3(P.total_blocks), dim3(block), 0, st, P, rec,
-                           tape, lam, gU);
+    if (nl == 1 && gU)
+        hipLaunchKernelGGL((adjoint64_kernel<1, true>), dim3(P.total_blocks), dim3(block),
+                           (size_t)kAdjAccNodes * 4 * sizeof(double), st, P, rec, tape, lam, gU,
+                           kAdjAccNodes);
+    else if (nl == 1)
+        hipLaunchKernelGGL((adjoint64_kernel<1, false>), dim3(P.total_blocks), dim3(block), 0, st,
+                           P, rec, tape, lam, (double *)nullptr, 0);
     else
-        hipLaunchKernelGGL(adjoint64_kernel<2>, dim3(P.total_blocks), dim3(block), 0, st, P, rec,
-                           tape, lam, (double *)nullptr);
+        hipLaunchKernelGGL((adjoint64_kernel<2, false>), dim3(P.total_blocks), dim3(block), 0, st,
+                           P, rec, tape, lam, (double *)nullptr, 0);
     return hipGetLastError();
 }
 

@@ -231,6 +231,22 @@ constexpr int fill_rows()
     return sizeof(Rec) <= 16 ? 4 : 2;
 }
 
+// LDS layout of a tile entry: FP64 records are kept whole; FP32 records are
+// split into two planes of (u, v), one per time level (entry k of level h at
+// float2 index h * area + k).
+__device__ __forceinline__ void tile_store(Rec64 *lds, int k, int area, const Rec64 &r)
+{
+    (void)area;
+    lds[k] = r;
+}
+
+__device__ __forceinline__ void tile_store(float4 *lds, int k, int area, const float4 &r)
+{
+    float2 *q = reinterpret_cast<float2 *>(lds);
+    q[k] = make_float2(r.x, r.y);
+    q[area + k] = make_float2(r.z, r.w);
+}
+
 // Copy the tile's node records into LDS (all threads of the block).  The
 // tile is walked as one flat row-major index space, so every index is lane
 // arithmetic (no per-row scalar work) and all lanes load: entry k = ty * w +
@@ -272,23 +288,23 @@ __device__ __forceinline__ void fill_tile(Rec *lds, const Rec *__restrict__ rec0
         }
         __builtin_amdgcn_sched_barrier(0);   // the group's loads ahead of its writes
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[dst[r]] = buf[r];
+        for (int r = 0; r < R; ++r) tile_store(lds, dst[r], area, buf[r]);
     }
 }
 
-// Cooperative tile set-up of one block (all threads must call it).
-// (cx, cy): the thread's stored cell (ignored when !active); (ax, ay): the
-// stored cell of the block's first particle, which is always active.  The
-// box is reduced on cell offsets from (ax, ay), biased by 2^15 and packed
-// two per word, as maxima of (r + 2^15) and (2^15 - r).
-template <typename Rec>
-__device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec0,
-                                          const StepParams &P, bool active, int cx, int cy,
-                                          int ax, int ay, int lo, int hi, int nactive)
+// Bounding box of the stored cells of a block's active particles, widened by
+// lo cells before and hi cells after on each axis (all threads must call
+// it; returns with the block synchronised).  (cx, cy): the thread's cell
+// (ignored when !active); (ax, ay): the cell of the block's first particle,
+// which is always active.  The box is reduced on offsets from (ax, ay),
+// biased by 2^15 and packed two per word, as maxima of (r + 2^15) and
+// (2^15 - r).  Fills x0, y0, w, h of the result; `on` is left 0.
+__device__ __forceinline__ Tile block_box(bool active, int cx, int cy, int ax, int ay, int n,
+                                          int mask, int lo, int hi)
 {
     __shared__ uint32_t red[2][kMaxBlock / kWave];
     constexpr int kBias = 1 << 15;
-    const int n = P.n, mask = P.mask, half = n >> 1;
+    const int half = n >> 1;
     int rx = 0, ry = 0;
     if (active) {   // cx - ax lies in (-n, n): map it to (-n/2, n/2]
         rx = cx - ax;
@@ -314,17 +330,38 @@ __device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec
     }
     const int mxx = (int)(up & 0xFFFFu) - kBias, mxy = (int)(up >> 16) - kBias;
     const int mnx = kBias - (int)(dn & 0xFFFFu), mny = kBias - (int)(dn >> 16);
-    Tile T;
+    Tile T = no_tile();
     T.w = mxx - mnx + 1 + lo + hi;
     T.h = mxy - mny + 1 + lo + hi;
     T.x0 = wrap_cell(ax + mnx - lo, n, mask);
     T.y0 = wrap_cell(ay + mny - lo, n, mask);
+    return T;
+}
+
+// Cooperative tile set-up of one block (all threads must call it): the box
+// of block_box, staged in LDS if it fits the capacity and is not much larger
+// than the block's particle count.
+template <typename Rec>
+__device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec0,
+                                          const StepParams &P, bool active, int cx, int cy,
+                                          int ax, int ay, int lo, int hi, int nactive)
+{
+    const int n = P.n;
+    Tile T = block_box(active, cx, cy, ax, ay, n, P.mask, lo, hi);
     const int area = T.w * T.h;
     T.on = P.tile_cap > 0 && area <= P.tile_cap && T.w < n && T.h < n &&
            area <= kTileWaste * nactive;
     fill_tile<Rec>(lds, rec0, P, T);
     __syncthreads();
     return T;
+}
+
+// Halo extents of a scheme: a bilinear stencil spans nodes i..i+1, a bicubic
+// one i-1..i+2 (the compatibility fallback to bilinear stays inside both).
+__device__ __forceinline__ void stencil_reach(int scheme, int &lo, int &hi)
+{
+    lo = scheme == kBilinear ? 0 : 1;
+    hi = scheme == kBilinear ? 1 : 2;
 }
 
 // ===========================================================================

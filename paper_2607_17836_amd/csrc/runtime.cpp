@@ -298,13 +298,11 @@ lpt_status do_sort(lpt_ctx *c)
     const int tb = tile_bits(c);
     const int kb = std::max(1, tb + species_bits(c));
     if (c->precision == LPT_FP64)
-        HIP_TRY(c, launch_keys64(P, c->s64[c->cur], c->sort_tile, tb, c->sw.keys[0], c->sw.vals[0],
-                                 c->stream));
+        HIP_TRY(c, launch_keys64(P, c->s64[c->cur], c->sort_tile, tb, kb, c->sw, c->stream));
     else
-        HIP_TRY(c, launch_keys32(P, c->s32[c->cur], c->sort_tile, tb, c->sw.keys[0], c->sw.vals[0],
-                                 c->stream));
+        HIP_TRY(c, launch_keys32(P, c->s32[c->cur], c->sort_tile, tb, kb, c->sw, c->stream));
     int res = 0;
-    HIP_TRY(c, radix_sort(c->sw, c->np, kb, &res, c->stream));
+    HIP_TRY(c, radix_sort(c->sw, c->np, kb, true, &res, c->stream));
     const uint32_t *perm = c->sw.vals[res];
     if (c->precision == LPT_FP64)
         HIP_TRY(c, launch_permute64(c->s64[c->cur], c->s64[1 - c->cur], perm, c->np,
@@ -1360,9 +1358,10 @@ lpt_status lpt_radix_sort(lpt_ctx *c, int64_t npts, int32_t key_bits, const uint
     if (e == hipSuccess) e = dalloc(w.scan_tmp, (size_t)sort_scan_blocks(npts));
     if (e == hipSuccess)
         e = hipMemcpyAsync(w.keys[0], keys_in, (size_t)npts * 4, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = launch_iota(w.vals[0], npts, c->stream);
+    // a single key is its own sorted order (the sort then launches nothing)
+    if (e == hipSuccess && npts == 1) e = hipMemsetAsync(w.vals[0], 0, sizeof(uint32_t), c->stream);
     int res = 0;
-    if (e == hipSuccess) e = radix_sort(w, npts, key_bits, &res, c->stream);
+    if (e == hipSuccess) e = radix_sort(w, npts, key_bits, false, &res, c->stream);
     if (e == hipSuccess && keys_out)
         e = hipMemcpyAsync(keys_out, w.keys[res], (size_t)npts * 4, hipMemcpyDeviceToDevice,
                            c->stream);

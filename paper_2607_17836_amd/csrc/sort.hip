@@ -8,6 +8,13 @@
 // counts live in LDS and are turned into scatter bases by one scan over the
 // waves.  Equal digits therefore keep input order: tile order, then wave,
 // then iteration, then lane -- which is the input order.
+//
+// The key kernel also builds the first pass's histogram, and the first
+// scatter takes the input index as the value, so the sort reads no value
+// array it did not write.  Histograms count runs: each thread takes 16
+// consecutive keys and adds one LDS increment per run of equal digits, since
+// the keys of a state sorted a few steps ago arrive nearly in order (where
+// one LDS bin per lane increment would serialise a wave on one address).
 #include "lpt_kernels.h"
 
 namespace lpt {
@@ -56,26 +63,102 @@ __device__ __forceinline__ uint32_t tile_key(int ci, int cj, int n, int tile_shi
     return ((uint32_t)species << tile_bits) | (ty * tiles_x + tx);
 }
 
-__global__ void keys64_kernel(StepParams P, State64 S, int tile_shift, int tile_bits,
-                              uint32_t *keys, uint32_t *vals, int64_t total)
+// Adds the digits of v[0 .. cnt) to the LDS histogram h, one increment per
+// run of equal digits.
+template <int CNT>
+__device__ __forceinline__ void count_runs(const uint32_t *v, int cnt, int shift, uint32_t mask,
+                                           uint32_t *h)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= total) return;
-    const double2 x = S.pos[p];
-    const int ci = cell_of_pos(x.x, P.invh, P.n), cj = cell_of_pos(x.y, P.invh, P.n);
-    keys[p] = tile_key(ci, cj, P.n, tile_shift, tile_bits, species_of_particle(P, p));
-    vals[p] = (uint32_t)p;
+    if (cnt <= 0) return;
+    uint32_t cur = (v[0] >> shift) & mask, run = 1;
+#pragma unroll
+    for (int k = 1; k < CNT; ++k) {
+        if (k >= cnt) break;
+        const uint32_t d = (v[k] >> shift) & mask;
+        if (d != cur) {
+            atomicAdd(&h[cur], run);
+            cur = d;
+            run = 0;
+        }
+        ++run;
+    }
+    atomicAdd(&h[cur], run);
 }
 
-__global__ void keys32_kernel(StepParams P, State32 S, int tile_shift, int tile_bits,
-                              uint32_t *keys, uint32_t *vals, int64_t total)
+// Keys of the 16 consecutive particles of each thread, written to keys[], and
+// the tile's histogram of the low `mask` digit.  load(i0, cnt, k) fills
+// k[0 .. cnt) with the keys of particles i0 ...
+template <typename Load>
+__device__ __forceinline__ void keys_tile(Load load, int64_t total, uint32_t *keys, uint32_t mask,
+                                          uint32_t *hist, int ntiles)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= total) return;
-    const uint32_t c = S.cell[p];
-    keys[p] = tile_key((int)(c & 0xFFFFu), (int)(c >> 16), P.n, tile_shift, tile_bits,
-                       species_of_particle(P, p));
-    vals[p] = (uint32_t)p;
+    __shared__ uint32_t h[256];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * kTile + (int64_t)tid * kItems;
+    const int cnt = (int)(total - i0 < kItems ? (total - i0 > 0 ? total - i0 : 0) : kItems);
+    uint32_t k[kItems];
+    load(i0, cnt, k);
+    if (cnt == kItems) {
+#pragma unroll
+        for (int j = 0; j < kItems; j += 4)
+            *reinterpret_cast<uint4 *>(keys + i0 + j) = make_uint4(k[j], k[j + 1], k[j + 2], k[j + 3]);
+    } else {
+        for (int j = 0; j < cnt; ++j) keys[i0 + j] = k[j];
+    }
+    count_runs<kItems>(k, cnt, 0, mask, h);
+    __syncthreads();
+    hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
+}
+
+__global__ __launch_bounds__(kSortThreads) void keys64_kernel(StepParams P, State64 S,
+                                                              int tile_shift, int tile_bits,
+                                                              uint32_t *keys, int64_t total,
+                                                              uint32_t mask, uint32_t *hist,
+                                                              int ntiles)
+{
+    keys_tile(
+        [&](int64_t i0, int cnt, uint32_t *k) {
+#pragma unroll
+            for (int j = 0; j < kItems; ++j) {
+                if (j >= cnt) break;
+                const double2 x = S.pos[i0 + j];
+                const int ci = cell_of_pos(x.x, P.invh, P.n), cj = cell_of_pos(x.y, P.invh, P.n);
+                k[j] = tile_key(ci, cj, P.n, tile_shift, tile_bits, species_of_particle(P, i0 + j));
+            }
+        },
+        total, keys, mask, hist, ntiles);
+}
+
+__global__ __launch_bounds__(kSortThreads) void keys32_kernel(StepParams P, State32 S,
+                                                              int tile_shift, int tile_bits,
+                                                              uint32_t *keys, int64_t total,
+                                                              uint32_t mask, uint32_t *hist,
+                                                              int ntiles)
+{
+    keys_tile(
+        [&](int64_t i0, int cnt, uint32_t *k) {
+            uint32_t c[kItems];
+            if (cnt == kItems) {
+#pragma unroll
+                for (int j = 0; j < kItems; j += 4) {
+                    const uint4 q = *reinterpret_cast<const uint4 *>(S.cell + i0 + j);
+                    c[j] = q.x;
+                    c[j + 1] = q.y;
+                    c[j + 2] = q.z;
+                    c[j + 3] = q.w;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < kItems; ++j) c[j] = j < cnt ? S.cell[i0 + j] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < kItems; ++j)
+                k[j] = tile_key((int)(c[j] & 0xFFFFu), (int)(c[j] >> 16), P.n, tile_shift,
+                                tile_bits, species_of_particle(P, i0 + j));
+        },
+        total, keys, mask, hist, ntiles);
 }
 
 static int64_t total_particles(const StepParams &P)
@@ -91,37 +174,25 @@ static int ilog2(int t)
     return s;
 }
 
+static uint32_t first_mask(int key_bits) { return key_bits >= 8 ? 0xFFu : (1u << key_bits) - 1u; }
+
 hipError_t launch_keys64(const StepParams &P, const State64 &S, int tile, int tile_bits,
-                         uint32_t *keys, uint32_t *vals, hipStream_t st)
+                         int key_bits, SortWork &W, hipStream_t st)
 {
     const int64_t total = total_particles(P);
-    const int b = 256;
-    hipLaunchKernelGGL(keys64_kernel, dim3((unsigned)((total + b - 1) / b)), dim3(b), 0, st, P, S,
-                       ilog2(tile), tile_bits, keys, vals, total);
+    const int ntiles = (int)((total + kTile - 1) / kTile);
+    hipLaunchKernelGGL(keys64_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, P, S, ilog2(tile),
+                       tile_bits, W.keys[0], total, first_mask(key_bits), W.hist, ntiles);
     return hipGetLastError();
 }
 
 hipError_t launch_keys32(const StepParams &P, const State32 &S, int tile, int tile_bits,
-                         uint32_t *keys, uint32_t *vals, hipStream_t st)
+                         int key_bits, SortWork &W, hipStream_t st)
 {
     const int64_t total = total_particles(P);
-    const int b = 256;
-    hipLaunchKernelGGL(keys32_kernel, dim3((unsigned)((total + b - 1) / b)), dim3(b), 0, st, P, S,
-                       ilog2(tile), tile_bits, keys, vals, total);
-    return hipGetLastError();
-}
-
-__global__ void iota_kernel(uint32_t *v, int64_t n)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n) v[p] = (uint32_t)p;
-}
-
-hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    const int b = 256;
-    hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, v, n);
+    const int ntiles = (int)((total + kTile - 1) / kTile);
+    hipLaunchKernelGGL(keys32_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, P, S, ilog2(tile),
+                       tile_bits, W.keys[0], total, first_mask(key_bits), W.hist, ntiles);
     return hipGetLastError();
 }
 
@@ -136,12 +207,23 @@ __global__ __launch_bounds__(kSortThreads) void hist_kernel(const uint32_t *__re
     const int tid = threadIdx.x;
     h[tid] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t i0 = (int64_t)blockIdx.x * kTile + (int64_t)tid * kItems;
+    const int cnt = (int)(n - i0 < kItems ? (n - i0 > 0 ? n - i0 : 0) : kItems);
+    uint32_t k[kItems];
+    if (cnt == kItems) {
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int64_t i = base + (int64_t)k * kSortThreads + tid;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+        for (int j = 0; j < kItems; j += 4) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(keys + i0 + j);
+            k[j] = q.x;
+            k[j + 1] = q.y;
+            k[j + 2] = q.z;
+            k[j + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) k[j] = j < cnt ? keys[i0 + j] : 0u;
     }
+    count_runs<kItems>(k, cnt, shift, mask, h);
     __syncthreads();
     hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
 }
@@ -229,7 +311,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t *a, in
 }
 
 __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
-    const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
+    const uint32_t *__restrict__ keys_in, const uint32_t *vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, int64_t n, int shift,
     uint32_t mask, const uint32_t *__restrict__ offsets, int ntiles)
 {
@@ -247,7 +329,7 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
         const int64_t i = run0 + (int64_t)it * 64 + lane;
         const bool valid = i < n;
         key[it] = valid ? keys_in[i] : 0u;
-        val[it] = valid ? vals_in[i] : 0u;
+        val[it] = !valid ? 0u : vals_in ? vals_in[i] : (uint32_t)i;
         const uint32_t d = (key[it] >> shift) & mask;
         uint64_t m = __ballot(valid);
 #pragma unroll
@@ -284,7 +366,8 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
     }
 }
 
-hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, int *result, hipStream_t st)
+hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, bool first_hist, int *result,
+                      hipStream_t st)
 {
     *result = 0;
     if (n <= 1) return hipSuccess;
@@ -296,16 +379,18 @@ hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, int *result, hipStre
     for (int shift = 0; shift < key_bits; shift += 8) {
         const int bits = key_bits - shift < 8 ? key_bits - shift : 8;
         const uint32_t mask = (1u << bits) - 1u;
-        hipLaunchKernelGGL(hist_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, W.keys[cur], n,
-                           shift, mask, W.hist, ntiles);
+        if (shift > 0 || !first_hist)
+            hipLaunchKernelGGL(hist_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, W.keys[cur],
+                               n, shift, mask, W.hist, ntiles);
         hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st,
                            W.hist, m, W.scan_tmp);
         hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kTopThreads), 0, st, W.scan_tmp, nb);
         hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st, W.hist,
                            m, W.scan_tmp);
+        // the first pass takes each key's input index as its value
         hipLaunchKernelGGL(scatter_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, W.keys[cur],
-                           W.vals[cur], W.keys[1 - cur], W.vals[1 - cur], n, shift, mask, W.hist,
-                           ntiles);
+                           shift == 0 ? (const uint32_t *)nullptr : W.vals[cur], W.keys[1 - cur],
+                           W.vals[1 - cur], n, shift, mask, W.hist, ntiles);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         cur = 1 - cur;

@@ -46,13 +46,6 @@ __device__ __forceinline__ void block_sum3(double a, double b, double c, double 
     }
 }
 
-// Halo extents of a scheme: a bilinear stencil spans nodes i..i+1, a bicubic
-// one i-1..i+2 (the compatibility fallback to bilinear stays inside both).
-__device__ __forceinline__ void stencil_reach(int scheme, int &lo, int &hi)
-{
-    lo = scheme == kBilinear ? 0 : 1;
-    hi = scheme == kBilinear ? 1 : 2;
-}
 
 template <bool CUBIC, bool INERTIAL, bool STATS>
 __device__ __forceinline__ void step64_block(const StepParams &P, const State64 &S,
@@ -298,24 +291,54 @@ __device__ __forceinline__ int wrapn(int c, const StepParams &P)
     return wrap_cell(c, P.n, P.mask);
 }
 
-// Node records of one stencil row / column combination, evaluated from the
-// records starting at p with row pitch `pitch`.  ONE: read the half `h` of
-// each record (temporal weight (1, 0) or (0, 1)); else blend both halves
-// with (wa, wb).
-template <int SCH>
-__device__ __forceinline__ void eval32(const float4 *p, int pitch, float xi, float eta, bool one,
-                                       int h, float wa, float wb, float &u, float &v)
+// Node accessors of the FP32 step.  Global memory holds one {u0, v0, u1, v1}
+// record per node (ghost-bordered rows of `pitch` records); the LDS tile
+// holds two planes of (u, v), one per time level, so that a stage reading a
+// single level gathers 8 dense bytes per node.  Both are addressed from the
+// stencil's origin node (a, b: column and row offsets from it).
+struct GlobalNodes {
+    const float4 *p;
+    int pitch;
+    __device__ __forceinline__ float2 level(int a, int b, int h) const
+    {
+        return reinterpret_cast<const float2 *>(p + (b * pitch + a))[h];
+    }
+    __device__ __forceinline__ float4 both(int a, int b) const { return p[b * pitch + a]; }
+};
+
+struct TileNodes {
+    const float2 *p;   // origin node in plane 0
+    int pitch;         // tile width
+    int plane;         // entries per plane (tile area)
+    __device__ __forceinline__ float2 level(int a, int b, int h) const
+    {
+        return p[h * plane + b * pitch + a];
+    }
+    __device__ __forceinline__ float4 both(int a, int b) const
+    {
+        const float2 x = p[b * pitch + a], y = p[plane + b * pitch + a];
+        return make_float4(x.x, x.y, y.x, y.y);
+    }
+};
+
+// Velocity of one stencil (eqs. bilinear_interp, cr_interp, bspline_interp)
+// with the temporal interpolation of eq. temporal_interp: ONE reads only
+// level h (weight (1, 0) or (0, 1)); otherwise both levels blend with
+// (wa, wb).
+template <int SCH, typename Nodes>
+__device__ __forceinline__ void eval32(const Nodes &N, float xi, float eta, bool one, int h,
+                                       float wa, float wb, float &u, float &v)
 {
     if constexpr (SCH == kBilinear) {
         float w00, w10, w01, w11;
         bilinear_weights(xi, eta, w00, w10, w01, w11);
         if (one) {
-            const float2 *q = reinterpret_cast<const float2 *>(p) + h;
-            const float2 a = q[0], b = q[2], c = q[2 * pitch], d = q[2 * pitch + 2];
+            const float2 a = N.level(0, 0, h), b = N.level(1, 0, h);
+            const float2 c = N.level(0, 1, h), d = N.level(1, 1, h);
             u = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
             v = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
         } else {
-            const float4 a = p[0], b = p[1], c = p[pitch], d = p[pitch + 1];
+            const float4 a = N.both(0, 0), b = N.both(1, 0), c = N.both(0, 1), d = N.both(1, 1);
             const float ua = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
             const float va = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
             const float ub = w00 * a.z + w10 * b.z + w01 * c.z + w11 * d.z;
@@ -332,8 +355,56 @@ __device__ __forceinline__ void eval32(const float4 *p, int pitch, float xi, flo
             weights_bs(xi, wx);
             weights_bs(eta, wy);
         }
-        cub32(p, pitch, wx, wy, one ? h : kBlend, wa, wb, u, v);
+        if (one) {
+            float au = 0.f, av = 0.f;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                float ru = 0.f, rv = 0.f;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const float2 r = N.level(a, b, h);
+                    ru += wx[a] * r.x;
+                    rv += wx[a] * r.y;
+                }
+                au += wy[b] * ru;
+                av += wy[b] * rv;
+            }
+            u = au;
+            v = av;
+        } else {
+            float au = 0.f, av = 0.f, bu = 0.f, bv = 0.f;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                float ru = 0.f, rv = 0.f, su = 0.f, sv = 0.f;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const float4 r = N.both(a, b);
+                    ru += wx[a] * r.x;
+                    rv += wx[a] * r.y;
+                    su += wx[a] * r.z;
+                    sv += wx[a] * r.w;
+                }
+                au += wy[b] * ru;
+                av += wy[b] * rv;
+                bu += wy[b] * su;
+                bv += wy[b] * sv;
+            }
+            u = wa * au + wb * bu;
+            v = wa * av + wb * bv;
+        }
     }
+}
+
+__device__ __forceinline__ TileNodes tile_nodes(const float4 *lds, const Tile &T, int tx, int ty)
+{
+    return TileNodes{reinterpret_cast<const float2 *>(lds) + (__mul24(ty, T.w) + tx), T.w,
+                     T.w * T.h};
+}
+
+__device__ __forceinline__ GlobalNodes global_nodes(const float4 *rec0, const StepParams &P,
+                                                    int i, int j)
+{
+    return GlobalNodes{rec0 + (__mul24(j, P.pitch) + i), P.pitch};
 }
 
 // Fluid velocity (cells per unit time) of one RK4 stage at stored cell
@@ -355,18 +426,17 @@ __device__ __forceinline__ void stage32(const float4 *__restrict__ rec0, const f
         if (P.compat_edge) {   // the paper's bilinear fallback near the grid edge
             const int i = wrapn(cx + fx, P), j = wrapn(cy + fy, P);
             if (edge_cell(1, i, j, P.n)) {
-                eval32<kBilinear>(rec0 + (__mul24(j, P.pitch) + i), P.pitch, xi, eta, one, h, wa,
-                                  wb, u, v);
+                eval32<kBilinear>(global_nodes(rec0, P, i, j), xi, eta, one, h, wa, wb, u, v);
                 return;
             }
         }
     }
     const int tx = rx + fx - c1, ty = ry + fy - c1;
     if (T.on && (unsigned)tx <= (unsigned)(T.w - span) && (unsigned)ty <= (unsigned)(T.h - span)) {
-        eval32<SCH>(lds + (__mul24(ty, T.w) + tx), T.w, xi, eta, one, h, wa, wb, u, v);
+        eval32<SCH>(tile_nodes(lds, T, tx, ty), xi, eta, one, h, wa, wb, u, v);
     } else {
         const int i = wrapn(cx + fx, P) - c1, j = wrapn(cy + fy, P) - c1;
-        eval32<SCH>(rec0 + (__mul24(j, P.pitch) + i), P.pitch, xi, eta, one, h, wa, wb, u, v);
+        eval32<SCH>(global_nodes(rec0, P, i, j), xi, eta, one, h, wa, wb, u, v);
     }
 }
 
@@ -387,10 +457,9 @@ __device__ __forceinline__ void stage32_first(const float4 *__restrict__ rec0, c
         return;
     }
     if (T.on)
-        eval32<SCH>(lds + (__mul24(ry - c1, T.w) + (rx - c1)), T.w, o.x, o.y, ONE, h, wa, wb, u, v);
+        eval32<SCH>(tile_nodes(lds, T, rx - c1, ry - c1), o.x, o.y, ONE, h, wa, wb, u, v);
     else
-        eval32<SCH>(rec0 + (__mul24(cy - c1, P.pitch) + (cx - c1)), P.pitch, o.x, o.y, ONE, h, wa,
-                    wb, u, v);
+        eval32<SCH>(global_nodes(rec0, P, cx - c1, cy - c1), o.x, o.y, ONE, h, wa, wb, u, v);
 }
 
 // One RK4 step of one particle (eqs. rk4_update / rk4_inertial, Stokes drag
