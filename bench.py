@@ -212,7 +212,8 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False):
 def bench_adjoint(args, lpt):
     """2048^2 FP64 steady Taylor-Green + 0.1 x (k0 = 10 spectrum), 2^22
     tracers on the cell-centre lattice, bilinear, 200 steps of dt = 0.01 with
-    checkpoints every 20: the checkpointed forward run, the reverse sweep with
+    checkpoints every 20 (from cell order: one re-sort before the first
+    step): the checkpointed forward run, the reverse sweep with
     grid gradients of L = sum(a x_T + b y_T), and the Jacobian sweep."""
     import torch
     from paper_2607_17836_amd import synth
@@ -226,7 +227,7 @@ def bench_adjoint(args, lpt):
     dev = "cuda"
     a = torch.tensor(rng.normal(size=npart), device=dev)
     b = torch.tensor(rng.normal(size=npart), device=dev)
-    tr = lpt.Tracker(n, "fp64")
+    tr = lpt.Tracker(n, "fp64", sort_interval=20)
     tr.set_snapshot(0, 0.0, u, v)
     tr.set_snapshot(1, nsteps * dt, u, v)
     tr.add_species("tracer", 0.0, "bilinear", x0, y0)

@@ -272,8 +272,9 @@ lpt_status lpt_time_steps(lpt_ctx *ctx, int64_t nsteps, double dt, int32_t stats
  * index is constant, so d(xi)/dx = n/L.  LPT_FP64 contexts whose species are
  * all tracers (or St = 0) only; otherwise LPT_E_STATE. */
 
-/* Advance every species by nsteps steps like lpt_step (no statistics, no
- * re-sort), keeping the positions at every ckpt_every-th step and each
+/* Advance every species by nsteps steps like lpt_step (no statistics; with
+ * sort_interval > 0, one cell-order re-sort before the first step and none
+ * after it), keeping the positions at every ckpt_every-th step and each
  * step's temporal weights, so that lpt_adjoint / lpt_jacobian can recompute
  * the trajectory segment by segment.  Device memory: ceil(nsteps /
  * ckpt_every) * 16 bytes per particle for the checkpoints, plus

@@ -204,7 +204,8 @@ __global__ __launch_bounds__(kMaxBlock) void recompute64_kernel(StepParams P, co
 // of the grid (its particles' cells widened by the step's displacement
 // bound and the stencil reach; acc_cap nodes of LDS) and then adds the box
 // to gU with one atomic per nonzero entry; contributions outside the box
-// (particles faster than the bound) go to gU directly.
+// (particles faster than the bound, or a box beyond the LDS budget, which is
+// trimmed) go to gU directly.
 extern __shared__ __align__(32) unsigned char adj_dyn_lds[];
 
 template <int NL, bool AGG>
@@ -233,11 +234,21 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
         int lo, hi;
         stencil_reach(scheme, lo, hi);
         const int H = step_halo(P, scheme, (float)dt);
-        G.B = block_box(active, me.i, me.j, an.i, an.j, P.n, P.mask, lo + H, hi + H);
-        const int area = G.B.w * G.B.h;
-        G.B.on = area <= acc_cap && G.B.w < P.n && G.B.h < P.n;
-        if (G.B.on)
-            for (int k = threadIdx.x; k < 4 * area; k += blockDim.x) G.acc[k] = 0.0;
+        Tile B = block_box(active, me.i, me.j, an.i, an.j, P.n, P.mask, lo + H, hi + H);
+        // a box beyond the LDS budget first loses halo, then rows: whatever
+        // falls outside it is added to gU directly
+        int shrink = 0;
+        while (shrink < H && (B.w - 2 * shrink) * (B.h - 2 * shrink) > acc_cap) ++shrink;
+        B.w -= 2 * shrink;
+        B.h -= 2 * shrink;
+        B.x0 = wrap_cell(B.x0 + shrink, P.n, P.mask);
+        B.y0 = wrap_cell(B.y0 + shrink, P.n, P.mask);
+        B.w = min(min(B.w, acc_cap), P.n - 1);
+        B.h = min(min(B.h, acc_cap / B.w), P.n - 1);
+        B.on = 1;
+        G.B = B;
+        const int area = B.w * B.h;
+        for (int k = threadIdx.x; k < 4 * area; k += blockDim.x) G.acc[k] = 0.0;
         __syncthreads();
     }
 

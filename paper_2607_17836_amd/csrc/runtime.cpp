@@ -1011,6 +1011,12 @@ lpt_status lpt_forward_checkpointed(lpt_ctx *c, int64_t nsteps, double dt, int32
     c->ck_step0 = c->steps;
     c->ck_t0 = c->t;
     c->ck_valid = false;
+    // with re-sorting enabled, the run starts from cell order (kept for its
+    // whole length), so both sweeps touch the grid coherently per block
+    if (c->sort_interval > 0) {
+        s = do_sort(c);
+        if (s != LPT_OK) return s;
+    }
     s = run_steps(c, nsteps, dt, 0, true);
     if (s != LPT_OK) return s;
     c->ck_valid = true;
