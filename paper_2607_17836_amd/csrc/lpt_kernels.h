@@ -110,10 +110,14 @@ hipError_t launch_psi_to_velocity(const double *psi, double *u, double *v, int n
 hipError_t launch_step64(const StepParams &P, const State64 &S, const Rec64 *rec,
                          double *partials, DevClock *clock, bool stats, bool cubic,
                          bool inertial, int block, int grid, hipStream_t st);
-// schemes: the scheme shared by every species, or 3 if they differ.
-hipError_t launch_step32(const StepParams &P, const State32 &S, const float4 *rec,
-                         double *partials, DevClock *clock, bool stats, int schemes,
-                         bool inertial, int block, int grid, hipStream_t st);
+// schemes: the scheme shared by every species, or 3 if they differ.  The
+// step works in place on S; with perm (the permutation of a re-sort, dst
+// slot -> src slot) it reads S through perm and writes D, a different
+// buffer, so that it also applies the permutation (id included).
+hipError_t launch_step32(const StepParams &P, const State32 &S, const State32 &D,
+                         const uint32_t *perm, const float4 *rec, double *partials,
+                         DevClock *clock, bool stats, int schemes, bool inertial, int block,
+                         int grid, hipStream_t st);
 
 hipError_t launch_finalize(const StepParams &P, const double *partials, DevClock *clock,
                            double *records, int64_t rec_cap, double t0, hipStream_t st);

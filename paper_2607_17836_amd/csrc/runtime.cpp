@@ -287,8 +287,14 @@ hipError_t mark(lpt_ctx *c, hipEvent_t &ev)
     return r != hipSuccess ? r : hipEventRecord(ev, c->stream);
 }
 
-lpt_status do_sort(lpt_ctx *c)
+// Cell-order re-sort: keys, radix sort, then the permutation of the state
+// into the other buffer.  With `perm_out` (FP32 contexts), the permutation is
+// left to the caller's next step kernel instead, which reads through it:
+// *perm_out receives the permutation (dst slot -> src slot; null if nothing
+// was sorted) and the state buffer does not change here.
+lpt_status do_sort(lpt_ctx *c, const uint32_t **perm_out = nullptr)
 {
+    if (perm_out) *perm_out = nullptr;
     if (c->np <= 1) return LPT_OK;
     lpt_status s = ensure_sort_work(c);
     if (s != LPT_OK) return s;
@@ -304,6 +310,14 @@ lpt_status do_sort(lpt_ctx *c)
     int res = 0;
     HIP_TRY(c, radix_sort(c->sw, c->np, kb, true, &res, c->stream));
     const uint32_t *perm = c->sw.vals[res];
+    if (perm_out && c->precision == LPT_FP32_SPLIT) {
+        *perm_out = perm;
+        if (c->time_kernels) {
+            HIP_TRY(c, mark(c, e1));
+            c->ev_sort.emplace_back(e0, e1);
+        }
+        return LPT_OK;
+    }
     if (c->precision == LPT_FP64)
         HIP_TRY(c, launch_permute64(c->s64[c->cur], c->s64[1 - c->cur], perm, c->np,
                                     c->has_inertial, c->stream));
@@ -797,12 +811,14 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
     StepParams P = make_params(c);
     set_dt(P, dt);
     for (int64_t k = 0; k < nsteps; ++k) {
+        // an FP32 step right after a re-sort applies its permutation itself
+        const uint32_t *perm = nullptr;
         if (!ckpt && c->sort_interval > 0 && c->steps % c->sort_interval == 0) {
             if (launch) {
-                const lpt_status s = do_sort(c);
+                const lpt_status s = do_sort(c, &perm);
                 if (s != LPT_OK) return s;
             } else if (c->np > 1) {
-                c->cur = 1 - c->cur;   // what do_sort does to the host state
+                c->cur = 1 - c->cur;   // where the sort leaves the host state
             }
         }
         step_weights(c, dt, P);
@@ -831,10 +847,13 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
             HIP_TRY(c, launch_step64(P, c->s64[c->cur], static_cast<const Rec64 *>(c->rec),
                                      c->partials, c->clock, rec, c->has_cubic, c->has_inertial,
                                      c->block, P.total_blocks, c->stream));
-        else
-            HIP_TRY(c, launch_step32(P, c->s32[c->cur], static_cast<const float4 *>(c->rec),
-                                     c->partials, c->clock, rec, common_scheme(c),
-                                     c->has_inertial, c->block, P.total_blocks, c->stream));
+        else {
+            HIP_TRY(c, launch_step32(P, c->s32[c->cur], c->s32[perm ? 1 - c->cur : c->cur], perm,
+                                     static_cast<const float4 *>(c->rec), c->partials, c->clock,
+                                     rec, common_scheme(c), c->has_inertial, c->block,
+                                     P.total_blocks, c->stream));
+            if (perm) c->cur = 1 - c->cur;
+        }
         if (c->time_kernels) {
             HIP_TRY(c, mark(c, e1));
             c->ev_step.emplace_back(e0, e1);

@@ -467,9 +467,10 @@ __device__ __forceinline__ void stage32_first(const float4 *__restrict__ rec0, c
 // displacement.  Returns the new displacement squared per axis.
 template <int SCH, bool INERT, bool ONE>
 __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S,
-                                           const float4 *__restrict__ rec0, const float4 *lds,
-                                           const Tile &T, const SpeciesDev &sp, int64_t p,
-                                           uint32_t &cell, float2 o, double &r2x, double &r2y)
+                                           const State32 &D, const float4 *__restrict__ rec0,
+                                           const float4 *lds, const Tile &T, const SpeciesDev &sp,
+                                           int64_t p, int64_t q, uint32_t &cell, float2 o,
+                                           double &r2x, double &r2y)
 {
     int cx = (int)(cell & 0xFFFFu), cy = (int)(cell >> 16);
     int rx = 0, ry = 0;
@@ -483,7 +484,7 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
     constexpr bool one = ONE;   // first / last stage read a single time level
     float dqx, dqy;
     if constexpr (INERT) {
-        const float2 vn = ld_stream(S.vel + p);
+        const float2 vn = ld_stream(S.vel + q);
         const float is = (float)sp.inv_st;
         float u, v;
         const float V1x = vn.x, V1y = vn.y;
@@ -503,7 +504,7 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
         const float A4x = (u - V4x) * is, A4y = (v - V4y) * is;
         dqx = dt6 * (V1x + 2.0f * V2x + 2.0f * V3x + V4x);
         dqy = dt6 * (V1y + 2.0f * V2y + 2.0f * V3y + V4y);
-        st_stream(S.vel + p, make_float2(vn.x + dt6 * (A1x + 2.0f * A2x + 2.0f * A3x + A4x),
+        st_stream(D.vel + p, make_float2(vn.x + dt6 * (A1x + 2.0f * A2x + 2.0f * A3x + A4x),
                                          vn.y + dt6 * (A1y + 2.0f * A2y + 2.0f * A3y + A4y)));
     } else {
         float k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
@@ -521,13 +522,13 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
     float ox = o.x, oy = o.y;
     advance_split(cx, ox, dqx, P);
     advance_split(cy, oy, dqy, P);
-    double2 d = ld_stream(S.disp + p);
+    double2 d = ld_stream(S.disp + q);
     cell = (uint32_t)cx | ((uint32_t)cy << 16);
-    st_stream(S.cell + p, cell);
-    st_stream(S.off + p, make_float2(ox, oy));
+    st_stream(D.cell + p, cell);
+    st_stream(D.off + p, make_float2(ox, oy));
     d.x += (double)dqx * P.h;
     d.y += (double)dqy * P.h;
-    st_stream(S.disp + p, d);
+    st_stream(D.disp + p, d);
     r2x = d.x * d.x;
     r2y = d.y * d.y;
 }
@@ -547,33 +548,40 @@ constexpr bool scheme_compiled()
 // and kinds the launch may meet.
 template <int SCHS, int KINDS, bool ONE>
 __device__ __forceinline__ void particle_dispatch(const StepParams &P, const State32 &S,
+                                                  const State32 &D,
                                                   const float4 *__restrict__ rec0,
                                                   const float4 *lds, const Tile &T,
-                                                  const SpeciesDev &sp, int64_t p, uint32_t &cell,
-                                                  float2 o, double &r2x, double &r2y)
+                                                  const SpeciesDev &sp, int64_t p, int64_t q,
+                                                  uint32_t &cell, float2 o, double &r2x,
+                                                  double &r2y)
 {
     const bool inert = KINDS != 0 && sp.inertial;
     if (scheme_compiled<kBilinear, SCHS>() && (SCHS != kAnyScheme || sp.scheme == kBilinear)) {
         if (KINDS != 0 && inert)
-            particle32<kBilinear, KINDS != 0, ONE>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+            particle32<kBilinear, KINDS != 0, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
         else
-            particle32<kBilinear, false, ONE>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+            particle32<kBilinear, false, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
     } else if (scheme_compiled<kCatmullRom, SCHS>() &&
                (SCHS != kAnyScheme || sp.scheme == kCatmullRom)) {
         if (KINDS != 0 && inert)
-            particle32<kCatmullRom, KINDS != 0, ONE>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+            particle32<kCatmullRom, KINDS != 0, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
         else
-            particle32<kCatmullRom, false, ONE>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+            particle32<kCatmullRom, false, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
     } else if (scheme_compiled<kBSpline, SCHS>()) {
         if (KINDS != 0 && inert)
-            particle32<kBSpline, KINDS != 0, ONE>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+            particle32<kBSpline, KINDS != 0, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
         else
-            particle32<kBSpline, false, ONE>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+            particle32<kBSpline, false, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
     }
 }
 
-template <int SCHS, int KINDS, bool STATS>
+// One logical block of the step.  The state of slot p is read from S and
+// written to D: in place, or, on a step that follows a re-sort (GATHER),
+// slot p of D takes the particle of slot perm[p] of S, id included, so that
+// the step itself applies the sort's permutation.
+template <int SCHS, int KINDS, bool STATS, bool GATHER>
 __device__ __forceinline__ void step32_block(const StepParams &P, const State32 &S,
+                                             const State32 &D, const uint32_t *perm,
                                              const float4 *__restrict__ rec,
                                              double *__restrict__ partials, DevClock *clock,
                                              int lb)
@@ -587,11 +595,13 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
     const float4 *rec0 = rec + P.pitch + 1;
     double r2x = 0.0, r2y = 0.0;
 
+    int64_t q = p;
     uint32_t cell = 0;
     float2 o = make_float2(0.f, 0.f);
     if (active) {
-        cell = ld_stream(S.cell + p);
-        o = ld_stream(S.off + p);
+        if (GATHER) q = perm[p];
+        cell = ld_stream(S.cell + q);
+        o = ld_stream(S.off + q);
     }
     Tile T = no_tile();
     if (P.tile_cap > 0) {
@@ -600,15 +610,19 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
         const int H = step_halo(P, sp.scheme, P.dtf);
         const int64_t left = sp.count - base;
         const int nact = (int)(left < (int64_t)blockDim.x ? left : blockDim.x);
-        const uint32_t a = S.cell[sp.offset + base];
+        const int64_t a0 = sp.offset + base;
+        const uint32_t a = S.cell[GATHER ? (int64_t)perm[a0] : a0];
         T = stage_tile<float4>(lds, rec0, P, active, (int)(cell & 0xFFFFu), (int)(cell >> 16),
                                (int)(a & 0xFFFFu), (int)(a >> 16), lo + H, hi + H, nact);
     }
     if (active) {
         if (P.ends_one)
-            particle_dispatch<SCHS, KINDS, true>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+            particle_dispatch<SCHS, KINDS, true>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x,
+                                                 r2y);
         else
-            particle_dispatch<SCHS, KINDS, false>(P, S, rec0, lds, T, sp, p, cell, o, r2x, r2y);
+            particle_dispatch<SCHS, KINDS, false>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x,
+                                                  r2y);
+        if (GATHER) D.id[p] = S.id[q];
     }
     if (STATS) {
         const double r2 = r2x + r2y;
@@ -630,20 +644,38 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
 template <int SCHS, int KINDS, bool STATS>
 __global__ __launch_bounds__(kMaxBlock)
 __attribute__((amdgpu_waves_per_eu(SCHS == kBilinear ? 8 : 1)))
-void step32_kernel(StepParams P, State32 S,
-                                                           const float4 *__restrict__ rec,
-                                                           double *__restrict__ partials,
-                                                           DevClock *clock)
+void step32_kernel(StepParams P, State32 S, const float4 *__restrict__ rec,
+                   double *__restrict__ partials, DevClock *clock)
 {
     if (!P.persistent) {
-        step32_block<SCHS, KINDS, STATS>(P, S, rec, partials, clock,
-                                         xcd_logical_block(blockIdx.x, gridDim.x));
+        step32_block<SCHS, KINDS, STATS, false>(P, S, S, nullptr, rec, partials, clock,
+                                                xcd_logical_block(blockIdx.x, gridDim.x));
         return;
     }
     int first, stride, end;
     persistent_range(P.total_blocks, first, stride, end);
     for (int lb = first; lb < end; lb += stride)
-        step32_block<SCHS, KINDS, STATS>(P, S, rec, partials, clock, lb);
+        step32_block<SCHS, KINDS, STATS, false>(P, S, S, nullptr, rec, partials, clock, lb);
+}
+
+// The step that follows a re-sort: reads S through perm, writes D.  (A kernel
+// of its own, so that the in-place kernel above keeps its argument list.)
+template <int SCHS, int KINDS, bool STATS>
+__global__ __launch_bounds__(kMaxBlock)
+__attribute__((amdgpu_waves_per_eu(SCHS == kBilinear ? 8 : 1)))
+void step32_perm_kernel(StepParams P, State32 S, State32 D, const uint32_t *perm,
+                        const float4 *__restrict__ rec, double *__restrict__ partials,
+                        DevClock *clock)
+{
+    if (!P.persistent) {
+        step32_block<SCHS, KINDS, STATS, true>(P, S, D, perm, rec, partials, clock,
+                                               xcd_logical_block(blockIdx.x, gridDim.x));
+        return;
+    }
+    int first, stride, end;
+    persistent_range(P.total_blocks, first, stride, end);
+    for (int lb = first; lb < end; lb += stride)
+        step32_block<SCHS, KINDS, STATS, true>(P, S, D, perm, rec, partials, clock, lb);
 }
 
 // Grid of a launch: one workgroup per logical block, or -- when the step
@@ -685,28 +717,38 @@ static hipError_t launch64_t(const StepParams &P, const State64 &St, const Rec64
 }
 
 template <int SCHS, int KINDS, bool ST>
-static hipError_t launch32_t(const StepParams &P, const State32 &St, const float4 *rec,
-                             double *partials, DevClock *clock, int block, int grid,
-                             hipStream_t st)
+static hipError_t launch32_t(const StepParams &P, const State32 &S, const State32 &D,
+                             const uint32_t *perm, const float4 *rec, double *partials,
+                             DevClock *clock, int block, int grid, hipStream_t st)
 {
     const size_t lds = P.tile_cap > 0 ? (size_t)P.tile_cap * sizeof(float4) : 0;
     StepParams Q;
-    const int g = launch_grid(step32_kernel<SCHS, KINDS, ST>, P, block, lds, grid, Q);
-    hipLaunchKernelGGL((step32_kernel<SCHS, KINDS, ST>), dim3(g), dim3(block), lds, st, Q, St,
-                       rec, partials, clock);
+    if (perm) {
+        const int g = launch_grid(step32_perm_kernel<SCHS, KINDS, ST>, P, block, lds, grid, Q);
+        hipLaunchKernelGGL((step32_perm_kernel<SCHS, KINDS, ST>), dim3(g), dim3(block), lds, st,
+                           Q, S, D, perm, rec, partials, clock);
+    } else {
+        const int g = launch_grid(step32_kernel<SCHS, KINDS, ST>, P, block, lds, grid, Q);
+        hipLaunchKernelGGL((step32_kernel<SCHS, KINDS, ST>), dim3(g), dim3(block), lds, st, Q, S,
+                           rec, partials, clock);
+    }
     return hipGetLastError();
 }
 
 template <int SCHS>
-static hipError_t launch32_s(const StepParams &P, const State32 &S, const float4 *rec,
-                             double *partials, DevClock *clock, bool stats, bool inertial,
-                             int block, int grid, hipStream_t st)
+static hipError_t launch32_s(const StepParams &P, const State32 &S, const State32 &D,
+                             const uint32_t *perm, const float4 *rec, double *partials,
+                             DevClock *clock, bool stats, bool inertial, int block, int grid,
+                             hipStream_t st)
 {
     if (inertial)
-        return stats ? launch32_t<SCHS, 1, true>(P, S, rec, partials, clock, block, grid, st)
-                     : launch32_t<SCHS, 1, false>(P, S, rec, partials, clock, block, grid, st);
-    return stats ? launch32_t<SCHS, 0, true>(P, S, rec, partials, clock, block, grid, st)
-                 : launch32_t<SCHS, 0, false>(P, S, rec, partials, clock, block, grid, st);
+        return stats ? launch32_t<SCHS, 1, true>(P, S, D, perm, rec, partials, clock, block, grid,
+                                                 st)
+                     : launch32_t<SCHS, 1, false>(P, S, D, perm, rec, partials, clock, block,
+                                                  grid, st);
+    return stats ? launch32_t<SCHS, 0, true>(P, S, D, perm, rec, partials, clock, block, grid, st)
+                 : launch32_t<SCHS, 0, false>(P, S, D, perm, rec, partials, clock, block, grid,
+                                              st);
 }
 
 #define LPT_DISPATCH(fn, ...)                                                        \
@@ -731,19 +773,24 @@ hipError_t launch_step64(const StepParams &P, const State64 &S, const Rec64 *rec
     LPT_DISPATCH(launch64_t, P, S, rec, partials, clock, block, grid, st);
 }
 
-hipError_t launch_step32(const StepParams &P, const State32 &S, const float4 *rec,
-                         double *partials, DevClock *clock, bool stats, int schemes,
-                         bool inertial, int block, int grid, hipStream_t st)
+hipError_t launch_step32(const StepParams &P, const State32 &S, const State32 &D,
+                         const uint32_t *perm, const float4 *rec, double *partials,
+                         DevClock *clock, bool stats, int schemes, bool inertial, int block,
+                         int grid, hipStream_t st)
 {
     switch (schemes) {
     case kBilinear:
-        return launch32_s<kBilinear>(P, S, rec, partials, clock, stats, inertial, block, grid, st);
+        return launch32_s<kBilinear>(P, S, D, perm, rec, partials, clock, stats, inertial, block,
+                                     grid, st);
     case kCatmullRom:
-        return launch32_s<kCatmullRom>(P, S, rec, partials, clock, stats, inertial, block, grid, st);
+        return launch32_s<kCatmullRom>(P, S, D, perm, rec, partials, clock, stats, inertial,
+                                       block, grid, st);
     case kBSpline:
-        return launch32_s<kBSpline>(P, S, rec, partials, clock, stats, inertial, block, grid, st);
+        return launch32_s<kBSpline>(P, S, D, perm, rec, partials, clock, stats, inertial, block,
+                                    grid, st);
     default:
-        return launch32_s<kAnyScheme>(P, S, rec, partials, clock, stats, inertial, block, grid, st);
+        return launch32_s<kAnyScheme>(P, S, D, perm, rec, partials, clock, stats, inertial,
+                                      block, grid, st);
     }
 }
 // ===========================================================================
