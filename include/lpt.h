@@ -97,8 +97,9 @@ typedef struct {
     uint32_t flags;         /* LPT_FLAG_*                                     */
     int32_t tile_records;   /* capacity, in node records, of the per-block
                                LDS field tile of the step kernel: 0 selects
-                               the default (19200 bytes: 1200 FP32-split or
-                               600 FP64 records), -1 disables tiles (every
+                               the default (1200 records: 19200 bytes for
+                               FP32-split, 38400 for FP64), -1 disables
+                               tiles (every
                                stencil gathers from global memory), else
                                at least 16 records and at most 61440 bytes  */
 } lpt_config;

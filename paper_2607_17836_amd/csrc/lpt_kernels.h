@@ -107,13 +107,15 @@ hipError_t launch_speed_max(const double *u, const double *v, int64_t nn, double
 hipError_t launch_psi_to_velocity(const double *psi, double *u, double *v, int n, double h,
                                   hipStream_t st);
 
-hipError_t launch_step64(const StepParams &P, const State64 &S, const Rec64 *rec,
-                         double *partials, DevClock *clock, bool stats, bool cubic,
-                         bool inertial, int block, int grid, hipStream_t st);
-// schemes: the scheme shared by every species, or 3 if they differ.  The
-// step works in place on S; with perm (the permutation of a re-sort, dst
-// slot -> src slot) it reads S through perm and writes D, a different
-// buffer, so that it also applies the permutation (id included).
+// The step works in place on S; with perm (the permutation of a re-sort, dst
+// slot -> src slot) it reads S through perm and writes D, a different buffer,
+// so that it also applies the permutation (id included).
+hipError_t launch_step64(const StepParams &P, const State64 &S, const State64 &D,
+                         const uint32_t *perm, const Rec64 *rec, double *partials,
+                         DevClock *clock, bool stats, bool cubic, bool inertial, int block,
+                         int grid, hipStream_t st);
+// schemes: the scheme shared by every species, or 3 if they differ.  S, D
+// and perm as for launch_step64.
 hipError_t launch_step32(const StepParams &P, const State32 &S, const State32 &D,
                          const uint32_t *perm, const float4 *rec, double *partials,
                          DevClock *clock, bool stats, int schemes, bool inertial, int block,

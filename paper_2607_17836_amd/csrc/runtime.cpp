@@ -22,9 +22,12 @@ using namespace lpt;
 
 namespace {
 
-// LDS budget of the step kernel's field tile: the default keeps eight
-// 256-thread blocks (32 waves) resident per CU within the 160 KiB of LDS.
-constexpr size_t kTileBytesDefault = 19200;
+// Default capacity of the step kernel's field tile, in node records: 19200
+// bytes for FP32 (eight 256-thread blocks, 32 waves, resident per CU within
+// the 160 KiB of LDS), 38400 bytes for FP64 (four blocks; a smaller FP64
+// tile leaves too many blocks' boxes uncovered, which costs more than the
+// lost occupancy).
+constexpr int32_t kTileRecordsDefault = 1200;
 constexpr size_t kTileBytesMax = 61440;
 
 struct StepWeights {
@@ -288,8 +291,8 @@ hipError_t mark(lpt_ctx *c, hipEvent_t &ev)
 }
 
 // Cell-order re-sort: keys, radix sort, then the permutation of the state
-// into the other buffer.  With `perm_out` (FP32 contexts), the permutation is
-// left to the caller's next step kernel instead, which reads through it:
+// into the other buffer.  With `perm_out`, the permutation is left to the
+// caller's next step kernel instead, which reads through it:
 // *perm_out receives the permutation (dst slot -> src slot; null if nothing
 // was sorted) and the state buffer does not change here.
 lpt_status do_sort(lpt_ctx *c, const uint32_t **perm_out = nullptr)
@@ -310,7 +313,7 @@ lpt_status do_sort(lpt_ctx *c, const uint32_t **perm_out = nullptr)
     int res = 0;
     HIP_TRY(c, radix_sort(c->sw, c->np, kb, true, &res, c->stream));
     const uint32_t *perm = c->sw.vals[res];
-    if (perm_out && c->precision == LPT_FP32_SPLIT) {
+    if (perm_out) {
         *perm_out = perm;
         if (c->time_kernels) {
             HIP_TRY(c, mark(c, e1));
@@ -377,7 +380,7 @@ lpt_status lpt_create(const lpt_config *cfg, lpt_ctx **out)
     const size_t rec_size = cfg->precision == LPT_FP64 ? sizeof(Rec64) : sizeof(float4);
     const int32_t tile_max = (int32_t)(kTileBytesMax / rec_size);
     int32_t tile_cap = cfg->tile_records;
-    if (tile_cap == 0) tile_cap = (int32_t)(kTileBytesDefault / rec_size);
+    if (tile_cap == 0) tile_cap = kTileRecordsDefault;
     else if (tile_cap == -1) tile_cap = 0;
     else if (tile_cap < 16 || tile_cap > tile_max) return LPT_E_ARG;
 
@@ -811,7 +814,7 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
     StepParams P = make_params(c);
     set_dt(P, dt);
     for (int64_t k = 0; k < nsteps; ++k) {
-        // an FP32 step right after a re-sort applies its permutation itself
+        // the step right after a re-sort applies its permutation itself
         const uint32_t *perm = nullptr;
         if (!ckpt && c->sort_interval > 0 && c->steps % c->sort_interval == 0) {
             if (launch) {
@@ -843,11 +846,13 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->time_kernels) HIP_TRY(c, mark(c, e0));
-        if (c->precision == LPT_FP64)
-            HIP_TRY(c, launch_step64(P, c->s64[c->cur], static_cast<const Rec64 *>(c->rec),
-                                     c->partials, c->clock, rec, c->has_cubic, c->has_inertial,
-                                     c->block, P.total_blocks, c->stream));
-        else {
+        if (c->precision == LPT_FP64) {
+            HIP_TRY(c, launch_step64(P, c->s64[c->cur], c->s64[perm ? 1 - c->cur : c->cur], perm,
+                                     static_cast<const Rec64 *>(c->rec), c->partials, c->clock,
+                                     rec, c->has_cubic, c->has_inertial, c->block,
+                                     P.total_blocks, c->stream));
+            if (perm) c->cur = 1 - c->cur;
+        } else {
             HIP_TRY(c, launch_step32(P, c->s32[c->cur], c->s32[perm ? 1 - c->cur : c->cur], perm,
                                      static_cast<const float4 *>(c->rec), c->partials, c->clock,
                                      rec, common_scheme(c), c->has_inertial, c->block,
@@ -1609,7 +1614,7 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
         return fail(c, LPT_E_ARG, "block_size must be 64, 128, 256 or 512");
     const size_t rec_size = c->precision == LPT_FP64 ? sizeof(Rec64) : sizeof(float4);
     int32_t tile = t->tile_records;
-    if (tile == 0) tile = (int32_t)(kTileBytesDefault / rec_size);
+    if (tile == 0) tile = kTileRecordsDefault;
     else if (tile == -1) tile = 0;
     else if (tile < 16 || (size_t)tile > kTileBytesMax / rec_size)
         return fail(c, LPT_E_ARG, "tile_records out of range");

@@ -47,8 +47,12 @@ __device__ __forceinline__ void block_sum3(double a, double b, double c, double 
 }
 
 
-template <bool CUBIC, bool INERTIAL, bool STATS>
+// One logical block of the FP64 step: the state of slot p is read from S and
+// written to D, in place, or, on a step that follows a re-sort (GATHER), slot
+// p of D takes the particle of slot perm[p] of S, id included.
+template <bool CUBIC, bool INERTIAL, bool STATS, bool GATHER>
 __device__ __forceinline__ void step64_block(const StepParams &P, const State64 &S,
+                                             const State64 &D, const uint32_t *perm,
                                              const Rec64 *__restrict__ rec,
                                              double *__restrict__ partials, DevClock *clock,
                                              int lb)
@@ -63,11 +67,16 @@ __device__ __forceinline__ void step64_block(const StepParams &P, const State64 
     const double dt = P.dt, hdt = 0.5 * P.dt, dt6 = P.dt / 6.0;
     double r2x = 0.0, r2y = 0.0;
 
+    int64_t q = p;
     double2 x = make_double2(0.0, 0.0);
-    if (active) x = S.pos[p];
+    if (active) {
+        if (GATHER) q = perm[p];
+        x = S.pos[q];
+    }
     Tile T = no_tile();
     if (P.tile_cap > 0) {
-        const double2 a = S.pos[sp.offset + base];
+        const int64_t a0 = sp.offset + base;
+        const double2 a = S.pos[GATHER ? (int64_t)perm[a0] : a0];
         const int n = P.n, mask = P.mask;
         const int ax = cell_of_floor(floor(a.x * P.invh), n, mask);
         const int ay = cell_of_floor(floor(a.y * P.invh), n, mask);
@@ -82,11 +91,11 @@ __device__ __forceinline__ void step64_block(const StepParams &P, const State64 
     }
 
     if (active) {
-        double2 d = S.disp[p];
+        double2 d = S.disp[q];
         double ddx, ddy;
         if (INERTIAL && sp.inertial) {
             // eqs. inertial_particle, drag_rk4, rk4_inertial
-            const double2 vn = S.vel[p];
+            const double2 vn = S.vel[q];
             const double is = sp.inv_st;
             double u, v;
             const double V1x = vn.x, V1y = vn.y;
@@ -106,17 +115,18 @@ __device__ __forceinline__ void step64_block(const StepParams &P, const State64 
             const double A4x = (u - V4x) * is, A4y = (v - V4y) * is;
             ddx = dt6 * (V1x + 2.0 * V2x + 2.0 * V3x + V4x);
             ddy = dt6 * (V1y + 2.0 * V2y + 2.0 * V3y + V4y);
-            S.vel[p] = make_double2(vn.x + dt6 * (A1x + 2.0 * A2x + 2.0 * A3x + A4x),
+            D.vel[p] = make_double2(vn.x + dt6 * (A1x + 2.0 * A2x + 2.0 * A3x + A4x),
                                     vn.y + dt6 * (A1y + 2.0 * A2y + 2.0 * A3y + A4y));
         } else {
             rk4_tracer64<CUBIC>(rec0, lds, T, P, sp.scheme, x, ddx, ddy);
         }
         // wrapped coordinates for evaluation/output, unwrapped displacement
         // for statistics
-        S.pos[p] = make_double2(wrap_pos(x.x + ddx, P.L), wrap_pos(x.y + ddy, P.L));
+        D.pos[p] = make_double2(wrap_pos(x.x + ddx, P.L), wrap_pos(x.y + ddy, P.L));
         d.x += ddx;
         d.y += ddy;
-        S.disp[p] = d;
+        D.disp[p] = d;
+        if (GATHER) D.id[p] = S.id[q];
         r2x = d.x * d.x;
         r2y = d.y * d.y;
     }
@@ -137,14 +147,33 @@ __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64
                                                            DevClock *clock)
 {
     if (!P.persistent) {
-        step64_block<CUBIC, INERTIAL, STATS>(P, S, rec, partials, clock,
-                                             xcd_logical_block(blockIdx.x, gridDim.x));
+        step64_block<CUBIC, INERTIAL, STATS, false>(P, S, S, nullptr, rec, partials, clock,
+                                                    xcd_logical_block(blockIdx.x, gridDim.x));
         return;
     }
     int first, stride, end;
     persistent_range(P.total_blocks, first, stride, end);
     for (int lb = first; lb < end; lb += stride)
-        step64_block<CUBIC, INERTIAL, STATS>(P, S, rec, partials, clock, lb);
+        step64_block<CUBIC, INERTIAL, STATS, false>(P, S, S, nullptr, rec, partials, clock, lb);
+}
+
+// The FP64 step that follows a re-sort: reads S through perm, writes D.
+template <bool CUBIC, bool INERTIAL, bool STATS>
+__global__ __launch_bounds__(kMaxBlock) void step64_perm_kernel(StepParams P, State64 S,
+                                                                State64 D, const uint32_t *perm,
+                                                                const Rec64 *__restrict__ rec,
+                                                                double *__restrict__ partials,
+                                                                DevClock *clock)
+{
+    if (!P.persistent) {
+        step64_block<CUBIC, INERTIAL, STATS, true>(P, S, D, perm, rec, partials, clock,
+                                                   xcd_logical_block(blockIdx.x, gridDim.x));
+        return;
+    }
+    int first, stride, end;
+    persistent_range(P.total_blocks, first, stride, end);
+    for (int lb = first; lb < end; lb += stride)
+        step64_block<CUBIC, INERTIAL, STATS, true>(P, S, D, perm, rec, partials, clock, lb);
 }
 
 // ===========================================================================
@@ -704,15 +733,21 @@ static int launch_grid(K kernel, const StepParams &P, int block, size_t lds, int
 }
 
 template <bool C, bool I, bool S>
-static hipError_t launch64_t(const StepParams &P, const State64 &St, const Rec64 *rec,
-                             double *partials, DevClock *clock, int block, int grid,
-                             hipStream_t st)
+static hipError_t launch64_t(const StepParams &P, const State64 &St, const State64 &Dst,
+                             const uint32_t *perm, const Rec64 *rec, double *partials,
+                             DevClock *clock, int block, int grid, hipStream_t st)
 {
     const size_t lds = P.tile_cap > 0 ? (size_t)P.tile_cap * sizeof(Rec64) : 0;
     StepParams Q;
-    const int g = launch_grid(step64_kernel<C, I, S>, P, block, lds, grid, Q);
-    hipLaunchKernelGGL((step64_kernel<C, I, S>), dim3(g), dim3(block), lds, st, Q, St, rec,
-                       partials, clock);
+    if (perm) {
+        const int g = launch_grid(step64_perm_kernel<C, I, S>, P, block, lds, grid, Q);
+        hipLaunchKernelGGL((step64_perm_kernel<C, I, S>), dim3(g), dim3(block), lds, st, Q, St,
+                           Dst, perm, rec, partials, clock);
+    } else {
+        const int g = launch_grid(step64_kernel<C, I, S>, P, block, lds, grid, Q);
+        hipLaunchKernelGGL((step64_kernel<C, I, S>), dim3(g), dim3(block), lds, st, Q, St, rec,
+                           partials, clock);
+    }
     return hipGetLastError();
 }
 
@@ -766,11 +801,12 @@ static hipError_t launch32_s(const StepParams &P, const State32 &S, const State3
         }                                                                            \
     } while (0)
 
-hipError_t launch_step64(const StepParams &P, const State64 &S, const Rec64 *rec,
-                         double *partials, DevClock *clock, bool stats, bool cubic,
-                         bool inertial, int block, int grid, hipStream_t st)
+hipError_t launch_step64(const StepParams &P, const State64 &S, const State64 &D,
+                         const uint32_t *perm, const Rec64 *rec, double *partials,
+                         DevClock *clock, bool stats, bool cubic, bool inertial, int block,
+                         int grid, hipStream_t st)
 {
-    LPT_DISPATCH(launch64_t, P, S, rec, partials, clock, block, grid, st);
+    LPT_DISPATCH(launch64_t, P, S, D, perm, rec, partials, clock, block, grid, st);
 }
 
 hipError_t launch_step32(const StepParams &P, const State32 &S, const State32 &D,
