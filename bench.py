@@ -177,9 +177,12 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False):
     kern_ms = timing["step_kernel_ms"] / max(1, timing["step_launches"])
     bytes_per_launch = alg_bytes_per_step(w)
     achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
-    log(f"[bench] {args.steps} steps in {elapsed:.3f} s; step kernel {kern_ms * 1e3:.1f} us avg "
-        f"over {timing['step_launches']} launches; sort {timing['sort_ms']:.2f} ms over "
-        f"{timing['sorts']} sorts; {nstats} stats records")
+    perm_us = 1e3 * timing["perm_step_ms"] / max(1, timing["perm_steps"])
+    sort_us = 1e3 * timing["sort_ms"] / max(1, timing["sorts"])
+    log(f"[bench] {args.steps} steps in {elapsed:.3f} s; in-place step kernel {kern_ms * 1e3:.1f} us "
+        f"avg over {timing['step_launches']} launches; permuting step {perm_us:.1f} us avg over "
+        f"{timing['perm_steps']}; sort (keys + radix) {sort_us:.1f} us avg over "
+        f"{timing['sorts']}; {nstats} stats records")
     extra = {}
     if fp64_twin and not args.no_fp64:
         w64 = dataclasses.replace(w, name=w.name.replace("fp32split", "fp64"), precision="fp64")
@@ -204,6 +207,14 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False):
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
             "kernel": step_kernel_name(w), "kernel_avg_us": kern_ms * 1e3,
+            "kernel_launches": timing["step_launches"],
+            "note": "kernel = the in-place step; the step right after each re-sort is a "
+                    "separate kernel that also applies the sort's permutation "
+                    "(perm_step_avg_us); keys + radix sort per re-sort in sort_avg_us; "
+                    "value and ms_per_step include both",
+            "perm_step_avg_us": perm_us if timing["perm_steps"] else None,
+            "perm_steps": timing["perm_steps"],
+            "sort_avg_us": sort_us if timing["sorts"] else None,
             "alg_bytes_per_particle_step": bytes_per_launch / npart,
             "alg_bytes_per_launch": bytes_per_launch}
     return value, 1e3 * elapsed / args.steps, cfg, roof, extra

@@ -202,12 +202,17 @@ lpt_status lpt_get_order(lpt_ctx *ctx, int32_t species_id, int32_t *ids, int32_t
 
 /* Device time spent in the step kernel and in re-sorting since the last
  * reset, measured with HIP events on the context stream (needs
- * LPT_FLAG_TIME_KERNELS; synchronises the stream). */
+ * LPT_FLAG_TIME_KERNELS; synchronises the stream).  A step that follows a
+ * re-sort also applies the sort's permutation to the state (a kernel of its
+ * own); it is counted under perm_step_ms, not step_kernel_ms. */
 typedef struct {
-    double step_kernel_ms;    /* sum over step-kernel launches               */
+    double step_kernel_ms;    /* sum over in-place step-kernel launches      */
     int64_t step_launches;
-    double sort_ms;           /* sum over re-sorts (keys, radix, permute)     */
+    double sort_ms;           /* sum over re-sorts (keys, radix sort; and the
+                                 permutation where lpt_sort applies it)      */
     int64_t sorts;
+    double perm_step_ms;      /* sum over steps that apply a permutation     */
+    int64_t perm_steps;
 } lpt_timing;
 lpt_status lpt_get_timing(lpt_ctx *ctx, lpt_timing *out, int32_t reset);
 

@@ -118,7 +118,7 @@ struct lpt_ctx {
     bool time_kernels = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_step, ev_sort;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_step, ev_sort, ev_perm;
 };
 
 namespace {
@@ -861,7 +861,7 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
         }
         if (c->time_kernels) {
             HIP_TRY(c, mark(c, e1));
-            c->ev_step.emplace_back(e0, e1);
+            (perm ? c->ev_perm : c->ev_step).emplace_back(e0, e1);
         }
         if (rec) {
             HIP_TRY(c, launch_finalize(P, c->partials, c->clock, c->records, c->rec_cap,
@@ -1307,10 +1307,17 @@ lpt_status lpt_get_timing(lpt_ctx *c, lpt_timing *out, int32_t reset)
         t.sort_ms += ms;
         t.sorts += 1;
     }
+    for (const auto &p : c->ev_perm) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, p.first, p.second));
+        t.perm_step_ms += ms;
+        t.perm_steps += 1;
+    }
     *out = t;
     if (reset) {
         c->ev_step.clear();
         c->ev_sort.clear();
+        c->ev_perm.clear();
         c->ev_used = 0;
     }
     return LPT_OK;

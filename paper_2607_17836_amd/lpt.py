@@ -50,7 +50,8 @@ class LptTuning(C.Structure):
 
 class LptTiming(C.Structure):
     _fields_ = [("step_kernel_ms", C.c_double), ("step_launches", C.c_int64),
-                ("sort_ms", C.c_double), ("sorts", C.c_int64)]
+                ("sort_ms", C.c_double), ("sorts", C.c_int64),
+                ("perm_step_ms", C.c_double), ("perm_steps", C.c_int64)]
 
 
 STAT_DTYPE = np.dtype([("t", "<f8"), ("msd_x", "<f8"), ("msd_y", "<f8"), ("msd", "<f8"),
@@ -264,7 +265,8 @@ class Tracker:
         t = LptTiming()
         self._check(load().lpt_get_timing(self._h, C.byref(t), int(reset)))
         return dict(step_kernel_ms=t.step_kernel_ms, step_launches=t.step_launches,
-                    sort_ms=t.sort_ms, sorts=t.sorts)
+                    sort_ms=t.sort_ms, sorts=t.sorts, perm_step_ms=t.perm_step_ms,
+                    perm_steps=t.perm_steps)
 
     def get_time(self):
         s, t = C.c_int64(), C.c_double()
