@@ -81,7 +81,7 @@ __device__ __forceinline__ int species_of(const StepParams &P, int lb)
 {
     int s = 0;
     for (int k = 1; k < P.nspecies; ++k)
-        if (lb >= P.sp[k].block_begin) s = k;
+        if (lb >= P.sp[k].block_begin && lb < P.sp[k].block_end) s = k;
     return s;
 }
 

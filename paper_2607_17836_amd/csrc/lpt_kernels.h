@@ -62,6 +62,10 @@ struct StepParams {
     float halo_scale;      // tile halo = halo_scale x the largest-speed displacement
     const float *umax;     // device: largest node speed of slot 0 / 1, cells per unit time
     SpeciesDev sp[kMaxSpecies];
+    // the logical blocks [block_base, block_base + launch_blocks) of one FP32
+    // launch (one launch per species)
+    int32_t block_base;
+    int32_t launch_blocks;
 };
 
 // Device-resident clock so that captured step chunks can be replayed.
@@ -114,7 +118,8 @@ hipError_t launch_step64(const StepParams &P, const State64 &S, const State64 &D
                          const uint32_t *perm, const Rec64 *rec, double *partials,
                          DevClock *clock, bool stats, bool cubic, bool inertial, int block,
                          int grid, hipStream_t st);
-// schemes: the scheme shared by every species, or 3 if they differ.  S, D
+// One launch over the logical blocks [P.block_base, P.block_base +
+// P.launch_blocks) (= grid) of one species, whose scheme is `schemes`.  S, D
 // and perm as for launch_step64.
 hipError_t launch_step32(const StepParams &P, const State32 &S, const State32 &D,
                          const uint32_t *perm, const float4 *rec, double *partials,

@@ -215,6 +215,8 @@ StepParams make_params(const lpt_ctx *c)
         d.block_end = blk;
     }
     P.total_blocks = blk;
+    P.block_base = 0;
+    P.launch_blocks = blk;
     return P;
 }
 
@@ -246,14 +248,6 @@ int32_t slot_mode(double wa, double wb)
 }
 
 // The scheme every species uses, or 3 if they differ.
-int common_scheme(const lpt_ctx *c)
-{
-    int s = c->sp.empty() ? 0 : c->sp[0].scheme;
-    for (const SpeciesHost &h : c->sp)
-        if (h.scheme != s) return 3;
-    return s;
-}
-
 int species_bits(const lpt_ctx *c) { return c->sp.size() > 1 ? ilog2i((int64_t)c->sp.size()) : 0; }
 int tile_bits(const lpt_ctx *c) { return 2 * ilog2i(c->n / c->sort_tile); }
 
@@ -853,10 +847,21 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
                                      P.total_blocks, c->stream));
             if (perm) c->cur = 1 - c->cur;
         } else {
-            HIP_TRY(c, launch_step32(P, c->s32[c->cur], c->s32[perm ? 1 - c->cur : c->cur], perm,
-                                     static_cast<const float4 *>(c->rec), c->partials, c->clock,
-                                     rec, common_scheme(c), c->has_inertial, c->block,
-                                     P.total_blocks, c->stream));
+            // one launch per species: each launch runs one (scheme, kind)
+            // body, and spreads that species over all XCDs (a single launch
+            // hands each XCD one contiguous range of all blocks, so species
+            // of different cost per block would leave the XCDs unbalanced)
+            for (int s = 0; s < P.nspecies; ++s) {
+                const SpeciesDev &d = P.sp[s];
+                if (d.block_end <= d.block_begin) continue;
+                StepParams Q = P;
+                Q.block_base = d.block_begin;
+                Q.launch_blocks = d.block_end - d.block_begin;
+                HIP_TRY(c, launch_step32(Q, c->s32[c->cur], c->s32[perm ? 1 - c->cur : c->cur],
+                                         perm, static_cast<const float4 *>(c->rec), c->partials,
+                                         c->clock, rec, d.scheme, d.inertial != 0, c->block,
+                                         Q.launch_blocks, c->stream));
+            }
             if (perm) c->cur = 1 - c->cur;
         }
         if (c->time_kernels) {

@@ -562,19 +562,9 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
     r2y = d.y * d.y;
 }
 
-// SCHS: kBilinear / kCatmullRom / kBSpline when every species of the launch
-// uses that scheme, kAnyScheme otherwise.  KINDS: 0 tracers only (St == 0
+// The particle body for the block's kind.  SCHS: the scheme of every species
+// of the launch (one launch per scheme).  KINDS: 0 tracers only (St == 0
 // included), 1 tracers and/or inertial species.
-constexpr int kAnyScheme = 3;
-
-template <int SCH, int SCHS>
-constexpr bool scheme_compiled()
-{
-    return SCHS == kAnyScheme || SCHS == SCH;
-}
-
-// The particle body for the block's (scheme, kind), compiled for the schemes
-// and kinds the launch may meet.
 template <int SCHS, int KINDS, bool ONE>
 __device__ __forceinline__ void particle_dispatch(const StepParams &P, const State32 &S,
                                                   const State32 &D,
@@ -584,24 +574,10 @@ __device__ __forceinline__ void particle_dispatch(const StepParams &P, const Sta
                                                   uint32_t &cell, float2 o, double &r2x,
                                                   double &r2y)
 {
-    const bool inert = KINDS != 0 && sp.inertial;
-    if (scheme_compiled<kBilinear, SCHS>() && (SCHS != kAnyScheme || sp.scheme == kBilinear)) {
-        if (KINDS != 0 && inert)
-            particle32<kBilinear, KINDS != 0, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
-        else
-            particle32<kBilinear, false, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
-    } else if (scheme_compiled<kCatmullRom, SCHS>() &&
-               (SCHS != kAnyScheme || sp.scheme == kCatmullRom)) {
-        if (KINDS != 0 && inert)
-            particle32<kCatmullRom, KINDS != 0, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
-        else
-            particle32<kCatmullRom, false, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
-    } else if (scheme_compiled<kBSpline, SCHS>()) {
-        if (KINDS != 0 && inert)
-            particle32<kBSpline, KINDS != 0, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
-        else
-            particle32<kBSpline, false, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
-    }
+    if (KINDS != 0 && sp.inertial)
+        particle32<SCHS, KINDS != 0, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
+    else
+        particle32<SCHS, false, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
 }
 
 // One logical block of the step.  The state of slot p is read from S and
@@ -672,39 +648,43 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
 // that; the bicubic bodies need more registers and keep the default bound.
 template <int SCHS, int KINDS, bool STATS>
 __global__ __launch_bounds__(kMaxBlock)
-__attribute__((amdgpu_waves_per_eu(SCHS == kBilinear ? 8 : 1)))
+__attribute__((amdgpu_waves_per_eu(SCHS == kBilinear ? 8 : 6)))
 void step32_kernel(StepParams P, State32 S, const float4 *__restrict__ rec,
                    double *__restrict__ partials, DevClock *clock)
 {
     if (!P.persistent) {
-        step32_block<SCHS, KINDS, STATS, false>(P, S, S, nullptr, rec, partials, clock,
-                                                xcd_logical_block(blockIdx.x, gridDim.x));
+        step32_block<SCHS, KINDS, STATS, false>(
+            P, S, S, nullptr, rec, partials, clock,
+            P.block_base + xcd_logical_block(blockIdx.x, gridDim.x));
         return;
     }
     int first, stride, end;
-    persistent_range(P.total_blocks, first, stride, end);
+    persistent_range(P.launch_blocks, first, stride, end);
     for (int lb = first; lb < end; lb += stride)
-        step32_block<SCHS, KINDS, STATS, false>(P, S, S, nullptr, rec, partials, clock, lb);
+        step32_block<SCHS, KINDS, STATS, false>(P, S, S, nullptr, rec, partials, clock,
+                                                P.block_base + lb);
 }
 
 // The step that follows a re-sort: reads S through perm, writes D.  (A kernel
 // of its own, so that the in-place kernel above keeps its argument list.)
 template <int SCHS, int KINDS, bool STATS>
 __global__ __launch_bounds__(kMaxBlock)
-__attribute__((amdgpu_waves_per_eu(SCHS == kBilinear ? 8 : 1)))
+__attribute__((amdgpu_waves_per_eu(SCHS == kBilinear ? 8 : 6)))
 void step32_perm_kernel(StepParams P, State32 S, State32 D, const uint32_t *perm,
                         const float4 *__restrict__ rec, double *__restrict__ partials,
                         DevClock *clock)
 {
     if (!P.persistent) {
-        step32_block<SCHS, KINDS, STATS, true>(P, S, D, perm, rec, partials, clock,
-                                               xcd_logical_block(blockIdx.x, gridDim.x));
+        step32_block<SCHS, KINDS, STATS, true>(
+            P, S, D, perm, rec, partials, clock,
+            P.block_base + xcd_logical_block(blockIdx.x, gridDim.x));
         return;
     }
     int first, stride, end;
-    persistent_range(P.total_blocks, first, stride, end);
+    persistent_range(P.launch_blocks, first, stride, end);
     for (int lb = first; lb < end; lb += stride)
-        step32_block<SCHS, KINDS, STATS, true>(P, S, D, perm, rec, partials, clock, lb);
+        step32_block<SCHS, KINDS, STATS, true>(P, S, D, perm, rec, partials, clock,
+                                               P.block_base + lb);
 }
 
 // Grid of a launch: one workgroup per logical block, or -- when the step
@@ -825,8 +805,7 @@ hipError_t launch_step32(const StepParams &P, const State32 &S, const State32 &D
         return launch32_s<kBSpline>(P, S, D, perm, rec, partials, clock, stats, inertial, block,
                                     grid, st);
     default:
-        return launch32_s<kAnyScheme>(P, S, D, perm, rec, partials, clock, stats, inertial,
-                                      block, grid, st);
+        return hipErrorInvalidValue;
     }
 }
 // ===========================================================================
