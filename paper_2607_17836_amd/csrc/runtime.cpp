@@ -850,7 +850,10 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
             // one launch per species: each launch runs one (scheme, kind)
             // body, and spreads that species over all XCDs (a single launch
             // hands each XCD one contiguous range of all blocks, so species
-            // of different cost per block would leave the XCDs unbalanced)
+            // of different cost per block would leave the XCDs unbalanced).
+            // The FP64 step keeps one launch: it is not used for large
+            // heterogeneous batches, and for a few similar species the extra
+            // launches cost more than they balance.
             for (int s = 0; s < P.nspecies; ++s) {
                 const SpeciesDev &d = P.sp[s];
                 if (d.block_end <= d.block_begin) continue;
