@@ -158,11 +158,14 @@ def cpu_baseline(w, budget_s=15.0):
 
 
 def step_kernel_name(w):
-    schemes = {s[2] for s in w.species}
+    schemes = sorted({s[2] for s in w.species})
     inertial = any(k == "inertial" and st > 0 for k, st, _, _, _ in w.species)
-    sch = schemes.pop() if len(schemes) == 1 else "mixed schemes"
     kind = "tracers + inertial" if inertial else "tracers"
-    return f"step{'32' if w.precision == 'fp32_split' else '64'}_kernel<{sch}, {kind}>"
+    name = f"step{'32' if w.precision == 'fp32_split' else '64'}_kernel"
+    if len(w.species) > 1 and w.precision == "fp32_split":
+        return (f"{name}, one launch per species ({len(w.species)} per step; "
+                f"{' / '.join(schemes)}, {kind}); times are per step")
+    return f"{name}<{' / '.join(schemes)}, {kind}>"
 
 
 def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False):

@@ -117,8 +117,8 @@ def test_block_size_change_mid_run_keeps_results():
 
 def test_batched_species_match_one_context_per_species():
     """The batching workload's species mix (8 Stokes numbers, uneven counts,
-    scheme k mod 3; reduced counts and grid) in one launch per step gives
-    every particle exactly the state it gets when its species runs alone."""
+    scheme k mod 3; reduced counts and grid) in one context gives every
+    particle exactly the state it gets when its species runs alone."""
     n, dt = 256, 1e-3
     (ua, va), (ub, vb) = synth.spectrum_snapshots(n, 10, 4, dt)
     mix = [(("inertial" if st > 0 else "tracer"), st, SCHEMES[k % 3], 1000 + 613 * k, 40 + k)
