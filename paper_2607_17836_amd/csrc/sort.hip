@@ -7,7 +7,9 @@
 // 64 keys (lanes with an equal digit form a match mask); per-wave running
 // counts live in LDS and are turned into scatter bases by one scan over the
 // waves.  Equal digits therefore keep input order: tile order, then wave,
-// then iteration, then lane -- which is the input order.
+// then iteration, then lane -- which is the input order.  (The match masks
+// come from peeling the wave's distinct digits one ballot at a time when
+// there are at most 8 of them, as for the nearly sorted keys of a re-sort.)
 //
 // The key kernel also builds the first pass's histogram, and the first
 // scatter takes the input index as the value, so the sort reads no value
@@ -331,12 +333,26 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
         key[it] = valid ? keys_in[i] : 0u;
         val[it] = !valid ? 0u : vals_in ? vals_in[i] : (uint32_t)i;
         const uint32_t d = (key[it] >> shift) & mask;
-        uint64_t m = __ballot(valid);
+        // m = the valid lanes whose digit equals this lane's.  Nearly sorted
+        // keys give a wave few distinct digits: peel them one at a time
+        // (one ballot each); past 8, match all 8 digit bits instead.
+        const uint64_t act = __ballot(valid);
+        uint64_t m = 0, left = act;
+        for (int peel = 0; left != 0 && peel < 8; ++peel) {
+            const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane(
+                (int)d, (int)__builtin_ctzll((unsigned long long)left));
+            const uint64_t eq = __ballot(d == dl) & act;
+            if (d == dl) m = eq;
+            left &= ~eq;
+        }
+        if (left != 0) {
+            m = act;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bal = __ballot(bit);
-            m &= bit ? bal : ~bal;
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bal = __ballot(bit);
+                m &= bit ? bal : ~bal;
+            }
         }
         const uint32_t before = wcount[w][d];
         rank[it] = before + (uint32_t)__popcll(m & lt);
