@@ -231,20 +231,11 @@ constexpr int fill_rows()
     return sizeof(Rec) <= 16 ? 4 : 2;
 }
 
-// LDS layout of a tile entry: FP64 records are kept whole; FP32 records are
-// split into two planes of (u, v), one per time level (entry k of level h at
-// float2 index h * area + k).
+// LDS layout of a tile entry: the node record itself, entry k = ty * w + tx.
 __device__ __forceinline__ void tile_store(Rec64 *lds, int k, int area, const Rec64 &r)
 {
     (void)area;
     lds[k] = r;
-}
-
-__device__ __forceinline__ void tile_store(float4 *lds, int k, int area, const float4 &r)
-{
-    float2 *q = reinterpret_cast<float2 *>(lds);
-    q[k] = make_float2(r.x, r.y);
-    q[area + k] = make_float2(r.z, r.w);
 }
 
 // Copy the tile's node records into LDS (all threads of the block).  The
@@ -341,6 +332,45 @@ __device__ __forceinline__ Tile block_box(bool active, int cx, int cy, int ax, i
 // Cooperative tile set-up of one block (all threads must call it): the box
 // of block_box, staged in LDS if it fits the capacity and is not much larger
 // than the block's particle count.
+// FP32 tile fill by LDS DMA: the tile's flat index space is cut into chunks
+// of 64 entries; a wave takes every nw-th chunk, and lane l of chunk c loads
+// the 16-byte record of entry 64 c + l straight into LDS (the wave's LDS
+// destination is the chunk's first entry; lane l lands 16 l bytes after it),
+// so the records never pass through registers.  Lanes past the tile's area
+// are switched off.  Ends with every wave's loads complete.
+__device__ __forceinline__ void fill_tile_dma(float4 *lds, const float4 *__restrict__ rec0,
+                                              const StepParams &P, const Tile &T)
+{
+    if (!T.on) return;
+    const int n = P.n, w = T.w, area = T.w * T.h;
+    const float inv_w = 1.0f / (float)w;
+    const int lane = (int)threadIdx.x & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
+    const int nw = (int)blockDim.x / kWave;
+    const int chunks = (area + kWave - 1) / kWave;
+    for (int c = wv; c < chunks; c += nw) {
+        const int k = c * kWave + lane;
+        if (k < area) {
+            int ty = (int)((float)k * inv_w);
+            int tx = k - ty * w;
+            if (tx < 0) {
+                ty -= 1;
+                tx += w;
+            } else if (tx >= w) {
+                ty += 1;
+                tx -= w;
+            }
+            int gx = T.x0 + tx, gy = T.y0 + ty;
+            gx -= gx >= n ? n : 0;
+            gy -= gy >= n ? n : 0;
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(rec0 + (__mul24(gy, P.pitch) + gx)),
+                (void __attribute__((address_space(3))) *)(lds + c * kWave), 16, 0, 0);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
 template <typename Rec>
 __device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec0,
                                           const StepParams &P, bool active, int cx, int cy,
@@ -351,7 +381,10 @@ __device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec
     const int area = T.w * T.h;
     T.on = P.tile_cap > 0 && area <= P.tile_cap && T.w < n && T.h < n &&
            area <= kTileWaste * nactive;
-    fill_tile<Rec>(lds, rec0, P, T);
+    if constexpr (sizeof(Rec) == 16)
+        fill_tile_dma(lds, rec0, P, T);
+    else
+        fill_tile<Rec>(lds, rec0, P, T);
     __syncthreads();
     return T;
 }

@@ -336,18 +336,13 @@ struct GlobalNodes {
 };
 
 struct TileNodes {
-    const float2 *p;   // origin node in plane 0
+    const float4 *p;   // origin node
     int pitch;         // tile width
-    int plane;         // entries per plane (tile area)
     __device__ __forceinline__ float2 level(int a, int b, int h) const
     {
-        return p[h * plane + b * pitch + a];
+        return reinterpret_cast<const float2 *>(p + (b * pitch + a))[h];
     }
-    __device__ __forceinline__ float4 both(int a, int b) const
-    {
-        const float2 x = p[b * pitch + a], y = p[plane + b * pitch + a];
-        return make_float4(x.x, x.y, y.x, y.y);
-    }
+    __device__ __forceinline__ float4 both(int a, int b) const { return p[b * pitch + a]; }
 };
 
 // Velocity of one stencil (eqs. bilinear_interp, cr_interp, bspline_interp)
@@ -426,8 +421,7 @@ __device__ __forceinline__ void eval32(const Nodes &N, float xi, float eta, bool
 
 __device__ __forceinline__ TileNodes tile_nodes(const float4 *lds, const Tile &T, int tx, int ty)
 {
-    return TileNodes{reinterpret_cast<const float2 *>(lds) + (__mul24(ty, T.w) + tx), T.w,
-                     T.w * T.h};
+    return TileNodes{lds + (__mul24(ty, T.w) + tx), T.w};
 }
 
 __device__ __forceinline__ GlobalNodes global_nodes(const float4 *rec0, const StepParams &P,
@@ -736,7 +730,9 @@ static hipError_t launch32_t(const StepParams &P, const State32 &S, const State3
                              const uint32_t *perm, const float4 *rec, double *partials,
                              DevClock *clock, int block, int grid, hipStream_t st)
 {
-    const size_t lds = P.tile_cap > 0 ? (size_t)P.tile_cap * sizeof(float4) : 0;
+    // whole 64-entry chunks: the tile fill writes LDS a wave's chunk at a time
+    const size_t lds =
+        P.tile_cap > 0 ? (size_t)((P.tile_cap + kWave - 1) / kWave * kWave) * sizeof(float4) : 0;
     StepParams Q;
     if (perm) {
         const int g = launch_grid(step32_perm_kernel<SCHS, KINDS, ST>, P, block, lds, grid, Q);
