@@ -182,7 +182,7 @@ struct SortWork {
     uint32_t *keys[2];
     uint32_t *vals[2];
     uint32_t *hist;        // 256 * max_tiles counters
-    uint32_t *scan_tmp;    // block sums of the histogram scan
+    uint32_t *scan_tmp;    // per-digit totals of a radix pass (256)
     int64_t capacity;      // keys
 };
 int64_t sort_hist_entries(int64_t n);

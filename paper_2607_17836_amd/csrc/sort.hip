@@ -1,8 +1,10 @@
 // Cell-order re-sorting of the particle state: key generation, a stable LSD
 // radix sort with 8-bit digits, and the structure-of-arrays permutation.
 //
-// Radix pass = histogram (per 4096-key tile) -> exclusive scan of the
-// digit-major histogram table -> stable scatter.  Inside a tile, each wave
+// Radix pass = histogram (per 4096-key tile) -> one kernel scanning each
+// digit's row of tile counts -> stable scatter, which adds the start of each
+// digit's output run (the sum of the smaller digits' totals, scanned by every
+// scatter block from the 256 totals).  Inside a tile, each wave
 // owns a contiguous run of 1024 keys and ranks them with 8 ballots per
 // 64 keys (lanes with an equal digit form a match mask); per-wave running
 // counts live in LDS and are turned into scatter bases by one scan over the
@@ -28,14 +30,12 @@ constexpr int kTile = kSortThreads * kItems;           // 4096 keys
 constexpr int kWaveRun = kTile / kSortWaves;           // 1024 keys per wave
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
-constexpr int kScanChunk = kScanThreads * kScanItems;  // 2048 counters
-constexpr int kTopThreads = 1024;
-constexpr int kTopItems = 8;
 
 int64_t sort_hist_entries(int64_t n) { return 256 * ((n + kTile - 1) / kTile); }
 int64_t sort_scan_blocks(int64_t n)
 {
-    return (sort_hist_entries(n) + kScanChunk - 1) / kScanChunk;
+    (void)n;
+    return 256;   // per-digit totals
 }
 
 // ---------------------------------------------------------------------------
@@ -252,72 +252,47 @@ __device__ __forceinline__ uint32_t block_scan_incl(uint32_t x, uint32_t *wsum, 
     return x + before;
 }
 
-// Sum of each scan chunk.
-__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t *__restrict__ a,
-                                                                   int64_t m, uint32_t *sums)
+// Exclusive scan of digit d's row of the histogram table (its count in every
+// tile, in tile order), in place, in chunks of 2048 with a running carry;
+// totals[d] receives the row's sum.  One block per digit.
+__global__ __launch_bounds__(kScanThreads) void row_scan_kernel(uint32_t *hist, int ntiles,
+                                                                uint32_t *totals)
 {
     __shared__ uint32_t wsum[kScanThreads / 64];
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-    uint32_t s = 0;
+    uint32_t *row = hist + (int64_t)blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (int base = 0; base < ntiles; base += kScanThreads * kScanItems) {
+        const int i0 = base + (int)threadIdx.x * kScanItems;
+        uint32_t v[kScanItems];
+        uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < m) s += a[base + k];
-    uint32_t total;
-    block_scan_incl(s, wsum, total);
-    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = i0 + k < ntiles ? row[i0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t total;
+        const uint32_t incl = block_scan_incl(sum, wsum, total);
+        uint32_t run = carry + incl - sum;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (i0 + k < ntiles) row[i0 + k] = run;
+            run += v[k];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
-// Exclusive scan of the chunk sums in one block.
-__global__ __launch_bounds__(kTopThreads) void scan_top_kernel(uint32_t *sums, int64_t nb)
-{
-    __shared__ uint32_t wsum[kTopThreads / 64];
-    const int64_t base = (int64_t)threadIdx.x * kTopItems;
-    uint32_t v[kTopItems];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kTopItems; ++k) {
-        v[k] = base + k < nb ? sums[base + k] : 0u;
-        s += v[k];
-    }
-    uint32_t total;
-    const uint32_t incl = block_scan_incl(s, wsum, total);
-    uint32_t run = incl - s;
-#pragma unroll
-    for (int k = 0; k < kTopItems; ++k) {
-        if (base + k < nb) sums[base + k] = run;
-        run += v[k];
-    }
-}
-
-// Exclusive scan of each chunk, offset by its chunk base.
-__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(uint32_t *a, int64_t m,
-                                                                 const uint32_t *__restrict__ sums)
-{
-    __shared__ uint32_t wsum[kScanThreads / 64];
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < m ? a[base + k] : 0u;
-        s += v[k];
-    }
-    uint32_t total;
-    const uint32_t incl = block_scan_incl(s, wsum, total);
-    uint32_t run = sums[blockIdx.x] + incl - s;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < m) a[base + k] = run;
-        run += v[k];
-    }
-}
-
+// offsets: the row-scanned histogram table; totals: each digit's count (the
+// start of digit d's output run is the sum of the totals of smaller digits).
 __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, int64_t n, int shift,
-    uint32_t mask, const uint32_t *__restrict__ offsets, int ntiles)
+    uint32_t mask, const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ totals,
+    int ntiles)
 {
     __shared__ uint32_t wcount[kSortWaves][256];
+    __shared__ uint32_t wsum[kSortWaves];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 #pragma unroll
     for (int k = 0; k < kSortWaves; ++k) wcount[k][tid] = 0;
@@ -359,9 +334,12 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
         if (valid && lane == __ffsll((unsigned long long)m) - 1)
             wcount[w][d] = before + (uint32_t)__popcll(m);
     }
-    __syncthreads();
+    // block_scan_incl synchronises the block, which also publishes wcount
+    const uint32_t tot = (uint32_t)tid <= mask ? totals[tid] : 0u;
+    uint32_t all;
+    const uint32_t dstart = block_scan_incl(tot, wsum, all) - tot;
     {
-        uint32_t runv = offsets[(int64_t)tid * ntiles + blockIdx.x];
+        uint32_t runv = dstart + offsets[(int64_t)tid * ntiles + blockIdx.x];
 #pragma unroll
         for (int k = 0; k < kSortWaves; ++k) {
             const uint32_t c = wcount[k][tid];
@@ -388,9 +366,6 @@ hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, bool first_hist, int
     *result = 0;
     if (n <= 1) return hipSuccess;
     const int ntiles = (int)((n + kTile - 1) / kTile);
-    const int64_t m = 256LL * ntiles;
-    const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
-    if (nb > (int64_t)kTopThreads * kTopItems) return hipErrorInvalidValue;
     int cur = 0;
     for (int shift = 0; shift < key_bits; shift += 8) {
         const int bits = key_bits - shift < 8 ? key_bits - shift : 8;
@@ -398,15 +373,12 @@ hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, bool first_hist, int
         if (shift > 0 || !first_hist)
             hipLaunchKernelGGL(hist_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, W.keys[cur],
                                n, shift, mask, W.hist, ntiles);
-        hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st,
-                           W.hist, m, W.scan_tmp);
-        hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kTopThreads), 0, st, W.scan_tmp, nb);
-        hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st, W.hist,
-                           m, W.scan_tmp);
+        hipLaunchKernelGGL(row_scan_kernel, dim3(mask + 1), dim3(kScanThreads), 0, st, W.hist,
+                           ntiles, W.scan_tmp);
         // the first pass takes each key's input index as its value
         hipLaunchKernelGGL(scatter_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, W.keys[cur],
                            shift == 0 ? (const uint32_t *)nullptr : W.vals[cur], W.keys[1 - cur],
-                           W.vals[1 - cur], n, shift, mask, W.hist, ntiles);
+                           W.vals[1 - cur], n, shift, mask, W.hist, W.scan_tmp, ntiles);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         cur = 1 - cur;
