@@ -223,66 +223,6 @@ __device__ __forceinline__ uint32_t wave_pmax16(uint32_t x)
     return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-// Rows of the tile one wave loads before it writes any of them to LDS, so
-// that their global-memory latencies overlap.
-template <typename Rec>
-constexpr int fill_rows()
-{
-    return sizeof(Rec) <= 16 ? 4 : 2;
-}
-
-// LDS layout of a tile entry: the node record itself, entry k = ty * w + tx.
-__device__ __forceinline__ void tile_store(Rec64 *lds, int k, int area, const Rec64 &r)
-{
-    (void)area;
-    lds[k] = r;
-}
-
-// Copy the tile's node records into LDS (all threads of the block).  The
-// tile is walked as one flat row-major index space, so every index is lane
-// arithmetic (no per-row scalar work) and all lanes load: entry k = ty * w +
-// tx, with ty from a binary32 reciprocal of w corrected by one step (exact
-// for k < 2^22).  A thread issues the loads of a whole group before any LDS
-// write so that their latencies overlap; the last group's indices are
-// clamped to the last entry, which is then re-read and rewritten with the
-// same value.  T.x0 + tx and T.y0 + ty lie in [0, 2n): one conditional
-// subtraction wraps them.
-template <typename Rec>
-__device__ __forceinline__ void fill_tile(Rec *lds, const Rec *__restrict__ rec0,
-                                          const StepParams &P, const Tile &T)
-{
-    if (!T.on) return;
-    constexpr int R = fill_rows<Rec>();
-    const int n = P.n, w = T.w, area = T.w * T.h, nt = blockDim.x;
-    const float inv_w = 1.0f / (float)w;
-    const int groups = (area + R * nt - 1) / (R * nt);
-    for (int g = 0; g < groups; ++g) {
-        Rec buf[R];
-        int dst[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int k = min((int)threadIdx.x + (g * R + r) * nt, area - 1);
-            int ty = (int)((float)k * inv_w);
-            int tx = k - ty * w;
-            if (tx < 0) {
-                ty -= 1;
-                tx += w;
-            } else if (tx >= w) {
-                ty += 1;
-                tx -= w;
-            }
-            int gx = T.x0 + tx, gy = T.y0 + ty;
-            gx -= gx >= n ? n : 0;
-            gy -= gy >= n ? n : 0;
-            buf[r] = rec0[__mul24(gy, P.pitch) + gx];
-            dst[r] = k;
-        }
-        __builtin_amdgcn_sched_barrier(0);   // the group's loads ahead of its writes
-#pragma unroll
-        for (int r = 0; r < R; ++r) tile_store(lds, dst[r], area, buf[r]);
-    }
-}
-
 // Bounding box of the stored cells of a block's active particles, widened by
 // lo cells before and hi cells after on each axis (all threads must call
 // it; returns with the block synchronised).  (cx, cy): the thread's cell
@@ -332,15 +272,20 @@ __device__ __forceinline__ Tile block_box(bool active, int cx, int cy, int ax, i
 // Cooperative tile set-up of one block (all threads must call it): the box
 // of block_box, staged in LDS if it fits the capacity and is not much larger
 // than the block's particle count.
-// FP32 tile fill by LDS DMA: the tile's flat index space is cut into chunks
-// of 64 entries; a wave takes every nw-th chunk, and lane l of chunk c loads
-// the 16-byte record of entry 64 c + l straight into LDS (the wave's LDS
-// destination is the chunk's first entry; lane l lands 16 l bytes after it),
-// so the records never pass through registers.  Lanes past the tile's area
-// are switched off.  Ends with every wave's loads complete.
-__device__ __forceinline__ void fill_tile_dma(float4 *lds, const float4 *__restrict__ rec0,
+// Tile fill by LDS DMA: the tile's flat index space is cut into chunks of 64
+// entries; a wave takes every nw-th chunk, and lane l of chunk c loads the
+// record of entry 64 c + l straight into LDS in 16-byte pieces (the wave's
+// LDS destination is the chunk's first entry; lane l lands 16 l bytes after
+// it), so the records never pass through registers.  An FP32 record is one
+// piece (one plane of records); an FP64 record is two, level 0 and level 1,
+// into two planes `area` entries apart.  Lanes past the tile's area are
+// switched off.  Ends with every wave's loads complete.
+template <typename Rec>
+__device__ __forceinline__ void fill_tile_dma(Rec *lds_rec, const Rec *__restrict__ rec0,
                                               const StepParams &P, const Tile &T)
 {
+    constexpr int kPieces = (int)sizeof(Rec) / 16;
+    float4 *lds = reinterpret_cast<float4 *>(lds_rec);
     if (!T.on) return;
     const int n = P.n, w = T.w, area = T.w * T.h;
     const float inv_w = 1.0f / (float)w;
@@ -363,9 +308,14 @@ __device__ __forceinline__ void fill_tile_dma(float4 *lds, const float4 *__restr
             int gx = T.x0 + tx, gy = T.y0 + ty;
             gx -= gx >= n ? n : 0;
             gy -= gy >= n ? n : 0;
-            __builtin_amdgcn_global_load_lds(
-                (const void *)(rec0 + (__mul24(gy, P.pitch) + gx)),
-                (void __attribute__((address_space(3))) *)(lds + c * kWave), 16, 0, 0);
+            const float4 *src =
+                reinterpret_cast<const float4 *>(rec0 + (__mul24(gy, P.pitch) + gx));
+#pragma unroll
+            for (int piece = 0; piece < kPieces; ++piece)
+                __builtin_amdgcn_global_load_lds(
+                    (const void *)(src + piece),
+                    (void __attribute__((address_space(3))) *)(lds + piece * area + c * kWave), 16,
+                    0, 0);
         }
     }
     __builtin_amdgcn_s_waitcnt(0);
@@ -381,10 +331,7 @@ __device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec
     const int area = T.w * T.h;
     T.on = P.tile_cap > 0 && area <= P.tile_cap && T.w < n && T.h < n &&
            area <= kTileWaste * nactive;
-    if constexpr (sizeof(Rec) == 16)
-        fill_tile_dma(lds, rec0, P, T);
-    else
-        fill_tile<Rec>(lds, rec0, P, T);
+    fill_tile_dma<Rec>(lds, rec0, P, T);
     __syncthreads();
     return T;
 }
@@ -400,47 +347,79 @@ __device__ __forceinline__ void stencil_reach(int scheme, int &lo, int &hi)
 // ===========================================================================
 // FP64 path (physical units)
 // ===========================================================================
-// Time-blended (u, v) of one node record.
-__device__ __forceinline__ void node64(const Rec64 *r, int smode, double wa, double wb, double &u,
-                                       double &v)
+// Time-blended (u, v) of one node from its two levels (level 0 at q0, level 1
+// at q1; only the ones smode needs are read).
+__device__ __forceinline__ void blend64(const double2 *q0, const double2 *q1, int smode,
+                                        double wa, double wb, double &u, double &v)
 {
-    const double2 *q = reinterpret_cast<const double2 *>(r);
     if (smode == kSlot0) {
-        const double2 a = q[0];
+        const double2 a = *q0;
         u = a.x;
         v = a.y;
     } else if (smode == kSlot1) {
-        const double2 b = q[1];
+        const double2 b = *q1;
         u = b.x;
         v = b.y;
     } else {
-        const double2 a = q[0], b = q[1];
+        const double2 a = *q0, b = *q1;
         u = wa * a.x + wb * b.x;
         v = wa * a.y + wb * b.y;
     }
 }
 
-// eq. bilinear_interp on the records at p (node (i, j)), p + 1, p + pitch,
-// p + pitch + 1.
-__device__ __forceinline__ void bil64(const Rec64 *p, int pitch, double xi, double eta, int smode,
+// Time-blended (u, v) of one node record.
+__device__ __forceinline__ void node64(const Rec64 *r, int smode, double wa, double wb, double &u,
+                                       double &v)
+{
+    const double2 *q = reinterpret_cast<const double2 *>(r);
+    blend64(q, q + 1, smode, wa, wb, u, v);
+}
+
+// Stencil nodes in global memory: whole records, node (a, b) at p + b pitch + a.
+struct RecNodes64 {
+    const Rec64 *p;
+    int pitch;
+    __device__ __forceinline__ void get(int a, int b, int smode, double wa, double wb, double &u,
+                                        double &v) const
+    {
+        node64(p + (b * pitch + a), smode, wa, wb, u, v);
+    }
+};
+
+// Stencil nodes in the LDS tile: two planes of (u, v), level 0 then level 1,
+// `area` entries apart; node (a, b) at entry b pitch + a from p.
+struct TileNodes64 {
+    const double2 *p;
+    int pitch, area;
+    __device__ __forceinline__ void get(int a, int b, int smode, double wa, double wb, double &u,
+                                        double &v) const
+    {
+        const double2 *q = p + (b * pitch + a);
+        blend64(q, q + area, smode, wa, wb, u, v);
+    }
+};
+
+// eq. bilinear_interp on nodes (0, 0), (1, 0), (0, 1), (1, 1) of N.
+template <typename Nodes>
+__device__ __forceinline__ void bil64(const Nodes &N, double xi, double eta, int smode,
                                       double wa, double wb, double &u, double &v)
 {
     double u00, v00, u10, v10, u01, v01, u11, v11;
-    node64(p, smode, wa, wb, u00, v00);
-    node64(p + 1, smode, wa, wb, u10, v10);
-    node64(p + pitch, smode, wa, wb, u01, v01);
-    node64(p + pitch + 1, smode, wa, wb, u11, v11);
+    N.get(0, 0, smode, wa, wb, u00, v00);
+    N.get(1, 0, smode, wa, wb, u10, v10);
+    N.get(0, 1, smode, wa, wb, u01, v01);
+    N.get(1, 1, smode, wa, wb, u11, v11);
     double w00, w10, w01, w11;
     bilinear_weights(xi, eta, w00, w10, w01, w11);
     u = w00 * u00 + w10 * u10 + w01 * u01 + w11 * u11;
     v = w00 * v00 + w10 * v10 + w01 * v01 + w11 * v11;
 }
 
-// eqs. cr_interp / bspline_interp on the 4x4 records whose first is p
-// (node (i - 1, j - 1)).
-__device__ __forceinline__ void cub64(const Rec64 *p, int pitch, const double wx[4],
-                                      const double wy[4], int smode, double wa, double wb,
-                                      double &u, double &v)
+// eqs. cr_interp / bspline_interp on the 4x4 nodes of N (node (0, 0) is grid
+// node (i - 1, j - 1)).
+template <typename Nodes>
+__device__ __forceinline__ void cub64(const Nodes &N, const double wx[4], const double wy[4],
+                                      int smode, double wa, double wb, double &u, double &v)
 {
     double au = 0.0, av = 0.0;
 #pragma unroll
@@ -449,13 +428,12 @@ __device__ __forceinline__ void cub64(const Rec64 *p, int pitch, const double wx
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             double nu, nv;
-            node64(p + a, smode, wa, wb, nu, nv);
+            N.get(a, b, smode, wa, wb, nu, nv);
             ru += wx[a] * nu;
             rv += wx[a] * nv;
         }
         au += wy[b] * ru;
         av += wy[b] * rv;
-        p += pitch;
     }
     u = au;
     v = av;
@@ -463,9 +441,9 @@ __device__ __forceinline__ void cub64(const Rec64 *p, int pitch, const double wx
 
 // Velocity at (x, y) (physical units, any real value) with temporal weights
 // (wa, wb) on the two snapshot slots.  rec0 points at global node (0, 0);
-// tile/T is the block's LDS tile (T.on == 0: global only).
+// tile/T is the block's LDS tile, two planes (T.on == 0: global only).
 template <bool CUBIC>
-__device__ __forceinline__ void vel64(const Rec64 *__restrict__ rec0, const Rec64 *tile,
+__device__ __forceinline__ void vel64(const Rec64 *__restrict__ rec0, const double2 *tile,
                                       const Tile &T, const StepParams &P, int scheme, double x,
                                       double y, double wa, double wb, int smode, double &u,
                                       double &v)
@@ -478,9 +456,10 @@ __device__ __forceinline__ void vel64(const Rec64 *__restrict__ rec0, const Rec6
     int t;
     if (!CUBIC || scheme == kBilinear || edge_cell(P.compat_edge, i, j, n)) {
         if (tile_index(T, i, j, 2, n, mask, t))
-            bil64(tile + t, T.w, xi, eta, smode, wa, wb, u, v);
+            bil64(TileNodes64{tile + t, T.w, T.w * T.h}, xi, eta, smode, wa, wb, u, v);
         else
-            bil64(rec0 + (__mul24(j, P.pitch) + i), P.pitch, xi, eta, smode, wa, wb, u, v);
+            bil64(RecNodes64{rec0 + (__mul24(j, P.pitch) + i), P.pitch}, xi, eta, smode, wa, wb,
+                  u, v);
         return;
     }
     if constexpr (CUBIC) {
@@ -493,9 +472,10 @@ __device__ __forceinline__ void vel64(const Rec64 *__restrict__ rec0, const Rec6
             weights_bs(eta, wy);
         }
         if (tile_index(T, i - 1, j - 1, 4, n, mask, t))
-            cub64(tile + t, T.w, wx, wy, smode, wa, wb, u, v);
+            cub64(TileNodes64{tile + t, T.w, T.w * T.h}, wx, wy, smode, wa, wb, u, v);
         else
-            cub64(rec0 + (__mul24(j - 1, P.pitch) + (i - 1)), P.pitch, wx, wy, smode, wa, wb, u, v);
+            cub64(RecNodes64{rec0 + (__mul24(j - 1, P.pitch) + (i - 1)), P.pitch}, wx, wy, smode,
+                  wa, wb, u, v);
     }
 }
 
@@ -518,7 +498,7 @@ __device__ __forceinline__ double wrap_pos(double z, double L)
 // The step kernel and the adjoint's recomputation share it, so recomputed
 // trajectories repeat the forward ones bit for bit.
 template <bool CUBIC>
-__device__ __forceinline__ void rk4_tracer64(const Rec64 *__restrict__ rec0, const Rec64 *tile,
+__device__ __forceinline__ void rk4_tracer64(const Rec64 *__restrict__ rec0, const double2 *tile,
                                              const Tile &T, const StepParams &P, int scheme,
                                              double2 x, double &ddx, double &ddy)
 {

@@ -58,6 +58,7 @@ __device__ __forceinline__ void step64_block(const StepParams &P, const State64 
                                              int lb)
 {
     Rec64 *lds = reinterpret_cast<Rec64 *>(lpt_dyn_lds);
+    const double2 *planes = reinterpret_cast<const double2 *>(lpt_dyn_lds);   // tile, two planes
     const SpeciesDev &sp = P.sp[species_of(P, lb)];
     const int64_t base = (int64_t)(lb - sp.block_begin) * blockDim.x;
     const int64_t local = base + threadIdx.x;
@@ -99,18 +100,18 @@ __device__ __forceinline__ void step64_block(const StepParams &P, const State64 
             const double is = sp.inv_st;
             double u, v;
             const double V1x = vn.x, V1y = vn.y;
-            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x, x.y, P.wa[0], P.wb[0], P.smode[0], u, v);
+            vel64<CUBIC>(rec0, planes, T, P, sp.scheme, x.x, x.y, P.wa[0], P.wb[0], P.smode[0], u, v);
             const double A1x = (u - V1x) * is, A1y = (v - V1y) * is;
             const double V2x = vn.x + hdt * A1x, V2y = vn.y + hdt * A1y;
-            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x + hdt * V1x, x.y + hdt * V1y, P.wa[1],
+            vel64<CUBIC>(rec0, planes, T, P, sp.scheme, x.x + hdt * V1x, x.y + hdt * V1y, P.wa[1],
                          P.wb[1], P.smode[1], u, v);
             const double A2x = (u - V2x) * is, A2y = (v - V2y) * is;
             const double V3x = vn.x + hdt * A2x, V3y = vn.y + hdt * A2y;
-            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x + hdt * V2x, x.y + hdt * V2y, P.wa[2],
+            vel64<CUBIC>(rec0, planes, T, P, sp.scheme, x.x + hdt * V2x, x.y + hdt * V2y, P.wa[2],
                          P.wb[2], P.smode[2], u, v);
             const double A3x = (u - V3x) * is, A3y = (v - V3y) * is;
             const double V4x = vn.x + dt * A3x, V4y = vn.y + dt * A3y;
-            vel64<CUBIC>(rec0, lds, T, P, sp.scheme, x.x + dt * V3x, x.y + dt * V3y, P.wa[3],
+            vel64<CUBIC>(rec0, planes, T, P, sp.scheme, x.x + dt * V3x, x.y + dt * V3y, P.wa[3],
                          P.wb[3], P.smode[3], u, v);
             const double A4x = (u - V4x) * is, A4y = (v - V4y) * is;
             ddx = dt6 * (V1x + 2.0 * V2x + 2.0 * V3x + V4x);
@@ -118,7 +119,7 @@ __device__ __forceinline__ void step64_block(const StepParams &P, const State64 
             D.vel[p] = make_double2(vn.x + dt6 * (A1x + 2.0 * A2x + 2.0 * A3x + A4x),
                                     vn.y + dt6 * (A1y + 2.0 * A2y + 2.0 * A3y + A4y));
         } else {
-            rk4_tracer64<CUBIC>(rec0, lds, T, P, sp.scheme, x, ddx, ddy);
+            rk4_tracer64<CUBIC>(rec0, planes, T, P, sp.scheme, x, ddx, ddy);
         }
         // wrapped coordinates for evaluation/output, unwrapped displacement
         // for statistics
@@ -711,7 +712,8 @@ static hipError_t launch64_t(const StepParams &P, const State64 &St, const State
                              const uint32_t *perm, const Rec64 *rec, double *partials,
                              DevClock *clock, int block, int grid, hipStream_t st)
 {
-    const size_t lds = P.tile_cap > 0 ? (size_t)P.tile_cap * sizeof(Rec64) : 0;
+    // two planes of 16-byte entries; the fill writes whole 64-entry chunks of each
+    const size_t lds = P.tile_cap > 0 ? (size_t)(2 * P.tile_cap + kWave) * 16 : 0;
     StepParams Q;
     if (perm) {
         const int g = launch_grid(step64_perm_kernel<C, I, S>, P, block, lds, grid, Q);
