@@ -92,16 +92,18 @@ typedef struct {
     int32_t sort_interval;  /* steps between cell-order re-sorts; 0 = never   */
     int32_t sort_tile;      /* tile side T of the cell-order key (power of
                                two dividing n); 0 selects 16                  */
-    int32_t block_size;     /* threads per block of the step kernel, multiple
-                               of 64 in [64, 1024]; 0 selects 256             */
+    int32_t block_size;     /* threads per block of the step kernel: 64,
+                               128, 256 or 512; 0 selects 256 (else
+                               LPT_E_ARG)                                     */
     uint32_t flags;         /* LPT_FLAG_*                                     */
     int32_t tile_records;   /* capacity, in node records, of the per-block
                                LDS field tile of the step kernel: 0 selects
                                the default (1200 records: 19200 bytes for
-                               FP32-split, 38400 for FP64), -1 disables
-                               tiles (every
-                               stencil gathers from global memory), else
-                               at least 16 records and at most 61440 bytes  */
+                               FP32-split, 38400 for FP64, each rounded up
+                               to whole 64-entry fill chunks), -1 disables
+                               tiles (every stencil gathers from global
+                               memory), else at least 16 records and at
+                               most 61440 bytes of records; else LPT_E_ARG */
 } lpt_config;
 
 /* One statistics record of one species (Sec. 3.2, 5.5):
