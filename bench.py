@@ -182,6 +182,10 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False):
     achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
     perm_us = 1e3 * timing["perm_step_ms"] / max(1, timing["perm_steps"])
     sort_us = 1e3 * timing["sort_ms"] / max(1, timing["sorts"])
+    # share of the timed wall time spent on re-sorting: keys + radix sort, and
+    # what the permuting steps cost beyond an in-place step
+    resort_s = 1e-3 * (timing["sort_ms"] + timing["perm_step_ms"]
+                       - timing["perm_steps"] * kern_ms)
     log(f"[bench] {args.steps} steps in {elapsed:.3f} s; in-place step kernel {kern_ms * 1e3:.1f} us "
         f"avg over {timing['step_launches']} launches; permuting step {perm_us:.1f} us avg over "
         f"{timing['perm_steps']}; sort (keys + radix) {sort_us:.1f} us avg over "
@@ -218,6 +222,7 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False):
             "perm_step_avg_us": perm_us if timing["perm_steps"] else None,
             "perm_steps": timing["perm_steps"],
             "sort_avg_us": sort_us if timing["sorts"] else None,
+            "resort_share_of_time": resort_s / elapsed,
             "alg_bytes_per_particle_step": bytes_per_launch / npart,
             "alg_bytes_per_launch": bytes_per_launch}
     return value, 1e3 * elapsed / args.steps, cfg, roof, extra
@@ -283,7 +288,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="spec4096_split",
-                    choices=["spec4096_split", "batch2048", "spec1024_fp64", "tg64",
+                    choices=["spec4096_split", "spec4096_split_share8", "batch2048",
+                             "spec1024_fp64", "tg64",
                              "adjoint2048"])
     ap.add_argument("--scheme", default="bilinear", choices=["bilinear", "catmull_rom", "bspline"],
                     help="scheme of the spec1024_fp64 workload")
@@ -325,7 +331,9 @@ def main():
     else:
         tuning = None
         fp64_twin = False
-        if args.workload == "spec4096_split":
+        if args.workload == "spec4096_split_share8":
+            w = workloads.C3_SHARE8
+        elif args.workload == "spec4096_split":
             w = workloads.C3_SPLIT
             fp64_twin = True
         elif args.workload == "batch2048":

@@ -5,6 +5,7 @@ GPU tests share.  Every field comes from :mod:`paper_2607_17836_amd.synth`.
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -67,6 +68,11 @@ def c2_spectrum(scheme: str, per_species: int = 1 << 20, n: int = 1024, steps: i
 C3_SPLIT = Workload("spec4096_fp32split_bilinear_2p24", 4096, "fp32_split", "spectrum", k0=20.0,
                     field_seed=3, dt=1e-3, steps=10000, stats_every=100, sort_interval=12,
                     sort_tile=16, species=(("tracer", 0.0, "bilinear", 1 << 24, 31),))
+
+# One GPU's share of the headline on eight: 2^21 tracers on the same full
+# 4096^2 field (the field is replicated, the particles are split).
+C3_SHARE8 = dataclasses.replace(C3_SPLIT, name="spec4096_fp32split_bilinear_2p21_share8",
+                                species=(("tracer", 0.0, "bilinear", 1 << 21, 31),))
 
 # Batching: 2048^2 FP32, 8 Stokes-number species, counts 2^16..2^23, scheme
 # k mod 3, inertial velocities from the field.
