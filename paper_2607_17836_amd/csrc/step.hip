@@ -489,13 +489,18 @@ __device__ __forceinline__ void stage32_first(const float4 *__restrict__ rec0, c
 // One RK4 step of one particle (eqs. rk4_update / rk4_inertial, Stokes drag
 // of eq. drag_rk4), then the split-position update and the FP64
 // displacement.  Returns the new displacement squared per axis.
-template <int SCH, bool INERT, bool ONE>
+// GATHER: the step after a re-sort, whose state reads are gathers through the
+// permutation; the displacement is then loaded first, so that its latency
+// overlaps the stages (in place it is loaded last, which keeps registers free).
+template <int SCH, bool INERT, bool ONE, bool GATHER>
 __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S,
                                            const State32 &D, const float4 *__restrict__ rec0,
                                            const float4 *lds, const Tile &T, const SpeciesDev &sp,
                                            int64_t p, int64_t q, uint32_t &cell, float2 o,
                                            double &r2x, double &r2y)
 {
+    double2 d = make_double2(0.0, 0.0);
+    if constexpr (GATHER) d = ld_stream(S.disp + q);
     int cx = (int)(cell & 0xFFFFu), cy = (int)(cell >> 16);
     int rx = 0, ry = 0;
     if (T.on) {   // cx - T.x0 lies in (-n, n)
@@ -546,7 +551,7 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
     float ox = o.x, oy = o.y;
     advance_split(cx, ox, dqx, P);
     advance_split(cy, oy, dqy, P);
-    double2 d = ld_stream(S.disp + q);
+    if constexpr (!GATHER) d = ld_stream(S.disp + q);
     cell = (uint32_t)cx | ((uint32_t)cy << 16);
     st_stream(D.cell + p, cell);
     st_stream(D.off + p, make_float2(ox, oy));
@@ -560,7 +565,7 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
 // The particle body for the block's kind.  SCHS: the scheme of every species
 // of the launch (one launch per scheme).  KINDS: 0 tracers only (St == 0
 // included), 1 tracers and/or inertial species.
-template <int SCHS, int KINDS, bool ONE>
+template <int SCHS, int KINDS, bool ONE, bool GATHER>
 __device__ __forceinline__ void particle_dispatch(const StepParams &P, const State32 &S,
                                                   const State32 &D,
                                                   const float4 *__restrict__ rec0,
@@ -570,9 +575,10 @@ __device__ __forceinline__ void particle_dispatch(const StepParams &P, const Sta
                                                   double &r2y)
 {
     if (KINDS != 0 && sp.inertial)
-        particle32<SCHS, KINDS != 0, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
+        particle32<SCHS, KINDS != 0, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x,
+                                                  r2y);
     else
-        particle32<SCHS, false, ONE>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
+        particle32<SCHS, false, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
 }
 
 // One logical block of the step.  The state of slot p is read from S and
@@ -617,11 +623,11 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
     }
     if (active) {
         if (P.ends_one)
-            particle_dispatch<SCHS, KINDS, true>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x,
-                                                 r2y);
+            particle_dispatch<SCHS, KINDS, true, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, o,
+                                                         r2x, r2y);
         else
-            particle_dispatch<SCHS, KINDS, false>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x,
-                                                  r2y);
+            particle_dispatch<SCHS, KINDS, false, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, o,
+                                                          r2x, r2y);
         if (GATHER) D.id[p] = S.id[q];
     }
     if (STATS) {
