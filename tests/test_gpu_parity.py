@@ -326,14 +326,21 @@ def test_lds_tiles_never_change_results(precision):
     tile and with a tile too small to hold most blocks' boxes.  One inertial
     species starts ten times faster than any node, so its stage positions
     leave the tile halo and exercise the per-lane fallback to global
-    gathers; an even-sized grid and an odd one cover both index wraps."""
+    gathers; an even-sized grid and an odd one cover both index wraps; block
+    sizes of 64 to 512 threads change the tile fill's work split."""
     for n in (256, 200):
         say(f"lds tiles {precision} n={n}")
         (ua, va), (ub, vb) = synth.spectrum_snapshots(n, 10, 8, 0.002)
         outs = []
-        for tile, halo in ((-1, 1.0), (0, 1.0), (64, 1.0), (0, 0.3)):
+        # (tile records, halo scale, block size): the tile fill's chunks per
+        # wave depend on the block's wave count, so blocks of 1, 2 and 8 waves
+        # are covered too (their statistics sum in another tree: positions
+        # and velocities only)
+        cases = ((-1, 1.0, 0), (0, 1.0, 0), (64, 1.0, 0), (0, 0.3, 0), (0, 1.0, 64),
+                 (0, 1.0, 128), (0, 1.0, 512))
+        for tile, halo, block in cases:
             tr = lpt.Tracker(n, precision, sort_interval=4, sort_tile=8 if n == 256 else 0,
-                             tile_records=tile)
+                             tile_records=tile, block_size=block)
             tr.set_tuning(halo_scale=halo)
             tr.set_time_mode("pingpong")
             tr.set_snapshot(0, 0.0, ua, va)
@@ -349,7 +356,7 @@ def test_lds_tiles_never_change_results(precision):
             tr.step(13, 0.002, stats_every=13)
             outs.append([tr.get_positions(s) for s in sids] +
                         [tr.get_velocities(s) for s in sids[3:]] +
-                        [tr.get_stats(s)["msd"] for s in sids])
+                        ([tr.get_stats(s)["msd"] for s in sids] if block == 0 else []))
             tr.close()
         for other in outs[1:]:
             for a, b in zip(outs[0], other):
