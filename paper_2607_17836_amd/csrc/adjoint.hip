@@ -54,19 +54,27 @@ __device__ __forceinline__ void dweights_bs(double s, double w[4])
     w[3] = 0.5 * s * s;
 }
 
-// Stencil of the point: `cnt` nodes starting at (i0, j0), cnt x cnt, with
-// 1D weights and their derivatives per axis.
+// Stencil of the point: K x K nodes starting at (i0, j0) (K = 2 bilinear,
+// 4 bicubic), with 1D weights and their derivatives per axis.  K is a
+// compile-time size, so the arrays stay in registers.
+template <int K>
 struct Sten64 {
-    int cnt, i0, j0;
-    double wx[4], wy[4], dx[4], dy[4];
+    int i0, j0;
+    double wx[K], wy[K], dx[K], dy[K];
 };
 
-__device__ __forceinline__ Sten64 stencil64(const StepParams &P, int scheme, const Loc64 &l)
+// Whether the point's stencil is bilinear (the scheme, or the paper's
+// bilinear fallback near the grid edge).
+__device__ __forceinline__ bool bilinear_at(const StepParams &P, int scheme, const Loc64 &l)
 {
-    Sten64 s;
-    const bool bil = scheme == kBilinear || edge_cell(P.compat_edge, l.i, l.j, P.n);
-    if (bil) {
-        s.cnt = 2;
+    return scheme == kBilinear || edge_cell(P.compat_edge, l.i, l.j, P.n);
+}
+
+template <int K>
+__device__ __forceinline__ Sten64<K> stencil64(int scheme, const Loc64 &l)
+{
+    Sten64<K> s;
+    if constexpr (K == 2) {
         s.i0 = l.i;
         s.j0 = l.j;
         s.wx[0] = 1.0 - l.xi;
@@ -77,21 +85,20 @@ __device__ __forceinline__ Sten64 stencil64(const StepParams &P, int scheme, con
         s.dx[1] = 1.0;
         s.dy[0] = -1.0;
         s.dy[1] = 1.0;
-        return s;
-    }
-    s.cnt = 4;
-    s.i0 = l.i - 1;
-    s.j0 = l.j - 1;
-    if (scheme == kCatmullRom) {
-        weights_cr(l.xi, s.wx);
-        weights_cr(l.eta, s.wy);
-        dweights_cr(l.xi, s.dx);
-        dweights_cr(l.eta, s.dy);
     } else {
-        weights_bs(l.xi, s.wx);
-        weights_bs(l.eta, s.wy);
-        dweights_bs(l.xi, s.dx);
-        dweights_bs(l.eta, s.dy);
+        s.i0 = l.i - 1;
+        s.j0 = l.j - 1;
+        if (scheme == kCatmullRom) {
+            weights_cr(l.xi, s.wx);
+            weights_cr(l.eta, s.wy);
+            dweights_cr(l.xi, s.dx);
+            dweights_cr(l.eta, s.dy);
+        } else {
+            weights_bs(l.xi, s.wx);
+            weights_bs(l.eta, s.wy);
+            dweights_bs(l.xi, s.dx);
+            dweights_bs(l.eta, s.dy);
+        }
     }
     return s;
 }
@@ -99,15 +106,18 @@ __device__ __forceinline__ Sten64 stencil64(const StepParams &P, int scheme, con
 // Spatial Jacobian J = [du/dx, du/dy, dv/dx, dv/dy] of the time-blended
 // interpolated velocity at a stencil (records read through the ghost
 // border, so the stencil never wraps).
+template <int K>
 __device__ __forceinline__ void jacobian64(const Rec64 *__restrict__ rec0, const StepParams &P,
-                                           const Sten64 &s, double wa, double wb, int smode,
+                                           const Sten64<K> &s, double wa, double wb, int smode,
                                            double J[4])
 {
     double ux = 0.0, uy = 0.0, vx = 0.0, vy = 0.0;
-    for (int b = 0; b < s.cnt; ++b) {
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
         const Rec64 *row = rec0 + (__mul24(s.j0 + b, P.pitch) + s.i0);
         double rux = 0.0, rvx = 0.0, ru = 0.0, rv = 0.0;
-        for (int a = 0; a < s.cnt; ++a) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
             double u, v;
             node64(row + a, smode, wa, wb, u, v);
             rux += s.dx[a] * u;
@@ -136,19 +146,22 @@ struct GridGrad {
 };
 
 // dL/d(grid) += lam (x) (temporal weight) (x) (node weight).
+template <int K>
 __device__ __forceinline__ void scatter64(const GridGrad &G, const StepParams &P,
-                                          const Sten64 &s, double wa, double wb, double lx,
+                                          const Sten64<K> &s, double wa, double wb, double lx,
                                           double ly)
 {
     const int n = P.n;
     const int64_t nn = (int64_t)n * n;
     const int area = G.B.w * G.B.h;
     const double wt[2] = {wa, wb};
-    for (int b = 0; b < s.cnt; ++b) {
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
         const int j = wrap_cell(s.j0 + b, n, P.mask);
         int ry = j - G.B.y0;
         ry += ry < 0 ? n : 0;
-        for (int a = 0; a < s.cnt; ++a) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
             const int i = wrap_cell(s.i0 + a, n, P.mask);
             int rx = i - G.B.x0;
             rx += rx < 0 ? n : 0;
@@ -208,7 +221,7 @@ __global__ __launch_bounds__(kMaxBlock) void recompute64_kernel(StepParams P, co
 // trimmed) go to gU directly.
 extern __shared__ __align__(32) unsigned char adj_dyn_lds[];
 
-template <int NL, bool AGG>
+template <int NL, bool AGG, bool CUBIC>
 __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
                                                               const Rec64 *__restrict__ rec,
                                                               const double2 *__restrict__ tape,
@@ -258,66 +271,67 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
         double k1x, k1y, k2x, k2y, k3x, k3y;
         px[0] = x.x;
         py[0] = x.y;
-        vel64<true>(rec0, nullptr, no_tile(), P, scheme, px[0], py[0], P.wa[0], P.wb[0],
-                    P.smode[0], k1x, k1y);
+        vel64<CUBIC>(rec0, nullptr, no_tile(), P, scheme, px[0], py[0], P.wa[0], P.wb[0],
+                     P.smode[0], k1x, k1y);
         px[1] = x.x + hdt * k1x;
         py[1] = x.y + hdt * k1y;
-        vel64<true>(rec0, nullptr, no_tile(), P, scheme, px[1], py[1], P.wa[1], P.wb[1],
-                    P.smode[1], k2x, k2y);
+        vel64<CUBIC>(rec0, nullptr, no_tile(), P, scheme, px[1], py[1], P.wa[1], P.wb[1],
+                     P.smode[1], k2x, k2y);
         px[2] = x.x + hdt * k2x;
         py[2] = x.y + hdt * k2y;
-        vel64<true>(rec0, nullptr, no_tile(), P, scheme, px[2], py[2], P.wa[2], P.wb[2],
-                    P.smode[2], k3x, k3y);
+        vel64<CUBIC>(rec0, nullptr, no_tile(), P, scheme, px[2], py[2], P.wa[2], P.wb[2],
+                     P.smode[2], k3x, k3y);
         px[3] = x.x + dt * k3x;
         py[3] = x.y + dt * k3y;
 
-        Sten64 st[4];
-        double J[4][4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            st[q] = stencil64(P, scheme, locate64(P, px[q], py[q]));
-            jacobian64(rec0, P, st[q], P.wa[q], P.wb[q], P.smode[q], J[q]);
-        }
-
+        // Back through x' = x + dt/6 (k1 + 2 k2 + 2 k3 + k4), k_q = U(x_q),
+        // x_q = x + c_q dt k_(q-1) (c = 1/2, 1/2, 1): per adjoint vector r,
+        // lx[r] collects dL/dx and lk[r][q] the adjoint of k_q; the stages are
+        // taken newest first, one stencil at a time.
+        double lx[NL][2], lk[NL][4][2];
 #pragma unroll
         for (int r = 0; r < NL; ++r) {
             const double2 l = lam[p * NL + r];
-            // x' = x + dt/6 (k1 + 2 k2 + 2 k3 + k4)
-            double lx[2] = {l.x, l.y};
-            double l1[2] = {dt6 * l.x, dt6 * l.y};
-            double l2[2] = {dt3 * l.x, dt3 * l.y};
-            double l3[2] = {dt3 * l.x, dt3 * l.y};
-            const double l4[2] = {dt6 * l.x, dt6 * l.y};
-            double ls[2];
-            const bool grid = gU != nullptr && r == 0;
-            // k4 = U(x4), x4 = x + dt k3
-            if (grid) scatter64(G, P, st[3], P.wa[3], P.wb[3], l4[0], l4[1]);
-            add_jt(J[3], l4, ls);
-            lx[0] += ls[0];
-            lx[1] += ls[1];
-            l3[0] += dt * ls[0];
-            l3[1] += dt * ls[1];
-            // k3 = U(x3), x3 = x + dt/2 k2
-            if (grid) scatter64(G, P, st[2], P.wa[2], P.wb[2], l3[0], l3[1]);
-            add_jt(J[2], l3, ls);
-            lx[0] += ls[0];
-            lx[1] += ls[1];
-            l2[0] += hdt * ls[0];
-            l2[1] += hdt * ls[1];
-            // k2 = U(x2), x2 = x + dt/2 k1
-            if (grid) scatter64(G, P, st[1], P.wa[1], P.wb[1], l2[0], l2[1]);
-            add_jt(J[1], l2, ls);
-            lx[0] += ls[0];
-            lx[1] += ls[1];
-            l1[0] += hdt * ls[0];
-            l1[1] += hdt * ls[1];
-            // k1 = U(x)
-            if (grid) scatter64(G, P, st[0], P.wa[0], P.wb[0], l1[0], l1[1]);
-            add_jt(J[0], l1, ls);
-            lx[0] += ls[0];
-            lx[1] += ls[1];
-            lam[p * NL + r] = make_double2(lx[0], lx[1]);
+            lx[r][0] = l.x;
+            lx[r][1] = l.y;
+            lk[r][0][0] = dt6 * l.x;
+            lk[r][0][1] = dt6 * l.y;
+            lk[r][1][0] = dt3 * l.x;
+            lk[r][1][1] = dt3 * l.y;
+            lk[r][2][0] = dt3 * l.x;
+            lk[r][2][1] = dt3 * l.y;
+            lk[r][3][0] = dt6 * l.x;
+            lk[r][3][1] = dt6 * l.y;
         }
+        const bool grid = gU != nullptr;
+        const double back[4] = {0.0, hdt, hdt, dt};   // c_q dt
+#pragma unroll
+        for (int q = 3; q >= 0; --q) {
+            const Loc64 loc = locate64(P, px[q], py[q]);
+            double J[4];
+            if (!CUBIC || bilinear_at(P, scheme, loc)) {
+                const Sten64<2> st = stencil64<2>(scheme, loc);
+                if (grid) scatter64<2>(G, P, st, P.wa[q], P.wb[q], lk[0][q][0], lk[0][q][1]);
+                jacobian64<2>(rec0, P, st, P.wa[q], P.wb[q], P.smode[q], J);
+            } else if constexpr (CUBIC) {
+                const Sten64<4> st = stencil64<4>(scheme, loc);
+                if (grid) scatter64<4>(G, P, st, P.wa[q], P.wb[q], lk[0][q][0], lk[0][q][1]);
+                jacobian64<4>(rec0, P, st, P.wa[q], P.wb[q], P.smode[q], J);
+            }
+#pragma unroll
+            for (int r = 0; r < NL; ++r) {
+                double ls[2];
+                add_jt(J, lk[r][q], ls);
+                lx[r][0] += ls[0];
+                lx[r][1] += ls[1];
+                if (q > 0) {
+                    lk[r][q - 1][0] += back[q] * ls[0];
+                    lk[r][q - 1][1] += back[q] * ls[1];
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NL; ++r) lam[p * NL + r] = make_double2(lx[r][0], lx[r][1]);
     }
 
     if constexpr (AGG) {
@@ -391,20 +405,29 @@ hipError_t launch_recompute64(const StepParams &P, const Rec64 *rec, const doubl
 // LDS of the aggregating adjoint: four planes of doubles per box node.
 constexpr int kAdjAccNodes = 1024;
 
-hipError_t launch_adjoint64(const StepParams &P, const Rec64 *rec, const double2 *tape,
-                            double2 *lam, int nl, double *gU, int block, hipStream_t st)
+template <bool CUBIC>
+static hipError_t launch_adjoint64_c(const StepParams &P, const Rec64 *rec, const double2 *tape,
+                                     double2 *lam, int nl, double *gU, int block, hipStream_t st)
 {
     if (nl == 1 && gU)
-        hipLaunchKernelGGL((adjoint64_kernel<1, true>), dim3(P.total_blocks), dim3(block),
+        hipLaunchKernelGGL((adjoint64_kernel<1, true, CUBIC>), dim3(P.total_blocks), dim3(block),
                            (size_t)kAdjAccNodes * 4 * sizeof(double), st, P, rec, tape, lam, gU,
                            kAdjAccNodes);
     else if (nl == 1)
-        hipLaunchKernelGGL((adjoint64_kernel<1, false>), dim3(P.total_blocks), dim3(block), 0, st,
-                           P, rec, tape, lam, (double *)nullptr, 0);
+        hipLaunchKernelGGL((adjoint64_kernel<1, false, CUBIC>), dim3(P.total_blocks), dim3(block),
+                           0, st, P, rec, tape, lam, (double *)nullptr, 0);
     else
-        hipLaunchKernelGGL((adjoint64_kernel<2, false>), dim3(P.total_blocks), dim3(block), 0, st,
-                           P, rec, tape, lam, (double *)nullptr, 0);
+        hipLaunchKernelGGL((adjoint64_kernel<2, false, CUBIC>), dim3(P.total_blocks), dim3(block),
+                           0, st, P, rec, tape, lam, (double *)nullptr, 0);
     return hipGetLastError();
+}
+
+hipError_t launch_adjoint64(const StepParams &P, const Rec64 *rec, const double2 *tape,
+                            double2 *lam, int nl, double *gU, bool cubic, int block,
+                            hipStream_t st)
+{
+    return cubic ? launch_adjoint64_c<true>(P, rec, tape, lam, nl, gU, block, st)
+                 : launch_adjoint64_c<false>(P, rec, tape, lam, nl, gU, block, st);
 }
 
 hipError_t launch_seed_adjoint(const uint32_t *id, int64_t np, int nl, const double *gx,

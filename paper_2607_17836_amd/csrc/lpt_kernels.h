@@ -166,8 +166,10 @@ hipError_t launch_order(const uint32_t *id, int64_t offset, int64_t count, int32
 // the step kernel's block size (P's species block layout)
 hipError_t launch_recompute64(const StepParams &P, const Rec64 *rec, const double2 *in,
                               double2 *out, int block, hipStream_t st);
+// cubic: some species uses a bicubic scheme (else every stencil is bilinear)
 hipError_t launch_adjoint64(const StepParams &P, const Rec64 *rec, const double2 *tape,
-                            double2 *lam, int nl, double *gU, int block, hipStream_t st);
+                            double2 *lam, int nl, double *gU, bool cubic, int block,
+                            hipStream_t st);
 hipError_t launch_seed_adjoint(const uint32_t *id, int64_t np, int nl, const double *gx,
                                const double *gy, double2 *lam, hipStream_t st);
 hipError_t launch_gather_adjoint(const uint32_t *id, int64_t np, int nl, const double2 *lam,

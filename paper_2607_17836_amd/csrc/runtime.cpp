@@ -1091,7 +1091,8 @@ lpt_status reverse_sweep(lpt_ctx *c, int nl, double2 *lam, double *gU)
                 P.wb[q] = w.wb[q];
                 P.smode[q] = slot_mode(w.wa[q], w.wb[q]);
             }
-            e = launch_adjoint64(P, rec, tape + s * np, lam, nl, gU, c->block, c->stream);
+            e = launch_adjoint64(P, rec, tape + s * np, lam, nl, gU, c->has_cubic, c->block,
+                                 c->stream);
         }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
