@@ -484,3 +484,30 @@ def test_cell_keys_tile_major_bijection(tile):
     np.testing.assert_array_equal(kc, t)
     if tile == 1:
         np.testing.assert_array_equal(k, j * n + i)
+
+
+@pytest.mark.parametrize("scheme", ["bilinear", "catmull_rom", "bspline"])
+def test_psi_path_at_nodes_is_the_centred_difference(scheme):
+    """The psi path (psi interpolated at x +- h and y +- h, then centred
+    differences, eq. particle_velocity_reconstruction) on psi = sin x sin y,
+    evaluated at grid nodes: every psi sample then sits on a node, where
+    bilinear and Catmull-Rom return the node value and the B-spline returns
+    the node value times its Fourier multiplier (2 + cos kh)/3 per axis
+    (k = 1).  So u = s sin x cos y sin(h)/h, v = -s cos x sin y sin(h)/h with
+    s = 1 or ((2 + cos h)/3)^2: a dropped term, a wrong sign or swapped axes
+    in the psi path fail it."""
+    n = 32
+    h = L / n
+    g = np.arange(n) * h
+    X, Y = np.meshgrid(g, g, indexing="xy")          # [j][i], x fastest
+    psi = np.sin(X) * np.sin(Y)
+    fl = oracle.psi_flow(psi, scheme=oracle.SCHEMES[scheme])
+    rng = np.random.default_rng(3)
+    i = rng.integers(0, n, 200)
+    j = rng.integers(0, n, 200)
+    x, y = i * h, j * h
+    u, v = oracle.velocity(fl, x, y, 0.0)
+    s = ((2.0 + np.cos(h)) / 3.0) ** 2 if scheme == "bspline" else 1.0
+    fd = np.sin(h) / h
+    np.testing.assert_allclose(u, s * np.sin(x) * np.cos(y) * fd, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(v, -s * np.cos(x) * np.sin(y) * fd, rtol=0, atol=1e-13)
