@@ -206,7 +206,5 @@ hipError_t launch_permute64(const State64 &src, const State64 &dst, const uint32
                             int64_t n, bool with_vel, hipStream_t st);
 hipError_t launch_permute32(const State32 &src, const State32 &dst, const uint32_t *perm,
                             int64_t n, bool with_vel, hipStream_t st);
-// inv[id[p]] = p (id a permutation of 0 .. n-1)
-hipError_t launch_invert(const uint32_t *id, uint32_t *inv, int64_t n, hipStream_t st);
 
 }  // namespace lpt

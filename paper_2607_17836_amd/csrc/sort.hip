@@ -432,21 +432,6 @@ __global__ void permute32_kernel(State32 src, State32 dst, const uint32_t *__res
     if (with_vel) dst.vel[p] = src.vel[q];
 }
 
-// inv[id[p]] = p: the slot of every global particle index.
-__global__ void invert_kernel(const uint32_t *__restrict__ id, uint32_t *inv, int64_t n)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n) inv[id[p]] = (uint32_t)p;
-}
-
-hipError_t launch_invert(const uint32_t *id, uint32_t *inv, int64_t n, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    const int b = 256;
-    hipLaunchKernelGGL(invert_kernel, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, id, inv, n);
-    return hipGetLastError();
-}
-
 hipError_t launch_permute64(const State64 &src, const State64 &dst, const uint32_t *perm,
                             int64_t n, bool with_vel, hipStream_t st)
 {
