@@ -192,16 +192,19 @@ int64_t sort_scan_blocks(int64_t n);
 
 // keys[0] = (species << tile_bits) | tile index of the stored cell, plus the
 // histogram of the first radix digit (of a key_bits-bit sort) in W.hist.
+// Keys of at most 16 bits are stored as uint16_t (see radix_sort's narrow).
 hipError_t launch_keys64(const StepParams &P, const State64 &S, int tile, int tile_bits,
                          int key_bits, SortWork &W, hipStream_t st);
 hipError_t launch_keys32(const StepParams &P, const State32 &S, int tile, int tile_bits,
                          int key_bits, SortWork &W, hipStream_t st);
 // Stable LSD radix sort of keys[0] over the low key_bits bits, carrying each
 // key's input index as its value (vals[0] is not read).  first_hist: W.hist
-// already holds the first digit's histogram (from launch_keys*).  *result
-// receives the buffer index (0 or 1) holding the sorted keys and values.
-hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, bool first_hist, int *result,
-                      hipStream_t st);
+// already holds the first digit's histogram (from launch_keys*).  narrow:
+// keys of at most 16 bits are stored as uint16_t (as launch_keys* writes
+// them); else uint32_t.  *result receives the buffer index (0 or 1) holding
+// the sorted keys and values.
+hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, bool first_hist, bool narrow,
+                      int *result, hipStream_t st);
 hipError_t launch_permute64(const State64 &src, const State64 &dst, const uint32_t *perm,
                             int64_t n, bool with_vel, hipStream_t st);
 hipError_t launch_permute32(const State32 &src, const State32 &dst, const uint32_t *perm,

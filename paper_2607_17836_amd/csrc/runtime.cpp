@@ -305,7 +305,7 @@ lpt_status do_sort(lpt_ctx *c, const uint32_t **perm_out = nullptr)
     else
         HIP_TRY(c, launch_keys32(P, c->s32[c->cur], c->sort_tile, tb, kb, c->sw, c->stream));
     int res = 0;
-    HIP_TRY(c, radix_sort(c->sw, c->np, kb, true, &res, c->stream));
+    HIP_TRY(c, radix_sort(c->sw, c->np, kb, true, true, &res, c->stream));
     const uint32_t *perm = c->sw.vals[res];
     if (perm_out) {
         *perm_out = perm;
@@ -1407,7 +1407,7 @@ lpt_status lpt_radix_sort(lpt_ctx *c, int64_t npts, int32_t key_bits, const uint
     // a single key is its own sorted order (the sort then launches nothing)
     if (e == hipSuccess && npts == 1) e = hipMemsetAsync(w.vals[0], 0, sizeof(uint32_t), c->stream);
     int res = 0;
-    if (e == hipSuccess) e = radix_sort(w, npts, key_bits, false, &res, c->stream);
+    if (e == hipSuccess) e = radix_sort(w, npts, key_bits, false, false, &res, c->stream);
     if (e == hipSuccess && keys_out)
         e = hipMemcpyAsync(keys_out, w.keys[res], (size_t)npts * 4, hipMemcpyDeviceToDevice,
                            c->stream);

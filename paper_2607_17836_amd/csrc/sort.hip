@@ -87,11 +87,59 @@ __device__ __forceinline__ void count_runs(const uint32_t *v, int cnt, int shift
     atomicAdd(&h[cur], run);
 }
 
+// 16 consecutive keys of type K (uint32_t, or uint16_t when keys fit in 16
+// bits) from / to 16-byte aligned memory, widened to / narrowed from uint32.
+template <typename K>
+__device__ __forceinline__ void load16(const K *p, uint32_t k[kItems])
+{
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+    if constexpr (sizeof(K) == 4) {
+#pragma unroll
+        for (int c = 0; c < kItems / 4; ++c) {
+            const uint4 w = q[c];
+            k[4 * c] = w.x;
+            k[4 * c + 1] = w.y;
+            k[4 * c + 2] = w.z;
+            k[4 * c + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < kItems / 8; ++c) {
+            const uint4 w = q[c];
+            const uint32_t h[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                k[8 * c + 2 * m] = h[m] & 0xFFFFu;
+                k[8 * c + 2 * m + 1] = h[m] >> 16;
+            }
+        }
+    }
+}
+
+template <typename K>
+__device__ __forceinline__ void store16(K *p, const uint32_t k[kItems])
+{
+    uint4 *q = reinterpret_cast<uint4 *>(p);
+    if constexpr (sizeof(K) == 4) {
+#pragma unroll
+        for (int c = 0; c < kItems / 4; ++c)
+            q[c] = make_uint4(k[4 * c], k[4 * c + 1], k[4 * c + 2], k[4 * c + 3]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < kItems / 8; ++c) {
+            uint32_t h[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) h[m] = k[8 * c + 2 * m] | (k[8 * c + 2 * m + 1] << 16);
+            q[c] = make_uint4(h[0], h[1], h[2], h[3]);
+        }
+    }
+}
+
 // Keys of the 16 consecutive particles of each thread, written to keys[], and
 // the tile's histogram of the low `mask` digit.  load(i0, cnt, k) fills
 // k[0 .. cnt) with the keys of particles i0 ...
-template <typename Load>
-__device__ __forceinline__ void keys_tile(Load load, int64_t total, uint32_t *keys, uint32_t mask,
+template <typename K, typename Load>
+__device__ __forceinline__ void keys_tile(Load load, int64_t total, K *keys, uint32_t mask,
                                           uint32_t *hist, int ntiles)
 {
     __shared__ uint32_t h[256];
@@ -102,25 +150,23 @@ __device__ __forceinline__ void keys_tile(Load load, int64_t total, uint32_t *ke
     const int cnt = (int)(total - i0 < kItems ? (total - i0 > 0 ? total - i0 : 0) : kItems);
     uint32_t k[kItems];
     load(i0, cnt, k);
-    if (cnt == kItems) {
-#pragma unroll
-        for (int j = 0; j < kItems; j += 4)
-            *reinterpret_cast<uint4 *>(keys + i0 + j) = make_uint4(k[j], k[j + 1], k[j + 2], k[j + 3]);
-    } else {
-        for (int j = 0; j < cnt; ++j) keys[i0 + j] = k[j];
-    }
+    if (cnt == kItems)
+        store16<K>(keys + i0, k);
+    else
+        for (int j = 0; j < cnt; ++j) keys[i0 + j] = (K)k[j];
     count_runs<kItems>(k, cnt, 0, mask, h);
     __syncthreads();
     hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
 }
 
+template <typename K>
 __global__ __launch_bounds__(kSortThreads) void keys64_kernel(StepParams P, State64 S,
                                                               int tile_shift, int tile_bits,
-                                                              uint32_t *keys, int64_t total,
+                                                              K *keys, int64_t total,
                                                               uint32_t mask, uint32_t *hist,
                                                               int ntiles)
 {
-    keys_tile(
+    keys_tile<K>(
         [&](int64_t i0, int cnt, uint32_t *k) {
 #pragma unroll
             for (int j = 0; j < kItems; ++j) {
@@ -133,13 +179,14 @@ __global__ __launch_bounds__(kSortThreads) void keys64_kernel(StepParams P, Stat
         total, keys, mask, hist, ntiles);
 }
 
+template <typename K>
 __global__ __launch_bounds__(kSortThreads) void keys32_kernel(StepParams P, State32 S,
                                                               int tile_shift, int tile_bits,
-                                                              uint32_t *keys, int64_t total,
+                                                              K *keys, int64_t total,
                                                               uint32_t mask, uint32_t *hist,
                                                               int ntiles)
 {
-    keys_tile(
+    keys_tile<K>(
         [&](int64_t i0, int cnt, uint32_t *k) {
             uint32_t c[kItems];
             if (cnt == kItems) {
@@ -183,8 +230,14 @@ hipError_t launch_keys64(const StepParams &P, const State64 &S, int tile, int ti
 {
     const int64_t total = total_particles(P);
     const int ntiles = (int)((total + kTile - 1) / kTile);
-    hipLaunchKernelGGL(keys64_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, P, S, ilog2(tile),
-                       tile_bits, W.keys[0], total, first_mask(key_bits), W.hist, ntiles);
+    if (key_bits <= 16)
+        hipLaunchKernelGGL(keys64_kernel<uint16_t>, dim3(ntiles), dim3(kSortThreads), 0, st, P, S,
+                           ilog2(tile), tile_bits, reinterpret_cast<uint16_t *>(W.keys[0]), total,
+                           first_mask(key_bits), W.hist, ntiles);
+    else
+        hipLaunchKernelGGL(keys64_kernel<uint32_t>, dim3(ntiles), dim3(kSortThreads), 0, st, P, S,
+                           ilog2(tile), tile_bits, W.keys[0], total, first_mask(key_bits), W.hist,
+                           ntiles);
     return hipGetLastError();
 }
 
@@ -193,16 +246,23 @@ hipError_t launch_keys32(const StepParams &P, const State32 &S, int tile, int ti
 {
     const int64_t total = total_particles(P);
     const int ntiles = (int)((total + kTile - 1) / kTile);
-    hipLaunchKernelGGL(keys32_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, P, S, ilog2(tile),
-                       tile_bits, W.keys[0], total, first_mask(key_bits), W.hist, ntiles);
+    if (key_bits <= 16)
+        hipLaunchKernelGGL(keys32_kernel<uint16_t>, dim3(ntiles), dim3(kSortThreads), 0, st, P, S,
+                           ilog2(tile), tile_bits, reinterpret_cast<uint16_t *>(W.keys[0]), total,
+                           first_mask(key_bits), W.hist, ntiles);
+    else
+        hipLaunchKernelGGL(keys32_kernel<uint32_t>, dim3(ntiles), dim3(kSortThreads), 0, st, P, S,
+                           ilog2(tile), tile_bits, W.keys[0], total, first_mask(key_bits), W.hist,
+                           ntiles);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // radix pass kernels
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kSortThreads) void hist_kernel(const uint32_t *__restrict__ keys,
-                                                            int64_t n, int shift, uint32_t mask,
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void hist_kernel(const K *__restrict__ keys, int64_t n,
+                                                            int shift, uint32_t mask,
                                                             uint32_t *hist, int ntiles)
 {
     __shared__ uint32_t h[256];
@@ -213,17 +273,10 @@ __global__ __launch_bounds__(kSortThreads) void hist_kernel(const uint32_t *__re
     const int cnt = (int)(n - i0 < kItems ? (n - i0 > 0 ? n - i0 : 0) : kItems);
     uint32_t k[kItems];
     if (cnt == kItems) {
-#pragma unroll
-        for (int j = 0; j < kItems; j += 4) {
-            const uint4 q = *reinterpret_cast<const uint4 *>(keys + i0 + j);
-            k[j] = q.x;
-            k[j + 1] = q.y;
-            k[j + 2] = q.z;
-            k[j + 3] = q.w;
-        }
+        load16<K>(keys + i0, k);
     } else {
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) k[j] = j < cnt ? keys[i0 + j] : 0u;
+        for (int j = 0; j < kItems; ++j) k[j] = j < cnt ? (uint32_t)keys[i0 + j] : 0u;
     }
     count_runs<kItems>(k, cnt, shift, mask, h);
     __syncthreads();
@@ -285,9 +338,10 @@ __global__ __launch_bounds__(kScanThreads) void row_scan_kernel(uint32_t *hist, 
 
 // offsets: the row-scanned histogram table; totals: each digit's count (the
 // start of digit d's output run is the sum of the totals of smaller digits).
+template <typename K>
 __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
-    const uint32_t *__restrict__ keys_in, const uint32_t *vals_in,
-    uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, int64_t n, int shift,
+    const K *__restrict__ keys_in, const uint32_t *vals_in,
+    K *__restrict__ keys_out, uint32_t *__restrict__ vals_out, int64_t n, int shift,
     uint32_t mask, const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ totals,
     int ntiles)
 {
@@ -305,7 +359,7 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
     for (int it = 0; it < kItems; ++it) {
         const int64_t i = run0 + (int64_t)it * 64 + lane;
         const bool valid = i < n;
-        key[it] = valid ? keys_in[i] : 0u;
+        key[it] = valid ? (uint32_t)keys_in[i] : 0u;
         val[it] = !valid ? 0u : vals_in ? vals_in[i] : (uint32_t)i;
         const uint32_t d = (key[it] >> shift) & mask;
         // m = the valid lanes whose digit equals this lane's.  Nearly sorted
@@ -354,30 +408,30 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
         if (i < n) {
             const uint32_t d = (key[it] >> shift) & mask;
             const uint32_t pos = wcount[w][d] + rank[it];
-            keys_out[pos] = key[it];
+            keys_out[pos] = (K)key[it];
             vals_out[pos] = val[it];
         }
     }
 }
 
-hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, bool first_hist, int *result,
-                      hipStream_t st)
+template <typename K>
+static hipError_t radix_sort_t(SortWork &W, int64_t n, int key_bits, bool first_hist, int *result,
+                               hipStream_t st)
 {
-    *result = 0;
-    if (n <= 1) return hipSuccess;
     const int ntiles = (int)((n + kTile - 1) / kTile);
+    K *keys[2] = {reinterpret_cast<K *>(W.keys[0]), reinterpret_cast<K *>(W.keys[1])};
     int cur = 0;
     for (int shift = 0; shift < key_bits; shift += 8) {
         const int bits = key_bits - shift < 8 ? key_bits - shift : 8;
         const uint32_t mask = (1u << bits) - 1u;
         if (shift > 0 || !first_hist)
-            hipLaunchKernelGGL(hist_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, W.keys[cur],
+            hipLaunchKernelGGL(hist_kernel<K>, dim3(ntiles), dim3(kSortThreads), 0, st, keys[cur],
                                n, shift, mask, W.hist, ntiles);
         hipLaunchKernelGGL(row_scan_kernel, dim3(mask + 1), dim3(kScanThreads), 0, st, W.hist,
                            ntiles, W.scan_tmp);
         // the first pass takes each key's input index as its value
-        hipLaunchKernelGGL(scatter_kernel, dim3(ntiles), dim3(kSortThreads), 0, st, W.keys[cur],
-                           shift == 0 ? (const uint32_t *)nullptr : W.vals[cur], W.keys[1 - cur],
+        hipLaunchKernelGGL(scatter_kernel<K>, dim3(ntiles), dim3(kSortThreads), 0, st, keys[cur],
+                           shift == 0 ? (const uint32_t *)nullptr : W.vals[cur], keys[1 - cur],
                            W.vals[1 - cur], n, shift, mask, W.hist, W.scan_tmp, ntiles);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -385,6 +439,16 @@ hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, bool first_hist, int
     }
     *result = cur;
     return hipSuccess;
+}
+
+hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, bool first_hist, bool narrow,
+                      int *result, hipStream_t st)
+{
+    *result = 0;
+    if (n <= 1) return hipSuccess;
+    return narrow && key_bits <= 16
+               ? radix_sort_t<uint16_t>(W, n, key_bits, first_hist, result, st)
+               : radix_sort_t<uint32_t>(W, n, key_bits, first_hist, result, st);
 }
 
 __global__ void order_kernel(const uint32_t *__restrict__ id, int64_t offset, int64_t count,
