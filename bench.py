@@ -8,18 +8,22 @@ with two FP32 velocity snapshots from the k0 = 20 random-phase spectrum
 cell + FP32 offset, FP64 displacement), bilinear interpolation.  One step =
 one RK4 step of every particle (cell location, 4 stages of spatial + temporal
 interpolation, combine, wrap, FP64 displacement), plus the cell-order re-sort
-every 20 steps and the FP64 MSD/dispersion reduction every 100 steps, all
-inside the timed region.  Inputs are resident in HBM before timing starts.
+every 12 steps (applied by the following step's kernel) and the FP64
+MSD/dispersion reduction every 100 steps, all inside the timed region.  Inputs
+are resident in HBM before timing starts.
 
-Other workloads (--workload): batch2048 (8 Stokes-number species, all three
-schemes, autotuned launch shape), spec1024_fp64 (FP64 tracers + inertial
-particles, --scheme), tg64 (FP64 Taylor-Green, 4096 tracers) and adjoint2048
-(FP64 checkpointed forward run plus reverse sweep with grid gradients).
+Other workloads (--workload): spec4096_split_share8 (the headline with 2^21
+tracers: one GPU's share on eight, same full field), batch2048 (8
+Stokes-number species, all three schemes, one launch per species, autotuned
+launch shape), spec1024_fp64 (FP64 tracers + inertial particles, --scheme),
+tg64 (FP64 Taylor-Green, 4096 tracers) and adjoint2048 (FP64 checkpointed
+forward run plus reverse sweep with grid gradients).
 
-Prints one JSON line.  The roofline object reports the dominant kernel's
-algorithmic bytes per launch over its average duration, measured with HIP
-events recorded by the library on the stream the kernel runs on, against the
-8 TB/s HBM peak.
+Prints one JSON line.  The roofline object reports the dominant kernel's (the
+in-place step kernel's) algorithmic bytes per launch over its average
+duration, measured with HIP events recorded by the library on the stream the
+kernel runs on, against the 8 TB/s HBM peak; beside it, the permuting step
+after each re-sort, the re-sort itself and the re-sort share of the time.
 """
 from __future__ import annotations
 
