@@ -1,0 +1,29 @@
+"""Host-side parts of bench.py's contract (no GPU): the algorithmic bytes per
+particle-step that the roofline divides, and the refusal of multi-GPU runs."""
+import dataclasses
+import os
+import subprocess
+import sys
+
+import bench
+from paper_2607_17836_amd import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_algorithmic_bytes_per_particle_step():
+    # 2 x 28 B of split state (cell 4, offset 8, FP64 displacement 16) plus
+    # the 4096^2 x 16 B field pair read once, shared by the particles
+    w = workloads.C3_SPLIT
+    assert bench.alg_bytes_per_step(w) / w.particles == 2 * 28 + 4096 ** 2 * 16 / 2 ** 24 == 72.0
+    s = workloads.C3_SHARE8
+    assert bench.alg_bytes_per_step(s) / s.particles == 2 * 28 + 4096 ** 2 * 16 / 2 ** 21 == 184.0
+    d = dataclasses.replace(w, precision="fp64")
+    assert bench.alg_bytes_per_step(d) / d.particles == 2 * 32 + 4096 ** 2 * 32 / 2 ** 24 == 96.0
+
+
+def test_multi_gpu_request_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
