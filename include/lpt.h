@@ -258,8 +258,12 @@ typedef struct {
                                into a hipGraph once and replays it             */
     float halo_scale;       /* LDS tile halo as a multiple of the largest
                                displacement a step can make at the largest node
-                               speed, in (0, 4]; 0 selects 1.  Below 1 the
-                               fastest particles gather from global memory    */
+                               speed, in (0, 4], rounded up to whole cells;
+                               0 selects 0.125 (one cell for displacements of
+                               up to eight cells a step, 5.1 for Catmull-Rom).
+                               Particles whose stencil leaves the tile gather
+                               from global memory, so it never affects
+                               results                                        */
 } lpt_tuning;
 
 lpt_status lpt_get_tuning(lpt_ctx *ctx, lpt_tuning *out);

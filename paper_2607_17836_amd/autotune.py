@@ -21,7 +21,7 @@ SPACE = {
     "sort_interval": (20, 10, 12, 15, 40, 5),
     "persistent": (0, 1),
     "graph_chunk": (0, 100),
-    "halo_scale": (1.0, 0.7, 0.5),
+    "halo_scale": (0.125, 0.25, 0.5, 1.0),
 }
 
 
@@ -45,7 +45,7 @@ def tune(w, lpt_mod, workloads_mod, trial_steps=80, rounds=2, log=None):
     try:
         best = tr.get_tuning()
         best.update(sort_interval=w.sort_interval or 20, graph_chunk=0, persistent=0,
-                    tile_records=0, block_size=256, halo_scale=1.0)
+                    tile_records=0, block_size=256, halo_scale=0.125)
 
         def measure(t):
             tr.set_tuning(**t)

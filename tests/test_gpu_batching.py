@@ -92,6 +92,8 @@ def test_tuning_is_validated_and_changes_nothing_on_error():
                   graph_chunk=10, halo_scale=0.5)
     assert tr.get_tuning() == dict(block_size=512, tile_records=2400, sort_interval=7,
                                    persistent=1, graph_chunk=10, halo_scale=0.5)
+    tr.set_tuning(halo_scale=0.0)   # 0 selects the default
+    assert tr.get_tuning()["halo_scale"] == 0.125
     tr.close()
 
 

@@ -326,7 +326,8 @@ def test_lds_tiles_never_change_results(precision):
     tile and with a tile too small to hold most blocks' boxes.  One inertial
     species starts ten times faster than any node, so its stage positions
     leave the tile halo and exercise the per-lane fallback to global
-    gathers; an even-sized grid and an odd one cover both index wraps; block
+    gathers; halo scales from 0.125 (one cell) to 4 (the 16-cell clamp)
+    change every block's box; an even-sized grid and an odd one cover both index wraps; block
     sizes of 64 to 512 threads change the tile fill's work split."""
     for n in (256, 200):
         say(f"lds tiles {precision} n={n}")
@@ -336,8 +337,8 @@ def test_lds_tiles_never_change_results(precision):
         # wave depend on the block's wave count, so blocks of 1, 2 and 8 waves
         # are covered too (their statistics sum in another tree: positions
         # and velocities only)
-        cases = ((-1, 1.0, 0), (0, 1.0, 0), (64, 1.0, 0), (0, 0.3, 0), (0, 1.0, 64),
-                 (0, 1.0, 128), (0, 1.0, 512))
+        cases = ((-1, 1.0, 0), (0, 1.0, 0), (64, 1.0, 0), (0, 0.3, 0), (0, 0.125, 0),
+                 (0, 4.0, 0), (0, 1.0, 64), (0, 1.0, 128), (0, 1.0, 512))
         for tile, halo, block in cases:
             tr = lpt.Tracker(n, precision, sort_interval=4, sort_tile=8 if n == 256 else 0,
                              tile_records=tile, block_size=block)
