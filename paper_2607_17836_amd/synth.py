@@ -86,6 +86,28 @@ def spectrum_snapshots(n: int, k0: float, seed: int, dt_snap: float, length: flo
     return out
 
 
+def random_vorticity(n: int, k0: float, seed: int, omega_rms: float = 1.0,
+                     length: float = TWO_PI):
+    """Random-phase initial vorticity on the grid [n, n] (indexed [j, i]).
+
+    Same isotropic energy spectrum shape as ``spectrum_snapshots``,
+    E(k) ~ k^4 exp(-(k/k0)^2), so |omega_k|^2 ~ k E(k) = k^5 exp(-(k/k0)^2)
+    in mode-index units; phases uniform from ``numpy.random.default_rng(seed)``;
+    zero mean; scaled to the requested rms.  ``length`` only enters through
+    the caller's wavenumbers, so the field is the same for every L.
+    """
+    rng = np.random.default_rng(seed)
+    my = np.fft.fftfreq(n, d=1.0 / n)[:, None]
+    mx = np.fft.rfftfreq(n, d=1.0 / n)[None, :]
+    kmag = np.sqrt(mx * mx + my * my)
+    amp = np.sqrt(kmag ** 5 * np.exp(-(kmag / k0) ** 2))
+    amp[0, 0] = 0.0
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=amp.shape)
+    w = np.fft.irfft2(amp * np.exp(1j * phase), s=(n, n))
+    w *= omega_rms / np.sqrt(np.mean(w * w))
+    return np.ascontiguousarray(w)
+
+
 def random_points(count: int, seed: int, length: float = TWO_PI):
     """Uniform random points in [0, L)^2 (numpy generator, not the method's)."""
     rng = np.random.default_rng(seed)
