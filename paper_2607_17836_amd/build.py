@@ -1,4 +1,4 @@
-"""Build liblpt.so (gfx950) in-tree with hipcc.
+"""Build liblpt.so and libns2d.so (gfx950) in-tree with hipcc.
 
     python -m paper_2607_17836_amd.build
 """
@@ -27,7 +27,25 @@ FLAGS = [
 ]
 
 
+NS_LIB = os.path.join(PKG, "libns2d.so")
+NS_SOURCES = [os.path.join(PKG, "csrc_ns", "ns2d.hip")]
+ROCM_LIB = "/opt/rocm/lib"
+
+
+def build_ns(verbose: bool = False) -> str:
+    """libns2d.so: the Eulerian field producer (hipFFT transforms)."""
+    tmp = NS_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), *NS_SOURCES,
+           "-L", ROCM_LIB, "-lhipfft", "-Wl,-rpath," + ROCM_LIB, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, NS_LIB)
+    return NS_LIB
+
+
 def build(verbose: bool = False) -> str:
+    build_ns(verbose)
     srcs = []
     for s in SOURCES:
         path = os.path.join(CSRC, s)

@@ -1,0 +1,387 @@
+// Eulerian field producer: pseudospectral vorticity-streamfunction solver of
+// Sec. 3.1 on gfx950 (C ABI in ns2d.h).
+//
+// One step, with the grid fields (u, v, dw/dx, dw/dy) of the current level
+// already resident:
+//   1. product kernel: N = u dw/dx + v dw/dy on the grid (one pass over HBM);
+//   2. hipFFT D2Z of N;
+//   3. spectral kernel, one thread per half-plane mode: the 2/3 band, the
+//      right-hand side -N - nu k^2 w (eq. spectral_vorticity_evolution), the
+//      AB2 update (eq. ab2_fluid) with the previous right-hand side kept in
+//      HBM, then the Poisson solve (eq. poisson_spectral) and the four
+//      spectral fields i k_y psi, -i k_x psi (eq. spectral_velocity),
+//      i k_x w, i k_y w (eq. spectral_vorticity_derivatives), pre-scaled by
+//      1/n^2 so that the inverse transforms come out normalised;
+//   4. one batched hipFFT Z2D of the four fields.
+// Every pointwise operation lives in the two kernels, so each step reads and
+// writes each spectral array once; the transforms are the library's.
+#include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
+
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <string>
+
+#include "ns2d.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+struct Spec {
+    int n, nh;        // grid side, half-plane width n/2 + 1
+    double kscale;    // 2 pi / L
+    double nu, dt;
+    double inv_nn;    // 1 / n^2
+    size_t plane;     // n * nh complex entries per spectral field
+};
+
+// Signed mode index of row j of a length-n transform (rows n/2 .. n-1 hold
+// the negative modes).
+__device__ __forceinline__ int signed_mode(int j, int n) { return j < n / 2 ? j : j - n; }
+
+// 2/3 rule: a mode is kept when 3|m| < n on both axes.
+__device__ __forceinline__ bool in_band(int mx, int my, int n)
+{
+    return 3 * abs(mx) < n && 3 * abs(my) < n;
+}
+
+// The four spectral fields of vorticity w at wavenumber (kx, ky), scaled by
+// 1/n^2, into the four planes of `out`.
+__device__ __forceinline__ void emit_fields(double2 *__restrict__ out, size_t idx, size_t plane,
+                                            double kx, double ky, double2 w, double s)
+{
+    const double k2 = kx * kx + ky * ky;
+    double2 p = make_double2(0.0, 0.0);
+    if (k2 > 0.0) p = make_double2(w.x / k2, w.y / k2);
+    // i a z = (-a z.y, a z.x)
+    out[idx] = make_double2(-ky * p.y * s, ky * p.x * s);                  // u  =  i k_y psi
+    out[idx + plane] = make_double2(kx * p.y * s, -kx * p.x * s);          // v  = -i k_x psi
+    out[idx + 2 * plane] = make_double2(-kx * w.y * s, kx * w.x * s);      // dw/dx
+    out[idx + 3 * plane] = make_double2(-ky * w.y * s, ky * w.x * s);      // dw/dy
+}
+
+__global__ __launch_bounds__(kBlock) void product_kernel(const double2 *__restrict__ u,
+                                                         const double2 *__restrict__ v,
+                                                         const double2 *__restrict__ wx,
+                                                         const double2 *__restrict__ wy,
+                                                         double2 *__restrict__ out, size_t count2)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count2; i += stride) {
+        const double2 a = u[i], b = v[i], c = wx[i], d = wy[i];
+        out[i] = make_double2(a.x * c.x + b.x * d.x, a.y * c.y + b.y * d.y);
+    }
+}
+
+// After the forward transform of the initial vorticity: keep the band and
+// emit the fields of that state.
+__global__ __launch_bounds__(kBlock) void init_kernel(double2 *__restrict__ w_hat,
+                                                      double2 *__restrict__ fields, Spec S)
+{
+    const int ix = blockIdx.x * kBlock + threadIdx.x, jy = blockIdx.y;
+    if (ix >= S.nh) return;
+    const size_t idx = (size_t)jy * S.nh + ix;
+    const int my = signed_mode(jy, S.n);
+    double2 w = w_hat[idx];
+    if (!in_band(ix, my, S.n)) w = make_double2(0.0, 0.0);
+    w_hat[idx] = w;
+    emit_fields(fields, idx, S.plane, S.kscale * ix, S.kscale * my, w, S.inv_nn);
+}
+
+// One AB2 step in spectral space.  Plane 0 of `fields` holds the forward
+// transform of the advection term on entry; all four planes are overwritten
+// with the new level's fields (each thread reads its entry before writing).
+template <bool FIRST>
+__global__ __launch_bounds__(kBlock) void ab2_kernel(double2 *__restrict__ w_hat,
+                                                     double2 *__restrict__ r_prev,
+                                                     double2 *__restrict__ fields, Spec S)
+{
+    const int ix = blockIdx.x * kBlock + threadIdx.x, jy = blockIdx.y;
+    if (ix >= S.nh) return;
+    const size_t idx = (size_t)jy * S.nh + ix;
+    const int my = signed_mode(jy, S.n);
+    const double kx = S.kscale * ix, ky = S.kscale * my;
+    const double k2 = kx * kx + ky * ky;
+    const double2 w = w_hat[idx];
+    double2 N = fields[idx];
+    if (!in_band(ix, my, S.n)) N = make_double2(0.0, 0.0);
+    const double visc = S.nu * k2;
+    const double2 r = make_double2(-N.x - visc * w.x, -N.y - visc * w.y);
+    const double2 r_old = FIRST ? r : r_prev[idx];
+    const double2 wn = make_double2(w.x + S.dt * (1.5 * r.x - 0.5 * r_old.x),
+                                    w.y + S.dt * (1.5 * r.y - 0.5 * r_old.y));
+    w_hat[idx] = wn;
+    r_prev[idx] = r;
+    emit_fields(fields, idx, S.plane, kx, ky, wn, S.inv_nn);
+}
+
+// omega_hat / n^2 (which = 0) or psi_hat / n^2 (which = 1) into one plane.
+__global__ __launch_bounds__(kBlock) void scaled_kernel(const double2 *__restrict__ w_hat,
+                                                        double2 *__restrict__ out, Spec S,
+                                                        int which)
+{
+    const int ix = blockIdx.x * kBlock + threadIdx.x, jy = blockIdx.y;
+    if (ix >= S.nh) return;
+    const size_t idx = (size_t)jy * S.nh + ix;
+    const int my = signed_mode(jy, S.n);
+    const double kx = S.kscale * ix, ky = S.kscale * my;
+    const double k2 = kx * kx + ky * ky;
+    double2 w = w_hat[idx];
+    if (which == 1) w = k2 > 0.0 ? make_double2(w.x / k2, w.y / k2) : make_double2(0.0, 0.0);
+    out[idx] = make_double2(w.x * S.inv_nn, w.y * S.inv_nn);
+}
+
+}  // namespace
+
+struct ns2d_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n = 0, nh = 0;
+    double L = 0, nu = 0, dt = 0;
+    double2 *w_hat = nullptr, *r_prev = nullptr, *fields = nullptr;   // fields: 4 planes
+    double *grid = nullptr;   // 4 grid fields: u, v, dw/dx, dw/dy
+    double *tmp = nullptr;    // grid scratch: advection term, read-back transforms
+    hipfftHandle r2c = 0, c2r4 = 0, c2r1 = 0;
+    bool r2c_ok = false, c2r4_ok = false, c2r1_ok = false;
+    bool have_state = false, first = true;
+    int64_t steps = 0;
+    std::string err;
+};
+
+namespace {
+
+ns2d_status fail(ns2d_ctx *c, ns2d_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+#define NS_HIP(c, expr)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail((c), NS2D_E_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+#define NS_FFT(c, expr)                                                                  \
+    do {                                                                                 \
+        hipfftResult r_ = (expr);                                                        \
+        if (r_ != HIPFFT_SUCCESS)                                                        \
+            return fail((c), NS2D_E_FFT, std::string(#expr " failed, hipfftResult ") +     \
+                                             std::to_string((int)r_));                   \
+    } while (0)
+
+Spec make_spec(const ns2d_ctx *c)
+{
+    Spec S;
+    S.n = c->n;
+    S.nh = c->nh;
+    S.kscale = 2.0 * M_PI / c->L;
+    S.nu = c->nu;
+    S.dt = c->dt;
+    S.inv_nn = 1.0 / ((double)c->n * (double)c->n);
+    S.plane = (size_t)c->n * c->nh;
+    return S;
+}
+
+dim3 spectral_grid(const ns2d_ctx *c) { return dim3((c->nh + kBlock - 1) / kBlock, c->n); }
+
+void release(ns2d_ctx *c)
+{
+    if (c->r2c_ok) hipfftDestroy(c->r2c);
+    if (c->c2r4_ok) hipfftDestroy(c->c2r4);
+    if (c->c2r1_ok) hipfftDestroy(c->c2r1);
+    if (c->w_hat) (void)hipFree(c->w_hat);
+    if (c->r_prev) (void)hipFree(c->r_prev);
+    if (c->fields) (void)hipFree(c->fields);
+    if (c->grid) (void)hipFree(c->grid);
+    if (c->tmp) (void)hipFree(c->tmp);
+}
+
+// The four spectral planes to the four grid fields.
+ns2d_status to_grid4(ns2d_ctx *c)
+{
+    NS_FFT(c, hipfftExecZ2D(c->c2r4, reinterpret_cast<hipfftDoubleComplex *>(c->fields), c->grid));
+    return NS2D_OK;
+}
+
+ns2d_status copy_out(ns2d_ctx *c, double *dst, const double *src, int32_t on_device)
+{
+    const size_t bytes = (size_t)c->n * c->n * sizeof(double);
+    NS_HIP(c, hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             c->stream));
+    return NS2D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ns2d_status ns2d_create(const ns2d_config *cfg, ns2d_ctx **out)
+{
+    if (!cfg || !out) return NS2D_E_ARG;
+    *out = nullptr;
+    const int n = cfg->n;
+    const double L = cfg->length == 0.0 ? 2.0 * M_PI : cfg->length;
+    if (n < 8 || n > 16384 || (n & 1)) return NS2D_E_ARG;
+    if (!(L > 0.0) || !std::isfinite(L)) return NS2D_E_ARG;
+    if (!(cfg->nu >= 0.0) || !std::isfinite(cfg->nu)) return NS2D_E_ARG;
+    if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) return NS2D_E_ARG;
+    ns2d_ctx *c = new (std::nothrow) ns2d_ctx;
+    if (!c) return NS2D_E_NOMEM;
+    c->n = n;
+    c->nh = n / 2 + 1;
+    c->L = L;
+    c->nu = cfg->nu;
+    c->dt = cfg->dt;
+    c->stream = reinterpret_cast<hipStream_t>(cfg->hip_stream);
+    auto bail = [&](ns2d_status s) {
+        release(c);
+        delete c;
+        return s;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(NS2D_E_HIP);
+    const size_t plane = (size_t)n * c->nh, cells = (size_t)n * n;
+    if (hipMalloc(&c->w_hat, plane * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&c->r_prev, plane * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&c->fields, 4 * plane * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&c->grid, 4 * cells * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->tmp, cells * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(NS2D_E_NOMEM);
+    }
+    int dims[2] = {n, n};
+    if (hipfftPlan2d(&c->r2c, n, n, HIPFFT_D2Z) != HIPFFT_SUCCESS) return bail(NS2D_E_FFT);
+    c->r2c_ok = true;
+    if (hipfftPlanMany(&c->c2r4, 2, dims, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_Z2D, 4) != HIPFFT_SUCCESS)
+        return bail(NS2D_E_FFT);
+    c->c2r4_ok = true;
+    if (hipfftPlan2d(&c->c2r1, n, n, HIPFFT_Z2D) != HIPFFT_SUCCESS) return bail(NS2D_E_FFT);
+    c->c2r1_ok = true;
+    if (hipfftSetStream(c->r2c, c->stream) != HIPFFT_SUCCESS ||
+        hipfftSetStream(c->c2r4, c->stream) != HIPFFT_SUCCESS ||
+        hipfftSetStream(c->c2r1, c->stream) != HIPFFT_SUCCESS)
+        return bail(NS2D_E_FFT);
+    *out = c;
+    return NS2D_OK;
+}
+
+void ns2d_destroy(ns2d_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    release(ctx);
+    delete ctx;
+}
+
+const char *ns2d_last_error(const ns2d_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+ns2d_status ns2d_synchronize(ns2d_ctx *c)
+{
+    if (!c) return NS2D_E_ARG;
+    NS_HIP(c, hipSetDevice(c->device));
+    NS_HIP(c, hipStreamSynchronize(c->stream));
+    return NS2D_OK;
+}
+
+ns2d_status ns2d_set_vorticity(ns2d_ctx *c, const double *omega, int32_t on_device)
+{
+    if (!c) return NS2D_E_ARG;
+    if (!omega) return fail(c, NS2D_E_ARG, "omega is NULL");
+    if (on_device != 0 && on_device != 1) return fail(c, NS2D_E_ARG, "on_device is 0 or 1");
+    NS_HIP(c, hipSetDevice(c->device));
+    const size_t bytes = (size_t)c->n * c->n * sizeof(double);
+    NS_HIP(c, hipMemcpyAsync(c->tmp, omega, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             c->stream));
+    NS_FFT(c, hipfftExecD2Z(c->r2c, c->tmp, reinterpret_cast<hipfftDoubleComplex *>(c->w_hat)));
+    const Spec S = make_spec(c);
+    init_kernel<<<spectral_grid(c), kBlock, 0, c->stream>>>(c->w_hat, c->fields, S);
+    NS_HIP(c, hipGetLastError());
+    const ns2d_status st = to_grid4(c);
+    if (st != NS2D_OK) return st;
+    if (!on_device) NS_HIP(c, hipStreamSynchronize(c->stream));   // host buffer read before return
+    c->have_state = true;
+    c->first = true;
+    c->steps = 0;
+    return NS2D_OK;
+}
+
+ns2d_status ns2d_step(ns2d_ctx *c, int32_t count)
+{
+    if (!c) return NS2D_E_ARG;
+    if (count < 0) return fail(c, NS2D_E_ARG, "count must be >= 0");
+    if (!c->have_state) return fail(c, NS2D_E_STATE, "ns2d_set_vorticity has not been called");
+    NS_HIP(c, hipSetDevice(c->device));
+    const Spec S = make_spec(c);
+    const size_t cells = (size_t)c->n * c->n, count2 = cells / 2;
+    const double2 *g = reinterpret_cast<const double2 *>(c->grid);
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    const size_t want = (count2 + kBlock - 1) / kBlock;
+    const unsigned pgrid = (unsigned)(want < (size_t)cus * 16 ? want : (size_t)cus * 16);
+    for (int32_t s = 0; s < count; ++s) {
+        product_kernel<<<pgrid, kBlock, 0, c->stream>>>(g, g + count2, g + 2 * count2, g + 3 * count2,
+                                                        reinterpret_cast<double2 *>(c->tmp), count2);
+        NS_HIP(c, hipGetLastError());
+        NS_FFT(c, hipfftExecD2Z(c->r2c, c->tmp, reinterpret_cast<hipfftDoubleComplex *>(c->fields)));
+        if (c->first)
+            ab2_kernel<true><<<spectral_grid(c), kBlock, 0, c->stream>>>(c->w_hat, c->r_prev, c->fields, S);
+        else
+            ab2_kernel<false><<<spectral_grid(c), kBlock, 0, c->stream>>>(c->w_hat, c->r_prev, c->fields, S);
+        NS_HIP(c, hipGetLastError());
+        const ns2d_status st = to_grid4(c);
+        if (st != NS2D_OK) return st;
+        c->first = false;
+        ++c->steps;
+    }
+    return NS2D_OK;
+}
+
+ns2d_status ns2d_velocity(ns2d_ctx *c, const double **u, const double **v)
+{
+    if (!c) return NS2D_E_ARG;
+    if (!u || !v) return fail(c, NS2D_E_ARG, "u and v must not be NULL");
+    if (!c->have_state) return fail(c, NS2D_E_STATE, "ns2d_set_vorticity has not been called");
+    const size_t cells = (size_t)c->n * c->n;
+    *u = c->grid;
+    *v = c->grid + cells;
+    return NS2D_OK;
+}
+
+ns2d_status ns2d_get_fields(ns2d_ctx *c, double *u, double *v, double *omega, double *psi,
+                            int32_t on_device)
+{
+    if (!c) return NS2D_E_ARG;
+    if (on_device != 0 && on_device != 1) return fail(c, NS2D_E_ARG, "on_device is 0 or 1");
+    if (!c->have_state) return fail(c, NS2D_E_STATE, "ns2d_set_vorticity has not been called");
+    NS_HIP(c, hipSetDevice(c->device));
+    const size_t cells = (size_t)c->n * c->n;
+    ns2d_status st;
+    if (u && (st = copy_out(c, u, c->grid, on_device)) != NS2D_OK) return st;
+    if (v && (st = copy_out(c, v, c->grid + cells, on_device)) != NS2D_OK) return st;
+    const Spec S = make_spec(c);
+    double *outs[2] = {omega, psi};
+    for (int which = 0; which < 2; ++which) {
+        if (!outs[which]) continue;
+        // plane 0 of the spectral fields is free between steps (the next
+        // step's forward transform rewrites it before it is read)
+        scaled_kernel<<<spectral_grid(c), kBlock, 0, c->stream>>>(c->w_hat, c->fields, S, which);
+        NS_HIP(c, hipGetLastError());
+        NS_FFT(c, hipfftExecZ2D(c->c2r1, reinterpret_cast<hipfftDoubleComplex *>(c->fields), c->tmp));
+        if ((st = copy_out(c, outs[which], c->tmp, on_device)) != NS2D_OK) return st;
+    }
+    if (!on_device) NS_HIP(c, hipStreamSynchronize(c->stream));
+    return NS2D_OK;
+}
+
+ns2d_status ns2d_get_steps(const ns2d_ctx *c, int64_t *steps)
+{
+    if (!c || !steps) return NS2D_E_ARG;
+    *steps = c->steps;
+    return NS2D_OK;
+}
+
+}  // extern "C"

@@ -201,6 +201,12 @@ class Tracker:
         assert du == dv
         self._check(load().lpt_set_snapshot(self._h, slot, t, pu, pv, du))
 
+    def set_snapshot_device(self, slot, t, u_ptr, v_ptr):
+        """Velocity level from raw device pointers of n*n doubles each (for
+        instance the field producer's ns2d_velocity), read in stream order."""
+        assert u_ptr and v_ptr
+        self._check(load().lpt_set_snapshot(self._h, slot, t, u_ptr, v_ptr, 1))
+
     def set_snapshot_psi(self, slot, t, psi):
         p, d, k = _arr(psi, self.n * self.n)
         self._check(load().lpt_set_snapshot_psi(self._h, slot, t, p, d))
