@@ -16,8 +16,9 @@ Other workloads (--workload): spec4096_split_share8 (the headline with 2^21
 tracers: one GPU's share on eight, same full field), batch2048 (8
 Stokes-number species, all three schemes, one launch per species, autotuned
 launch shape), spec1024_fp64 (FP64 tracers + inertial particles, --scheme),
-tg64 (FP64 Taylor-Green, 4096 tracers) and adjoint2048 (FP64 checkpointed
-forward run plus reverse sweep with grid gradients).
+tg64 (FP64 Taylor-Green, 4096 tracers), adjoint2048 (FP64 checkpointed
+forward run plus reverse sweep with grid gradients) and ns2048 (the Eulerian
+field producer: one pseudospectral AB2 vorticity step on a 2048^2 FP64 grid).
 
 Prints one JSON line.  The roofline object reports the dominant kernel's (the
 in-place step kernel's) algorithmic bytes per launch over its average
@@ -286,6 +287,72 @@ def bench_adjoint(args, lpt):
     return value, 1e3 * (t_fwd + t_adj) / nsteps, cfg, roof
 
 
+NS_N, NS_NU, NS_DT, NS_K0, NS_RMS, NS_SEED = 2048, 1e-4, 1e-3, 10.0, 10.0, 61
+
+
+def ns_alg_bytes_per_step(n: int) -> int:
+    """HBM bytes one field step must move at least: the grid product reads
+    four grid fields and writes one; the forward transform reads a grid
+    field and writes a half spectrum; the spectral kernel reads the state,
+    the previous right-hand side and the transformed product and writes the
+    state, the right-hand side and four spectral fields; the four inverse
+    transforms each read a half spectrum and write a grid field."""
+    spec = n * (n // 2 + 1) * 16
+    grid = n * n * 8
+    return 5 * grid + (grid + spec) + 9 * spec + 4 * (spec + grid)
+
+
+def bench_ns(args):
+    """The Eulerian field producer on the 2048^2 grid in FP64: random-phase
+    initial vorticity (k0 = 10, rms 10), nu = 1e-4, dt = 1e-3; one step =
+    product kernel, forward transform, spectral AB2 kernel, four inverse
+    transforms.  HIP events on the null stream, which the producer runs on."""
+    import torch
+    from paper_2607_17836_amd import ns2d, synth
+    n = NS_N
+    g = ns2d.Ns2d(n, NS_NU, NS_DT)
+    g.set_vorticity(synth.random_vorticity(n, NS_K0, NS_SEED, omega_rms=NS_RMS))
+    g.step(args.warmup)
+    g.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    g.step(args.steps)
+    e1.record()
+    g.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    g.close()
+    step_us = 1e3 * ev_ms / args.steps
+    ab = ns_alg_bytes_per_step(n)
+    log(f"[bench] ns2048: {args.steps} steps in {wall:.3f} s; {step_us:.1f} us per step by events")
+    cfg = {"workload": "ns2048_fp64_ab2_vorticity", "grid": n, "nu": NS_NU, "dt": NS_DT,
+           "k0": NS_K0, "omega_rms": NS_RMS, "precision": "fp64", "parallelism": "1 GPU"}
+    roof = {"bound": "hbm", "achieved": ab / (step_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": ab / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "whole field step: product + D2Z + spectral AB2 + batched Z2D (4 fields)",
+            "kernel_avg_us": step_us, "alg_bytes_per_step": ab}
+    return args.steps / wall, 1e3 * wall / args.steps, cfg, roof
+
+
+def cpu_baseline_ns(budget_steps=3):
+    """The field oracle (numpy FFT, single-threaded) on the same 2048^2
+    workload: `budget_steps` steps after the forward-Euler first step."""
+    from oracle.ns2d import NS2D
+    from paper_2607_17836_amd import synth
+    o = NS2D(NS_N, NS_NU, NS_DT)
+    o.set_vorticity(synth.random_vorticity(NS_N, NS_K0, NS_SEED, omega_rms=NS_RMS))
+    o.step(1)
+    t0 = time.perf_counter()
+    o.step(budget_steps)
+    el = time.perf_counter() - t0
+    return {"value": budget_steps / el, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{budget_steps} AB2 steps of the same 2048^2 FP64 workload, {el:.1f} s, "
+                      f"numpy pocketfft (single-threaded)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,7 +361,7 @@ def main():
     ap.add_argument("--workload", default="spec4096_split",
                     choices=["spec4096_split", "spec4096_split_share8", "batch2048",
                              "spec1024_fp64", "tg64",
-                             "adjoint2048"])
+                             "adjoint2048", "ns2048"])
     ap.add_argument("--scheme", default="bilinear", choices=["bilinear", "catmull_rom", "bspline"],
                     help="scheme of the spec1024_fp64 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -327,7 +394,15 @@ def main():
     dtype = "f32"
     metric = METRIC
     w = None
-    if args.workload == "adjoint2048":
+    unit = "particle-steps/s"
+    if args.workload == "ns2048":
+        value, ms_per_step, cfg, roof = bench_ns(args)
+        dtype = "f64"
+        unit = "steps/s"
+        metric = "field steps/s (pseudospectral AB2 vorticity step), 2048^2 FP64"
+        if not args.no_cpu_baseline:
+            extra["cpu_baseline"] = cpu_baseline_ns()
+    elif args.workload == "adjoint2048":
         value, ms_per_step, cfg, roof = bench_adjoint(args, lpt)
         dtype = "f64"
         metric = "particle-steps/s (checkpointed forward + reverse sweep with grid gradient)"
@@ -369,7 +444,7 @@ def main():
     roof["achievable_triad_gbps"] = triad_gbs
     roof["frac_of_copy"] = roof["achieved"] / copy_gbs
     out = {
-        "metric": metric, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+        "metric": metric, "value": value, "unit": unit, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
         "data": "synthetic", "config": cfg, "roofline": roof,

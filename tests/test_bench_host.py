@@ -27,3 +27,13 @@ def test_multi_gpu_request_exits_with_a_message():
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_field_step_algorithmic_bytes():
+    """One field step moves 192 n^2 bytes plus the half spectrum's extra
+    column: 40 n^2 for the grid product, 16 n^2 for the forward transform,
+    72 n^2 for the spectral kernel and 64 n^2 for the four inverse ones."""
+    import bench
+    n = 2048
+    extra = 16 * n * (1 + 9 + 4)   # the column m_x = n/2: n complex doubles per spectral pass
+    assert bench.ns_alg_bytes_per_step(n) == 192 * n * n + extra
