@@ -67,12 +67,18 @@ typedef struct {
     double nu;          /* kinematic viscosity >= 0                             */
     double dt;          /* time step > 0                                        */
     void *hip_stream;   /* hipStream_t to enqueue on; NULL = null stream        */
+    int32_t transforms; /* 0: the library's own LDS transforms, fused with the
+                           pointwise work, for n = 1024 and 2048 (where they
+                           are faster), hipFFT for every other n; 1: hipFFT
+                           for every n; 2: the library's own transforms, for
+                           n = 512, 1024 or 2048 only (else NS2D_E_ARG)     */
 } ns2d_config;
 
 /* Create a context on the current HIP device: allocates the spectral state,
  * the AB2 history, four spectral and five grid work fields (about 11 n^2
- * doubles in total, 1.5 GB at n = 4096, plus the transform work areas) and
- * the three transform plans.  NS2D_E_ARG for a size outside the limits. */
+ * doubles in total, 1.5 GB at n = 4096) and either the twiddle table of the
+ * built-in transforms or the three hipFFT plans and their work areas.
+ * NS2D_E_ARG for a size or option outside the limits. */
 ns2d_status ns2d_create(const ns2d_config *cfg, ns2d_ctx **out);
 /* Release every resource of the context (NULL is a no-op). */
 void ns2d_destroy(ns2d_ctx *ctx);
@@ -100,6 +106,9 @@ ns2d_status ns2d_velocity(ns2d_ctx *ctx, const double **u, const double **v);
  * velocity (u, v), vorticity and stream function.  Any pointer may be NULL. */
 ns2d_status ns2d_get_fields(ns2d_ctx *ctx, double *u, double *v, double *omega, double *psi,
                             int32_t on_device);
+
+/* *builtin = 1 when the context uses its own transforms, 0 for hipFFT. */
+ns2d_status ns2d_get_transforms(const ns2d_ctx *ctx, int32_t *builtin);
 
 /* Steps taken since the last ns2d_set_vorticity. */
 ns2d_status ns2d_get_steps(const ns2d_ctx *ctx, int64_t *steps);

@@ -14,7 +14,21 @@
 //      1/n^2 so that the inverse transforms come out normalised;
 //   4. one batched hipFFT Z2D of the four fields.
 // Every pointwise operation lives in the two kernels, so each step reads and
-// writes each spectral array once; the transforms are the library's.
+// writes each spectral array once.
+//
+// For n = 1024 and 2048 (and 512 on request) the built-in transforms
+// (fft_lds.h) replace the library's and fuse with the pointwise work, in three kernels a step over a
+// transposed spectral layout (entry (row jy, column ix) of a half-plane
+// spectrum at ix * n + jy, so that every column is contiguous):
+//   a. fwd_rows_kernel: the grid product of four rows, two real rows packed
+//      into one complex transform along x, unpacked into two half spectra;
+//   b. column_kernel: per column, the transform along y, the band, the AB2
+//      update, then for each of the four fields its values and the inverse
+//      transform along y, all in LDS;
+//   c. inv_rows_kernel: two rows of each field packed into one complex
+//      inverse transform along x (Hermitian extension), written as grid rows.
+// Each spectral array is read and written once per step and the grid
+// advection term never reaches HBM.
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
 
@@ -22,7 +36,9 @@
 #include <cstdio>
 #include <new>
 #include <string>
+#include <vector>
 
+#include "fft_lds.h"
 #include "ns2d.h"
 
 namespace {
@@ -133,6 +149,188 @@ __global__ __launch_bounds__(kBlock) void scaled_kernel(const double2 *__restric
     out[idx] = make_double2(w.x * S.inv_nn, w.y * S.inv_nn);
 }
 
+// ---- built-in transform path (n = 512, 1024, 2048) ------------------------
+
+constexpr int kRowsPerBlock = 4;   // grid rows per row-pass block: two packed pairs
+
+// Columns ix = 0 .. band_cols(N) - 1 are the ones with 3 ix < N.  Every other
+// column of the band-limited state, of the four fields and of the read-back
+// fields is zero, so the built-in path neither transforms nor stores it:
+// the row passes skip it and the inverse row pass supplies the zeros.
+constexpr int band_cols(int N) { return (N - 1) / 3 + 1; }
+
+// Rows 4b .. 4b+3 of the advection term (PRODUCT: u dw/dx + v dw/dy from the
+// four grid fields at g) or of one grid field (g), transformed along x:
+// rows (a, b) form z = a + i b, Z = FFT(z), and the half spectra are
+// A(k) = (Z(k) + conj Z(-k)) / 2, B(k) = (Z(k) - conj Z(-k)) / (2i).
+template <int N, bool PRODUCT>
+__global__ __launch_bounds__(N / 8) void fwd_rows_kernel(const double *__restrict__ g,
+                                                        double2 *__restrict__ specT,
+                                                        const double2 *__restrict__ W)
+{
+    extern __shared__ double2 lds_rows[];   // two packed rows of N entries
+    constexpr int T = N / 8;
+    constexpr size_t cells = (size_t)N * N;
+    const int jy0 = blockIdx.x * kRowsPerBlock;
+    for (int p = 0; p < 2; ++p) {
+        double2 *buf = lds_rows + p * N;
+        const double *ra = g + (size_t)(jy0 + 2 * p) * N;
+        const double *rb = ra + N;
+        for (int x = threadIdx.x; x < N; x += T) {
+            double a, b;
+            if constexpr (PRODUCT) {
+                a = ra[x] * ra[x + 2 * cells] + ra[x + cells] * ra[x + 3 * cells];
+                b = rb[x] * rb[x + 2 * cells] + rb[x + cells] * rb[x + 3 * cells];
+            } else {
+                a = ra[x];
+                b = rb[x];
+            }
+            buf[x] = make_double2(a, b);
+        }
+    }
+    __syncthreads();
+    ns_fft::fft<N, false>(lds_rows, W);
+    ns_fft::fft<N, false>(lds_rows + N, W);
+    constexpr int KB = band_cols(N);
+    for (int e = threadIdx.x; e < 2 * KB; e += T) {
+        const int k = e >> 1, p = e & 1;
+        const double2 *buf = lds_rows + p * N;
+        const double2 z = buf[k], zc = buf[(N - k) & (N - 1)];
+        double2 *dst = specT + (size_t)k * N + jy0 + 2 * p;
+        dst[0] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+        dst[1] = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+    }
+}
+
+enum ColumnMode { kColInit = 0, kColFirst = 1, kColStep = 2, kColReadW = 3, kColReadPsi = 4 };
+
+// Column ix < band_cols(N) of the transposed spectra, one block per column.
+// Init and step modes transform plane 0 of `fields` (the x-transformed rows)
+// along y, take the band, store the state (init) or apply AB2 (step), then
+// emit the four fields, each transformed back along y into its plane.
+// Read-back modes emit omega / n^2 or psi / n^2 into plane 0.  Plane 0's
+// column is read whole into LDS before it is written.
+template <int N, int MODE>
+__global__ __launch_bounds__(N / 8) void column_kernel(double2 *__restrict__ w_hat,
+                                                      double2 *__restrict__ r_prev,
+                                                      double2 *__restrict__ fields, Spec S,
+                                                      const double2 *__restrict__ W)
+{
+    extern __shared__ double2 lds_col[];   // N transform entries, then N state entries
+    double2 *wn = lds_col + N;             // the column's new state, kept for the emits
+    constexpr int T = N / 8;
+    const int ix = blockIdx.x, t = threadIdx.x;
+    const size_t col = (size_t)ix * N;
+    const double kx = S.kscale * ix;
+    if constexpr (MODE <= kColStep) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) lds_col[t + q * T] = fields[col + t + q * T];
+        __syncthreads();
+        ns_fft::fft<N, false>(lds_col, W);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int jy = t + q * T;
+        const size_t idx = col + jy;
+        const int my = signed_mode(jy, N);
+        if constexpr (MODE == kColInit) {
+            const double2 w = in_band(ix, my, N) ? lds_col[jy] : make_double2(0.0, 0.0);
+            w_hat[idx] = w;
+            wn[jy] = w;
+        } else if constexpr (MODE == kColFirst || MODE == kColStep) {
+            const double ky = S.kscale * my;
+            const double visc = S.nu * (kx * kx + ky * ky);
+            const double2 Nh = in_band(ix, my, N) ? lds_col[jy] : make_double2(0.0, 0.0);
+            const double2 w = w_hat[idx];
+            const double2 r = make_double2(-Nh.x - visc * w.x, -Nh.y - visc * w.y);
+            const double2 r_old = MODE == kColFirst ? r : r_prev[idx];
+            wn[jy] = make_double2(w.x + S.dt * (1.5 * r.x - 0.5 * r_old.x),
+                                 w.y + S.dt * (1.5 * r.y - 0.5 * r_old.y));
+            w_hat[idx] = wn[jy];
+            r_prev[idx] = r;
+        } else {
+            wn[jy] = w_hat[idx];
+        }
+    }
+    constexpr int nf = MODE >= kColReadW ? 1 : 4;
+    const double s = S.inv_nn;
+    for (int f = 0; f < nf; ++f) {
+        __syncthreads();   // the previous contents of lds_col are consumed
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int jy = t + q * T;
+            const double ky = S.kscale * signed_mode(jy, N);
+            const double k2 = kx * kx + ky * ky;
+            const double2 w = wn[jy];
+            double2 p = make_double2(0.0, 0.0);
+            if (k2 > 0.0) p = make_double2(w.x / k2, w.y / k2);
+            double2 v;
+            if constexpr (MODE == kColReadW) v = make_double2(w.x * s, w.y * s);
+            else if constexpr (MODE == kColReadPsi) v = make_double2(p.x * s, p.y * s);
+            else if (f == 0) v = make_double2(-ky * p.y * s, ky * p.x * s);    // u  =  i k_y psi
+            else if (f == 1) v = make_double2(kx * p.y * s, -kx * p.x * s);    // v  = -i k_x psi
+            else if (f == 2) v = make_double2(-kx * w.y * s, kx * w.x * s);    // dw/dx
+            else v = make_double2(-ky * w.y * s, ky * w.x * s);                // dw/dy
+            lds_col[jy] = v;
+        }
+        __syncthreads();
+        ns_fft::fft<N, true>(lds_col, W);
+        double2 *dst = fields + (size_t)f * S.plane + col;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dst[t + q * T] = lds_col[t + q * T];
+    }
+}
+
+// Rows 4b .. 4b+3 of nf fields (planes of the transposed spectra, already
+// transformed along y) back to the grid: rows (a, b) of a field form
+// Z(k) = A(k) + i B(k) and Z(N-k) = conj A(k) + i conj B(k) for the band
+// columns k < KB (the imaginary parts at k = 0 dropped as in any
+// complex-to-real transform) and zero elsewhere; z = IFFT(Z) gives a = Re z,
+// b = Im z.
+template <int N>
+__global__ __launch_bounds__(N / 8) void inv_rows_kernel(const double2 *__restrict__ fields,
+                                                        double *__restrict__ grid, int nf,
+                                                        size_t plane,
+                                                        const double2 *__restrict__ W)
+{
+    extern __shared__ double2 lds_rows[];   // two packed rows of N entries
+    constexpr int T = N / 8, KB = band_cols(N);
+    constexpr size_t cells = (size_t)N * N;
+    const int jy0 = blockIdx.x * kRowsPerBlock;
+    for (int f = 0; f < nf; ++f) {
+        const double2 *src = fields + (size_t)f * plane;
+        for (int e = threadIdx.x; e < 2 * KB; e += T) {
+            const int k = e >> 1, p = e & 1;
+            const double2 *sp = src + (size_t)k * N + jy0 + 2 * p;
+            double2 A = sp[0], B = sp[1];
+            if (k == 0) {
+                A.y = 0.0;
+                B.y = 0.0;
+            }
+            double2 *buf = lds_rows + p * N;
+            buf[k] = make_double2(A.x - B.y, A.y + B.x);
+            if (k > 0) buf[N - k] = make_double2(A.x + B.y, B.x - A.y);
+        }
+        // columns KB .. N/2 and their mirrors N/2 .. N-KB are zero
+        for (int x = KB + threadIdx.x; x <= N - KB; x += T) {
+            lds_rows[x] = make_double2(0.0, 0.0);
+            lds_rows[N + x] = make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        ns_fft::fft<N, true>(lds_rows, W);
+        ns_fft::fft<N, true>(lds_rows + N, W);
+        for (int p = 0; p < 2; ++p) {
+            double *ra = grid + (size_t)f * cells + (size_t)(jy0 + 2 * p) * N;
+            for (int x = threadIdx.x; x < N; x += T) {
+                const double2 z = lds_rows[p * N + x];
+                ra[x] = z.x;
+                ra[x + N] = z.y;
+            }
+        }
+        __syncthreads();   // lds_rows is refilled for the next field
+    }
+}
+
 }  // namespace
 
 struct ns2d_ctx {
@@ -145,6 +343,8 @@ struct ns2d_ctx {
     double *tmp = nullptr;    // grid scratch: advection term, read-back transforms
     hipfftHandle r2c = 0, c2r4 = 0, c2r1 = 0;
     bool r2c_ok = false, c2r4_ok = false, c2r1_ok = false;
+    bool builtin = false;        // built-in transforms, transposed spectral layout
+    double2 *twiddle = nullptr;  // exp(-2 pi i m / n), m < n (built-in path)
     bool have_state = false, first = true;
     int64_t steps = 0;
     std::string err;
@@ -198,6 +398,54 @@ void release(ns2d_ctx *c)
     if (c->fields) (void)hipFree(c->fields);
     if (c->grid) (void)hipFree(c->grid);
     if (c->tmp) (void)hipFree(c->tmp);
+    if (c->twiddle) (void)hipFree(c->twiddle);
+}
+
+enum BuiltinOp { kOpInit, kOpStep, kOpReadW, kOpReadPsi };
+
+template <int N>
+ns2d_status run_builtin_n(ns2d_ctx *c, BuiltinOp op)
+{
+    constexpr int T = N / 8;
+    const size_t rows_lds = 2 * (size_t)N * sizeof(double2), col_lds = rows_lds;
+    const dim3 rows_grid(N / kRowsPerBlock), col_grid(band_cols(N));
+    const Spec S = make_spec(c);
+    hipStream_t st = c->stream;
+    switch (op) {
+    case kOpInit:
+        fwd_rows_kernel<N, false><<<rows_grid, T, rows_lds, st>>>(c->tmp, c->fields, c->twiddle);
+        column_kernel<N, kColInit><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, c->twiddle);
+        inv_rows_kernel<N><<<rows_grid, T, rows_lds, st>>>(c->fields, c->grid, 4, S.plane, c->twiddle);
+        break;
+    case kOpStep:
+        fwd_rows_kernel<N, true><<<rows_grid, T, rows_lds, st>>>(c->grid, c->fields, c->twiddle);
+        if (c->first)
+            column_kernel<N, kColFirst><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, c->twiddle);
+        else
+            column_kernel<N, kColStep><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, c->twiddle);
+        inv_rows_kernel<N><<<rows_grid, T, rows_lds, st>>>(c->fields, c->grid, 4, S.plane, c->twiddle);
+        break;
+    case kOpReadW:
+    case kOpReadPsi:
+        if (op == kOpReadW)
+            column_kernel<N, kColReadW><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, c->twiddle);
+        else
+            column_kernel<N, kColReadPsi><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, c->twiddle);
+        inv_rows_kernel<N><<<rows_grid, T, rows_lds, st>>>(c->fields, c->tmp, 1, S.plane, c->twiddle);
+        break;
+    }
+    NS_HIP(c, hipGetLastError());
+    return NS2D_OK;
+}
+
+ns2d_status run_builtin(ns2d_ctx *c, BuiltinOp op)
+{
+    switch (c->n) {
+    case 512: return run_builtin_n<512>(c, op);
+    case 1024: return run_builtin_n<1024>(c, op);
+    case 2048: return run_builtin_n<2048>(c, op);
+    default: return fail(c, NS2D_E_STATE, "no built-in transform for this n");
+    }
 }
 
 // The four spectral planes to the four grid fields.
@@ -229,6 +477,8 @@ ns2d_status ns2d_create(const ns2d_config *cfg, ns2d_ctx **out)
     if (!(L > 0.0) || !std::isfinite(L)) return NS2D_E_ARG;
     if (!(cfg->nu >= 0.0) || !std::isfinite(cfg->nu)) return NS2D_E_ARG;
     if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) return NS2D_E_ARG;
+    if (cfg->transforms < 0 || cfg->transforms > 2) return NS2D_E_ARG;
+    if (cfg->transforms == 2 && n != 512 && n != 1024 && n != 2048) return NS2D_E_ARG;
     ns2d_ctx *c = new (std::nothrow) ns2d_ctx;
     if (!c) return NS2D_E_NOMEM;
     c->n = n;
@@ -251,6 +501,26 @@ ns2d_status ns2d_create(const ns2d_config *cfg, ns2d_ctx **out)
         hipMalloc(&c->tmp, cells * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         return bail(NS2D_E_NOMEM);
+    }
+    // measured: the built-in path is faster from n = 1024 on; at 512 its
+    // n / 4 row blocks and n / 2 + 1 column blocks of n / 8 threads leave the
+    // chip under-filled and hipFFT wins
+    c->builtin = cfg->transforms == 2 || (cfg->transforms == 0 && (n == 1024 || n == 2048));
+    if (c->builtin) {
+        // twiddles from the long-double cosine and sine, rounded once
+        std::vector<double2> w(n);
+        for (int m = 0; m < n; ++m) {
+            const long double a = 2.0L * 3.14159265358979323846264338327950288L * m / n;
+            w[m] = make_double2((double)cosl(a), (double)-sinl(a));
+        }
+        if (hipMalloc(&c->twiddle, n * sizeof(double2)) != hipSuccess) {
+            (void)hipGetLastError();
+            return bail(NS2D_E_NOMEM);
+        }
+        if (hipMemcpy(c->twiddle, w.data(), n * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(NS2D_E_HIP);
+        *out = c;
+        return NS2D_OK;
     }
     int dims[2] = {n, n};
     if (hipfftPlan2d(&c->r2c, n, n, HIPFFT_D2Z) != HIPFFT_SUCCESS) return bail(NS2D_E_FFT);
@@ -296,12 +566,17 @@ ns2d_status ns2d_set_vorticity(ns2d_ctx *c, const double *omega, int32_t on_devi
     const size_t bytes = (size_t)c->n * c->n * sizeof(double);
     NS_HIP(c, hipMemcpyAsync(c->tmp, omega, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                              c->stream));
-    NS_FFT(c, hipfftExecD2Z(c->r2c, c->tmp, reinterpret_cast<hipfftDoubleComplex *>(c->w_hat)));
-    const Spec S = make_spec(c);
-    init_kernel<<<spectral_grid(c), kBlock, 0, c->stream>>>(c->w_hat, c->fields, S);
-    NS_HIP(c, hipGetLastError());
-    const ns2d_status st = to_grid4(c);
-    if (st != NS2D_OK) return st;
+    if (c->builtin) {
+        const ns2d_status st = run_builtin(c, kOpInit);
+        if (st != NS2D_OK) return st;
+    } else {
+        NS_FFT(c, hipfftExecD2Z(c->r2c, c->tmp, reinterpret_cast<hipfftDoubleComplex *>(c->w_hat)));
+        const Spec S = make_spec(c);
+        init_kernel<<<spectral_grid(c), kBlock, 0, c->stream>>>(c->w_hat, c->fields, S);
+        NS_HIP(c, hipGetLastError());
+        const ns2d_status st = to_grid4(c);
+        if (st != NS2D_OK) return st;
+    }
     if (!on_device) NS_HIP(c, hipStreamSynchronize(c->stream));   // host buffer read before return
     c->have_state = true;
     c->first = true;
@@ -322,6 +597,15 @@ ns2d_status ns2d_step(ns2d_ctx *c, int32_t count)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     const size_t want = (count2 + kBlock - 1) / kBlock;
     const unsigned pgrid = (unsigned)(want < (size_t)cus * 16 ? want : (size_t)cus * 16);
+    if (c->builtin) {
+        for (int32_t s = 0; s < count; ++s) {
+            const ns2d_status st = run_builtin(c, kOpStep);
+            if (st != NS2D_OK) return st;
+            c->first = false;
+            ++c->steps;
+        }
+        return NS2D_OK;
+    }
     for (int32_t s = 0; s < count; ++s) {
         product_kernel<<<pgrid, kBlock, 0, c->stream>>>(g, g + count2, g + 2 * count2, g + 3 * count2,
                                                         reinterpret_cast<double2 *>(c->tmp), count2);
@@ -368,12 +652,23 @@ ns2d_status ns2d_get_fields(ns2d_ctx *c, double *u, double *v, double *omega, do
         if (!outs[which]) continue;
         // plane 0 of the spectral fields is free between steps (the next
         // step's forward transform rewrites it before it is read)
-        scaled_kernel<<<spectral_grid(c), kBlock, 0, c->stream>>>(c->w_hat, c->fields, S, which);
-        NS_HIP(c, hipGetLastError());
-        NS_FFT(c, hipfftExecZ2D(c->c2r1, reinterpret_cast<hipfftDoubleComplex *>(c->fields), c->tmp));
+        if (c->builtin) {
+            if ((st = run_builtin(c, which == 0 ? kOpReadW : kOpReadPsi)) != NS2D_OK) return st;
+        } else {
+            scaled_kernel<<<spectral_grid(c), kBlock, 0, c->stream>>>(c->w_hat, c->fields, S, which);
+            NS_HIP(c, hipGetLastError());
+            NS_FFT(c, hipfftExecZ2D(c->c2r1, reinterpret_cast<hipfftDoubleComplex *>(c->fields), c->tmp));
+        }
         if ((st = copy_out(c, outs[which], c->tmp, on_device)) != NS2D_OK) return st;
     }
     if (!on_device) NS_HIP(c, hipStreamSynchronize(c->stream));
+    return NS2D_OK;
+}
+
+ns2d_status ns2d_get_transforms(const ns2d_ctx *c, int32_t *builtin)
+{
+    if (!c || !builtin) return NS2D_E_ARG;
+    *builtin = c->builtin ? 1 : 0;
     return NS2D_OK;
 }
 

@@ -25,7 +25,7 @@ OK, E_ARG, E_STATE, E_NOMEM, E_HIP, E_FFT = 0, 1, 2, 4, 5, 6
 
 class Ns2dConfig(C.Structure):
     _fields_ = [("n", C.c_int32), ("length", C.c_double), ("nu", C.c_double),
-                ("dt", C.c_double), ("hip_stream", C.c_void_p)]
+                ("dt", C.c_double), ("hip_stream", C.c_void_p), ("transforms", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -38,6 +38,7 @@ _SIGS = [
     ("ns2d_step", C.c_int, [_P, C.c_int32]),
     ("ns2d_velocity", C.c_int, [_P, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     ("ns2d_get_fields", C.c_int, [_P, _P, _P, _P, _P, C.c_int32]),
+    ("ns2d_get_transforms", C.c_int, [_P, C.POINTER(C.c_int32)]),
     ("ns2d_get_steps", C.c_int, [_P, C.POINTER(C.c_int64)]),
 ]
 
@@ -69,8 +70,11 @@ class Ns2dError(RuntimeError):
 class Ns2d:
     """One libns2d context (see include/ns2d.h for every call)."""
 
-    def __init__(self, n, nu, dt, length=0.0, stream=None):
-        cfg = Ns2dConfig(n=n, length=length, nu=nu, dt=dt, hip_stream=stream)
+    def __init__(self, n, nu, dt, length=0.0, stream=None, transforms="auto"):
+        """transforms: "auto" (the library's own for n = 1024 and 2048,
+        hipFFT otherwise), "hipfft", or "builtin" (n = 512, 1024, 2048)."""
+        cfg = Ns2dConfig(n=n, length=length, nu=nu, dt=dt, hip_stream=stream,
+                         transforms={"auto": 0, "hipfft": 1, "builtin": 2}[transforms])
         h = C.c_void_p()
         st = load().ns2d_create(C.byref(cfg), C.byref(h))
         if st != OK:
@@ -120,6 +124,13 @@ class Ns2d:
         out = [np.empty((self.n, self.n)) for _ in range(4)]
         self._check(load().ns2d_get_fields(self._h, *[a.ctypes.data for a in out], 0))
         return tuple(out)
+
+    @property
+    def builtin(self):
+        """True when the context runs the library's own transforms."""
+        b = C.c_int32()
+        self._check(load().ns2d_get_transforms(self._h, C.byref(b)))
+        return bool(b.value)
 
     @property
     def steps(self):

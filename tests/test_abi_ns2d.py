@@ -40,12 +40,14 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.parametrize("kw", [
     dict(n=6), dict(n=31), dict(n=32768), dict(n=64, length=-1.0),
     dict(n=64, length=float("nan")), dict(n=64, nu=-1e-3), dict(n=64, nu=float("inf")),
-    dict(n=64, dt=0.0), dict(n=64, dt=float("nan")),
+    dict(n=64, dt=0.0), dict(n=64, dt=float("nan")), dict(n=64, transforms=3),
+    dict(n=64, transforms=-1), dict(n=64, transforms=2), dict(n=4096, transforms=2),
 ])
 def test_create_rejects_bad_config_without_gpu(kw):
     L = _built()
     cfg = ns2d.Ns2dConfig(n=kw.get("n", 64), length=kw.get("length", 0.0), nu=kw.get("nu", 1e-3),
-                          dt=kw.get("dt", 1e-3), hip_stream=None)
+                          dt=kw.get("dt", 1e-3), hip_stream=None,
+                          transforms=kw.get("transforms", 0))
     h = C.c_void_p()
     assert L.ns2d_create(C.byref(cfg), C.byref(h)) == ns2d.E_ARG
     assert not h.value
@@ -59,5 +61,6 @@ def test_null_handles_are_rejected():
     assert L.ns2d_get_fields(None, None, None, None, None, 0) == ns2d.E_ARG
     assert L.ns2d_synchronize(None) == ns2d.E_ARG
     assert L.ns2d_get_steps(None, None) == ns2d.E_ARG
+    assert L.ns2d_get_transforms(None, None) == ns2d.E_ARG
     assert L.ns2d_last_error(None) == b"null context"
     L.ns2d_destroy(None)

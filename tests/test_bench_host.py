@@ -30,10 +30,9 @@ def test_multi_gpu_request_exits_with_a_message():
 
 
 def test_field_step_algorithmic_bytes():
-    """One field step moves 192 n^2 bytes plus the half spectrum's extra
-    column: 40 n^2 for the grid product, 16 n^2 for the forward transform,
-    72 n^2 for the spectral kernel and 64 n^2 for the four inverse ones."""
+    """One field step at n = 2048 moves 4 + 4 grid fields (8 n^2 bytes each)
+    and 14 spectral arrays of n x 683 complex doubles (the columns inside
+    the 2/3 band: 3 * 682 < 2048 <= 3 * 683)."""
     import bench
     n = 2048
-    extra = 16 * n * (1 + 9 + 4)   # the column m_x = n/2: n complex doubles per spectral pass
-    assert bench.ns_alg_bytes_per_step(n) == 192 * n * n + extra
+    assert bench.ns_alg_bytes_per_step(n) == 8 * n * n * 8 + 14 * n * 683 * 16

@@ -5,9 +5,11 @@ then the particle step between the two retained levels).
 
 Tolerance: the two sides differ only in the rounding of the transforms
 (rocFFT against numpy's pocketfft) and of the pointwise products, about
-1e-16 relative per transform and step.  Measured on MI355X: at most 1.0e-15
-(n = 64), 1.6e-15 (n = 96) and 1.5e-15 (n = 2048) of each field's maximum;
-the bound is 1e-13."""
+1e-16 relative per transform and step.  Measured on MI355X, of each
+field's maximum: hipFFT at most 1.1e-15 (n = 64), 1.5e-15 (n = 96),
+5.2e-15 (n = 512), 1.5e-15 (n = 2048); the library's own transforms at most
+3.9e-15 (n = 512), 3.2e-15 (n = 1024), 9.4e-16 (n = 2048).  The bound is
+1e-13."""
 import numpy as np
 import pytest
 
@@ -32,15 +34,21 @@ def _compare(gpu_fields, ora_fields, rel=REL, what=""):
     return max(np.abs(g - o).max() / np.abs(o).max() for g, o in zip(gpu_fields, ora_fields))
 
 
-@pytest.mark.parametrize("n,length", [(64, 2 * np.pi), (96, 3.0)])
-def test_matches_oracle_step_by_step(n, length):
+@pytest.mark.parametrize("n,length,transforms", [
+    (64, 2 * np.pi, "auto"), (96, 3.0, "auto"), (512, 2 * np.pi, "builtin"), (1024, 3.0, "auto"),
+    (512, 2 * np.pi, "auto")])
+def test_matches_oracle_step_by_step(n, length, transforms):
     """Step 0 (band truncation), step 1 (forward Euler), step 2 (first AB2
-    step) and step 30, on a power-of-two grid and on n = 96 (divisible by 3:
-    the edge of the 2/3 rule; radix-3 transforms) with L != 2 pi."""
-    say(f"n={n} L={length}")
-    nu, dt = 2e-3, 2e-3
-    w0 = synth.random_vorticity(n, n / 10, 21, omega_rms=5.0)
-    g = ns2d.Ns2d(n, nu, dt, length=length)
+    step) and step 30: hipFFT on a small power-of-two grid and on n = 96
+    (divisible by 3: the edge of the 2/3 rule; radix-3 transforms) with
+    L != 2 pi; the library's own transforms at n = 512 (on request) and 1024
+    (L != 2 pi); hipFFT at 512, where "auto" picks it."""
+    say(f"n={n} L={length} transforms={transforms}")
+    # nu k_max^2 dt <= 0.2 at every size: the explicit viscous term stays stable
+    nu, dt = 2e-4, 2e-3
+    w0 = synth.random_vorticity(n, min(n / 10, 40.0), 21, omega_rms=5.0)
+    g = ns2d.Ns2d(n, nu, dt, length=length, transforms=transforms)
+    assert g.builtin == (transforms == "builtin" or (transforms == "auto" and n in (1024, 2048)))
     o = NS2D(n, nu, dt, length=length)
     g.set_vorticity(w0)
     o.set_vorticity(w0)
@@ -54,12 +62,15 @@ def test_matches_oracle_step_by_step(n, length):
     g.close()
 
 
-def test_full_size_matches_oracle():
-    """2048^2 (the benchmark's grid), 3 steps, every grid value compared."""
+@pytest.mark.parametrize("transforms", ["auto", "hipfft"])
+def test_full_size_matches_oracle(transforms):
+    """2048^2 (the benchmark's grid), 3 steps, every grid value compared,
+    with the library's own transforms and with hipFFT."""
     n, nu, dt = 2048, 1e-4, 1e-3
-    say(f"full size n={n}")
-    w0 = synth.random_vorticity(n, 10.0, 22, omega_rms=10.0)
-    g = ns2d.Ns2d(n, nu, dt)
+    say(f"full size n={n} transforms={transforms}")
+    w0 = synth.random_vorticity(n, 10.0, 22, omega_rms=3.0)
+    g = ns2d.Ns2d(n, nu, dt, transforms=transforms)
+    assert g.builtin == (transforms == "auto")
     o = NS2D(n, nu, dt)
     g.set_vorticity(w0)
     o.set_vorticity(w0)
@@ -70,13 +81,18 @@ def test_full_size_matches_oracle():
     g.close()
 
 
-def test_taylor_green_vortex_decay_on_the_gpu():
+@pytest.mark.parametrize("n,nu", [(64, 0.05), (512, 0.005)])
+def test_taylor_green_vortex_decay_on_the_gpu(n, nu):
     """psi = sin x sin y decays as exp(-2 nu t) in every field (no advection
-    for a Laplacian eigenfunction); AB2 error below 1e-8 at nu dt = 5e-5."""
-    n, nu, dt, steps = 64, 0.05, 1e-3, 200
+    for a Laplacian eigenfunction); AB2 error below 1e-8 at nu dt <= 5e-5;
+    hipFFT at n = 64, the library's own transforms at 512.  nu keeps
+    nu k_max^2 dt below 1 (0.29 at n = 512): the explicit viscous term would
+    otherwise amplify the transforms' rounding in the highest modes."""
+    dt, steps = 1e-3, 200
     x = np.arange(n) * (2 * np.pi / n)
     X, Y = x[None, :], x[:, None]
-    g = ns2d.Ns2d(n, nu, dt)
+    g = ns2d.Ns2d(n, nu, dt, transforms="builtin" if n == 512 else "auto")
+    assert g.builtin == (n == 512)
     g.set_vorticity(2 * np.sin(X) * np.sin(Y))
     g.step(steps)
     u, v, w, psi = g.get_fields()
@@ -132,15 +148,17 @@ def test_errors():
     g.close()
 
 
-def test_coupled_loop_matches_the_oracles():
+@pytest.mark.parametrize("n", [128, 512])
+def test_coupled_loop_matches_the_oracles(n):
     """The producer's velocity streamed into the particle library each step
     (ping-pong slots, device pointers, same stream), tracers and inertial
     particles, against the field oracle feeding the particle oracle the same
-    levels: positions within 1e-10 after 10 steps."""
-    n, nu, dt, nsteps = 128, 1e-3, 2e-3, 10
-    say("coupled loop")
+    levels: positions within 1e-10 after 10 steps (hipFFT at n = 128, the
+    library's own transforms at 512)."""
+    nu, dt, nsteps = 1e-3, 2e-3, 10
+    say(f"coupled loop n={n}")
     w0 = synth.random_vorticity(n, 8.0, 24, omega_rms=5.0)
-    g = ns2d.Ns2d(n, nu, dt)
+    g = ns2d.Ns2d(n, nu, dt, transforms="builtin" if n == 512 else "auto")
     g.set_vorticity(w0)
     tr = lpt.Tracker(n, "fp64")
     tr.set_time_mode("pingpong")
@@ -181,3 +199,19 @@ def test_coupled_loop_matches_the_oracles():
 
     for got, sp in ((xt, sp_t), (xi, sp_i)):
         assert np.max(pdist(got[0], sp.xw)) < 1e-10 and np.max(pdist(got[1], sp.yw)) < 1e-10
+
+
+def test_own_transforms_match_hipfft():
+    """The library's own transforms and hipFFT give the same fields to
+    rounding (1e-13 of each field's maximum) after 20 steps at n = 1024."""
+    n = 1024
+    w0 = synth.random_vorticity(n, 20.0, 25, omega_rms=8.0)
+    out = []
+    for tf in ("auto", "hipfft"):
+        g = ns2d.Ns2d(n, 5e-4, 1e-3, transforms=tf)
+        g.set_vorticity(w0)
+        g.step(20)
+        out.append(g.get_fields())
+        g.close()
+    worst = _compare(out[0], out[1], what="own vs hipFFT")
+    say(f"own vs hipFFT: worst relative difference {worst:.2e}")
