@@ -16,8 +16,8 @@
 // Every pointwise operation lives in the two kernels, so each step reads and
 // writes each spectral array once.
 //
-// For n = 1024 and 2048 (and 512 on request) the built-in transforms
-// (fft_lds.h) replace the library's and fuse with the pointwise work, in three kernels a step over a
+// For n = 512, 1024 and 2048 the built-in transforms (fft_lds.h) replace
+// the library's and fuse with the pointwise work, in three kernels a step over a
 // transposed spectral layout (entry (row jy, column ix) of a half-plane
 // spectrum at ix * n + jy, so that every column is contiguous):
 //   a. fwd_rows_kernel: the grid product of four rows, two real rows packed
@@ -151,7 +151,24 @@ __global__ __launch_bounds__(kBlock) void scaled_kernel(const double2 *__restric
 
 // ---- built-in transform path (n = 512, 1024, 2048) ------------------------
 
-constexpr int kRowsPerBlock = 4;   // grid rows per row-pass block: two packed pairs
+// Grid rows per row-pass block: four (two packed complex rows, 2N entries of
+// LDS) at N = 2048, two (one packed row) below, where twice as many blocks
+// fill the chip better (measured: 1024^2 step 71.9 -> 61.1 us; 2048^2 step
+// 163 -> 167 us with two).
+template <int N>
+constexpr int rows_per_block() { return N >= 2048 ? 4 : 2; }
+
+// Row slab of a row-pass block.  Workgroups go to the eight XCDs round-robin;
+// XCD x takes the contiguous slabs [x G/8, (x+1) G/8) (G = N / rows per
+// block, a multiple of 8 for every built-in size), so the two slabs that share each
+// 128-byte line of a transposed column run on one XCD and share its L2.
+template <int N>
+__device__ __forceinline__ int row_slab()
+{
+    constexpr int G = N / rows_per_block<N>();
+    static_assert(G % 8 == 0, "slabs split evenly over the XCDs");
+    return (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8);
+}
 
 // Columns ix = 0 .. band_cols(N) - 1 are the ones with 3 ix < N.  Every other
 // column of the band-limited state, of the four fields and of the read-back
@@ -159,7 +176,7 @@ constexpr int kRowsPerBlock = 4;   // grid rows per row-pass block: two packed p
 // the row passes skip it and the inverse row pass supplies the zeros.
 constexpr int band_cols(int N) { return (N - 1) / 3 + 1; }
 
-// Rows 4b .. 4b+3 of the advection term (PRODUCT: u dw/dx + v dw/dy from the
+// One slab of rows (rows_per_block) of the advection term (PRODUCT: u dw/dx + v dw/dy from the
 // four grid fields at g) or of one grid field (g), transformed along x:
 // rows (a, b) form z = a + i b, Z = FFT(z), and the half spectra are
 // A(k) = (Z(k) + conj Z(-k)) / 2, B(k) = (Z(k) - conj Z(-k)) / (2i).
@@ -168,11 +185,12 @@ __global__ __launch_bounds__(N / 8) void fwd_rows_kernel(const double *__restric
                                                         double2 *__restrict__ specT,
                                                         const double2 *__restrict__ W)
 {
-    extern __shared__ double2 lds_rows[];   // two packed rows of N entries
+    extern __shared__ double2 lds_rows[];   // kPairs packed rows of N entries
     constexpr int T = N / 8;
     constexpr size_t cells = (size_t)N * N;
-    const int jy0 = blockIdx.x * kRowsPerBlock;
-    for (int p = 0; p < 2; ++p) {
+    constexpr int kPairs = rows_per_block<N>() / 2;
+    const int jy0 = row_slab<N>() * rows_per_block<N>();
+    for (int p = 0; p < kPairs; ++p) {
         double2 *buf = lds_rows + p * N;
         const double *ra = g + (size_t)(jy0 + 2 * p) * N;
         const double *rb = ra + N;
@@ -189,11 +207,10 @@ __global__ __launch_bounds__(N / 8) void fwd_rows_kernel(const double *__restric
         }
     }
     __syncthreads();
-    ns_fft::fft<N, false>(lds_rows, W);
-    ns_fft::fft<N, false>(lds_rows + N, W);
+    for (int p = 0; p < kPairs; ++p) ns_fft::fft<N, false>(lds_rows + p * N, W);
     constexpr int KB = band_cols(N);
-    for (int e = threadIdx.x; e < 2 * KB; e += T) {
-        const int k = e >> 1, p = e & 1;
+    for (int e = threadIdx.x; e < kPairs * KB; e += T) {
+        const int k = e / kPairs, p = e % kPairs;
         const double2 *buf = lds_rows + p * N;
         const double2 z = buf[k], zc = buf[(N - k) & (N - 1)];
         double2 *dst = specT + (size_t)k * N + jy0 + 2 * p;
@@ -281,7 +298,7 @@ __global__ __launch_bounds__(N / 8) void column_kernel(double2 *__restrict__ w_h
     }
 }
 
-// Rows 4b .. 4b+3 of nf fields (planes of the transposed spectra, already
+// One slab of rows (rows_per_block) of nf fields (planes of the transposed spectra, already
 // transformed along y) back to the grid: rows (a, b) of a field form
 // Z(k) = A(k) + i B(k) and Z(N-k) = conj A(k) + i conj B(k) for the band
 // columns k < KB (the imaginary parts at k = 0 dropped as in any
@@ -293,14 +310,15 @@ __global__ __launch_bounds__(N / 8) void inv_rows_kernel(const double2 *__restri
                                                         size_t plane,
                                                         const double2 *__restrict__ W)
 {
-    extern __shared__ double2 lds_rows[];   // two packed rows of N entries
+    extern __shared__ double2 lds_rows[];   // kPairs packed rows of N entries
     constexpr int T = N / 8, KB = band_cols(N);
     constexpr size_t cells = (size_t)N * N;
-    const int jy0 = blockIdx.x * kRowsPerBlock;
+    constexpr int kPairs = rows_per_block<N>() / 2;
+    const int jy0 = row_slab<N>() * rows_per_block<N>();
     for (int f = 0; f < nf; ++f) {
         const double2 *src = fields + (size_t)f * plane;
-        for (int e = threadIdx.x; e < 2 * KB; e += T) {
-            const int k = e >> 1, p = e & 1;
+        for (int e = threadIdx.x; e < kPairs * KB; e += T) {
+            const int k = e / kPairs, p = e % kPairs;
             const double2 *sp = src + (size_t)k * N + jy0 + 2 * p;
             double2 A = sp[0], B = sp[1];
             if (k == 0) {
@@ -312,14 +330,11 @@ __global__ __launch_bounds__(N / 8) void inv_rows_kernel(const double2 *__restri
             if (k > 0) buf[N - k] = make_double2(A.x + B.y, B.x - A.y);
         }
         // columns KB .. N/2 and their mirrors N/2 .. N-KB are zero
-        for (int x = KB + threadIdx.x; x <= N - KB; x += T) {
-            lds_rows[x] = make_double2(0.0, 0.0);
-            lds_rows[N + x] = make_double2(0.0, 0.0);
-        }
+        for (int x = KB + threadIdx.x; x <= N - KB; x += T)
+            for (int p = 0; p < kPairs; ++p) lds_rows[p * N + x] = make_double2(0.0, 0.0);
         __syncthreads();
-        ns_fft::fft<N, true>(lds_rows, W);
-        ns_fft::fft<N, true>(lds_rows + N, W);
-        for (int p = 0; p < 2; ++p) {
+        for (int p = 0; p < kPairs; ++p) ns_fft::fft<N, true>(lds_rows + p * N, W);
+        for (int p = 0; p < kPairs; ++p) {
             double *ra = grid + (size_t)f * cells + (size_t)(jy0 + 2 * p) * N;
             for (int x = threadIdx.x; x < N; x += T) {
                 const double2 z = lds_rows[p * N + x];
@@ -407,8 +422,10 @@ template <int N>
 ns2d_status run_builtin_n(ns2d_ctx *c, BuiltinOp op)
 {
     constexpr int T = N / 8;
-    const size_t rows_lds = 2 * (size_t)N * sizeof(double2), col_lds = rows_lds;
-    const dim3 rows_grid(N / kRowsPerBlock), col_grid(band_cols(N));
+    constexpr int kPairs = rows_per_block<N>() / 2;
+    const size_t rows_lds = kPairs * (size_t)N * sizeof(double2);
+    const size_t col_lds = 2 * (size_t)N * sizeof(double2);
+    const dim3 rows_grid(N / rows_per_block<N>()), col_grid(band_cols(N));
     const Spec S = make_spec(c);
     hipStream_t st = c->stream;
     switch (op) {
@@ -502,10 +519,9 @@ ns2d_status ns2d_create(const ns2d_config *cfg, ns2d_ctx **out)
         (void)hipGetLastError();
         return bail(NS2D_E_NOMEM);
     }
-    // measured: the built-in path is faster from n = 1024 on; at 512 its
-    // n / 4 row blocks and n / 2 + 1 column blocks of n / 8 threads leave the
-    // chip under-filled and hipFFT wins
-    c->builtin = cfg->transforms == 2 || (cfg->transforms == 0 && (n == 1024 || n == 2048));
+    // measured faster than hipFFT at every built-in size (2048^2: 163 vs
+    // 337 us a step; 1024^2: 61 vs 101; 512^2: 35 vs 43)
+    c->builtin = cfg->transforms != 1 && (n == 512 || n == 1024 || n == 2048);
     if (c->builtin) {
         // twiddles from the long-double cosine and sine, rounded once
         std::vector<double2> w(n);

@@ -71,8 +71,8 @@ class Ns2d:
     """One libns2d context (see include/ns2d.h for every call)."""
 
     def __init__(self, n, nu, dt, length=0.0, stream=None, transforms="auto"):
-        """transforms: "auto" (the library's own for n = 1024 and 2048,
-        hipFFT otherwise), "hipfft", or "builtin" (n = 512, 1024, 2048)."""
+        """transforms: "auto" (the library's own for n = 512, 1024, 2048,
+        hipFFT otherwise), "hipfft", or "builtin" (n = 512, 1024, 2048 only)."""
         cfg = Ns2dConfig(n=n, length=length, nu=nu, dt=dt, hip_stream=stream,
                          transforms={"auto": 0, "hipfft": 1, "builtin": 2}[transforms])
         h = C.c_void_p()

@@ -36,19 +36,19 @@ def _compare(gpu_fields, ora_fields, rel=REL, what=""):
 
 @pytest.mark.parametrize("n,length,transforms", [
     (64, 2 * np.pi, "auto"), (96, 3.0, "auto"), (512, 2 * np.pi, "builtin"), (1024, 3.0, "auto"),
-    (512, 2 * np.pi, "auto")])
+    (512, 2 * np.pi, "hipfft")])
 def test_matches_oracle_step_by_step(n, length, transforms):
     """Step 0 (band truncation), step 1 (forward Euler), step 2 (first AB2
     step) and step 30: hipFFT on a small power-of-two grid and on n = 96
     (divisible by 3: the edge of the 2/3 rule; radix-3 transforms) with
-    L != 2 pi; the library's own transforms at n = 512 (on request) and 1024
-    (L != 2 pi); hipFFT at 512, where "auto" picks it."""
+    L != 2 pi; the library's own transforms at n = 512 and 1024 (L != 2 pi);
+    hipFFT at 512 on request."""
     say(f"n={n} L={length} transforms={transforms}")
     # nu k_max^2 dt <= 0.2 at every size: the explicit viscous term stays stable
     nu, dt = 2e-4, 2e-3
     w0 = synth.random_vorticity(n, min(n / 10, 40.0), 21, omega_rms=5.0)
     g = ns2d.Ns2d(n, nu, dt, length=length, transforms=transforms)
-    assert g.builtin == (transforms == "builtin" or (transforms == "auto" and n in (1024, 2048)))
+    assert g.builtin == (transforms != "hipfft" and n in (512, 1024, 2048))
     o = NS2D(n, nu, dt, length=length)
     g.set_vorticity(w0)
     o.set_vorticity(w0)
@@ -91,7 +91,7 @@ def test_taylor_green_vortex_decay_on_the_gpu(n, nu):
     dt, steps = 1e-3, 200
     x = np.arange(n) * (2 * np.pi / n)
     X, Y = x[None, :], x[:, None]
-    g = ns2d.Ns2d(n, nu, dt, transforms="builtin" if n == 512 else "auto")
+    g = ns2d.Ns2d(n, nu, dt)
     assert g.builtin == (n == 512)
     g.set_vorticity(2 * np.sin(X) * np.sin(Y))
     g.step(steps)
@@ -158,7 +158,7 @@ def test_coupled_loop_matches_the_oracles(n):
     nu, dt, nsteps = 1e-3, 2e-3, 10
     say(f"coupled loop n={n}")
     w0 = synth.random_vorticity(n, 8.0, 24, omega_rms=5.0)
-    g = ns2d.Ns2d(n, nu, dt, transforms="builtin" if n == 512 else "auto")
+    g = ns2d.Ns2d(n, nu, dt)
     g.set_vorticity(w0)
     tr = lpt.Tracker(n, "fp64")
     tr.set_time_mode("pingpong")
