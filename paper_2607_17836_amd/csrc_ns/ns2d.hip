@@ -22,9 +22,9 @@
 // spectrum at ix * n + jy, so that every column is contiguous):
 //   a. fwd_rows_kernel: the grid product of four rows, two real rows packed
 //      into one complex transform along x, unpacked into two half spectra;
-//   b. column_kernel: per column, the transform along y, the band, the AB2
-//      update, then for each of the four fields its values and the inverse
-//      transform along y, all in LDS;
+//   b. column_fwd_kernel: per band column, the transform along y, the band
+//      and the AB2 update; column_emit_kernel: per band column and field,
+//      the field's values and its inverse transform along y;
 //   c. inv_rows_kernel: two rows of each field packed into one complex
 //      inverse transform along x (Hermitian extension), written as grid rows.
 // Each spectral array is read and written once per step and the grid
@@ -158,6 +158,21 @@ __global__ __launch_bounds__(kBlock) void scaled_kernel(const double2 *__restric
 template <int N>
 constexpr int rows_per_block() { return N >= 2048 ? 4 : 2; }
 
+// Inverse row pass: one block per field and slab below N = 2048 (1024^2 step
+// 56.1 -> 52.3 us, 512^2 33.1 -> 30.7 us); at 2048 one block per slab walks
+// the four fields (161 us a step against 185 with a block per field).
+template <int N>
+constexpr bool field_blocks() { return N < 2048; }
+
+// Contiguous logical block ranges per XCD (workgroups go to the eight XCDs
+// round-robin): XCD x = b mod 8 takes logical blocks [x G/8, (x+1) G/8) up to
+// the remainder, so consecutive logical blocks share an L2.
+__device__ __forceinline__ int xcd_block(int b, int G)
+{
+    const int x = b % 8, k = b / 8, q = G / 8, r = G % 8;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // Row slab of a row-pass block.  Workgroups go to the eight XCDs round-robin;
 // XCD x takes the contiguous slabs [x G/8, (x+1) G/8) (G = N / rows per
 // block, a multiple of 8 for every built-in size), so the two slabs that share each
@@ -219,87 +234,93 @@ __global__ __launch_bounds__(N / 8) void fwd_rows_kernel(const double *__restric
     }
 }
 
-enum ColumnMode { kColInit = 0, kColFirst = 1, kColStep = 2, kColReadW = 3, kColReadPsi = 4 };
+enum ColumnMode { kColInit = 0, kColFirst = 1, kColStep = 2 };
 
-// Column ix < band_cols(N) of the transposed spectra, one block per column.
-// Init and step modes transform plane 0 of `fields` (the x-transformed rows)
-// along y, take the band, store the state (init) or apply AB2 (step), then
-// emit the four fields, each transformed back along y into its plane.
-// Read-back modes emit omega / n^2 or psi / n^2 into plane 0.  Plane 0's
-// column is read whole into LDS before it is written.
+// Column ix < band_cols(N) of the transposed spectra, one block per column:
+// plane 0 of `fields` (the x-transformed rows) transformed along y, the band
+// taken, and the state stored (init) or advanced by AB2 (step).
 template <int N, int MODE>
-__global__ __launch_bounds__(N / 8) void column_kernel(double2 *__restrict__ w_hat,
-                                                      double2 *__restrict__ r_prev,
-                                                      double2 *__restrict__ fields, Spec S,
-                                                      const double2 *__restrict__ W)
+__global__ __launch_bounds__(N / 8) void column_fwd_kernel(double2 *__restrict__ w_hat,
+                                                          double2 *__restrict__ r_prev,
+                                                          const double2 *__restrict__ fields,
+                                                          Spec S, const double2 *__restrict__ W)
 {
-    extern __shared__ double2 lds_col[];   // N transform entries, then N state entries
-    double2 *wn = lds_col + N;             // the column's new state, kept for the emits
+    extern __shared__ double2 lds_col[];   // N entries
     constexpr int T = N / 8;
     const int ix = blockIdx.x, t = threadIdx.x;
     const size_t col = (size_t)ix * N;
     const double kx = S.kscale * ix;
-    if constexpr (MODE <= kColStep) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) lds_col[t + q * T] = fields[col + t + q * T];
-        __syncthreads();
-        ns_fft::fft<N, false>(lds_col, W);
-    }
+    for (int q = 0; q < 8; ++q) lds_col[t + q * T] = fields[col + t + q * T];
+    __syncthreads();
+    ns_fft::fft<N, false>(lds_col, W);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int jy = t + q * T;
         const size_t idx = col + jy;
         const int my = signed_mode(jy, N);
+        const double2 Nh = in_band(ix, my, N) ? lds_col[jy] : make_double2(0.0, 0.0);
         if constexpr (MODE == kColInit) {
-            const double2 w = in_band(ix, my, N) ? lds_col[jy] : make_double2(0.0, 0.0);
-            w_hat[idx] = w;
-            wn[jy] = w;
-        } else if constexpr (MODE == kColFirst || MODE == kColStep) {
+            w_hat[idx] = Nh;
+        } else {
             const double ky = S.kscale * my;
             const double visc = S.nu * (kx * kx + ky * ky);
-            const double2 Nh = in_band(ix, my, N) ? lds_col[jy] : make_double2(0.0, 0.0);
             const double2 w = w_hat[idx];
             const double2 r = make_double2(-Nh.x - visc * w.x, -Nh.y - visc * w.y);
             const double2 r_old = MODE == kColFirst ? r : r_prev[idx];
-            wn[jy] = make_double2(w.x + S.dt * (1.5 * r.x - 0.5 * r_old.x),
-                                 w.y + S.dt * (1.5 * r.y - 0.5 * r_old.y));
-            w_hat[idx] = wn[jy];
+            w_hat[idx] = make_double2(w.x + S.dt * (1.5 * r.x - 0.5 * r_old.x),
+                                      w.y + S.dt * (1.5 * r.y - 0.5 * r_old.y));
             r_prev[idx] = r;
-        } else {
-            wn[jy] = w_hat[idx];
         }
-    }
-    constexpr int nf = MODE >= kColReadW ? 1 : 4;
-    const double s = S.inv_nn;
-    for (int f = 0; f < nf; ++f) {
-        __syncthreads();   // the previous contents of lds_col are consumed
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int jy = t + q * T;
-            const double ky = S.kscale * signed_mode(jy, N);
-            const double k2 = kx * kx + ky * ky;
-            const double2 w = wn[jy];
-            double2 p = make_double2(0.0, 0.0);
-            if (k2 > 0.0) p = make_double2(w.x / k2, w.y / k2);
-            double2 v;
-            if constexpr (MODE == kColReadW) v = make_double2(w.x * s, w.y * s);
-            else if constexpr (MODE == kColReadPsi) v = make_double2(p.x * s, p.y * s);
-            else if (f == 0) v = make_double2(-ky * p.y * s, ky * p.x * s);    // u  =  i k_y psi
-            else if (f == 1) v = make_double2(kx * p.y * s, -kx * p.x * s);    // v  = -i k_x psi
-            else if (f == 2) v = make_double2(-kx * w.y * s, kx * w.x * s);    // dw/dx
-            else v = make_double2(-ky * w.y * s, ky * w.x * s);                // dw/dy
-            lds_col[jy] = v;
-        }
-        __syncthreads();
-        ns_fft::fft<N, true>(lds_col, W);
-        double2 *dst = fields + (size_t)f * S.plane + col;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) dst[t + q * T] = lds_col[t + q * T];
     }
 }
 
-// One slab of rows (rows_per_block) of nf fields (planes of the transposed spectra, already
-// transformed along y) back to the grid: rows (a, b) of a field form
+enum EmitMode { kEmitFields = 0, kEmitW = 1, kEmitPsi = 2 };
+
+// One field of one band column, transformed back along y: the four fields
+// u = i k_y psi, v = -i k_x psi, dw/dx = i k_x w, dw/dy = i k_y w (emit
+// mode), or omega or psi alone (read-back modes), each scaled by 1/n^2.
+// Logical block l = column * nf + field, so a column's fields run on one XCD
+// and re-read its state from that L2.
+template <int N, int MODE>
+__global__ __launch_bounds__(N / 8) void column_emit_kernel(const double2 *__restrict__ w_hat,
+                                                           double2 *__restrict__ fields, Spec S,
+                                                           const double2 *__restrict__ W)
+{
+    extern __shared__ double2 lds_col[];   // N entries
+    constexpr int T = N / 8;
+    constexpr int nf = MODE == kEmitFields ? 4 : 1;
+    const int l = xcd_block(blockIdx.x, band_cols(N) * nf);
+    const int ix = l / nf, f = l % nf, t = threadIdx.x;
+    const size_t col = (size_t)ix * N;
+    const double kx = S.kscale * ix, s = S.inv_nn;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int jy = t + q * T;
+        const double ky = S.kscale * signed_mode(jy, N);
+        const double k2 = kx * kx + ky * ky;
+        const double2 w = w_hat[col + jy];
+        double2 p = make_double2(0.0, 0.0);
+        if (k2 > 0.0) p = make_double2(w.x / k2, w.y / k2);
+        double2 v;
+        if constexpr (MODE == kEmitW) v = make_double2(w.x * s, w.y * s);
+        else if constexpr (MODE == kEmitPsi) v = make_double2(p.x * s, p.y * s);
+        else if (f == 0) v = make_double2(-ky * p.y * s, ky * p.x * s);    // u  =  i k_y psi
+        else if (f == 1) v = make_double2(kx * p.y * s, -kx * p.x * s);    // v  = -i k_x psi
+        else if (f == 2) v = make_double2(-kx * w.y * s, kx * w.x * s);    // dw/dx
+        else v = make_double2(-ky * w.y * s, ky * w.x * s);                // dw/dy
+        lds_col[jy] = v;
+    }
+    __syncthreads();
+    ns_fft::fft<N, true>(lds_col, W);
+    double2 *dst = fields + (size_t)f * S.plane + col;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dst[t + q * T] = lds_col[t + q * T];
+}
+
+// One slab of rows (rows_per_block) of one or all nf fields (planes of the
+// transposed spectra, already transformed along y; see field_blocks) back
+// to the grid: rows (a, b) of a field form
 // Z(k) = A(k) + i B(k) and Z(N-k) = conj A(k) + i conj B(k) for the band
 // columns k < KB (the imaginary parts at k = 0 dropped as in any
 // complex-to-real transform) and zero elsewhere; z = IFFT(Z) gives a = Re z,
@@ -312,10 +333,21 @@ __global__ __launch_bounds__(N / 8) void inv_rows_kernel(const double2 *__restri
 {
     extern __shared__ double2 lds_rows[];   // kPairs packed rows of N entries
     constexpr int T = N / 8, KB = band_cols(N);
+    constexpr int kPairs = rows_per_block<N>() / 2, G = N / rows_per_block<N>();
     constexpr size_t cells = (size_t)N * N;
-    constexpr int kPairs = rows_per_block<N>() / 2;
-    const int jy0 = row_slab<N>() * rows_per_block<N>();
-    for (int f = 0; f < nf; ++f) {
+    int f0, f1, jy0;
+    if constexpr (field_blocks<N>()) {
+        // one block per (field, slab); a field's adjacent slabs share an XCD
+        const int l = xcd_block(blockIdx.x, nf * G);
+        f0 = l / G;
+        f1 = f0 + 1;
+        jy0 = (l % G) * rows_per_block<N>();
+    } else {
+        f0 = 0;
+        f1 = nf;
+        jy0 = row_slab<N>() * rows_per_block<N>();
+    }
+    for (int f = f0; f < f1; ++f) {
         const double2 *src = fields + (size_t)f * plane;
         for (int e = threadIdx.x; e < kPairs * KB; e += T) {
             const int k = e / kPairs, p = e % kPairs;
@@ -424,31 +456,36 @@ ns2d_status run_builtin_n(ns2d_ctx *c, BuiltinOp op)
     constexpr int T = N / 8;
     constexpr int kPairs = rows_per_block<N>() / 2;
     const size_t rows_lds = kPairs * (size_t)N * sizeof(double2);
-    const size_t col_lds = 2 * (size_t)N * sizeof(double2);
+    const size_t col_lds = (size_t)N * sizeof(double2);
     const dim3 rows_grid(N / rows_per_block<N>()), col_grid(band_cols(N));
     const Spec S = make_spec(c);
     hipStream_t st = c->stream;
+    const double2 *Wt = c->twiddle;
+    const dim3 emit4_grid(4 * band_cols(N)), emit1_grid(band_cols(N));
+    const dim3 inv4_grid(field_blocks<N>() ? 4 * rows_grid.x : rows_grid.x);
     switch (op) {
     case kOpInit:
-        fwd_rows_kernel<N, false><<<rows_grid, T, rows_lds, st>>>(c->tmp, c->fields, c->twiddle);
-        column_kernel<N, kColInit><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, c->twiddle);
-        inv_rows_kernel<N><<<rows_grid, T, rows_lds, st>>>(c->fields, c->grid, 4, S.plane, c->twiddle);
+        fwd_rows_kernel<N, false><<<rows_grid, T, rows_lds, st>>>(c->tmp, c->fields, Wt);
+        column_fwd_kernel<N, kColInit><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, Wt);
+        column_emit_kernel<N, kEmitFields><<<emit4_grid, T, col_lds, st>>>(c->w_hat, c->fields, S, Wt);
+        inv_rows_kernel<N><<<inv4_grid, T, rows_lds, st>>>(c->fields, c->grid, 4, S.plane, Wt);
         break;
     case kOpStep:
-        fwd_rows_kernel<N, true><<<rows_grid, T, rows_lds, st>>>(c->grid, c->fields, c->twiddle);
+        fwd_rows_kernel<N, true><<<rows_grid, T, rows_lds, st>>>(c->grid, c->fields, Wt);
         if (c->first)
-            column_kernel<N, kColFirst><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, c->twiddle);
+            column_fwd_kernel<N, kColFirst><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, Wt);
         else
-            column_kernel<N, kColStep><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, c->twiddle);
-        inv_rows_kernel<N><<<rows_grid, T, rows_lds, st>>>(c->fields, c->grid, 4, S.plane, c->twiddle);
+            column_fwd_kernel<N, kColStep><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, Wt);
+        column_emit_kernel<N, kEmitFields><<<emit4_grid, T, col_lds, st>>>(c->w_hat, c->fields, S, Wt);
+        inv_rows_kernel<N><<<inv4_grid, T, rows_lds, st>>>(c->fields, c->grid, 4, S.plane, Wt);
         break;
     case kOpReadW:
     case kOpReadPsi:
         if (op == kOpReadW)
-            column_kernel<N, kColReadW><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, c->twiddle);
+            column_emit_kernel<N, kEmitW><<<emit1_grid, T, col_lds, st>>>(c->w_hat, c->fields, S, Wt);
         else
-            column_kernel<N, kColReadPsi><<<col_grid, T, col_lds, st>>>(c->w_hat, c->r_prev, c->fields, S, c->twiddle);
-        inv_rows_kernel<N><<<rows_grid, T, rows_lds, st>>>(c->fields, c->tmp, 1, S.plane, c->twiddle);
+            column_emit_kernel<N, kEmitPsi><<<emit1_grid, T, col_lds, st>>>(c->w_hat, c->fields, S, Wt);
+        inv_rows_kernel<N><<<rows_grid, T, rows_lds, st>>>(c->fields, c->tmp, 1, S.plane, Wt);
         break;
     }
     NS_HIP(c, hipGetLastError());
