@@ -17,8 +17,10 @@ tracers: one GPU's share on eight, same full field), batch2048 (8
 Stokes-number species, all three schemes, one launch per species, autotuned
 launch shape), spec1024_fp64 (FP64 tracers + inertial particles, --scheme),
 tg64 (FP64 Taylor-Green, 4096 tracers), adjoint2048 (FP64 checkpointed
-forward run plus reverse sweep with grid gradients) and ns2048 (the Eulerian
-field producer: one pseudospectral AB2 vorticity step on a 2048^2 FP64 grid).
+forward run plus reverse sweep with grid gradients), ns2048 (the Eulerian
+field producer: one pseudospectral AB2 vorticity step on a 2048^2 FP64 grid)
+and coupled2048 (the coupled loop: that field step, the new level handed to
+the particle library by device pointer, and 2^20 FP64 tracers stepped).
 
 Prints one JSON line.  The roofline object reports the dominant kernel's (the
 in-place step kernel's) algorithmic bytes per launch over its average
@@ -350,6 +352,80 @@ def bench_ns(args):
     return args.steps / wall, 1e3 * wall / args.steps, cfg, roof
 
 
+COUPLED_PARTICLES, COUPLED_SEED = 1 << 20, 71
+
+
+def coupled_alg_bytes_per_step(n: int, particles: int) -> int:
+    """One coupled step: the field step, the ingest of the new level (u and v
+    read for the node records and again for the largest speed, the level's
+    half of each 32-byte FP64 record written) and the FP64 tracer step
+    (state read and written, both levels of the field read once)."""
+    return (ns_alg_bytes_per_step(n) + 48 * n * n
+            + particles * 2 * state_bytes("fp64", "tracer", 0.0) + field_pair_bytes(n, "fp64"))
+
+
+def bench_coupled(args):
+    """The coupled loop of Alg. coupled_EL on one GPU: per step, the field
+    producer advances the 2048^2 FP64 vorticity (the ns2048 workload), its
+    grid velocity becomes the particle library's newer level by device
+    pointer (ping-pong slots, same stream), and 2^20 FP64 tracers take one
+    bilinear RK4 step between the two levels (cell-order re-sort every 20
+    steps, MSD every 100).  HIP events on the null stream bracket the timed
+    steps."""
+    import torch
+    from paper_2607_17836_amd import lpt, ns2d, synth
+    n, dt = NS_N, NS_DT
+    g = ns2d.Ns2d(n, NS_NU, dt)
+    g.set_vorticity(synth.random_vorticity(n, NS_K0, NS_SEED, omega_rms=NS_RMS))
+    tr = lpt.Tracker(n, "fp64", sort_interval=20)
+    tr.set_time_mode("pingpong")
+    tr.set_snapshot_device(0, 0.0, *g.velocity_ptrs())
+    g.step(1)
+    tr.set_snapshot_device(1, dt, *g.velocity_ptrs())
+    zeros = np.zeros(COUPLED_PARTICLES)
+    sid = tr.add_species("tracer", 0.0, "bilinear", zeros, zeros)
+    tr.init_uniform(sid, COUPLED_SEED)
+    done = [0]
+
+    def run(k):
+        for _ in range(k):
+            s = done[0]
+            tr.step(1, dt, 100)
+            g.step(1)
+            tr.set_snapshot_device(s % 2, (s + 2) * dt, *g.velocity_ptrs())
+            done[0] += 1
+
+    run(args.warmup)
+    tr.synchronize()
+    g.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    run(args.steps)
+    e1.record()
+    tr.synchronize()
+    g.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_us = 1e3 * e0.elapsed_time(e1) / args.steps
+    xw, yw, _, _ = tr.get_positions(sid)
+    tr.close()
+    g.close()
+    if not (np.isfinite(xw).all() and np.isfinite(yw).all()):
+        raise RuntimeError("coupled2048: non-finite particle positions")
+    ab = coupled_alg_bytes_per_step(n, COUPLED_PARTICLES)
+    log(f"[bench] coupled2048: {args.steps} steps in {wall:.3f} s; {step_us:.1f} us per coupled step by events")
+    cfg = {"workload": "coupled2048_fp64_ns_ab2_plus_2p20_tracers", "grid": n, "particles": COUPLED_PARTICLES,
+           "nu": NS_NU, "dt": dt, "k0": NS_K0, "omega_rms": NS_RMS, "precision": "fp64",
+           "scheme": "bilinear", "sort_interval": 20, "stats_every": 100, "parallelism": "1 GPU"}
+    roof = {"bound": "hbm", "achieved": ab / (step_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": ab / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "whole coupled step: field step + ingest of the new level + tracer step",
+            "kernel_avg_us": step_us, "alg_bytes_per_step": ab}
+    return args.steps / wall, 1e3 * wall / args.steps, cfg, roof
+
+
 def cpu_baseline_ns(budget_steps=3):
     """The field oracle (numpy FFT, single-threaded) on the same 2048^2
     workload: `budget_steps` steps after the forward-Euler first step."""
@@ -374,7 +450,7 @@ def main():
     ap.add_argument("--workload", default="spec4096_split",
                     choices=["spec4096_split", "spec4096_split_share8", "batch2048",
                              "spec1024_fp64", "tg64",
-                             "adjoint2048", "ns2048"])
+                             "adjoint2048", "ns2048", "coupled2048"])
     ap.add_argument("--scheme", default="bilinear", choices=["bilinear", "catmull_rom", "bspline"],
                     help="scheme of the spec1024_fp64 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -415,6 +491,12 @@ def main():
         metric = "field steps/s (pseudospectral AB2 vorticity step), 2048^2 FP64"
         if not args.no_cpu_baseline:
             extra["cpu_baseline"] = cpu_baseline_ns()
+    elif args.workload == "coupled2048":
+        value, ms_per_step, cfg, roof = bench_coupled(args)
+        dtype = "f64"
+        unit = "steps/s"
+        metric = ("coupled steps/s (2048^2 FP64 field step + level hand-off + 2^20 FP64 tracer "
+                  "RK4 step)")
     elif args.workload == "adjoint2048":
         value, ms_per_step, cfg, roof = bench_adjoint(args, lpt)
         dtype = "f64"

@@ -102,12 +102,11 @@ struct alignas(32) Rec64 { double u0, v0, u1, v1; };
 
 // ---- launch wrappers (return hipGetLastError of the launch) -------------
 // rec: the padded record array ((n + 3)^2 records).
-hipError_t launch_pack64(Rec64 *rec, int slot, const double *u, const double *v, int n,
-                         hipStream_t st);
-hipError_t launch_pack32(float4 *rec, int slot, const double *u, const double *v, int n,
-                         double scale, hipStream_t st);
-hipError_t launch_speed_max(const double *u, const double *v, int64_t nn, double scale,
-                            float *out, hipStream_t st);
+// One level's half of every record (FP64: Rec64 doubles; FP32: float4
+// records of u * scale) and its largest |u| or |v| times vscale folded into
+// *umax (which the caller zeroes first).
+hipError_t launch_pack(void *rec, bool fp64, int slot, const double *u, const double *v, int n,
+                       double scale, double vscale, float *umax, hipStream_t st);
 hipError_t launch_psi_to_velocity(const double *psi, double *u, double *v, int n, double h,
                                   hipStream_t st);
 

@@ -505,12 +505,8 @@ lpt_status lpt_set_snapshot(lpt_ctx *c, int32_t slot, double t, const double *u,
     if (s == LPT_OK) s = stage_in(c, st, v, nn, on_device, dv);
     if (s != LPT_OK) return s;
     HIP_TRY(c, hipMemsetAsync(c->umax + slot, 0, sizeof(float), c->stream));
-    HIP_TRY(c, launch_speed_max(du, dv, nn, c->invh, c->umax + slot, c->stream));
-    if (c->precision == LPT_FP64)
-        HIP_TRY(c, launch_pack64(static_cast<Rec64 *>(c->rec), slot, du, dv, c->n, c->stream));
-    else
-        HIP_TRY(c, launch_pack32(static_cast<float4 *>(c->rec), slot, du, dv, c->n, c->invh,
-                                 c->stream));
+    HIP_TRY(c, launch_pack(c->rec, c->precision == LPT_FP64, slot, du, dv, c->n, c->invh, c->invh,
+                           c->umax + slot, c->stream));
     if (!st.bufs.empty()) HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->slot_set[slot] = true;
     c->t_slot[slot] = t;
@@ -535,13 +531,8 @@ lpt_status lpt_set_snapshot_psi(lpt_ctx *c, int32_t slot, double t, const double
     st.bufs.push_back(uv);
     HIP_TRY(c, launch_psi_to_velocity(dp, uv, uv + nn, c->n, c->h, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->umax + slot, 0, sizeof(float), c->stream));
-    HIP_TRY(c, launch_speed_max(uv, uv + nn, nn, c->invh, c->umax + slot, c->stream));
-    if (c->precision == LPT_FP64)
-        HIP_TRY(c, launch_pack64(static_cast<Rec64 *>(c->rec), slot, uv, uv + nn, c->n,
-                                 c->stream));
-    else
-        HIP_TRY(c, launch_pack32(static_cast<float4 *>(c->rec), slot, uv, uv + nn, c->n, c->invh,
-                                 c->stream));
+    HIP_TRY(c, launch_pack(c->rec, c->precision == LPT_FP64, slot, uv, uv + nn, c->n, c->invh,
+                           c->invh, c->umax + slot, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->slot_set[slot] = true;
     c->t_slot[slot] = t;

@@ -888,62 +888,12 @@ __device__ __forceinline__ int ghost_source(int a, int n)
     return i;
 }
 
-__global__ void pack64_kernel(Rec64 *rec, int slot, const double *__restrict__ u,
-                              const double *__restrict__ v, int n)
+// Block-wide maximum of m folded into *out with an unsigned max on the
+// binary32 bit pattern (non-negative floats order like their bits).  Every
+// thread of the block must call it.
+__device__ __forceinline__ void block_max_to(float m, unsigned *out)
 {
-    const int pitch = n + kGhostLo + kGhostHi;
-    const int a = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
-    if (a >= pitch) return;
-    const int64_t src = (int64_t)ghost_source(b, n) * n + ghost_source(a, n);
-    double2 *q = reinterpret_cast<double2 *>(rec + (int64_t)b * pitch + a) + slot;
-    *q = make_double2(u[src], v[src]);
-}
-
-__global__ void pack32_kernel(float4 *rec, int slot, const double *__restrict__ u,
-                              const double *__restrict__ v, int n, double scale)
-{
-    const int pitch = n + kGhostLo + kGhostHi;
-    const int a = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
-    if (a >= pitch) return;
-    const int64_t src = (int64_t)ghost_source(b, n) * n + ghost_source(a, n);
-    float2 *q = reinterpret_cast<float2 *>(rec + (int64_t)b * pitch + a) + slot;
-    *q = make_float2((float)(u[src] * scale), (float)(v[src] * scale));
-}
-
-hipError_t launch_pack64(Rec64 *rec, int slot, const double *u, const double *v, int n,
-                         hipStream_t st)
-{
-    const int pitch = n + kGhostLo + kGhostHi, b = 256;
-    hipLaunchKernelGGL(pack64_kernel, dim3((pitch + b - 1) / b, pitch), dim3(b), 0, st, rec, slot,
-                       u, v, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_pack32(float4 *rec, int slot, const double *u, const double *v, int n,
-                         double scale, hipStream_t st)
-{
-    const int pitch = n + kGhostLo + kGhostHi, b = 256;
-    hipLaunchKernelGGL(pack32_kernel, dim3((pitch + b - 1) / b, pitch), dim3(b), 0, st, rec, slot,
-                       u, v, n, scale);
-    return hipGetLastError();
-}
-
-// Largest |u| or |v| of one time level, times `scale` (to cells per unit
-// time), folded into *out with an unsigned max on the binary32 bit pattern
-// (monotonic for non-negative values).  *out must be zeroed first.  Only the
-// LDS tile halo of the step kernel uses it.
-constexpr int kMaxThreads = 256;
-
-__global__ __launch_bounds__(kMaxThreads) void speed_max_kernel(const double *__restrict__ u,
-                                                                const double *__restrict__ v,
-                                                                int64_t nn, double scale,
-                                                                unsigned *out)
-{
-    __shared__ float red[kMaxThreads / kWave];
-    float m = 0.0f;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nn;
-         k += (int64_t)gridDim.x * blockDim.x)
-        m = fmaxf(m, (float)(fmax(fabs(u[k]), fabs(v[k])) * scale));
+    __shared__ float red[kMaxBlock / kWave];
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
     if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = m;
@@ -954,13 +904,48 @@ __global__ __launch_bounds__(kMaxThreads) void speed_max_kernel(const double *__
     }
 }
 
-hipError_t launch_speed_max(const double *u, const double *v, int64_t nn, double scale,
-                            float *out, hipStream_t st)
+// One ingest pass: each node record's half for this level (ghost records
+// are periodic images), and the level's largest |u| or |v| times vscale
+// (cells per unit time), which the step kernel's LDS tile halo uses, folded
+// into *umax.  Blocks walk columns a of the padded grid and stride over its
+// rows, so the grid stays at about a thousand blocks (one atomic each).
+template <bool FP64>
+__global__ __launch_bounds__(256) void pack_kernel(void *rec, int slot, const double *__restrict__ u,
+                                                   const double *__restrict__ v, int n,
+                                                   double scale, double vscale, unsigned *umax)
 {
-    const int64_t want = (nn + kMaxThreads - 1) / kMaxThreads;
-    const unsigned grid = (unsigned)(want < 1024 ? (want > 0 ? want : 1) : 1024);
-    hipLaunchKernelGGL(speed_max_kernel, dim3(grid), dim3(kMaxThreads), 0, st, u, v, nn, scale,
-                       reinterpret_cast<unsigned *>(out));
+    const int pitch = n + kGhostLo + kGhostHi;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    float m = 0.0f;
+    if (a < pitch) {
+        const int i = ghost_source(a, n);
+        for (int b = blockIdx.y; b < pitch; b += gridDim.y) {
+            const int64_t src = (int64_t)ghost_source(b, n) * n + i;
+            const double uu = u[src], vv = v[src];
+            const int64_t r = (int64_t)b * pitch + a;
+            if constexpr (FP64)
+                reinterpret_cast<double2 *>(static_cast<Rec64 *>(rec) + r)[slot] = make_double2(uu, vv);
+            else
+                reinterpret_cast<float2 *>(static_cast<float4 *>(rec) + r)[slot] =
+                    make_float2((float)(uu * scale), (float)(vv * scale));
+            m = fmaxf(m, (float)(fmax(fabs(uu), fabs(vv)) * vscale));
+        }
+    }
+    block_max_to(m, umax);
+}
+
+hipError_t launch_pack(void *rec, bool fp64, int slot, const double *u, const double *v, int n,
+                       double scale, double vscale, float *umax, hipStream_t st)
+{
+    const int pitch = n + kGhostLo + kGhostHi, b = 256;
+    const dim3 grid((pitch + b - 1) / b, pitch < 128 ? pitch : 128);
+    unsigned *out = reinterpret_cast<unsigned *>(umax);
+    if (fp64)
+        hipLaunchKernelGGL(pack_kernel<true>, grid, dim3(b), 0, st, rec, slot, u, v, n, scale,
+                           vscale, out);
+    else
+        hipLaunchKernelGGL(pack_kernel<false>, grid, dim3(b), 0, st, rec, slot, u, v, n, scale,
+                           vscale, out);
     return hipGetLastError();
 }
 

@@ -36,3 +36,13 @@ def test_field_step_algorithmic_bytes():
     import bench
     n = 2048
     assert bench.ns_alg_bytes_per_step(n) == 8 * n * n * 8 + 14 * n * 683 * 16
+
+
+def test_coupled_step_algorithmic_bytes():
+    """A coupled step adds to the field step the ingest of the new level
+    (48 n^2 bytes) and the FP64 tracer step (64 B per tracer, both levels
+    of the 32-byte node records read once)."""
+    import bench
+    n, m = 2048, 1 << 20
+    assert bench.coupled_alg_bytes_per_step(n, m) == (bench.ns_alg_bytes_per_step(n) + 48 * n * n
+                                                       + 64 * m + 32 * n * n)
