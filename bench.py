@@ -8,7 +8,7 @@ with two FP32 velocity snapshots from the k0 = 20 random-phase spectrum
 cell + FP32 offset, FP64 displacement), bilinear interpolation.  One step =
 one RK4 step of every particle (cell location, 4 stages of spatial + temporal
 interpolation, combine, wrap, FP64 displacement), plus the cell-order re-sort
-every 12 steps (applied by the following step's kernel) and the FP64
+every 16 steps (applied by the following step's kernel) and the FP64
 MSD/dispersion reduction every 100 steps, all inside the timed region.  Inputs
 are resident in HBM before timing starts.
 

@@ -18,7 +18,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lpt_tuning.json
 SPACE = {
     "block_size": (256, 128, 512),
     "tile_records": (0, -1, 800, 1600, 2400),
-    "sort_interval": (20, 10, 12, 15, 40, 5),
+    "sort_interval": (20, 10, 12, 16, 40, 5),
     "persistent": (0, 1),
     "graph_chunk": (0, 100),
     "halo_scale": (0.125, 0.25, 0.5, 1.0),

@@ -64,9 +64,9 @@ def c2_spectrum(scheme: str, per_species: int = 1 << 20, n: int = 1024, steps: i
 # The headline workload: 4096^2 FP32 fields from the k0 = 20 spectrum, 2^24
 # tracers in split (int cell + FP32 offset) form, bilinear, dt = 1e-3,
 # ping-pong time levels, FP64 MSD every 100 steps, cell-order re-sort every
-# 12 steps (the measured optimum of re-sort cost against tile locality).
+# 16 steps (the measured optimum of re-sort cost against tile locality).
 C3_SPLIT = Workload("spec4096_fp32split_bilinear_2p24", 4096, "fp32_split", "spectrum", k0=20.0,
-                    field_seed=3, dt=1e-3, steps=10000, stats_every=100, sort_interval=12,
+                    field_seed=3, dt=1e-3, steps=10000, stats_every=100, sort_interval=16,
                     sort_tile=16, species=(("tracer", 0.0, "bilinear", 1 << 24, 31),))
 
 # One GPU's share of the headline on eight: 2^21 tracers on the same full

@@ -529,7 +529,7 @@ def test_fp32_split_tracks_fp64_oracle():
 
 def test_c3_full_size_sampled():
     """The headline configuration as the benchmark runs it (4096^2 FP32
-    fields, 2^24 split tracers, re-sorted every 12 steps, so the run includes
+    fields, 2^24 split tracers, re-sorted every 16 steps, so the run includes
     two permuting steps): after 20 steps, 1024 sampled particles lie within
     1e-6 of the FP64 oracle on the binary32-rounded fields."""
     w = workloads.C3_SPLIT
