@@ -6,8 +6,9 @@ then the particle step between the two retained levels).
 Tolerance: the two sides differ only in the rounding of the transforms
 (rocFFT against numpy's pocketfft) and of the pointwise products, about
 1e-16 relative per transform and step.  Measured on MI355X, of each
-field's maximum: hipFFT at most 1.1e-15 (n = 64), 1.5e-15 (n = 96),
-5.2e-15 (n = 512), 1.5e-15 (n = 2048); the library's own transforms at most
+field's maximum: hipFFT at most 4.9e-16 (n = 8), 1.1e-15 (n = 64),
+1.5e-15 (n = 96), 5.2e-15 (n = 512), 1.5e-15 (n = 2048), 2.2e-15
+(n = 4096); the library's own transforms at most
 3.9e-15 (n = 512), 3.2e-15 (n = 1024), 9.4e-16 (n = 2048).  The bound is
 1e-13."""
 import numpy as np
@@ -35,11 +36,12 @@ def _compare(gpu_fields, ora_fields, rel=REL, what=""):
 
 
 @pytest.mark.parametrize("n,length,transforms", [
-    (64, 2 * np.pi, "auto"), (96, 3.0, "auto"), (512, 2 * np.pi, "builtin"), (1024, 3.0, "auto"),
-    (512, 2 * np.pi, "hipfft")])
+    (8, 2 * np.pi, "auto"), (64, 2 * np.pi, "auto"), (96, 3.0, "auto"), (512, 2 * np.pi, "builtin"),
+    (1024, 3.0, "auto"), (512, 2 * np.pi, "hipfft")])
 def test_matches_oracle_step_by_step(n, length, transforms):
     """Step 0 (band truncation), step 1 (forward Euler), step 2 (first AB2
-    step) and step 30: hipFFT on a small power-of-two grid and on n = 96
+    step) and step 30: hipFFT on the smallest grid (n = 8, band |m| <= 2), on
+    a small power-of-two grid and on n = 96
     (divisible by 3: the edge of the 2/3 rule; radix-3 transforms) with
     L != 2 pi; the library's own transforms at n = 512 and 1024 (L != 2 pi);
     hipFFT at 512 on request."""
@@ -58,6 +60,24 @@ def test_matches_oracle_step_by_step(n, length, transforms):
         o.step(upto - o.steps)
         assert g.steps == upto
         worst = max(worst, _compare(g.get_fields(), o.fields(), what=f"step {upto}"))
+    say(f"n={n}: worst relative difference {worst:.2e}")
+    g.close()
+
+
+def test_largest_grid_matches_oracle():
+    """4096^2, the largest grid here (hipFFT; 1.5 GB of fields), 2 steps,
+    every grid value compared."""
+    n = 4096
+    say(f"n={n}")
+    w0 = synth.random_vorticity(n, 20.0, 26, omega_rms=3.0)
+    g = ns2d.Ns2d(n, 2e-5, 5e-4)
+    assert not g.builtin
+    o = NS2D(n, 2e-5, 5e-4)
+    g.set_vorticity(w0)
+    o.set_vorticity(w0)
+    g.step(2)
+    o.step(2)
+    worst = _compare(g.get_fields(), o.fields(), what="n=4096 step 2")
     say(f"n={n}: worst relative difference {worst:.2e}")
     g.close()
 
@@ -124,6 +144,13 @@ def test_device_vorticity_input_and_velocity_pointers():
         def __init__(self, ptr):
             self.__cuda_array_interface__ = dict(shape=(n, n), typestr="<f8", data=(ptr, False),
                                                  version=3, strides=None)
+
+    # the fields read into device buffers equal the host read-back
+    dev = [torch.empty(n * n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    assert ns2d.load().ns2d_get_fields(b._h, *[d.data_ptr() for d in dev], 1) == ns2d.OK
+    b.synchronize()
+    for d, h in zip(dev, fb):
+        np.testing.assert_array_equal(d.cpu().numpy().reshape(n, n), h)
 
     pu, pv = b.velocity_ptrs()
     b.synchronize()
