@@ -17,11 +17,13 @@
 // writes each spectral array once.
 //
 // For n = 512, 1024 and 2048 the built-in transforms (fft_lds.h) replace
-// the library's and fuse with the pointwise work, in three kernels a step over a
-// transposed spectral layout (entry (row jy, column ix) of a half-plane
-// spectrum at ix * n + jy, so that every column is contiguous):
-//   a. fwd_rows_kernel: the grid product of four rows, two real rows packed
-//      into one complex transform along x, unpacked into two half spectra;
+// the library's and fuse with the pointwise work, in four kernels a step
+// over a transposed spectral layout (entry (row jy, column ix) of a
+// half-plane spectrum at ix * n + jy, so that every column is contiguous)
+// that holds only the columns inside the 2/3 band:
+//   a. fwd_rows_kernel: the grid product of a slab of rows, two real rows
+//      packed into one complex transform along x, unpacked into two half
+//      spectra;
 //   b. column_fwd_kernel: per band column, the transform along y, the band
 //      and the AB2 update; column_emit_kernel: per band column and field,
 //      the field's values and its inverse transform along y;
