@@ -889,8 +889,11 @@ __device__ __forceinline__ int ghost_source(int a, int n)
 }
 
 // Block-wide maximum of m folded into *out with an unsigned max on the
-// binary32 bit pattern (non-negative floats order like their bits).  Every
-// thread of the block must call it.
+// binary32 bit pattern (non-negative floats order like their bits).  The
+// atomic is skipped when *out already holds at least m: *out only grows, so
+// a stale read can only cause an unneeded atomic, never a missed one (with a
+// thousand blocks on one address the atomics are what costs).  Every thread
+// of the block must call it.
 __device__ __forceinline__ void block_max_to(float m, unsigned *out)
 {
     __shared__ float red[kMaxBlock / kWave];
@@ -900,7 +903,8 @@ __device__ __forceinline__ void block_max_to(float m, unsigned *out)
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int k = 1; k < (int)(blockDim.x / kWave); ++k) m = fmaxf(m, red[k]);
-        atomicMax(out, __float_as_uint(m));
+        const unsigned bits = __float_as_uint(m);
+        if (bits > __atomic_load_n(out, __ATOMIC_RELAXED)) atomicMax(out, bits);
     }
 }
 
