@@ -8,14 +8,16 @@ particles (the first 1024 to 10^3 steps, the first 128 to 10^4 steps) twice:
 on the FP64 fields, and on the binary32-rounded fields (which separates the
 field rounding from the arithmetic rounding).  The report -- error quantiles
 in grid spacings by horizon, and the MSD difference relative and in units
-of its standard error -- is written to gpurun_out/precision_report.json and
-printed.  Pass/fail covers only sanity bounds: per-particle trajectories of
+of its standard error -- is printed and written to the file that
+LPT_PRECISION_REPORT names (default: precision_report.json in the system's
+temporary directory).  Pass/fail covers only sanity bounds: per-particle trajectories of
 this chaotic flow decorrelate over T = 10, so long-horizon errors are
 stated, not bounded.  Each particle's GPU result does not depend on the
 other particles in the context, so the subset reproduces its values in the
 full 2^24 run."""
 import json
 import os
+import tempfile
 
 import numpy as np
 import pytest
@@ -85,7 +87,8 @@ def test_fp32_split_error_report():
                                 "msd_diff_in_sem": float(abs(msd_g - msd_o) / sem)}
     text = json.dumps(report, indent=1)
     print(text, flush=True)
-    out = os.environ.get("LPT_PRECISION_REPORT", os.path.join("gpurun_out", "precision_report.json"))
+    out = os.environ.get("LPT_PRECISION_REPORT",
+                         os.path.join(tempfile.gettempdir(), "precision_report.json"))
     try:
         os.makedirs(os.path.dirname(out), exist_ok=True)
         with open(out, "w") as f:
