@@ -365,65 +365,54 @@ def coupled_alg_bytes_per_step(n: int, particles: int) -> int:
 
 
 def bench_coupled(args):
-    """The coupled loop of Alg. coupled_EL on one GPU: per step, the field
-    producer advances the 2048^2 FP64 vorticity (the ns2048 workload), its
-    grid velocity becomes the particle library's newer level by device
-    pointer (ping-pong slots, same stream), and 2^20 FP64 tracers take one
-    bilinear RK4 step between the two levels (cell-order re-sort every 20
-    steps, MSD every 100).  HIP events on the null stream bracket the timed
-    steps."""
+    """The coupled loop of Alg. coupled_EL on one GPU: per step, 2^20 FP64
+    tracers take one bilinear RK4 step between the two current levels
+    (cell-order re-sort every 20 steps, MSD every 100), the field producer
+    advances the 2048^2 FP64 vorticity (the ns2048 workload), and the new
+    level replaces the older one by device pointer, all on one stream.  HIP
+    events bracket the timed steps; the same loop with the field and the
+    particles on two overlapping streams is timed too (it is slower)."""
     import torch
-    from paper_2607_17836_amd import lpt, ns2d, synth
-    n, dt = NS_N, NS_DT
-    g = ns2d.Ns2d(n, NS_NU, dt)
-    g.set_vorticity(synth.random_vorticity(n, NS_K0, NS_SEED, omega_rms=NS_RMS))
-    tr = lpt.Tracker(n, "fp64", sort_interval=20)
-    tr.set_time_mode("pingpong")
-    tr.set_snapshot_device(0, 0.0, *g.velocity_ptrs())
-    g.step(1)
-    tr.set_snapshot_device(1, dt, *g.velocity_ptrs())
-    zeros = np.zeros(COUPLED_PARTICLES)
-    sid = tr.add_species("tracer", 0.0, "bilinear", zeros, zeros)
-    tr.init_uniform(sid, COUPLED_SEED)
-    done = [0]
-
-    def run(k):
-        for _ in range(k):
-            s = done[0]
-            tr.step(1, dt, 100)
-            g.step(1)
-            tr.set_snapshot_device(s % 2, (s + 2) * dt, *g.velocity_ptrs())
-            done[0] += 1
-
-    run(args.warmup)
-    tr.synchronize()
-    g.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record()
-    run(args.steps)
-    e1.record()
-    tr.synchronize()
-    g.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    step_us = 1e3 * e0.elapsed_time(e1) / args.steps
-    xw, yw, _, _ = tr.get_positions(sid)
-    tr.close()
-    g.close()
-    if not (np.isfinite(xw).all() and np.isfinite(yw).all()):
-        raise RuntimeError("coupled2048: non-finite particle positions")
-    ab = coupled_alg_bytes_per_step(n, COUPLED_PARTICLES)
-    log(f"[bench] coupled2048: {args.steps} steps in {wall:.3f} s; {step_us:.1f} us per coupled step by events")
-    cfg = {"workload": "coupled2048_fp64_ns_ab2_plus_2p20_tracers", "grid": n, "particles": COUPLED_PARTICLES,
-           "nu": NS_NU, "dt": dt, "k0": NS_K0, "omega_rms": NS_RMS, "precision": "fp64",
-           "scheme": "bilinear", "sort_interval": 20, "stats_every": 100, "parallelism": "1 GPU"}
+    from paper_2607_17836_amd import coupled, synth
+    w0 = synth.random_vorticity(NS_N, NS_K0, NS_SEED, omega_rms=NS_RMS)
+    out = {}
+    for streams in (1, 2):
+        loop = coupled.CoupledLoop(NS_N, NS_NU, NS_DT, w0, precision="fp64", streams=streams,
+                                   sort_interval=20)
+        zeros = np.zeros(COUPLED_PARTICLES)
+        sid = loop.tracker.add_species("tracer", 0.0, "bilinear", zeros, zeros)
+        loop.tracker.init_uniform(sid, COUPLED_SEED)
+        steps = args.steps if streams == 1 else max(1, args.steps // 2)
+        loop.step(args.warmup, 100)
+        loop.synchronize()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        loop.record_event(e0)
+        loop.step(steps, 100)
+        loop.record_event(e1)
+        loop.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        xw, yw, _, _ = loop.tracker.get_positions(sid)
+        loop.close()
+        if not (np.isfinite(xw).all() and np.isfinite(yw).all()):
+            raise RuntimeError("coupled2048: non-finite particle positions")
+        out[streams] = (1e3 * e0.elapsed_time(e1) / steps, wall / steps)
+    step_us, wall_step = out[1]
+    ab = coupled_alg_bytes_per_step(NS_N, COUPLED_PARTICLES)
+    log(f"[bench] coupled2048: {step_us:.1f} us per coupled step on one stream, "
+        f"{out[2][0]:.1f} us on two")
+    cfg = {"workload": "coupled2048_fp64_ns_ab2_plus_2p20_tracers", "grid": NS_N,
+           "particles": COUPLED_PARTICLES, "nu": NS_NU, "dt": NS_DT, "k0": NS_K0,
+           "omega_rms": NS_RMS, "precision": "fp64", "scheme": "bilinear", "sort_interval": 20,
+           "stats_every": 100, "streams": 1, "parallelism": "1 GPU"}
     roof = {"bound": "hbm", "achieved": ab / (step_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": ab / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS, "traffic": None,
             "kernel": "whole coupled step: field step + ingest of the new level + tracer step",
-            "kernel_avg_us": step_us, "alg_bytes_per_step": ab}
-    return args.steps / wall, 1e3 * wall / args.steps, cfg, roof
+            "kernel_avg_us": step_us, "two_stream_step_us": out[2][0],
+            "alg_bytes_per_step": ab}
+    return 1.0 / wall_step, 1e3 * wall_step, cfg, roof
 
 
 def cpu_baseline_ns(budget_steps=3):
