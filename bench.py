@@ -357,10 +357,10 @@ COUPLED_PARTICLES, COUPLED_SEED = 1 << 20, 71
 
 def coupled_alg_bytes_per_step(n: int, particles: int) -> int:
     """One coupled step: the field step, the ingest of the new level (u and v
-    read for the node records and again for the largest speed, the level's
-    half of each 32-byte FP64 record written) and the FP64 tracer step
-    (state read and written, both levels of the field read once)."""
-    return (ns_alg_bytes_per_step(n) + 48 * n * n
+    read once, for the node records and the largest speed together; the
+    level's half of each 32-byte FP64 record written) and the FP64 tracer
+    step (state read and written, both levels of the field read once)."""
+    return (ns_alg_bytes_per_step(n) + 32 * n * n
             + particles * 2 * state_bytes("fp64", "tracer", 0.0) + field_pair_bytes(n, "fp64"))
 
 

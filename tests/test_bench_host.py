@@ -40,9 +40,10 @@ def test_field_step_algorithmic_bytes():
 
 def test_coupled_step_algorithmic_bytes():
     """A coupled step adds to the field step the ingest of the new level
-    (48 n^2 bytes) and the FP64 tracer step (64 B per tracer, both levels
-    of the 32-byte node records read once)."""
+    (u, v read once and half of each 32-byte record written: 32 n^2 bytes)
+    and the FP64 tracer step (64 B per tracer, both levels of the 32-byte
+    node records read once)."""
     import bench
     n, m = 2048, 1 << 20
-    assert bench.coupled_alg_bytes_per_step(n, m) == (bench.ns_alg_bytes_per_step(n) + 48 * n * n
+    assert bench.coupled_alg_bytes_per_step(n, m) == (bench.ns_alg_bytes_per_step(n) + 32 * n * n
                                                        + 64 * m + 32 * n * n)
