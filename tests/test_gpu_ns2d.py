@@ -268,3 +268,38 @@ def test_coupled_loop_on_two_streams_equals_one_stream():
     np.testing.assert_array_equal(out[0][2], out[1][2])
     for qa, qb in zip(out[0][3], out[1][3]):
         np.testing.assert_array_equal(qa, qb)
+
+
+def test_coupled_loop_fp32_split_tracers_match_the_oracles():
+    """The producer's FP64 levels streamed into an FP32-split tracker (the
+    FP32 ingest from device pointers): 8 coupled steps against the field
+    oracle's levels rounded to binary32 and stepped by the particle oracle;
+    binary32 velocities bound the position error by 1e-6 (as in the FP32
+    parity tests)."""
+    from paper_2607_17836_amd import coupled
+    n, nu, dt, nsteps = 512, 1e-3, 2e-3, 8
+    say("coupled loop fp32_split")
+    w0 = synth.random_vorticity(n, 8.0, 28, omega_rms=3.0)
+    x0, y0 = oracle.init_uniform(84, 4000)
+    loop = coupled.CoupledLoop(n, nu, dt, w0, precision="fp32_split", sort_interval=4)
+    sid = loop.tracker.add_species("tracer", 0.0, "bilinear", x0, y0)
+    loop.step(nsteps)
+    xw, yw, _, _ = loop.tracker.get_positions(sid)
+    loop.close()
+
+    o = NS2D(n, nu, dt)
+    o.set_vorticity(w0)
+    r32 = lambda f: f.astype(np.float32).astype(np.float64)
+    levels = [tuple(r32(f) for f in o.fields()[:2])]
+    for _ in range(nsteps):
+        o.step(1)
+        levels.append(tuple(r32(f) for f in o.fields()[:2]))
+    sp = oracle.Species(x0, y0)
+    for k in range(nsteps):
+        (ua, va), (ub, vb) = levels[k], levels[k + 1]
+        fl = oracle.grid_flow(ua, va, ub, vb, t_slot=(k * dt, (k + 1) * dt))
+        oracle.run(fl, sp, 1, dt, t_start=k * dt, step0=k)
+    d = np.abs(np.concatenate([xw - sp.xw, yw - sp.yw])) % (2 * np.pi)
+    err = np.minimum(d, 2 * np.pi - d).max()
+    say(f"coupled fp32_split: max position error {err:.2e}")
+    assert err < 1e-6
