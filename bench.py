@@ -12,7 +12,8 @@ every 16 steps (applied by the following step's kernel) and the FP64
 MSD/dispersion reduction every 100 steps, all inside the timed region.  Inputs
 are resident in HBM before timing starts.
 
-Other workloads (--workload): spec4096_split_share8 (the headline with 2^21
+Other workloads (--workload): spec4096_fp64 (the headline in FP64 positions
+and fields), spec4096_split_share8 (the headline with 2^21
 tracers: one GPU's share on eight, same full field), batch2048 (8
 Stokes-number species, all three schemes, one launch per species, autotuned
 launch shape), spec1024_fp64 (FP64 tracers + inertial particles, --scheme),
@@ -437,7 +438,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="spec4096_split",
-                    choices=["spec4096_split", "spec4096_split_share8", "batch2048",
+                    choices=["spec4096_split", "spec4096_fp64", "spec4096_split_share8", "batch2048",
                              "spec1024_fp64", "tg64",
                              "adjoint2048", "ns2048", "coupled2048"])
     ap.add_argument("--scheme", default="bilinear", choices=["bilinear", "catmull_rom", "bspline"],
@@ -496,6 +497,10 @@ def main():
         fp64_twin = False
         if args.workload == "spec4096_split_share8":
             w = workloads.C3_SHARE8
+        elif args.workload == "spec4096_fp64":
+            w = dataclasses.replace(workloads.C3_SPLIT, name="spec4096_fp64_bilinear_2p24",
+                                    precision="fp64")
+            dtype = "f64"
         elif args.workload == "spec4096_split":
             w = workloads.C3_SPLIT
             fp64_twin = True
