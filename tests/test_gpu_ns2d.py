@@ -175,24 +175,25 @@ def test_errors():
     g.close()
 
 
-@pytest.mark.parametrize("n", [128, 512])
-def test_coupled_loop_matches_the_oracles(n):
+@pytest.mark.parametrize("n,length", [(128, 2 * np.pi), (512, 2 * np.pi), (512, 3.0)])
+def test_coupled_loop_matches_the_oracles(n, length):
     """The producer's velocity streamed into the particle library each step
     (ping-pong slots, device pointers, same stream), tracers and inertial
     particles, against the field oracle feeding the particle oracle the same
     levels: positions within 1e-10 after 10 steps (hipFFT at n = 128, the
-    library's own transforms at 512)."""
+    library's own transforms at 512; a domain of side 3 as well as 2 pi)."""
     nu, dt, nsteps = 1e-3, 2e-3, 10
-    say(f"coupled loop n={n}")
+    L = length
+    say(f"coupled loop n={n} L={L}")
     w0 = synth.random_vorticity(n, 8.0, 24, omega_rms=5.0)
-    g = ns2d.Ns2d(n, nu, dt)
+    g = ns2d.Ns2d(n, nu, dt, length=L)
     g.set_vorticity(w0)
-    tr = lpt.Tracker(n, "fp64")
+    tr = lpt.Tracker(n, "fp64", length=L)
     tr.set_time_mode("pingpong")
     tr.set_snapshot_device(0, 0.0, *g.velocity_ptrs())
     g.step(1)
     tr.set_snapshot_device(1, dt, *g.velocity_ptrs())
-    x0, y0 = oracle.init_uniform(81, 2000)
+    x0, y0 = oracle.init_uniform(81, 2000, L)
     rng = np.random.default_rng(82)
     vx0, vy0 = rng.normal(size=500), rng.normal(size=500)
     st = tr.add_species("tracer", 0.0, "bilinear", x0, y0)
@@ -206,23 +207,25 @@ def test_coupled_loop_matches_the_oracles(n):
     tr.close()
     g.close()
 
-    o = NS2D(n, nu, dt)
+    o = NS2D(n, nu, dt, length=L)
     o.set_vorticity(w0)
     levels = [o.fields()[:2]]
     for _ in range(nsteps):
         o.step(1)
         levels.append(o.fields()[:2])
-    sp_t = oracle.Species(x0, y0)
-    sp_i = oracle.Species(x0[:500], y0[:500], kind=oracle.INERTIAL, st=0.2, vx0=vx0, vy0=vy0)
+    sp_t = oracle.Species(x0, y0, length=L)
+    sp_i = oracle.Species(x0[:500], y0[:500], kind=oracle.INERTIAL, st=0.2, vx0=vx0, vy0=vy0,
+                          length=L)
     for k in range(nsteps):
         (ua, va), (ub, vb) = levels[k], levels[k + 1]
         for sp, scheme in ((sp_t, oracle.BILINEAR), (sp_i, oracle.CATMULL_ROM)):
-            fl = oracle.grid_flow(ua, va, ub, vb, scheme=scheme, t_slot=(k * dt, (k + 1) * dt))
+            fl = oracle.grid_flow(ua, va, ub, vb, scheme=scheme, t_slot=(k * dt, (k + 1) * dt),
+                                  length=L)
             oracle.run(fl, sp, 1, dt, t_start=k * dt, step0=k)
 
     def pdist(a, b):
-        d = np.abs(np.asarray(a) - np.asarray(b)) % (2 * np.pi)
-        return np.minimum(d, 2 * np.pi - d)
+        d = np.abs(np.asarray(a) - np.asarray(b)) % L
+        return np.minimum(d, L - d)
 
     for got, sp in ((xt, sp_t), (xi, sp_i)):
         assert np.max(pdist(got[0], sp.xw)) < 1e-10 and np.max(pdist(got[1], sp.yw)) < 1e-10
