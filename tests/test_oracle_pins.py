@@ -362,6 +362,55 @@ def test_rk4_fourth_order_in_analytic_flow():
     assert 14.0 < r1 < 18.5 and 14.0 < r2 < 18.5, errs
 
 
+@pytest.mark.parametrize("t", [0.37, 1.1, 2.9])
+def test_oscillating_tg_stagnation_points_follow_the_shift(t):
+    """Eq. kinematic_flow translates the steady cellular flow by
+    (eps sin(omega t), eps sin(omega t + phi)), so every hyperbolic
+    stagnation point of the steady flow, (m pi / k, l pi / k), moves with that
+    shift: the velocity vanishes there at every t.  k != 1, alpha != 1 and
+    phi != 0 with sin(omega t) != 0, so that the shift on the wrong axis, the
+    wrong sign of eps sin(omega t), or k applied to x alone fails; a point a
+    tenth of a cell away still moves."""
+    al, k, eps, om, phi = 1.5, 2.0, 0.3, 1.8, 1.0
+    fl = oracle.tg_flow(alpha=al, k=k, eps=eps, omega=om, phi=phi)
+    sx, sy = eps * np.sin(om * t), eps * np.sin(om * t + phi)
+    m, l = np.meshgrid(np.arange(-2, 3), np.arange(-2, 3))
+    x = m.ravel() * np.pi / k + sx
+    y = l.ravel() * np.pi / k + sy
+    u, v = oracle.velocity(fl, x, y, t)
+    assert np.max(np.abs(u)) < 1e-14 and np.max(np.abs(v)) < 1e-14
+    u, v = oracle.velocity(fl, x + 0.1, y - 0.1, t)
+    assert np.min(np.hypot(u, v)) > 0.1
+
+
+@pytest.mark.parametrize("corner", [0, 1])
+def test_oscillating_tg_linearised_trajectory_closed_form(corner):
+    """Near a stagnation point (cx, cy) of eq. kinematic_flow the flow is the
+    time-shifted linear strain x' = A (x - cx - eps sin wt),
+    y' = -A (y - cy - eps sin(wt + phi)), A = +-alpha k, up to terms cubic in
+    the distance.  A tracer released at (cx, cy) with eps = 1e-5 then follows
+    the closed form of that linear system,
+        dx(t) = -A eps (w e^{A t} - A sin wt - w cos wt) / (A^2 + w^2),
+        dy(t) =  A eps (A sin(wt + phi) - w cos(wt + phi)
+                        - e^{-A t} (A sin phi - w cos phi)) / (A^2 + w^2),
+    to ~1e-12 while the displacements are ~1e-4.  This checks the time
+    argument that the RK4 stages pass to the flow: a stage evaluated at the
+    wrong time, a sign error in the shift or the phase on the wrong axis
+    moves the result by at least 1e-7."""
+    al, k, eps, om, phi = 1.5, 2.0, 1e-5, 1.8, 1.0
+    fl = oracle.tg_flow(alpha=al, k=k, eps=eps, omega=om, phi=phi)
+    cx, A = (0.0, al * k) if corner == 0 else (np.pi / k, -al * k)
+    sp = oracle.Species([cx], [0.0])
+    T = 1.0
+    oracle.run(fl, sp, 1000, T / 1000)
+    D = A * A + om * om
+    ex = -A * eps * (om * np.exp(A * T) - A * np.sin(om * T) - om * np.cos(om * T)) / D
+    ey = A * eps * (A * np.sin(om * T + phi) - om * np.cos(om * T + phi)
+                    - np.exp(-A * T) * (A * np.sin(phi) - om * np.cos(phi))) / D
+    assert min(abs(ex), abs(ey)) > 5e-6
+    assert abs(sp.dx[0] - ex) < 1e-10 and abs(sp.dy[0] - ey) < 1e-10, (sp.dx, ex, sp.dy, ey)
+
+
 def test_grid_tg_interpolation_error_is_second_order():
     """Bilinear interpolation of the gridded Taylor-Green field has O(h^2)
     error: doubling n divides the path error by ~4."""
