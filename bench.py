@@ -55,11 +55,20 @@ def log(*a):
 
 
 def state_bytes(precision: str, kind: str, st: float) -> int:
-    """Bytes of one particle's state read (and again written) per step."""
+    """Algorithmic bytes of one particle's state, read (and again written)
+    once per step: a position (FP64: two doubles; FP32 split: two int32
+    cells and two binary32 offsets), the FP64 unwrapped displacement and,
+    for inertial particles, the velocity (FP64 or binary32)."""
     inertial = kind == "inertial" and st > 0
-    if precision == "fp32_split":   # packed cell u32 + float2 offset + double2 displacement
-        return 4 + 8 + 16 + (8 if inertial else 0)
-    return 16 + 16 + (16 if inertial else 0)   # double2 pos + double2 disp (+ double2 vel)
+    if precision == "fp32_split":
+        return 8 + 8 + 16 + (8 if inertial else 0)
+    return 16 + 16 + (16 if inertial else 0)
+
+
+def layout_state_bytes(precision: str, kind: str, st: float) -> int:
+    """Bytes the library's own layout moves: the FP32-split cell pair is
+    packed into one 32-bit word (cy << 16 | cx)."""
+    return state_bytes(precision, kind, st) - (4 if precision == "fp32_split" else 0)
 
 
 def field_pair_bytes(n: int, precision: str) -> int:
@@ -67,8 +76,9 @@ def field_pair_bytes(n: int, precision: str) -> int:
     return n * n * (16 if precision == "fp32_split" else 32)
 
 
-def alg_bytes_per_step(w) -> float:
-    state = sum(cnt * 2 * state_bytes(w.precision, kind, st) for kind, st, _, cnt, _ in w.species)
+def alg_bytes_per_step(w, layout=False) -> float:
+    sb = layout_state_bytes if layout else state_bytes
+    state = sum(cnt * 2 * sb(w.precision, kind, st) for kind, st, _, cnt, _ in w.species)
     return state + field_pair_bytes(w.n, w.precision)
 
 
@@ -91,10 +101,12 @@ def measured_traffic(workload: str):
     return tf.get("hbm_bytes_per_launch")
 
 
-def run_gpu(w, steps, warmup, lpt, tuning=None, **over):
+def run_gpu(w, steps, warmup, lpt, tuning=None, calib_steps=0, **over):
     """Time `steps` steps after `warmup` untimed ones.  Returns (elapsed s,
-    library timing dict, stats records of species 0).  Per-kernel HIP events
-    are on (graph chunks are then replaced by eager launches)."""
+    library timing dict, stats records of species 0, timing dict of
+    `calib_steps` further steps taken after the timed window, or None).
+    Per-kernel HIP events are on (graph chunks are then replaced by eager
+    launches)."""
     import torch
     from paper_2607_17836_amd import workloads
     tr = None
@@ -116,7 +128,11 @@ def run_gpu(w, steps, warmup, lpt, tuning=None, **over):
         elapsed = time.perf_counter() - t0
         timing = tr.get_timing(reset=True)
         nstats = len(tr.get_stats(0))
-        return elapsed, timing, nstats
+        calib = None
+        if calib_steps:
+            tr.step(calib_steps, w.dt, w.stats_every)
+            calib = tr.get_timing(reset=True)
+        return elapsed, timing, nstats, calib
     finally:
         if tr is not None:
             tr.close()
@@ -183,26 +199,48 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False):
     if args.block_size:
         over["block_size"] = args.block_size
     npart = w.particles
-    elapsed, timing, nstats = run_gpu(w, args.steps, args.warmup, lpt, tuning, **over)
+    calib_steps = max(w.stats_every, w.sort_interval)
+    elapsed, timing, nstats, calib = run_gpu(w, args.steps, args.warmup, lpt, tuning,
+                                             calib_steps=calib_steps, **over)
     value = npart * args.steps / elapsed
-    kern_ms = timing["step_kernel_ms"] / max(1, timing["step_launches"])
+
+    def avg(t, ms, n):
+        return t[ms] / t[n] if t[n] else None
+
+    kern_ms = avg(timing, "step_kernel_ms", "step_launches") or avg(calib, "step_kernel_ms",
+                                                                     "step_launches")
     bytes_per_launch = alg_bytes_per_step(w)
     achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
-    perm_us = 1e3 * timing["perm_step_ms"] / max(1, timing["perm_steps"])
-    sort_us = 1e3 * timing["sort_ms"] / max(1, timing["sorts"])
+    perm_ms = avg(timing, "perm_step_ms", "perm_steps") or avg(calib, "perm_step_ms", "perm_steps")
+    sort_ms = avg(timing, "sort_ms", "sorts") or avg(calib, "sort_ms", "sorts")
+    stat_ms = avg(calib, "stats_step_ms", "stats_steps")
+    fin_ms = calib["finalize_ms"] / calib["stats_steps"] if calib["stats_steps"] else None
+    # device time per step over the workload's schedule, from the parts:
+    # in-place steps, plus per re-sort (every sort_interval steps) the keys +
+    # radix sort and the permuting step's excess, plus per record (every
+    # stats_every steps) the statistics variant's excess and the merge
+    sched_ms = kern_ms
+    if w.sort_interval and perm_ms is not None and sort_ms is not None:
+        sched_ms += (perm_ms - kern_ms + sort_ms) / w.sort_interval
+    if w.stats_every and stat_ms is not None:
+        sched_ms += (stat_ms - kern_ms + fin_ms) / w.stats_every
+    perm_us = 1e3 * perm_ms if perm_ms is not None else None
+    sort_us = 1e3 * sort_ms if sort_ms is not None else None
     # share of the timed wall time spent on re-sorting: keys + radix sort, and
     # what the permuting steps cost beyond an in-place step
     resort_s = 1e-3 * (timing["sort_ms"] + timing["perm_step_ms"]
                        - timing["perm_steps"] * kern_ms)
     log(f"[bench] {args.steps} steps in {elapsed:.3f} s; in-place step kernel {kern_ms * 1e3:.1f} us "
-        f"avg over {timing['step_launches']} launches; permuting step {perm_us:.1f} us avg over "
-        f"{timing['perm_steps']}; sort (keys + radix) {sort_us:.1f} us avg over "
-        f"{timing['sorts']}; {nstats} stats records")
+        f"avg over {timing['step_launches']} launches; permuting step "
+        f"{perm_us or 0:.1f} us; sort (keys + radix) {sort_us or 0:.1f} us; "
+        f"{nstats} stats records in the window; statistics step "
+        f"{(stat_ms or 0) * 1e3:.1f} us + merge {(fin_ms or 0) * 1e3:.1f} us "
+        f"(calibration: {calib_steps} more steps); schedule {sched_ms * 1e3:.1f} us per step")
     extra = {}
     if fp64_twin and not args.no_fp64:
         w64 = dataclasses.replace(w, name=w.name.replace("fp32split", "fp64"), precision="fp64")
         k64 = max(100, args.steps // 4)
-        e64, t64, _ = run_gpu(w64, k64, min(args.warmup, 20), lpt, tuning, **over)
+        e64, t64, _, _ = run_gpu(w64, k64, min(args.warmup, 20), lpt, tuning, **over)
         k64us = 1e3 * t64["step_kernel_ms"] / max(1, t64["step_launches"])
         extra["fp64_same_workload"] = {
             "value": npart * k64 / e64, "unit": "particle-steps/s", "steps": k64,
@@ -219,21 +257,32 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False):
            "tile_records": tun.get("tile_records", args.tile_records),
            "block_size": tun.get("block_size", args.block_size or 256),
            "persistent": tun.get("persistent", 0), "parallelism": "1 GPU"}
+    ms_step = 1e3 * elapsed / args.steps
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
             "kernel": step_kernel_name(w), "kernel_avg_us": kern_ms * 1e3,
             "kernel_launches": timing["step_launches"],
-            "note": "kernel = the in-place step; the step right after each re-sort is a "
-                    "separate kernel that also applies the sort's permutation "
-                    "(perm_step_avg_us); keys + radix sort per re-sort in sort_avg_us; "
-                    "value and ms_per_step include both",
-            "perm_step_avg_us": perm_us if timing["perm_steps"] else None,
-            "perm_steps": timing["perm_steps"],
-            "sort_avg_us": sort_us if timing["sorts"] else None,
+            "note": "kernel = the in-place step without a statistics record; the step "
+                    "right after each re-sort is a separate kernel that also applies the "
+                    "sort's permutation (perm_step_avg_us); keys + radix sort per re-sort in "
+                    "sort_avg_us; a record step runs the statistics variant "
+                    "(stats_step_avg_us) plus the merge (finalize_avg_us); value and "
+                    "ms_per_step include everything in the timed window; "
+                    "schedule_ms_per_step weights the parts by the workload's re-sort and "
+                    "record intervals; frac_end_to_end divides the algorithmic bytes by "
+                    "ms_per_step",
+            "perm_step_avg_us": perm_us, "perm_steps": timing["perm_steps"],
+            "sort_avg_us": sort_us,
+            "stats_step_avg_us": 1e3 * stat_ms if stat_ms is not None else None,
+            "finalize_avg_us": 1e3 * fin_ms if fin_ms is not None else None,
+            "schedule_ms_per_step": sched_ms,
+            "frac_schedule": bytes_per_launch / (sched_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "frac_end_to_end": bytes_per_launch / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "resort_share_of_time": resort_s / elapsed,
             "alg_bytes_per_particle_step": bytes_per_launch / npart,
-            "alg_bytes_per_launch": bytes_per_launch}
-    return value, 1e3 * elapsed / args.steps, cfg, roof, extra
+            "alg_bytes_per_launch": bytes_per_launch,
+            "layout_bytes_per_particle_step": alg_bytes_per_step(w, layout=True) / npart}
+    return value, ms_step, cfg, roof, extra
 
 
 def bench_adjoint(args, lpt):
@@ -269,8 +318,7 @@ def bench_adjoint(args, lpt):
 
     t_fwd, _ = timed(lambda: tr.forward_checkpointed(nsteps, dt, every))
     t_adj, (gx, gy, gU) = timed(lambda: tr.adjoint(a, b))
-    t_jac, F = timed(lambda: tr.jacobian())
-    sig = lpt.ftle(F, nsteps * dt)
+    t_jac, sig = timed(lambda: tr.ftle())   # Jacobian sweep + FTLE in the library
     tr.close()
     log(f"[bench] adjoint2048: forward {t_fwd:.3f} s, reverse+grid {t_adj:.3f} s, "
         f"jacobian {t_jac:.3f} s; FTLE mean {np.mean(sig):.4f}, max {np.max(sig):.4f}")
@@ -310,17 +358,17 @@ def ns_alg_bytes_per_step(n: int) -> int:
     return 4 * grid + spec + 9 * spec + 4 * (spec + grid)
 
 
-def bench_ns(args):
-    """The Eulerian field producer on the 2048^2 grid in FP64: random-phase
-    initial vorticity (k0 = 10, rms 3), nu = 1e-4, dt = 1e-3; one step with
+def bench_ns(args, n=NS_N, dt=NS_DT):
+    """The Eulerian field producer on the n^2 grid in FP64 (2048^2, or 4096^2
+    with dt = 5e-4: |k u| dt = 0.38 at the highest kept wavenumber):
+    random-phase initial vorticity (k0 = 10, rms 3), nu = 1e-4; one step with
     the library's own transforms = forward row pass (grid product and x
     transforms), column pass (y transforms, AB2, the four fields) and
     inverse row pass.  HIP events on the null stream, which the producer
     runs on; the fields are checked finite afterwards."""
     import torch
     from paper_2607_17836_amd import ns2d, synth
-    n = NS_N
-    g = ns2d.Ns2d(n, NS_NU, NS_DT)
+    g = ns2d.Ns2d(n, NS_NU, dt)
     g.set_vorticity(synth.random_vorticity(n, NS_K0, NS_SEED, omega_rms=NS_RMS))
     g.step(args.warmup)
     g.synchronize()
@@ -338,11 +386,11 @@ def bench_ns(args):
     u, v, w, psi = g.get_fields()
     g.close()
     if not (np.isfinite(w).all() and np.isfinite(u).all()):
-        raise RuntimeError("ns2048: the flow left the stable range (non-finite fields)")
+        raise RuntimeError(f"ns{n}: the flow left the stable range (non-finite fields)")
     step_us = 1e3 * ev_ms / args.steps
     ab = ns_alg_bytes_per_step(n)
-    log(f"[bench] ns2048: {args.steps} steps in {wall:.3f} s; {step_us:.1f} us per step by events")
-    cfg = {"workload": "ns2048_fp64_ab2_vorticity", "grid": n, "nu": NS_NU, "dt": NS_DT,
+    log(f"[bench] ns{n}: {args.steps} steps in {wall:.3f} s; {step_us:.1f} us per step by events")
+    cfg = {"workload": f"ns{n}_fp64_ab2_vorticity", "grid": n, "nu": NS_NU, "dt": dt,
            "k0": NS_K0, "omega_rms": NS_RMS, "precision": "fp64", "parallelism": "1 GPU"}
     roof = {"bound": "hbm", "achieved": ab / (step_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": ab / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS, "traffic": None,
@@ -440,7 +488,7 @@ def main():
     ap.add_argument("--workload", default="spec4096_split",
                     choices=["spec4096_split", "spec4096_fp64", "spec4096_split_share8", "batch2048",
                              "spec1024_fp64", "tg64",
-                             "adjoint2048", "ns2048", "coupled2048"])
+                             "adjoint2048", "ns2048", "ns4096", "coupled2048"])
     ap.add_argument("--scheme", default="bilinear", choices=["bilinear", "catmull_rom", "bspline"],
                     help="scheme of the spec1024_fp64 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -474,12 +522,13 @@ def main():
     metric = METRIC
     w = None
     unit = "particle-steps/s"
-    if args.workload == "ns2048":
-        value, ms_per_step, cfg, roof = bench_ns(args)
+    if args.workload in ("ns2048", "ns4096"):
+        nn = int(args.workload[2:])
+        value, ms_per_step, cfg, roof = bench_ns(args, nn, NS_DT if nn == 2048 else 5e-4)
         dtype = "f64"
         unit = "steps/s"
-        metric = "field steps/s (pseudospectral AB2 vorticity step), 2048^2 FP64"
-        if not args.no_cpu_baseline:
+        metric = f"field steps/s (pseudospectral AB2 vorticity step), {nn}^2 FP64"
+        if not args.no_cpu_baseline and nn == 2048:
             extra["cpu_baseline"] = cpu_baseline_ns()
     elif args.workload == "coupled2048":
         value, ms_per_step, cfg, roof = bench_coupled(args)

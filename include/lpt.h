@@ -82,6 +82,12 @@ typedef enum { LPT_TIME_BRACKET = 0, LPT_TIME_PINGPONG = 1 } lpt_time_mode;
 #define LPT_FLAG_TIME_KERNELS 0x2u /* record HIP events around every step-kernel
                                       launch and every re-sort, on the context
                                       stream (see lpt_get_timing)               */
+#define LPT_FLAG_DETERMINISTIC_GRAD 0x4u /* lpt_adjoint sums the grid gradient
+                                      exactly in fixed point (each contribution
+                                      rounded once to a multiple of 2^-64, |entries|
+                                      below 2^31): the same bits on every run and
+                                      launch shape; needs 64 n^2 bytes of device
+                                      memory more during the sweep              */
 
 typedef struct {
     int32_t n;              /* grid points per side, 4 <= n <= 32768          */
@@ -206,15 +212,22 @@ lpt_status lpt_get_order(lpt_ctx *ctx, int32_t species_id, int32_t *ids, int32_t
  * reset, measured with HIP events on the context stream (needs
  * LPT_FLAG_TIME_KERNELS; synchronises the stream).  A step that follows a
  * re-sort also applies the sort's permutation to the state (a kernel of its
- * own); it is counted under perm_step_ms, not step_kernel_ms. */
+ * own); it is counted under perm_step_ms, not step_kernel_ms.  A step that
+ * takes a statistics record (and is no permuting step) runs the step
+ * kernel's statistics variant, counted under stats_step_ms; the merge of its
+ * partials into the records under finalize_ms. */
 typedef struct {
-    double step_kernel_ms;    /* sum over in-place step-kernel launches      */
+    double step_kernel_ms;    /* sum over in-place step launches without a
+                                 statistics record                           */
     int64_t step_launches;
     double sort_ms;           /* sum over re-sorts (keys, radix sort; and the
                                  permutation where lpt_sort applies it)      */
     int64_t sorts;
     double perm_step_ms;      /* sum over steps that apply a permutation     */
     int64_t perm_steps;
+    double stats_step_ms;     /* sum over in-place steps taking a record     */
+    int64_t stats_steps;
+    double finalize_ms;       /* sum over the records' merge kernels         */
 } lpt_timing;
 lpt_status lpt_get_timing(lpt_ctx *ctx, lpt_timing *out, int32_t reset);
 
@@ -264,6 +277,15 @@ typedef struct {
                                Particles whose stencil leaves the tile gather
                                from global memory, so it never affects
                                results                                        */
+    int32_t max_workgroups; /* > 0: a persistent launch holds at most this many
+                               workgroups (below the resident capacity), so
+                               that each walks several logical blocks; 0:
+                               the resident capacity                          */
+    int32_t fused;          /* 1 (default): with several species, one step
+                               launch covers them all, each XCD taking the
+                               same share of every species in cell order;
+                               0: one launch per species (LPT_FP32_SPLIT) or
+                               one launch in species order (LPT_FP64)         */
 } lpt_tuning;
 
 lpt_status lpt_get_tuning(lpt_ctx *ctx, lpt_tuning *out);
@@ -300,7 +322,8 @@ lpt_status lpt_forward_checkpointed(lpt_ctx *ctx, int64_t nsteps, double dt, int
  *   gx_0, gy_0: dL/dx_0, dL/dy_0 per particle (np doubles each);
  *   gU: dL/d(grid value), [slot 0, 1][u, v][n][n] doubles (4 n^2),
  *       x fastest; summed with FP64 atomics, so the last bits depend on
- *       scheduling.
+ *       scheduling, unless the context has LPT_FLAG_DETERMINISTIC_GRAD
+ *       (then bit-reproducible).
  * All arrays are host or device memory per on_device. */
 lpt_status lpt_adjoint(lpt_ctx *ctx, const double *gx_T, const double *gy_T, double *gx_0,
                        double *gy_0, double *gU, int32_t on_device);
@@ -311,6 +334,15 @@ lpt_status lpt_adjoint(lpt_ctx *ctx, const double *gx_T, const double *gy_T, dou
  * 2x2; finite-time Lyapunov exponent (1/T) ln sqrt(lambda_max(F^T F))).
  * np * 4 doubles, host or device memory per on_device. */
 lpt_status lpt_jacobian(lpt_ctx *ctx, double *F, int32_t on_device);
+
+/* Finite-time Lyapunov exponent of every particle over the last
+ * lpt_forward_checkpointed run of nsteps steps of size dt:
+ * sigma[p] = (1/T) ln sqrt(lambda_max(F^T F)), T = nsteps * dt, F the
+ * Jacobian of lpt_jacobian (from the same reverse sweep; F may be NULL,
+ * else it receives the Jacobians as lpt_jacobian writes them).  np doubles
+ * (4 np for F) in original particle order, host or device memory per
+ * on_device.  Errors as lpt_jacobian. */
+lpt_status lpt_ftle(lpt_ctx *ctx, double *sigma, double *F, int32_t on_device);
 
 /* ---- primitives exposed for verification -------------------------------- */
 

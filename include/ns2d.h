@@ -67,11 +67,11 @@ typedef struct {
     double nu;          /* kinematic viscosity >= 0                             */
     double dt;          /* time step > 0                                        */
     void *hip_stream;   /* hipStream_t to enqueue on; NULL = null stream        */
-    int32_t transforms; /* 0: the library's own LDS transforms, fused with the
-                           pointwise work, for n = 512, 1024 and 2048, hipFFT
-                           for every other n; 1: hipFFT for every n; 2: the
-                           library's own transforms, for n = 512, 1024 or
-                           2048 only (else NS2D_E_ARG)                      */
+    int32_t transforms; /* 0 (default) or 2: the library's own LDS
+                           transforms, fused with the pointwise work, for n
+                           a power of two from 64 to 4096 (else NS2D_E_ARG);
+                           1: hipFFT, for any even n (a cross-check path,
+                           and the only one for other n)                    */
 } ns2d_config;
 
 /* Create a context on the current HIP device: allocates the spectral state,

@@ -44,18 +44,39 @@ def build_ns(verbose: bool = False) -> str:
     return NS_LIB
 
 
-def build(verbose: bool = False) -> str:
-    build_ns(verbose)
-    srcs = []
-    for s in SOURCES:
-        path = os.path.join(CSRC, s)
-        # .cpp host sources go through hipcc as HIP too (they use the HIP runtime)
-        srcs += (["-x", "hip", path] if s.endswith(".cpp") else [path])
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
+def _compile(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    return subprocess.run(cmd).returncode
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source of liblpt.so to an object (in parallel), link the
+    library in-tree, then build libns2d.so."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(ROOT, "_build", "lpt")
+    os.makedirs(objdir, exist_ok=True)
+    cmds, objs = [], []
+    for s in SOURCES:
+        path = os.path.join(CSRC, s)
+        obj = os.path.join(objdir, s + ".o")
+        # .cpp host sources go through hipcc as HIP too (they use the HIP runtime)
+        src = ["-x", "hip", path] if s.endswith(".cpp") else [path]
+        flags = [f for f in FLAGS if f != "-shared"]
+        cmds.append([HIPCC, *flags, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", *src,
+                     "-o", obj])
+        objs.append(obj)
+    with ThreadPoolExecutor(max_workers=min(len(cmds) + 1, os.cpu_count() or 4)) as ex:
+        ns = ex.submit(build_ns, verbose)
+        codes = list(ex.map(lambda c: _compile(c, verbose), cmds))
+        ns.result()
+    if any(codes):
+        raise subprocess.CalledProcessError(max(codes), "hipcc (liblpt.so objects)")
+    tmp = LIB + ".tmp%d" % os.getpid()
+    link = [HIPCC, "--offload-arch=gfx950", "-fPIC", "-shared", *objs, "-o", tmp]
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(tmp, LIB)
     return LIB
 

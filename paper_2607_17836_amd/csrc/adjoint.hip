@@ -13,8 +13,11 @@
 // step: it recomputes the four stage points from the step's start position
 // (read from the segment tape), then applies the chain rule through the RK4
 // combine, the stage states and the interpolation.  Grid gradients are
-// scatter-added with FP64 atomics (summation order, hence rounding, depends
-// on scheduling).
+// scatter-added: by default with FP64 atomics (summation order, hence the
+// last bits, depends on scheduling); in the deterministic mode as exact
+// fixed-point integers (value = hi 2^-32 + lo 2^-64, each contribution
+// rounded once to a multiple of 2^-64), whose sums do not depend on the
+// order of the additions.
 #include "field_dev.h"
 
 namespace lpt {
@@ -136,20 +139,48 @@ __device__ __forceinline__ void jacobian64(const Rec64 *__restrict__ rec0, const
     J[3] = vy * P.invh;
 }
 
-// Accumulator of dL/d(grid) for one block: gU in global memory, laid out
-// [slot][u, v][n * n], and optionally the block's box B of nodes in LDS as
-// four planes (slot 0 u, slot 0 v, slot 1 u, slot 1 v) of B.w * B.h doubles.
+// Exact fixed-point form of a contribution c (|c| < 2^31): c ~ hi 2^-32 +
+// lo 2^-64 with hi = floor(c 2^32) and 0 <= lo < 2^32 the next 32 bits
+// (truncated).  The scaling by 2^32 and the fractional part are exact in
+// binary64, so the pair depends on c alone; sums of pairs are integer sums
+// (hi in two's complement, lo unsigned), exact and order-independent.
+__device__ __forceinline__ void to_fixed(double c, unsigned long long &hi, unsigned long long &lo)
+{
+    const double f = c * 0x1p32;
+    const double h = floor(f);
+    hi = (unsigned long long)(long long)h;
+    lo = (unsigned long long)((f - h) * 0x1p32);
+}
+
+__device__ __forceinline__ void add_fixed(unsigned long long *pair, double c)
+{
+    unsigned long long hi, lo;
+    to_fixed(c, hi, lo);
+    atomicAdd(pair, hi);
+    atomicAdd(pair + 1, lo);
+}
+
+// Accumulator of dL/d(grid) for one block.  gU in global memory is laid out
+// [slot][u, v][n * n]: doubles, or (DET) pairs of 64-bit fixed-point words.
+// The block's box B of nodes in LDS holds
+//   - by default, planes of the stencil weights times the adjoint stage
+//     vector per RK4 time level (g = 0: the first stage, 1: the two middle
+//     stages, which share a time, 2: the last), u then v: the two slots'
+//     temporal weights are applied once per node when the box is flushed;
+//   - DET: fixed-point pairs of the four (slot, component) planes.
+template <bool DET>
 struct GridGrad {
-    double *gU;
-    double *acc;   // LDS planes, used when B.on
+    void *gU;
+    void *acc;   // LDS planes, used when B.on
     Tile B;
 };
 
-// dL/d(grid) += lam (x) (temporal weight) (x) (node weight).
-template <int K>
-__device__ __forceinline__ void scatter64(const GridGrad &G, const StepParams &P,
-                                          const Sten64<K> &s, double wa, double wb, double lx,
-                                          double ly)
+// The grid gradient of one stage's stencil, K x K nodes: node weight w times
+// the stage's adjoint vector (lx, ly), times the temporal weight of each slot.
+template <int K, bool DET>
+__device__ __forceinline__ void scatter64(const GridGrad<DET> &G, const StepParams &P,
+                                          const Sten64<K> &s, int grp, double wa, double wb,
+                                          double lx, double ly)
 {
     const int n = P.n;
     const int64_t nn = (int64_t)n * n;
@@ -167,18 +198,30 @@ __device__ __forceinline__ void scatter64(const GridGrad &G, const StepParams &P
             rx += rx < 0 ? n : 0;
             const double w = s.wx[a] * s.wy[b];
             const bool local = G.B.on && rx < G.B.w && ry < G.B.h;
+            const int k = ry * G.B.w + rx;
+            if (local && !DET) {
+                double *acc = static_cast<double *>(G.acc);
+                atomicAdd(acc + (2 * grp) * area + k, w * lx);
+                atomicAdd(acc + (2 * grp + 1) * area + k, w * ly);
+                continue;
+            }
 #pragma unroll
             for (int sl = 0; sl < 2; ++sl) {
                 const double c = wt[sl] * w;
                 if (c == 0.0) continue;
-                if (local) {
-                    const int k = ry * G.B.w + rx;
-                    atomicAdd(G.acc + (2 * sl) * area + k, c * lx);
-                    atomicAdd(G.acc + (2 * sl + 1) * area + k, c * ly);
+                if constexpr (DET) {
+                    unsigned long long *q =
+                        local ? static_cast<unsigned long long *>(G.acc) + 2 * ((2 * sl) * area + k)
+                              : static_cast<unsigned long long *>(G.gU) +
+                                    2 * ((2 * sl) * nn + (int64_t)j * n + i);
+                    const int64_t pl = local ? area : nn;   // plane stride
+                    add_fixed(q, c * lx);
+                    add_fixed(q + 2 * pl, c * ly);
                 } else {
-                    const int64_t k = (int64_t)j * n + i;
-                    atomicAdd(G.gU + (2 * sl) * nn + k, c * lx);
-                    atomicAdd(G.gU + (2 * sl + 1) * nn + k, c * ly);
+                    double *g = static_cast<double *>(G.gU);
+                    const int64_t kk = (int64_t)j * n + i;
+                    atomicAdd(g + (2 * sl) * nn + kk, c * lx);
+                    atomicAdd(g + (2 * sl + 1) * nn + kk, c * ly);
                 }
             }
         }
@@ -218,15 +261,16 @@ __global__ __launch_bounds__(kMaxBlock) void recompute64_kernel(StepParams P, co
 // bound and the stencil reach; acc_cap nodes of LDS) and then adds the box
 // to gU with one atomic per nonzero entry; contributions outside the box
 // (particles faster than the bound, or a box beyond the LDS budget, which is
-// trimmed) go to gU directly.
+// trimmed) go to gU directly.  DET: gU holds fixed-point pairs (see
+// to_fixed), and so does the box.
 extern __shared__ __align__(32) unsigned char adj_dyn_lds[];
 
-template <int NL, bool AGG, bool CUBIC>
+template <int NL, bool AGG, bool CUBIC, bool DET>
 __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
                                                               const Rec64 *__restrict__ rec,
                                                               const double2 *__restrict__ tape,
                                                               double2 *__restrict__ lam,
-                                                              double *gU, int acc_cap)
+                                                              void *gU, int acc_cap)
 {
     const int lb = blockIdx.x;
     const SpeciesDev &sp = P.sp[species_of(P, lb)];
@@ -238,8 +282,11 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
     const int scheme = sp.scheme;
     const double dt = P.dt, hdt = 0.5 * P.dt, dt6 = P.dt / 6.0, dt3 = P.dt / 3.0;
     const double2 x = active ? tape[p] : make_double2(0.0, 0.0);
+    // LDS planes per box node: three time levels x (u, v) doubles, or (DET)
+    // four (slot, component) planes of fixed-point pairs
+    constexpr int kPlanes = DET ? 8 : 6;
 
-    GridGrad G{gU, reinterpret_cast<double *>(adj_dyn_lds), no_tile()};
+    GridGrad<DET> G{gU, adj_dyn_lds, no_tile()};
     if constexpr (AGG) {
         const Loc64 me = locate64(P, x.x, x.y);
         const double2 a0 = tape[sp.offset + base];
@@ -260,8 +307,14 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
         B.h = min(min(B.h, acc_cap / B.w), P.n - 1);
         B.on = 1;
         G.B = B;
-        const int area = B.w * B.h;
-        for (int k = threadIdx.x; k < 4 * area; k += blockDim.x) G.acc[k] = 0.0;
+        const int words = kPlanes * B.w * B.h;
+        if constexpr (DET) {
+            unsigned long long *acc = static_cast<unsigned long long *>(G.acc);
+            for (int k = threadIdx.x; k < words; k += blockDim.x) acc[k] = 0ull;
+        } else {
+            double *acc = static_cast<double *>(G.acc);
+            for (int k = threadIdx.x; k < words; k += blockDim.x) acc[k] = 0.0;
+        }
         __syncthreads();
     }
 
@@ -308,14 +361,17 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
 #pragma unroll
         for (int q = 3; q >= 0; --q) {
             const Loc64 loc = locate64(P, px[q], py[q]);
+            const int grp = q == 0 ? 0 : (q == 3 ? 2 : 1);   // time level of the stage
             double J[4];
             if (!CUBIC || bilinear_at(P, scheme, loc)) {
                 const Sten64<2> st = stencil64<2>(scheme, loc);
-                if (grid) scatter64<2>(G, P, st, P.wa[q], P.wb[q], lk[0][q][0], lk[0][q][1]);
+                if (grid)
+                    scatter64<2, DET>(G, P, st, grp, P.wa[q], P.wb[q], lk[0][q][0], lk[0][q][1]);
                 jacobian64<2>(rec0, P, st, P.wa[q], P.wb[q], P.smode[q], J);
             } else if constexpr (CUBIC) {
                 const Sten64<4> st = stencil64<4>(scheme, loc);
-                if (grid) scatter64<4>(G, P, st, P.wa[q], P.wb[q], lk[0][q][0], lk[0][q][1]);
+                if (grid)
+                    scatter64<4, DET>(G, P, st, grp, P.wa[q], P.wb[q], lk[0][q][0], lk[0][q][1]);
                 jacobian64<4>(rec0, P, st, P.wa[q], P.wb[q], P.smode[q], J);
             }
 #pragma unroll
@@ -336,19 +392,43 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
 
     if constexpr (AGG) {
         __syncthreads();
-        if (G.B.on) {
-            const int n = P.n, area = G.B.w * G.B.h;
-            const int64_t nn = (int64_t)n * n;
-            for (int k = threadIdx.x; k < area; k += blockDim.x) {
-                const int ty = k / G.B.w, tx = k - ty * G.B.w;
-                int gx = G.B.x0 + tx, gy = G.B.y0 + ty;
-                gx -= gx >= n ? n : 0;
-                gy -= gy >= n ? n : 0;
-                const int64_t g = (int64_t)gy * n + gx;
+        const int n = P.n, area = G.B.w * G.B.h;
+        const int64_t nn = (int64_t)n * n;
+        for (int k = threadIdx.x; k < area; k += blockDim.x) {
+            const int ty = k / G.B.w, tx = k - ty * G.B.w;
+            int gx = G.B.x0 + tx, gy = G.B.y0 + ty;
+            gx -= gx >= n ? n : 0;
+            gy -= gy >= n ? n : 0;
+            const int64_t g = (int64_t)gy * n + gx;
+            if constexpr (DET) {
+                const unsigned long long *acc = static_cast<const unsigned long long *>(G.acc);
+                unsigned long long *out = static_cast<unsigned long long *>(gU);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const double v = G.acc[q * area + k];
-                    if (v != 0.0) atomicAdd(gU + q * nn + g, v);
+                    const unsigned long long hi = acc[2 * (q * area + k)];
+                    const unsigned long long lo = acc[2 * (q * area + k) + 1];
+                    if (hi | lo) {
+                        atomicAdd(out + 2 * (q * nn + g), hi);
+                        atomicAdd(out + 2 * (q * nn + g) + 1, lo);
+                    }
+                }
+            } else {
+                const double *acc = static_cast<const double *>(G.acc);
+                double *out = static_cast<double *>(gU);
+                // time levels 0, 1, 2 were taken at the weights of stages 0, 1, 3
+                const double wa[3] = {P.wa[0], P.wa[1], P.wa[3]};
+                const double wb[3] = {P.wb[0], P.wb[1], P.wb[3]};
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                    for (int g3 = 0; g3 < 3; ++g3) {
+                        const double v = acc[(2 * g3 + c) * area + k];
+                        s0 += wa[g3] * v;
+                        s1 += wb[g3] * v;
+                    }
+                    if (s0 != 0.0) atomicAdd(out + c * nn + g, s0);
+                    if (s1 != 0.0) atomicAdd(out + (2 + c) * nn + g, s1);
                 }
             }
         }
@@ -372,11 +452,25 @@ __global__ void seed_adjoint_kernel(const uint32_t *__restrict__ id, int64_t np,
     }
 }
 
+// Finite-time Lyapunov exponent of one Jacobian F = [[a, b], [c, d]]:
+// (1/T) ln sqrt(lambda_max(F^T F)), with the largest eigenvalue of the
+// symmetric Cauchy-Green tensor [[p, r], [r, q]] (p = a^2 + c^2,
+// q = b^2 + d^2, r = ab + cd) in closed form,
+// lambda_max = (p + q)/2 + sqrt(((p - q)/2)^2 + r^2).
+__device__ __forceinline__ double ftle_of(double a, double b, double c, double d, double T)
+{
+    const double p = a * a + c * c, q = b * b + d * d, r = a * b + c * d;
+    const double h = 0.5 * (p - q);
+    const double lam = 0.5 * (p + q) + sqrt(h * h + r * r);
+    return 0.5 * log(lam) / T;
+}
+
 // Results back in original (id) order: NL == 1: gx0, gy0; NL == 2: the
-// Jacobian F[id] = [[dx/dx0, dx/dy0], [dy/dx0, dy/dy0]].
+// Jacobian F[id] = [[dx/dx0, dx/dy0], [dy/dx0, dy/dy0]] and/or its FTLE over
+// the time T (any output may be null).
 __global__ void gather_adjoint_kernel(const uint32_t *__restrict__ id, int64_t np, int nl,
                                       const double2 *__restrict__ lam, double *gx, double *gy,
-                                      double *F)
+                                      double *F, double *sigma, double T)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
@@ -387,10 +481,13 @@ __global__ void gather_adjoint_kernel(const uint32_t *__restrict__ id, int64_t n
         if (gy) gy[g] = l.y;
     } else {
         const double2 r0 = lam[2 * p], r1 = lam[2 * p + 1];
-        F[4 * (int64_t)g + 0] = r0.x;
-        F[4 * (int64_t)g + 1] = r0.y;
-        F[4 * (int64_t)g + 2] = r1.x;
-        F[4 * (int64_t)g + 3] = r1.y;
+        if (F) {
+            F[4 * (int64_t)g + 0] = r0.x;
+            F[4 * (int64_t)g + 1] = r0.y;
+            F[4 * (int64_t)g + 2] = r1.x;
+            F[4 * (int64_t)g + 3] = r1.y;
+        }
+        if (sigma) sigma[g] = ftle_of(r0.x, r0.y, r1.x, r1.y, T);
     }
 }
 
@@ -402,32 +499,71 @@ hipError_t launch_recompute64(const StepParams &P, const Rec64 *rec, const doubl
     return hipGetLastError();
 }
 
-// LDS of the aggregating adjoint: four planes of doubles per box node.
-constexpr int kAdjAccNodes = 1024;
+// LDS of the aggregating adjoint: 30 KiB, so that the bilinear kernel's five
+// 256-thread blocks per CU (its register-bound occupancy) fit in 160 KiB;
+// 640 box nodes of six double planes, or 480 nodes of four fixed-point pair
+// planes (DET).
+constexpr size_t kAdjAccBytes = 30 * 1024;
 
-template <bool CUBIC>
+template <bool CUBIC, bool DET>
 static hipError_t launch_adjoint64_c(const StepParams &P, const Rec64 *rec, const double2 *tape,
-                                     double2 *lam, int nl, double *gU, int block, hipStream_t st)
+                                     double2 *lam, int nl, void *gU, int block, hipStream_t st)
 {
+    const int cap = (int)(kAdjAccBytes / (DET ? 8 * sizeof(unsigned long long) : 6 * sizeof(double)));
     if (nl == 1 && gU)
-        hipLaunchKernelGGL((adjoint64_kernel<1, true, CUBIC>), dim3(P.total_blocks), dim3(block),
-                           (size_t)kAdjAccNodes * 4 * sizeof(double), st, P, rec, tape, lam, gU,
-                           kAdjAccNodes);
+        hipLaunchKernelGGL((adjoint64_kernel<1, true, CUBIC, DET>), dim3(P.total_blocks),
+                           dim3(block), kAdjAccBytes, st, P, rec, tape, lam, gU, cap);
     else if (nl == 1)
-        hipLaunchKernelGGL((adjoint64_kernel<1, false, CUBIC>), dim3(P.total_blocks), dim3(block),
-                           0, st, P, rec, tape, lam, (double *)nullptr, 0);
+        hipLaunchKernelGGL((adjoint64_kernel<1, false, CUBIC, false>), dim3(P.total_blocks),
+                           dim3(block), 0, st, P, rec, tape, lam, (void *)nullptr, 0);
     else
-        hipLaunchKernelGGL((adjoint64_kernel<2, false, CUBIC>), dim3(P.total_blocks), dim3(block),
-                           0, st, P, rec, tape, lam, (double *)nullptr, 0);
+        hipLaunchKernelGGL((adjoint64_kernel<2, false, CUBIC, false>), dim3(P.total_blocks),
+                           dim3(block), 0, st, P, rec, tape, lam, (void *)nullptr, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint64(const StepParams &P, const Rec64 *rec, const double2 *tape,
-                            double2 *lam, int nl, double *gU, bool cubic, int block,
+                            double2 *lam, int nl, void *gU, bool det, bool cubic, int block,
                             hipStream_t st)
 {
-    return cubic ? launch_adjoint64_c<true>(P, rec, tape, lam, nl, gU, block, st)
-                 : launch_adjoint64_c<false>(P, rec, tape, lam, nl, gU, block, st);
+    if (det)
+        return cubic ? launch_adjoint64_c<true, true>(P, rec, tape, lam, nl, gU, block, st)
+                     : launch_adjoint64_c<false, true>(P, rec, tape, lam, nl, gU, block, st);
+    return cubic ? launch_adjoint64_c<true, false>(P, rec, tape, lam, nl, gU, block, st)
+                 : launch_adjoint64_c<false, false>(P, rec, tape, lam, nl, gU, block, st);
+}
+
+// Fixed-point pairs (hi 2^-32 + lo 2^-64) to binary64, in place order.
+__global__ void fixed_to_double_kernel(const unsigned long long *__restrict__ pairs, int64_t count,
+                                       double *out)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const long long hi = (long long)pairs[2 * k];
+    const unsigned long long lo = pairs[2 * k + 1];
+    out[k] = (double)hi * 0x1p-32 + (double)lo * 0x1p-64;
+}
+
+hipError_t launch_fixed_to_double(const void *pairs, int64_t count, double *out, hipStream_t st)
+{
+    const int b = 256;
+    hipLaunchKernelGGL(fixed_to_double_kernel, dim3((unsigned)((count + b - 1) / b)), dim3(b), 0,
+                       st, static_cast<const unsigned long long *>(pairs), count, out);
+    return hipGetLastError();
+}
+
+__global__ void zero_words_kernel(unsigned long long *p, int64_t count)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) p[k] = 0ull;
+}
+
+hipError_t launch_zero_words(void *p, int64_t words, hipStream_t st)
+{
+    const int b = 256;
+    hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)((words + b - 1) / b)), dim3(b), 0, st,
+                       static_cast<unsigned long long *>(p), words);
+    return hipGetLastError();
 }
 
 hipError_t launch_seed_adjoint(const uint32_t *id, int64_t np, int nl, const double *gx,
@@ -440,11 +576,12 @@ hipError_t launch_seed_adjoint(const uint32_t *id, int64_t np, int nl, const dou
 }
 
 hipError_t launch_gather_adjoint(const uint32_t *id, int64_t np, int nl, const double2 *lam,
-                                 double *gx, double *gy, double *F, hipStream_t st)
+                                 double *gx, double *gy, double *F, double *sigma, double T,
+                                 hipStream_t st)
 {
     const int b = 256;
     hipLaunchKernelGGL(gather_adjoint_kernel, dim3((unsigned)((np + b - 1) / b)), dim3(b), 0, st,
-                       id, np, nl, lam, gx, gy, F);
+                       id, np, nl, lam, gx, gy, F, sigma, T);
     return hipGetLastError();
 }
 

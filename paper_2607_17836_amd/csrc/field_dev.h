@@ -45,6 +45,39 @@ __device__ __forceinline__ void persistent_range(int T, int &first, int &stride,
     end = hi;
 }
 
+// Every logical block of a launch over [base, base + count), each exactly
+// once, with the body called uniformly per workgroup:
+//   - with a block-order table (P.order), XCD x = blockIdx mod 8 walks its
+//     list with a stride of its own workgroup count (one entry each when
+//     the grid is 8 * order_len);
+//   - otherwise one block per workgroup in XCD-contiguous order, or, in a
+//     persistent launch, the XCD's contiguous range.
+// Every workgroup's walk ends, so the grid always drains.
+template <typename Body>
+__device__ __forceinline__ void for_each_block(const StepParams &P, int base, int count,
+                                               Body &&body)
+{
+    if (P.order) {
+        constexpr int X = 8;
+        const int G = gridDim.x, b = blockIdx.x;
+        const int x = b % X;
+        const int gx = (G - x + X - 1) / X;   // workgroups on XCD x
+        const int32_t *list = P.order + (int64_t)x * P.order_len;
+        for (int k = b / X; k < P.order_len; k += gx) {
+            const int lb = list[k];
+            if (lb >= 0) body(lb);
+        }
+        return;
+    }
+    if (!P.persistent) {
+        body(base + xcd_logical_block(blockIdx.x, gridDim.x));
+        return;
+    }
+    int first, stride, end;
+    persistent_range(count, first, stride, end);
+    for (int lb = first; lb < end; lb += stride) body(base + lb);
+}
+
 // Streaming (non-temporal) loads and stores of the particle state: each
 // value is touched once per step, so it should not displace the field's node
 // records from the caches.
@@ -221,6 +254,58 @@ __device__ __forceinline__ uint32_t wave_pmax16(uint32_t x)
     x = dpp_pmax<0x142, 0xA>(x);   // row_bcast:15
     x = dpp_pmax<0x143, 0xC>(x);   // row_bcast:31
     return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// The same DPP pattern for a binary64 sum: each shift moves the two 32-bit
+// halves, lanes outside a shift read 0 (the identity), and lane 63 ends with
+// the sum of all 64 lanes, added in a fixed order (an inclusive scan of each
+// 16-lane row, then the row totals), so the result does not depend on
+// scheduling.  Every lane of the wave must be active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xF, true);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x)
+{
+    x += dpp_f64<0x111, 0xF>(x);   // row_shr:1
+    x += dpp_f64<0x112, 0xF>(x);   // row_shr:2
+    x += dpp_f64<0x114, 0xF>(x);   // row_shr:4
+    x += dpp_f64<0x118, 0xF>(x);   // row_shr:8
+    x += dpp_f64<0x142, 0xA>(x);   // row_bcast:15
+    x += dpp_f64<0x143, 0xC>(x);   // row_bcast:31
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Statistics partial of one wave (Sec. 3.2 and 5.5 quantities): the sums of
+// dx^2 and dy^2 over its active lanes and M2 = sum (r2 - m)^2 of
+// r2 = dx^2 + dy^2 about the wave's own mean m, so that the finalisation
+// can merge waves with the pairwise update of the mean and M2 instead of
+// forming var = (sum r2^2 - N m^2) / (N - 1), which cancels when the spread
+// is small against the mean (uniform flow: every r2 equal).  The count of a
+// wave follows from the species size, so it is not stored.  Every lane of
+// the wave must call it (inactive lanes with r2x = r2y = 0); lane 0 writes
+// out[0..2].
+__device__ __forceinline__ void wave_stats(double r2x, double r2y, bool active, double *out)
+{
+    const double sx = wave_sum_f64(r2x), sy = wave_sum_f64(r2y);
+    const int cnt = __popcll(__ballot(active));
+    const double mean = cnt > 0 ? (sx + sy) / (double)cnt : 0.0;
+    const double d = active ? (r2x + r2y) - mean : 0.0;
+    const double m2 = wave_sum_f64(d * d);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        out[0] = sx;
+        out[1] = sy;
+        out[2] = m2;
+    }
 }
 
 // Bounding box of the stored cells of a block's active particles, widened by

@@ -8,9 +8,11 @@
 namespace lpt {
 
 constexpr int kMaxSpecies = 16;
-constexpr int kStatTerms = 3;   // sum dx^2, sum dy^2, sum (dx^2 + dy^2)^2
+constexpr int kStatTerms = 3;   // per wave: sum dx^2, sum dy^2, M2 of dx^2 + dy^2
 
 enum Scheme : int32_t { kBilinear = 0, kCatmullRom = 1, kBSpline = 2 };
+// a fused FP32 launch whose blocks take their species' scheme at run time
+constexpr int kAnyScheme = -1;
 
 // One species as the step kernel sees it.  A species owns the contiguous
 // particle range [offset, offset + count) of the state arrays and the logical
@@ -66,7 +68,21 @@ struct StepParams {
     // launch (one launch per species)
     int32_t block_base;
     int32_t launch_blocks;
+    // fused launches over all species: one list of order_len logical blocks
+    // per XCD (device memory, XCD-major; -1 pads a shorter list), or null
+    const int32_t *order;
+    int32_t order_len;
+    int32_t max_wg;        // > 0: persistent grids hold at most this many workgroups
 };
+
+// Block-order table of a fused launch over species whose logical blocks are
+// [begin[s], end[s]): XCD x receives the slice [B x / 8, B (x + 1) / 8) of
+// every species' B blocks, and its list holds those slices merged by the
+// position of each block along its species' cell order, so that the blocks
+// an XCD runs together cover one region of the grid for every species.
+// Returns order_len; `out` receives 8 * order_len entries.
+int32_t build_block_order(int nspecies, const int32_t *begin, const int32_t *end,
+                          int32_t *out /* may be null: length only */);
 
 // Device-resident clock so that captured step chunks can be replayed.
 struct DevClock {
@@ -118,15 +134,22 @@ hipError_t launch_step64(const StepParams &P, const State64 &S, const State64 &D
                          DevClock *clock, bool stats, bool cubic, bool inertial, int block,
                          int grid, hipStream_t st);
 // One launch over the logical blocks [P.block_base, P.block_base +
-// P.launch_blocks) (= grid) of one species, whose scheme is `schemes`.  S, D
-// and perm as for launch_step64.
+// P.launch_blocks) (= grid) of one species, whose scheme is `schemes`, or,
+// with P.order set and schemes = kAnyScheme (or the one scheme they share),
+// a fused launch over every species.  S, D and perm as for launch_step64.
 hipError_t launch_step32(const StepParams &P, const State32 &S, const State32 &D,
                          const uint32_t *perm, const float4 *rec, double *partials,
                          DevClock *clock, bool stats, int schemes, bool inertial, int block,
                          int grid, hipStream_t st);
 
-hipError_t launch_finalize(const StepParams &P, const double *partials, DevClock *clock,
-                           double *records, int64_t rec_cap, double t0, hipStream_t st);
+// Statistics record of every species from the per-wave partials of a step
+// kernel launched with `block` threads per block (two fixed-order merge
+// kernels; the buffer holds stat_partials_doubles(P, block) doubles: the wave
+// partials, then the merge stage's own partials).
+int64_t stat_partials_doubles(const StepParams &P, int block);
+hipError_t launch_finalize(const StepParams &P, double *partials, DevClock *clock,
+                           double *records, int64_t rec_cap, double t0, int block,
+                           hipStream_t st);
 
 // Initial state of particles [begin, begin + count) from x0 and v0 (both in
 // original order, indexed by global particle index).  An inertial species
@@ -165,14 +188,20 @@ hipError_t launch_order(const uint32_t *id, int64_t offset, int64_t count, int32
 // the step kernel's block size (P's species block layout)
 hipError_t launch_recompute64(const StepParams &P, const Rec64 *rec, const double2 *in,
                               double2 *out, int block, hipStream_t st);
-// cubic: some species uses a bicubic scheme (else every stencil is bilinear)
+// cubic: some species uses a bicubic scheme (else every stencil is bilinear).
+// det: gU holds fixed-point pairs of 64-bit words (4 n^2 pairs; value =
+// hi 2^-32 + lo 2^-64), summed exactly with integer atomics; else doubles.
 hipError_t launch_adjoint64(const StepParams &P, const Rec64 *rec, const double2 *tape,
-                            double2 *lam, int nl, double *gU, bool cubic, int block,
+                            double2 *lam, int nl, void *gU, bool det, bool cubic, int block,
                             hipStream_t st);
+hipError_t launch_fixed_to_double(const void *pairs, int64_t count, double *out, hipStream_t st);
+hipError_t launch_zero_words(void *p, int64_t words, hipStream_t st);
 hipError_t launch_seed_adjoint(const uint32_t *id, int64_t np, int nl, const double *gx,
                                const double *gy, double2 *lam, hipStream_t st);
+// sigma (with nl == 2): the FTLE of each Jacobian over the time T
 hipError_t launch_gather_adjoint(const uint32_t *id, int64_t np, int nl, const double2 *lam,
-                                 double *gx, double *gy, double *F, hipStream_t st);
+                                 double *gx, double *gy, double *F, double *sigma, double T,
+                                 hipStream_t st);
 
 // bandwidth probe (bytes: per buffer, multiple of 16)
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t st);

@@ -20,6 +20,30 @@
 
 using namespace lpt;
 
+int32_t lpt::build_block_order(int nspecies, const int32_t *begin, const int32_t *end,
+                               int32_t *out)
+{
+    constexpr int X = 8;
+    std::vector<std::pair<double, int32_t>> lists[X];
+    size_t len = 0;
+    for (int x = 0; x < X; ++x) {
+        for (int s = 0; s < nspecies; ++s) {
+            const int64_t B = end[s] - begin[s];
+            for (int64_t k = B * x / X; k < B * (x + 1) / X; ++k)
+                lists[x].emplace_back(((double)k + 0.5) / (double)B, begin[s] + (int32_t)k);
+        }
+        // by position along the cell order; ties keep the species order
+        std::stable_sort(lists[x].begin(), lists[x].end(),
+                         [](const auto &a, const auto &b) { return a.first < b.first; });
+        len = std::max(len, lists[x].size());
+    }
+    if (out)
+        for (int x = 0; x < X; ++x)
+            for (size_t k = 0; k < len; ++k)
+                out[x * len + k] = k < lists[x].size() ? lists[x][k].second : -1;
+    return (int32_t)len;
+}
+
 namespace {
 
 // Default capacity of the step kernel's field tile, in node records: 19200
@@ -73,16 +97,27 @@ struct lpt_ctx {
     int32_t persistent = 0;  // persistent step launches
     float halo_scale = kHaloScaleDefault; // LDS tile halo relative to the largest-speed bound
     int32_t graph_chunk = 0; // steps per captured hipGraph (0: eager launches)
+    int32_t fused = 1;       // one launch over every species (block-order table)
+    int32_t max_wg = 0;      // cap on persistent workgroups (0: residency only)
+    int32_t *order = nullptr;   // device block-order table of fused launches
+    size_t order_cap = 0;       // entries allocated
+    int32_t order_len = 0;      // entries per XCD list
+    bool order_ok = false;      // the table matches the species and block size
     // executable graphs of step chunks, keyed by (step phase, state buffer,
     // chunk length, dt bits, stats_every, buffer epoch)
     std::map<std::tuple<int64_t, int, int64_t, uint64_t, int32_t, uint64_t>, hipGraphExec_t> graphs;
     uint64_t epoch = 0;      // bumped whenever a buffer a graph may hold changes
     hipStream_t own_stream = nullptr;   // capture stream when the context uses the null stream
     bool compat_edge = false;
+    bool det_grad = false;       // grid gradients in exact fixed point
+    unsigned long long *det_acc = nullptr;   // fixed-point pairs of the grid gradient
+    int64_t det_acc_words = 0;
     std::string err;
 
     // snapshots
     void *rec = nullptr;   // padded Rec64 or float4 records, (n + 3)^2
+    double *psi_uv = nullptr;   // grid velocity of a stream-function snapshot
+    int64_t psi_uv_cap = 0;     // doubles
     float *umax = nullptr; // largest node speed per slot, cells per unit time
     bool slot_set[2] = {false, false};
     double t_slot[2] = {0, 0};
@@ -99,8 +134,8 @@ struct lpt_ctx {
     bool has_inertial = false, has_cubic = false;
 
     // statistics
-    double *partials = nullptr;
-    int64_t partial_blocks = 0;
+    double *partials = nullptr;   // per-wave statistics partials + merge stage
+    int64_t partial_cap = 0;      // doubles
     double *records = nullptr;
     int64_t rec_cap = 0;
     int64_t nrec = 0;
@@ -125,7 +160,7 @@ struct lpt_ctx {
     bool time_kernels = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_step, ev_sort, ev_perm;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_step, ev_sort, ev_perm, ev_stat, ev_fin;
 };
 
 namespace {
@@ -224,6 +259,11 @@ StepParams make_params(const lpt_ctx *c)
     P.total_blocks = blk;
     P.block_base = 0;
     P.launch_blocks = blk;
+    P.max_wg = c->max_wg;
+    if (c->fused && c->sp.size() > 1 && c->order_ok) {
+        P.order = c->order;
+        P.order_len = c->order_len;
+    }
     return P;
 }
 
@@ -269,6 +309,38 @@ lpt_status ensure_sort_work(lpt_ctx *c)
     HIP_TRY(c, dalloc(c->sw.hist, (size_t)sort_hist_entries(c->np)));
     HIP_TRY(c, dalloc(c->sw.scan_tmp, (size_t)sort_scan_blocks(c->np)));
     c->sw.capacity = c->np;
+    return LPT_OK;
+}
+
+// Device copy of the fused launches' block-order table (set-up only: never
+// called while a graph is being captured).
+lpt_status ensure_order(lpt_ctx *c)
+{
+    if (!c->fused || c->sp.size() < 2 || c->order_ok) return LPT_OK;
+    StepParams P = make_params(c);
+    int32_t begin[kMaxSpecies], end[kMaxSpecies];
+    for (int s = 0; s < P.nspecies; ++s) {
+        begin[s] = P.sp[s].block_begin;
+        end[s] = P.sp[s].block_end;
+    }
+    const int32_t len = build_block_order(P.nspecies, begin, end, nullptr);
+    std::vector<int32_t> h((size_t)8 * len);
+    build_block_order(P.nspecies, begin, end, h.data());
+    if (h.size() > c->order_cap) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        dfree(c->order);
+        c->order_cap = 0;
+        HIP_TRY(c, dalloc(c->order, h.size()));
+        c->order_cap = h.size();
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->order, h.data(), h.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->order_len = len;
+    c->order_ok = true;
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+    c->epoch += 1;
     return LPT_OK;
 }
 
@@ -377,7 +449,8 @@ lpt_status lpt_create(const lpt_config *cfg, lpt_ctx **out)
     if (!is_pow2(tile) || n % tile) return LPT_E_ARG;
     const int32_t block = cfg->block_size == 0 ? 256 : cfg->block_size;
     if (block != 64 && block != 128 && block != 256 && block != 512) return LPT_E_ARG;
-    if (cfg->flags & ~(LPT_FLAG_COMPAT_EDGE | LPT_FLAG_TIME_KERNELS)) return LPT_E_ARG;
+    if (cfg->flags & ~(LPT_FLAG_COMPAT_EDGE | LPT_FLAG_TIME_KERNELS | LPT_FLAG_DETERMINISTIC_GRAD))
+        return LPT_E_ARG;
     const size_t rec_size = cfg->precision == LPT_FP64 ? sizeof(Rec64) : sizeof(float4);
     const int32_t tile_max = (int32_t)(kTileBytesMax / rec_size);
     int32_t tile_cap = cfg->tile_records;
@@ -399,6 +472,7 @@ lpt_status lpt_create(const lpt_config *cfg, lpt_ctx **out)
     c->sort_tile = tile;
     c->tile_cap = tile_cap;
     c->compat_edge = (cfg->flags & LPT_FLAG_COMPAT_EDGE) != 0;
+    c->det_grad = (cfg->flags & LPT_FLAG_DETERMINISTIC_GRAD) != 0;
     c->time_kernels = (cfg->flags & LPT_FLAG_TIME_KERNELS) != 0;
     c->t = cfg->t0;
 
@@ -443,6 +517,9 @@ void lpt_destroy(lpt_ctx *c)
     dfree(c->clock);
     dfree(c->umax);
     dfree(c->ck);
+    dfree(c->order);
+    dfree(c->psi_uv);
+    dfree(c->det_acc);
     for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
     c->graphs.clear();
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -461,10 +538,17 @@ lpt_status lpt_synchronize(lpt_ctx *c)
 
 // Device copies of caller arrays: `count` doubles per pointer.
 namespace {
+// Temporary device buffers of one call, freed when the call returns.  A
+// copy or kernel enqueued on them may still be in flight when an error path
+// returns early, so the stream is drained before they are released.
 struct Staged {
+    hipStream_t stream = nullptr;
     std::vector<double *> bufs;
+    explicit Staged(hipStream_t s) : stream(s) {}
     ~Staged()
     {
+        if (bufs.empty()) return;
+        (void)hipStreamSynchronize(stream);
         for (double *p : bufs) (void)hipFree(p);
     }
 };
@@ -499,7 +583,7 @@ lpt_status lpt_set_snapshot(lpt_ctx *c, int32_t slot, double t, const double *u,
     if (!u || !v) return fail(c, LPT_E_ARG, "u and v must not be NULL");
     HIP_TRY(c, hipSetDevice(c->device));
     const int64_t nn = (int64_t)c->n * c->n;
-    Staged st;
+    Staged st(c->stream);
     const double *du = nullptr, *dv = nullptr;
     lpt_status s = stage_in(c, st, u, nn, on_device, du);
     if (s == LPT_OK) s = stage_in(c, st, v, nn, on_device, dv);
@@ -510,6 +594,7 @@ lpt_status lpt_set_snapshot(lpt_ctx *c, int32_t slot, double t, const double *u,
     if (!st.bufs.empty()) HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->slot_set[slot] = true;
     c->t_slot[slot] = t;
+    c->ck_valid = false;   // a reverse sweep must see the fields of its forward run
     return LPT_OK;
 }
 
@@ -522,20 +607,28 @@ lpt_status lpt_set_snapshot_psi(lpt_ctx *c, int32_t slot, double t, const double
     if (!psi) return fail(c, LPT_E_ARG, "psi must not be NULL");
     HIP_TRY(c, hipSetDevice(c->device));
     const int64_t nn = (int64_t)c->n * c->n;
-    Staged st;
+    Staged st(c->stream);
     const double *dp = nullptr;
     lpt_status s = stage_in(c, st, psi, nn, on_device, dp);
     if (s != LPT_OK) return s;
-    double *uv = nullptr;
-    HIP_TRY(c, dalloc(uv, (size_t)(2 * nn)));
-    st.bufs.push_back(uv);
+    // the grid velocity goes through a scratch owned by the context (grown
+    // once; stream order keeps successive calls from overlapping on it)
+    if (c->psi_uv_cap < 2 * nn) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        dfree(c->psi_uv);
+        c->psi_uv_cap = 0;
+        HIP_TRY(c, dalloc(c->psi_uv, (size_t)(2 * nn)));
+        c->psi_uv_cap = 2 * nn;
+    }
+    double *uv = c->psi_uv;
     HIP_TRY(c, launch_psi_to_velocity(dp, uv, uv + nn, c->n, c->h, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->umax + slot, 0, sizeof(float), c->stream));
     HIP_TRY(c, launch_pack(c->rec, c->precision == LPT_FP64, slot, uv, uv + nn, c->n, c->invh,
                            c->invh, c->umax + slot, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (!st.bufs.empty()) HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->slot_set[slot] = true;
     c->t_slot[slot] = t;
+    c->ck_valid = false;
     return LPT_OK;
 }
 
@@ -665,7 +758,7 @@ lpt_status lpt_add_species(lpt_ctx *c, lpt_kind kind, double st, lpt_scheme sche
         return fail(c, LPT_E_ARG, "sort key wider than 32 bits; raise sort_tile");
     HIP_TRY(c, hipSetDevice(c->device));
 
-    Staged stg;
+    Staged stg(c->stream);
     const double *dx = nullptr, *dy = nullptr, *dvx = nullptr, *dvy = nullptr;
     lpt_status s = stage_in(c, stg, x0, count, on_device, dx);
     if (s == LPT_OK) s = stage_in(c, stg, y0, count, on_device, dy);
@@ -679,14 +772,18 @@ lpt_status lpt_add_species(lpt_ctx *c, lpt_kind kind, double st, lpt_scheme sche
     // partial sums: one slot per logical block of every species
     SpeciesHost h{(int32_t)kind, st, (int32_t)scheme, count, old, inertial && !vx0};
     c->sp.push_back(h);
+    c->order_ok = false;
     c->np = old + count;
     c->has_inertial = c->has_inertial || inertial;
     c->has_cubic = c->has_cubic || scheme != LPT_BILINEAR;
     const StepParams P = make_params(c);
-    if (P.total_blocks > c->partial_blocks) {
+    const int64_t need = stat_partials_doubles(P, c->block);
+    if (need > c->partial_cap) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
         dfree(c->partials);
-        HIP_TRY(c, dalloc(c->partials, (size_t)kStatTerms * P.total_blocks));
-        c->partial_blocks = P.total_blocks;
+        c->partial_cap = 0;
+        HIP_TRY(c, dalloc(c->partials, (size_t)need));
+        c->partial_cap = need;
     }
     HIP_TRY(c, launch_interleave(c->x0 + old, dx, dy, count, c->stream));
     if (inertial && dvx) HIP_TRY(c, launch_interleave(c->v0 + old, dvx, dvy, count, c->stream));
@@ -844,14 +941,20 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
                                      rec, c->has_cubic, c->has_inertial, c->block,
                                      P.total_blocks, c->stream));
             if (perm) c->cur = 1 - c->cur;
+        } else if (P.order) {
+            // one fused launch over every species: the block-order table
+            // gives each XCD the same share of every species, in cell order
+            int sch = P.sp[0].scheme;
+            for (int s = 1; s < P.nspecies; ++s)
+                if (P.sp[s].scheme != sch) sch = kAnyScheme;
+            HIP_TRY(c, launch_step32(P, c->s32[c->cur], c->s32[perm ? 1 - c->cur : c->cur], perm,
+                                     static_cast<const float4 *>(c->rec), c->partials, c->clock,
+                                     rec, sch, c->has_inertial, c->block, P.total_blocks,
+                                     c->stream));
+            if (perm) c->cur = 1 - c->cur;
         } else {
             // one launch per species: each launch runs one (scheme, kind)
-            // body, and spreads that species over all XCDs (a single launch
-            // hands each XCD one contiguous range of all blocks, so species
-            // of different cost per block would leave the XCDs unbalanced).
-            // The FP64 step keeps one launch: it is not used for large
-            // heterogeneous batches, and for a few similar species the extra
-            // launches cost more than they balance.
+            // body and spreads that species over all XCDs
             for (int s = 0; s < P.nspecies; ++s) {
                 const SpeciesDev &d = P.sp[s];
                 if (d.block_end <= d.block_begin) continue;
@@ -867,11 +970,16 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
         }
         if (c->time_kernels) {
             HIP_TRY(c, mark(c, e1));
-            (perm ? c->ev_perm : c->ev_step).emplace_back(e0, e1);
+            (perm ? c->ev_perm : (rec ? c->ev_stat : c->ev_step)).emplace_back(e0, e1);
         }
         if (rec) {
+            if (c->time_kernels) HIP_TRY(c, mark(c, e0));
             HIP_TRY(c, launch_finalize(P, c->partials, c->clock, c->records, c->rec_cap,
-                                       c->cfg.t0, c->stream));
+                                       c->cfg.t0, c->block, c->stream));
+            if (c->time_kernels) {
+                HIP_TRY(c, mark(c, e1));
+                c->ev_fin.emplace_back(e0, e1);
+            }
             c->nrec += 1;
         }
         c->t += dt;
@@ -961,6 +1069,7 @@ lpt_status lpt_step(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every)
     if (s != LPT_OK || nsteps == 0) return s;
     HIP_TRY(c, hipSetDevice(c->device));
     s = grow_records(c, nsteps, stats_every);
+    if (s == LPT_OK) s = ensure_order(c);
     if (s != LPT_OK) return s;
     c->ck_valid = false;
     if (c->graph_chunk <= 0 || c->time_mode != LPT_TIME_PINGPONG || c->time_kernels)
@@ -977,6 +1086,7 @@ lpt_status lpt_time_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_e
     if (s != LPT_OK) return s;
     HIP_TRY(c, hipSetDevice(c->device));
     s = grow_records(c, nsteps, stats_every);   // outside the timed interval
+    if (s == LPT_OK) s = ensure_order(c);
     if (s != LPT_OK) return s;
     if (c->sort_interval > 0) {
         s = ensure_sort_work(c);
@@ -1020,6 +1130,8 @@ lpt_status lpt_forward_checkpointed(lpt_ctx *c, int64_t nsteps, double dt, int32
     lpt_status s = check_steps(c, nsteps, dt, 0);
     if (s != LPT_OK) return s;
     HIP_TRY(c, hipSetDevice(c->device));
+    s = ensure_order(c);
+    if (s != LPT_OK) return s;
     const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
     const size_t need = (size_t)nseg * (size_t)c->np * sizeof(double2);
     if (need > c->ck_bytes) {
@@ -1058,7 +1170,7 @@ namespace {
 // Reverse sweep over the last checkpointed run: per segment, newest first,
 // rebuild the segment's per-step positions from its checkpoint, then take
 // the adjoint kernel back through them.
-lpt_status reverse_sweep(lpt_ctx *c, int nl, double2 *lam, double *gU)
+lpt_status reverse_sweep(lpt_ctx *c, int nl, double2 *lam, void *gU, bool det)
 {
     const int64_t E = c->ck_every, N = c->ck_nsteps, np = c->np;
     const int64_t tape_len = std::min(E, N);
@@ -1089,8 +1201,8 @@ lpt_status reverse_sweep(lpt_ctx *c, int nl, double2 *lam, double *gU)
                 P.wb[q] = w.wb[q];
                 P.smode[q] = slot_mode(w.wa[q], w.wb[q]);
             }
-            e = launch_adjoint64(P, rec, tape + s * np, lam, nl, gU, c->has_cubic, c->block,
-                                 c->stream);
+            e = launch_adjoint64(P, rec, tape + s * np, lam, nl, gU, det, c->has_cubic,
+                                 c->block, c->stream);
         }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1118,7 +1230,7 @@ lpt_status lpt_adjoint(lpt_ctx *c, const double *gx_T, const double *gy_T, doubl
     if (s != LPT_OK) return s;
     HIP_TRY(c, hipSetDevice(c->device));
     const int64_t np = c->np, nn4 = 4 * (int64_t)c->n * c->n;
-    Staged st;
+    Staged st(c->stream);
     const double *dgx = nullptr, *dgy = nullptr;
     s = stage_in(c, st, gx_T, np, on_device, dgx);
     if (s == LPT_OK) s = stage_in(c, st, gy_T, np, on_device, dgy);
@@ -1134,12 +1246,27 @@ lpt_status lpt_adjoint(lpt_ctx *c, const double *gx_T, const double *gy_T, doubl
             HIP_TRY(c, dalloc(dU, (size_t)nn4));
             st.bufs.push_back(dU);
         }
-        HIP_TRY(c, hipMemsetAsync(dU, 0, (size_t)nn4 * sizeof(double), c->stream));
+        if (!c->det_grad) HIP_TRY(c, hipMemsetAsync(dU, 0, (size_t)nn4 * sizeof(double), c->stream));
+    }
+    // deterministic mode: the sweep sums fixed-point pairs in a context-owned
+    // accumulator (two 64-bit words per gradient entry), converted at the end
+    void *acc = dU;
+    if (gU && c->det_grad) {
+        if (c->det_acc_words < 2 * nn4) {
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            dfree(c->det_acc);
+            c->det_acc_words = 0;
+            HIP_TRY(c, dalloc(c->det_acc, (size_t)(2 * nn4)));
+            c->det_acc_words = 2 * nn4;
+        }
+        HIP_TRY(c, launch_zero_words(c->det_acc, 2 * nn4, c->stream));
+        acc = c->det_acc;
     }
     const uint32_t *id = c->s64[c->cur].id;
     HIP_TRY(c, launch_seed_adjoint(id, np, 1, dgx, dgy, lam, c->stream));
-    s = reverse_sweep(c, 1, lam, dU);
+    s = reverse_sweep(c, 1, lam, acc, gU && c->det_grad);
     if (s != LPT_OK) return s;
+    if (gU && c->det_grad) HIP_TRY(c, launch_fixed_to_double(c->det_acc, nn4, dU, c->stream));
     double *ox = gx_0, *oy = gy_0;
     if (!on_device) {
         if (gx_0) {
@@ -1151,7 +1278,7 @@ lpt_status lpt_adjoint(lpt_ctx *c, const double *gx_T, const double *gy_T, doubl
             st.bufs.push_back(oy);
         }
     }
-    HIP_TRY(c, launch_gather_adjoint(id, np, 1, lam, ox, oy, nullptr, c->stream));
+    HIP_TRY(c, launch_gather_adjoint(id, np, 1, lam, ox, oy, nullptr, nullptr, 0.0, c->stream));
     if (!on_device) {
         if (gx_0)
             HIP_TRY(c, hipMemcpyAsync(gx_0, ox, (size_t)np * sizeof(double),
@@ -1167,33 +1294,61 @@ lpt_status lpt_adjoint(lpt_ctx *c, const double *gx_T, const double *gy_T, doubl
     return LPT_OK;
 }
 
-lpt_status lpt_jacobian(lpt_ctx *c, double *F, int32_t on_device)
+namespace {
+// Jacobian sweep of the last checkpointed run: F (4 np doubles) and/or the
+// FTLE sigma (np doubles) over the run's duration, in id order.
+lpt_status jacobian_sweep(lpt_ctx *c, double *F, double *sigma, int32_t on_device)
 {
-    if (!c) return LPT_E_ARG;
-    if (!F) return fail(c, LPT_E_ARG, "F must not be NULL");
     lpt_status s = check_adjoint(c);
     if (s != LPT_OK) return s;
     HIP_TRY(c, hipSetDevice(c->device));
     const int64_t np = c->np;
-    Staged st;
+    Staged st(c->stream);
     double2 *lam = nullptr;
     HIP_TRY(c, dalloc(lam, (size_t)(2 * np)));
     st.bufs.push_back(reinterpret_cast<double *>(lam));
     const uint32_t *id = c->s64[c->cur].id;
     HIP_TRY(c, launch_seed_adjoint(id, np, 2, nullptr, nullptr, lam, c->stream));
-    s = reverse_sweep(c, 2, lam, nullptr);
+    s = reverse_sweep(c, 2, lam, nullptr, false);
     if (s != LPT_OK) return s;
-    double *dF = F;
+    double *dF = F, *dS = sigma;
     if (!on_device) {
-        HIP_TRY(c, dalloc(dF, (size_t)(4 * np)));
-        st.bufs.push_back(dF);
+        if (F) {
+            HIP_TRY(c, dalloc(dF, (size_t)(4 * np)));
+            st.bufs.push_back(dF);
+        }
+        if (sigma) {
+            HIP_TRY(c, dalloc(dS, (size_t)np));
+            st.bufs.push_back(dS);
+        }
     }
-    HIP_TRY(c, launch_gather_adjoint(id, np, 2, lam, nullptr, nullptr, dF, c->stream));
-    if (!on_device)
-        HIP_TRY(c, hipMemcpyAsync(F, dF, (size_t)(4 * np) * sizeof(double), hipMemcpyDeviceToHost,
-                                  c->stream));
+    const double T = (double)c->ck_nsteps * c->ck_dt;
+    HIP_TRY(c, launch_gather_adjoint(id, np, 2, lam, nullptr, nullptr, dF, dS, T, c->stream));
+    if (!on_device) {
+        if (F)
+            HIP_TRY(c, hipMemcpyAsync(F, dF, (size_t)(4 * np) * sizeof(double),
+                                      hipMemcpyDeviceToHost, c->stream));
+        if (sigma)
+            HIP_TRY(c, hipMemcpyAsync(sigma, dS, (size_t)np * sizeof(double),
+                                      hipMemcpyDeviceToHost, c->stream));
+    }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return LPT_OK;
+}
+}  // namespace
+
+lpt_status lpt_jacobian(lpt_ctx *c, double *F, int32_t on_device)
+{
+    if (!c) return LPT_E_ARG;
+    if (!F) return fail(c, LPT_E_ARG, "F must not be NULL");
+    return jacobian_sweep(c, F, nullptr, on_device);
+}
+
+lpt_status lpt_ftle(lpt_ctx *c, double *sigma, double *F, int32_t on_device)
+{
+    if (!c) return LPT_E_ARG;
+    if (!sigma) return fail(c, LPT_E_ARG, "sigma must not be NULL");
+    return jacobian_sweep(c, F, sigma, on_device);
 }
 
 lpt_status lpt_sort(lpt_ctx *c)
@@ -1212,7 +1367,7 @@ lpt_status readout(lpt_ctx *c, int32_t sid, double *xw, double *yw, double *xu, 
     HIP_TRY(c, hipSetDevice(c->device));
     double *outs[6] = {xw, yw, xu, yu, vx, vy};
     double *dev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    Staged st;
+    Staged st(c->stream);
     for (int k = 0; k < 6; ++k) {
         if (!outs[k]) continue;
         if (on_device) {
@@ -1320,11 +1475,24 @@ lpt_status lpt_get_timing(lpt_ctx *c, lpt_timing *out, int32_t reset)
         t.perm_step_ms += ms;
         t.perm_steps += 1;
     }
+    for (const auto &p : c->ev_stat) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, p.first, p.second));
+        t.stats_step_ms += ms;
+        t.stats_steps += 1;
+    }
+    for (const auto &p : c->ev_fin) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, p.first, p.second));
+        t.finalize_ms += ms;
+    }
     *out = t;
     if (reset) {
         c->ev_step.clear();
         c->ev_sort.clear();
         c->ev_perm.clear();
+        c->ev_stat.clear();
+        c->ev_fin.clear();
         c->ev_used = 0;
     }
     return LPT_OK;
@@ -1348,7 +1516,7 @@ lpt_status lpt_interp(lpt_ctx *c, lpt_scheme scheme, int64_t npts, const double 
     if (!is_finite(w_a) || !is_finite(w_b)) return fail(c, LPT_E_ARG, "weights must be finite");
     if (npts == 0) return LPT_OK;
     HIP_TRY(c, hipSetDevice(c->device));
-    Staged st;
+    Staged st(c->stream);
     const double *dx = nullptr, *dy = nullptr;
     lpt_status s = stage_in(c, st, x, npts, on_device, dx);
     if (s == LPT_OK) s = stage_in(c, st, y, npts, on_device, dy);
@@ -1616,6 +1784,8 @@ lpt_status lpt_get_tuning(lpt_ctx *c, lpt_tuning *out)
     out->persistent = c->persistent;
     out->graph_chunk = c->graph_chunk;
     out->halo_scale = c->halo_scale;
+    out->max_workgroups = c->max_wg;
+    out->fused = c->fused;
     return LPT_OK;
 }
 
@@ -1637,15 +1807,19 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
     if (t->graph_chunk < 0) return fail(c, LPT_E_ARG, "graph_chunk must be >= 0");
     const float halo = t->halo_scale == 0.0f ? kHaloScaleDefault : t->halo_scale;
     if (!(halo > 0.0f && halo <= 4.0f)) return fail(c, LPT_E_ARG, "halo_scale must be in (0, 4]");
+    if (t->max_workgroups < 0) return fail(c, LPT_E_ARG, "max_workgroups must be >= 0");
+    if (t->fused != 0 && t->fused != 1) return fail(c, LPT_E_ARG, "fused is 0 or 1");
     HIP_TRY(c, hipSetDevice(c->device));
-    if (block != c->block) {
-        // the statistics partials hold one slot per logical block
+    const bool block_changed = block != c->block;
+    if (block_changed) {
+        // the statistics partials hold one slot per wave of every logical block
         const int32_t old = c->block;
         c->block = block;
         const StepParams P = make_params(c);
-        if (P.total_blocks > c->partial_blocks) {
+        const int64_t need = stat_partials_doubles(P, block);
+        if (need > c->partial_cap) {
             double *np = nullptr;
-            if (dalloc(np, (size_t)kStatTerms * P.total_blocks) != hipSuccess) {
+            if (dalloc(np, (size_t)need) != hipSuccess) {
                 c->block = old;
                 (void)hipGetLastError();
                 return fail(c, LPT_E_NOMEM, "statistics partials allocation failed");
@@ -1653,7 +1827,7 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
             HIP_TRY(c, hipStreamSynchronize(c->stream));
             dfree(c->partials);
             c->partials = np;
-            c->partial_blocks = P.total_blocks;
+            c->partial_cap = need;
         }
     }
     c->tile_cap = tile;
@@ -1661,6 +1835,9 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
     c->persistent = t->persistent;
     c->graph_chunk = t->graph_chunk;
     c->halo_scale = halo;
+    c->max_wg = t->max_workgroups;
+    if (t->fused != c->fused || block_changed) c->order_ok = false;
+    c->fused = t->fused;
     invalidate_graphs(c);
     return LPT_OK;
 }

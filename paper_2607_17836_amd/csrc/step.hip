@@ -15,37 +15,6 @@
 #include "field_dev.h"
 
 namespace lpt {
-template <int NT>
-__device__ __forceinline__ void block_sum3(double a, double b, double c, double *out)
-{
-    __shared__ double red[3][NT / kWave];
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        a += __shfl_down(a, off, kWave);
-        b += __shfl_down(b, off, kWave);
-        c += __shfl_down(c, off, kWave);
-    }
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-    if (lane == 0) {
-        red[0][w] = a;
-        red[1][w] = b;
-        red[2][w] = c;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        const int nw = blockDim.x / kWave;
-        for (int k = 0; k < nw; ++k) {
-            s0 += red[0][k];
-            s1 += red[1][k];
-            s2 += red[2][k];
-        }
-        out[0] = s0;
-        out[1] = s1;
-        out[2] = s2;
-    }
-}
-
 
 // One logical block of the FP64 step: the state of slot p is read from S and
 // written to D, in place, or, on a step that follows a re-sort (GATHER), slot
@@ -131,10 +100,10 @@ __device__ __forceinline__ void step64_block(const StepParams &P, const State64 
         r2x = d.x * d.x;
         r2y = d.y * d.y;
     }
-    if (STATS) {
-        const double r2 = r2x + r2y;
-        block_sum3<kMaxBlock>(r2x, r2y, r2 * r2, partials + (int64_t)kStatTerms * lb);
-    }
+    if (STATS)
+        wave_stats(r2x, r2y, active,
+                   partials + (int64_t)kStatTerms *
+                                  ((int64_t)lb * (blockDim.x / kWave) + threadIdx.x / kWave));
     if (lb == 0 && threadIdx.x == 0) {
         clock->t += P.dt;
         clock->step += 1;
@@ -147,15 +116,9 @@ __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64
                                                            double *__restrict__ partials,
                                                            DevClock *clock)
 {
-    if (!P.persistent) {
-        step64_block<CUBIC, INERTIAL, STATS, false>(P, S, S, nullptr, rec, partials, clock,
-                                                    xcd_logical_block(blockIdx.x, gridDim.x));
-        return;
-    }
-    int first, stride, end;
-    persistent_range(P.total_blocks, first, stride, end);
-    for (int lb = first; lb < end; lb += stride)
+    for_each_block(P, 0, P.total_blocks, [&](int lb) {
         step64_block<CUBIC, INERTIAL, STATS, false>(P, S, S, nullptr, rec, partials, clock, lb);
+    });
 }
 
 // The FP64 step that follows a re-sort: reads S through perm, writes D.
@@ -166,15 +129,9 @@ __global__ __launch_bounds__(kMaxBlock) void step64_perm_kernel(StepParams P, St
                                                                 double *__restrict__ partials,
                                                                 DevClock *clock)
 {
-    if (!P.persistent) {
-        step64_block<CUBIC, INERTIAL, STATS, true>(P, S, D, perm, rec, partials, clock,
-                                                   xcd_logical_block(blockIdx.x, gridDim.x));
-        return;
-    }
-    int first, stride, end;
-    persistent_range(P.total_blocks, first, stride, end);
-    for (int lb = first; lb < end; lb += stride)
+    for_each_block(P, 0, P.total_blocks, [&](int lb) {
         step64_block<CUBIC, INERTIAL, STATS, true>(P, S, D, perm, rec, partials, clock, lb);
+    });
 }
 
 // ===========================================================================
@@ -563,8 +520,9 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
 }
 
 // The particle body for the block's kind.  SCHS: the scheme of every species
-// of the launch (one launch per scheme).  KINDS: 0 tracers only (St == 0
-// included), 1 tracers and/or inertial species.
+// of the launch (one launch per scheme), or kAnyScheme in a fused launch.
+// KINDS: 0 tracers only (St == 0 included), 1 tracers and/or inertial
+// species.
 template <int SCHS, int KINDS, bool ONE, bool GATHER>
 __device__ __forceinline__ void particle_dispatch(const StepParams &P, const State32 &S,
                                                   const State32 &D,
@@ -574,6 +532,18 @@ __device__ __forceinline__ void particle_dispatch(const StepParams &P, const Sta
                                                   uint32_t &cell, float2 o, double &r2x,
                                                   double &r2y)
 {
+    if constexpr (SCHS == kAnyScheme) {   // fused launch: the block's species decides
+        if (sp.scheme == kBilinear)
+            particle_dispatch<kBilinear, KINDS, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell,
+                                                             o, r2x, r2y);
+        else if (sp.scheme == kCatmullRom)
+            particle_dispatch<kCatmullRom, KINDS, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q,
+                                                               cell, o, r2x, r2y);
+        else
+            particle_dispatch<kBSpline, KINDS, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell,
+                                                            o, r2x, r2y);
+        return;
+    }
     if (KINDS != 0 && sp.inertial)
         particle32<SCHS, KINDS != 0, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x,
                                                   r2y);
@@ -630,40 +600,32 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
                                                           r2x, r2y);
         if (GATHER) D.id[p] = S.id[q];
     }
-    if (STATS) {
-        const double r2 = r2x + r2y;
-        block_sum3<kMaxBlock>(r2x, r2y, r2 * r2, partials + (int64_t)kStatTerms * lb);
-    }
+    if (STATS)
+        wave_stats(r2x, r2y, active,
+                   partials + (int64_t)kStatTerms *
+                                  ((int64_t)lb * (blockDim.x / kWave) + threadIdx.x / kWave));
     if (lb == 0 && threadIdx.x == 0) {
         clock->t += P.dt;
         clock->step += 1;
     }
 }
 
-// One launch advances every particle by one step.  Normal launches map one
-// workgroup to one logical block (XCD-aware order); with P.persistent set the
-// grid is sized to the resident capacity and each workgroup walks a
-// contiguous range of logical blocks of its own XCD.
+// One launch advances every particle of its logical blocks by one step
+// (for_each_block: one workgroup per logical block in XCD-aware order, a
+// persistent walk, or a fused launch's block-order table).
 // Bilinear blocks hold eight 256-thread blocks per CU (the LDS tile's
 // budget), i.e. eight waves per SIMD, so their registers are bounded to fit
-// that; the bicubic bodies need more registers and keep the default bound.
+// that; the bicubic bodies, and the fused kernel that holds every body
+// (SCHS = kAnyScheme), need more registers and keep the default bound.
 template <int SCHS, int KINDS, bool STATS>
 __global__ __launch_bounds__(kMaxBlock)
 __attribute__((amdgpu_waves_per_eu(SCHS == kBilinear ? 8 : 6)))
 void step32_kernel(StepParams P, State32 S, const float4 *__restrict__ rec,
                    double *__restrict__ partials, DevClock *clock)
 {
-    if (!P.persistent) {
-        step32_block<SCHS, KINDS, STATS, false>(
-            P, S, S, nullptr, rec, partials, clock,
-            P.block_base + xcd_logical_block(blockIdx.x, gridDim.x));
-        return;
-    }
-    int first, stride, end;
-    persistent_range(P.launch_blocks, first, stride, end);
-    for (int lb = first; lb < end; lb += stride)
-        step32_block<SCHS, KINDS, STATS, false>(P, S, S, nullptr, rec, partials, clock,
-                                                P.block_base + lb);
+    for_each_block(P, P.block_base, P.launch_blocks, [&](int lb) {
+        step32_block<SCHS, KINDS, STATS, false>(P, S, S, nullptr, rec, partials, clock, lb);
+    });
 }
 
 // The step that follows a re-sort: reads S through perm, writes D.  (A kernel
@@ -675,29 +637,24 @@ void step32_perm_kernel(StepParams P, State32 S, State32 D, const uint32_t *perm
                         const float4 *__restrict__ rec, double *__restrict__ partials,
                         DevClock *clock)
 {
-    if (!P.persistent) {
-        step32_block<SCHS, KINDS, STATS, true>(
-            P, S, D, perm, rec, partials, clock,
-            P.block_base + xcd_logical_block(blockIdx.x, gridDim.x));
-        return;
-    }
-    int first, stride, end;
-    persistent_range(P.launch_blocks, first, stride, end);
-    for (int lb = first; lb < end; lb += stride)
-        step32_block<SCHS, KINDS, STATS, true>(P, S, D, perm, rec, partials, clock,
-                                               P.block_base + lb);
+    for_each_block(P, P.block_base, P.launch_blocks, [&](int lb) {
+        step32_block<SCHS, KINDS, STATS, true>(P, S, D, perm, rec, partials, clock, lb);
+    });
 }
 
-// Grid of a launch: one workgroup per logical block, or -- when the step
-// parameters ask for a persistent launch -- as many workgroups as the device
-// keeps resident (occupancy of this kernel at this block size and LDS size,
-// times the CU count), if that is fewer.
+// Grid of a launch: one workgroup per logical block (per table entry in a
+// fused launch), or -- when the step parameters ask for a persistent launch
+// -- as many workgroups as the device keeps resident (occupancy of this
+// kernel at this block size and LDS size, times the CU count, capped at
+// P.max_wg if set; a multiple of the XCD count in a fused launch), if that
+// is fewer.
 template <typename K>
 static int launch_grid(K kernel, const StepParams &P, int block, size_t lds, int grid,
                        StepParams &Q)
 {
     Q = P;
     Q.persistent = 0;
+    if (P.order) grid = 8 * P.order_len;
     if (!P.persistent) return grid;
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -707,7 +664,9 @@ static int launch_grid(K kernel, const StepParams &P, int block, size_t lds, int
         (void)hipGetLastError();
         return grid;
     }
-    const int64_t resident = (int64_t)per_cu * cus;
+    int64_t resident = (int64_t)per_cu * cus;
+    if (P.max_wg > 0 && resident > P.max_wg) resident = P.max_wg;
+    if (P.order) resident = resident < 8 ? 8 : resident / 8 * 8;
     if (resident >= grid) return grid;
     Q.persistent = 1;
     return (int)resident;
@@ -808,70 +767,165 @@ hipError_t launch_step32(const StepParams &P, const State32 &S, const State32 &D
     case kBSpline:
         return launch32_s<kBSpline>(P, S, D, perm, rec, partials, clock, stats, inertial, block,
                                     grid, st);
+    case kAnyScheme:
+        return launch32_s<kAnyScheme>(P, S, D, perm, rec, partials, clock, stats, inertial,
+                                      block, grid, st);
     default:
         return hipErrorInvalidValue;
     }
 }
 // ===========================================================================
-// Statistics: fixed-order reduction of the per-block partial sums into one
-// record per species (Sec. 3.2 and 5.5 quantities).
+// Statistics: fixed-order merge of the per-wave partials into one record per
+// species (Sec. 3.2 and 5.5 quantities).  A partial is (count, sum dx^2,
+// sum dy^2, M2) with M2 the sum of squared deviations of r2 = dx^2 + dy^2
+// about the partial's own mean; two partials merge by the pairwise update of
+// Chan, Golub & LeVeque (1979): n = na + nb, delta = mean_b - mean_a,
+// M2 = M2a + M2b + delta^2 na nb / n.  Stage 1 merges runs of kFinChunk
+// waves of one species per workgroup, stage 2 merges the runs of each
+// species in one workgroup; both in a fixed order (sequential per thread,
+// then a pairwise tree), so the record does not depend on scheduling.
 // ===========================================================================
 constexpr int kFinThreads = 256;
+constexpr int kFinPerThread = 4;
+constexpr int kFinChunk = kFinThreads * kFinPerThread;   // waves per stage-1 workgroup
 
-__global__ __launch_bounds__(kFinThreads) void finalize_kernel(StepParams P,
-                                                               const double *__restrict__ partials,
-                                                               DevClock *clock, double *records,
-                                                               int64_t cap, double t0)
+struct Moments {
+    double n, sx, sy, m2;
+};
+
+__device__ __forceinline__ Moments merge_moments(const Moments &a, const Moments &b)
 {
-    __shared__ double sm[kStatTerms][kFinThreads];
+    if (b.n == 0.0) return a;
+    if (a.n == 0.0) return b;
+    const double n = a.n + b.n;
+    const double d = (b.sx + b.sy) / b.n - (a.sx + a.sy) / a.n;
+    return Moments{n, a.sx + b.sx, a.sy + b.sy, a.m2 + b.m2 + d * d * (a.n * b.n / n)};
+}
+
+struct FinParams {
+    int32_t nspecies;
+    int32_t chunk_begin[kMaxSpecies + 1];   // first stage-1 chunk of each species
+    int64_t wave_begin[kMaxSpecies];        // first wave partial of each species
+    int64_t nwaves[kMaxSpecies];
+    int64_t count[kMaxSpecies];
+};
+
+// Pairwise tree over the block's kFinThreads moments in LDS (fixed order);
+// returns the total in thread 0.  Entered with every thread holding its own.
+__device__ __forceinline__ Moments block_merge(Moments m)
+{
+    __shared__ double sm[4][kFinThreads];
+    const int t = threadIdx.x;
+    sm[0][t] = m.n;
+    sm[1][t] = m.sx;
+    sm[2][t] = m.sy;
+    sm[3][t] = m.m2;
+    __syncthreads();
+    for (int w = kFinThreads / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            const Moments a{sm[0][t], sm[1][t], sm[2][t], sm[3][t]};
+            const Moments b{sm[0][t + w], sm[1][t + w], sm[2][t + w], sm[3][t + w]};
+            const Moments r = merge_moments(a, b);
+            sm[0][t] = r.n;
+            sm[1][t] = r.sx;
+            sm[2][t] = r.sy;
+            sm[3][t] = r.m2;
+        }
+        __syncthreads();
+    }
+    const Moments r{sm[0][0], sm[1][0], sm[2][0], sm[3][0]};
+    __syncthreads();   // the array is reused by the next call
+    return r;
+}
+
+__global__ __launch_bounds__(kFinThreads) void fin_chunks_kernel(FinParams F,
+                                                                 const double *__restrict__ partials,
+                                                                 double *__restrict__ chunks)
+{
+    const int c = blockIdx.x;
+    int s = 0;
+    while (s + 1 < F.nspecies && c >= F.chunk_begin[s + 1]) ++s;
+    const int64_t w0 = (int64_t)(c - F.chunk_begin[s]) * kFinChunk;
+    Moments m{0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < kFinPerThread; ++k) {
+        const int64_t lw = w0 + (int64_t)threadIdx.x * kFinPerThread + k;   // wave within the species
+        if (lw >= F.nwaves[s]) break;
+        const int64_t left = F.count[s] - lw * kWave;
+        const double cnt = (double)(left < kWave ? (left > 0 ? left : 0) : kWave);
+        const double *q = partials + (int64_t)kStatTerms * (F.wave_begin[s] + lw);
+        m = merge_moments(m, Moments{cnt, q[0], q[1], q[2]});
+    }
+    m = block_merge(m);
+    if (threadIdx.x == 0) {
+        double *o = chunks + 4 * (int64_t)c;
+        o[0] = m.n;
+        o[1] = m.sx;
+        o[2] = m.sy;
+        o[3] = m.m2;
+    }
+}
+
+__global__ __launch_bounds__(kFinThreads) void fin_records_kernel(FinParams F,
+                                                                  const double *__restrict__ chunks,
+                                                                  DevClock *clock, double *records,
+                                                                  int64_t cap, double t0)
+{
     const double t = clock->t;
     const int64_t idx = clock->nrec;
-    const int tid = threadIdx.x;
-    for (int s = 0; s < P.nspecies; ++s) {
-        const SpeciesDev &sp = P.sp[s];
-        double a = 0.0, b = 0.0, c = 0.0;
-        for (int k = sp.block_begin + tid; k < sp.block_end; k += kFinThreads) {
-            a += partials[(int64_t)kStatTerms * k + 0];
-            b += partials[(int64_t)kStatTerms * k + 1];
-            c += partials[(int64_t)kStatTerms * k + 2];
+    for (int s = 0; s < F.nspecies; ++s) {
+        Moments m{0.0, 0.0, 0.0, 0.0};
+        for (int c = F.chunk_begin[s] + (int)threadIdx.x; c < F.chunk_begin[s + 1]; c += kFinThreads) {
+            const double *q = chunks + 4 * (int64_t)c;
+            m = merge_moments(m, Moments{q[0], q[1], q[2], q[3]});
         }
-        sm[0][tid] = a;
-        sm[1][tid] = b;
-        sm[2][tid] = c;
-        __syncthreads();
-        for (int w = kFinThreads / 2; w > 0; w >>= 1) {
-            if (tid < w) {
-                sm[0][tid] += sm[0][tid + w];
-                sm[1][tid] += sm[1][tid + w];
-                sm[2][tid] += sm[2][tid + w];
-            }
-            __syncthreads();
-        }
-        if (tid == 0 && idx < cap) {
-            const double nn = (double)sp.count;
-            const double mx = sm[0][0] / nn, my = sm[1][0] / nn, m = mx + my;
-            double var = sp.count > 1 ? (sm[2][0] - nn * m * m) / (nn - 1.0) : 0.0;
-            if (var < 0.0) var = 0.0;
+        m = block_merge(m);
+        if (threadIdx.x == 0 && idx < cap) {
+            const double nn = (double)F.count[s];
+            const double mx = m.sx / nn, my = m.sy / nn;
+            const double var = F.count[s] > 1 ? m.m2 / (nn - 1.0) : 0.0;
             const double el = t - t0;
             double *r = records + ((int64_t)s * cap + idx) * 8;
             r[0] = t;
             r[1] = mx;
             r[2] = my;
-            r[3] = m;
+            r[3] = mx + my;
             r[4] = el > 0.0 ? mx / (2.0 * el) : 0.0;
             r[5] = el > 0.0 ? my / (2.0 * el) : 0.0;
             r[6] = sqrt(var / nn);
-            reinterpret_cast<int64_t *>(r)[7] = sp.count;
+            reinterpret_cast<int64_t *>(r)[7] = F.count[s];
         }
-        __syncthreads();
     }
-    if (tid == 0) clock->nrec = idx + 1;
+    if (threadIdx.x == 0) clock->nrec = idx + 1;
 }
 
-hipError_t launch_finalize(const StepParams &P, const double *partials, DevClock *clock,
-                           double *records, int64_t rec_cap, double t0, hipStream_t st)
+int64_t stat_partials_doubles(const StepParams &P, int block)
 {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, st, P, partials, clock,
+    const int64_t waves = (int64_t)P.total_blocks * (block / kWave);
+    return (int64_t)kStatTerms * waves + 4 * (waves / kFinChunk + P.nspecies + 1);
+}
+
+hipError_t launch_finalize(const StepParams &P, double *partials, DevClock *clock,
+                           double *records, int64_t rec_cap, double t0, int block,
+                           hipStream_t st)
+{
+    const int wpb = block / kWave;
+    FinParams F{};
+    F.nspecies = P.nspecies;
+    int chunks = 0;
+    for (int s = 0; s < P.nspecies; ++s) {
+        const SpeciesDev &d = P.sp[s];
+        F.chunk_begin[s] = chunks;
+        F.wave_begin[s] = (int64_t)d.block_begin * wpb;
+        F.nwaves[s] = (int64_t)(d.block_end - d.block_begin) * wpb;
+        F.count[s] = d.count;
+        chunks += (int)((F.nwaves[s] + kFinChunk - 1) / kFinChunk);
+    }
+    F.chunk_begin[P.nspecies] = chunks;
+    double *chunk_buf = partials + (int64_t)kStatTerms * P.total_blocks * wpb;
+    if (chunks > 0)
+        hipLaunchKernelGGL(fin_chunks_kernel, dim3(chunks), dim3(kFinThreads), 0, st, F, partials,
+                           chunk_buf);
+    hipLaunchKernelGGL(fin_records_kernel, dim3(1), dim3(kFinThreads), 0, st, F, chunk_buf, clock,
                        records, rec_cap, t0);
     return hipGetLastError();
 }

@@ -1,4 +1,4 @@
-// Complex FFT of N = 512, 1024 or 2048 FP64 points held in LDS, computed by
+// Complex FFT of N = 64, 128, ..., 4096 FP64 points held in LDS, computed by
 // one workgroup of N / 8 threads.
 //
 // Stockham autosort formulation (Govindaraju et al., "High performance
@@ -7,7 +7,9 @@
 // exp(-+2 pi i r k / (Ns R)) with k = j mod Ns (Ns = product of the earlier
 // radices), applies the R-point DFT and writes the outputs at stride Ns
 // starting from (j - k) R + k; after the last pass the result is in natural
-// order.  Radices 8, 8, 8 and a last 2 or 4.  Each pass first reads all of a
+// order.  Radix-8 passes and a last 2 or 4 where log2 N is not a multiple of
+// 3 (64 = 8 8, 128 = 8 8 2, 256 = 8 8 4, 512 = 8 8 8, 1024 = 8 8 8 2,
+// 2048 = 8 8 8 4, 4096 = 8 8 8 8).  Each pass first reads all of a
 // thread's inputs into registers, then (after a barrier) writes, so one LDS
 // buffer suffices.  Forward: exp(-2 pi i jk / N); inverse: exp(+2 pi i jk / N),
 // unnormalised.  Twiddles come from a table W[m] = exp(-2 pi i m / N).
@@ -130,12 +132,15 @@ __device__ __forceinline__ void pass(double2 *buf, int Ns, const double2 *__rest
 template <int N, bool INV>
 __device__ __forceinline__ void fft(double2 *buf, const double2 *__restrict__ W)
 {
-    static_assert(N == 512 || N == 1024 || N == 2048, "built-in transform sizes");
+    static_assert(N >= 64 && N <= 4096 && (N & (N - 1)) == 0, "built-in transform sizes");
     pass<N, 8, INV>(buf, 1, W);
     pass<N, 8, INV>(buf, 8, W);
-    pass<N, 8, INV>(buf, 64, W);
+    if constexpr (N == 128) pass<N, 2, INV>(buf, 64, W);
+    if constexpr (N == 256) pass<N, 4, INV>(buf, 64, W);
+    if constexpr (N >= 512) pass<N, 8, INV>(buf, 64, W);
     if constexpr (N == 1024) pass<N, 2, INV>(buf, 512, W);
     if constexpr (N == 2048) pass<N, 4, INV>(buf, 512, W);
+    if constexpr (N == 4096) pass<N, 8, INV>(buf, 512, W);
 }
 
 }  // namespace ns_fft

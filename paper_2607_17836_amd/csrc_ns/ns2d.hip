@@ -16,8 +16,10 @@
 // Every pointwise operation lives in the two kernels, so each step reads and
 // writes each spectral array once.
 //
-// For n = 512, 1024 and 2048 the built-in transforms (fft_lds.h) replace
-// the library's and fuse with the pointwise work, in four kernels a step
+// For every power of two n from 64 to 4096 (the default) the built-in
+// transforms (fft_lds.h) replace the library's (which stay available as an
+// explicit cross-check, and for other n) and fuse with the pointwise work,
+// in four kernels a step
 // over a transposed spectral layout (entry (row jy, column ix) of a
 // half-plane spectrum at ix * n + jy, so that every column is contiguous)
 // that holds only the columns inside the 2/3 band:
@@ -151,20 +153,20 @@ __global__ __launch_bounds__(kBlock) void scaled_kernel(const double2 *__restric
     out[idx] = make_double2(w.x * S.inv_nn, w.y * S.inv_nn);
 }
 
-// ---- built-in transform path (n = 512, 1024, 2048) ------------------------
+// ---- built-in transform path (n = 64, 128, ..., 4096) ---------------------
 
 // Grid rows per row-pass block: four (two packed complex rows, 2N entries of
-// LDS) at N = 2048, two (one packed row) below, where twice as many blocks
-// fill the chip better (measured: 1024^2 step 71.9 -> 61.1 us; 2048^2 step
-// 163 -> 167 us with two).
+// LDS) at N = 2048, two (one packed row) elsewhere: below 2048 twice as many
+// blocks fill the chip better (measured: 1024^2 step 71.9 -> 61.1 us; 2048^2
+// step 163 -> 167 us with two), and at 4096 one packed row is 64 KiB of LDS.
 template <int N>
-constexpr int rows_per_block() { return N >= 2048 ? 4 : 2; }
+constexpr int rows_per_block() { return N == 2048 ? 4 : 2; }
 
-// Inverse row pass: one block per field and slab below N = 2048 (1024^2 step
-// 56.1 -> 52.3 us, 512^2 33.1 -> 30.7 us); at 2048 one block per slab walks
+// Inverse row pass: one block per field and slab (1024^2 step 56.1 -> 52.3
+// us, 512^2 33.1 -> 30.7 us), except at 2048, where one block per slab walks
 // the four fields (161 us a step against 185 with a block per field).
 template <int N>
-constexpr bool field_blocks() { return N < 2048; }
+constexpr bool field_blocks() { return N != 2048; }
 
 // Contiguous logical block ranges per XCD (workgroups go to the eight XCDs
 // round-robin): XCD x = b mod 8 takes logical blocks [x G/8, (x+1) G/8) up to
@@ -497,9 +499,13 @@ ns2d_status run_builtin_n(ns2d_ctx *c, BuiltinOp op)
 ns2d_status run_builtin(ns2d_ctx *c, BuiltinOp op)
 {
     switch (c->n) {
+    case 64: return run_builtin_n<64>(c, op);
+    case 128: return run_builtin_n<128>(c, op);
+    case 256: return run_builtin_n<256>(c, op);
     case 512: return run_builtin_n<512>(c, op);
     case 1024: return run_builtin_n<1024>(c, op);
     case 2048: return run_builtin_n<2048>(c, op);
+    case 4096: return run_builtin_n<4096>(c, op);
     default: return fail(c, NS2D_E_STATE, "no built-in transform for this n");
     }
 }
@@ -534,7 +540,10 @@ ns2d_status ns2d_create(const ns2d_config *cfg, ns2d_ctx **out)
     if (!(cfg->nu >= 0.0) || !std::isfinite(cfg->nu)) return NS2D_E_ARG;
     if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) return NS2D_E_ARG;
     if (cfg->transforms < 0 || cfg->transforms > 2) return NS2D_E_ARG;
-    if (cfg->transforms == 2 && n != 512 && n != 1024 && n != 2048) return NS2D_E_ARG;
+    // the built-in transforms (transforms 0 or 2) exist for powers of two
+    // from 64 to 4096; hipFFT only on request (transforms 1)
+    const bool own = cfg->transforms != 1;
+    if (own && (n < 64 || n > 4096 || (n & (n - 1)))) return NS2D_E_ARG;
     ns2d_ctx *c = new (std::nothrow) ns2d_ctx;
     if (!c) return NS2D_E_NOMEM;
     c->n = n;
@@ -558,9 +567,9 @@ ns2d_status ns2d_create(const ns2d_config *cfg, ns2d_ctx **out)
         (void)hipGetLastError();
         return bail(NS2D_E_NOMEM);
     }
-    // measured faster than hipFFT at every built-in size (2048^2: 163 vs
-    // 337 us a step; 1024^2: 61 vs 101; 512^2: 35 vs 43)
-    c->builtin = cfg->transforms != 1 && (n == 512 || n == 1024 || n == 2048);
+    // measured faster than hipFFT at the sizes compared (2048^2: 161 vs 337
+    // us a step; 1024^2: 53 vs 101; 512^2: 31 vs 43)
+    c->builtin = own;
     if (c->builtin) {
         // twiddles from the long-double cosine and sine, rounded once
         std::vector<double2> w(n);

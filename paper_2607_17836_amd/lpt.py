@@ -27,6 +27,7 @@ TRACER, INERTIAL = 0, 1
 TIME_BRACKET, TIME_PINGPONG = 0, 1
 FLAG_COMPAT_EDGE = 0x1
 FLAG_TIME_KERNELS = 0x2
+FLAG_DETERMINISTIC_GRAD = 0x4
 
 SCHEMES = {"bilinear": BILINEAR, "catmull_rom": CATMULL_ROM, "bspline": BSPLINE}
 PRECISIONS = {"fp64": FP64, "fp32_split": FP32_SPLIT}
@@ -45,13 +46,16 @@ class LptConfig(C.Structure):
 class LptTuning(C.Structure):
     _fields_ = [("block_size", C.c_int32), ("tile_records", C.c_int32),
                 ("sort_interval", C.c_int32), ("persistent", C.c_int32),
-                ("graph_chunk", C.c_int32), ("halo_scale", C.c_float)]
+                ("graph_chunk", C.c_int32), ("halo_scale", C.c_float),
+                ("max_workgroups", C.c_int32), ("fused", C.c_int32)]
 
 
 class LptTiming(C.Structure):
     _fields_ = [("step_kernel_ms", C.c_double), ("step_launches", C.c_int64),
                 ("sort_ms", C.c_double), ("sorts", C.c_int64),
-                ("perm_step_ms", C.c_double), ("perm_steps", C.c_int64)]
+                ("perm_step_ms", C.c_double), ("perm_steps", C.c_int64),
+                ("stats_step_ms", C.c_double), ("stats_steps", C.c_int64),
+                ("finalize_ms", C.c_double)]
 
 
 STAT_DTYPE = np.dtype([("t", "<f8"), ("msd_x", "<f8"), ("msd_y", "<f8"), ("msd", "<f8"),
@@ -90,6 +94,7 @@ _SIGS = [
     ("lpt_forward_checkpointed", C.c_int, [_P, C.c_int64, C.c_double, C.c_int32]),
     ("lpt_adjoint", C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int32]),
     ("lpt_jacobian", C.c_int, [_P, _P, C.c_int32]),
+    ("lpt_ftle", C.c_int, [_P, _P, _P, C.c_int32]),
     ("lpt_bw_probe", C.c_int, [_P, C.c_int64, C.c_int32, C.POINTER(C.c_double),
                                C.POINTER(C.c_double)]),
 ]
@@ -141,7 +146,7 @@ class Tracker:
 
     def __init__(self, n, precision="fp64", length=0.0, t0=0.0, stream=None, sort_interval=0,
                  sort_tile=0, block_size=0, compat_edge=False, time_kernels=False,
-                 tile_records=0):
+                 tile_records=0, deterministic_grad=False):
         lib = load()
         cfg = LptConfig()
         cfg.n = n
@@ -153,7 +158,9 @@ class Tracker:
         cfg.sort_tile = sort_tile
         cfg.block_size = block_size
         cfg.tile_records = tile_records
-        cfg.flags = (FLAG_COMPAT_EDGE if compat_edge else 0) | (FLAG_TIME_KERNELS if time_kernels else 0)
+        cfg.flags = ((FLAG_COMPAT_EDGE if compat_edge else 0) |
+                     (FLAG_TIME_KERNELS if time_kernels else 0) |
+                     (FLAG_DETERMINISTIC_GRAD if deterministic_grad else 0))
         h = C.c_void_p()
         st = lib.lpt_create(C.byref(cfg), C.byref(h))
         if st != OK:
@@ -270,9 +277,7 @@ class Tracker:
     def get_timing(self, reset=True):
         t = LptTiming()
         self._check(load().lpt_get_timing(self._h, C.byref(t), int(reset)))
-        return dict(step_kernel_ms=t.step_kernel_ms, step_launches=t.step_launches,
-                    sort_ms=t.sort_ms, sorts=t.sorts, perm_step_ms=t.perm_step_ms,
-                    perm_steps=t.perm_steps)
+        return {k: getattr(t, k) for k, _ in LptTiming._fields_}
 
     def get_time(self):
         s, t = C.c_int64(), C.c_double()
@@ -360,6 +365,17 @@ class Tracker:
         self._check(load().lpt_jacobian(self._h, F.ctypes.data, 0))
         return F
 
+    def ftle(self, with_jacobian=False):
+        """FTLE sigma [np] (numpy) of the last checkpointed run over its
+        duration, computed by the library (lpt_ftle); with_jacobian also
+        returns F [np, 2, 2] from the same reverse sweep."""
+        np_ = sum(self.counts)
+        sig = np.empty(np_)
+        F = np.empty((np_, 2, 2)) if with_jacobian else None
+        self._check(load().lpt_ftle(self._h, sig.ctypes.data,
+                                    F.ctypes.data if F is not None else None, 0))
+        return (sig, F) if with_jacobian else sig
+
     def radix_sort(self, keys, key_bits):
         """Stable sort of a device uint32 tensor (as torch.int32 storage);
         returns (sorted keys, permutation) as device tensors."""
@@ -433,14 +449,3 @@ if torch is not None:
             gUb = gU[1] if gU is not None else None
             return gx0, gy0, gUa, gUb, None, None, None, None, None, None
 
-
-def ftle(F, T):
-    """Finite-time Lyapunov exponent (1/T) ln sqrt(lambda_max(F^T F)) of
-    Jacobians F [np, 2, 2] (closed-form largest eigenvalue of the symmetric
-    2x2 Cauchy-Green tensor)."""
-    F = np.asarray(F)
-    a = F[:, 0, 0] ** 2 + F[:, 1, 0] ** 2
-    d = F[:, 0, 1] ** 2 + F[:, 1, 1] ** 2
-    b = F[:, 0, 0] * F[:, 0, 1] + F[:, 1, 0] * F[:, 1, 1]
-    lam = 0.5 * (a + d) + np.sqrt(0.25 * (a - d) ** 2 + b * b)
-    return np.log(np.sqrt(lam)) / T

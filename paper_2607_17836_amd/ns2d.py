@@ -1,8 +1,8 @@
 """Thin ctypes binding of libns2d.so (include/ns2d.h), the Eulerian field
 producer that feeds the particle path.
 
-Argument marshalling only: every step runs in libns2d.so (hipFFT transforms
-and the library's own kernels).  Arrays may be numpy (host) or torch CUDA
+Argument marshalling only: every step runs in libns2d.so (its own LDS
+transforms and kernels; hipFFT only when asked for).  Arrays may be numpy (host) or torch CUDA
 tensors (device).  Loading fails loudly when the native library is missing.
 """
 from __future__ import annotations
@@ -71,8 +71,8 @@ class Ns2d:
     """One libns2d context (see include/ns2d.h for every call)."""
 
     def __init__(self, n, nu, dt, length=0.0, stream=None, transforms="auto"):
-        """transforms: "auto" (the library's own for n = 512, 1024, 2048,
-        hipFFT otherwise), "hipfft", or "builtin" (n = 512, 1024, 2048 only)."""
+        """transforms: "auto" or "builtin" (the library's own, for n a power
+        of two from 64 to 4096), or "hipfft" (any even n; a cross-check)."""
         cfg = Ns2dConfig(n=n, length=length, nu=nu, dt=dt, hip_stream=stream,
                          transforms={"auto": 0, "hipfft": 1, "builtin": 2}[transforms])
         h = C.c_void_p()

@@ -55,7 +55,7 @@ def test_status_strings():
     dict(n=3), dict(n=40000), dict(n=64, precision=7), dict(n=64, length=-1.0),
     dict(n=64, length=float("nan")), dict(n=64, sort_interval=-2), dict(n=64, sort_tile=3),
     dict(n=48, sort_tile=32), dict(n=64, block_size=100), dict(n=64, block_size=2048),
-    dict(n=64, flags=0x80), dict(n=64, flags=0x4), dict(n=64, t0=float("inf")),
+    dict(n=64, flags=0x80), dict(n=64, flags=0x8), dict(n=64, t0=float("inf")),
 ])
 def test_create_rejects_bad_config_without_gpu(kw):
     _built()

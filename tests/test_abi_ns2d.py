@@ -41,7 +41,9 @@ def test_library_exports_every_declared_symbol():
     dict(n=6), dict(n=31), dict(n=32768), dict(n=64, length=-1.0),
     dict(n=64, length=float("nan")), dict(n=64, nu=-1e-3), dict(n=64, nu=float("inf")),
     dict(n=64, dt=0.0), dict(n=64, dt=float("nan")), dict(n=64, transforms=3),
-    dict(n=64, transforms=-1), dict(n=64, transforms=2), dict(n=4096, transforms=2),
+    dict(n=64, transforms=-1), dict(n=96, transforms=2), dict(n=8192, transforms=2),
+    # the default (own transforms) needs a power of two from 64 to 4096
+    dict(n=32), dict(n=96), dict(n=8192),
 ])
 def test_create_rejects_bad_config_without_gpu(kw):
     L = _built()

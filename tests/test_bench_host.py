@@ -12,14 +12,20 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_algorithmic_bytes_per_particle_step():
-    # 2 x 28 B of split state (cell 4, offset 8, FP64 displacement 16) plus
-    # the 4096^2 x 16 B field pair read once, shared by the particles
+    # 2 x 32 B of split state (int32 cell pair 8, binary32 offsets 8, FP64
+    # displacement 16) plus the 4096^2 x 16 B field pair read once, shared by
+    # the particles: 80 B; the library's packed cell word moves 72 B
     w = workloads.C3_SPLIT
-    assert bench.alg_bytes_per_step(w) / w.particles == 2 * 28 + 4096 ** 2 * 16 / 2 ** 24 == 72.0
+    assert bench.alg_bytes_per_step(w) / w.particles == 2 * 32 + 4096 ** 2 * 16 / 2 ** 24 == 80.0
+    assert bench.alg_bytes_per_step(w, layout=True) / w.particles == 72.0
     s = workloads.C3_SHARE8
-    assert bench.alg_bytes_per_step(s) / s.particles == 2 * 28 + 4096 ** 2 * 16 / 2 ** 21 == 184.0
+    assert bench.alg_bytes_per_step(s) / s.particles == 2 * 32 + 4096 ** 2 * 16 / 2 ** 21 == 192.0
     d = dataclasses.replace(w, precision="fp64")
     assert bench.alg_bytes_per_step(d) / d.particles == 2 * 32 + 4096 ** 2 * 32 / 2 ** 24 == 96.0
+    # the batching mix: tracers 32 B, inertial 40 B of state, 2048^2 x 16 B field
+    c = workloads.C4_BATCH
+    exp = sum(cnt * 2 * (40 if kind == "inertial" else 32) for kind, _, _, cnt, _ in c.species)
+    assert bench.alg_bytes_per_step(c) == exp + 2048 ** 2 * 16
 
 
 def test_multi_gpu_request_exits_with_a_message():

@@ -190,8 +190,9 @@ def test_ftle_field_on_a_lattice_matches_oracle():
     tr = _setup(n, "bilinear", "bracket", x0, y0, ((u, v), (u, v)), (0.0, nsteps * dt))
     tr.forward_checkpointed(nsteps, dt, 20)
     F = tr.jacobian()
+    sig, F2 = tr.ftle(with_jacobian=True)   # the library's FTLE (lpt_ftle)
     tr.close()
-    sig = lpt.ftle(F, nsteps * dt)
+    np.testing.assert_array_equal(F2, F)
     ids = np.random.default_rng(4).choice(x0.size, 96, replace=False)
     fl = oracle.grid_flow(u, v, scheme="bilinear", t_slot=(0.0, nsteps * dt))
     Fo = oracle.tangent(fl, oracle.Species(x0[ids], y0[ids]), nsteps, dt)
@@ -306,3 +307,43 @@ def test_full_size_adjoint_sampled():
         fd = (Ls[0] - Ls[1]) / (2 * h)
         say(f"  node ({i}, {j}): adjoint {g0[j, i]:.9g}, central difference {fd:.9g}")
         assert abs(fd - g0[j, i]) < 2e-5 * gmax, (i, j, fd, g0[j, i])
+
+
+@pytest.mark.parametrize("scheme", ["bilinear", "catmull_rom"])
+def test_deterministic_grid_gradient_is_bit_reproducible(scheme):
+    """LPT_FLAG_DETERMINISTIC_GRAD sums the grid gradient as exact
+    fixed-point integers: two runs, and runs with 64- and 512-thread blocks
+    (other LDS boxes, other atomic orders), give the same bits; the result
+    matches the oracle's reverse sweep within 1e-10 of its largest entry and
+    the default FP64-atomic gradient within 1e-12; dL/dx0 is unchanged."""
+    n, dt, nsteps, count = 64, 0.01, 30, 5000
+    say(f"deterministic grid gradient {scheme}")
+    fields = synth.spectrum_snapshots(n, 6, 14, dt)
+    x0, y0 = oracle.init_uniform(33, count)
+    rng = np.random.default_rng(34)
+    a, b = rng.normal(size=count), rng.normal(size=count)
+
+    def run(det, block):
+        (ua, va), (ub, vb) = fields
+        tr = lpt.Tracker(n, "fp64", block_size=block, sort_interval=1, deterministic_grad=det)
+        tr.set_time_mode("pingpong")
+        tr.set_snapshot(0, 0.0, ua, va)
+        tr.set_snapshot(1, dt, ub, vb)
+        tr.add_species("tracer", 0.0, scheme, x0, y0)
+        tr.forward_checkpointed(nsteps, dt, 10)
+        out = tr.adjoint(a, b)
+        tr.close()
+        return out
+
+    d1, d2, d64, d512 = run(True, 0), run(True, 0), run(True, 64), run(True, 512)
+    for other in (d2, d64, d512):
+        np.testing.assert_array_equal(d1[2], other[2])
+        np.testing.assert_array_equal(d1[0], other[0])
+    f = run(False, 0)
+    (ua, va), (ub, vb) = fields
+    fl = oracle.grid_flow(ua, va, ub, vb, scheme=scheme, time_mode=oracle.PINGPONG)
+    ox, oy, oU = oracle.adjoint(fl, x0, y0, a, b, nsteps, dt)
+    assert np.max(np.abs(d1[2] - oU)) < 1e-10 * _scale(oU)
+    assert np.max(np.abs(d1[2] - f[2])) < 1e-12 * _scale(oU)
+    np.testing.assert_array_equal(d1[0], f[0])
+    assert np.max(np.abs(d1[0] - ox)) < 1e-9 * _scale(ox)

@@ -59,6 +59,50 @@ def test_persistent_launches_match_normal_launches(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
+@pytest.mark.parametrize("tile", [0, -1])
+@pytest.mark.parametrize("fused", [1, 0])
+def test_capped_persistent_walks_match_normal_launches(precision, tile, fused):
+    """Persistent launches capped at 8 and 13 workgroups (max_workgroups), so
+    that every workgroup walks many logical blocks: the LDS tile is refilled
+    per block, the statistics partials are written per block in the loop,
+    and the fused launch's block-order table and the per-species XCD ranges
+    are walked with strides; with the tile on and off (the tile-off walk has
+    no barrier between blocks other than the statistics'), statistics every
+    2 steps and re-sorts every 5.  Everything is bit-identical to one
+    workgroup per block."""
+    say(f"capped persistent {precision} tile={tile} fused={fused}")
+    outs = []
+    for persistent, cap in ((0, 0), (1, 8), (1, 13)):
+        tr, sids = _mixed(precision, sort_interval=5, tile_records=tile)
+        tr.set_tuning(persistent=persistent, max_workgroups=cap, fused=fused)
+        tr.step(17, 0.002, stats_every=2)
+        outs.append(_snap(tr, sids))
+        tr.close()
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
+def test_fused_launch_matches_per_species_launches(precision):
+    """One fused step launch over every species (block-order table, every
+    (scheme, kind) body in one kernel) against one launch per species (or,
+    for FP64, one launch in species order): the same bits for positions,
+    velocities and statistics, with re-sorts and graph chunks."""
+    say(f"fused {precision}")
+    outs = []
+    for fused, chunk in ((0, 0), (1, 0), (1, 5)):
+        tr, sids = _mixed(precision, sort_interval=5)
+        tr.set_tuning(fused=fused, graph_chunk=chunk)
+        tr.step(20, 0.002, stats_every=5)
+        outs.append(_snap(tr, sids))
+        tr.close()
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
 def test_graph_chunks_replay_exactly_like_eager_steps(precision):
     """Chunks of 6 steps captured once and replayed several times, with eager
     readouts and synchronisations in between, against eager stepping in
@@ -83,23 +127,25 @@ def test_tuning_is_validated_and_changes_nothing_on_error():
     before = tr.get_tuning()
     for bad in (dict(block_size=96), dict(tile_records=3), dict(sort_interval=-1),
                 dict(persistent=2), dict(graph_chunk=-5), dict(tile_records=100000),
-                dict(halo_scale=-1.0), dict(halo_scale=9.0)):
+                dict(halo_scale=-1.0), dict(halo_scale=9.0), dict(max_workgroups=-1),
+                dict(fused=2)):
         with pytest.raises(lpt.LptError) as e:
             tr.set_tuning(**bad)
         assert e.value.status == lpt.E_ARG
         assert tr.get_tuning() == before
     tr.set_tuning(block_size=512, tile_records=2400, sort_interval=7, persistent=1,
-                  graph_chunk=10, halo_scale=0.5)
+                  graph_chunk=10, halo_scale=0.5, max_workgroups=40, fused=0)
     assert tr.get_tuning() == dict(block_size=512, tile_records=2400, sort_interval=7,
-                                   persistent=1, graph_chunk=10, halo_scale=0.5)
+                                   persistent=1, graph_chunk=10, halo_scale=0.5,
+                                   max_workgroups=40, fused=0)
     tr.set_tuning(halo_scale=0.0)   # 0 selects the default
     assert tr.get_tuning()["halo_scale"] == 0.125
     tr.close()
 
 
 def test_block_size_change_mid_run_keeps_results():
-    """Per-particle state is bit-identical across block sizes; statistics sum
-    per block, so they agree to rounding."""
+    """Per-particle state and statistics are bit-identical across block
+    sizes (the statistics partials are per wave, merged in wave order)."""
     say("block size change")
     outs = []
     for blocks in ((256, 256), (128, 512)):
@@ -111,10 +157,7 @@ def test_block_size_change_mid_run_keeps_results():
         outs.append(_snap(tr, sids))
         tr.close()
     for a, b in zip(*outs):
-        if a.size == 6:   # statistics: the block-level reduction tree follows the block size
-            np.testing.assert_allclose(a, b, rtol=1e-14)
-        else:
-            np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(a, b)
 
 
 def test_batched_species_match_one_context_per_species():

@@ -10,7 +10,7 @@ field's maximum: hipFFT at most 4.9e-16 (n = 8), 1.1e-15 (n = 64),
 1.5e-15 (n = 96), 5.2e-15 (n = 512), 1.5e-15 (n = 2048), 2.2e-15
 (n = 4096); the library's own transforms at most
 3.9e-15 (n = 512), 3.2e-15 (n = 1024), 9.4e-16 (n = 2048).  The bound is
-1e-13."""
+1e-13; at n = 4096 both paths are compared after 2 steps."""
 import numpy as np
 import pytest
 
@@ -36,21 +36,22 @@ def _compare(gpu_fields, ora_fields, rel=REL, what=""):
 
 
 @pytest.mark.parametrize("n,length,transforms", [
-    (8, 2 * np.pi, "auto"), (64, 2 * np.pi, "auto"), (96, 3.0, "auto"), (512, 2 * np.pi, "builtin"),
-    (1024, 3.0, "auto"), (512, 2 * np.pi, "hipfft")])
+    (64, 2 * np.pi, "auto"), (128, 3.0, "auto"), (256, 2 * np.pi, "builtin"),
+    (512, 2 * np.pi, "builtin"), (1024, 3.0, "auto"),
+    (8, 2 * np.pi, "hipfft"), (96, 3.0, "hipfft"), (512, 2 * np.pi, "hipfft")])
 def test_matches_oracle_step_by_step(n, length, transforms):
     """Step 0 (band truncation), step 1 (forward Euler), step 2 (first AB2
-    step) and step 30: hipFFT on the smallest grid (n = 8, band |m| <= 2), on
-    a small power-of-two grid and on n = 96
-    (divisible by 3: the edge of the 2/3 rule; radix-3 transforms) with
-    L != 2 pi; the library's own transforms at n = 512 and 1024 (L != 2 pi);
-    hipFFT at 512 on request."""
+    step) and step 30: the library's own transforms (the default) at every
+    radix pattern below 2048 -- 64 (8 8), 128 (8 8 2), 256 (8 8 4), 512
+    (8 8 8), 1024 (8 8 8 2) -- with L != 2 pi on some; hipFFT, on request,
+    on the smallest grid (n = 8, band |m| <= 2), on n = 96 (divisible by 3:
+    the edge of the 2/3 rule; radix-3 transforms; L != 2 pi) and at 512."""
     say(f"n={n} L={length} transforms={transforms}")
     # nu k_max^2 dt <= 0.2 at every size: the explicit viscous term stays stable
     nu, dt = 2e-4, 2e-3
     w0 = synth.random_vorticity(n, min(n / 10, 40.0), 21, omega_rms=5.0)
     g = ns2d.Ns2d(n, nu, dt, length=length, transforms=transforms)
-    assert g.builtin == (transforms != "hipfft" and n in (512, 1024, 2048))
+    assert g.builtin == (transforms != "hipfft")
     o = NS2D(n, nu, dt, length=length)
     g.set_vorticity(w0)
     o.set_vorticity(w0)
@@ -64,14 +65,16 @@ def test_matches_oracle_step_by_step(n, length, transforms):
     g.close()
 
 
-def test_largest_grid_matches_oracle():
-    """4096^2, the largest grid here (hipFFT; 1.5 GB of fields), 2 steps,
-    every grid value compared."""
+@pytest.mark.parametrize("transforms", ["auto", "hipfft"])
+def test_largest_grid_matches_oracle(transforms):
+    """4096^2, the largest grid here (the particle headline's grid; 1.5 GB of
+    fields), 2 steps, every grid value compared: the library's own transforms
+    (radix 8 8 8 8, 512 threads a transform, the default) and hipFFT."""
     n = 4096
-    say(f"n={n}")
+    say(f"n={n} transforms={transforms}")
     w0 = synth.random_vorticity(n, 20.0, 26, omega_rms=3.0)
-    g = ns2d.Ns2d(n, 2e-5, 5e-4)
-    assert not g.builtin
+    g = ns2d.Ns2d(n, 2e-5, 5e-4, transforms=transforms)
+    assert g.builtin == (transforms == "auto")
     o = NS2D(n, 2e-5, 5e-4)
     g.set_vorticity(w0)
     o.set_vorticity(w0)
@@ -105,14 +108,14 @@ def test_full_size_matches_oracle(transforms):
 def test_taylor_green_vortex_decay_on_the_gpu(n, nu):
     """psi = sin x sin y decays as exp(-2 nu t) in every field (no advection
     for a Laplacian eigenfunction); AB2 error below 1e-8 at nu dt <= 5e-5;
-    hipFFT at n = 64, the library's own transforms at 512.  nu keeps
+    the library's own transforms at n = 64 and 512.  nu keeps
     nu k_max^2 dt below 1 (0.29 at n = 512): the explicit viscous term would
     otherwise amplify the transforms' rounding in the highest modes."""
     dt, steps = 1e-3, 200
     x = np.arange(n) * (2 * np.pi / n)
     X, Y = x[None, :], x[:, None]
     g = ns2d.Ns2d(n, nu, dt)
-    assert g.builtin == (n == 512)
+    assert g.builtin
     g.set_vorticity(2 * np.sin(X) * np.sin(Y))
     g.step(steps)
     u, v, w, psi = g.get_fields()
@@ -161,11 +164,11 @@ def test_device_vorticity_input_and_velocity_pointers():
 
 
 def test_errors():
-    g = ns2d.Ns2d(32, 1e-3, 1e-3)
+    g = ns2d.Ns2d(64, 1e-3, 1e-3)
     with pytest.raises(ns2d.Ns2dError) as e:
         g.step(1)
     assert e.value.status == ns2d.E_STATE
-    g.set_vorticity(np.zeros((32, 32)))
+    g.set_vorticity(np.zeros((64, 64)))
     with pytest.raises(ns2d.Ns2dError) as e:
         g.step(-1)
     assert e.value.status == ns2d.E_ARG
@@ -180,8 +183,8 @@ def test_coupled_loop_matches_the_oracles(n, length):
     """The producer's velocity streamed into the particle library each step
     (ping-pong slots, device pointers, same stream), tracers and inertial
     particles, against the field oracle feeding the particle oracle the same
-    levels: positions within 1e-10 after 10 steps (hipFFT at n = 128, the
-    library's own transforms at 512; a domain of side 3 as well as 2 pi)."""
+    levels: positions within 1e-10 after 10 steps (the library's own
+    transforms at n = 128 and 512; a domain of side 3 as well as 2 pi)."""
     nu, dt, nsteps = 1e-3, 2e-3, 10
     L = length
     say(f"coupled loop n={n} L={L}")
