@@ -281,11 +281,13 @@ typedef struct {
                                workgroups (below the resident capacity), so
                                that each walks several logical blocks; 0:
                                the resident capacity                          */
-    int32_t fused;          /* 1 (default): with several species, one step
-                               launch covers them all, each XCD taking the
-                               same share of every species in cell order;
-                               0: one launch per species (LPT_FP32_SPLIT) or
-                               one launch in species order (LPT_FP64)         */
+    int32_t fused;          /* with several species, 1 (default) or 2: one
+                               step launch covers them all, each XCD taking
+                               the same share of every species, species
+                               after species (1) or interleaved along the
+                               cell order (2); 0: one launch per species
+                               (LPT_FP32_SPLIT) or one launch in species
+                               order (LPT_FP64)                               */
 } lpt_tuning;
 
 lpt_status lpt_get_tuning(lpt_ctx *ctx, lpt_tuning *out);

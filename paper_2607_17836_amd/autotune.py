@@ -22,7 +22,7 @@ SPACE = {
     "persistent": (0, 1),
     "graph_chunk": (0, 100),
     "halo_scale": (0.125, 0.25, 0.5, 1.0),
-    "fused": (1, 0),
+    "fused": (1, 0, 2),
 }
 
 

@@ -77,11 +77,13 @@ struct StepParams {
 
 // Block-order table of a fused launch over species whose logical blocks are
 // [begin[s], end[s]): XCD x receives the slice [B x / 8, B (x + 1) / 8) of
-// every species' B blocks, and its list holds those slices merged by the
+// every species' B blocks, so every XCD carries the same share of each
+// species.  Its list holds those slices species after species (a CU then
+// runs one species' code at a time), or, with `interleave`, merged by the
 // position of each block along its species' cell order, so that the blocks
 // an XCD runs together cover one region of the grid for every species.
 // Returns order_len; `out` receives 8 * order_len entries.
-int32_t build_block_order(int nspecies, const int32_t *begin, const int32_t *end,
+int32_t build_block_order(int nspecies, const int32_t *begin, const int32_t *end, bool interleave,
                           int32_t *out /* may be null: length only */);
 
 // Device-resident clock so that captured step chunks can be replayed.

@@ -21,7 +21,7 @@
 using namespace lpt;
 
 int32_t lpt::build_block_order(int nspecies, const int32_t *begin, const int32_t *end,
-                               int32_t *out)
+                               bool interleave, int32_t *out)
 {
     constexpr int X = 8;
     std::vector<std::pair<double, int32_t>> lists[X];
@@ -32,9 +32,11 @@ int32_t lpt::build_block_order(int nspecies, const int32_t *begin, const int32_t
             for (int64_t k = B * x / X; k < B * (x + 1) / X; ++k)
                 lists[x].emplace_back(((double)k + 0.5) / (double)B, begin[s] + (int32_t)k);
         }
-        // by position along the cell order; ties keep the species order
-        std::stable_sort(lists[x].begin(), lists[x].end(),
-                         [](const auto &a, const auto &b) { return a.first < b.first; });
+        // interleaved: by position along the cell order (ties keep the species
+        // order); else species after species
+        if (interleave)
+            std::stable_sort(lists[x].begin(), lists[x].end(),
+                             [](const auto &a, const auto &b) { return a.first < b.first; });
         len = std::max(len, lists[x].size());
     }
     if (out)
@@ -97,7 +99,8 @@ struct lpt_ctx {
     int32_t persistent = 0;  // persistent step launches
     float halo_scale = kHaloScaleDefault; // LDS tile halo relative to the largest-speed bound
     int32_t graph_chunk = 0; // steps per captured hipGraph (0: eager launches)
-    int32_t fused = 1;       // one launch over every species (block-order table)
+    int32_t fused = 1;       // one launch over every species (block-order table):
+                             // 1 species-major per XCD, 2 interleaved in cell order
     int32_t max_wg = 0;      // cap on persistent workgroups (0: residency only)
     int32_t *order = nullptr;   // device block-order table of fused launches
     size_t order_cap = 0;       // entries allocated
@@ -323,9 +326,10 @@ lpt_status ensure_order(lpt_ctx *c)
         begin[s] = P.sp[s].block_begin;
         end[s] = P.sp[s].block_end;
     }
-    const int32_t len = build_block_order(P.nspecies, begin, end, nullptr);
+    const bool il = c->fused == 2;
+    const int32_t len = build_block_order(P.nspecies, begin, end, il, nullptr);
     std::vector<int32_t> h((size_t)8 * len);
-    build_block_order(P.nspecies, begin, end, h.data());
+    build_block_order(P.nspecies, begin, end, il, h.data());
     if (h.size() > c->order_cap) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         dfree(c->order);
@@ -1808,7 +1812,7 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
     const float halo = t->halo_scale == 0.0f ? kHaloScaleDefault : t->halo_scale;
     if (!(halo > 0.0f && halo <= 4.0f)) return fail(c, LPT_E_ARG, "halo_scale must be in (0, 4]");
     if (t->max_workgroups < 0) return fail(c, LPT_E_ARG, "max_workgroups must be >= 0");
-    if (t->fused != 0 && t->fused != 1) return fail(c, LPT_E_ARG, "fused is 0 or 1");
+    if (t->fused < 0 || t->fused > 2) return fail(c, LPT_E_ARG, "fused is 0, 1 or 2");
     HIP_TRY(c, hipSetDevice(c->device));
     const bool block_changed = block != c->block;
     if (block_changed) {

@@ -60,7 +60,7 @@ def test_persistent_launches_match_normal_launches(precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
 @pytest.mark.parametrize("tile", [0, -1])
-@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("fused", [1, 2, 0])
 def test_capped_persistent_walks_match_normal_launches(precision, tile, fused):
     """Persistent launches capped at 8 and 13 workgroups (max_workgroups), so
     that every workgroup walks many logical blocks: the LDS tile is refilled
@@ -85,13 +85,14 @@ def test_capped_persistent_walks_match_normal_launches(precision, tile, fused):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
 def test_fused_launch_matches_per_species_launches(precision):
-    """One fused step launch over every species (block-order table, every
-    (scheme, kind) body in one kernel) against one launch per species (or,
-    for FP64, one launch in species order): the same bits for positions,
-    velocities and statistics, with re-sorts and graph chunks."""
+    """One fused step launch over every species (block-order table, species
+    after species or interleaved in cell order; every (scheme, kind) body in
+    one kernel) against one launch per species (or, for FP64, one launch in
+    species order): the same bits for positions, velocities and statistics,
+    with re-sorts and graph chunks."""
     say(f"fused {precision}")
     outs = []
-    for fused, chunk in ((0, 0), (1, 0), (1, 5)):
+    for fused, chunk in ((0, 0), (1, 0), (2, 0), (1, 5), (2, 5)):
         tr, sids = _mixed(precision, sort_interval=5)
         tr.set_tuning(fused=fused, graph_chunk=chunk)
         tr.step(20, 0.002, stats_every=5)
@@ -128,7 +129,7 @@ def test_tuning_is_validated_and_changes_nothing_on_error():
     for bad in (dict(block_size=96), dict(tile_records=3), dict(sort_interval=-1),
                 dict(persistent=2), dict(graph_chunk=-5), dict(tile_records=100000),
                 dict(halo_scale=-1.0), dict(halo_scale=9.0), dict(max_workgroups=-1),
-                dict(fused=2)):
+                dict(fused=3)):
         with pytest.raises(lpt.LptError) as e:
             tr.set_tuning(**bad)
         assert e.value.status == lpt.E_ARG

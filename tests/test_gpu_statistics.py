@@ -89,7 +89,7 @@ def test_statistics_do_not_depend_on_block_size_or_launch_shape():
     n, dt = 128, 0.002
     (ua, va), (ub, vb) = synth.spectrum_snapshots(n, 8, 12, dt)
     outs = []
-    for block, persistent, fused in ((256, 0, 1), (64, 0, 1), (512, 1, 0), (128, 1, 1)):
+    for block, persistent, fused in ((256, 0, 1), (64, 0, 1), (512, 1, 0), (128, 1, 2)):
         tr = lpt.Tracker(n, "fp32_split", sort_interval=4, block_size=block)
         tr.set_tuning(persistent=persistent, fused=fused, max_workgroups=16 * persistent)
         tr.set_time_mode("pingpong")
