@@ -363,6 +363,19 @@ lpt_status lpt_interp(lpt_ctx *ctx, lpt_scheme scheme, int64_t npts, const doubl
 lpt_status lpt_radix_sort(lpt_ctx *ctx, int64_t npts, int32_t key_bits,
                           const uint32_t *keys_in, uint32_t *keys_out, uint32_t *perm);
 
+/* lpt_radix_sort for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same stable sort and the same results, through a fixed scratch array
+ * that the library holds on every GPU it runs on (16.3 MiB, for the life
+ * of the process), so the call allocates nothing and does not synchronise.
+ * npts <= LPT_STATIC_SORT_MAX, else LPT_E_ARG.  All pointers are device
+ * memory; the results are in keys_out / perm once the context's stream has
+ * reached the call.  Every call on one GPU uses the same scratch: calls that
+ * overlap on one GPU (other streams, other threads, other contexts) race. */
+#define LPT_STATIC_SORT_MAX 1048576
+lpt_status lpt_radix_sort_static(lpt_ctx *ctx, int64_t npts, int32_t key_bits,
+                                 const uint32_t *keys_in, uint32_t *keys_out, uint32_t *perm);
+
 /* Achievable device-memory bandwidth: a plain copy of `bytes` (rounded down
  * to a multiple of 16) between two device buffers, and a STREAM triad
  * a = b + s*c over three such buffers, each repeated `iters` times on the

@@ -219,6 +219,8 @@ struct SortWork {
 };
 int64_t sort_hist_entries(int64_t n);
 int64_t sort_scan_blocks(int64_t n);
+// p[0 .. n) = v (a kernel, so that it can sit in a captured graph)
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 
 // keys[0] = (species << tile_bits) | tile index of the stored cell, plus the
 // histogram of the first radix digit (of a key_bits-bit sort) in W.hist.

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <cmath>
 #include <cstdio>
@@ -112,6 +113,7 @@ struct lpt_ctx {
     uint64_t epoch = 0;      // bumped whenever a buffer a graph may hold changes
     hipStream_t own_stream = nullptr;   // capture stream when the context uses the null stream
     bool compat_edge = false;
+    uint32_t *static_sort = nullptr;   // this device's fixed sort scratch
     bool det_grad = false;       // grid gradients in exact fixed point
     unsigned long long *det_acc = nullptr;   // fixed-point pairs of the grid gradient
     int64_t det_acc_words = 0;
@@ -416,6 +418,43 @@ bool is_finite(double v) { return std::isfinite(v); }
 
 }  // namespace
 
+// ---- allocation-free radix sort: a fixed scratch array per GPU -------------
+// Room for the sort of up to kStaticSortMax keys: two key and two value
+// buffers, the per-tile digit histograms and the per-digit totals (16.3 MiB).
+// Each GPU that loads the library holds its own copy for the life of the
+// process; every lpt_radix_sort_static call on that GPU shares it.
+namespace {
+constexpr int64_t kStaticSortMax = LPT_STATIC_SORT_MAX;
+constexpr int64_t kStaticSortHist = 256 * ((kStaticSortMax + 4095) / 4096);
+constexpr int64_t kStaticSortWords = 4 * kStaticSortMax + kStaticSortHist + 256;
+}  // namespace
+
+static __device__ __align__(256) uint32_t scratch[kStaticSortWords];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, uint32_t *> g_scratch;   // device -> address of that device's scratch
+
+// Device address of the scratch on the current device (device `dev`), looked
+// up once per device.  The array's host-side name is only a handle for the
+// lookup: kernels and copies take the returned address.
+hipError_t bind_scratch(int dev, uint32_t **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = static_cast<uint32_t *>(p);
+    *out = static_cast<uint32_t *>(p);
+    return hipSuccess;
+}
+}  // namespace
+
 extern "C" {
 
 const char *lpt_status_string(lpt_status s)
@@ -486,6 +525,8 @@ lpt_status lpt_create(const lpt_config *cfg, lpt_ctx **out)
         return LPT_E_HIP;
     };
     hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) return bail(e);
+    e = bind_scratch(c->device, &c->static_sort);
     if (e != hipSuccess) return bail(e);
     const size_t np2 = (size_t)padded_pitch(n) * (size_t)padded_pitch(n);
     const size_t rec_bytes = np2 * (c->precision == LPT_FP64 ? sizeof(Rec64) : sizeof(float4));
@@ -1586,6 +1627,49 @@ lpt_status lpt_radix_sort(lpt_ctx *c, int64_t npts, int32_t key_bits, const uint
     release();
     if (e != hipSuccess) s = fail(c, LPT_E_HIP, std::string("radix sort: ") + hipGetErrorString(e));
     return s;
+}
+
+lpt_status lpt_radix_sort_static(lpt_ctx *c, int64_t npts, int32_t key_bits,
+                                 const uint32_t *keys_in, uint32_t *keys_out, uint32_t *perm)
+{
+    if (!c) return LPT_E_ARG;
+    if (npts < 0) return fail(c, LPT_E_ARG, "bad npts");
+    if (npts > kStaticSortMax)
+        return fail(c, LPT_E_ARG,
+                    "npts exceeds the fixed scratch of lpt_radix_sort_static (at most " +
+                        std::to_string((long long)kStaticSortMax) + " keys)");
+    if (key_bits < 1 || key_bits > 32) return fail(c, LPT_E_ARG, "key_bits must be in [1, 32]");
+    if (npts > 0 && !keys_in) return fail(c, LPT_E_ARG, "keys_in must not be NULL");
+    if (npts == 0) return LPT_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (!c->static_sort) return fail(c, LPT_E_STATE, "no fixed scratch on this device");
+    uint32_t *base = c->static_sort;
+    if (npts == 1) {   // a single key is its own sorted order
+        if (keys_out)
+            HIP_TRY(c, hipMemcpyAsync(keys_out, keys_in, sizeof(uint32_t),
+                                      hipMemcpyDeviceToDevice, c->stream));
+        if (perm) HIP_TRY(c, launch_fill_u32(perm, 1, 0u, c->stream));
+        return LPT_OK;
+    }
+    SortWork w{};
+    w.keys[0] = base;
+    w.keys[1] = base + kStaticSortMax;
+    w.vals[0] = base + 2 * kStaticSortMax;
+    w.vals[1] = base + 3 * kStaticSortMax;
+    w.hist = base + 4 * kStaticSortMax;
+    w.scan_tmp = w.hist + kStaticSortHist;
+    w.capacity = kStaticSortMax;
+    HIP_TRY(c, hipMemcpyAsync(w.keys[0], keys_in, (size_t)npts * 4, hipMemcpyDeviceToDevice,
+                              c->stream));
+    int res = 0;
+    HIP_TRY(c, radix_sort(w, npts, key_bits, false, false, &res, c->stream));
+    if (keys_out)
+        HIP_TRY(c, hipMemcpyAsync(keys_out, w.keys[res], (size_t)npts * 4,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    if (perm)
+        HIP_TRY(c, hipMemcpyAsync(perm, w.vals[res], (size_t)npts * 4, hipMemcpyDeviceToDevice,
+                                  c->stream));
+    return LPT_OK;
 }
 
 // ---- checkpoint / resume ---------------------------------------------------

@@ -451,6 +451,20 @@ hipError_t radix_sort(SortWork &W, int64_t n, int key_bits, bool first_hist, boo
                : radix_sort_t<uint32_t>(W, n, key_bits, first_hist, result, st);
 }
 
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + b - 1) / b)), dim3(b), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
 __global__ void order_kernel(const uint32_t *__restrict__ id, int64_t offset, int64_t count,
                              int32_t *out)
 {

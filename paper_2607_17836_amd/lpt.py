@@ -86,6 +86,7 @@ _SIGS = [
     ("lpt_interp", C.c_int, [_P, C.c_int, C.c_int64, _P, _P, C.c_double, C.c_double, _P, _P,
                              C.c_int32]),
     ("lpt_radix_sort", C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, _P]),
+    ("lpt_radix_sort_static", C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, _P]),
     ("lpt_get_state", C.c_int, [_P, _P, C.c_size_t, C.POINTER(C.c_size_t)]),
     ("lpt_set_state", C.c_int, [_P, _P, C.c_size_t]),
     ("lpt_get_tuning", C.c_int, [_P, C.POINTER(LptTuning)]),
@@ -385,6 +386,21 @@ class Tracker:
         self._check(load().lpt_radix_sort(self._h, keys.numel(), key_bits, keys.data_ptr(),
                                           out.data_ptr(), perm.data_ptr()))
         return out, perm
+
+    def radix_sort_static(self, keys, key_bits, out=None, perm=None):
+        """radix_sort through the library's fixed scratch (no allocation in
+        the library; at most STATIC_SORT_MAX keys).  out / perm: caller
+        device tensors (allocated here if None)."""
+        assert _is_dev(keys) and keys.dtype == torch.int32 and keys.is_contiguous()
+        out = torch.empty_like(keys) if out is None else out
+        perm = torch.empty_like(keys) if perm is None else perm
+        self._check(load().lpt_radix_sort_static(self._h, keys.numel(), key_bits,
+                                                 keys.data_ptr(), out.data_ptr(),
+                                                 perm.data_ptr()))
+        return out, perm
+
+
+STATIC_SORT_MAX = 1 << 20
 
 
 def create_error_status(n, **kw):
