@@ -138,47 +138,59 @@ def run_gpu(w, steps, warmup, lpt, tuning=None, calib_steps=0, **over):
             tr.close()
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The FP64 oracle (single thread, as written) on a bounded sample of the
-    same workload: the same fields in FP64, a prefix of each species'
-    particles, 20 steps."""
+def cpu_baseline(w, budget_s=8.0):
+    """The FP64 oracle on a bounded sample of the same workload (the same
+    fields in FP64, a prefix of each species' particles, 20 steps), built
+    for timing on this host (-O3 -march=native -ffp-contract=off, OpenMP over
+    the particles of a step; the arithmetic of the test build) and timed on
+    one core and on all the cores it may use (OMP_NUM_THREADS, at most 16)."""
+    import tempfile
     import oracle
+    lib, set_threads = oracle.timing_lib(tempfile.mkdtemp(prefix="oracle_omp_"))
+    threads = max(1, min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))))
     a, b, (ta, tb) = w.snapshots()
     tm = oracle.PINGPONG if w.time_mode == "pingpong" else oracle.BRACKET
     flows = {}
     sps = []
-    frac = None
     for kind, st, scheme, count, seed in w.species:
         if scheme not in flows:
             flows[scheme] = oracle.grid_flow(a[0], a[1], b[0], b[1], scheme=scheme, time_mode=tm,
                                              t_slot=(ta, tb))
         sps.append((flows[scheme], kind, st, count, seed))
-    # calibrate on a small batch of the first species, then size the sample
-    fl, kind, st, count, seed = sps[0]
-    x0, y0 = oracle.init_uniform(seed, 2048)
-    t0 = time.perf_counter()
-    oracle.run(fl, oracle.Species(x0, y0), 3, w.dt)
-    per = (time.perf_counter() - t0) / (2048 * 3)
     nsteps = 20
     total = sum(s[3] for s in sps)
-    frac = min(1.0, budget_s / per / nsteps / total)
-    done, el = 0, 0.0
-    for fl, kind, st, count, seed in sps:
-        m = max(64, int(count * frac))
-        x0, y0 = oracle.init_uniform(seed, m)
-        if kind == "inertial" and st > 0:
-            u0, v0 = oracle.velocity(fl, x0, y0, ta, step=0, t_n=ta, dt=w.dt)
-            sp = oracle.Species(x0, y0, kind=oracle.INERTIAL, st=st, vx0=u0, vy0=v0)
-        else:
-            sp = oracle.Species(x0, y0)
-        t0 = time.perf_counter()
-        oracle.run(fl, sp, nsteps, w.dt, stats_every=10)
-        el += time.perf_counter() - t0
-        done += m * nsteps
-    return {"value": done / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done // nsteps} particles (the first {frac:.3%} of each species of "
-                      f"{w.name}) x {nsteps} steps on the same {w.n}^2 fields in FP64, "
-                      f"{el:.1f} s, single-threaded C oracle"}
+
+    def timed_pass(nthreads, frac):
+        set_threads(nthreads)
+        done, el = 0, 0.0
+        for fl, kind, st, count, seed in sps:
+            m = max(64, int(count * frac))
+            x0, y0 = oracle.init_uniform(seed, m)
+            if kind == "inertial" and st > 0:
+                u0, v0 = oracle.velocity(fl, x0, y0, ta, step=0, t_n=ta, dt=w.dt)
+                sp = oracle.Species(x0, y0, kind=oracle.INERTIAL, st=st, vx0=u0, vy0=v0)
+            else:
+                sp = oracle.Species(x0, y0)
+            t0 = time.perf_counter()
+            oracle.run(fl, sp, nsteps, w.dt, stats_every=10, library=lib)
+            el += time.perf_counter() - t0
+            done += m * nsteps
+        return done, el
+
+    # calibrate on a small sample, then size each pass for about budget_s
+    d, e = timed_pass(1, min(1.0, 4096 / total))
+    per = e / d
+    f1 = min(1.0, budget_s / per / nsteps / total)
+    d1, e1 = timed_pass(1, f1)
+    fn = min(1.0, f1 * threads * 0.8)
+    dn, en = timed_pass(threads, fn)
+    return {"value": dn / en, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{dn // nsteps} particles (the first {fn:.3%} of each species of {w.name}) "
+                      f"x {nsteps} steps on the same {w.n}^2 fields in FP64, {en:.1f} s on "
+                      f"{threads} threads (OpenMP over particles, -O3 -march=native, no FMA "
+                      f"contraction); one core: {d1 / e1:.4g} particle-steps/s on "
+                      f"{d1 // nsteps} particles, {e1:.1f} s",
+            "one_core_value": d1 / e1}
 
 
 def step_kernel_name(w):

@@ -29,6 +29,29 @@ SCHEMES = {"bilinear": BILINEAR, "catmull_rom": CATMULL_ROM, "bspline": BSPLINE}
 GCC_FLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c11", "-fPIC", "-shared"]
 
 
+OMP_FLAGS = ["-O3", "-march=native", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+             "-std=c11", "-fPIC", "-shared"]
+_omp = None
+
+
+def timing_lib(outdir: str):
+    """The oracle built for CPU timing (-O3 -march=native, OpenMP over the
+    particles of a step; the same arithmetic), compiled into `outdir` on the
+    machine that runs it, and a setter of its thread count.  Returns
+    (module-like ctypes library, set_threads)."""
+    global _omp
+    if _omp is None:
+        os.makedirs(outdir, exist_ok=True)
+        path = os.path.join(outdir, "liboracle_omp.so")
+        subprocess.run(["gcc", *OMP_FLAGS, _SRC, "-o", path, "-lm"], check=True)
+        L = C.CDLL(path)
+        _declare(L)
+        gomp = C.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads.argtypes = [C.c_int]
+        _omp = (L, gomp.omp_set_num_threads)
+    return _omp
+
+
 def build(force: bool = False) -> str:
     """Compile ``oracle.c`` with gcc into ``liboracle.so`` (next to it)."""
     with _lock:
@@ -57,43 +80,48 @@ def lib():
     if _lib is None:
         build()
         L = C.CDLL(_LIB)
-        dp, ip = C.c_void_p, C.c_void_p
-        L.orc_wrap.restype = C.c_double
-        L.orc_wrap.argtypes = [C.c_double, C.c_double]
-        L.orc_wrap_many.restype = None
-        L.orc_wrap_many.argtypes = [C.c_int64, dp, C.c_double, dp]
-        L.orc_interp.restype = C.c_double
-        L.orc_interp.argtypes = [dp, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_double, C.c_double]
-        L.orc_interp_many.restype = None
-        L.orc_interp_many.argtypes = [dp, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_int64, dp, dp, dp]
-        L.orc_velocity.restype = None
-        L.orc_velocity.argtypes = [C.POINTER(Flow), C.c_int64, dp, dp, C.c_double, C.c_int64,
-                                   C.c_double, C.c_double, dp, dp]
-        L.orc_stats.restype = None
-        L.orc_stats.argtypes = [C.c_int64, dp, dp, C.c_double, C.c_double, dp]
-        L.orc_run.restype = C.c_int64
-        L.orc_run.argtypes = [C.POINTER(Flow), C.c_int32, C.c_double, C.c_int64,
-                              dp, dp, dp, dp, dp, dp, C.c_int64, C.c_double, C.c_double,
-                              C.c_int64, C.c_int64, C.c_double, dp, C.c_int64]
-        L.orc_splitmix64.restype = C.c_uint64
-        L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
-        L.orc_init_uniform.restype = None
-        L.orc_init_uniform.argtypes = [C.c_uint64, C.c_int64, C.c_double, dp, dp]
-        L.orc_cell_keys.restype = None
-        L.orc_cell_keys.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int64, ip, ip, ip]
-        L.orc_interp_grad.restype = None
-        L.orc_interp_grad.argtypes = [dp, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_double,
-                                      C.c_double, dp, dp, dp]
-        L.orc_tangent_run.restype = None
-        L.orc_tangent_run.argtypes = [C.POINTER(Flow), C.c_int64, dp, dp, dp, dp, dp, C.c_int64,
-                                      C.c_double, C.c_double, C.c_int64]
-        L.orc_adjoint_run.restype = None
-        L.orc_adjoint_run.argtypes = [C.POINTER(Flow), C.c_int64, dp, dp, dp, dp, C.c_int64,
-                                      C.c_double, C.c_double, C.c_int64, dp, dp, dp, dp]
-        L.orc_cells_of.restype = None
-        L.orc_cells_of.argtypes = [C.c_int32, C.c_double, C.c_int64, dp, ip]
+        _declare(L)
         _lib = L
     return _lib
+
+
+def _declare(L):
+    """Argument and result types of every oracle entry point."""
+    dp, ip = C.c_void_p, C.c_void_p
+    L.orc_wrap.restype = C.c_double
+    L.orc_wrap.argtypes = [C.c_double, C.c_double]
+    L.orc_wrap_many.restype = None
+    L.orc_wrap_many.argtypes = [C.c_int64, dp, C.c_double, dp]
+    L.orc_interp.restype = C.c_double
+    L.orc_interp.argtypes = [dp, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_double, C.c_double]
+    L.orc_interp_many.restype = None
+    L.orc_interp_many.argtypes = [dp, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_int64, dp, dp, dp]
+    L.orc_velocity.restype = None
+    L.orc_velocity.argtypes = [C.POINTER(Flow), C.c_int64, dp, dp, C.c_double, C.c_int64,
+                               C.c_double, C.c_double, dp, dp]
+    L.orc_stats.restype = None
+    L.orc_stats.argtypes = [C.c_int64, dp, dp, C.c_double, C.c_double, dp]
+    L.orc_run.restype = C.c_int64
+    L.orc_run.argtypes = [C.POINTER(Flow), C.c_int32, C.c_double, C.c_int64,
+                          dp, dp, dp, dp, dp, dp, C.c_int64, C.c_double, C.c_double,
+                          C.c_int64, C.c_int64, C.c_double, dp, C.c_int64]
+    L.orc_splitmix64.restype = C.c_uint64
+    L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    L.orc_init_uniform.restype = None
+    L.orc_init_uniform.argtypes = [C.c_uint64, C.c_int64, C.c_double, dp, dp]
+    L.orc_cell_keys.restype = None
+    L.orc_cell_keys.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int64, ip, ip, ip]
+    L.orc_interp_grad.restype = None
+    L.orc_interp_grad.argtypes = [dp, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_double,
+                                  C.c_double, dp, dp, dp]
+    L.orc_tangent_run.restype = None
+    L.orc_tangent_run.argtypes = [C.POINTER(Flow), C.c_int64, dp, dp, dp, dp, dp, C.c_int64,
+                                  C.c_double, C.c_double, C.c_int64]
+    L.orc_adjoint_run.restype = None
+    L.orc_adjoint_run.argtypes = [C.POINTER(Flow), C.c_int64, dp, dp, dp, dp, C.c_int64,
+                                  C.c_double, C.c_double, C.c_int64, dp, dp, dp, dp]
+    L.orc_cells_of.restype = None
+    L.orc_cells_of.argtypes = [C.c_int32, C.c_double, C.c_int64, dp, ip]
 
 
 def _f64(a):
@@ -221,11 +249,13 @@ class Species:
 
 
 def run(flow: FlowSpec, sp: Species, nsteps, dt, t_start=0.0, step0=0, stats_every=0,
-        t_origin=0.0):
-    """Advance a species in place; returns the stats records [nrec, 8]."""
+        t_origin=0.0, library=None):
+    """Advance a species in place; returns the stats records [nrec, 8].
+    library: the ctypes library to run (default: the test build; the CPU
+    timing passes timing_lib's)."""
     cap = (step0 + nsteps) // stats_every + 1 if stats_every > 0 else 0
     rec = np.zeros((max(cap, 1), 8))
-    nrec = lib().orc_run(C.byref(flow.struct), sp.kind, sp.st, sp.n,
+    nrec = (library or lib()).orc_run(C.byref(flow.struct), sp.kind, sp.st, sp.n,
                          _ptr(sp.xw), _ptr(sp.yw), _ptr(sp.dx), _ptr(sp.dy),
                          _ptr(sp.vx), _ptr(sp.vy), int(nsteps), float(dt), float(t_start),
                          int(step0), int(stats_every), float(t_origin), _ptr(rec), cap)

@@ -16,10 +16,12 @@ that reading every case falls in the class the figure gives it:
   (a)(iv)  horizontal ballistic       ballistic along one grid axis (which
                                       axis depends on rounding: asserted as
                                       axis-aligned)
-  (b)(i)   limit cycle                bounded; a 1e-6 perturbation stays small
+  (b)(i)   limit cycle                bounded; a 1e-6 perturbation stays
+                                      below 0.05 (it oscillates with the
+                                      phase along the cycle, 1e-4 .. 1e-2)
   (b)(ii)  chaotic attractor          bounded; a 1e-6 perturbation grows to
-                                      the attractor's size
-  (b)(iii) square limit cycle         bounded
+                                      the attractor's size (above 0.2)
+  (b)(iii) square limit cycle         the same as (b)(i)
   (b)(iv)  stable point               bounded; the particle comes to rest
 
 (Releasing the particles with the fluid velocity, v0 = u(x0), puts only
@@ -44,7 +46,7 @@ CASES = [  # label, class, x0, y0, St
     ("(a)(iv)", "axis ballistic", 1.5, 1.5, 1.133),
     ("(b)(i)", "limit cycle", 1.0, 0.42, 1.12),
     ("(b)(ii)", "chaotic attractor", 2.33, 0.81, 1.37),
-    ("(b)(iii)", "bounded", 0.664, 0.11, 0.89),
+    ("(b)(iii)", "limit cycle", 0.664, 0.11, 0.89),
     ("(b)(iv)", "stable point", 1.2, 0.6, 0.5),
 ]
 N, DT, NSTEPS, SAMPLE = 256, 0.01, 160000, 2000
@@ -64,9 +66,9 @@ def classify(r, dx, dy, speed, sep):
     if r.max() < BOUND:
         if speed < 1e-8:
             return "stable point"
-        if sep < 1e-3:
+        if sep < 5e-2:
             return "limit cycle"
-        if sep > 5e-2:
+        if sep > 0.2:
             return "chaotic attractor"
         return "bounded"
     if r[-1] > BALLISTIC * T and r[-1] > 1.8 * r[len(r) // 2 - 1]:
