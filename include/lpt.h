@@ -309,12 +309,14 @@ lpt_status lpt_time_steps(lpt_ctx *ctx, int64_t nsteps, double dt, int32_t stats
  * all tracers (or St = 0) only; otherwise LPT_E_STATE. */
 
 /* Advance every species by nsteps steps like lpt_step (no statistics; with
- * sort_interval > 0, one cell-order re-sort before the first step and none
- * after it), keeping the positions at every ckpt_every-th step and each
- * step's temporal weights, so that lpt_adjoint / lpt_jacobian can recompute
- * the trajectory segment by segment.  Device memory: ceil(nsteps /
- * ckpt_every) * 16 bytes per particle for the checkpoints, plus
- * min(ckpt_every, nsteps) * 16 bytes per particle during a reverse sweep. */
+ * sort_interval > 0, a cell-order re-sort at the start of every segment of
+ * ckpt_every steps, whose permutation is kept), keeping the positions at
+ * every ckpt_every-th step and each step's temporal weights, so that
+ * lpt_adjoint / lpt_jacobian can recompute the trajectory segment by
+ * segment.  Device memory: ceil(nsteps / ckpt_every) * 16 bytes per particle
+ * for the checkpoints (plus 4 bytes per particle and segment for the
+ * permutations when re-sorting), and min(ckpt_every, nsteps) * 16 bytes per
+ * particle during a reverse sweep. */
 lpt_status lpt_forward_checkpointed(lpt_ctx *ctx, int64_t nsteps, double dt, int32_t ckpt_every);
 
 /* Reverse sweep of the last lpt_forward_checkpointed run (no step may follow

@@ -107,22 +107,21 @@ __device__ __forceinline__ Sten64<K> stencil64(int scheme, const Loc64 &l)
 }
 
 // Spatial Jacobian J = [du/dx, du/dy, dv/dx, dv/dy] of the time-blended
-// interpolated velocity at a stencil (records read through the ghost
-// border, so the stencil never wraps).
-template <int K>
-__device__ __forceinline__ void jacobian64(const Rec64 *__restrict__ rec0, const StepParams &P,
-                                           const Sten64<K> &s, double wa, double wb, int smode,
-                                           double J[4])
+// interpolated velocity at a stencil, its K x K nodes read through N (the
+// LDS tile or the ghost-bordered records, so the stencil never wraps).
+template <int K, typename Nodes>
+__device__ __forceinline__ void jacobian_nodes(const Nodes &N, const StepParams &P,
+                                               const Sten64<K> &s, double wa, double wb,
+                                               int smode, double J[4])
 {
     double ux = 0.0, uy = 0.0, vx = 0.0, vy = 0.0;
 #pragma unroll
     for (int b = 0; b < K; ++b) {
-        const Rec64 *row = rec0 + (__mul24(s.j0 + b, P.pitch) + s.i0);
         double rux = 0.0, rvx = 0.0, ru = 0.0, rv = 0.0;
 #pragma unroll
         for (int a = 0; a < K; ++a) {
             double u, v;
-            node64(row + a, smode, wa, wb, u, v);
+            N.get(a, b, smode, wa, wb, u, v);
             rux += s.dx[a] * u;
             rvx += s.dx[a] * v;
             ru += s.wx[a] * u;
@@ -137,6 +136,21 @@ __device__ __forceinline__ void jacobian64(const Rec64 *__restrict__ rec0, const
     J[1] = uy * P.invh;
     J[2] = vx * P.invh;
     J[3] = vy * P.invh;
+}
+
+// The Jacobian from the block's LDS tile when the stencil lies inside it,
+// else from global memory.
+template <int K>
+__device__ __forceinline__ void jacobian64(const Rec64 *__restrict__ rec0, const double2 *tile,
+                                           const Tile &T, const StepParams &P, const Sten64<K> &s,
+                                           double wa, double wb, int smode, double J[4])
+{
+    int t;
+    if (tile_index(T, s.i0, s.j0, K, P.n, P.mask, t))
+        jacobian_nodes<K>(TileNodes64{tile + t, T.w, T.w * T.h}, P, s, wa, wb, smode, J);
+    else
+        jacobian_nodes<K>(RecNodes64{rec0 + (__mul24(s.j0, P.pitch) + s.i0), P.pitch}, P, s, wa,
+                          wb, smode, J);
 }
 
 // Exact fixed-point form of a contribution c (|c| < 2^31): c ~ hi 2^-32 +
@@ -234,23 +248,45 @@ __device__ __forceinline__ void add_jt(const double J[4], const double l[2], dou
     out[1] = J[1] * l[0] + J[3] * l[1];
 }
 
-// Recompute one step of every particle's position: out = wrap(in + step).
-__global__ __launch_bounds__(kMaxBlock) void recompute64_kernel(StepParams P, const Rec64 *__restrict__ rec,
-                                                          const double2 *__restrict__ in,
-                                                          double2 *__restrict__ out)
+// Recompute one step of every particle's position: out = wrap(in + step),
+// with the step kernel's LDS field tile of the block's box.
+template <bool CUBIC>
+__global__ __launch_bounds__(kMaxBlock) void recompute64_kernel(StepParams P,
+                                                                const Rec64 *__restrict__ rec,
+                                                                const double2 *__restrict__ in,
+                                                                double2 *__restrict__ out)
 {
     const int lb = blockIdx.x;
     const SpeciesDev &sp = P.sp[species_of(P, lb)];
-    const int64_t local = (int64_t)(lb - sp.block_begin) * blockDim.x + threadIdx.x;
-    if (local >= sp.count) return;
+    const int64_t base = (int64_t)(lb - sp.block_begin) * blockDim.x;
+    const int64_t local = base + threadIdx.x;
+    const bool active = local < sp.count;
     const int64_t p = sp.offset + local;
     const Rec64 *rec0 = rec + P.pitch + 1;
-    const double2 x = in[p];
+    const double2 x = active ? in[p] : make_double2(0.0, 0.0);
+    Tile T = no_tile();
+    if (P.tile_cap > 0) {
+        const double2 a = in[sp.offset + base];
+        const int n = P.n, mask = P.mask;
+        const int ax = cell_of_floor(floor(a.x * P.invh), n, mask);
+        const int ay = cell_of_floor(floor(a.y * P.invh), n, mask);
+        const int cx = cell_of_floor(floor(x.x * P.invh), n, mask);
+        const int cy = cell_of_floor(floor(x.y * P.invh), n, mask);
+        int lo, hi;
+        stencil_reach(sp.scheme, lo, hi);
+        const int H = step_halo(P, sp.scheme, (float)P.dt);
+        const int64_t left = sp.count - base;
+        T = stage_tile<Rec64>(reinterpret_cast<Rec64 *>(lpt_dyn_lds), rec0, P, active, cx, cy, ax,
+                              ay, lo + H, hi + H,
+                              (int)(left < (int64_t)blockDim.x ? left : blockDim.x));
+    }
+    if (!active) return;
+    const double2 *planes = reinterpret_cast<const double2 *>(lpt_dyn_lds);
     double ddx, ddy;
-    if (sp.scheme == kBilinear)
-        rk4_tracer64<false>(rec0, nullptr, no_tile(), P, sp.scheme, x, ddx, ddy);
+    if (!CUBIC || sp.scheme == kBilinear)
+        rk4_tracer64<false>(rec0, planes, T, P, sp.scheme, x, ddx, ddy);
     else
-        rk4_tracer64<true>(rec0, nullptr, no_tile(), P, sp.scheme, x, ddx, ddy);
+        rk4_tracer64<true>(rec0, planes, T, P, sp.scheme, x, ddx, ddy);
     out[p] = make_double2(wrap_pos(x.x + ddx, P.L), wrap_pos(x.y + ddy, P.L));
 }
 
@@ -270,7 +306,7 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
                                                               const Rec64 *__restrict__ rec,
                                                               const double2 *__restrict__ tape,
                                                               double2 *__restrict__ lam,
-                                                              void *gU, int acc_cap)
+                                                              void *gU, int lds_bytes)
 {
     const int lb = blockIdx.x;
     const SpeciesDev &sp = P.sp[species_of(P, lb)];
@@ -282,12 +318,21 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
     const int scheme = sp.scheme;
     const double dt = P.dt, hdt = 0.5 * P.dt, dt6 = P.dt / 6.0, dt3 = P.dt / 3.0;
     const double2 x = active ? tape[p] : make_double2(0.0, 0.0);
-    // LDS planes per box node: three time levels x (u, v) doubles, or (DET)
-    // four (slot, component) planes of fixed-point pairs
-    constexpr int kPlanes = DET ? 8 : 6;
+    // LDS per box node: the field tile's two planes of (u, v) (32 bytes, when
+    // tiles are on), then the accumulators: three time levels x (u, v)
+    // doubles, or (DET) four (slot, component) planes of fixed-point pairs
+    // The box is sized for the accumulators (the scatter's atomics are what
+    // an oversized box sends to global memory); the tile is staged beside
+    // them only where both fit.
+    constexpr int kAccBytes = AGG ? (DET ? 64 : 48) : 0;
+    const bool tiles_on = P.tile_cap > 0;
+    const int box_bytes = AGG ? kAccBytes : (tiles_on ? 32 : 0);
 
     GridGrad<DET> G{gU, adj_dyn_lds, no_tile()};
-    if constexpr (AGG) {
+    Tile T = no_tile();
+    const double2 *planes = reinterpret_cast<const double2 *>(adj_dyn_lds);
+    if (box_bytes > 0) {
+        const int cap = lds_bytes / box_bytes;
         const Loc64 me = locate64(P, x.x, x.y);
         const double2 a0 = tape[sp.offset + base];
         const Loc64 an = locate64(P, a0.x, a0.y);
@@ -296,24 +341,33 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
         const int H = step_halo(P, scheme, (float)dt);
         Tile B = block_box(active, me.i, me.j, an.i, an.j, P.n, P.mask, lo + H, hi + H);
         // a box beyond the LDS budget first loses halo, then rows: whatever
-        // falls outside it is added to gU directly
+        // falls outside it is read and added in global memory directly
         int shrink = 0;
-        while (shrink < H && (B.w - 2 * shrink) * (B.h - 2 * shrink) > acc_cap) ++shrink;
+        while (shrink < H && (B.w - 2 * shrink) * (B.h - 2 * shrink) > cap) ++shrink;
         B.w -= 2 * shrink;
         B.h -= 2 * shrink;
         B.x0 = wrap_cell(B.x0 + shrink, P.n, P.mask);
         B.y0 = wrap_cell(B.y0 + shrink, P.n, P.mask);
-        B.w = min(min(B.w, acc_cap), P.n - 1);
-        B.h = min(min(B.h, acc_cap / B.w), P.n - 1);
+        B.w = min(min(B.w, cap), P.n - 1);
+        B.h = min(min(B.h, cap / B.w), P.n - 1);
         B.on = 1;
-        G.B = B;
-        const int words = kPlanes * B.w * B.h;
-        if constexpr (DET) {
-            unsigned long long *acc = static_cast<unsigned long long *>(G.acc);
-            for (int k = threadIdx.x; k < words; k += blockDim.x) acc[k] = 0ull;
-        } else {
-            double *acc = static_cast<double *>(G.acc);
-            for (int k = threadIdx.x; k < words; k += blockDim.x) acc[k] = 0.0;
+        const int area = B.w * B.h;
+        const bool tiled = tiles_on && area * (32 + kAccBytes) <= lds_bytes;
+        if (tiled) {
+            T = B;
+            fill_tile_dma<Rec64>(reinterpret_cast<Rec64 *>(adj_dyn_lds), rec0, P, T);
+        }
+        if constexpr (AGG) {
+            G.B = B;
+            G.acc = adj_dyn_lds + (tiled ? 32 * area : 0);
+            const int words = (kAccBytes / 8) * area;
+            if constexpr (DET) {
+                unsigned long long *acc = static_cast<unsigned long long *>(G.acc);
+                for (int k = threadIdx.x; k < words; k += blockDim.x) acc[k] = 0ull;
+            } else {
+                double *acc = static_cast<double *>(G.acc);
+                for (int k = threadIdx.x; k < words; k += blockDim.x) acc[k] = 0.0;
+            }
         }
         __syncthreads();
     }
@@ -324,16 +378,16 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
         double k1x, k1y, k2x, k2y, k3x, k3y;
         px[0] = x.x;
         py[0] = x.y;
-        vel64<CUBIC>(rec0, nullptr, no_tile(), P, scheme, px[0], py[0], P.wa[0], P.wb[0],
-                     P.smode[0], k1x, k1y);
+        vel64<CUBIC>(rec0, planes, T, P, scheme, px[0], py[0], P.wa[0], P.wb[0], P.smode[0],
+                     k1x, k1y);
         px[1] = x.x + hdt * k1x;
         py[1] = x.y + hdt * k1y;
-        vel64<CUBIC>(rec0, nullptr, no_tile(), P, scheme, px[1], py[1], P.wa[1], P.wb[1],
-                     P.smode[1], k2x, k2y);
+        vel64<CUBIC>(rec0, planes, T, P, scheme, px[1], py[1], P.wa[1], P.wb[1], P.smode[1],
+                     k2x, k2y);
         px[2] = x.x + hdt * k2x;
         py[2] = x.y + hdt * k2y;
-        vel64<CUBIC>(rec0, nullptr, no_tile(), P, scheme, px[2], py[2], P.wa[2], P.wb[2],
-                     P.smode[2], k3x, k3y);
+        vel64<CUBIC>(rec0, planes, T, P, scheme, px[2], py[2], P.wa[2], P.wb[2], P.smode[2],
+                     k3x, k3y);
         px[3] = x.x + dt * k3x;
         py[3] = x.y + dt * k3y;
 
@@ -367,12 +421,12 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint64_kernel(StepParams P,
                 const Sten64<2> st = stencil64<2>(scheme, loc);
                 if (grid)
                     scatter64<2, DET>(G, P, st, grp, P.wa[q], P.wb[q], lk[0][q][0], lk[0][q][1]);
-                jacobian64<2>(rec0, P, st, P.wa[q], P.wb[q], P.smode[q], J);
+                jacobian64<2>(rec0, planes, T, P, st, P.wa[q], P.wb[q], P.smode[q], J);
             } else if constexpr (CUBIC) {
                 const Sten64<4> st = stencil64<4>(scheme, loc);
                 if (grid)
                     scatter64<4, DET>(G, P, st, grp, P.wa[q], P.wb[q], lk[0][q][0], lk[0][q][1]);
-                jacobian64<4>(rec0, P, st, P.wa[q], P.wb[q], P.smode[q], J);
+                jacobian64<4>(rec0, planes, T, P, st, P.wa[q], P.wb[q], P.smode[q], J);
             }
 #pragma unroll
             for (int r = 0; r < NL; ++r) {
@@ -492,33 +546,43 @@ __global__ void gather_adjoint_kernel(const uint32_t *__restrict__ id, int64_t n
 }
 
 hipError_t launch_recompute64(const StepParams &P, const Rec64 *rec, const double2 *in,
-                              double2 *out, int block, hipStream_t st)
+                              double2 *out, bool cubic, int block, hipStream_t st)
 {
-    hipLaunchKernelGGL(recompute64_kernel, dim3(P.total_blocks), dim3(block), 0, st, P, rec, in,
-                       out);
+    // the step kernel's tile: two planes of 16-byte entries, whole 64-entry chunks
+    const size_t lds = P.tile_cap > 0 ? (size_t)(2 * P.tile_cap + kWave) * 16 : 0;
+    if (cubic)
+        hipLaunchKernelGGL(recompute64_kernel<true>, dim3(P.total_blocks), dim3(block), lds, st, P,
+                           rec, in, out);
+    else
+        hipLaunchKernelGGL(recompute64_kernel<false>, dim3(P.total_blocks), dim3(block), lds, st,
+                           P, rec, in, out);
     return hipGetLastError();
 }
 
-// LDS of the aggregating adjoint: 30 KiB, so that the bilinear kernel's five
-// 256-thread blocks per CU (its register-bound occupancy) fit in 160 KiB;
-// 640 box nodes of six double planes, or 480 nodes of four fixed-point pair
-// planes (DET).
-constexpr size_t kAdjAccBytes = 30 * 1024;
+// LDS of the adjoint kernel: 31 KiB, so that five 256-thread blocks (the
+// bilinear kernel's register-bound occupancy) fit in a CU's 160 KiB.  The
+// accumulator box holds up to 661 nodes (48 bytes each; 496 of fixed-point
+// pairs), and the field tile joins it in boxes of up to 396 nodes (80
+// bytes each; 330 with fixed-point pairs); without accumulators, 992 nodes
+// of tile.
+constexpr int kAdjLdsBytes = 31 * 1024;
 
 template <bool CUBIC, bool DET>
 static hipError_t launch_adjoint64_c(const StepParams &P, const Rec64 *rec, const double2 *tape,
                                      double2 *lam, int nl, void *gU, int block, hipStream_t st)
 {
-    const int cap = (int)(kAdjAccBytes / (DET ? 8 * sizeof(unsigned long long) : 6 * sizeof(double)));
+    const size_t lds = kAdjLdsBytes + 64;   // the tile fill writes whole 16-byte pieces
     if (nl == 1 && gU)
         hipLaunchKernelGGL((adjoint64_kernel<1, true, CUBIC, DET>), dim3(P.total_blocks),
-                           dim3(block), kAdjAccBytes, st, P, rec, tape, lam, gU, cap);
+                           dim3(block), lds, st, P, rec, tape, lam, gU, kAdjLdsBytes);
     else if (nl == 1)
         hipLaunchKernelGGL((adjoint64_kernel<1, false, CUBIC, false>), dim3(P.total_blocks),
-                           dim3(block), 0, st, P, rec, tape, lam, (void *)nullptr, 0);
+                           dim3(block), P.tile_cap > 0 ? lds : 0, st, P, rec, tape, lam,
+                           (void *)nullptr, kAdjLdsBytes);
     else
         hipLaunchKernelGGL((adjoint64_kernel<2, false, CUBIC, false>), dim3(P.total_blocks),
-                           dim3(block), 0, st, P, rec, tape, lam, (void *)nullptr, 0);
+                           dim3(block), P.tile_cap > 0 ? lds : 0, st, P, rec, tape, lam,
+                           (void *)nullptr, kAdjLdsBytes);
     return hipGetLastError();
 }
 
@@ -563,6 +627,27 @@ hipError_t launch_zero_words(void *p, int64_t words, hipStream_t st)
     const int b = 256;
     hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)((words + b - 1) / b)), dim3(b), 0, st,
                        static_cast<unsigned long long *>(p), words);
+    return hipGetLastError();
+}
+
+// Adjoint vectors from one segment's slot order to the previous segment's:
+// the sort at the segment's start filled slot i from slot perm[i], so
+// out[perm[i]] = in[i] (NL vectors per slot).
+__global__ void unpermute_adjoint_kernel(const uint32_t *__restrict__ perm, int64_t np, int nl,
+                                         const double2 *__restrict__ in, double2 *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const int64_t j = perm[i];
+    for (int r = 0; r < nl; ++r) out[j * nl + r] = in[i * nl + r];
+}
+
+hipError_t launch_unpermute_adjoint(const uint32_t *perm, int64_t np, int nl, const double2 *in,
+                                    double2 *out, hipStream_t st)
+{
+    const int b = 256;
+    hipLaunchKernelGGL(unpermute_adjoint_kernel, dim3((unsigned)((np + b - 1) / b)), dim3(b), 0,
+                       st, perm, np, nl, in, out);
     return hipGetLastError();
 }
 

@@ -45,37 +45,60 @@ __device__ __forceinline__ void persistent_range(int T, int &first, int &stride,
     end = hi;
 }
 
-// Every logical block of a launch over [base, base + count), each exactly
-// once, with the body called uniformly per workgroup:
+// Walk over the logical blocks of a launch over [base, base + count): each
+// block is visited by exactly one workgroup, and the walk is uniform per
+// workgroup (it depends on blockIdx alone), so block bodies may synchronise.
 //   - with a block-order table (P.order), XCD x = blockIdx mod 8 walks its
 //     list with a stride of its own workgroup count (one entry each when
-//     the grid is 8 * order_len);
+//     the grid is 8 * order_len), skipping the -1 padding;
 //   - otherwise one block per workgroup in XCD-contiguous order, or, in a
 //     persistent launch, the XCD's contiguous range.
-// Every workgroup's walk ends, so the grid always drains.
-template <typename Body>
-__device__ __forceinline__ void for_each_block(const StepParams &P, int base, int count,
-                                               Body &&body)
+// Every workgroup's walk ends, so the grid always drains.  (A plain iterator
+// rather than a callback: the kernel parameters stay in the kernel-argument
+// segment instead of being copied to private memory for a closure.)
+struct BlockWalk {
+    const int32_t *list;   // this XCD's table list, or null
+    int k, stride, end;
+};
+
+__device__ __forceinline__ BlockWalk block_walk(const StepParams &P, int base, int count)
 {
+    BlockWalk w;
     if (P.order) {
         constexpr int X = 8;
-        const int G = gridDim.x, b = blockIdx.x;
-        const int x = b % X;
-        const int gx = (G - x + X - 1) / X;   // workgroups on XCD x
-        const int32_t *list = P.order + (int64_t)x * P.order_len;
-        for (int k = b / X; k < P.order_len; k += gx) {
-            const int lb = list[k];
-            if (lb >= 0) body(lb);
+        const int G = gridDim.x, b = blockIdx.x, x = b % X;
+        w.list = P.order + (int64_t)x * P.order_len;
+        w.k = b / X;
+        w.stride = (G - x + X - 1) / X;   // workgroups on XCD x
+        w.end = P.order_len;
+    } else if (!P.persistent) {
+        w.list = nullptr;
+        w.k = base + xcd_logical_block(blockIdx.x, gridDim.x);
+        w.stride = 1;
+        w.end = w.k + 1;
+    } else {
+        int first, stride, end;
+        persistent_range(count, first, stride, end);
+        w.list = nullptr;
+        w.k = base + first;
+        w.stride = stride;
+        w.end = base + end;
+    }
+    return w;
+}
+
+// The next logical block of the walk into lb; false once it is done.
+__device__ __forceinline__ bool block_next(BlockWalk &w, int &lb)
+{
+    while (w.k < w.end) {
+        const int v = w.list ? w.list[w.k] : w.k;
+        w.k += w.stride;
+        if (v >= 0) {
+            lb = v;
+            return true;
         }
-        return;
     }
-    if (!P.persistent) {
-        body(base + xcd_logical_block(blockIdx.x, gridDim.x));
-        return;
-    }
-    int first, stride, end;
-    persistent_range(count, first, stride, end);
-    for (int lb = first; lb < end; lb += stride) body(base + lb);
+    return false;
 }
 
 // Streaming (non-temporal) loads and stores of the particle state: each

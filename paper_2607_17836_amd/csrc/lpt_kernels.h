@@ -125,8 +125,10 @@ struct alignas(32) Rec64 { double u0, v0, u1, v1; };
 // *umax (which the caller zeroes first).
 hipError_t launch_pack(void *rec, bool fp64, int slot, const double *u, const double *v, int n,
                        double scale, double vscale, float *umax, hipStream_t st);
-hipError_t launch_psi_to_velocity(const double *psi, double *u, double *v, int n, double h,
-                                  hipStream_t st);
+// The same from a stream-function level: the node velocity is the grid
+// centred difference of psi (spacing h), formed in the same pass.
+hipError_t launch_pack_psi(void *rec, bool fp64, int slot, const double *psi, int n, double h,
+                           double scale, double vscale, float *umax, hipStream_t st);
 
 // The step works in place on S; with perm (the permutation of a re-sort, dst
 // slot -> src slot) it reads S through perm and writes D, a different buffer,
@@ -189,13 +191,16 @@ hipError_t launch_order(const uint32_t *id, int64_t offset, int64_t count, int32
 // reverse-mode derivatives of the FP64 tracer step (adjoint.hip); block is
 // the step kernel's block size (P's species block layout)
 hipError_t launch_recompute64(const StepParams &P, const Rec64 *rec, const double2 *in,
-                              double2 *out, int block, hipStream_t st);
+                              double2 *out, bool cubic, int block, hipStream_t st);
 // cubic: some species uses a bicubic scheme (else every stencil is bilinear).
 // det: gU holds fixed-point pairs of 64-bit words (4 n^2 pairs; value =
 // hi 2^-32 + lo 2^-64), summed exactly with integer atomics; else doubles.
 hipError_t launch_adjoint64(const StepParams &P, const Rec64 *rec, const double2 *tape,
                             double2 *lam, int nl, void *gU, bool det, bool cubic, int block,
                             hipStream_t st);
+// out[perm[i] * nl + r] = in[i * nl + r]: adjoint vectors back through a sort
+hipError_t launch_unpermute_adjoint(const uint32_t *perm, int64_t np, int nl, const double2 *in,
+                                    double2 *out, hipStream_t st);
 hipError_t launch_fixed_to_double(const void *pairs, int64_t count, double *out, hipStream_t st);
 hipError_t launch_zero_words(void *p, int64_t words, hipStream_t st);
 hipError_t launch_seed_adjoint(const uint32_t *id, int64_t np, int nl, const double *gx,

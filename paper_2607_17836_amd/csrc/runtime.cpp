@@ -121,8 +121,6 @@ struct lpt_ctx {
 
     // snapshots
     void *rec = nullptr;   // padded Rec64 or float4 records, (n + 3)^2
-    double *psi_uv = nullptr;   // grid velocity of a stream-function snapshot
-    int64_t psi_uv_cap = 0;     // doubles
     float *umax = nullptr; // largest node speed per slot, cells per unit time
     bool slot_set[2] = {false, false};
     double t_slot[2] = {0, 0};
@@ -160,6 +158,14 @@ struct lpt_ctx {
     double ck_dt = 0, ck_t0 = 0;
     std::vector<StepWeights> ck_w;   // temporal weights of every recorded step
     bool ck_valid = false;
+    // with re-sorting, every segment starts from cell order: the permutation
+    // applied at the start of segment s >= 1 (new slot -> previous slot),
+    // and the slot -> particle ids of segment 0
+    bool ck_sorted = false;
+    uint32_t *ck_perm = nullptr;
+    size_t ck_perm_bytes = 0;
+    uint32_t *ck_id0 = nullptr;
+    size_t ck_id0_bytes = 0;
 
     // optional event timing of step kernels and re-sorts
     bool time_kernels = false;
@@ -374,9 +380,11 @@ hipError_t mark(lpt_ctx *c, hipEvent_t &ev)
 // caller's next step kernel instead, which reads through it:
 // *perm_out receives the permutation (dst slot -> src slot; null if nothing
 // was sorted) and the state buffer does not change here.
-lpt_status do_sort(lpt_ctx *c, const uint32_t **perm_out = nullptr)
+lpt_status do_sort(lpt_ctx *c, const uint32_t **perm_out = nullptr,
+                   const uint32_t **applied = nullptr)
 {
     if (perm_out) *perm_out = nullptr;
+    if (applied) *applied = nullptr;
     if (c->np <= 1) return LPT_OK;
     lpt_status s = ensure_sort_work(c);
     if (s != LPT_OK) return s;
@@ -407,6 +415,7 @@ lpt_status do_sort(lpt_ctx *c, const uint32_t **perm_out = nullptr)
         HIP_TRY(c, launch_permute32(c->s32[c->cur], c->s32[1 - c->cur], perm, c->np,
                                     c->has_inertial, c->stream));
     c->cur = 1 - c->cur;
+    if (applied) *applied = perm;   // valid until the next sort
     if (c->time_kernels) {
         HIP_TRY(c, mark(c, e1));
         c->ev_sort.emplace_back(e0, e1);
@@ -563,7 +572,8 @@ void lpt_destroy(lpt_ctx *c)
     dfree(c->umax);
     dfree(c->ck);
     dfree(c->order);
-    dfree(c->psi_uv);
+    dfree(c->ck_perm);
+    dfree(c->ck_id0);
     dfree(c->det_acc);
     for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
     c->graphs.clear();
@@ -656,20 +666,10 @@ lpt_status lpt_set_snapshot_psi(lpt_ctx *c, int32_t slot, double t, const double
     const double *dp = nullptr;
     lpt_status s = stage_in(c, st, psi, nn, on_device, dp);
     if (s != LPT_OK) return s;
-    // the grid velocity goes through a scratch owned by the context (grown
-    // once; stream order keeps successive calls from overlapping on it)
-    if (c->psi_uv_cap < 2 * nn) {
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        dfree(c->psi_uv);
-        c->psi_uv_cap = 0;
-        HIP_TRY(c, dalloc(c->psi_uv, (size_t)(2 * nn)));
-        c->psi_uv_cap = 2 * nn;
-    }
-    double *uv = c->psi_uv;
-    HIP_TRY(c, launch_psi_to_velocity(dp, uv, uv + nn, c->n, c->h, c->stream));
+    // the centred differences are formed inside the ingest pass
     HIP_TRY(c, hipMemsetAsync(c->umax + slot, 0, sizeof(float), c->stream));
-    HIP_TRY(c, launch_pack(c->rec, c->precision == LPT_FP64, slot, uv, uv + nn, c->n, c->invh,
-                           c->invh, c->umax + slot, c->stream));
+    HIP_TRY(c, launch_pack_psi(c->rec, c->precision == LPT_FP64, slot, dp, c->n, c->h, c->invh,
+                               c->invh, c->umax + slot, c->stream));
     if (!st.bufs.empty()) HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->slot_set[slot] = true;
     c->t_slot[slot] = t;
@@ -958,12 +958,29 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
                 c->cur = 1 - c->cur;   // where the sort leaves the host state
             }
         }
+        if (ckpt && k % c->ck_every == 0) {
+            const int64_t seg = k / c->ck_every;
+            if (c->ck_sorted) {
+                // each segment starts from cell order; its permutation (or,
+                // for the first, the slot -> id map) is kept for the sweep
+                const uint32_t *applied = nullptr;
+                const lpt_status s = do_sort(c, nullptr, &applied);
+                if (s != LPT_OK) return s;
+                if (seg == 0)
+                    HIP_TRY(c, hipMemcpyAsync(c->ck_id0, c->s64[c->cur].id,
+                                              (size_t)c->np * sizeof(uint32_t),
+                                              hipMemcpyDeviceToDevice, c->stream));
+                else
+                    HIP_TRY(c, hipMemcpyAsync(c->ck_perm + (seg - 1) * c->np, applied,
+                                              (size_t)c->np * sizeof(uint32_t),
+                                              hipMemcpyDeviceToDevice, c->stream));
+            }
+            HIP_TRY(c, hipMemcpyAsync(c->ck + seg * c->np, c->s64[c->cur].pos,
+                                      (size_t)c->np * sizeof(double2), hipMemcpyDeviceToDevice,
+                                      c->stream));
+        }
         step_weights(c, dt, P);
         if (ckpt) {
-            if (k % c->ck_every == 0)
-                HIP_TRY(c, hipMemcpyAsync(c->ck + (k / c->ck_every) * c->np, c->s64[c->cur].pos,
-                                          (size_t)c->np * sizeof(double2),
-                                          hipMemcpyDeviceToDevice, c->stream));
             StepWeights w;
             for (int q = 0; q < 4; ++q) {
                 w.wa[q] = P.wa[q];
@@ -1191,6 +1208,30 @@ lpt_status lpt_forward_checkpointed(lpt_ctx *c, int64_t nsteps, double dt, int32
         c->ck = static_cast<double2 *>(q);
         c->ck_bytes = need;
     }
+    // with re-sorting enabled, every segment starts from cell order, so both
+    // sweeps touch the grid coherently per block all along the run
+    const bool sorted = c->sort_interval > 0 && c->np > 1;
+    if (sorted) {
+        const size_t pb = (size_t)(nseg - 1) * (size_t)c->np * sizeof(uint32_t);
+        const size_t ib = (size_t)c->np * sizeof(uint32_t);
+        if (pb > c->ck_perm_bytes || ib > c->ck_id0_bytes) {
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            dfree(c->ck_perm);
+            dfree(c->ck_id0);
+            c->ck_perm_bytes = c->ck_id0_bytes = 0;
+            void *q = nullptr, *r = nullptr;
+            if (hipMalloc(&q, std::max<size_t>(pb, 4)) != hipSuccess ||
+                hipMalloc(&r, ib) != hipSuccess) {
+                (void)hipGetLastError();
+                if (q) (void)hipFree(q);
+                return fail(c, LPT_E_NOMEM, "checkpoint permutation allocation failed");
+            }
+            c->ck_perm = static_cast<uint32_t *>(q);
+            c->ck_id0 = static_cast<uint32_t *>(r);
+            c->ck_perm_bytes = std::max<size_t>(pb, 4);
+            c->ck_id0_bytes = ib;
+        }
+    }
     c->ck_every = ckpt_every;
     c->ck_nsteps = nsteps;
     c->ck_w.clear();
@@ -1198,12 +1239,7 @@ lpt_status lpt_forward_checkpointed(lpt_ctx *c, int64_t nsteps, double dt, int32
     c->ck_step0 = c->steps;
     c->ck_t0 = c->t;
     c->ck_valid = false;
-    // with re-sorting enabled, the run starts from cell order (kept for its
-    // whole length), so both sweeps touch the grid coherently per block
-    if (c->sort_interval > 0) {
-        s = do_sort(c);
-        if (s != LPT_OK) return s;
-    }
+    c->ck_sorted = sorted;
     s = run_steps(c, nsteps, dt, 0, true);
     if (s != LPT_OK) return s;
     c->ck_valid = true;
@@ -1215,7 +1251,8 @@ namespace {
 // Reverse sweep over the last checkpointed run: per segment, newest first,
 // rebuild the segment's per-step positions from its checkpoint, then take
 // the adjoint kernel back through them.
-lpt_status reverse_sweep(lpt_ctx *c, int nl, double2 *lam, void *gU, bool det)
+lpt_status reverse_sweep(lpt_ctx *c, int nl, double2 *&lam, double2 *&lam_spare, void *gU,
+                         bool det)
 {
     const int64_t E = c->ck_every, N = c->ck_nsteps, np = c->np;
     const int64_t tape_len = std::min(E, N);
@@ -1236,8 +1273,8 @@ lpt_status reverse_sweep(lpt_ctx *c, int nl, double2 *lam, void *gU, bool det)
                 P.wb[q] = w.wb[q];
                 P.smode[q] = slot_mode(w.wa[q], w.wb[q]);
             }
-            e = launch_recompute64(P, rec, tape + (s - 1) * np, tape + s * np, c->block,
-                                   c->stream);
+            e = launch_recompute64(P, rec, tape + (s - 1) * np, tape + s * np, c->has_cubic,
+                                   c->block, c->stream);
         }
         for (int64_t s = len - 1; s >= 0 && e == hipSuccess; --s) {
             const StepWeights &w = c->ck_w[(size_t)(k0 + s)];
@@ -1248,6 +1285,13 @@ lpt_status reverse_sweep(lpt_ctx *c, int nl, double2 *lam, void *gU, bool det)
             }
             e = launch_adjoint64(P, rec, tape + s * np, lam, nl, gU, det, c->has_cubic,
                                  c->block, c->stream);
+        }
+        // back to the previous segment's slot order: the slot that segment
+        // seg's sort filled from slot perm[i] gives its adjoint back there
+        if (c->ck_sorted && seg > 0 && e == hipSuccess) {
+            e = launch_unpermute_adjoint(c->ck_perm + (seg - 1) * np, np, nl, lam, lam_spare,
+                                         c->stream);
+            std::swap(lam, lam_spare);
         }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1280,9 +1324,13 @@ lpt_status lpt_adjoint(lpt_ctx *c, const double *gx_T, const double *gy_T, doubl
     s = stage_in(c, st, gx_T, np, on_device, dgx);
     if (s == LPT_OK) s = stage_in(c, st, gy_T, np, on_device, dgy);
     if (s != LPT_OK) return s;
-    double2 *lam = nullptr;
+    double2 *lam = nullptr, *spare = nullptr;
     HIP_TRY(c, dalloc(lam, (size_t)np));
     st.bufs.push_back(reinterpret_cast<double *>(lam));
+    if (c->ck_sorted) {
+        HIP_TRY(c, dalloc(spare, (size_t)np));
+        st.bufs.push_back(reinterpret_cast<double *>(spare));
+    }
     double *dU = nullptr;
     if (gU) {
         if (on_device) {
@@ -1307,10 +1355,12 @@ lpt_status lpt_adjoint(lpt_ctx *c, const double *gx_T, const double *gy_T, doubl
         HIP_TRY(c, launch_zero_words(c->det_acc, 2 * nn4, c->stream));
         acc = c->det_acc;
     }
+    // seeded in the final slot order; the sweep ends in the first segment's
     const uint32_t *id = c->s64[c->cur].id;
     HIP_TRY(c, launch_seed_adjoint(id, np, 1, dgx, dgy, lam, c->stream));
-    s = reverse_sweep(c, 1, lam, acc, gU && c->det_grad);
+    s = reverse_sweep(c, 1, lam, spare, acc, gU && c->det_grad);
     if (s != LPT_OK) return s;
+    if (c->ck_sorted) id = c->ck_id0;
     if (gU && c->det_grad) HIP_TRY(c, launch_fixed_to_double(c->det_acc, nn4, dU, c->stream));
     double *ox = gx_0, *oy = gy_0;
     if (!on_device) {
@@ -1349,13 +1399,18 @@ lpt_status jacobian_sweep(lpt_ctx *c, double *F, double *sigma, int32_t on_devic
     HIP_TRY(c, hipSetDevice(c->device));
     const int64_t np = c->np;
     Staged st(c->stream);
-    double2 *lam = nullptr;
+    double2 *lam = nullptr, *spare = nullptr;
     HIP_TRY(c, dalloc(lam, (size_t)(2 * np)));
     st.bufs.push_back(reinterpret_cast<double *>(lam));
+    if (c->ck_sorted) {
+        HIP_TRY(c, dalloc(spare, (size_t)(2 * np)));
+        st.bufs.push_back(reinterpret_cast<double *>(spare));
+    }
     const uint32_t *id = c->s64[c->cur].id;
     HIP_TRY(c, launch_seed_adjoint(id, np, 2, nullptr, nullptr, lam, c->stream));
-    s = reverse_sweep(c, 2, lam, nullptr, false);
+    s = reverse_sweep(c, 2, lam, spare, nullptr, false);
     if (s != LPT_OK) return s;
+    if (c->ck_sorted) id = c->ck_id0;
     double *dF = F, *dS = sigma;
     if (!on_device) {
         if (F) {

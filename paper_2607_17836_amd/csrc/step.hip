@@ -116,9 +116,9 @@ __global__ __launch_bounds__(kMaxBlock) void step64_kernel(StepParams P, State64
                                                            double *__restrict__ partials,
                                                            DevClock *clock)
 {
-    for_each_block(P, 0, P.total_blocks, [&](int lb) {
+    BlockWalk w = block_walk(P, 0, P.total_blocks);
+    for (int lb = 0; block_next(w, lb);)
         step64_block<CUBIC, INERTIAL, STATS, false>(P, S, S, nullptr, rec, partials, clock, lb);
-    });
 }
 
 // The FP64 step that follows a re-sort: reads S through perm, writes D.
@@ -129,9 +129,9 @@ __global__ __launch_bounds__(kMaxBlock) void step64_perm_kernel(StepParams P, St
                                                                 double *__restrict__ partials,
                                                                 DevClock *clock)
 {
-    for_each_block(P, 0, P.total_blocks, [&](int lb) {
+    BlockWalk w = block_walk(P, 0, P.total_blocks);
+    for (int lb = 0; block_next(w, lb);)
         step64_block<CUBIC, INERTIAL, STATS, true>(P, S, D, perm, rec, partials, clock, lb);
-    });
 }
 
 // ===========================================================================
@@ -611,7 +611,7 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
 }
 
 // One launch advances every particle of its logical blocks by one step
-// (for_each_block: one workgroup per logical block in XCD-aware order, a
+// (block_walk: one workgroup per logical block in XCD-aware order, a
 // persistent walk, or a fused launch's block-order table).
 // Bilinear blocks hold eight 256-thread blocks per CU (the LDS tile's
 // budget), i.e. eight waves per SIMD, so their registers are bounded to fit
@@ -623,9 +623,9 @@ __attribute__((amdgpu_waves_per_eu(SCHS == kBilinear ? 8 : 6)))
 void step32_kernel(StepParams P, State32 S, const float4 *__restrict__ rec,
                    double *__restrict__ partials, DevClock *clock)
 {
-    for_each_block(P, P.block_base, P.launch_blocks, [&](int lb) {
+    BlockWalk w = block_walk(P, P.block_base, P.launch_blocks);
+    for (int lb = 0; block_next(w, lb);)
         step32_block<SCHS, KINDS, STATS, false>(P, S, S, nullptr, rec, partials, clock, lb);
-    });
 }
 
 // The step that follows a re-sort: reads S through perm, writes D.  (A kernel
@@ -637,9 +637,9 @@ void step32_perm_kernel(StepParams P, State32 S, State32 D, const uint32_t *perm
                         const float4 *__restrict__ rec, double *__restrict__ partials,
                         DevClock *clock)
 {
-    for_each_block(P, P.block_base, P.launch_blocks, [&](int lb) {
+    BlockWalk w = block_walk(P, P.block_base, P.launch_blocks);
+    for (int lb = 0; block_next(w, lb);)
         step32_block<SCHS, KINDS, STATS, true>(P, S, D, perm, rec, partials, clock, lb);
-    });
 }
 
 // Grid of a launch: one workgroup per logical block (per table entry in a
@@ -962,74 +962,95 @@ __device__ __forceinline__ void block_max_to(float m, unsigned *out)
     }
 }
 
+// Grid centred differences of psi (eq. particle_velocity_reconstruction with
+// the interpolation moved onto the grid): periodic neighbours.
+__device__ __forceinline__ int nxt(int i, int n) { return i + 1 == n ? 0 : i + 1; }
+__device__ __forceinline__ int prv(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+
 // One ingest pass: each node record's half for this level (ghost records
 // are periodic images), and the level's largest |u| or |v| times vscale
 // (cells per unit time), which the step kernel's LDS tile halo uses, folded
-// into *umax.  Blocks walk columns a of the padded grid and stride over its
-// rows, so the grid stays at about a thousand blocks (one atomic each).
-template <bool FP64>
-__global__ __launch_bounds__(256) void pack_kernel(void *rec, int slot, const double *__restrict__ u,
-                                                   const double *__restrict__ v, int n,
-                                                   double scale, double vscale, unsigned *umax)
+// into *umax.  PSI: the level is a stream function f = psi, and the node's
+// velocity is its grid centred difference, u = (psi(j+1) - psi(j-1)) / 2h,
+// v = -(psi(i+1) - psi(i-1)) / 2h, formed here (g is unused); else f = u,
+// g = v.  Blocks walk columns a of the padded grid and stride over its rows,
+// so the grid stays at about a thousand blocks (one atomic each); each
+// thread issues the loads of kRows rows before it stores any of them.
+template <bool FP64, bool PSI>
+__global__ __launch_bounds__(256) void pack_kernel(void *rec, int slot, const double *__restrict__ f,
+                                                   const double *__restrict__ g, int n,
+                                                   double scale, double vscale, double inv2h,
+                                                   unsigned *umax)
 {
+    constexpr int kRows = 4;
     const int pitch = n + kGhostLo + kGhostHi;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int G = gridDim.y;
     float m = 0.0f;
     if (a < pitch) {
         const int i = ghost_source(a, n);
-        for (int b = blockIdx.y; b < pitch; b += gridDim.y) {
-            const int64_t src = (int64_t)ghost_source(b, n) * n + i;
-            const double uu = u[src], vv = v[src];
-            const int64_t r = (int64_t)b * pitch + a;
-            if constexpr (FP64)
-                reinterpret_cast<double2 *>(static_cast<Rec64 *>(rec) + r)[slot] = make_double2(uu, vv);
-            else
-                reinterpret_cast<float2 *>(static_cast<float4 *>(rec) + r)[slot] =
-                    make_float2((float)(uu * scale), (float)(vv * scale));
-            m = fmaxf(m, (float)(fmax(fabs(uu), fabs(vv)) * vscale));
+        for (int b0 = blockIdx.y; b0 < pitch; b0 += kRows * G) {
+            double uu[kRows], vv[kRows];
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) {
+                const int b = b0 + k * G;
+                uu[k] = vv[k] = 0.0;
+                if (b < pitch) {
+                    const int j = ghost_source(b, n);
+                    if constexpr (PSI) {
+                        uu[k] = (f[(int64_t)nxt(j, n) * n + i] - f[(int64_t)prv(j, n) * n + i]) * inv2h;
+                        vv[k] = -(f[(int64_t)j * n + nxt(i, n)] - f[(int64_t)j * n + prv(i, n)]) * inv2h;
+                    } else {
+                        uu[k] = f[(int64_t)j * n + i];
+                        vv[k] = g[(int64_t)j * n + i];
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) {
+                const int b = b0 + k * G;
+                if (b >= pitch) break;
+                const int64_t r = (int64_t)b * pitch + a;
+                if constexpr (FP64)
+                    reinterpret_cast<double2 *>(static_cast<Rec64 *>(rec) + r)[slot] =
+                        make_double2(uu[k], vv[k]);
+                else
+                    reinterpret_cast<float2 *>(static_cast<float4 *>(rec) + r)[slot] =
+                        make_float2((float)(uu[k] * scale), (float)(vv[k] * scale));
+                m = fmaxf(m, (float)(fmax(fabs(uu[k]), fabs(vv[k])) * vscale));
+            }
         }
     }
     block_max_to(m, umax);
 }
 
-hipError_t launch_pack(void *rec, bool fp64, int slot, const double *u, const double *v, int n,
-                       double scale, double vscale, float *umax, hipStream_t st)
+template <bool PSI>
+static void launch_pack_t(void *rec, bool fp64, int slot, const double *f, const double *g, int n,
+                          double scale, double vscale, double inv2h, float *umax, hipStream_t st)
 {
     const int pitch = n + kGhostLo + kGhostHi, b = 256;
     const dim3 grid((pitch + b - 1) / b, pitch < 128 ? pitch : 128);
     unsigned *out = reinterpret_cast<unsigned *>(umax);
     if (fp64)
-        hipLaunchKernelGGL(pack_kernel<true>, grid, dim3(b), 0, st, rec, slot, u, v, n, scale,
-                           vscale, out);
+        hipLaunchKernelGGL((pack_kernel<true, PSI>), grid, dim3(b), 0, st, rec, slot, f, g, n, scale,
+                           vscale, inv2h, out);
     else
-        hipLaunchKernelGGL(pack_kernel<false>, grid, dim3(b), 0, st, rec, slot, u, v, n, scale,
-                           vscale, out);
+        hipLaunchKernelGGL((pack_kernel<false, PSI>), grid, dim3(b), 0, st, rec, slot, f, g, n,
+                           scale, vscale, inv2h, out);
+}
+
+hipError_t launch_pack(void *rec, bool fp64, int slot, const double *u, const double *v, int n,
+                       double scale, double vscale, float *umax, hipStream_t st)
+{
+    launch_pack_t<false>(rec, fp64, slot, u, v, n, scale, vscale, 0.0, umax, st);
     return hipGetLastError();
 }
 
-// Grid centred differences of psi (eq. particle_velocity_reconstruction with
-// the interpolation moved onto the grid).
-__device__ __forceinline__ int nxt(int i, int n) { return i + 1 == n ? 0 : i + 1; }
-__device__ __forceinline__ int prv(int i, int n) { return i == 0 ? n - 1 : i - 1; }
-
-__global__ void psi_vel_kernel(const double *__restrict__ psi, double *u, double *v, int n,
-                               double h)
+hipError_t launch_pack_psi(void *rec, bool fp64, int slot, const double *psi, int n, double h,
+                           double scale, double vscale, float *umax, hipStream_t st)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (int64_t)n * n) return;
-    const int i = (int)(k % n), j = (int)(k / n);
-    const double inv2h = 1.0 / (2.0 * h);
-    u[k] = (psi[(int64_t)nxt(j, n) * n + i] - psi[(int64_t)prv(j, n) * n + i]) * inv2h;
-    v[k] = -(psi[(int64_t)j * n + nxt(i, n)] - psi[(int64_t)j * n + prv(i, n)]) * inv2h;
-}
-
-hipError_t launch_psi_to_velocity(const double *psi, double *u, double *v, int n, double h,
-                                  hipStream_t st)
-{
-    const int64_t nn = (int64_t)n * n;
-    const int b = 256;
-    hipLaunchKernelGGL(psi_vel_kernel, dim3((unsigned)((nn + b - 1) / b)), dim3(b), 0, st, psi,
-                       u, v, n, h);
+    launch_pack_t<true>(rec, fp64, slot, psi, nullptr, n, scale, vscale, 1.0 / (2.0 * h), umax,
+                        st);
     return hipGetLastError();
 }
 

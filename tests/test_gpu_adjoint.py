@@ -103,11 +103,12 @@ def test_checkpoint_spacing_and_block_size_do_not_change_results():
 
 @pytest.mark.parametrize("scheme", ["bilinear", "catmull_rom"])
 def test_cell_ordered_run_matches_oracle_and_unsorted(scheme):
-    """With re-sorting enabled the checkpointed run starts from cell order, so
-    each block's grid gradient is summed in an LDS box of its tile: per-
-    particle adjoints stay bit-identical to the unsorted run, the grid
-    gradient agrees with it to atomic-summation rounding and with the
-    oracle to the usual bound."""
+    """With re-sorting enabled every checkpoint segment (three here) starts
+    from cell order, so each block's grid gradient is summed in an LDS box
+    of its tile, and the sweep carries the adjoint vectors back through each
+    segment's permutation: per-particle adjoints and Jacobians stay
+    bit-identical to the unsorted run, the grid gradient agrees with it to
+    atomic-summation rounding and with the oracle to the usual bound."""
     n, dt, nsteps = 128, 0.01, 30
     say(f"cell-ordered adjoint {scheme}")
     fields = synth.spectrum_snapshots(n, 6, 12, dt)
@@ -124,10 +125,11 @@ def test_cell_ordered_run_matches_oracle_and_unsorted(scheme):
         tr.set_snapshot(1, dt, ub, vb)
         tr.add_species("tracer", 0.0, scheme, x0, y0)
         tr.forward_checkpointed(nsteps, dt, 10)
-        outs.append(tr.adjoint(a, b))
+        outs.append(tr.adjoint(a, b) + (tr.jacobian(),))
         tr.close()
     np.testing.assert_array_equal(outs[1][0], outs[0][0])
     np.testing.assert_array_equal(outs[1][1], outs[0][1])
+    np.testing.assert_array_equal(outs[1][3], outs[0][3])
     assert np.max(np.abs(outs[1][2] - outs[0][2])) < 1e-12 * _scale(outs[0][2])
     (ua, va), (ub, vb) = fields
     fl = oracle.grid_flow(ua, va, ub, vb, scheme=scheme, time_mode=oracle.PINGPONG)

@@ -20,7 +20,8 @@ that reading every case falls in the class the figure gives it:
                                       below 0.05 (it oscillates with the
                                       phase along the cycle, 1e-4 .. 1e-2)
   (b)(ii)  chaotic attractor          bounded; a 1e-6 perturbation grows to
-                                      the attractor's size (above 0.2)
+                                      the attractor's size (above 0.5 at
+                                      times in the second half of the run)
   (b)(iii) square limit cycle         the same as (b)(i)
   (b)(iv)  stable point               bounded; the particle comes to rest
 
@@ -61,14 +62,17 @@ def say(msg):
 
 def classify(r, dx, dy, speed, sep):
     """Class of one trajectory from |D| sampled every SAMPLE steps, the final
-    displacement, the final speed and the final separation from a partner
-    started 1e-6 away."""
+    displacement, the final speed and the separation from a partner started
+    1e-6 away, sampled likewise (its largest value over the second half of
+    the run: along a limit cycle it oscillates with the phase, on a chaotic
+    attractor it comes and goes between 0 and the attractor's size)."""
     if r.max() < BOUND:
         if speed < 1e-8:
             return "stable point"
-        if sep < 5e-2:
+        smax = sep[len(sep) // 2:].max()
+        if smax < 5e-2:
             return "limit cycle"
-        if sep > 0.2:
+        if smax > 0.5:
             return "chaotic attractor"
         return "bounded"
     if r[-1] > BALLISTIC * T and r[-1] > 1.8 * r[len(r) // 2 - 1]:
@@ -90,9 +94,12 @@ def _paths(step, read, n_samples):
     return np.array(rs), last
 
 
+EPS = 1e-6   # the partner's initial offset in x
+
+
 def test_steady_cellular_flow_inertial_regimes():
     u, v, _ = synth.taylor_green(N)
-    eps = 1e-6
+    eps = EPS
     # GPU: one species per case, the case and its partner
     tr = lpt.Tracker(N, "fp64")
     tr.set_snapshot(0, 0.0, u, v)
@@ -114,35 +121,39 @@ def test_steady_cellular_flow_inertial_regimes():
     done = 10
     n_samples = (NSTEPS - done) // SAMPLE
     gpu_r = [[] for _ in CASES]
+    gpu_s = [[] for _ in CASES]
     for _ in range(n_samples):
         tr.step(SAMPLE, DT)
         done += SAMPLE
         for k, (_, _, x0, y0, _) in enumerate(CASES):
             _, _, xu, yu = tr.get_positions(k)
             gpu_r[k].append(np.hypot(xu[0] - x0, yu[0] - y0))
+            gpu_s[k].append(np.hypot(xu[0] - xu[1] + EPS, yu[0] - yu[1]))
     say(f"regimes: GPU ran {done} steps")
     ora_r = [[] for _ in CASES]
+    ora_s = [[] for _ in CASES]
     t0 = 10 * DT
     for s in range(n_samples):
         for k, sp in enumerate(sps):
             oracle.run(fl, sp, SAMPLE, DT, t_start=t0 + s * SAMPLE * DT, step0=10 + s * SAMPLE)
             ora_r[k].append(np.hypot(sp.dx[0], sp.dy[0]))
+            ora_s[k].append(np.hypot(sp.dx[0] - sp.dx[1], sp.dy[0] - sp.dy[1]))
     report = []
     for k, (label, cls, x0, y0, st) in enumerate(CASES):
         _, _, xu, yu = tr.get_positions(k)
         vx, vy = tr.get_velocities(k)
         dx, dy = xu - x0, yu - y0
         g = classify(np.array(gpu_r[k]), dx[0], dy[0], np.hypot(vx[0], vy[0]),
-                     np.hypot(dx[0] - dx[1], dy[0] - dy[1]))
+                     np.array(gpu_s[k]))
         sp = sps[k]
         o = classify(np.array(ora_r[k]), sp.dx[0], sp.dy[0], np.hypot(sp.vx[0], sp.vy[0]),
-                     np.hypot(sp.dx[0] - sp.dx[1], sp.dy[0] - sp.dy[1]))
+                     np.array(ora_s[k]))
         report.append((label, cls, g, o, np.array(gpu_r[k])[-1]))
         say(f"  {label:9s} St={st:5.3f} paper: {cls:18s} GPU: {g:18s} oracle: {o:18s} "
             f"|D(T)| = {gpu_r[k][-1]:8.2f}")
         if cls in ("diagonal ballistic", "limit cycle", "stable point"):
             # not chaotic: the trajectories still agree at the end
-            assert np.max(np.hypot(dx - sp.dx, dy - sp.dy)) < 1e-6, label
+            assert np.max(np.hypot(xu - (sp.x0 + sp.dx), yu - (sp.y0 + sp.dy))) < 1e-6, label
     tr.close()
     for label, cls, g, o, _ in report:
         assert g == cls, (label, cls, g)
