@@ -138,6 +138,27 @@ def run_gpu(w, steps, warmup, lpt, tuning=None, calib_steps=0, **over):
             tr.close()
 
 
+def run_gpu_graphs(w, steps, warmup, lpt, tuning, chunk):
+    """Whole-job timing with hipGraph replays of `chunk`-step chunks (no
+    per-kernel events): `warmup` steps (which capture the graphs), then
+    `steps` steps between HIP events on the context stream.  Returns
+    (elapsed device s, elapsed wall s)."""
+    import torch
+    from paper_2607_17836_amd import workloads
+    tr = workloads.build_tracker(w, lpt)
+    try:
+        tr.set_tuning(**dict(tuning or {}, graph_chunk=chunk))
+        tr.step(warmup, w.dt, w.stats_every)
+        tr.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dev_ms = tr.time_steps(steps, w.dt, w.stats_every)
+        wall = time.perf_counter() - t0
+        return 1e-3 * dev_ms, wall
+    finally:
+        tr.close()
+
+
 def cpu_baseline(w, budget_s=8.0):
     """The FP64 oracle on a bounded sample of the same workload (the same
     fields in FP64, a prefix of each species' particles, 20 steps), built
@@ -204,7 +225,7 @@ def step_kernel_name(w):
     return f"{name}<{' / '.join(schemes)}, {kind}>"
 
 
-def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False):
+def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False, graph_chunk=0):
     over = {}
     if args.tile_records:
         over["tile_records"] = args.tile_records
@@ -214,6 +235,18 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False):
     calib_steps = max(w.stats_every, w.sort_interval)
     elapsed, timing, nstats, calib = run_gpu(w, args.steps, args.warmup, lpt, tuning,
                                              calib_steps=calib_steps, **over)
+    graph = None
+    if graph_chunk:
+        # the workload as specified: graph replays of graph_chunk steps; the
+        # eager run above (per-kernel events) gives the kernel averages
+        gdev, gwall = run_gpu_graphs(w, args.steps, args.warmup, lpt, tuning, graph_chunk)
+        graph = {"chunk": graph_chunk, "device_ms_per_step": 1e3 * gdev / args.steps,
+                 "wall_ms_per_step": 1e3 * gwall / args.steps,
+                 "eager_wall_ms_per_step": 1e3 * elapsed / args.steps}
+        log(f"[bench] graph replays of {graph_chunk} steps: {graph['wall_ms_per_step']:.4f} ms per "
+            f"step wall, {graph['device_ms_per_step']:.4f} ms by events (eager: "
+            f"{graph['eager_wall_ms_per_step']:.4f} ms)")
+        elapsed = gwall
     value = npart * args.steps / elapsed
 
     def avg(t, ms, n):
@@ -294,6 +327,10 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False):
             "alg_bytes_per_particle_step": bytes_per_launch / npart,
             "alg_bytes_per_launch": bytes_per_launch,
             "layout_bytes_per_particle_step": alg_bytes_per_step(w, layout=True) / npart}
+    if graph:
+        roof["graph_replays"] = graph
+        roof["note"] += ("; value and ms_per_step are the graph-replay run's wall time, the "
+                         "kernel averages come from an eager run of the same steps")
     return value, ms_step, cfg, roof, extra
 
 
@@ -556,6 +593,7 @@ def main():
     else:
         tuning = None
         fp64_twin = False
+        graph_chunk = 0
         if args.workload == "spec4096_split_share8":
             w = workloads.C3_SHARE8
         elif args.workload == "spec4096_fp64":
@@ -573,6 +611,11 @@ def main():
                 w, lpt, workloads, torch.cuda.get_device_name(0),
                 log=lambda m: None)
             tuning = dict(tuning, graph_chunk=0)   # per-kernel events need eager launches
+            graph_chunk = 100                      # the workload's 100-step graph chunks
+            # whole chunks; two warm-up chunks capture the graphs of both
+            # state-buffer parities (an odd number of re-sorts per chunk flips it)
+            args.steps = max(graph_chunk, args.steps // graph_chunk * graph_chunk)
+            args.warmup = max(2 * graph_chunk, args.warmup // graph_chunk * graph_chunk)
             log(f"[bench] autotuned launch shape ({'cached' if hit else 'tuned now'}): {tuning}")
         elif args.workload == "spec1024_fp64":
             w = workloads.c2_spectrum(args.scheme)
@@ -585,7 +628,7 @@ def main():
         if args.sort_interval is not None:
             w = dataclasses.replace(w, sort_interval=args.sort_interval)
         value, ms_per_step, cfg, roof, extra = bench_steps(args, lpt, workloads, w, tuning,
-                                                           fp64_twin)
+                                                           fp64_twin, graph_chunk)
         if w.precision == "fp64":
             dtype = "f64"
         if w is not workloads.C3_SPLIT:

@@ -104,12 +104,14 @@ typedef struct {
     uint32_t flags;         /* LPT_FLAG_*                                     */
     int32_t tile_records;   /* capacity, in node records, of the per-block
                                LDS field tile of the step kernel: 0 selects
-                               the default (1200 records: 19200 bytes for
-                               FP32-split, 38400 for FP64, each rounded up
-                               to whole 64-entry fill chunks), -1 disables
-                               tiles (every stencil gathers from global
-                               memory), else at least 16 records and at
-                               most 61440 bytes of records; else LPT_E_ARG */
+                               the default (FP32-split: per launch, the
+                               largest capacity that keeps the kernel's
+                               register-bound occupancy; FP64: 1200 records,
+                               38400 bytes), -1 disables tiles (every
+                               stencil gathers from global memory), else at
+                               least 16 records and at most 61440 bytes of
+                               records (rounded up to whole 64-entry fill
+                               chunks); else LPT_E_ARG                      */
 } lpt_config;
 
 /* One statistics record of one species (Sec. 3.2, 5.5):
@@ -255,8 +257,10 @@ lpt_status lpt_set_state(lpt_ctx *ctx, const void *blob, size_t size);
 /* Launch-shape choices of the step path.  None of them changes a
  * per-particle result (positions, displacements and velocities are the same
  * bits with any choice), so an autotuner may pick them for speed.  The
- * statistics sum per block, so a different block size changes their last
- * bits; they are run-to-run reproducible for a fixed block size. */
+ * statistics are summed per wave of 64 slots and merged in slot order, so the
+ * block size and launch shape leave them unchanged too; a different sort
+ * interval or sort key reorders the slots and so may change their last bits.
+ * They are run-to-run reproducible for fixed choices. */
 typedef struct {
     int32_t block_size;     /* threads per block of the step kernel: 64, 128,
                                256 or 512 (0 selects 256)                    */
@@ -288,6 +292,12 @@ typedef struct {
                                cell order (2); 0: one launch per species
                                (LPT_FP32_SPLIT) or one launch in species
                                order (LPT_FP64)                               */
+    int32_t sort_cells;     /* 1: the re-sort key orders the cells inside each
+                               T x T tile too (row-major), so that neighbouring
+                               slots sit in neighbouring cells; the key grows
+                               by 2 log2 T bits and must stay within 32 bits
+                               (else LPT_E_ARG); 0 (default): tiles only, ties
+                               keep their order                               */
 } lpt_tuning;
 
 lpt_status lpt_get_tuning(lpt_ctx *ctx, lpt_tuning *out);

@@ -1,7 +1,7 @@
 """Launch-shape autotuner of the step path.
 
-Picks block size, LDS tile capacity, re-sort interval, persistent launches,
-fused or per-species step launches and hipGraph chunk length for one
+Picks block size, LDS tile capacity, re-sort interval and key, persistent
+launches, fused or per-species step launches and hipGraph chunk length for one
 workload by timing candidates with HIP events on a throwaway context of that workload (``lpt_time_steps``), by
 coordinate descent from the library defaults.  None of these choices changes
 a per-particle result (see ``lpt_set_tuning``), only the time per step.
@@ -23,6 +23,7 @@ SPACE = {
     "graph_chunk": (0, 100),
     "halo_scale": (0.125, 0.25, 0.5, 1.0),
     "fused": (1, 0, 2),
+    "sort_cells": (0, 1),
 }
 
 
@@ -47,7 +48,7 @@ def tune(w, lpt_mod, workloads_mod, trial_steps=80, rounds=2, log=None):
         best = tr.get_tuning()
         best.update(sort_interval=w.sort_interval or 20, graph_chunk=0, persistent=0,
                     tile_records=0, block_size=256, halo_scale=0.125, fused=1,
-                    max_workgroups=0)
+                    max_workgroups=0, sort_cells=0)
 
         def measure(t):
             tr.set_tuning(**t)

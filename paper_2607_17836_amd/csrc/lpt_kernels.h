@@ -73,6 +73,8 @@ struct StepParams {
     const int32_t *order;
     int32_t order_len;
     int32_t max_wg;        // > 0: persistent grids hold at most this many workgroups
+    int32_t tile_auto;     // 1: each step launch replaces tile_cap by the largest
+                           // capacity that keeps its kernel's register-bound occupancy
 };
 
 // Block-order table of a fused launch over species whose logical blocks are
@@ -227,13 +229,15 @@ int64_t sort_scan_blocks(int64_t n);
 // p[0 .. n) = v (a kernel, so that it can sit in a captured graph)
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 
-// keys[0] = (species << tile_bits) | tile index of the stored cell, plus the
-// histogram of the first radix digit (of a key_bits-bit sort) in W.hist.
-// Keys of at most 16 bits are stored as uint16_t (see radix_sort's narrow).
+// keys[0] = (species << tile_bits) | tile index of the stored cell -- with
+// `cells`, shifted up by 2 log2(tile) bits over the cell's row-major index
+// inside its tile -- plus the histogram of the first radix digit (of a
+// key_bits-bit sort) in W.hist.  Keys of at most 16 bits are stored as
+// uint16_t (see radix_sort's narrow).
 hipError_t launch_keys64(const StepParams &P, const State64 &S, int tile, int tile_bits,
-                         int key_bits, SortWork &W, hipStream_t st);
+                         bool cells, int key_bits, SortWork &W, hipStream_t st);
 hipError_t launch_keys32(const StepParams &P, const State32 &S, int tile, int tile_bits,
-                         int key_bits, SortWork &W, hipStream_t st);
+                         bool cells, int key_bits, SortWork &W, hipStream_t st);
 // Stable LSD radix sort of keys[0] over the low key_bits bits, carrying each
 // key's input index as its value (vals[0] is not read).  first_hist: W.hist
 // already holds the first digit's histogram (from launch_keys*).  narrow:

@@ -49,11 +49,13 @@ int32_t lpt::build_block_order(int nspecies, const int32_t *begin, const int32_t
 
 namespace {
 
-// Default capacity of the step kernel's field tile, in node records: 19200
-// bytes for FP32 (eight 256-thread blocks, 32 waves, resident per CU within
-// the 160 KiB of LDS), 38400 bytes for FP64 (four blocks; a smaller FP64
-// tile leaves too many blocks' boxes uncovered, which costs more than the
-// lost occupancy).
+// Capacity of the field tile, in node records, of the FP64 step kernel and
+// the adjoint's recompute kernel when the tuning asks for the default (0):
+// 38400 bytes (four 256-thread blocks per CU; a smaller FP64 tile leaves too
+// many blocks' boxes uncovered, which costs more than the lost occupancy).
+// The FP32 step kernels then size their tile per launch to the occupancy
+// their registers allow (1216 records for the bilinear kernel's eight blocks
+// per CU, more for the bicubic and fused kernels, which hold fewer).
 constexpr int32_t kTileRecordsDefault = 1200;
 constexpr size_t kTileBytesMax = 61440;
 // Default tile halo, as a fraction of the largest per-step displacement: small
@@ -96,7 +98,10 @@ struct lpt_ctx {
     int32_t block = 256;
     int32_t sort_interval = 0;
     int32_t sort_tile = 16;
+    int32_t sort_cells = 0;  // 1: the key also orders cells inside each tile
     int32_t tile_cap = 0;    // LDS tile capacity of the step kernel, node records
+    int32_t tile_auto = 0;   // 1: step launches size the tile to their occupancy
+                             // (tile_cap is then the adjoint kernels' capacity)
     int32_t persistent = 0;  // persistent step launches
     float halo_scale = kHaloScaleDefault; // LDS tile halo relative to the largest-speed bound
     int32_t graph_chunk = 0; // steps per captured hipGraph (0: eager launches)
@@ -271,6 +276,7 @@ StepParams make_params(const lpt_ctx *c)
     P.block_base = 0;
     P.launch_blocks = blk;
     P.max_wg = c->max_wg;
+    P.tile_auto = c->tile_auto;
     if (c->fused && c->sp.size() > 1 && c->order_ok) {
         P.order = c->order;
         P.order_len = c->order_len;
@@ -308,6 +314,13 @@ int32_t slot_mode(double wa, double wb)
 // The scheme every species uses, or 3 if they differ.
 int species_bits(const lpt_ctx *c) { return c->sp.size() > 1 ? ilog2i((int64_t)c->sp.size()) : 0; }
 int tile_bits(const lpt_ctx *c) { return 2 * ilog2i(c->n / c->sort_tile); }
+// Width of the cell-order key: species, tile and (with sort_cells) the cell
+// inside the tile.
+int key_width(int n, int tile, int cells, int nspecies)
+{
+    return 2 * ilog2i(n / tile) + (cells ? 2 * ilog2i(tile) : 0) +
+           (nspecies > 1 ? ilog2i(nspecies) : 0);
+}
 
 lpt_status ensure_sort_work(lpt_ctx *c)
 {
@@ -392,11 +405,14 @@ lpt_status do_sort(lpt_ctx *c, const uint32_t **perm_out = nullptr,
     if (c->time_kernels) HIP_TRY(c, mark(c, e0));
     const StepParams P = make_params(c);
     const int tb = tile_bits(c);
-    const int kb = std::max(1, tb + species_bits(c));
+    const int kb = std::max(1, key_width(c->n, c->sort_tile, c->sort_cells, (int)c->sp.size()));
+    const bool cells = c->sort_cells != 0;
     if (c->precision == LPT_FP64)
-        HIP_TRY(c, launch_keys64(P, c->s64[c->cur], c->sort_tile, tb, kb, c->sw, c->stream));
+        HIP_TRY(c, launch_keys64(P, c->s64[c->cur], c->sort_tile, tb, cells, kb, c->sw,
+                                 c->stream));
     else
-        HIP_TRY(c, launch_keys32(P, c->s32[c->cur], c->sort_tile, tb, kb, c->sw, c->stream));
+        HIP_TRY(c, launch_keys32(P, c->s32[c->cur], c->sort_tile, tb, cells, kb, c->sw,
+                                 c->stream));
     int res = 0;
     HIP_TRY(c, radix_sort(c->sw, c->np, kb, true, true, &res, c->stream));
     const uint32_t *perm = c->sw.vals[res];
@@ -506,6 +522,7 @@ lpt_status lpt_create(const lpt_config *cfg, lpt_ctx **out)
     const size_t rec_size = cfg->precision == LPT_FP64 ? sizeof(Rec64) : sizeof(float4);
     const int32_t tile_max = (int32_t)(kTileBytesMax / rec_size);
     int32_t tile_cap = cfg->tile_records;
+    const int32_t tile_auto = tile_cap == 0;
     if (tile_cap == 0) tile_cap = kTileRecordsDefault;
     else if (tile_cap == -1) tile_cap = 0;
     else if (tile_cap < 16 || tile_cap > tile_max) return LPT_E_ARG;
@@ -523,6 +540,7 @@ lpt_status lpt_create(const lpt_config *cfg, lpt_ctx **out)
     c->sort_interval = cfg->sort_interval;
     c->sort_tile = tile;
     c->tile_cap = tile_cap;
+    c->tile_auto = tile_auto;
     c->compat_edge = (cfg->flags & LPT_FLAG_COMPAT_EDGE) != 0;
     c->det_grad = (cfg->flags & LPT_FLAG_DETERMINISTIC_GRAD) != 0;
     c->time_kernels = (cfg->flags & LPT_FLAG_TIME_KERNELS) != 0;
@@ -799,7 +817,7 @@ lpt_status lpt_add_species(lpt_ctx *c, lpt_kind kind, double st, lpt_scheme sche
     if (inertial && !vx0 && !(c->slot_set[0] && c->slot_set[1]))
         return fail(c, LPT_E_STATE, "v0 from the field needs both snapshots set");
     int32_t nsp = (int32_t)c->sp.size() + 1;
-    if (2 * ilog2i(c->n / c->sort_tile) + (nsp > 1 ? ilog2i(nsp) : 0) > 32)
+    if (key_width(c->n, c->sort_tile, c->sort_cells, nsp) > 32)
         return fail(c, LPT_E_ARG, "sort key wider than 32 bits; raise sort_tile");
     HIP_TRY(c, hipSetDevice(c->device));
 
@@ -1260,6 +1278,11 @@ lpt_status reverse_sweep(lpt_ctx *c, int nl, double2 *&lam, double2 *&lam_spare,
     HIP_TRY(c, dalloc(tape, (size_t)(tape_len * np)));
     StepParams P = make_params(c);
     set_dt(P, c->ck_dt);
+    // The sweep's LDS boxes (field tile, gradient accumulators) take the full
+    // displacement bound as their halo, so that a block's stage points stay
+    // inside them (an oversized box is trimmed by the kernels); a point
+    // outside costs global gathers and, in the adjoint, global atomics.
+    P.halo_scale = 1.0f;
     const Rec64 *rec = static_cast<const Rec64 *>(c->rec);
     hipError_t e = hipSuccess;
     for (int64_t seg = (N - 1) / E; seg >= 0 && e == hipSuccess; --seg) {
@@ -1922,13 +1945,14 @@ lpt_status lpt_get_tuning(lpt_ctx *c, lpt_tuning *out)
     if (!c) return LPT_E_ARG;
     if (!out) return fail(c, LPT_E_ARG, "out must not be NULL");
     out->block_size = c->block;
-    out->tile_records = c->tile_cap > 0 ? c->tile_cap : -1;
+    out->tile_records = c->tile_auto ? 0 : (c->tile_cap > 0 ? c->tile_cap : -1);
     out->sort_interval = c->sort_interval;
     out->persistent = c->persistent;
     out->graph_chunk = c->graph_chunk;
     out->halo_scale = c->halo_scale;
     out->max_workgroups = c->max_wg;
     out->fused = c->fused;
+    out->sort_cells = c->sort_cells;
     return LPT_OK;
 }
 
@@ -1941,6 +1965,7 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
         return fail(c, LPT_E_ARG, "block_size must be 64, 128, 256 or 512");
     const size_t rec_size = c->precision == LPT_FP64 ? sizeof(Rec64) : sizeof(float4);
     int32_t tile = t->tile_records;
+    const int32_t tile_auto = tile == 0;
     if (tile == 0) tile = kTileRecordsDefault;
     else if (tile == -1) tile = 0;
     else if (tile < 16 || (size_t)tile > kTileBytesMax / rec_size)
@@ -1952,6 +1977,9 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
     if (!(halo > 0.0f && halo <= 4.0f)) return fail(c, LPT_E_ARG, "halo_scale must be in (0, 4]");
     if (t->max_workgroups < 0) return fail(c, LPT_E_ARG, "max_workgroups must be >= 0");
     if (t->fused < 0 || t->fused > 2) return fail(c, LPT_E_ARG, "fused is 0, 1 or 2");
+    if (t->sort_cells != 0 && t->sort_cells != 1) return fail(c, LPT_E_ARG, "sort_cells is 0 or 1");
+    if (key_width(c->n, c->sort_tile, t->sort_cells, (int)c->sp.size()) > 32)
+        return fail(c, LPT_E_ARG, "sort key wider than 32 bits with sort_cells; raise sort_tile");
     HIP_TRY(c, hipSetDevice(c->device));
     const bool block_changed = block != c->block;
     if (block_changed) {
@@ -1974,6 +2002,7 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
         }
     }
     c->tile_cap = tile;
+    c->tile_auto = tile_auto;
     c->sort_interval = t->sort_interval;
     c->persistent = t->persistent;
     c->graph_chunk = t->graph_chunk;
@@ -1981,6 +2010,7 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
     c->max_wg = t->max_workgroups;
     if (t->fused != c->fused || block_changed) c->order_ok = false;
     c->fused = t->fused;
+    c->sort_cells = t->sort_cells;
     invalidate_graphs(c);
     return LPT_OK;
 }

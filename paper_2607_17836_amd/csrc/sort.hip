@@ -57,12 +57,20 @@ __device__ __forceinline__ int species_of_particle(const StepParams &P, int64_t 
     return s;
 }
 
+// Cell-order key of the stored cell (ci, cj): the species, then the T x T
+// tile (T = 2^tile_shift) in row-major tile order, then -- with `cells` --
+// the cell row-major inside its tile (2 tile_shift more low bits).
 __device__ __forceinline__ uint32_t tile_key(int ci, int cj, int n, int tile_shift, int tile_bits,
-                                             int species)
+                                             int cells, int species)
 {
     const uint32_t tx = (uint32_t)ci >> tile_shift, ty = (uint32_t)cj >> tile_shift;
     const uint32_t tiles_x = (uint32_t)n >> tile_shift;
-    return ((uint32_t)species << tile_bits) | (ty * tiles_x + tx);
+    uint32_t k = ((uint32_t)species << tile_bits) | (ty * tiles_x + tx);
+    if (cells) {
+        const uint32_t m = (1u << tile_shift) - 1u;
+        k = (k << (2 * tile_shift)) | (((uint32_t)cj & m) << tile_shift) | ((uint32_t)ci & m);
+    }
+    return k;
 }
 
 // Adds the digits of v[0 .. cnt) to the LDS histogram h, one increment per
@@ -162,7 +170,7 @@ __device__ __forceinline__ void keys_tile(Load load, int64_t total, K *keys, uin
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void keys64_kernel(StepParams P, State64 S,
                                                               int tile_shift, int tile_bits,
-                                                              K *keys, int64_t total,
+                                                              int cells, K *keys, int64_t total,
                                                               uint32_t mask, uint32_t *hist,
                                                               int ntiles)
 {
@@ -173,7 +181,8 @@ __global__ __launch_bounds__(kSortThreads) void keys64_kernel(StepParams P, Stat
                 if (j >= cnt) break;
                 const double2 x = S.pos[i0 + j];
                 const int ci = cell_of_pos(x.x, P.invh, P.n), cj = cell_of_pos(x.y, P.invh, P.n);
-                k[j] = tile_key(ci, cj, P.n, tile_shift, tile_bits, species_of_particle(P, i0 + j));
+                k[j] = tile_key(ci, cj, P.n, tile_shift, tile_bits, cells,
+                                species_of_particle(P, i0 + j));
             }
         },
         total, keys, mask, hist, ntiles);
@@ -182,7 +191,7 @@ __global__ __launch_bounds__(kSortThreads) void keys64_kernel(StepParams P, Stat
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void keys32_kernel(StepParams P, State32 S,
                                                               int tile_shift, int tile_bits,
-                                                              K *keys, int64_t total,
+                                                              int cells, K *keys, int64_t total,
                                                               uint32_t mask, uint32_t *hist,
                                                               int ntiles)
 {
@@ -205,7 +214,7 @@ __global__ __launch_bounds__(kSortThreads) void keys32_kernel(StepParams P, Stat
 #pragma unroll
             for (int j = 0; j < kItems; ++j)
                 k[j] = tile_key((int)(c[j] & 0xFFFFu), (int)(c[j] >> 16), P.n, tile_shift,
-                                tile_bits, species_of_particle(P, i0 + j));
+                                tile_bits, cells, species_of_particle(P, i0 + j));
         },
         total, keys, mask, hist, ntiles);
 }
@@ -226,34 +235,36 @@ static int ilog2(int t)
 static uint32_t first_mask(int key_bits) { return key_bits >= 8 ? 0xFFu : (1u << key_bits) - 1u; }
 
 hipError_t launch_keys64(const StepParams &P, const State64 &S, int tile, int tile_bits,
-                         int key_bits, SortWork &W, hipStream_t st)
+                         bool cells, int key_bits, SortWork &W, hipStream_t st)
 {
     const int64_t total = total_particles(P);
     const int ntiles = (int)((total + kTile - 1) / kTile);
     if (key_bits <= 16)
         hipLaunchKernelGGL(keys64_kernel<uint16_t>, dim3(ntiles), dim3(kSortThreads), 0, st, P, S,
-                           ilog2(tile), tile_bits, reinterpret_cast<uint16_t *>(W.keys[0]), total,
+                           ilog2(tile), tile_bits, (int)cells,
+                           reinterpret_cast<uint16_t *>(W.keys[0]), total,
                            first_mask(key_bits), W.hist, ntiles);
     else
         hipLaunchKernelGGL(keys64_kernel<uint32_t>, dim3(ntiles), dim3(kSortThreads), 0, st, P, S,
-                           ilog2(tile), tile_bits, W.keys[0], total, first_mask(key_bits), W.hist,
-                           ntiles);
+                           ilog2(tile), tile_bits, (int)cells, W.keys[0], total,
+                           first_mask(key_bits), W.hist, ntiles);
     return hipGetLastError();
 }
 
 hipError_t launch_keys32(const StepParams &P, const State32 &S, int tile, int tile_bits,
-                         int key_bits, SortWork &W, hipStream_t st)
+                         bool cells, int key_bits, SortWork &W, hipStream_t st)
 {
     const int64_t total = total_particles(P);
     const int ntiles = (int)((total + kTile - 1) / kTile);
     if (key_bits <= 16)
         hipLaunchKernelGGL(keys32_kernel<uint16_t>, dim3(ntiles), dim3(kSortThreads), 0, st, P, S,
-                           ilog2(tile), tile_bits, reinterpret_cast<uint16_t *>(W.keys[0]), total,
+                           ilog2(tile), tile_bits, (int)cells,
+                           reinterpret_cast<uint16_t *>(W.keys[0]), total,
                            first_mask(key_bits), W.hist, ntiles);
     else
         hipLaunchKernelGGL(keys32_kernel<uint32_t>, dim3(ntiles), dim3(kSortThreads), 0, st, P, S,
-                           ilog2(tile), tile_bits, W.keys[0], total, first_mask(key_bits), W.hist,
-                           ntiles);
+                           ilog2(tile), tile_bits, (int)cells, W.keys[0], total,
+                           first_mask(key_bits), W.hist, ntiles);
     return hipGetLastError();
 }
 

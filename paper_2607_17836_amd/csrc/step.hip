@@ -14,6 +14,10 @@
 // cell-ordered particles (sort.hip) and an XCD-aware block order for L2 reuse.
 #include "field_dev.h"
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace lpt {
 
 // One logical block of the FP64 step: the state of slot p is read from S and
@@ -672,20 +676,73 @@ static int launch_grid(K kernel, const StepParams &P, int block, size_t lds, int
     return (int)resident;
 }
 
+// Automatic LDS tile capacity of an FP32 step kernel at a block size: the
+// CU's LDS split between as many blocks as the kernel's registers let stay
+// resident (less each block's static LDS), in whole 64-entry fill chunks,
+// lowered while it would still cost a resident block.  planes: 16-byte
+// entries per node record (one for FP32; two, plus one chunk of fill
+// overrun, for FP64).  The occupancy queries run once per (kernel, block
+// size, device).
+template <typename K>
+static int32_t auto_tile_cap(K kernel, int block, int planes, int32_t fallback)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, int>, int32_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fallback;
+    }
+    const auto key = std::make_tuple(reinterpret_cast<const void *>(kernel), block, dev);
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    auto lds_of = [planes](int32_t cap) {
+        return planes == 1 ? (size_t)cap * 16 : (size_t)(2 * cap + kWave) * 16;
+    };
+    int lds_cu = 0, blocks = 0;
+    hipFuncAttributes fa{};
+    int32_t cap = fallback;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+            hipSuccess &&
+        hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kernel)) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, block, 0) == hipSuccess &&
+        blocks > 0 && lds_cu > 0) {
+        const int64_t per_block = (int64_t)lds_cu / blocks - (int64_t)fa.sharedSizeBytes;
+        const int64_t entries = per_block / 16 - (planes == 1 ? 0 : kWave);
+        int64_t c = entries / planes / kWave * kWave;
+        const int64_t most = (int64_t)(61440 / (16 * planes)) / kWave * kWave;
+        c = c > most ? most : c;
+        int resident = 0;
+        while (c >= kWave &&
+               (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kernel, block,
+                                                             lds_of((int32_t)c)) != hipSuccess ||
+                resident < blocks))
+            c -= kWave;
+        if (c >= kWave) cap = (int32_t)c;
+    }
+    (void)hipGetLastError();
+    cache.emplace(key, cap);
+    return cap;
+}
+
 template <bool C, bool I, bool S>
 static hipError_t launch64_t(const StepParams &P, const State64 &St, const State64 &Dst,
                              const uint32_t *perm, const Rec64 *rec, double *partials,
                              DevClock *clock, int block, int grid, hipStream_t st)
 {
+    // The FP64 tile keeps its fixed capacity in automatic mode too: sized to
+    // the register-bound occupancy it would leave too many boxes uncovered.
+    const StepParams &P1 = P;
     // two planes of 16-byte entries; the fill writes whole 64-entry chunks of each
-    const size_t lds = P.tile_cap > 0 ? (size_t)(2 * P.tile_cap + kWave) * 16 : 0;
+    const size_t lds = P1.tile_cap > 0 ? (size_t)(2 * P1.tile_cap + kWave) * 16 : 0;
     StepParams Q;
     if (perm) {
-        const int g = launch_grid(step64_perm_kernel<C, I, S>, P, block, lds, grid, Q);
+        const int g = launch_grid(step64_perm_kernel<C, I, S>, P1, block, lds, grid, Q);
         hipLaunchKernelGGL((step64_perm_kernel<C, I, S>), dim3(g), dim3(block), lds, st, Q, St,
                            Dst, perm, rec, partials, clock);
     } else {
-        const int g = launch_grid(step64_kernel<C, I, S>, P, block, lds, grid, Q);
+        const int g = launch_grid(step64_kernel<C, I, S>, P1, block, lds, grid, Q);
         hipLaunchKernelGGL((step64_kernel<C, I, S>), dim3(g), dim3(block), lds, st, Q, St, rec,
                            partials, clock);
     }
@@ -697,16 +754,20 @@ static hipError_t launch32_t(const StepParams &P, const State32 &S, const State3
                              const uint32_t *perm, const float4 *rec, double *partials,
                              DevClock *clock, int block, int grid, hipStream_t st)
 {
+    StepParams P1 = P;
+    if (P.tile_auto && P.tile_cap > 0)
+        P1.tile_cap = perm ? auto_tile_cap(step32_perm_kernel<SCHS, KINDS, ST>, block, 1, P.tile_cap)
+                           : auto_tile_cap(step32_kernel<SCHS, KINDS, ST>, block, 1, P.tile_cap);
     // whole 64-entry chunks: the tile fill writes LDS a wave's chunk at a time
     const size_t lds =
-        P.tile_cap > 0 ? (size_t)((P.tile_cap + kWave - 1) / kWave * kWave) * sizeof(float4) : 0;
+        P1.tile_cap > 0 ? (size_t)((P1.tile_cap + kWave - 1) / kWave * kWave) * sizeof(float4) : 0;
     StepParams Q;
     if (perm) {
-        const int g = launch_grid(step32_perm_kernel<SCHS, KINDS, ST>, P, block, lds, grid, Q);
+        const int g = launch_grid(step32_perm_kernel<SCHS, KINDS, ST>, P1, block, lds, grid, Q);
         hipLaunchKernelGGL((step32_perm_kernel<SCHS, KINDS, ST>), dim3(g), dim3(block), lds, st,
                            Q, S, D, perm, rec, partials, clock);
     } else {
-        const int g = launch_grid(step32_kernel<SCHS, KINDS, ST>, P, block, lds, grid, Q);
+        const int g = launch_grid(step32_kernel<SCHS, KINDS, ST>, P1, block, lds, grid, Q);
         hipLaunchKernelGGL((step32_kernel<SCHS, KINDS, ST>), dim3(g), dim3(block), lds, st, Q, S,
                            rec, partials, clock);
     }

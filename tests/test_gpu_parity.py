@@ -296,13 +296,15 @@ def test_radix_sort_bit_exact(count, bits):
 @pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
 def test_sorting_never_changes_results(precision):
     """Per-particle results are bit-identical with and without cell-order
-    re-sorting (each particle's arithmetic does not depend on its slot)."""
+    re-sorting, by tiles or by tiles and cells (each particle's arithmetic
+    does not depend on its slot)."""
     say(f"sort invariance {precision}")
     n = 256
     (ua, va), (ub, vb) = synth.spectrum_snapshots(n, 10, 8, 0.002)
     outs = []
-    for interval in (0, 3):
+    for interval, cells in ((0, 0), (3, 0), (3, 1)):
         tr = lpt.Tracker(n, precision, sort_interval=interval, sort_tile=8)
+        tr.set_tuning(sort_cells=cells)
         tr.set_time_mode("pingpong")
         tr.set_snapshot(0, 0.0, ua, va)
         tr.set_snapshot(1, 0.002, ub, vb)
@@ -314,9 +316,10 @@ def test_sorting_never_changes_results(precision):
         tr.step(25, 0.002, stats_every=5)
         outs.append((tr.get_positions(s0), tr.get_positions(s1), tr.get_velocities(s1)))
         tr.close()
-    for a, b in zip(outs[0], outs[1]):
-        for qa, qb in zip(a, b):
-            np.testing.assert_array_equal(qa, qb)
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            for qa, qb in zip(a, b):
+                np.testing.assert_array_equal(qa, qb)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
@@ -394,15 +397,18 @@ def test_tile_escapees_match_oracle(scheme):
     assert np.max(np.abs(vx - sp.vx)) < 1e-8 and np.max(np.abs(vy - sp.vy)) < 1e-8
 
 
+@pytest.mark.parametrize("cells", [0, 1])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
-def test_sort_produces_stable_tile_order(precision):
+def test_sort_produces_stable_tile_order(precision, cells):
     """Right after initialisation (slots in original order), lpt_sort leaves
     the slots in the stable argsort order of the cell-tile keys of the
-    stored cells, species by species."""
-    say(f"sort order {precision}")
+    stored cells, species by species: tiles alone, or (sort_cells) tiles
+    and then the cells row-major inside each tile."""
+    say(f"sort order {precision} cells={cells}")
     n = 128
     u, v, _ = synth.taylor_green(n)
     tr = lpt.Tracker(n, precision, sort_tile=8)
+    tr.set_tuning(sort_cells=cells)
     tr.set_snapshot(0, 0.0, u, v)
     tr.set_snapshot(1, 1.0, u, v)
     z = np.zeros(30000)
@@ -420,7 +426,7 @@ def test_sort_produces_stable_tile_order(precision):
         else:   # the split path stores floor(x * n / L)
             ci = np.floor(x0 * (n / L)).astype(np.int32)
             cj = np.floor(y0 * (n / L)).astype(np.int32)
-        keys = oracle.cell_keys(n, 8, ci, cj, coarse=True)
+        keys = oracle.cell_keys(n, 8, ci, cj, coarse=not cells)
         np.testing.assert_array_equal(order, oracle.sort_permutation(keys))
 
 
