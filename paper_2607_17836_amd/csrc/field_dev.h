@@ -294,40 +294,67 @@ __device__ __forceinline__ double dpp_f64(double x)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-__device__ __forceinline__ double wave_sum_f64(double x)
+// Exchanges of 64-bit lane values between lane groups (gfx950 permlane
+// swaps, one per 32-bit half).  swap32: x takes [x lanes 0-31 | y lanes
+// 0-31], y takes [x lanes 32-63 | y lanes 32-63].  swap16, per 16-lane row r:
+// x takes [x r0 | y r0 | x r2 | y r2], y takes [x r1 | y r1 | x r3 | y r3].
+__device__ __forceinline__ void swap32_f64(double &x, double &y)
 {
-    x += dpp_f64<0x111, 0xF>(x);   // row_shr:1
-    x += dpp_f64<0x112, 0xF>(x);   // row_shr:2
-    x += dpp_f64<0x114, 0xF>(x);   // row_shr:4
-    x += dpp_f64<0x118, 0xF>(x);   // row_shr:8
-    x += dpp_f64<0x142, 0xA>(x);   // row_bcast:15
-    x += dpp_f64<0x143, 0xC>(x);   // row_bcast:31
-    const uint64_t b = __builtin_bit_cast(uint64_t, x);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    const uint64_t bx = __builtin_bit_cast(uint64_t, x), by = __builtin_bit_cast(uint64_t, y);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)bx, (uint32_t)by, false, false);
+    const auto hi =
+        __builtin_amdgcn_permlane32_swap((uint32_t)(bx >> 32), (uint32_t)(by >> 32), false, false);
+    x = __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0]);
+    y = __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1]);
+}
+
+__device__ __forceinline__ void swap16_f64(double &x, double &y)
+{
+    const uint64_t bx = __builtin_bit_cast(uint64_t, x), by = __builtin_bit_cast(uint64_t, y);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)bx, (uint32_t)by, false, false);
+    const auto hi =
+        __builtin_amdgcn_permlane16_swap((uint32_t)(bx >> 32), (uint32_t)(by >> 32), false, false);
+    x = __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0]);
+    y = __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1]);
 }
 
 // Statistics partial of one wave (Sec. 3.2 and 5.5 quantities): the sums of
-// dx^2 and dy^2 over its active lanes and M2 = sum (r2 - m)^2 of
-// r2 = dx^2 + dy^2 about the wave's own mean m, so that the finalisation
-// can merge waves with the pairwise update of the mean and M2 instead of
-// forming var = (sum r2^2 - N m^2) / (N - 1), which cancels when the spread
-// is small against the mean (uniform flow: every r2 equal).  The count of a
-// wave follows from the species size, so it is not stored.  Every lane of
-// the wave must call it (inactive lanes with r2x = r2y = 0); lane 0 writes
-// out[0..2].
+// dx^2 and dy^2 over its active lanes, and the sums of d and d^2 for
+// d = r2 - K, r2 = dx^2 + dy^2, with K the r2 of the wave's first active
+// lane.  The finalisation forms the wave's M2 = sum d^2 - (sum d)^2 / count,
+// the sum of squared deviations of r2 about the wave's mean: shifted by a
+// sample of the wave, it keeps its accuracy where the spread of r2 is small
+// against its mean (uniform flow: every d is zero), unlike
+// (sum r2^2 - N m^2) / (N - 1).  The four sums are reduced together: two
+// swap-and-add levels leave one quantity per 16-lane row, a row reduction
+// finishes them, and the last lane of each row stores its sum, so out
+// receives (sum dx^2, sum dy^2, sum d, sum d^2).  Every lane of the wave must
+// call it (inactive lanes with r2x = r2y = 0).
 __device__ __forceinline__ void wave_stats(double r2x, double r2y, bool active, double *out)
 {
-    const double sx = wave_sum_f64(r2x), sy = wave_sum_f64(r2y);
-    const int cnt = __popcll(__ballot(active));
-    const double mean = cnt > 0 ? (sx + sy) / (double)cnt : 0.0;
-    const double d = active ? (r2x + r2y) - mean : 0.0;
-    const double m2 = wave_sum_f64(d * d);
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-        out[0] = sx;
-        out[1] = sy;
-        out[2] = m2;
+    const uint64_t live = __ballot(active);
+    const int first = live ? __builtin_ctzll(live) : 0;
+    const double r2 = r2x + r2y;
+    const uint64_t br = __builtin_bit_cast(uint64_t, r2);
+    const uint32_t klo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)br, first);
+    const uint32_t khi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(br >> 32), first);
+    const double K = __builtin_bit_cast(double, ((uint64_t)khi << 32) | klo);
+    const double d = active ? r2 - K : 0.0;
+    double a = r2x, b = r2y, c = d, e = d * d;
+    swap32_f64(a, b);
+    swap32_f64(c, e);
+    double x = a + b;   // lanes 0-31: sum dx^2 halves, lanes 32-63: sum dy^2 halves
+    double y = c + e;   // likewise sum d, sum d^2
+    swap16_f64(x, y);
+    double z = x + y;   // rows: sum dx^2, sum d, sum dy^2, sum d^2 over 16 lanes each
+    z += dpp_f64<0x111, 0xF>(z);   // row_shr:1
+    z += dpp_f64<0x112, 0xF>(z);   // row_shr:2
+    z += dpp_f64<0x114, 0xF>(z);   // row_shr:4
+    z += dpp_f64<0x118, 0xF>(z);   // row_shr:8
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    if ((lane & 15) == 15) {
+        const int row = lane >> 4;
+        out[(row & 1) * 2 + (row >> 1)] = z;   // rows 0, 1, 2, 3 -> out[0], out[2], out[1], out[3]
     }
 }
 

@@ -8,7 +8,9 @@
 namespace lpt {
 
 constexpr int kMaxSpecies = 16;
-constexpr int kStatTerms = 3;   // per wave: sum dx^2, sum dy^2, M2 of dx^2 + dy^2
+// per wave: sum dx^2, sum dy^2, and the sums of d and d^2 for
+// d = r2 - K, r2 = dx^2 + dy^2, K = r2 of the wave's first active lane
+constexpr int kStatTerms = 4;
 
 enum Scheme : int32_t { kBilinear = 0, kCatmullRom = 1, kBSpline = 2 };
 // a fused FP32 launch whose blocks take their species' scheme at run time

@@ -837,21 +837,27 @@ hipError_t launch_step32(const StepParams &P, const State32 &S, const State32 &D
 }
 // ===========================================================================
 // Statistics: fixed-order merge of the per-wave partials into one record per
-// species (Sec. 3.2 and 5.5 quantities).  A partial is (count, sum dx^2,
-// sum dy^2, M2) with M2 the sum of squared deviations of r2 = dx^2 + dy^2
-// about the partial's own mean; two partials merge by the pairwise update of
-// Chan, Golub & LeVeque (1979): n = na + nb, delta = mean_b - mean_a,
-// M2 = M2a + M2b + delta^2 na nb / n.  Stage 1 merges runs of kFinChunk
-// waves of one species per workgroup, stage 2 merges the runs of each
-// species in one workgroup; both in a fixed order (sequential per thread,
-// then a pairwise tree), so the record does not depend on scheduling.
+// species (Sec. 3.2 and 5.5 quantities).  A wave's partial becomes (count,
+// sum dx^2, sum dy^2, mean of r2, M2) with M2 = sum d^2 - (sum d)^2 / count
+// the sum of squared deviations of r2 = dx^2 + dy^2 about the wave's mean (d
+// is r2 shifted by a sample of the wave; see wave_stats).  Two partials
+// merge by the pairwise update of Chan, Golub & LeVeque (1979):
+// n = na + nb, delta = mean_b - mean_a, mean = mean_a + delta nb / n,
+// M2 = M2a + M2b + delta^2 na nb / n.  Stage 1 merges runs of kFinChunk waves
+// of one species per workgroup (sequentially per thread, then a butterfly
+// over each wave, then the block's waves in order); stage 2 merges the runs
+// of every species at once, one wave per species.  (A single launch whose
+// last workgroup merges the runs needs agent-scope fences, whose L2
+// write-backs cost more than the second launch.)  Every merge pairs the
+// same operands in the same order whatever the scheduling, so the record
+// does not depend on it.
 // ===========================================================================
 constexpr int kFinThreads = 256;
 constexpr int kFinPerThread = 4;
 constexpr int kFinChunk = kFinThreads * kFinPerThread;   // waves per stage-1 workgroup
 
 struct Moments {
-    double n, sx, sy, m2;
+    double n, sx, sy, mean, m2;
 };
 
 __device__ __forceinline__ Moments merge_moments(const Moments &a, const Moments &b)
@@ -859,8 +865,32 @@ __device__ __forceinline__ Moments merge_moments(const Moments &a, const Moments
     if (b.n == 0.0) return a;
     if (a.n == 0.0) return b;
     const double n = a.n + b.n;
-    const double d = (b.sx + b.sy) / b.n - (a.sx + a.sy) / a.n;
-    return Moments{n, a.sx + b.sx, a.sy + b.sy, a.m2 + b.m2 + d * d * (a.n * b.n / n)};
+    const double f = b.n / n;
+    const double d = b.mean - a.mean;
+    return Moments{n, a.sx + b.sx, a.sy + b.sy, a.mean + d * f, a.m2 + b.m2 + d * d * (a.n * f)};
+}
+
+__device__ __forceinline__ double shfl_xor_f64(double v, int m)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)b, m);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(b >> 32), m);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Butterfly merge over a wave: at each level a lane pair merges (lower lane,
+// higher lane), so both hold the same result; every lane ends with the merge
+// of all 64 in a fixed tree order.
+__device__ __forceinline__ Moments wave_merge(Moments m)
+{
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+#pragma unroll
+    for (int k = 1; k < kWave; k <<= 1) {
+        const Moments o{shfl_xor_f64(m.n, k), shfl_xor_f64(m.sx, k), shfl_xor_f64(m.sy, k),
+                        shfl_xor_f64(m.mean, k), shfl_xor_f64(m.m2, k)};
+        m = (lane & k) ? merge_moments(o, m) : merge_moments(m, o);
+    }
+    return m;
 }
 
 struct FinParams {
@@ -871,98 +901,95 @@ struct FinParams {
     int64_t count[kMaxSpecies];
 };
 
-// Pairwise tree over the block's kFinThreads moments in LDS (fixed order);
-// returns the total in thread 0.  Entered with every thread holding its own.
-__device__ __forceinline__ Moments block_merge(Moments m)
+// Record of species s from the merged moments (lane 0 of the calling wave).
+__device__ __forceinline__ void write_record(const FinParams &F, int s, const Moments &m, double t,
+                                             double t0, int64_t idx, double *records, int64_t cap)
 {
-    __shared__ double sm[4][kFinThreads];
-    const int t = threadIdx.x;
-    sm[0][t] = m.n;
-    sm[1][t] = m.sx;
-    sm[2][t] = m.sy;
-    sm[3][t] = m.m2;
-    __syncthreads();
-    for (int w = kFinThreads / 2; w > 0; w >>= 1) {
-        if (t < w) {
-            const Moments a{sm[0][t], sm[1][t], sm[2][t], sm[3][t]};
-            const Moments b{sm[0][t + w], sm[1][t + w], sm[2][t + w], sm[3][t + w]};
-            const Moments r = merge_moments(a, b);
-            sm[0][t] = r.n;
-            sm[1][t] = r.sx;
-            sm[2][t] = r.sy;
-            sm[3][t] = r.m2;
-        }
-        __syncthreads();
-    }
-    const Moments r{sm[0][0], sm[1][0], sm[2][0], sm[3][0]};
-    __syncthreads();   // the array is reused by the next call
-    return r;
+    if (idx >= cap) return;
+    const double nn = (double)F.count[s];
+    const double mx = m.sx / nn, my = m.sy / nn;
+    const double var = F.count[s] > 1 ? m.m2 / (nn - 1.0) : 0.0;
+    const double el = t - t0;
+    double *r = records + ((int64_t)s * cap + idx) * 8;
+    r[0] = t;
+    r[1] = mx;
+    r[2] = my;
+    r[3] = mx + my;
+    r[4] = el > 0.0 ? mx / (2.0 * el) : 0.0;
+    r[5] = el > 0.0 ? my / (2.0 * el) : 0.0;
+    r[6] = sqrt(var / nn);
+    reinterpret_cast<int64_t *>(r)[7] = F.count[s];
 }
 
 __global__ __launch_bounds__(kFinThreads) void fin_chunks_kernel(FinParams F,
                                                                  const double *__restrict__ partials,
                                                                  double *__restrict__ chunks)
 {
+    __shared__ double sm[kFinThreads / kWave][5];
     const int c = blockIdx.x;
     int s = 0;
     while (s + 1 < F.nspecies && c >= F.chunk_begin[s + 1]) ++s;
     const int64_t w0 = (int64_t)(c - F.chunk_begin[s]) * kFinChunk;
-    Moments m{0.0, 0.0, 0.0, 0.0};
+    Moments m{0.0, 0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < kFinPerThread; ++k) {
         const int64_t lw = w0 + (int64_t)threadIdx.x * kFinPerThread + k;   // wave within the species
         if (lw >= F.nwaves[s]) break;
         const int64_t left = F.count[s] - lw * kWave;
-        const double cnt = (double)(left < kWave ? (left > 0 ? left : 0) : kWave);
+        const int cnt = (int)(left < kWave ? (left > 0 ? left : 0) : kWave);
+        if (cnt == 0) break;
         const double *q = partials + (int64_t)kStatTerms * (F.wave_begin[s] + lw);
-        m = merge_moments(m, Moments{cnt, q[0], q[1], q[2]});
+        const double n = (double)cnt;
+        const double m2 = fmax(q[3] - q[2] * (q[2] / n), 0.0);
+        m = merge_moments(m, Moments{n, q[0], q[1], (q[0] + q[1]) / n, m2});
     }
-    m = block_merge(m);
+    m = wave_merge(m);
+    const int wv = (int)threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        sm[wv][0] = m.n;
+        sm[wv][1] = m.sx;
+        sm[wv][2] = m.sy;
+        sm[wv][3] = m.mean;
+        sm[wv][4] = m.m2;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        double *o = chunks + 4 * (int64_t)c;
-        o[0] = m.n;
-        o[1] = m.sx;
-        o[2] = m.sy;
-        o[3] = m.m2;
+        Moments r{sm[0][0], sm[0][1], sm[0][2], sm[0][3], sm[0][4]};
+        for (int k = 1; k < kFinThreads / kWave; ++k)
+            r = merge_moments(r, Moments{sm[k][0], sm[k][1], sm[k][2], sm[k][3], sm[k][4]});
+        double *o = chunks + 5 * (int64_t)c;
+        o[0] = r.n;
+        o[1] = r.sx;
+        o[2] = r.sy;
+        o[3] = r.mean;
+        o[4] = r.m2;
     }
 }
 
-__global__ __launch_bounds__(kFinThreads) void fin_records_kernel(FinParams F,
-                                                                  const double *__restrict__ chunks,
-                                                                  DevClock *clock, double *records,
-                                                                  int64_t cap, double t0)
+// One wave per species (blockDim.x = 64 x nspecies): lane l merges the runs
+// l, l + 64, ... of its species in order, then the wave's butterfly; lane 0
+// writes the record.
+__global__ __launch_bounds__(kWave * kMaxSpecies) void fin_records_kernel(
+    FinParams F, const double *__restrict__ chunks, DevClock *clock, double *records,
+    int64_t cap, double t0)
 {
     const double t = clock->t;
     const int64_t idx = clock->nrec;
-    for (int s = 0; s < F.nspecies; ++s) {
-        Moments m{0.0, 0.0, 0.0, 0.0};
-        for (int c = F.chunk_begin[s] + (int)threadIdx.x; c < F.chunk_begin[s + 1]; c += kFinThreads) {
-            const double *q = chunks + 4 * (int64_t)c;
-            m = merge_moments(m, Moments{q[0], q[1], q[2], q[3]});
-        }
-        m = block_merge(m);
-        if (threadIdx.x == 0 && idx < cap) {
-            const double nn = (double)F.count[s];
-            const double mx = m.sx / nn, my = m.sy / nn;
-            const double var = F.count[s] > 1 ? m.m2 / (nn - 1.0) : 0.0;
-            const double el = t - t0;
-            double *r = records + ((int64_t)s * cap + idx) * 8;
-            r[0] = t;
-            r[1] = mx;
-            r[2] = my;
-            r[3] = mx + my;
-            r[4] = el > 0.0 ? mx / (2.0 * el) : 0.0;
-            r[5] = el > 0.0 ? my / (2.0 * el) : 0.0;
-            r[6] = sqrt(var / nn);
-            reinterpret_cast<int64_t *>(r)[7] = F.count[s];
-        }
+    const int s = (int)threadIdx.x / kWave, lane = (int)(threadIdx.x & (kWave - 1));
+    Moments m{0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c = F.chunk_begin[s] + lane; c < F.chunk_begin[s + 1]; c += kWave) {
+        const double *q = chunks + 5 * (int64_t)c;
+        m = merge_moments(m, Moments{q[0], q[1], q[2], q[3], q[4]});
     }
+    m = wave_merge(m);
+    if (lane == 0) write_record(F, s, m, t, t0, idx, records, cap);
+    __syncthreads();   // every wave has read the record index
     if (threadIdx.x == 0) clock->nrec = idx + 1;
 }
 
 int64_t stat_partials_doubles(const StepParams &P, int block)
 {
     const int64_t waves = (int64_t)P.total_blocks * (block / kWave);
-    return (int64_t)kStatTerms * waves + 4 * (waves / kFinChunk + P.nspecies + 1);
+    return (int64_t)kStatTerms * waves + 5 * (waves / kFinChunk + P.nspecies + 1);
 }
 
 hipError_t launch_finalize(const StepParams &P, double *partials, DevClock *clock,
@@ -986,8 +1013,8 @@ hipError_t launch_finalize(const StepParams &P, double *partials, DevClock *cloc
     if (chunks > 0)
         hipLaunchKernelGGL(fin_chunks_kernel, dim3(chunks), dim3(kFinThreads), 0, st, F, partials,
                            chunk_buf);
-    hipLaunchKernelGGL(fin_records_kernel, dim3(1), dim3(kFinThreads), 0, st, F, chunk_buf, clock,
-                       records, rec_cap, t0);
+    hipLaunchKernelGGL(fin_records_kernel, dim3(1), dim3(kWave * P.nspecies), 0, st, F, chunk_buf,
+                       clock, records, rec_cap, t0);
     return hipGetLastError();
 }
 
