@@ -214,12 +214,15 @@ def cpu_baseline(w, budget_s=8.0):
             "one_core_value": d1 / e1}
 
 
-def step_kernel_name(w):
+def step_kernel_name(w, tuning=None):
     schemes = sorted({s[2] for s in w.species})
     inertial = any(k == "inertial" and st > 0 for k, st, _, _, _ in w.species)
     kind = "tracers + inertial" if inertial else "tracers"
     name = f"step{'32' if w.precision == 'fp32_split' else '64'}_kernel"
     if len(w.species) > 1 and w.precision == "fp32_split":
+        if (tuning or {}).get("fused", 1):
+            return (f"{name}<any scheme>, one fused launch over the {len(w.species)} species "
+                    f"({' / '.join(schemes)}, {kind})")
         return (f"{name}, one launch per species ({len(w.species)} per step; "
                 f"{' / '.join(schemes)}, {kind}); times are per step")
     return f"{name}<{' / '.join(schemes)}, {kind}>"
@@ -305,7 +308,7 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False, graph_chu
     ms_step = 1e3 * elapsed / args.steps
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
-            "kernel": step_kernel_name(w), "kernel_avg_us": kern_ms * 1e3,
+            "kernel": step_kernel_name(w, tuning), "kernel_avg_us": kern_ms * 1e3,
             "kernel_launches": timing["step_launches"],
             "note": "kernel = the in-place step without a statistics record; the step "
                     "right after each re-sort is a separate kernel that also applies the "
@@ -608,7 +611,7 @@ def main():
             from paper_2607_17836_amd import autotune
             w = workloads.C4_BATCH
             tuning, ms, hit = autotune.cached_or_tune(
-                w, lpt, workloads, torch.cuda.get_device_name(0),
+                w, lpt, workloads, autotune.device_key(0),
                 log=lambda m: None)
             tuning = dict(tuning, graph_chunk=0)   # per-kernel events need eager launches
             graph_chunk = 100                      # the workload's 100-step graph chunks

@@ -6,7 +6,10 @@ workload by timing candidates with HIP events on a throwaway context of that wor
 coordinate descent from the library defaults.  None of these choices changes
 a per-particle result (see ``lpt_set_tuning``), only the time per step.
 Results are cached in a JSON file keyed by the device, the grid, the
-precision and the species mix.
+precision and the species mix.  The package ships a table of tunings taken
+on MI355X (``tuned_mi355x.json``, written by ``python -m
+paper_2607_17836_amd.autotune <workload> --out <file>``); an entry there is
+used before the user cache and before tuning.
 """
 from __future__ import annotations
 
@@ -14,6 +17,7 @@ import json
 import os
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lpt_tuning.json")
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
 
 SPACE = {
     "block_size": (256, 128, 512),
@@ -25,6 +29,15 @@ SPACE = {
     "fused": (1, 0, 2),
     "sort_cells": (0, 1),
 }
+
+
+def device_key(index: int = 0) -> str:
+    """The device part of a tuning key: the gfx architecture and the compute
+    unit count (stable, unlike the marketing name, which depends on the
+    driver's name table)."""
+    import torch
+    p = torch.cuda.get_device_properties(index)
+    return f"{p.gcnArchName.split(':')[0]}/{p.multi_processor_count}cu"
 
 
 def workload_key(w, device_name: str) -> str:
@@ -41,10 +54,14 @@ def _valid(t, precision):
     return True
 
 
-def tune(w, lpt_mod, workloads_mod, trial_steps=80, rounds=2, log=None):
-    """Coordinate descent over SPACE; returns (best tuning dict, ms per step)."""
+def tune(w, lpt_mod, workloads_mod, trial_steps=80, rounds=2, log=None, warm_steps=200):
+    """Coordinate descent over SPACE, after `warm_steps` steps of the workload
+    (so that the trials see a developed particle distribution, not the
+    initial one); returns (best tuning dict, ms per step)."""
     tr = workloads_mod.build_tracker(w, lpt_mod)
     try:
+        if warm_steps:
+            tr.step(warm_steps, w.dt, w.stats_every)
         best = tr.get_tuning()
         best.update(sort_interval=w.sort_interval or 20, graph_chunk=0, persistent=0,
                     tile_records=0, block_size=256, halo_scale=0.125, fused=1,
@@ -87,11 +104,14 @@ def load_cache(path=None):
 
 
 def cached_or_tune(w, lpt_mod, workloads_mod, device_name, path=None, log=None, **kw):
-    """The cached tuning of a workload on this device, tuning it first if the
-    cache has no entry."""
+    """The shipped or cached tuning of a workload on this device, tuning it
+    first if neither has an entry."""
+    key = workload_key(w, device_name)
+    shipped = load_cache(SHIPPED)
+    if key in shipped:
+        return shipped[key]["tuning"], shipped[key]["ms_per_step"], True
     path = path or os.environ.get("LPT_TUNE_CACHE", DEFAULT_CACHE)
     cache = load_cache(path)
-    key = workload_key(w, device_name)
     if key in cache:
         return cache[key]["tuning"], cache[key]["ms_per_step"], True
     best, ms = tune(w, lpt_mod, workloads_mod, log=log, **kw)
@@ -105,3 +125,26 @@ def cached_or_tune(w, lpt_mod, workloads_mod, device_name, path=None, log=None, 
     except OSError:
         pass
     return best, ms, False
+
+
+if __name__ == "__main__":
+    import argparse
+    import sys
+
+    ap = argparse.ArgumentParser(description="tune one workload of the workloads module on GPU 0 "
+                                 "and add its entry to a tuning table")
+    ap.add_argument("workload", help="name of a Workload in paper_2607_17836_amd.workloads, "
+                    "e.g. C4_BATCH")
+    ap.add_argument("--out", required=True, help="JSON table to add the entry to")
+    a = ap.parse_args()
+    import torch
+
+    from paper_2607_17836_amd import lpt, workloads
+    wl = getattr(workloads, a.workload)
+    dev = device_key(0)
+    best, ms = tune(wl, lpt, workloads, log=lambda m: print(m, flush=True))
+    table = load_cache(a.out)
+    table[workload_key(wl, dev)] = {"tuning": best, "ms_per_step": ms}
+    with open(a.out, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    print(f"{a.workload}: {best} -> {ms * 1e3:.1f} us/step", file=sys.stderr)

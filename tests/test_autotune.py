@@ -1,0 +1,46 @@
+"""Host logic of the launch-shape autotuner: the shipped MI355X tuning table
+is well formed and is used before the user cache and before tuning."""
+import json
+
+import pytest
+
+from paper_2607_17836_amd import autotune, workloads
+
+
+def test_shipped_table_entries_are_valid_tunings():
+    table = json.load(open(autotune.SHIPPED))
+    assert table
+    fields = {"block_size", "tile_records", "sort_interval", "persistent", "graph_chunk",
+              "halo_scale", "max_workgroups", "fused", "sort_cells"}
+    for key, ent in table.items():
+        dev, rest = key.split("|", 1)
+        assert dev.startswith("gfx950/")
+        t = ent["tuning"]
+        assert set(t) == fields
+        for name, values in autotune.SPACE.items():
+            assert t[name] in values, (name, t[name])
+        assert ent["ms_per_step"] > 0
+
+
+def test_shipped_entry_is_used_without_tuning(monkeypatch, tmp_path):
+    w = workloads.C4_BATCH
+    table = json.load(open(autotune.SHIPPED))
+    dev = next(k for k in table if k.split("|", 1)[1] == autotune.workload_key(w, "x").split("|", 1)[1])
+    dev = dev.split("|", 1)[0]
+
+    def no_tuning(*a, **k):
+        raise AssertionError("tuned although the shipped table has the workload")
+
+    monkeypatch.setattr(autotune, "tune", no_tuning)
+    t, ms, hit = autotune.cached_or_tune(w, None, None, dev, path=str(tmp_path / "c.json"))
+    assert hit and t == table[autotune.workload_key(w, dev)]["tuning"]
+
+
+def test_user_cache_is_used_for_other_devices(monkeypatch, tmp_path):
+    w = workloads.C4_BATCH
+    path = tmp_path / "cache.json"
+    key = autotune.workload_key(w, "gfx000/1cu")
+    json.dump({key: {"tuning": {"block_size": 128}, "ms_per_step": 1.0}}, open(path, "w"))
+    monkeypatch.setattr(autotune, "tune", lambda *a, **k: pytest.fail("tuned"))
+    t, ms, hit = autotune.cached_or_tune(w, None, None, "gfx000/1cu", path=str(path))
+    assert hit and t == {"block_size": 128} and ms == 1.0
