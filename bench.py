@@ -82,6 +82,38 @@ def alg_bytes_per_step(w, layout=False) -> float:
     return state + field_pair_bytes(w.n, w.precision)
 
 
+# Vector peaks of MI355X (256 CUs at 2.4 GHz): FP64 128 flop per clock per CU,
+# FP32 256 (with packed FP32; this build's kernels run unpacked FP32, half that).
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def flops_per_particle(scheme: str, inertial: bool) -> int:
+    """Algorithmic flops of one particle-step (an FMA counts 2), from the
+    method's definitions: per RK4 stage, the 1D weights (bilinear: 1 - xi,
+    1 - eta, 2 flops; bicubic: four cubics per axis by Horner, 8 x 3 FMAs),
+    the 2D weight products (4 or 16 multiplies), the tensor sums of the two
+    components at the two time levels (4 x 4 or 4 x 16 FMAs), the temporal
+    blend of the two components (2 x (1 mul + 1 FMA)) and the stage position
+    (2 FMAs); then the RK4 combine (2 x (3 FMAs + 1 mul)) and the
+    displacement update (2 adds).  An inertial particle adds, per stage, the
+    drag (u - v) / St of both components and the stage velocity (2 x
+    (1 sub + 1 mul + 1 FMA)), and the velocity's RK4 combine."""
+    if scheme == "bilinear":
+        stage = 2 + 4 + 4 * 4 * 2 + 2 * 3 + 2 * 2
+    else:
+        stage = 8 * 3 * 2 + 16 + 4 * 16 * 2 + 2 * 3 + 2 * 2
+    per = 4 * stage + 2 * (3 * 2 + 1) + 2
+    if inertial:
+        per += 4 * 2 * (1 + 1 + 2) + 2 * (3 * 2 + 1)
+    return per
+
+
+def alg_flops_per_step(w) -> float:
+    return float(sum(cnt * flops_per_particle(sch, kind == "inertial" and st > 0)
+                     for kind, st, sch, cnt, _ in w.species))
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in sorted(os.listdir(CSRC)):
@@ -330,6 +362,13 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False, graph_chu
             "alg_bytes_per_particle_step": bytes_per_launch / npart,
             "alg_bytes_per_launch": bytes_per_launch,
             "layout_bytes_per_particle_step": alg_bytes_per_step(w, layout=True) / npart}
+    # the arithmetic side of the same kernel time (both fractions, as for the
+    # bicubic FP64 workloads, whose flops per byte approach the FP64 ridge)
+    fl = alg_flops_per_step(w)
+    fpeak = FP64_PEAK_TFLOPS if w.precision == "fp64" else FP32_PEAK_TFLOPS
+    roof["flops"] = {"per_particle_step": fl / npart, "achieved_tflops": fl / (kern_ms * 1e-3) / 1e12,
+                     "peak_tflops": fpeak, "frac": fl / (kern_ms * 1e-3) / 1e12 / fpeak,
+                     "unit": "TFLOP/s", "dtype": "f64" if w.precision == "fp64" else "f32"}
     if graph:
         roof["graph_replays"] = graph
         roof["note"] += ("; value and ms_per_step are the graph-replay run's wall time, the "

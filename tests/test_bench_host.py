@@ -1,5 +1,6 @@
-"""Host-side parts of bench.py's contract (no GPU): the algorithmic bytes per
-particle-step that the roofline divides, and the refusal of multi-GPU runs."""
+"""Host-side parts of bench.py's contract (no GPU): the algorithmic bytes and
+flops per particle-step that the roofline divides, and the refusal of
+multi-GPU runs."""
 import dataclasses
 import os
 import subprocess
@@ -53,3 +54,21 @@ def test_coupled_step_algorithmic_bytes():
     n, m = 2048, 1 << 20
     assert bench.coupled_alg_bytes_per_step(n, m) == (bench.ns_alg_bytes_per_step(n) + 32 * n * n
                                                        + 64 * m + 32 * n * n)
+
+
+def test_flops_per_particle_step_counts():
+    """The arithmetic side of the roofline: an FMA counts 2 flops.  Per stage
+    a bilinear tracer takes 2 (weights) + 4 (2D products) + 32 (two
+    components at two levels, 4 nodes) + 6 (blend) + 4 (stage position); a
+    bicubic one 48 + 16 + 128 + 6 + 4; then the RK4 combine (14) and the
+    displacement (2).  An inertial particle adds 32 per step for the drag
+    and stage velocities and 14 for its velocity combine."""
+    b = bench
+    assert b.flops_per_particle("bilinear", False) == 4 * 48 + 16 == 208
+    assert b.flops_per_particle("catmull_rom", False) == 4 * 202 + 16 == 824
+    assert b.flops_per_particle("bspline", False) == 824
+    assert b.flops_per_particle("bilinear", True) - 208 == 32 + 14
+    w = workloads.C4_BATCH
+    tot = sum(cnt * b.flops_per_particle(sch, kind == "inertial" and st > 0)
+              for kind, st, sch, cnt, _ in w.species)
+    assert b.alg_flops_per_step(w) == tot
