@@ -211,6 +211,39 @@ def test_c2_full_size_sampled(scheme):
     tr.close()
 
 
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_c2_full_size_500_steps_sampled(scheme):
+    """The full 1024^2, 2^20 + 2^20 configuration over its whole 500 steps
+    (re-sorts every 20, a record every 10): the 512 sampled particles per
+    species within 1e-6 of the oracle run on those particles alone, and the
+    last record equal to exact sums of the downloaded displacements of the
+    whole population.  The tolerance follows from the flow's sensitivity:
+    perturbing the oracle's own start positions by 1e-15 (relative) moves
+    its 500-step positions by up to 9e-9 (Catmull-Rom tracers), so rounding
+    differences of a few ulps per step stay well inside 1e-6."""
+    w = workloads.c2_spectrum(scheme)
+    say(f"C2 full 500 steps {w.name} particles={w.particles}")
+    tr = workloads.build_tracker(w, lpt)
+    tr.step(w.steps, w.dt, w.stats_every)
+    ids = np.random.default_rng(98).choice(1 << 20, 512, replace=False)
+    fl, sps = _spectrum_oracle_pair(w, scheme, ids)
+    for sid, sp in enumerate(sps):
+        oracle.run(fl, sp, w.steps, w.dt)
+        xw, yw, xu, yu = tr.get_positions(sid)
+        assert np.max(pdist(xw[ids], sp.xw)) < 1e-6 and np.max(pdist(yw[ids], sp.yw)) < 1e-6
+        x0, y0 = oracle.init_uniform(w.species[sid][4], 1 << 20)
+        dx, dy = xu - x0, yu - y0
+        st = tr.get_stats(sid)
+        assert len(st) == w.steps // w.stats_every
+        mx = math.fsum(dx * dx) / dx.size
+        my = math.fsum(dy * dy) / dy.size
+        assert abs(st[-1]["msd_x"] - mx) <= 1e-12 * mx and abs(st[-1]["msd_y"] - my) <= 1e-12 * my
+        r2 = dx * dx + dy * dy
+        sem = math.sqrt(np.var(r2, ddof=1) / r2.size)
+        assert abs(st[-1]["sem"] - sem) <= 1e-6 * sem
+    tr.close()
+
+
 # --------------------------------------------------------------------------
 # Inertial closed forms on the GPU (Sec. 5.3)
 # --------------------------------------------------------------------------
