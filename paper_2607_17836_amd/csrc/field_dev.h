@@ -463,8 +463,25 @@ __device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec
 {
     const int n = P.n;
     Tile T = block_box(active, cx, cy, ax, ay, n, P.mask, lo, hi);
+    // A box beyond the capacity (a block whose particles have spread since
+    // the last re-sort) is cut down about its centre to a window of the same
+    // shape that fits: the stencils inside it still read LDS, the others
+    // global memory, instead of the whole block losing its tile.  A window
+    // narrower than the widest stencil (4 nodes) is not staged, so every
+    // tile holds at least one whole stencil along each axis.
+    bool fits = true;
+    if (P.tile_cap > 0 && T.w * T.h > P.tile_cap && T.w < n && T.h < n) {
+        const float f = sqrtf((float)P.tile_cap / (float)(T.w * T.h));
+        const int w = max(1, (int)((float)T.w * f));
+        const int h = min(T.h, P.tile_cap / w);
+        T.x0 = wrap_cell(T.x0 + (T.w - w) / 2, n, P.mask);
+        T.y0 = wrap_cell(T.y0 + (T.h - h) / 2, n, P.mask);
+        T.w = w;
+        T.h = h;
+        fits = w >= 4 && h >= 4;
+    }
     const int area = T.w * T.h;
-    T.on = P.tile_cap > 0 && area <= P.tile_cap && T.w < n && T.h < n &&
+    T.on = fits && P.tile_cap > 0 && area <= P.tile_cap && T.w < n && T.h < n &&
            area <= kTileWaste * nactive;
     fill_tile_dma<Rec>(lds, rec0, P, T);
     __syncthreads();

@@ -428,8 +428,8 @@ __device__ __forceinline__ void stage32(const float4 *__restrict__ rec0, const f
 // The first stage sits at the stored position itself: stored cell, in-cell
 // coordinates = the stored offset in [0, 1) (so floor(q) = 0 and the general
 // stage computes the same values).  The stored cell lies inside the block's
-// box, and the tile adds the stencil reach around it, so with a tile the
-// stencil is always inside and no check or fallback is needed.
+// box and the box adds the stencil reach, so the stencil is inside the tile
+// unless the box was cut down to the tile's capacity.
 template <int SCH, bool ONE>
 __device__ __forceinline__ void stage32_first(const float4 *__restrict__ rec0, const float4 *lds,
                                               const Tile &T, const StepParams &P, int cx, int cy,
@@ -441,7 +441,9 @@ __device__ __forceinline__ void stage32_first(const float4 *__restrict__ rec0, c
         stage32<SCH>(rec0, lds, T, P, cx, cy, rx, ry, o.x, o.y, ONE, h, wa, wb, u, v);
         return;
     }
-    if (T.on)
+    constexpr int span = SCH == kBilinear ? 2 : 4;
+    if (T.on && (unsigned)(rx - c1) <= (unsigned)(T.w - span) &&
+        (unsigned)(ry - c1) <= (unsigned)(T.h - span))
         eval32<SCH>(tile_nodes(lds, T, rx - c1, ry - c1), o.x, o.y, ONE, h, wa, wb, u, v);
     else
         eval32<SCH>(global_nodes(rec0, P, cx - c1, cy - c1), o.x, o.y, ONE, h, wa, wb, u, v);
