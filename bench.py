@@ -66,9 +66,12 @@ def state_bytes(precision: str, kind: str, st: float) -> int:
 
 
 def layout_state_bytes(precision: str, kind: str, st: float) -> int:
-    """Bytes the library's own layout moves: the FP32-split cell pair is
-    packed into one 32-bit word (cy << 16 | cx)."""
-    return state_bytes(precision, kind, st) - (4 if precision == "fp32_split" else 0)
+    """Bytes the library's own layout moves: the FP32-split state keeps the
+    unwrapped cell pair (two int32) and the binary32 offsets, from which the
+    displacement follows exactly, so it stores no FP64 displacement."""
+    if precision == "fp32_split":
+        return state_bytes(precision, kind, st) - 16
+    return state_bytes(precision, kind, st)
 
 
 def field_pair_bytes(n: int, precision: str) -> int:

@@ -121,7 +121,19 @@ __device__ __forceinline__ double2 ld_stream(const double2 *p)
     const f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p));
     return make_double2(v.x, v.y);
 }
+__device__ __forceinline__ int2 ld_stream(const int2 *p)
+{
+    typedef int i32x2 __attribute__((ext_vector_type(2)));
+    const i32x2 v = __builtin_nontemporal_load(reinterpret_cast<const i32x2 *>(p));
+    return make_int2(v.x, v.y);
+}
 __device__ __forceinline__ void st_stream(uint32_t *p, uint32_t v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_stream(int2 *p, int2 v)
+{
+    typedef int i32x2 __attribute__((ext_vector_type(2)));
+    i32x2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<i32x2 *>(p));
+}
 __device__ __forceinline__ void st_stream(float2 *p, float2 v)
 {
     f32x2 w = {v.x, v.y};

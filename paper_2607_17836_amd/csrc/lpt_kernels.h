@@ -106,15 +106,20 @@ struct State64 {
     uint32_t *id;      // global particle index (species offset + local index)
 };
 
-// FP32 split state: integer periodic cell packed as (cy << 16) | cx, binary32
-// offset in [0, 1) cell units, binary64 displacement (physical units),
-// binary32 velocity in cells per unit time.
+// FP32 split state: the unwrapped integer cell (x, y) -- the stored cell is
+// its residue mod n -- and the binary32 offset in [0, 1) cell units, so that
+// the position unwrapped since initialisation is (uc + off) h exactly and no
+// displacement is stored; binary32 velocity in cells per unit time.  16 bytes
+// a tracer, 24 an inertial particle, read and written once a step; the id is
+// moved only by the step after a re-sort.  x0: the initial positions by
+// original index (binary64, read by record steps and readout: the
+// displacement is (uc + off) - split(x0), in cells).
 struct State32 {
-    uint32_t *cell;
+    int2 *uc;
     float2 *off;
-    double2 *disp;
     float2 *vel;
     uint32_t *id;
+    const double2 *x0;
 };
 
 // Snapshot records: both time levels of one node side by side.
@@ -185,9 +190,9 @@ hipError_t launch_interp32(const StepParams &P, const float4 *rec, int scheme, i
 hipError_t launch_readout64(const State64 &S, const double2 *x0, int64_t offset, int64_t count,
                             double L, double *xw, double *yw, double *xu, double *yu,
                             double *vx, double *vy, hipStream_t st);
-hipError_t launch_readout32(const State32 &S, const double2 *x0, int64_t offset, int64_t count,
-                            double h, double *xw, double *yw, double *xu, double *yu,
-                            double *vx, double *vy, hipStream_t st);
+hipError_t launch_readout32(const StepParams &P, const State32 &S, int64_t offset, int64_t count,
+                            double *xw, double *yw, double *xu, double *yu, double *vx,
+                            double *vy, hipStream_t st);
 
 hipError_t launch_order(const uint32_t *id, int64_t offset, int64_t count, int32_t *out,
                         hipStream_t st);

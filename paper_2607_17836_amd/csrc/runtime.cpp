@@ -220,9 +220,8 @@ void free_state(lpt_ctx *c)
         dfree(c->s64[k].disp);
         dfree(c->s64[k].vel);
         dfree(c->s64[k].id);
-        dfree(c->s32[k].cell);
+        dfree(c->s32[k].uc);
         dfree(c->s32[k].off);
-        dfree(c->s32[k].disp);
         dfree(c->s32[k].vel);
         dfree(c->s32[k].id);
     }
@@ -732,8 +731,7 @@ lpt_status grow_state(lpt_ctx *c, int64_t np, int64_t old, bool inertial)
     auto cleanup = [&]() {
         for (int k = 0; k < 2; ++k) {
             dfree(n64[k].pos); dfree(n64[k].disp); dfree(n64[k].vel); dfree(n64[k].id);
-            dfree(n32[k].cell); dfree(n32[k].off); dfree(n32[k].disp); dfree(n32[k].vel);
-            dfree(n32[k].id);
+            dfree(n32[k].uc); dfree(n32[k].off); dfree(n32[k].vel); dfree(n32[k].id);
         }
         dfree(nx0);
         dfree(nv0);
@@ -746,8 +744,8 @@ lpt_status grow_state(lpt_ctx *c, int64_t np, int64_t old, bool inertial)
                  dalloc(n64[k].id, np) == hipSuccess &&
                  (!vel || dalloc(n64[k].vel, np) == hipSuccess);
         } else {
-            ok = dalloc(n32[k].cell, np) == hipSuccess && dalloc(n32[k].off, np) == hipSuccess &&
-                 dalloc(n32[k].disp, np) == hipSuccess && dalloc(n32[k].id, np) == hipSuccess &&
+            ok = dalloc(n32[k].uc, np) == hipSuccess && dalloc(n32[k].off, np) == hipSuccess &&
+                 dalloc(n32[k].id, np) == hipSuccess &&
                  (!vel || dalloc(n32[k].vel, np) == hipSuccess);
         }
     }
@@ -770,9 +768,8 @@ lpt_status grow_state(lpt_ctx *c, int64_t np, int64_t old, bool inertial)
             cp(n64[k].vel, c->s64[k].vel, old * sizeof(double2));
             cp(n64[k].id, c->s64[k].id, old * sizeof(uint32_t));
         } else {
-            cp(n32[k].cell, c->s32[k].cell, old * sizeof(uint32_t));
+            cp(n32[k].uc, c->s32[k].uc, old * sizeof(int2));
             cp(n32[k].off, c->s32[k].off, old * sizeof(float2));
-            cp(n32[k].disp, c->s32[k].disp, old * sizeof(double2));
             cp(n32[k].vel, c->s32[k].vel, old * sizeof(float2));
             cp(n32[k].id, c->s32[k].id, old * sizeof(uint32_t));
         }
@@ -793,6 +790,7 @@ lpt_status grow_state(lpt_ctx *c, int64_t np, int64_t old, bool inertial)
     }
     c->x0 = nx0;
     c->v0 = nv0;
+    c->s32[0].x0 = c->s32[1].x0 = nx0;   // the split state's displacement reference
     return LPT_OK;
 }
 
@@ -1504,7 +1502,7 @@ lpt_status readout(lpt_ctx *c, int32_t sid, double *xw, double *yw, double *xu, 
         HIP_TRY(c, launch_readout64(c->s64[c->cur], c->x0, s.offset, s.count, c->L, dev[0], dev[1],
                                     dev[2], dev[3], dev[4], dev[5], c->stream));
     else
-        HIP_TRY(c, launch_readout32(c->s32[c->cur], c->x0, s.offset, s.count, c->h, dev[0],
+        HIP_TRY(c, launch_readout32(make_params(c), c->s32[c->cur], s.offset, s.count, dev[0],
                                     dev[1], dev[2], dev[3], dev[4], dev[5], c->stream));
     if (!on_device) {
         for (int k = 0; k < 6; ++k)
@@ -1783,7 +1781,7 @@ std::vector<size_t> state_arrays(const lpt_ctx *c)
         a = {np * sizeof(double2), np * sizeof(double2)};
         if (c->has_inertial) a.push_back(np * sizeof(double2));
     } else {
-        a = {np * sizeof(uint32_t), np * sizeof(float2), np * sizeof(double2)};
+        a = {np * sizeof(int2), np * sizeof(float2)};
         if (c->has_inertial) a.push_back(np * sizeof(float2));
     }
     a.push_back(np * sizeof(uint32_t));                    // id (slot -> particle)
@@ -1800,7 +1798,7 @@ std::vector<void *> state_ptrs(lpt_ctx *c, int k)
         if (c->has_inertial) p.push_back(c->s64[k].vel);
         p.push_back(c->s64[k].id);
     } else {
-        p = {c->s32[k].cell, c->s32[k].off, c->s32[k].disp};
+        p = {c->s32[k].uc, c->s32[k].off};
         if (c->has_inertial) p.push_back(c->s32[k].vel);
         p.push_back(c->s32[k].id);
     }
@@ -1833,7 +1831,7 @@ lpt_status lpt_get_state(lpt_ctx *c, void *blob, size_t cap, size_t *size)
     char *out = static_cast<char *>(blob);
     StateHeader h{};
     std::memcpy(h.magic, kStateMagic, 8);
-    h.version = 1;
+    h.version = 2;   // 2: FP32-split state as unwrapped cells + offsets
     h.n = c->n;
     h.precision = c->precision;
     h.nspecies = (int32_t)c->sp.size();
@@ -1876,7 +1874,7 @@ lpt_status lpt_set_state(lpt_ctx *c, const void *blob, size_t size)
     const char *in = static_cast<const char *>(blob);
     StateHeader h;
     std::memcpy(&h, in, sizeof h);
-    if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1)
+    if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 2)
         return fail(c, LPT_E_ARG, "not an lpt state blob");
     if (h.n != c->n || h.precision != c->precision || h.nspecies != (int32_t)c->sp.size() ||
         h.np != c->np || h.has_vel != (c->has_inertial ? 1 : 0))

@@ -49,6 +49,14 @@ __device__ __forceinline__ int cell_of_pos(double x, double invh, int n)
     return ci;
 }
 
+// The stored cell of an unwrapped cell coordinate: its residue in [0, n).
+__device__ __forceinline__ int stored_cell(int u, int n, int mask)
+{
+    if (mask >= 0) return u & mask;
+    int c = u % n;
+    return c < 0 ? c + n : c;
+}
+
 __device__ __forceinline__ int species_of_particle(const StepParams &P, int64_t p)
 {
     int s = 0;
@@ -197,24 +205,22 @@ __global__ __launch_bounds__(kSortThreads) void keys32_kernel(StepParams P, Stat
 {
     keys_tile<K>(
         [&](int64_t i0, int cnt, uint32_t *k) {
-            uint32_t c[kItems];
+            int2 c[kItems];   // unwrapped cells; the stored cell is their residue mod n
             if (cnt == kItems) {
 #pragma unroll
-                for (int j = 0; j < kItems; j += 4) {
-                    const uint4 q = *reinterpret_cast<const uint4 *>(S.cell + i0 + j);
-                    c[j] = q.x;
-                    c[j + 1] = q.y;
-                    c[j + 2] = q.z;
-                    c[j + 3] = q.w;
+                for (int j = 0; j < kItems; j += 2) {
+                    const int4 q = *reinterpret_cast<const int4 *>(S.uc + i0 + j);
+                    c[j] = make_int2(q.x, q.y);
+                    c[j + 1] = make_int2(q.z, q.w);
                 }
             } else {
 #pragma unroll
-                for (int j = 0; j < kItems; ++j) c[j] = j < cnt ? S.cell[i0 + j] : 0u;
+                for (int j = 0; j < kItems; ++j) c[j] = j < cnt ? S.uc[i0 + j] : make_int2(0, 0);
             }
 #pragma unroll
             for (int j = 0; j < kItems; ++j)
-                k[j] = tile_key((int)(c[j] & 0xFFFFu), (int)(c[j] >> 16), P.n, tile_shift,
-                                tile_bits, cells, species_of_particle(P, i0 + j));
+                k[j] = tile_key(stored_cell(c[j].x, P.n, P.mask), stored_cell(c[j].y, P.n, P.mask),
+                                P.n, tile_shift, tile_bits, cells, species_of_particle(P, i0 + j));
         },
         total, keys, mask, hist, ntiles);
 }
@@ -514,9 +520,8 @@ __global__ void permute32_kernel(State32 src, State32 dst, const uint32_t *__res
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const uint32_t q = perm[p];
-    dst.cell[p] = src.cell[q];
+    dst.uc[p] = src.uc[q];
     dst.off[p] = src.off[q];
-    dst.disp[p] = src.disp[q];
     dst.id[p] = src.id[q];
     if (with_vel) dst.vel[p] = src.vel[q];
 }

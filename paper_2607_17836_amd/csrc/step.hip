@@ -259,14 +259,52 @@ __device__ __forceinline__ void vel32(const float4 *__restrict__ rec0, const flo
 
 // New (cell, offset) after a displacement of dq cells from offset o; the
 // offset stays in [0, 1) (fract never returns 1).
-__device__ __forceinline__ void advance_split(int &c, float &o, float dq, const StepParams &P)
+__device__ __forceinline__ int advance_split(int &c, float &o, float dq, const StepParams &P)
 {
     const float q = o + dq;
-    const float f = floorf(q);
+    const float f = __builtin_amdgcn_fmed3f(floorf(q), -kCellClampF, kCellClampF);
     float r = __builtin_amdgcn_fractf(q);
     if (!(r >= 0.0f)) r = 0.0f;   // NaN guard keeps the state in range
-    c = cell_plus(c, f, P.n, P.mask);
+    const int m = (int)f;         // the cell move (0 for NaN)
+    c = wrap_cell(c + m, P.n, P.mask);
     o = r;
+    return m;
+}
+
+// Unwrapped cell plus a move, wrapping modulo 2^32 (moves are clamped, so
+// only an absurd state, never a real trajectory, gets there).
+__device__ __forceinline__ int ucell_plus(int u, int m)
+{
+    return (int)((uint32_t)u + (uint32_t)m);
+}
+
+// Split form of a binary64 position: the cell floor(x n / L) in [0, n) and the
+// binary32 offset in [0, 1) (the initial state of a particle).
+__device__ __forceinline__ void split_of(double x, const StepParams &P, int &c, float &o)
+{
+    const double s = x * P.invh;
+    const double f = floor(s);
+    float r = (float)(s - f);
+    int ci = cell_of_floor(f, P.n, P.mask);
+    if (r >= 1.0f) {
+        r = 0.0f;
+        ci = wrap_cell(ci + 1, P.n, P.mask);
+    }
+    if (!(r >= 0.0f)) r = 0.0f;
+    c = ci;
+    o = r;
+}
+
+// Displacement since initialisation (physical units) of a particle at
+// unwrapped cell u, offset o, that started at x0.
+__device__ __forceinline__ double2 split_disp(int2 u, float2 o, double2 x0, const StepParams &P)
+{
+    int cx, cy;
+    float ox, oy;
+    split_of(x0.x, P, cx, ox);
+    split_of(x0.y, P, cy, oy);
+    return make_double2(((double)(int)((uint32_t)u.x - (uint32_t)cx) + ((double)o.x - (double)ox)) * P.h,
+                        ((double)(int)((uint32_t)u.y - (uint32_t)cy) + ((double)o.y - (double)oy)) * P.h);
 }
 
 // ---------------------------------------------------------------------------
@@ -459,11 +497,9 @@ template <int SCH, bool INERT, bool ONE, bool GATHER>
 __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S,
                                            const State32 &D, const float4 *__restrict__ rec0,
                                            const float4 *lds, const Tile &T, const SpeciesDev &sp,
-                                           int64_t p, int64_t q, uint32_t &cell, float2 o,
-                                           double &r2x, double &r2y)
+                                           int64_t p, int64_t q, uint32_t cell, int2 &uc,
+                                           float2 &o)
 {
-    double2 d = make_double2(0.0, 0.0);
-    if constexpr (GATHER) d = ld_stream(S.disp + q);
     int cx = (int)(cell & 0xFFFFu), cy = (int)(cell >> 16);
     int rx = 0, ry = 0;
     if (T.on) {   // cx - T.x0 lies in (-n, n)
@@ -512,17 +548,12 @@ __device__ __forceinline__ void particle32(const StepParams &P, const State32 &S
         dqy = dt6 * (k1y + 2.0f * k2y + 2.0f * k3y + k4y);
     }
     float ox = o.x, oy = o.y;
-    advance_split(cx, ox, dqx, P);
-    advance_split(cy, oy, dqy, P);
-    if constexpr (!GATHER) d = ld_stream(S.disp + q);
-    cell = (uint32_t)cx | ((uint32_t)cy << 16);
-    st_stream(D.cell + p, cell);
-    st_stream(D.off + p, make_float2(ox, oy));
-    d.x += (double)dqx * P.h;
-    d.y += (double)dqy * P.h;
-    st_stream(D.disp + p, d);
-    r2x = d.x * d.x;
-    r2y = d.y * d.y;
+    const int mx = advance_split(cx, ox, dqx, P);
+    const int my = advance_split(cy, oy, dqy, P);
+    uc = make_int2(ucell_plus(uc.x, mx), ucell_plus(uc.y, my));
+    o = make_float2(ox, oy);
+    st_stream(D.uc + p, uc);
+    st_stream(D.off + p, o);
 }
 
 // The particle body for the block's kind.  SCHS: the scheme of every species
@@ -535,26 +566,24 @@ __device__ __forceinline__ void particle_dispatch(const StepParams &P, const Sta
                                                   const float4 *__restrict__ rec0,
                                                   const float4 *lds, const Tile &T,
                                                   const SpeciesDev &sp, int64_t p, int64_t q,
-                                                  uint32_t &cell, float2 o, double &r2x,
-                                                  double &r2y)
+                                                  uint32_t cell, int2 &uc, float2 &o)
 {
     if constexpr (SCHS == kAnyScheme) {   // fused launch: the block's species decides
         if (sp.scheme == kBilinear)
             particle_dispatch<kBilinear, KINDS, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell,
-                                                             o, r2x, r2y);
+                                                             uc, o);
         else if (sp.scheme == kCatmullRom)
             particle_dispatch<kCatmullRom, KINDS, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q,
-                                                               cell, o, r2x, r2y);
+                                                               cell, uc, o);
         else
             particle_dispatch<kBSpline, KINDS, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell,
-                                                            o, r2x, r2y);
+                                                            uc, o);
         return;
     }
     if (KINDS != 0 && sp.inertial)
-        particle32<SCHS, KINDS != 0, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x,
-                                                  r2y);
+        particle32<SCHS, KINDS != 0, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, uc, o);
     else
-        particle32<SCHS, false, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, o, r2x, r2y);
+        particle32<SCHS, false, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, uc, o);
 }
 
 // One logical block of the step.  The state of slot p is read from S and
@@ -578,12 +607,14 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
     double r2x = 0.0, r2y = 0.0;
 
     int64_t q = p;
-    uint32_t cell = 0;
+    uint32_t cell = 0;   // the stored cell, (cy << 16) | cx
+    int2 uc = make_int2(0, 0);
     float2 o = make_float2(0.f, 0.f);
     if (active) {
         if (GATHER) q = perm[p];
-        cell = ld_stream(S.cell + q);
+        uc = ld_stream(S.uc + q);
         o = ld_stream(S.off + q);
+        cell = (uint32_t)wrapn(uc.x, P) | ((uint32_t)wrapn(uc.y, P) << 16);
     }
     Tile T = no_tile();
     if (P.tile_cap > 0) {
@@ -593,18 +624,26 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
         const int64_t left = sp.count - base;
         const int nact = (int)(left < (int64_t)blockDim.x ? left : blockDim.x);
         const int64_t a0 = sp.offset + base;
-        const uint32_t a = S.cell[GATHER ? (int64_t)perm[a0] : a0];
+        const int2 a = S.uc[GATHER ? (int64_t)perm[a0] : a0];
         T = stage_tile<float4>(lds, rec0, P, active, (int)(cell & 0xFFFFu), (int)(cell >> 16),
-                               (int)(a & 0xFFFFu), (int)(a >> 16), lo + H, hi + H, nact);
+                               wrapn(a.x, P), wrapn(a.y, P), lo + H, hi + H, nact);
     }
     if (active) {
         if (P.ends_one)
-            particle_dispatch<SCHS, KINDS, true, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, o,
-                                                         r2x, r2y);
+            particle_dispatch<SCHS, KINDS, true, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, uc,
+                                                         o);
         else
-            particle_dispatch<SCHS, KINDS, false, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, o,
-                                                          r2x, r2y);
-        if (GATHER) D.id[p] = S.id[q];
+            particle_dispatch<SCHS, KINDS, false, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell,
+                                                          uc, o);
+        if (GATHER || STATS) {
+            const uint32_t g = S.id[q];
+            if (GATHER) D.id[p] = g;
+            if (STATS) {   // the displacement since initialisation, from the new state
+                const double2 d = split_disp(uc, o, S.x0[g], P);
+                r2x = d.x * d.x;
+                r2y = d.y * d.y;
+            }
+        }
     }
     if (STATS)
         wave_stats(r2x, r2y, active,
@@ -1177,21 +1216,6 @@ __global__ void init64_kernel(StepParams P, State64 S, const double2 *__restrict
     }
 }
 
-__device__ __forceinline__ void split_of(double x, const StepParams &P, int &c, float &o)
-{
-    const double s = x * P.invh;
-    const double f = floor(s);
-    float r = (float)(s - f);
-    int ci = cell_of_floor(f, P.n, P.mask);
-    if (r >= 1.0f) {
-        r = 0.0f;
-        ci = wrap_cell(ci + 1, P.n, P.mask);
-    }
-    if (!(r >= 0.0f)) r = 0.0f;
-    c = ci;
-    o = r;
-}
-
 __global__ void init32_kernel(StepParams P, State32 S, const double2 *__restrict__ x0,
                               const double2 *__restrict__ v0, const float4 *__restrict__ rec,
                               int species, int64_t begin, int64_t count, double wa, double wb,
@@ -1206,9 +1230,8 @@ __global__ void init32_kernel(StepParams P, State32 S, const double2 *__restrict
     float ox, oy;
     split_of(x.x, P, cx, ox);
     split_of(x.y, P, cy, oy);
-    S.cell[p] = (uint32_t)cx | ((uint32_t)cy << 16);
+    S.uc[p] = make_int2(cx, cy);
     S.off[p] = make_float2(ox, oy);
-    S.disp[p] = make_double2(0.0, 0.0);
     S.id[p] = (uint32_t)p;
     if (sp.inertial) {
         if (vel_from_field) {
@@ -1376,9 +1399,9 @@ __global__ void readout64_kernel(State64 S, const double2 *__restrict__ x0, int6
     }
 }
 
-__global__ void readout32_kernel(State32 S, const double2 *__restrict__ x0, int64_t offset,
-                                 int64_t count, double h, double *xw, double *yw, double *xu,
-                                 double *yu, double *vx, double *vy)
+__global__ void readout32_kernel(StepParams P, State32 S, int64_t offset, int64_t count,
+                                 double *xw, double *yw, double *xu, double *yu, double *vx,
+                                 double *vy)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= count) return;
@@ -1386,20 +1409,20 @@ __global__ void readout32_kernel(State32 S, const double2 *__restrict__ x0, int6
     const uint32_t g = S.id[p];
     const int64_t q = (int64_t)g - offset;
     if (q < 0 || q >= count) return;
-    const uint32_t c = S.cell[p];
+    const int2 u = S.uc[p];
     const float2 o = S.off[p];
-    if (xw) xw[q] = ((double)(c & 0xFFFFu) + (double)o.x) * h;
-    if (yw) yw[q] = ((double)(c >> 16) + (double)o.y) * h;
+    if (xw) xw[q] = ((double)wrap_cell(u.x, P.n, P.mask) + (double)o.x) * P.h;
+    if (yw) yw[q] = ((double)wrap_cell(u.y, P.n, P.mask) + (double)o.y) * P.h;
     if (xu || yu) {
-        const double2 d = S.disp[p];
-        const double2 a = x0[g];
+        const double2 a = S.x0[g];
+        const double2 d = split_disp(u, o, a, P);
         if (xu) xu[q] = a.x + d.x;
         if (yu) yu[q] = a.y + d.y;
     }
     if (vx || vy) {
         const float2 w = S.vel[p];
-        if (vx) vx[q] = (double)w.x * h;
-        if (vy) vy[q] = (double)w.y * h;
+        if (vx) vx[q] = (double)w.x * P.h;
+        if (vy) vy[q] = (double)w.y * P.h;
     }
 }
 
@@ -1415,14 +1438,14 @@ hipError_t launch_readout64(const State64 &S, const double2 *x0, int64_t offset,
     return hipGetLastError();
 }
 
-hipError_t launch_readout32(const State32 &S, const double2 *x0, int64_t offset, int64_t count,
-                            double h, double *xw, double *yw, double *xu, double *yu,
-                            double *vx, double *vy, hipStream_t st)
+hipError_t launch_readout32(const StepParams &P, const State32 &S, int64_t offset, int64_t count,
+                            double *xw, double *yw, double *xu, double *yu, double *vx,
+                            double *vy, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
     const int b = 256;
     hipLaunchKernelGGL(readout32_kernel, dim3((unsigned)((count + b - 1) / b)), dim3(b), 0, st,
-                       S, x0, offset, count, h, xw, yw, xu, yu, vx, vy);
+                       P, S, offset, count, xw, yw, xu, yu, vx, vy);
     return hipGetLastError();
 }
 

@@ -15,10 +15,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_algorithmic_bytes_per_particle_step():
     # 2 x 32 B of split state (int32 cell pair 8, binary32 offsets 8, FP64
     # displacement 16) plus the 4096^2 x 16 B field pair read once, shared by
-    # the particles: 80 B; the library's packed cell word moves 72 B
+    # the particles: 80 B; the library's state (unwrapped cells and offsets,
+    # no stored displacement) moves 2 x 16 + 16 = 48 B
     w = workloads.C3_SPLIT
     assert bench.alg_bytes_per_step(w) / w.particles == 2 * 32 + 4096 ** 2 * 16 / 2 ** 24 == 80.0
-    assert bench.alg_bytes_per_step(w, layout=True) / w.particles == 72.0
+    assert bench.alg_bytes_per_step(w, layout=True) / w.particles == 48.0
     s = workloads.C3_SHARE8
     assert bench.alg_bytes_per_step(s) / s.particles == 2 * 32 + 4096 ** 2 * 16 / 2 ** 21 == 192.0
     d = dataclasses.replace(w, precision="fp64")
