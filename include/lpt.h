@@ -60,8 +60,11 @@ typedef enum { LPT_BILINEAR = 0, LPT_CATMULL_ROM = 1, LPT_BSPLINE = 2 } lpt_sche
 
 /* LPT_FP64: fields, positions and all arithmetic in binary64.
  * LPT_FP32_SPLIT: fields and interpolation in binary32; a position is an
- * integer periodic cell plus a binary32 offset in cell units; velocities are
- * binary32; unwrapped displacements and the statistics stay binary64. */
+ * unwrapped integer cell (its residue mod n is the periodic cell) plus a
+ * binary32 offset in cell units, so the unwrapped displacement is that
+ * position minus the split form of the initial one, formed in binary64 with
+ * the offset's resolution (about 6e-8 cells) however far the particle has
+ * gone; velocities are binary32; the statistics are binary64. */
 typedef enum { LPT_FP64 = 0, LPT_FP32_SPLIT = 1 } lpt_precision;
 
 typedef enum { LPT_TRACER = 0, LPT_INERTIAL = 1 } lpt_kind;
