@@ -295,12 +295,16 @@ typedef struct {
                                cell order (2); 0: one launch per species
                                (LPT_FP32_SPLIT) or one launch in species
                                order (LPT_FP64)                               */
-    int32_t sort_cells;     /* 1: the re-sort key orders the cells inside each
-                               T x T tile too (row-major), so that neighbouring
-                               slots sit in neighbouring cells; the key grows
-                               by 2 log2 T bits and must stay within 32 bits
-                               (else LPT_E_ARG); 0 (default): tiles only, ties
-                               keep their order                               */
+    int32_t sort_cells;     /* 1: every re-sort key orders the cells inside
+                               each T x T tile too (row-major), so that
+                               neighbouring slots sit in neighbouring cells;
+                               the key grows by 2 log2 T bits and must stay
+                               within 32 bits (else LPT_E_ARG); 0: tiles only,
+                               ties keep their order; 2 (default): cells on
+                               the first re-sort after the particles are
+                               placed (where the key fits), tiles after it --
+                               the later tile sorts, being stable, keep most
+                               of that order                                 */
 } lpt_tuning;
 
 lpt_status lpt_get_tuning(lpt_ctx *ctx, lpt_tuning *out);

@@ -27,7 +27,7 @@ SPACE = {
     "graph_chunk": (0, 100),
     "halo_scale": (0.125, 0.25, 0.5, 1.0),
     "fused": (1, 0, 2),
-    "sort_cells": (0, 1),
+    "sort_cells": (2, 0, 1),
 }
 
 
@@ -65,7 +65,7 @@ def tune(w, lpt_mod, workloads_mod, trial_steps=80, rounds=2, log=None, warm_ste
         best = tr.get_tuning()
         best.update(sort_interval=w.sort_interval or 20, graph_chunk=0, persistent=0,
                     tile_records=0, block_size=256, halo_scale=0.125, fused=1,
-                    max_workgroups=0, sort_cells=0)
+                    max_workgroups=0, sort_cells=2)
 
         def measure(t):
             tr.set_tuning(**t)

@@ -98,7 +98,9 @@ struct lpt_ctx {
     int32_t block = 256;
     int32_t sort_interval = 0;
     int32_t sort_tile = 16;
-    int32_t sort_cells = 0;  // 1: the key also orders cells inside each tile
+    int32_t sort_cells = 2;  // 1: the key also orders cells inside each tile; 2: on
+                             // the first re-sort only
+    bool sorted_once = false;   // a re-sort has put the present particles in order
     int32_t tile_cap = 0;    // LDS tile capacity of the step kernel, node records
     int32_t tile_auto = 0;   // 1: step launches size the tile to their occupancy
                              // (tile_cap is then the adjoint kernels' capacity)
@@ -113,8 +115,9 @@ struct lpt_ctx {
     int32_t order_len = 0;      // entries per XCD list
     bool order_ok = false;      // the table matches the species and block size
     // executable graphs of step chunks, keyed by (step phase, state buffer,
-    // chunk length, dt bits, stats_every, buffer epoch)
-    std::map<std::tuple<int64_t, int, int64_t, uint64_t, int32_t, uint64_t>, hipGraphExec_t> graphs;
+    // chunk length, dt bits, stats_every, buffer epoch, first re-sort done)
+    std::map<std::tuple<int64_t, int, int64_t, uint64_t, int32_t, uint64_t, bool>, hipGraphExec_t>
+        graphs;
     uint64_t epoch = 0;      // bumped whenever a buffer a graph may hold changes
     hipStream_t own_stream = nullptr;   // capture stream when the context uses the null stream
     bool compat_edge = false;
@@ -404,8 +407,12 @@ lpt_status do_sort(lpt_ctx *c, const uint32_t **perm_out = nullptr,
     if (c->time_kernels) HIP_TRY(c, mark(c, e0));
     const StepParams P = make_params(c);
     const int tb = tile_bits(c);
-    const int kb = std::max(1, key_width(c->n, c->sort_tile, c->sort_cells, (int)c->sp.size()));
-    const bool cells = c->sort_cells != 0;
+    // the cell-inside-tile key on every re-sort (1), or on the first one (2),
+    // where it fits in 32 bits; tiles only otherwise
+    bool cells = c->sort_cells == 1 || (c->sort_cells == 2 && !c->sorted_once);
+    if (cells && key_width(c->n, c->sort_tile, 1, (int)c->sp.size()) > 32) cells = false;
+    c->sorted_once = true;
+    const int kb = std::max(1, key_width(c->n, c->sort_tile, cells, (int)c->sp.size()));
     if (c->precision == LPT_FP64)
         HIP_TRY(c, launch_keys64(P, c->s64[c->cur], c->sort_tile, tb, cells, kb, c->sw,
                                  c->stream));
@@ -707,6 +714,7 @@ namespace {
 
 lpt_status init_species_state(lpt_ctx *c, int sid)
 {
+    c->sorted_once = false;   // new positions: the next re-sort starts from scratch
     const StepParams P = make_params(c);
     const SpeciesHost &s = c->sp[sid];
     double wa = 1.0, wb = 0.0;
@@ -754,6 +762,33 @@ lpt_status grow_state(lpt_ctx *c, int64_t np, int64_t old, bool inertial)
         cleanup();
         (void)hipGetLastError();
         return fail(c, LPT_E_NOMEM, "device allocation of the particle state failed");
+    }
+    {
+        // touch every page of both state buffers now, so that the first
+        // steps (whose re-sort writes the other buffer) meet no first-touch
+        // cost
+        hipError_t e = hipSuccess;
+        auto z = [&](void *d, size_t bytes) {
+            if (e == hipSuccess && d) e = hipMemsetAsync(d, 0, bytes, c->stream);
+        };
+        const size_t n = (size_t)np;
+        for (int k = 0; k < 2; ++k) {
+            if (fp64) {
+                z(n64[k].pos, n * sizeof(double2));
+                z(n64[k].disp, n * sizeof(double2));
+                z(n64[k].vel, n * sizeof(double2));
+                z(n64[k].id, n * sizeof(uint32_t));
+            } else {
+                z(n32[k].uc, n * sizeof(int2));
+                z(n32[k].off, n * sizeof(float2));
+                z(n32[k].vel, n * sizeof(float2));
+                z(n32[k].id, n * sizeof(uint32_t));
+            }
+        }
+        if (e != hipSuccess) {
+            cleanup();
+            return fail(c, LPT_E_HIP, std::string("state clear: ") + hipGetErrorString(e));
+        }
     }
     if (old > 0) {
         const int k = c->cur;
@@ -815,7 +850,7 @@ lpt_status lpt_add_species(lpt_ctx *c, lpt_kind kind, double st, lpt_scheme sche
     if (inertial && !vx0 && !(c->slot_set[0] && c->slot_set[1]))
         return fail(c, LPT_E_STATE, "v0 from the field needs both snapshots set");
     int32_t nsp = (int32_t)c->sp.size() + 1;
-    if (key_width(c->n, c->sort_tile, c->sort_cells, nsp) > 32)
+    if (key_width(c->n, c->sort_tile, c->sort_cells == 1, nsp) > 32)
         return fail(c, LPT_E_ARG, "sort key wider than 32 bits; raise sort_tile");
     HIP_TRY(c, hipSetDevice(c->device));
 
@@ -972,6 +1007,7 @@ lpt_status run_steps(lpt_ctx *c, int64_t nsteps, double dt, int32_t stats_every,
                 if (s != LPT_OK) return s;
             } else if (c->np > 1) {
                 c->cur = 1 - c->cur;   // where the sort leaves the host state
+                c->sorted_once = true;
             }
         }
         if (ckpt && k % c->ck_every == 0) {
@@ -1096,8 +1132,9 @@ lpt_status run_graph_chunks_on(lpt_ctx *c, int64_t nsteps, double dt, int32_t st
     std::memcpy(&dt_bits, &dt, sizeof dt_bits);
     while (nsteps > 0) {
         const int64_t len = std::min<int64_t>(c->graph_chunk, nsteps);
+        // the first re-sort may use another key than the later ones
         const auto key = std::make_tuple(c->steps % period, c->cur, len, dt_bits, stats_every,
-                                         c->epoch);
+                                         c->epoch, c->sorted_once);
         auto it = c->graphs.find(key);
         hipGraphExec_t exec = nullptr;
         if (it == c->graphs.end()) {
@@ -1760,6 +1797,7 @@ struct StateHeader {
     int64_t np, steps, nrec;
     double t;
     int32_t time_mode, has_vel;
+    int32_t sorted_once, pad_;   // whether the first re-sort has happened
     DevClock clock;
 };
 
@@ -1841,6 +1879,7 @@ lpt_status lpt_get_state(lpt_ctx *c, void *blob, size_t cap, size_t *size)
     h.t = c->t;
     h.time_mode = c->time_mode;
     h.has_vel = c->has_inertial ? 1 : 0;
+    h.sorted_once = c->sorted_once ? 1 : 0;
     HIP_TRY(c, hipMemcpyAsync(&h.clock, c->clock, sizeof(DevClock), hipMemcpyDeviceToHost,
                               c->stream));
     size_t off = sizeof(StateHeader);
@@ -1933,6 +1972,7 @@ lpt_status lpt_set_state(lpt_ctx *c, const void *blob, size_t size)
     c->t = h.t;
     c->nrec = h.nrec;
     c->time_mode = h.time_mode;
+    c->sorted_once = h.sorted_once != 0;
     c->ck_valid = false;
     invalidate_graphs(c);
     return LPT_OK;
@@ -1975,8 +2015,8 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
     if (!(halo > 0.0f && halo <= 4.0f)) return fail(c, LPT_E_ARG, "halo_scale must be in (0, 4]");
     if (t->max_workgroups < 0) return fail(c, LPT_E_ARG, "max_workgroups must be >= 0");
     if (t->fused < 0 || t->fused > 2) return fail(c, LPT_E_ARG, "fused is 0, 1 or 2");
-    if (t->sort_cells != 0 && t->sort_cells != 1) return fail(c, LPT_E_ARG, "sort_cells is 0 or 1");
-    if (key_width(c->n, c->sort_tile, t->sort_cells, (int)c->sp.size()) > 32)
+    if (t->sort_cells < 0 || t->sort_cells > 2) return fail(c, LPT_E_ARG, "sort_cells is 0, 1 or 2");
+    if (key_width(c->n, c->sort_tile, t->sort_cells == 1, (int)c->sp.size()) > 32)
         return fail(c, LPT_E_ARG, "sort key wider than 32 bits with sort_cells; raise sort_tile");
     HIP_TRY(c, hipSetDevice(c->device));
     const bool block_changed = block != c->block;

@@ -126,11 +126,11 @@ def test_graph_chunks_replay_exactly_like_eager_steps(precision):
 def test_tuning_is_validated_and_changes_nothing_on_error():
     tr, _ = _mixed("fp32_split")
     before = tr.get_tuning()
-    assert before["tile_records"] == 0 and before["sort_cells"] == 0   # defaults: automatic tile
+    assert before["tile_records"] == 0 and before["sort_cells"] == 2   # defaults
     for bad in (dict(block_size=96), dict(tile_records=3), dict(sort_interval=-1),
                 dict(persistent=2), dict(graph_chunk=-5), dict(tile_records=100000),
                 dict(halo_scale=-1.0), dict(halo_scale=9.0), dict(max_workgroups=-1),
-                dict(fused=3), dict(sort_cells=2)):
+                dict(fused=3), dict(sort_cells=3), dict(sort_cells=-1)):
         with pytest.raises(lpt.LptError) as e:
             tr.set_tuning(**bad)
         assert e.value.status == lpt.E_ARG

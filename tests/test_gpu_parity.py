@@ -335,7 +335,7 @@ def test_sorting_never_changes_results(precision):
     n = 256
     (ua, va), (ub, vb) = synth.spectrum_snapshots(n, 10, 8, 0.002)
     outs = []
-    for interval, cells in ((0, 0), (3, 0), (3, 1)):
+    for interval, cells in ((0, 0), (3, 0), (3, 1), (3, 2)):
         tr = lpt.Tracker(n, precision, sort_interval=interval, sort_tile=8)
         tr.set_tuning(sort_cells=cells)
         tr.set_time_mode("pingpong")
@@ -430,13 +430,14 @@ def test_tile_escapees_match_oracle(scheme):
     assert np.max(np.abs(vx - sp.vx)) < 1e-8 and np.max(np.abs(vy - sp.vy)) < 1e-8
 
 
-@pytest.mark.parametrize("cells", [0, 1])
+@pytest.mark.parametrize("cells", [0, 1, 2])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
 def test_sort_produces_stable_tile_order(precision, cells):
     """Right after initialisation (slots in original order), lpt_sort leaves
     the slots in the stable argsort order of the cell-tile keys of the
-    stored cells, species by species: tiles alone, or (sort_cells) tiles
-    and then the cells row-major inside each tile."""
+    stored cells, species by species: tiles alone (sort_cells 0), or tiles
+    and then the cells row-major inside each tile (1, and 2, whose first
+    re-sort after placement uses that key)."""
     say(f"sort order {precision} cells={cells}")
     n = 128
     u, v, _ = synth.taylor_green(n)
@@ -459,7 +460,7 @@ def test_sort_produces_stable_tile_order(precision, cells):
         else:   # the split path stores floor(x * n / L)
             ci = np.floor(x0 * (n / L)).astype(np.int32)
             cj = np.floor(y0 * (n / L)).astype(np.int32)
-        keys = oracle.cell_keys(n, 8, ci, cj, coarse=not cells)
+        keys = oracle.cell_keys(n, 8, ci, cj, coarse=cells == 0)
         np.testing.assert_array_equal(order, oracle.sort_permutation(keys))
 
 
