@@ -416,17 +416,17 @@ __device__ __forceinline__ Tile block_box(bool active, int cx, int cy, int ax, i
     return T;
 }
 
-// Cooperative tile set-up of one block (all threads must call it): the box
-// of block_box, staged in LDS if it fits the capacity and is not much larger
-// than the block's particle count.
 // Tile fill by LDS DMA: the tile's flat index space is cut into chunks of 64
 // entries; a wave takes every nw-th chunk, and lane l of chunk c loads the
 // record of entry 64 c + l straight into LDS in 16-byte pieces (the wave's
 // LDS destination is the chunk's first entry; lane l lands 16 l bytes after
-// it), so the records never pass through registers.  An FP32 record is one
-// piece (one plane of records); an FP64 record is two, level 0 and level 1,
-// into two planes `area` entries apart.  Lanes past the tile's area are
-// switched off.  Ends with every wave's loads complete.
+// it), so the records never pass through registers.  A lane's tile column
+// and row are divided out once per tile; from one of its chunks to the next
+// its entry moves by 64 nw, a fixed number of rows and columns, so they are
+// carried forward with one compare per chunk.  An FP32 record is one piece
+// (one plane of records); an FP64 record is two, level 0 and level 1, into
+// two planes `area` entries apart.  Lanes past the tile's area are switched
+// off.  Ends with every wave's loads complete.
 template <typename Rec>
 __device__ __forceinline__ void fill_tile_dma(Rec *lds_rec, const Rec *__restrict__ rec0,
                                               const StepParams &P, const Tile &T)
@@ -434,25 +434,22 @@ __device__ __forceinline__ void fill_tile_dma(Rec *lds_rec, const Rec *__restric
     constexpr int kPieces = (int)sizeof(Rec) / 16;
     float4 *lds = reinterpret_cast<float4 *>(lds_rec);
     if (!T.on) return;
-    const int n = P.n, w = T.w, area = T.w * T.h;
-    const float inv_w = 1.0f / (float)w;
+    const int n = P.n;
+    const int w = __builtin_amdgcn_readfirstlane(T.w), h = __builtin_amdgcn_readfirstlane(T.h);
+    const int x0 = __builtin_amdgcn_readfirstlane(T.x0);
+    const int y0 = __builtin_amdgcn_readfirstlane(T.y0);
+    const int area = w * h;
     const int lane = (int)threadIdx.x & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
     const int nw = (int)blockDim.x / kWave;
     const int chunks = (area + kWave - 1) / kWave;
+    const int step = nw * kWave;                     // entries between a wave's chunks
+    const int sy = step / w, sx = step - sy * w;     // ... as rows and columns
+    int k = wv * kWave + lane;
+    int ty = k / w, tx = k - ty * w;
     for (int c = wv; c < chunks; c += nw) {
-        const int k = c * kWave + lane;
         if (k < area) {
-            int ty = (int)((float)k * inv_w);
-            int tx = k - ty * w;
-            if (tx < 0) {
-                ty -= 1;
-                tx += w;
-            } else if (tx >= w) {
-                ty += 1;
-                tx -= w;
-            }
-            int gx = T.x0 + tx, gy = T.y0 + ty;
+            int gx = x0 + tx, gy = y0 + ty;   // below 2 n: x0, y0 < n, tx < w < n, ty < h < n
             gx -= gx >= n ? n : 0;
             gy -= gy >= n ? n : 0;
             const float4 *src =
@@ -464,10 +461,20 @@ __device__ __forceinline__ void fill_tile_dma(Rec *lds_rec, const Rec *__restric
                     (void __attribute__((address_space(3))) *)(lds + piece * area + c * kWave), 16,
                     0, 0);
         }
+        k += step;
+        tx += sx;
+        ty += sy;
+        if (tx >= w) {
+            tx -= w;
+            ty += 1;
+        }
     }
     __builtin_amdgcn_s_waitcnt(0);
 }
 
+// Cooperative tile set-up of one block (all threads must call it): the box
+// of block_box, staged in LDS if it fits the capacity and is not much larger
+// than the block's particle count.
 template <typename Rec>
 __device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec0,
                                           const StepParams &P, bool active, int cx, int cy,
