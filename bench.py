@@ -668,8 +668,10 @@ def main():
         else:
             w = workloads.C1_TG
             dtype = "f64"
-            # steady field: the bracket just has to cover warm-up + timed steps
-            w = dataclasses.replace(w, steps=max(w.steps, args.steps + args.warmup))
+            # steady field: the bracket just has to cover the warm-up, timed and
+            # calibration steps (one more for the rounding of the summed time)
+            w = dataclasses.replace(
+                w, steps=max(w.steps, args.steps + args.warmup + max(w.stats_every, w.sort_interval) + 1))
         if args.sort_interval is not None:
             w = dataclasses.replace(w, sort_interval=args.sort_interval)
         value, ms_per_step, cfg, roof, extra = bench_steps(args, lpt, workloads, w, tuning,
