@@ -270,7 +270,9 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False, graph_chu
     if args.block_size:
         over["block_size"] = args.block_size
     npart = w.particles
-    calib_steps = max(w.stats_every, w.sort_interval)
+    # the re-sort interval in force: the tuning's, if it sets one
+    sort_interval = (tuning or {}).get("sort_interval", w.sort_interval)
+    calib_steps = max(w.stats_every, sort_interval)
     elapsed, timing, nstats, calib = run_gpu(w, args.steps, args.warmup, lpt, tuning,
                                              calib_steps=calib_steps, **over)
     graph = None
@@ -303,8 +305,8 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False, graph_chu
     # radix sort and the permuting step's excess, plus per record (every
     # stats_every steps) the statistics variant's excess and the merge
     sched_ms = kern_ms
-    if w.sort_interval and perm_ms is not None and sort_ms is not None:
-        sched_ms += (perm_ms - kern_ms + sort_ms) / w.sort_interval
+    if sort_interval and perm_ms is not None and sort_ms is not None:
+        sched_ms += (perm_ms - kern_ms + sort_ms) / sort_interval
     if w.stats_every and stat_ms is not None:
         sched_ms += (stat_ms - kern_ms + fin_ms) / w.stats_every
     perm_us = 1e3 * perm_ms if perm_ms is not None else None
@@ -323,7 +325,8 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False, graph_chu
     if fp64_twin and not args.no_fp64:
         w64 = dataclasses.replace(w, name=w.name.replace("fp32split", "fp64"), precision="fp64")
         k64 = max(100, args.steps // 4)
-        e64, t64, _, _ = run_gpu(w64, k64, min(args.warmup, 20), lpt, tuning, **over)
+        # the FP64 path with its own defaults (the tuning is the FP32 workload's)
+        e64, t64, _, _ = run_gpu(w64, k64, min(args.warmup, 20), lpt, None, **over)
         k64us = 1e3 * t64["step_kernel_ms"] / max(1, t64["step_launches"])
         extra["fp64_same_workload"] = {
             "value": npart * k64 / e64, "unit": "particle-steps/s", "steps": k64,
@@ -339,6 +342,7 @@ def bench_steps(args, lpt, workloads, w, tuning=None, fp64_twin=False, graph_chu
            "sort_tile": w.sort_tile, "stats_every": w.stats_every,
            "tile_records": tun.get("tile_records", args.tile_records),
            "block_size": tun.get("block_size", args.block_size or 256),
+           "rows": tun.get("rows", 1),
            "persistent": tun.get("persistent", 0), "parallelism": "1 GPU"}
     ms_step = 1e3 * elapsed / args.steps
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -672,8 +676,15 @@ def main():
             # calibration steps (one more for the rounding of the summed time)
             w = dataclasses.replace(
                 w, steps=max(w.steps, args.steps + args.warmup + max(w.stats_every, w.sort_interval) + 1))
+        if w in (workloads.C3_SPLIT, workloads.C3_SHARE8):
+            from paper_2607_17836_amd import autotune
+            tuning, ms, hit = autotune.cached_or_tune(w, lpt, workloads, autotune.device_key(0),
+                                                      log=lambda m: None)
+            log(f"[bench] autotuned launch shape ({'cached' if hit else 'tuned now'}): {tuning}")
         if args.sort_interval is not None:
             w = dataclasses.replace(w, sort_interval=args.sort_interval)
+            if tuning:
+                tuning = dict(tuning, sort_interval=args.sort_interval)
         value, ms_per_step, cfg, roof, extra = bench_steps(args, lpt, workloads, w, tuning,
                                                            fp64_twin, graph_chunk)
         if w.precision == "fp64":

@@ -305,6 +305,16 @@ typedef struct {
                                placed (where the key fits), tiles after it --
                                the later tile sorts, being stable, keep most
                                of that order                                 */
+    int32_t rows;           /* LPT_FP32_SPLIT bilinear tracer step kernels:
+                               particles per thread, 1 (0 selects 1) or 2.
+                               The block_size slots of a logical block are
+                               then run by block_size / rows threads (at
+                               least 64), which share one box, tile and
+                               set-up; a smaller workgroup holds less LDS at
+                               the same occupancy, so the tile's capacity per
+                               particle halves.  Other bodies (bicubic,
+                               inertial, fused, LPT_FP64) run one particle per
+                               thread.  Results do not depend on it          */
 } lpt_tuning;
 
 lpt_status lpt_get_tuning(lpt_ctx *ctx, lpt_tuning *out);

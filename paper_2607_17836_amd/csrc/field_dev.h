@@ -371,29 +371,50 @@ __device__ __forceinline__ void wave_stats(double r2x, double r2y, bool active, 
 }
 
 // Bounding box of the stored cells of a block's active particles, widened by
-// lo cells before and hi cells after on each axis (all threads must call
-// it; returns with the block synchronised).  (cx, cy): the thread's cell
-// (ignored when !active); (ax, ay): the cell of the block's first particle,
-// which is always active.  The box is reduced on offsets from (ax, ay),
-// biased by 2^15 and packed two per word, as maxima of (r + 2^15) and
-// (2^15 - r).  Fills x0, y0, w, h of the result; `on` is left 0.
-__device__ __forceinline__ Tile block_box(bool active, int cx, int cy, int ax, int ay, int n,
-                                          int mask, int lo, int hi)
+// lo cells before and hi cells after on each axis.  The box is reduced on
+// offsets from (ax, ay), the cell of the block's first particle (which is
+// always active), biased by 2^15 and packed two per word, as maxima of
+// (r + 2^15) and (2^15 - r).  A thread first folds its own particles into a
+// BoxAcc (box_add), then block_box_reduce combines the block's threads (all
+// threads must call it; it returns with the block synchronised) and fills
+// x0, y0, w, h of the result; `on` is left 0.
+struct BoxAcc {
+    uint32_t up, dn;
+};
+
+constexpr int kBoxBias = 1 << 15;
+
+// The anchor's own offset (0, 0), which every box holds.
+__device__ __forceinline__ BoxAcc box_init()
+{
+    constexpr uint32_t z = (uint32_t)kBoxBias | ((uint32_t)kBoxBias << 16);
+    return BoxAcc{z, z};
+}
+
+// The box terms of the single cell (cx, cy).
+__device__ __forceinline__ BoxAcc box_of(int cx, int cy, int ax, int ay, int n)
+{
+    const int half = n >> 1;
+    int rx = cx - ax, ry = cy - ay;   // in (-n, n): map it to (-n/2, n/2]
+    rx += rx < -half ? n : (rx > half ? -n : 0);
+    ry += ry < -half ? n : (ry > half ? -n : 0);
+    return BoxAcc{(uint32_t)(rx + kBoxBias) | ((uint32_t)(ry + kBoxBias) << 16),
+                  (uint32_t)(kBoxBias - rx) | ((uint32_t)(kBoxBias - ry) << 16)};
+}
+
+__device__ __forceinline__ void box_add(BoxAcc &b, int cx, int cy, int ax, int ay, int n)
+{
+    const BoxAcc c = box_of(cx, cy, ax, ay, n);
+    b.up = pmax16(b.up, c.up);
+    b.dn = pmax16(b.dn, c.dn);
+}
+
+__device__ __forceinline__ Tile block_box_reduce(BoxAcc b, int ax, int ay, int n, int mask,
+                                                 int lo, int hi)
 {
     __shared__ uint32_t red[2][kMaxBlock / kWave];
-    constexpr int kBias = 1 << 15;
-    const int half = n >> 1;
-    int rx = 0, ry = 0;
-    if (active) {   // cx - ax lies in (-n, n): map it to (-n/2, n/2]
-        rx = cx - ax;
-        ry = cy - ay;
-        rx += rx < -half ? n : (rx > half ? -n : 0);
-        ry += ry < -half ? n : (ry > half ? -n : 0);
-    }
-    uint32_t up = (uint32_t)(rx + kBias) | ((uint32_t)(ry + kBias) << 16);
-    uint32_t dn = (uint32_t)(kBias - rx) | ((uint32_t)(kBias - ry) << 16);
-    up = wave_pmax16(up);
-    dn = wave_pmax16(dn);
+    uint32_t up = wave_pmax16(b.up);
+    uint32_t dn = wave_pmax16(b.dn);
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     if (lane == 0) {
         red[0][wv] = up;
@@ -406,14 +427,23 @@ __device__ __forceinline__ Tile block_box(bool active, int cx, int cy, int ax, i
         up = pmax16(up, red[0][k]);
         dn = pmax16(dn, red[1][k]);
     }
-    const int mxx = (int)(up & 0xFFFFu) - kBias, mxy = (int)(up >> 16) - kBias;
-    const int mnx = kBias - (int)(dn & 0xFFFFu), mny = kBias - (int)(dn >> 16);
+    const int mxx = (int)(up & 0xFFFFu) - kBoxBias, mxy = (int)(up >> 16) - kBoxBias;
+    const int mnx = kBoxBias - (int)(dn & 0xFFFFu), mny = kBoxBias - (int)(dn >> 16);
     Tile T = no_tile();
     T.w = mxx - mnx + 1 + lo + hi;
     T.h = mxy - mny + 1 + lo + hi;
     T.x0 = wrap_cell(ax + mnx - lo, n, mask);
     T.y0 = wrap_cell(ay + mny - lo, n, mask);
     return T;
+}
+
+// The box of one particle per thread: (cx, cy) is the thread's cell
+// (ignored when !active).
+__device__ __forceinline__ Tile block_box(bool active, int cx, int cy, int ax, int ay, int n,
+                                          int mask, int lo, int hi)
+{
+    return block_box_reduce(active ? box_of(cx, cy, ax, ay, n) : box_init(), ax, ay, n, mask, lo,
+                            hi);
 }
 
 // Tile fill by LDS DMA: the tile's flat index space is cut into chunks of 64
@@ -473,15 +503,16 @@ __device__ __forceinline__ void fill_tile_dma(Rec *lds_rec, const Rec *__restric
 }
 
 // Cooperative tile set-up of one block (all threads must call it): the box
-// of block_box, staged in LDS if it fits the capacity and is not much larger
-// than the block's particle count.
+// of the block's particles (folded into b by each thread, see box_add),
+// staged in LDS if it fits the capacity and is not much larger than the
+// block's particle count.
 template <typename Rec>
-__device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec0,
-                                          const StepParams &P, bool active, int cx, int cy,
-                                          int ax, int ay, int lo, int hi, int nactive)
+__device__ __forceinline__ Tile stage_tile_acc(Rec *lds, const Rec *__restrict__ rec0,
+                                              const StepParams &P, BoxAcc b, int ax, int ay,
+                                              int lo, int hi, int nactive)
 {
     const int n = P.n;
-    Tile T = block_box(active, cx, cy, ax, ay, n, P.mask, lo, hi);
+    Tile T = block_box_reduce(b, ax, ay, n, P.mask, lo, hi);
     // A box beyond the capacity (a block whose particles have spread since
     // the last re-sort) is cut down about its centre to a window of the same
     // shape that fits: the stencils inside it still read LDS, the others
@@ -505,6 +536,15 @@ __device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec
     fill_tile_dma<Rec>(lds, rec0, P, T);
     __syncthreads();
     return T;
+}
+
+template <typename Rec>
+__device__ __forceinline__ Tile stage_tile(Rec *lds, const Rec *__restrict__ rec0,
+                                          const StepParams &P, bool active, int cx, int cy,
+                                          int ax, int ay, int lo, int hi, int nactive)
+{
+    return stage_tile_acc<Rec>(lds, rec0, P, active ? box_of(cx, cy, ax, ay, P.n) : box_init(), ax,
+                               ay, lo, hi, nactive);
 }
 
 // Halo extents of a scheme: a bilinear stencil spans nodes i..i+1, a bicubic

@@ -77,6 +77,7 @@ struct StepParams {
     int32_t max_wg;        // > 0: persistent grids hold at most this many workgroups
     int32_t tile_auto;     // 1: each step launch replaces tile_cap by the largest
                            // capacity that keeps its kernel's register-bound occupancy
+    int32_t rows;          // FP32 bilinear tracer step: rows of blockDim.x slots per block
 };
 
 // Block-order table of a fused launch over species whose logical blocks are

@@ -103,6 +103,7 @@ struct lpt_ctx {
     bool sorted_once = false;   // a re-sort has put the present particles in order
     int32_t tile_cap = 0;    // LDS tile capacity of the step kernel, node records
     int32_t tile_auto = 0;   // 1: step launches size the tile to their occupancy
+    int32_t rows = 1;        // FP32 bilinear tracer step: particles per thread
                              // (tile_cap is then the adjoint kernels' capacity)
     int32_t persistent = 0;  // persistent step launches
     float halo_scale = kHaloScaleDefault; // LDS tile halo relative to the largest-speed bound
@@ -279,6 +280,7 @@ StepParams make_params(const lpt_ctx *c)
     P.launch_blocks = blk;
     P.max_wg = c->max_wg;
     P.tile_auto = c->tile_auto;
+    P.rows = c->precision == LPT_FP64 ? 1 : c->rows;
     if (c->fused && c->sp.size() > 1 && c->order_ok) {
         P.order = c->order;
         P.order_len = c->order_len;
@@ -1991,6 +1993,7 @@ lpt_status lpt_get_tuning(lpt_ctx *c, lpt_tuning *out)
     out->max_workgroups = c->max_wg;
     out->fused = c->fused;
     out->sort_cells = c->sort_cells;
+    out->rows = c->rows;
     return LPT_OK;
 }
 
@@ -2016,6 +2019,9 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
     if (t->max_workgroups < 0) return fail(c, LPT_E_ARG, "max_workgroups must be >= 0");
     if (t->fused < 0 || t->fused > 2) return fail(c, LPT_E_ARG, "fused is 0, 1 or 2");
     if (t->sort_cells < 0 || t->sort_cells > 2) return fail(c, LPT_E_ARG, "sort_cells is 0, 1 or 2");
+    const int32_t rows = t->rows == 0 ? 1 : t->rows;
+    if (rows != 1 && rows != 2) return fail(c, LPT_E_ARG, "rows is 1 or 2");
+    if (block / rows < 64) return fail(c, LPT_E_ARG, "block_size / rows must be at least 64");
     if (key_width(c->n, c->sort_tile, t->sort_cells == 1, (int)c->sp.size()) > 32)
         return fail(c, LPT_E_ARG, "sort key wider than 32 bits with sort_cells; raise sort_tile");
     HIP_TRY(c, hipSetDevice(c->device));
@@ -2049,6 +2055,7 @@ lpt_status lpt_set_tuning(lpt_ctx *c, const lpt_tuning *t)
     if (t->fused != c->fused || block_changed) c->order_ok = false;
     c->fused = t->fused;
     c->sort_cells = t->sort_cells;
+    c->rows = rows;
     invalidate_graphs(c);
     return LPT_OK;
 }

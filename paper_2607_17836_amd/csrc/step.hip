@@ -586,12 +586,10 @@ __device__ __forceinline__ void particle_dispatch(const StepParams &P, const Sta
         particle32<SCHS, false, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, uc, o);
 }
 
-// One logical block of the step.  The state of slot p is read from S and
-// written to D: in place, or, on a step that follows a re-sort (GATHER),
-// slot p of D takes the particle of slot perm[p] of S, id included, so that
-// the step itself applies the sort's permutation.
+// One logical block of one particle per thread (the original single-row
+// body; see step32_block).
 template <int SCHS, int KINDS, bool STATS, bool GATHER>
-__device__ __forceinline__ void step32_block(const StepParams &P, const State32 &S,
+__device__ __forceinline__ void step32_block1(const StepParams &P, const State32 &S,
                                              const State32 &D, const uint32_t *perm,
                                              const float4 *__restrict__ rec,
                                              double *__restrict__ partials, DevClock *clock,
@@ -655,6 +653,114 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
     }
 }
 
+// One logical block of the step.  The state of slot p is read from S and
+// written to D: in place, or, on a step that follows a re-sort (GATHER),
+// slot p of D takes the particle of slot perm[p] of S, id included, so that
+// the step itself applies the sort's permutation.  A logical block holds
+// ROWS rows of blockDim.x slots: thread t takes slot t of every row, so the
+// block's set-up (its box, tile and launch bookkeeping) is shared by ROWS
+// particles per thread.  Row 0 keeps its state in registers from the box to
+// the step; the cells of later rows are read for the box and again for the
+// step (the second read finds them in the cache).
+template <int SCHS, int KINDS, bool STATS, bool GATHER, int ROWS>
+__device__ __forceinline__ void step32_block(const StepParams &P, const State32 &S,
+                                             const State32 &D, const uint32_t *perm,
+                                             const float4 *__restrict__ rec,
+                                             double *__restrict__ partials, DevClock *clock,
+                                             int lb)
+{
+    if constexpr (ROWS == 1) {
+        step32_block1<SCHS, KINDS, STATS, GATHER>(P, S, D, perm, rec, partials, clock, lb);
+        return;
+    }
+    float4 *lds = reinterpret_cast<float4 *>(lpt_dyn_lds);
+    const SpeciesDev &sp = P.sp[P.nspecies > 1 ? species_of(P, lb) : 0];
+    const int threads = (int)blockDim.x;
+    const int64_t slots = (int64_t)threads * ROWS;
+    const int64_t base = (int64_t)(lb - sp.block_begin) * slots;
+    const float4 *rec0 = rec + P.pitch + 1;
+
+    const bool active0 = base + threadIdx.x < sp.count;
+    int64_t q0 = sp.offset + base + threadIdx.x;
+    uint32_t cell0 = 0;   // the stored cell, (cy << 16) | cx
+    int2 uc0 = make_int2(0, 0);
+    float2 o0 = make_float2(0.f, 0.f);
+    if (active0) {
+        if (GATHER) q0 = perm[q0];
+        uc0 = ld_stream(S.uc + q0);
+        o0 = ld_stream(S.off + q0);
+        cell0 = (uint32_t)wrapn(uc0.x, P) | ((uint32_t)wrapn(uc0.y, P) << 16);
+    }
+    Tile T = no_tile();
+    if (P.tile_cap > 0) {
+        int lo, hi;
+        stencil_reach(sp.scheme, lo, hi);
+        const int H = step_halo(P, sp.scheme, P.dtf);
+        const int64_t left = sp.count - base;
+        const int nact = (int)(left < slots ? left : slots);
+        const int64_t a0 = sp.offset + base;
+        const int2 a = S.uc[GATHER ? (int64_t)perm[a0] : a0];
+        const int ax = wrapn(a.x, P), ay = wrapn(a.y, P);
+        BoxAcc b = active0 ? box_of((int)(cell0 & 0xFFFFu), (int)(cell0 >> 16), ax, ay, P.n)
+                           : box_init();
+#pragma unroll
+        for (int r = 1; r < ROWS; ++r) {
+            const int64_t local = base + (int64_t)r * threads + threadIdx.x;
+            if (local < sp.count) {
+                const int64_t p = sp.offset + local;
+                const int2 u = S.uc[GATHER ? (int64_t)perm[p] : p];
+                box_add(b, wrapn(u.x, P), wrapn(u.y, P), ax, ay, P.n);
+            }
+        }
+        T = stage_tile_acc<float4>(lds, rec0, P, b, ax, ay, lo + H, hi + H, nact);
+    }
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int64_t local = base + (int64_t)r * threads + threadIdx.x;
+        const bool active = local < sp.count;
+        const int64_t p = sp.offset + local;
+        double r2x = 0.0, r2y = 0.0;
+        if (active) {
+            int64_t q = q0;
+            int2 uc = uc0;
+            float2 o = o0;
+            uint32_t cell = cell0;
+            if (r > 0) {
+                q = GATHER ? (int64_t)perm[p] : p;
+                uc = ld_stream(S.uc + q);
+                o = ld_stream(S.off + q);
+                cell = (uint32_t)wrapn(uc.x, P) | ((uint32_t)wrapn(uc.y, P) << 16);
+            }
+            if (P.ends_one)
+                particle_dispatch<SCHS, KINDS, true, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell,
+                                                             uc, o);
+            else
+                particle_dispatch<SCHS, KINDS, false, GATHER>(P, S, D, rec0, lds, T, sp, p, q,
+                                                              cell, uc, o);
+            if (GATHER || STATS) {
+                const uint32_t g = S.id[q];
+                if (GATHER) D.id[p] = g;
+                if (STATS) {   // the displacement since initialisation, from the new state
+                    const double2 d = split_disp(uc, o, S.x0[g], P);
+                    r2x = d.x * d.x;
+                    r2y = d.y * d.y;
+                }
+            }
+        }
+        // one partial per 64 slots, in slot order: wave w of row r covers the
+        // slots lb * slots + r * threads + 64 w + [0, 64)
+        if (STATS)
+            wave_stats(r2x, r2y, active,
+                       partials + (int64_t)kStatTerms *
+                                      (((int64_t)lb * slots + (int64_t)r * threads) / kWave +
+                                       threadIdx.x / kWave));
+    }
+    if (lb == 0 && threadIdx.x == 0) {
+        clock->t += P.dt;
+        clock->step += 1;
+    }
+}
+
 // One launch advances every particle of its logical blocks by one step
 // (block_walk: one workgroup per logical block in XCD-aware order, a
 // persistent walk, or a fused launch's block-order table).
@@ -662,7 +768,7 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
 // budget), i.e. eight waves per SIMD, so their registers are bounded to fit
 // that; the bicubic bodies, and the fused kernel that holds every body
 // (SCHS = kAnyScheme), need more registers and keep the default bound.
-template <int SCHS, int KINDS, bool STATS>
+template <int SCHS, int KINDS, bool STATS, int ROWS>
 __global__ __launch_bounds__(kMaxBlock)
 __attribute__((amdgpu_waves_per_eu(SCHS == kBilinear ? 8 : 6)))
 void step32_kernel(StepParams P, State32 S, const float4 *__restrict__ rec,
@@ -670,12 +776,12 @@ void step32_kernel(StepParams P, State32 S, const float4 *__restrict__ rec,
 {
     BlockWalk w = block_walk(P, P.block_base, P.launch_blocks);
     for (int lb = 0; block_next(w, lb);)
-        step32_block<SCHS, KINDS, STATS, false>(P, S, S, nullptr, rec, partials, clock, lb);
+        step32_block<SCHS, KINDS, STATS, false, ROWS>(P, S, S, nullptr, rec, partials, clock, lb);
 }
 
 // The step that follows a re-sort: reads S through perm, writes D.  (A kernel
 // of its own, so that the in-place kernel above keeps its argument list.)
-template <int SCHS, int KINDS, bool STATS>
+template <int SCHS, int KINDS, bool STATS, int ROWS>
 __global__ __launch_bounds__(kMaxBlock)
 __attribute__((amdgpu_waves_per_eu(SCHS == kBilinear ? 8 : 6)))
 void step32_perm_kernel(StepParams P, State32 S, State32 D, const uint32_t *perm,
@@ -684,7 +790,7 @@ void step32_perm_kernel(StepParams P, State32 S, State32 D, const uint32_t *perm
 {
     BlockWalk w = block_walk(P, P.block_base, P.launch_blocks);
     for (int lb = 0; block_next(w, lb);)
-        step32_block<SCHS, KINDS, STATS, true>(P, S, D, perm, rec, partials, clock, lb);
+        step32_block<SCHS, KINDS, STATS, true, ROWS>(P, S, D, perm, rec, partials, clock, lb);
 }
 
 // Grid of a launch: one workgroup per logical block (per table entry in a
@@ -790,29 +896,49 @@ static hipError_t launch64_t(const StepParams &P, const State64 &St, const State
     return hipGetLastError();
 }
 
-template <int SCHS, int KINDS, bool ST>
-static hipError_t launch32_t(const StepParams &P, const State32 &S, const State32 &D,
+template <int SCHS, int KINDS, bool ST, int ROWS>
+static hipError_t launch32_r(const StepParams &P, const State32 &S, const State32 &D,
                              const uint32_t *perm, const float4 *rec, double *partials,
                              DevClock *clock, int block, int grid, hipStream_t st)
 {
+    // a logical block of `block` slots runs on block / ROWS threads
+    const int threads = block / ROWS;
     StepParams P1 = P;
     if (P.tile_auto && P.tile_cap > 0)
-        P1.tile_cap = perm ? auto_tile_cap(step32_perm_kernel<SCHS, KINDS, ST>, block, 1, P.tile_cap)
-                           : auto_tile_cap(step32_kernel<SCHS, KINDS, ST>, block, 1, P.tile_cap);
+        P1.tile_cap = perm ? auto_tile_cap(step32_perm_kernel<SCHS, KINDS, ST, ROWS>, threads, 1,
+                                           P.tile_cap)
+                           : auto_tile_cap(step32_kernel<SCHS, KINDS, ST, ROWS>, threads, 1,
+                                           P.tile_cap);
     // whole 64-entry chunks: the tile fill writes LDS a wave's chunk at a time
     const size_t lds =
         P1.tile_cap > 0 ? (size_t)((P1.tile_cap + kWave - 1) / kWave * kWave) * sizeof(float4) : 0;
     StepParams Q;
     if (perm) {
-        const int g = launch_grid(step32_perm_kernel<SCHS, KINDS, ST>, P1, block, lds, grid, Q);
-        hipLaunchKernelGGL((step32_perm_kernel<SCHS, KINDS, ST>), dim3(g), dim3(block), lds, st,
-                           Q, S, D, perm, rec, partials, clock);
+        const int g =
+            launch_grid(step32_perm_kernel<SCHS, KINDS, ST, ROWS>, P1, threads, lds, grid, Q);
+        hipLaunchKernelGGL((step32_perm_kernel<SCHS, KINDS, ST, ROWS>), dim3(g), dim3(threads),
+                           lds, st, Q, S, D, perm, rec, partials, clock);
     } else {
-        const int g = launch_grid(step32_kernel<SCHS, KINDS, ST>, P1, block, lds, grid, Q);
-        hipLaunchKernelGGL((step32_kernel<SCHS, KINDS, ST>), dim3(g), dim3(block), lds, st, Q, S,
-                           rec, partials, clock);
+        const int g = launch_grid(step32_kernel<SCHS, KINDS, ST, ROWS>, P1, threads, lds, grid, Q);
+        hipLaunchKernelGGL((step32_kernel<SCHS, KINDS, ST, ROWS>), dim3(g), dim3(threads), lds, st,
+                           Q, S, rec, partials, clock);
     }
     return hipGetLastError();
+}
+
+template <int SCHS, int KINDS, bool ST>
+static hipError_t launch32_t(const StepParams &P, const State32 &S, const State32 &D,
+                             const uint32_t *perm, const float4 *rec, double *partials,
+                             DevClock *clock, int block, int grid, hipStream_t st)
+{
+    // two rows per thread exist for the bilinear tracer bodies only (the
+    // bodies where the block's set-up is the largest share of the work);
+    // every other body runs one row, whatever P.rows asks
+    if constexpr (SCHS == kBilinear && KINDS == 0)
+        if (P.rows == 2)
+            return launch32_r<SCHS, KINDS, ST, 2>(P, S, D, perm, rec, partials, clock, block, grid,
+                                                  st);
+    return launch32_r<SCHS, KINDS, ST, 1>(P, S, D, perm, rec, partials, clock, block, grid, st);
 }
 
 template <int SCHS>

@@ -48,7 +48,7 @@ class LptTuning(C.Structure):
                 ("sort_interval", C.c_int32), ("persistent", C.c_int32),
                 ("graph_chunk", C.c_int32), ("halo_scale", C.c_float),
                 ("max_workgroups", C.c_int32), ("fused", C.c_int32),
-                ("sort_cells", C.c_int32)]
+                ("sort_cells", C.c_int32), ("rows", C.c_int32)]
 
 
 class LptTiming(C.Structure):

@@ -11,14 +11,15 @@ def test_shipped_table_entries_are_valid_tunings():
     table = json.load(open(autotune.SHIPPED))
     assert table
     fields = {"block_size", "tile_records", "sort_interval", "persistent", "graph_chunk",
-              "halo_scale", "max_workgroups", "fused", "sort_cells"}
+              "halo_scale", "max_workgroups", "fused", "sort_cells", "rows"}
     for key, ent in table.items():
         dev, rest = key.split("|", 1)
         assert dev.startswith("gfx950/")
         t = ent["tuning"]
         assert set(t) == fields
         for name, values in autotune.SPACE.items():
-            assert t[name] in values, (name, t[name])
+            got = tuple(t[k] for k in name) if isinstance(name, tuple) else t[name]
+            assert got in values, (name, got)
         assert ent["ms_per_step"] > 0
 
 

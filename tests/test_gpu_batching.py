@@ -123,23 +123,55 @@ def test_graph_chunks_replay_exactly_like_eager_steps(precision):
     graph.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
+def test_two_rows_per_thread_match_one_row(precision):
+    """A logical block of block_size slots run by block_size / 2 threads, two
+    particles each (the FP32-split bilinear tracer bodies; the others, and
+    FP64, run one row whatever the tuning says): per-species launches, so
+    that the bilinear tracers of the mix (5000, a ragged count) take that
+    body, plain, 128- and 256-thread rows, a persistent walk capped at 8
+    workgroups and graph chunks, with re-sorts every 5 steps and statistics
+    every 2: positions, velocities and every statistics field bit-identical
+    to one particle per thread."""
+    say(f"rows {precision}")
+    outs = []
+    for block, rows, extra in ((256, 1, {}), (512, 2, {}), (256, 2, {}),
+                               (512, 2, dict(persistent=1, max_workgroups=8)),
+                               (512, 2, dict(graph_chunk=5))):
+        tr, sids = _mixed(precision, sort_interval=5)
+        tr.set_tuning(block_size=block, rows=rows, fused=0, **extra)
+        tr.step(20, 0.002, stats_every=2)
+        snap = _snap(tr, sids)
+        for s in sids:
+            st = tr.get_stats(s)
+            snap += [st[f] for f in ("t", "msd_x", "msd_y", "msd", "d_x", "d_y", "sem", "n")]
+        outs.append(snap)
+        tr.close()
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            np.testing.assert_array_equal(a, b)
+
+
 def test_tuning_is_validated_and_changes_nothing_on_error():
     tr, _ = _mixed("fp32_split")
     before = tr.get_tuning()
     assert before["tile_records"] == 0 and before["sort_cells"] == 2   # defaults
+    assert before["rows"] == 1
     for bad in (dict(block_size=96), dict(tile_records=3), dict(sort_interval=-1),
                 dict(persistent=2), dict(graph_chunk=-5), dict(tile_records=100000),
                 dict(halo_scale=-1.0), dict(halo_scale=9.0), dict(max_workgroups=-1),
-                dict(fused=3), dict(sort_cells=3), dict(sort_cells=-1)):
+                dict(fused=3), dict(sort_cells=3), dict(sort_cells=-1), dict(rows=3),
+                dict(rows=-1), dict(block_size=64, rows=2)):
         with pytest.raises(lpt.LptError) as e:
             tr.set_tuning(**bad)
         assert e.value.status == lpt.E_ARG
         assert tr.get_tuning() == before
     tr.set_tuning(block_size=512, tile_records=2400, sort_interval=7, persistent=1,
-                  graph_chunk=10, halo_scale=0.5, max_workgroups=40, fused=0, sort_cells=1)
+                  graph_chunk=10, halo_scale=0.5, max_workgroups=40, fused=0, sort_cells=1,
+                  rows=2)
     assert tr.get_tuning() == dict(block_size=512, tile_records=2400, sort_interval=7,
                                    persistent=1, graph_chunk=10, halo_scale=0.5,
-                                   max_workgroups=40, fused=0, sort_cells=1)
+                                   max_workgroups=40, fused=0, sort_cells=1, rows=2)
     tr.set_tuning(halo_scale=0.0)   # 0 selects the default
     assert tr.get_tuning()["halo_scale"] == 0.125
     tr.close()
