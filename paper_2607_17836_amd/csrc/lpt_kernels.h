@@ -232,6 +232,8 @@ struct SortWork {
     uint32_t *scan_tmp;    // per-digit totals of a radix pass (256)
     int64_t capacity;      // keys
 };
+// Keys per radix-sort tile: each tile holds one row of digit histograms.
+constexpr int kSortTileKeys = 4096;
 int64_t sort_hist_entries(int64_t n);
 int64_t sort_scan_blocks(int64_t n);
 // p[0 .. n) = v (a kernel, so that it can sit in a captured graph)

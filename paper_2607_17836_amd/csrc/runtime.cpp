@@ -458,7 +458,7 @@ bool is_finite(double v) { return std::isfinite(v); }
 // process; every lpt_radix_sort_static call on that GPU shares it.
 namespace {
 constexpr int64_t kStaticSortMax = LPT_STATIC_SORT_MAX;
-constexpr int64_t kStaticSortHist = 256 * ((kStaticSortMax + 4095) / 4096);
+constexpr int64_t kStaticSortHist = 256 * ((kStaticSortMax + kSortTileKeys - 1) / kSortTileKeys);
 constexpr int64_t kStaticSortWords = 4 * kStaticSortMax + kStaticSortHist + 256;
 }  // namespace
 

@@ -27,6 +27,7 @@ constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kItems = 16;                             // keys per thread
 constexpr int kTile = kSortThreads * kItems;           // 4096 keys
+static_assert(kTile == kSortTileKeys, "the tile the histogram buffers are sized for");
 constexpr int kWaveRun = kTile / kSortWaves;           // 1024 keys per wave
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
