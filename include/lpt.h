@@ -101,9 +101,10 @@ typedef struct {
     int32_t sort_interval;  /* steps between cell-order re-sorts; 0 = never   */
     int32_t sort_tile;      /* tile side T of the cell-order key (power of
                                two dividing n); 0 selects 16                  */
-    int32_t block_size;     /* threads per block of the step kernel: 64,
-                               128, 256 or 512; 0 selects 256 (else
-                               LPT_E_ARG)                                     */
+    int32_t block_size;     /* particles per logical block of the step
+                               kernel (its threads, at one particle per
+                               thread; see lpt_tuning.rows): 64, 128, 256 or
+                               512; 0 selects 256 (else LPT_E_ARG)            */
     uint32_t flags;         /* LPT_FLAG_*                                     */
     int32_t tile_records;   /* capacity, in node records, of the per-block
                                LDS field tile of the step kernel: 0 selects
@@ -265,8 +266,10 @@ lpt_status lpt_set_state(lpt_ctx *ctx, const void *blob, size_t size);
  * interval or sort key reorders the slots and so may change their last bits.
  * They are run-to-run reproducible for fixed choices. */
 typedef struct {
-    int32_t block_size;     /* threads per block of the step kernel: 64, 128,
-                               256 or 512 (0 selects 256)                    */
+    int32_t block_size;     /* particles (slots) per logical block of the step
+                               kernel, 64, 128, 256 or 512 (0 selects 256);
+                               the threads of its workgroup, unless `rows`
+                               below splits it                               */
     int32_t tile_records;   /* as lpt_config.tile_records (0 default, -1 off) */
     int32_t sort_interval;  /* steps between cell-order re-sorts; 0 = never   */
     int32_t persistent;     /* 1: launch only as many workgroups as stay
