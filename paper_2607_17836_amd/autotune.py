@@ -48,7 +48,17 @@ def workload_key(w, device_name: str) -> str:
     return f"{device_name}|n={w.n}|{w.precision}|{w.time_mode}|dt={w.dt}|K={w.stats_every}|{mix}"
 
 
-def _valid(t, precision):
+def _rows_apply(w):
+    """Two rows per thread exist for FP32-split bilinear tracer bodies only
+    (an inertial species of St = 0 steps as a tracer); elsewhere `rows` has
+    no effect, and trying it would only let noise pick it."""
+    return w.precision == "fp32_split" and any(
+        sch == "bilinear" and (kind == "tracer" or st == 0.0) for kind, st, sch, _, _ in w.species)
+
+
+def _valid(t, precision, rows_apply=True):
+    if t.get("rows", 1) != 1 and not rows_apply:
+        return False
     rec = 32 if precision == "fp64" else 16
     if t["tile_records"] > 0 and t["tile_records"] * rec > 61440:
         return False
@@ -87,7 +97,7 @@ def tune(w, lpt_mod, workloads_mod, trial_steps=80, rounds=2, log=None, warm_ste
                     if all(best[k] == x for k, x in setting.items()):
                         continue
                     cand = dict(best, **setting)
-                    if not _valid(cand, w.precision):
+                    if not _valid(cand, w.precision, _rows_apply(w)):
                         continue
                     ms = measure(cand)
                     if log:
@@ -151,13 +161,15 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser(description="tune one workload of the workloads module on GPU 0 "
                                  "and add its entry to a tuning table")
     ap.add_argument("workload", help="name of a Workload in paper_2607_17836_amd.workloads, "
-                    "e.g. C4_BATCH")
+                    "e.g. C4_BATCH, or a workload function and its argument, e.g. "
+                    "c2_spectrum:catmull_rom")
     ap.add_argument("--out", required=True, help="JSON table to add the entry to")
     a = ap.parse_args()
     import torch
 
     from paper_2607_17836_amd import lpt, workloads
-    wl = getattr(workloads, a.workload)
+    name, _, arg = a.workload.partition(":")
+    wl = getattr(workloads, name)(arg) if arg else getattr(workloads, name)
     dev = device_key(0)
     best, ms = tune(wl, lpt, workloads, log=lambda m: print(m, flush=True))
     table = load_cache(a.out)

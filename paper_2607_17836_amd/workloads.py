@@ -71,6 +71,10 @@ C3_SPLIT = Workload("spec4096_fp32split_bilinear_2p24", 4096, "fp32_split", "spe
 
 # One GPU's share of the headline on eight: 2^21 tracers on the same full
 # 4096^2 field (the field is replicated, the particles are split).
+# The headline's particles and fields in FP64 positions and FP64 node records:
+# the plain FP64 path on the same workload.
+C3_FP64 = dataclasses.replace(C3_SPLIT, name="spec4096_fp64_bilinear_2p24", precision="fp64")
+
 C3_SHARE8 = dataclasses.replace(C3_SPLIT, name="spec4096_fp32split_bilinear_2p21_share8",
                                 species=(("tracer", 0.0, "bilinear", 1 << 21, 31),))
 

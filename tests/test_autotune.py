@@ -45,3 +45,14 @@ def test_user_cache_is_used_for_other_devices(monkeypatch, tmp_path):
     monkeypatch.setattr(autotune, "tune", lambda *a, **k: pytest.fail("tuned"))
     t, ms, hit = autotune.cached_or_tune(w, None, None, "gfx000/1cu", path=str(path))
     assert hit and t == {"block_size": 128} and ms == 1.0
+
+
+def test_rows_are_tried_only_where_they_apply():
+    """Two rows per thread change only FP32-split bilinear tracer bodies; the
+    tuner does not try them elsewhere (FP64, bicubic or inertial-only mixes)."""
+    assert autotune._rows_apply(workloads.C3_SPLIT)
+    assert not autotune._rows_apply(workloads.C3_FP64)
+    assert not autotune._rows_apply(workloads.c2_spectrum("catmull_rom"))
+    assert autotune._rows_apply(workloads.C4_BATCH)   # its species 0: bilinear tracers
+    t = {"rows": 2, "tile_records": 0, "graph_chunk": 0, "sort_interval": 16}
+    assert autotune._valid(t, "fp32_split", True) and not autotune._valid(t, "fp64", False)
