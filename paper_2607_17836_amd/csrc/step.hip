@@ -586,8 +586,9 @@ __device__ __forceinline__ void particle_dispatch(const StepParams &P, const Sta
         particle32<SCHS, false, ONE, GATHER>(P, S, D, rec0, lds, T, sp, p, q, cell, uc, o);
 }
 
-// One logical block of one particle per thread (the original single-row
-// body; see step32_block).
+// One logical block at one particle per thread: step32_block with ROWS = 1,
+// as a body of its own (the row loop's carried state would cost registers a
+// single row does not need).
 template <int SCHS, int KINDS, bool STATS, bool GATHER>
 __device__ __forceinline__ void step32_block1(const StepParams &P, const State32 &S,
                                              const State32 &D, const uint32_t *perm,
