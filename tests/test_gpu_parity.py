@@ -29,6 +29,20 @@ def say(msg):
     print(msg, flush=True)
 
 
+def bench_tracker(w):
+    """A tracker of workload w in the launch configuration bench.py times:
+    the shipped MI355X tuning table's entry for the workload on this device,
+    if it has one (the library defaults otherwise)."""
+    from paper_2607_17836_amd import autotune
+    tr = workloads.build_tracker(w, lpt)
+    ent = autotune.load_cache(autotune.SHIPPED).get(
+        autotune.workload_key(w, autotune.device_key(0)))
+    if ent:
+        tr.set_tuning(**ent["tuning"])
+        say(f"  launch shape of the benchmark: {ent['tuning']}")
+    return tr
+
+
 # --------------------------------------------------------------------------
 # a3 + a4 + a5: cell location, spatial and temporal interpolation
 # --------------------------------------------------------------------------
@@ -185,13 +199,13 @@ def test_c2_shape_parity_and_msd(scheme):
 
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_c2_full_size_sampled(scheme):
-    """The full 1024^2, 2^20 + 2^20 configuration (sorting every 20 steps as
-    configured): 10-step positions of 512 sampled particles per species
+    """The full 1024^2, 2^20 + 2^20 configuration, in the benchmark's launch
+    shape: 10-step positions of 512 sampled particles per species
     within 1e-10 of the oracle run on those particles alone, and the GPU
     statistics equal to exact sums of the downloaded displacements."""
     w = workloads.c2_spectrum(scheme)
     say(f"C2 full {w.name} particles={w.particles}")
-    tr = workloads.build_tracker(w, lpt)
+    tr = bench_tracker(w)
     tr.step(10, w.dt, 10)
     ids = np.random.default_rng(99).choice(1 << 20, 512, replace=False)
     fl, sps = _spectrum_oracle_pair(w, scheme, ids)
@@ -214,7 +228,8 @@ def test_c2_full_size_sampled(scheme):
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_c2_full_size_500_steps_sampled(scheme):
     """The full 1024^2, 2^20 + 2^20 configuration over its whole 500 steps
-    (re-sorts every 20, a record every 10): the 512 sampled particles per
+    in the benchmark's launch shape (a record every 10): the 512 sampled
+    particles per
     species within 1e-6 of the oracle run on those particles alone, and the
     last record equal to exact sums of the downloaded displacements of the
     whole population.  The tolerance follows from the flow's sensitivity:
@@ -223,7 +238,7 @@ def test_c2_full_size_500_steps_sampled(scheme):
     differences of a few ulps per step stay well inside 1e-6."""
     w = workloads.c2_spectrum(scheme)
     say(f"C2 full 500 steps {w.name} particles={w.particles}")
-    tr = workloads.build_tracker(w, lpt)
+    tr = bench_tracker(w)
     tr.step(w.steps, w.dt, w.stats_every)
     ids = np.random.default_rng(98).choice(1 << 20, 512, replace=False)
     fl, sps = _spectrum_oracle_pair(w, scheme, ids)
@@ -569,12 +584,13 @@ def test_fp32_split_tracks_fp64_oracle():
 
 def test_c3_full_size_sampled():
     """The headline configuration as the benchmark runs it (4096^2 FP32
-    fields, 2^24 split tracers, re-sorted every 16 steps, so the run includes
-    two permuting steps): after 20 steps, 1024 sampled particles lie within
-    1e-6 of the FP64 oracle on the binary32-rounded fields."""
+    fields, 2^24 split tracers, the benchmark's launch shape: 512-slot blocks
+    of two rows per thread, re-sorted every 16 steps, so the run includes two
+    permuting steps): after 20 steps, 1024 sampled particles lie within 1e-6
+    of the FP64 oracle on the binary32-rounded fields."""
     w = workloads.C3_SPLIT
     say(f"C3 full {w.name}")
-    tr = workloads.build_tracker(w, lpt)
+    tr = bench_tracker(w)
     tr.step(20, w.dt, w.stats_every)
     xw, yw, xu, yu = tr.get_positions(0)
     tr.close()
@@ -592,8 +608,8 @@ def test_c3_full_size_sampled():
 
 def test_c4_full_size_sampled():
     """The batching configuration at full size (2048^2 FP32 fields, 8 species
-    of 2^16 .. 2^23 particles, Stokes numbers 0 .. 10, scheme k mod 3; one
-    launch per species and step, re-sorted at the first step): after 10
+    of 2^16 .. 2^23 particles, Stokes numbers 0 .. 10, scheme k mod 3; in the
+    benchmark's launch shape, re-sorted at the first step): after 10
     steps, 64 sampled particles of every species match the FP64 oracle on the
     binary32-rounded fields within the binary32 bounds of the split path
     (positions 1e-6; velocities 1e-5, whose initial values the GPU forms in
@@ -601,7 +617,7 @@ def test_c4_full_size_sampled():
     w = workloads.C4_BATCH
     say(f"C4 full {w.name}")
     nsteps = 10
-    tr = workloads.build_tracker(w, lpt)
+    tr = bench_tracker(w)
     tr.step(nsteps, w.dt, w.stats_every)
     got = []
     for k, (kind, st, scheme, cnt, seed) in enumerate(w.species):
