@@ -606,6 +606,31 @@ def test_c3_full_size_sampled():
     assert err < 1e-6
 
 
+def test_c3_fp64_full_size_sampled():
+    """The headline configuration on the FP64 path (4096^2 FP64 node
+    records, 2^24 FP64 tracers), in its own benchmark launch shape (an
+    800-record tile, re-sorts every 10 steps, so the run includes a permuting
+    step): after 10 steps, 1024 sampled particles within 1e-10 of the FP64
+    oracle, wrapped and unwrapped."""
+    w = workloads.C3_FP64
+    say(f"C3 FP64 full {w.name}")
+    tr = bench_tracker(w)
+    tr.step(10, w.dt, w.stats_every)
+    xw, yw, xu, yu = tr.get_positions(0)
+    tr.close()
+    a, b, _ = w.snapshots()
+    fl = oracle.grid_flow(a[0], a[1], b[0], b[1], time_mode=oracle.PINGPONG)
+    ids = np.random.default_rng(7).choice(1 << 24, 1024, replace=False)
+    x0, y0 = oracle.init_uniform(31, 1 << 24)
+    sp = oracle.Species(x0[ids], y0[ids])
+    oracle.run(fl, sp, 10, w.dt)
+    ox, oy = sp.unwrapped()
+    err = max(np.max(pdist(xw[ids], sp.xw)), np.max(pdist(yw[ids], sp.yw)))
+    erru = max(np.max(np.abs(xu[ids] - ox)), np.max(np.abs(yu[ids] - oy)))
+    say(f"C3 FP64 sampled max position error after 10 steps: {err:.3e} (unwrapped {erru:.3e})")
+    assert err < 1e-10 and erru < 1e-10
+
+
 def test_c4_full_size_sampled():
     """The batching configuration at full size (2048^2 FP32 fields, 8 species
     of 2^16 .. 2^23 particles, Stokes numbers 0 .. 10, scheme k mod 3; in the
