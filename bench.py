@@ -86,7 +86,7 @@ def alg_bytes_per_step(w, layout=False) -> float:
 
 
 # Vector peaks of MI355X (256 CUs at 2.4 GHz): FP64 128 flop per clock per CU,
-# FP32 256 (with packed FP32; this build's kernels run unpacked FP32, half that).
+# FP32 256 (with packed FP32; the library's kernels run unpacked FP32, half that).
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
@@ -608,7 +608,7 @@ def main():
                     help="only run the copy/triad bandwidth probe and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build runs the "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs the "
               f"particle path on a single GPU and has no multi-GPU mode", file=sys.stderr)
         sys.exit(2)
 
