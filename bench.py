@@ -4,19 +4,21 @@
 
 Default workload (the headline configuration): a 4096^2 doubly periodic grid
 with two FP32 velocity snapshots from the k0 = 20 random-phase spectrum
-(ping-pong time levels, dt = 1e-3), 2^24 passive tracers in split form (int
-cell + FP32 offset, FP64 displacement), bilinear interpolation.  One step =
-one RK4 step of every particle (cell location, 4 stages of spatial + temporal
-interpolation, combine, wrap, FP64 displacement), plus the cell-order re-sort
-every 16 steps (applied by the following step's kernel) and the FP64
-MSD/dispersion reduction every 100 steps, all inside the timed region.  Inputs
-are resident in HBM before timing starts.
+(ping-pong time levels, dt = 1e-3), 2^24 passive tracers in split form
+(unwrapped int32 cell + binary32 offset; the FP64 displacement follows
+exactly from it and the initial position), bilinear interpolation.  One
+step = one RK4 step of every particle (cell location, 4 stages of spatial +
+temporal interpolation, combine, wrap), plus the cell-order re-sort every 16
+steps (applied by the following step's kernel) and the FP64 MSD/dispersion
+reduction every 100 steps, all inside the timed region.  Inputs are resident
+in HBM before timing starts; the bandwidth probe runs right before the
+warm-up steps.
 
 Other workloads (--workload): spec4096_fp64 (the headline in FP64 positions
 and fields), spec4096_split_share8 (the headline with 2^21
 tracers: one GPU's share on eight, same full field), batch2048 (8
-Stokes-number species, all three schemes, one launch per species, autotuned
-launch shape), spec1024_fp64 (FP64 tracers + inertial particles, --scheme),
+Stokes-number species, all three schemes, one fused launch over the
+species, 100-step graph chunks, shipped launch shape), spec1024_fp64 (FP64 tracers + inertial particles, --scheme),
 tg64 (FP64 Taylor-Green, 4096 tracers), adjoint2048 (FP64 checkpointed
 forward run plus reverse sweep with grid gradients), ns2048 (the Eulerian
 field producer: one pseudospectral AB2 vorticity step on a 2048^2 FP64 grid)
@@ -136,6 +138,27 @@ def measured_traffic(workload: str):
     return tf.get("hbm_bytes_per_launch")
 
 
+BW_PROBES = []   # (copy GB/s, triad GB/s), in the order taken
+
+
+def bw_probe(lpt):
+    """Copy and triad bandwidth of plain streaming kernels (1 GiB buffers, 10
+    launches each, about 12 ms of GPU time).  Every timed run takes it right
+    after its set-up and just before its warm-up steps: besides the
+    achievable bandwidth, it brings the GPU out of the idle state that the
+    host-side set-up (field synthesis, upload: about 1.3 s at 4096^2) leaves
+    it in, so that a window of a few milliseconds sees the clock state of a
+    sustained run."""
+    probe = lpt.Tracker(16, "fp64")
+    try:
+        copy_gbs, triad_gbs = probe.bw_probe(1 << 30, 10)
+    finally:
+        probe.close()
+    BW_PROBES.append((copy_gbs, triad_gbs))
+    log(f"[bench] achievable bandwidth: copy {copy_gbs:.0f} GB/s, triad {triad_gbs:.0f} GB/s")
+    return copy_gbs, triad_gbs
+
+
 def run_gpu(w, steps, warmup, lpt, tuning=None, calib_steps=0, **over):
     """Time `steps` steps after `warmup` untimed ones.  Returns (elapsed s,
     library timing dict, stats records of species 0, timing dict of
@@ -152,6 +175,7 @@ def run_gpu(w, steps, warmup, lpt, tuning=None, calib_steps=0, **over):
             tr.set_tuning(**tuning)
         tr.synchronize()
         log(f"[bench] setup of {w.name}: {time.perf_counter() - t0:.1f} s")
+        bw_probe(lpt)
         tr.step(warmup, w.dt, w.stats_every)
         tr.synchronize()
         tr.get_timing(reset=True)
@@ -183,6 +207,8 @@ def run_gpu_graphs(w, steps, warmup, lpt, tuning, chunk):
     tr = workloads.build_tracker(w, lpt)
     try:
         tr.set_tuning(**dict(tuning or {}, graph_chunk=chunk))
+        tr.synchronize()
+        bw_probe(lpt)
         tr.step(warmup, w.dt, w.stats_every)
         tr.synchronize()
         torch.cuda.synchronize()
@@ -413,7 +439,9 @@ def bench_adjoint(args, lpt):
     tr.set_snapshot(0, 0.0, u, v)
     tr.set_snapshot(1, nsteps * dt, u, v)
     tr.add_species("tracer", 0.0, "bilinear", x0, y0)
+    tr.synchronize()
     torch.cuda.synchronize()
+    bw_probe(lpt)
 
     def timed(fn):
         torch.cuda.synchronize()
@@ -473,9 +501,11 @@ def bench_ns(args, n=NS_N, dt=NS_DT):
     inverse row pass.  HIP events on the null stream, which the producer
     runs on; the fields are checked finite afterwards."""
     import torch
-    from paper_2607_17836_amd import ns2d, synth
+    from paper_2607_17836_amd import lpt, ns2d, synth
     g = ns2d.Ns2d(n, NS_NU, dt)
     g.set_vorticity(synth.random_vorticity(n, NS_K0, NS_SEED, omega_rms=NS_RMS))
+    g.synchronize()
+    bw_probe(lpt)
     g.step(args.warmup)
     g.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -528,7 +558,7 @@ def bench_coupled(args):
     events bracket the timed steps; the same loop with the field and the
     particles on two overlapping streams is timed too (it is slower)."""
     import torch
-    from paper_2607_17836_amd import coupled, synth
+    from paper_2607_17836_amd import coupled, lpt, synth
     w0 = synth.random_vorticity(NS_N, NS_K0, NS_SEED, omega_rms=NS_RMS)
     out = {}
     for streams in (1, 2):
@@ -538,6 +568,8 @@ def bench_coupled(args):
         sid = loop.tracker.add_species("tracer", 0.0, "bilinear", zeros, zeros)
         loop.tracker.init_uniform(sid, COUPLED_SEED)
         steps = args.steps if streams == 1 else max(1, args.steps // 2)
+        loop.synchronize()
+        bw_probe(lpt)
         loop.step(args.warmup, 100)
         loop.synchronize()
         torch.cuda.synchronize()
@@ -614,11 +646,8 @@ def main():
 
     from paper_2607_17836_amd import lpt, workloads
     lpt.load()
-    probe = lpt.Tracker(16, "fp64")
-    copy_gbs, triad_gbs = probe.bw_probe(1 << 30, 10)
-    probe.close()
-    log(f"[bench] achievable bandwidth: copy {copy_gbs:.0f} GB/s, triad {triad_gbs:.0f} GB/s")
     if args.bw_probe:
+        copy_gbs, triad_gbs = bw_probe(lpt)
         print(json.dumps({"copy_gbps": copy_gbs, "triad_gbps": triad_gbs,
                           "bytes_per_buffer": 1 << 30, "iters": 10}), flush=True)
         return
@@ -699,6 +728,8 @@ def main():
             dtype = "f64"
         if w is not workloads.C3_SPLIT:
             metric = f"particle-steps/s (RK4+interp), {w.name}"
+    # the probe taken right before the reported run's warm-up steps
+    copy_gbs, triad_gbs = BW_PROBES[0] if BW_PROBES else bw_probe(lpt)
     roof["achievable_copy_gbps"] = copy_gbs
     roof["achievable_triad_gbps"] = triad_gbs
     roof["frac_of_copy"] = roof["achieved"] / copy_gbs
