@@ -27,6 +27,9 @@ struct SpeciesDev {
     int64_t count;
     int32_t block_begin;
     int32_t block_end;
+    uint64_t x0_seed;      // with x0_drawn: the seed the initial positions were drawn from
+    int32_t x0_drawn;      // 1: initial positions are the SplitMix64 draws of x0_seed
+    int32_t pad_;
 };
 
 // Node records are stored with a periodic ghost border: one node before and

@@ -77,6 +77,11 @@ struct SpeciesHost {
     int64_t count;
     int64_t offset;
     bool vel_from_field;
+    // the initial positions are still the SplitMix64 draws of x0_seed
+    // (lpt_init_uniform), so a record step can draw them again instead of
+    // gathering them in particle order
+    bool x0_drawn = false;
+    uint64_t x0_seed = 0;
 };
 
 template <typename T>
@@ -274,6 +279,9 @@ StepParams make_params(const lpt_ctx *c)
         d.block_begin = blk;
         blk += (int32_t)((h.count + c->block - 1) / c->block);
         d.block_end = blk;
+        d.x0_seed = h.x0_seed;
+        d.x0_drawn = h.x0_drawn ? 1 : 0;
+        d.pad_ = 0;
     }
     P.total_blocks = blk;
     P.block_base = 0;
@@ -898,8 +906,10 @@ lpt_status lpt_init_uniform(lpt_ctx *c, int32_t sid, uint64_t seed)
     if (sid < 0 || sid >= (int32_t)c->sp.size()) return fail(c, LPT_E_ARG, "unknown species");
     if (c->steps > 0) return fail(c, LPT_E_STATE, "initialisation only before the first step");
     HIP_TRY(c, hipSetDevice(c->device));
-    const SpeciesHost &s = c->sp[sid];
+    SpeciesHost &s = c->sp[sid];
     HIP_TRY(c, launch_splitmix(c->x0 + s.offset, s.count, seed, c->L, c->stream));
+    s.x0_drawn = true;
+    s.x0_seed = seed;
     // a previous sort may have moved particles of this species around inside
     // its range: re-initialising writes the state in original order again
     return init_species_state(c, sid);
@@ -1956,6 +1966,9 @@ lpt_status lpt_set_state(lpt_ctx *c, const void *blob, size_t size)
     }
     const std::vector<size_t> sizes = state_arrays(c);
     const std::vector<void *> dst = state_ptrs(c, c->cur);
+    // the blob's initial positions replace the species' own: record steps
+    // read them from now on instead of drawing them again
+    for (SpeciesHost &sh : c->sp) sh.x0_drawn = false;
     for (size_t a = 0; a < sizes.size(); ++a) {
         HIP_TRY(c, hipMemcpyAsync(dst[a], in + off, sizes[a], hipMemcpyHostToDevice, c->stream));
         off += sizes[a];

@@ -295,6 +295,38 @@ __device__ __forceinline__ void split_of(double x, const StepParams &P, int &c, 
     o = r;
 }
 
+// Counter-indexed SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output k of
+// the stream seeded with s is mix(s + (k + 1) * golden gamma).
+__device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// Uniform initial position of particle k of a species drawn with `seed`:
+// outputs 2k and 2k + 1 of the stream, top 53 bits as a fraction of L.  The
+// one definition both the initialisation and the record steps use, so a
+// position drawn again is the stored one, bit for bit.
+__device__ __forceinline__ double2 draw_x0(uint64_t seed, uint64_t k, double L)
+{
+    const double ux = (double)(splitmix_at(seed, 2 * k) >> 11) * 0x1p-53;
+    const double uy = (double)(splitmix_at(seed, 2 * k + 1) >> 11) * 0x1p-53;
+    return make_double2(wrap_pos(L * ux, L), wrap_pos(L * uy, L));
+}
+
+// Initial position of particle g (global id) of species sp: drawn again
+// where the species was initialised uniformly (a few integer operations
+// instead of a gather in particle order, which is random after re-sorts),
+// else read.
+__device__ __forceinline__ double2 initial_pos(const SpeciesDev &sp, const double2 *x0, uint32_t g,
+                                               const StepParams &P)
+{
+    if (sp.x0_drawn) return draw_x0(sp.x0_seed, (uint64_t)((int64_t)g - sp.offset), P.L);
+    return x0[g];
+}
+
 // Displacement since initialisation (physical units) of a particle at
 // unwrapped cell u, offset o, that started at x0.
 __device__ __forceinline__ double2 split_disp(int2 u, float2 o, double2 x0, const StepParams &P)
@@ -638,7 +670,7 @@ __device__ __forceinline__ void step32_block1(const StepParams &P, const State32
             const uint32_t g = S.id[q];
             if (GATHER) D.id[p] = g;
             if (STATS) {   // the displacement since initialisation, from the new state
-                const double2 d = split_disp(uc, o, S.x0[g], P);
+                const double2 d = split_disp(uc, o, initial_pos(sp, S.x0, g, P), P);
                 r2x = d.x * d.x;
                 r2y = d.y * d.y;
             }
@@ -742,7 +774,7 @@ __device__ __forceinline__ void step32_block(const StepParams &P, const State32 
                 const uint32_t g = S.id[q];
                 if (GATHER) D.id[p] = g;
                 if (STATS) {   // the displacement since initialisation, from the new state
-                    const double2 d = split_disp(uc, o, S.x0[g], P);
+                    const double2 d = split_disp(uc, o, initial_pos(sp, S.x0, g, P), P);
                     r2x = d.x * d.x;
                     r2y = d.y * d.y;
                 }
@@ -1413,23 +1445,11 @@ hipError_t launch_interleave(double2 *dst, const double *a, const double *b, int
     return hipGetLastError();
 }
 
-// Counter-indexed SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output k of
-// the stream seeded with s is mix(s + (k + 1) * golden gamma).
-__device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t k)
-{
-    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ULL;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    return z ^ (z >> 31);
-}
-
 __global__ void splitmix_kernel(double2 *x0, int64_t count, uint64_t seed, double L)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= count) return;
-    const double ux = (double)(splitmix_at(seed, 2 * (uint64_t)k) >> 11) * 0x1p-53;
-    const double uy = (double)(splitmix_at(seed, 2 * (uint64_t)k + 1) >> 11) * 0x1p-53;
-    x0[k] = make_double2(wrap_pos(L * ux, L), wrap_pos(L * uy, L));
+    x0[k] = draw_x0(seed, (uint64_t)k, L);
 }
 
 hipError_t launch_splitmix(double2 *x0, int64_t count, uint64_t seed, double L, hipStream_t st)

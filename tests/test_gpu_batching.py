@@ -17,7 +17,9 @@ def say(msg):
     print(msg, flush=True)
 
 
-def _mixed(precision, n=128, dt=0.002, **tr_kw):
+def _mixed(precision, n=128, dt=0.002, x0s=None, **tr_kw):
+    """Four species on a spectrum field, initialised uniformly (seeds
+    300 ...), or at the given initial positions x0s[k] = (x, y)."""
     (ua, va), (ub, vb) = synth.spectrum_snapshots(n, 8, 12, dt)
     tr = lpt.Tracker(n, precision, **tr_kw)
     tr.set_time_mode("pingpong")
@@ -28,9 +30,12 @@ def _mixed(precision, n=128, dt=0.002, **tr_kw):
                                              ("inertial", 0.05, "catmull_rom", 3001),
                                              ("inertial", 1.0, "bspline", 777),
                                              ("tracer", 0.0, "bspline", 64)]):
-        z = np.zeros(cnt)
-        sids.append(tr.add_species(kind, st, sch, z, z))
-        tr.init_uniform(sids[-1], 300 + k)
+        if x0s is None:
+            z = np.zeros(cnt)
+            sids.append(tr.add_species(kind, st, sch, z, z))
+            tr.init_uniform(sids[-1], 300 + k)
+        else:
+            sids.append(tr.add_species(kind, st, sch, *x0s[k]))
     return tr, sids
 
 
@@ -236,12 +241,39 @@ def test_batched_species_match_one_context_per_species():
         one.close()
 
 
+def test_record_steps_draw_uniform_initial_positions_bit_for_bit():
+    """On FP32-split record steps a species initialised by init_uniform has
+    its initial positions drawn again from the seed (no gather in particle
+    order); a species given the same positions explicitly reads them.  The
+    two give the same bits -- records (every field), positions and
+    velocities -- through re-sorts every 4 steps, for species at offsets
+    other than 0 too."""
+    say("drawn initial positions")
+    a, sids = _mixed("fp32_split", sort_interval=4)
+    # before any step the unwrapped readout is the initial position itself
+    x0s = [tuple(a.get_positions(s)[2:]) for s in sids]
+    b, _ = _mixed("fp32_split", sort_interval=4, x0s=x0s)
+    for tr in (a, b):
+        tr.step(30, 0.002, stats_every=3)
+    for x, y in zip(_snap(a, sids), _snap(b, sids)):
+        np.testing.assert_array_equal(x, y)
+    for s in sids:
+        ra, rb = a.get_stats(s), b.get_stats(s)
+        assert len(ra) == 10
+        for f in ra.dtype.names:
+            np.testing.assert_array_equal(ra[f], rb[f])
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
 def test_state_resume_continues_bit_for_bit(precision):
     """Save after 7 steps, restore into a fresh context with the same
     species, step 11 more: identical bits to stepping 18 without a break
-    (re-sorts every 4 steps and statistics every 3 included); a mismatched
-    context refuses the blob."""
+    (re-sorts every 4 steps and statistics every 3 included; in FP32 split
+    the resumed context reads the blob's initial positions on record steps
+    where the uninterrupted one draws them again); a mismatched context
+    refuses the blob."""
     say(f"resume {precision}")
     a, sids = _mixed(precision, sort_interval=4)
     a.step(7, 0.002, stats_every=3)
