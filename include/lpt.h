@@ -179,7 +179,9 @@ lpt_status lpt_add_species(lpt_ctx *ctx, lpt_kind kind, double st, lpt_scheme sc
  * particle p takes outputs 2p and 2p+1 of the counter-indexed SplitMix64
  * stream seeded with `seed`, u = (z >> 11) * 2^-53, x = L*u.  Resets the
  * displacements (and the velocity, if it was taken from the field).  Only
- * before the first step. */
+ * before the first step.  In FP32-split mode the statistics steps draw these
+ * positions again from the seed (the same bits) instead of reading them,
+ * until lpt_set_state replaces them. */
 lpt_status lpt_init_uniform(lpt_ctx *ctx, int32_t species_id, uint64_t seed);
 
 /* Advance every species by nsteps RK4 steps of size dt (Alg. coupled_EL,

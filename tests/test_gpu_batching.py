@@ -241,19 +241,23 @@ def test_batched_species_match_one_context_per_species():
         one.close()
 
 
-def test_record_steps_draw_uniform_initial_positions_bit_for_bit():
+@pytest.mark.parametrize("shape", [dict(), dict(block_size=512, rows=2, fused=0)])
+def test_record_steps_draw_uniform_initial_positions_bit_for_bit(shape):
     """On FP32-split record steps a species initialised by init_uniform has
     its initial positions drawn again from the seed (no gather in particle
     order); a species given the same positions explicitly reads them.  The
     two give the same bits -- records (every field), positions and
     velocities -- through re-sorts every 4 steps, for species at offsets
-    other than 0 too."""
-    say("drawn initial positions")
+    other than 0 too; in the fused launch and, with two rows per thread, in
+    the bilinear tracer body of one launch per species."""
+    say(f"drawn initial positions {shape}")
     a, sids = _mixed("fp32_split", sort_interval=4)
     # before any step the unwrapped readout is the initial position itself
     x0s = [tuple(a.get_positions(s)[2:]) for s in sids]
     b, _ = _mixed("fp32_split", sort_interval=4, x0s=x0s)
     for tr in (a, b):
+        if shape:
+            tr.set_tuning(**shape)
         tr.step(30, 0.002, stats_every=3)
     for x, y in zip(_snap(a, sids), _snap(b, sids)):
         np.testing.assert_array_equal(x, y)
